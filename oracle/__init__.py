@@ -1,0 +1,240 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg.  The product library never imports or links
+this package, and this package imports nothing from the product.  Systems are
+passed as any object with the attributes of a seeded synthetic system
+(ion_xyz, shell tables, mo_coef, n_up, n_dn, Jastrow parameters).
+
+Every function here follows a passage of the paper (arXiv 2504.07948, QMC
+section); see oracle.c for the mapping (Eq. 1-3).  Parity is pinned by the
+CPU tests against direct determinants, finite differences, closed forms and
+the zero-variance hydrogen-like case.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (FP64, no FP contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                               "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Sys(C.Structure):
+    _fields_ = [
+        ("n_atom", C.c_int32), ("ion_xyz", C.c_void_p), ("ion_charge", C.c_void_p),
+        ("n_shell", C.c_int32), ("shell_atom", C.c_void_p), ("shell_l", C.c_void_p),
+        ("shell_nprim", C.c_void_p), ("prim_alpha", C.c_void_p), ("prim_coef", C.c_void_p),
+        ("n_basis", C.c_int32), ("n_mo", C.c_int32), ("mo_coef", C.c_void_p),
+        ("n_up", C.c_int32), ("n_dn", C.c_int32),
+        ("jee_a_anti", C.c_double), ("jee_a_para", C.c_double), ("jee_b", C.c_double),
+        ("jen_a", C.c_void_p), ("jen_b", C.c_double),
+        ("n_det", C.c_int32), ("det_exc", C.c_void_p), ("ci_coef", C.c_void_p),
+    ]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = C.CDLL(_LIB)
+        P = C.c_void_p
+        lib.orc_basis_vgl.argtypes = [P, P, P]
+        lib.orc_orbitals_vgl.argtypes = [P, P, C.c_int32, P]
+        lib.orc_lu_slogdet_inv.argtypes = [C.c_int32, P, P, P, P]
+        lib.orc_jastrow.argtypes = [P, P, P, P, P]
+        lib.orc_potential.argtypes = [P, P]
+        lib.orc_potential.restype = C.c_double
+        lib.orc_evaluate.argtypes = [P, P, P, P, P, P]
+        lib.orc_philox4x32_10.argtypes = [P, P, P]
+        lib.orc_philox4x32_10.restype = None
+        lib.orc_move_draws.argtypes = [C.c_uint64, C.c_int64, C.c_int32, C.c_int32, P, P]
+        lib.orc_move_draws.restype = None
+        lib.orc_run.argtypes = [P, C.c_int32, P, P, P, C.c_int64, C.c_int32, C.c_int32,
+                                C.c_double, C.c_uint64, C.c_double, C.c_int32, P, P, C.c_int32]
+        lib.orc_ion_grads.argtypes = [P, P, P, P]
+        lib.orc_ion_grads_batch.argtypes = [P, C.c_int32, P, P, P, C.c_int32]
+        lib.orc_evaluate_batch.argtypes = [P, C.c_int32, P, P, P, P, C.c_int32]
+        lib.orc_msd_ratio_direct.argtypes = [P, P, P]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class OracleSystem:
+    """Holds contiguous copies of a system's arrays and the C struct."""
+
+    def __init__(self, sys):
+        f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)
+        self.sys = sys
+        self.keep = dict(
+            ion_xyz=f64(sys.ion_xyz), ion_charge=f64(sys.ion_charge), shell_atom=i32(sys.shell_atom),
+            shell_l=i32(sys.shell_l), shell_nprim=i32(sys.shell_nprim), prim_alpha=f64(sys.prim_alpha),
+            prim_coef=f64(sys.prim_coef), mo_coef=f64(sys.mo_coef), jen_a=f64(sys.jen_a))
+        n_det = int(getattr(sys, "n_det", 0) or 0)
+        if n_det:
+            self.keep["det_exc"] = i32(sys.det_exc)
+            self.keep["ci_coef"] = f64(sys.ci_coef)
+        k = self.keep
+        self.c = _Sys(
+            n_atom=k["ion_xyz"].shape[0], ion_xyz=_ptr(k["ion_xyz"]), ion_charge=_ptr(k["ion_charge"]),
+            n_shell=k["shell_l"].shape[0], shell_atom=_ptr(k["shell_atom"]), shell_l=_ptr(k["shell_l"]),
+            shell_nprim=_ptr(k["shell_nprim"]), prim_alpha=_ptr(k["prim_alpha"]),
+            prim_coef=_ptr(k["prim_coef"]), n_basis=k["mo_coef"].shape[0], n_mo=k["mo_coef"].shape[1],
+            mo_coef=_ptr(k["mo_coef"]), n_up=sys.n_up, n_dn=sys.n_dn, jee_a_anti=sys.jee_a_anti,
+            jee_a_para=sys.jee_a_para, jee_b=sys.jee_b, jen_a=_ptr(k["jen_a"]), jen_b=sys.jen_b,
+            n_det=n_det, det_exc=_ptr(k.get("det_exc")), ci_coef=_ptr(k.get("ci_coef")))
+        self.n_elec = sys.n_up + sys.n_dn
+        self.n_atom = k["ion_xyz"].shape[0]
+        self.n_basis = k["mo_coef"].shape[0]
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+
+def _osys(sys):
+    return sys if isinstance(sys, OracleSystem) else OracleSystem(sys)
+
+
+def basis_vgl(sys, r):
+    o = _osys(sys)
+    out = np.zeros((o.n_basis, 5))
+    rc = _load().orc_basis_vgl(o.ref, _ptr(np.ascontiguousarray(r, dtype=np.float64)), _ptr(out))
+    assert rc == 0
+    return out
+
+
+def orbitals_vgl(sys, r, n_orb):
+    o = _osys(sys)
+    out = np.zeros((5, n_orb))
+    rc = _load().orc_orbitals_vgl(o.ref, _ptr(np.ascontiguousarray(r, dtype=np.float64)), n_orb,
+                                  _ptr(out))
+    assert rc == 0
+    return out
+
+
+def lu_slogdet_inv(A):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    ld = C.c_double()
+    sg = C.c_int32()
+    inv = np.zeros_like(A)
+    rc = _load().orc_lu_slogdet_inv(n, _ptr(A), C.byref(ld), C.byref(sg), _ptr(inv))
+    return int(sg.value), float(ld.value), inv, rc
+
+
+def jastrow(sys, R):
+    o = _osys(sys)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    J = C.c_double()
+    g = np.zeros((o.n_elec, 3))
+    l = np.zeros(o.n_elec)
+    _load().orc_jastrow(o.ref, _ptr(R), C.byref(J), _ptr(g), _ptr(l))
+    return float(J.value), g, l
+
+
+def potential(sys, R):
+    o = _osys(sys)
+    return float(_load().orc_potential(o.ref, _ptr(np.ascontiguousarray(R, dtype=np.float64))))
+
+
+def evaluate(sys, R):
+    """-> (log|Psi|, sign, E_L, drift[n_elec,3]) at one configuration."""
+    o = _osys(sys)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    lp = C.c_double()
+    sg = C.c_int32()
+    el = C.c_double()
+    dr = np.zeros((o.n_elec, 3))
+    rc = _load().orc_evaluate(o.ref, _ptr(R), C.byref(lp), C.byref(sg), C.byref(el), _ptr(dr))
+    return float(lp.value), int(sg.value), float(el.value), dr, rc
+
+
+def evaluate_batch(sys, R, n_threads=0):
+    o = _osys(sys)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    W = R.shape[0]
+    lp = np.zeros(W)
+    sg = np.zeros(W, dtype=np.int32)
+    el = np.zeros(W)
+    rc = _load().orc_evaluate_batch(o.ref, W, _ptr(R), _ptr(lp), _ptr(sg), _ptr(el), n_threads)
+    return lp, sg, el, rc
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _load().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def move_draws(seed, step, walker, elec):
+    chi = np.zeros(3)
+    u = C.c_double()
+    _load().orc_move_draws(seed, step, walker, elec, _ptr(chi), C.byref(u))
+    return chi, float(u.value)
+
+
+def run(sys, R, log_w=None, step0=0, n_steps=1, mode=1, tau=0.01, seed=1, e_trial=0.0,
+        walker_offset=0, want_logs=True, n_threads=0):
+    """Run n_steps sweeps on a copy of R. mode 0 = VMC, 1 = DMC.
+    Returns dict(R, log_w, e_local, accept_log[n_steps,W,ne], e_log[n_steps,W])."""
+    o = _osys(sys)
+    R = np.array(R, dtype=np.float64, copy=True, order="C")
+    W = R.shape[0]
+    lw = np.zeros(W) if log_w is None else np.array(log_w, dtype=np.float64, copy=True)
+    el = np.zeros(W)
+    acc = np.zeros((n_steps, W, o.n_elec), dtype=np.uint8) if want_logs else None
+    elog = np.zeros((n_steps, W)) if want_logs else None
+    rc = _load().orc_run(o.ref, W, _ptr(R), _ptr(lw), _ptr(el), step0, n_steps, mode, tau, seed,
+                         e_trial, walker_offset, _ptr(acc), _ptr(elog), n_threads)
+    return dict(R=R, log_w=lw, e_local=el, accept_log=acc, e_log=elog, rc=rc)
+
+
+def ion_grads(sys, R):
+    o = _osys(sys)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    dl = np.zeros((o.n_atom, 3))
+    dv = np.zeros((o.n_atom, 3))
+    rc = _load().orc_ion_grads(o.ref, _ptr(R), _ptr(dl), _ptr(dv))
+    return dl, dv, rc
+
+
+def ion_grads_batch(sys, R, n_threads=0):
+    o = _osys(sys)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    W = R.shape[0]
+    dl = np.zeros((W, o.n_atom, 3))
+    dv = np.zeros((W, o.n_atom, 3))
+    rc = _load().orc_ion_grads_batch(o.ref, W, _ptr(R), _ptr(dl), _ptr(dv), n_threads)
+    return dl, dv, rc
+
+
+def msd_ratio_direct(sys, R):
+    o = _osys(sys)
+    out = C.c_double()
+    _load().orc_msd_ratio_direct(o.ref, _ptr(np.ascontiguousarray(R, dtype=np.float64)),
+                                 C.byref(out))
+    return float(out.value)

@@ -1,0 +1,641 @@
+/*
+ * Plain FP64 CPU oracle for the DMC hot path (Slater-Jastrow, LCAO orbitals).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path.  It shares no code
+ * with the HIP library.  Build: gcc -O2 -ffp-contract=off -fopenmp -shared.
+ *
+ * Paper passages followed (arXiv 2504.07948, QMC section):
+ *   Eq. 1   imaginary-time projection; fixed-node constraint (text after Eq. 1)
+ *   Eq. 2   Psi_T = exp(sum J) sum_k C_k D_k^up D_k^dn, phi_i = sum_l C_l^i Phi_l
+ *   Eq. 3   d ln D / d lambda = tr(A^{-1} B), B = dA/d lambda, A_ij = phi_j(r_i)
+ *   DMC parameters: time step 0.01 a.u., walkers evaluated as a crowd.
+ * Readings of what the paper leaves open (Pade Jastrow form, Cartesian
+ * Gaussians, no drift limiter, fixed population with log-weights, Philox
+ * stream layout) are listed with the project documentation.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ basis */
+/* Cartesian exponent triples, canonical component order. */
+static const int CART[3][6][3] = {
+    {{0, 0, 0}},
+    {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}},
+    {{2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}},
+};
+static const int NCART[3] = {1, 3, 6};
+
+/* c * x^n with the convention x^n = 0 for n < 0 (derivative of a monomial). */
+static double mono(double x, int n) {
+  if (n < 0) return 0.0;
+  double v = 1.0;
+  for (int k = 0; k < n; ++k) v *= x;
+  return v;
+}
+
+/* Phi(r) = x^a y^b z^c * R(s^2), R(s^2) = sum_p d_p exp(-alpha_p s^2),
+ * with (x,y,z) = r - R_atom.  Derivatives from the product rule:
+ *   dPhi/dx = (dP/dx) R + P * 2x R'      (R' = dR/d(s^2))
+ *   lap Phi = R lap P + 2 grad P . grad R + P lap R,
+ *   grad R = 2 r R',  lap R = 6 R' + 4 s^2 R''. */
+int orc_basis_vgl(const orc_system *s, const double r[3], double *out) {
+  int prim = 0, fn = 0;
+  for (int sh = 0; sh < s->n_shell; ++sh) {
+    const int l = s->shell_l[sh];
+    if (l < 0 || l > 2) return 1;
+    const double *c = s->ion_xyz + 3 * s->shell_atom[sh];
+    const double d[3] = {r[0] - c[0], r[1] - c[1], r[2] - c[2]};
+    const double s2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double R0 = 0.0, R1 = 0.0, R2 = 0.0;
+    for (int p = 0; p < s->shell_nprim[sh]; ++p, ++prim) {
+      const double a = s->prim_alpha[prim];
+      const double e = s->prim_coef[prim] * exp(-a * s2);
+      R0 += e;
+      R1 += -a * e;
+      R2 += a * a * e;
+    }
+    const double gradR[3] = {2.0 * d[0] * R1, 2.0 * d[1] * R1, 2.0 * d[2] * R1};
+    const double lapR = 6.0 * R1 + 4.0 * s2 * R2;
+    for (int k = 0; k < NCART[l]; ++k, ++fn) {
+      const int *e = CART[l][k];
+      const double px = mono(d[0], e[0]), py = mono(d[1], e[1]), pz = mono(d[2], e[2]);
+      const double P = px * py * pz;
+      const double dP[3] = {e[0] * mono(d[0], e[0] - 1) * py * pz,
+                            e[1] * px * mono(d[1], e[1] - 1) * pz,
+                            e[2] * px * py * mono(d[2], e[2] - 1)};
+      const double lapP = e[0] * (e[0] - 1) * mono(d[0], e[0] - 2) * py * pz +
+                          e[1] * (e[1] - 1) * px * mono(d[1], e[1] - 2) * pz +
+                          e[2] * (e[2] - 1) * px * py * mono(d[2], e[2] - 2);
+      double *o = out + 5 * fn;
+      o[0] = P * R0;
+      for (int x = 0; x < 3; ++x) o[1 + x] = dP[x] * R0 + P * gradR[x];
+      o[4] = lapP * R0 + 2.0 * (dP[0] * gradR[0] + dP[1] * gradR[1] + dP[2] * gradR[2]) +
+             P * lapR;
+    }
+  }
+  return fn == s->n_basis ? 0 : 1;
+}
+
+/* phi_j = sum_l C_lj Phi_l, for value, gradient and Laplacian rows. */
+int orc_orbitals_vgl(const orc_system *s, const double r[3], int32_t n_orb, double *out) {
+  double *b = (double *)malloc(sizeof(double) * 5 * (size_t)s->n_basis);
+  if (!b) return 2;
+  int rc = orc_basis_vgl(s, r, b);
+  for (int c = 0; c < 5; ++c)
+    for (int j = 0; j < n_orb; ++j) {
+      double acc = 0.0;
+      for (int l = 0; l < s->n_basis; ++l) acc += s->mo_coef[(size_t)l * s->n_mo + j] * b[5 * l + c];
+      out[c * n_orb + j] = acc;
+    }
+  free(b);
+  return rc;
+}
+
+/* ------------------------------------------------------------ dense LU --- */
+int orc_lu_slogdet_inv(int32_t n, const double *A, double *logdet, int32_t *sign, double *inv) {
+  double *lu = (double *)malloc(sizeof(double) * (size_t)n * n + 1);
+  int *piv = (int *)malloc(sizeof(int) * (size_t)n + 1);
+  memcpy(lu, A, sizeof(double) * (size_t)n * n);
+  int sgn = 1, singular = 0;
+  double ld = 0.0;
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = fabs(lu[(size_t)k * n + k]);
+    for (int i = k + 1; i < n; ++i)
+      if (fabs(lu[(size_t)i * n + k]) > best) { best = fabs(lu[(size_t)i * n + k]); p = i; }
+    piv[k] = p;
+    if (p != k) {
+      for (int j = 0; j < n; ++j) {
+        double t = lu[(size_t)k * n + j];
+        lu[(size_t)k * n + j] = lu[(size_t)p * n + j];
+        lu[(size_t)p * n + j] = t;
+      }
+      sgn = -sgn;
+    }
+    const double pv = lu[(size_t)k * n + k];
+    if (pv == 0.0) { singular = 1; break; }
+    if (pv < 0) sgn = -sgn;
+    ld += log(fabs(pv));
+    for (int i = k + 1; i < n; ++i) {
+      const double m = lu[(size_t)i * n + k] / pv;
+      lu[(size_t)i * n + k] = m;
+      for (int j = k + 1; j < n; ++j) lu[(size_t)i * n + j] -= m * lu[(size_t)k * n + j];
+    }
+  }
+  if (logdet) *logdet = singular ? -INFINITY : ld;
+  if (sign) *sign = singular ? 0 : sgn;
+  if (inv && !singular) {
+    /* solve A X = I column by column: P A = L U */
+    double *col = (double *)malloc(sizeof(double) * (size_t)n + 1);
+    for (int c = 0; c < n; ++c) {
+      for (int i = 0; i < n; ++i) col[i] = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < n; ++k)
+        if (piv[k] != k) { double t = col[k]; col[k] = col[piv[k]]; col[piv[k]] = t; }
+      for (int i = 0; i < n; ++i)
+        for (int k = 0; k < i; ++k) col[i] -= lu[(size_t)i * n + k] * col[k];
+      for (int i = n - 1; i >= 0; --i) {
+        for (int k = i + 1; k < n; ++k) col[i] -= lu[(size_t)i * n + k] * col[k];
+        col[i] /= lu[(size_t)i * n + i];
+      }
+      for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = col[i];
+    }
+    free(col);
+  }
+  free(lu);
+  free(piv);
+  return singular;
+}
+
+/* ------------------------------------------------------------- Jastrow --- */
+/* Pade u(r) = a r / (1 + b r), u' = a/(1+br)^2, u'' = -2ab/(1+br)^3. */
+static double pade(double a, double b, double r) { return a * r / (1.0 + b * r); }
+static double pade_d1(double a, double b, double r) {
+  const double t = 1.0 + b * r;
+  return a / (t * t);
+}
+static double pade_d2(double a, double b, double r) {
+  const double t = 1.0 + b * r;
+  return -2.0 * a * b / (t * t * t);
+}
+
+static int spin_of(const orc_system *s, int i) { return i < s->n_up ? 0 : 1; }
+
+static double ee_a(const orc_system *s, int i, int j) {
+  return spin_of(s, i) == spin_of(s, j) ? s->jee_a_para : s->jee_a_anti;
+}
+
+/* J = sum_{i<j} u_ee(r_ij) + sum_{i,A} u_A(r_iA) */
+int orc_jastrow(const orc_system *s, const double *R, double *J, double *grad, double *lap) {
+  const int ne = s->n_up + s->n_dn;
+  double jv = 0.0;
+  if (grad) memset(grad, 0, sizeof(double) * 3 * ne);
+  if (lap) memset(lap, 0, sizeof(double) * ne);
+  for (int i = 0; i < ne; ++i) {
+    for (int j = 0; j < ne; ++j) {
+      if (j == i) continue;
+      const double d[3] = {R[3 * i] - R[3 * j], R[3 * i + 1] - R[3 * j + 1], R[3 * i + 2] - R[3 * j + 2]};
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const double a = ee_a(s, i, j), b = s->jee_b;
+      if (j > i) jv += pade(a, b, r);
+      const double u1 = pade_d1(a, b, r), u2 = pade_d2(a, b, r);
+      if (grad)
+        for (int x = 0; x < 3; ++x) grad[3 * i + x] += u1 * d[x] / r;
+      if (lap) lap[i] += u2 + 2.0 * u1 / r;
+    }
+    for (int A = 0; A < s->n_atom; ++A) {
+      const double *c = s->ion_xyz + 3 * A;
+      const double d[3] = {R[3 * i] - c[0], R[3 * i + 1] - c[1], R[3 * i + 2] - c[2]};
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const double a = s->jen_a[A], b = s->jen_b;
+      jv += pade(a, b, r);
+      const double u1 = pade_d1(a, b, r), u2 = pade_d2(a, b, r);
+      if (grad)
+        for (int x = 0; x < 3; ++x) grad[3 * i + x] += u1 * d[x] / r;
+      if (lap) lap[i] += u2 + 2.0 * u1 / r;
+    }
+  }
+  if (J) *J = jv;
+  return 0;
+}
+
+/* J and grad_i J of electron i placed at ri, the rest at R (one-electron sums). */
+static void jastrow_one(const orc_system *s, const double *R, int i, const double ri[3], double *u,
+                        double g[3]) {
+  const int ne = s->n_up + s->n_dn;
+  double acc = 0.0, gg[3] = {0, 0, 0};
+  for (int j = 0; j < ne; ++j) {
+    if (j == i) continue;
+    const double d[3] = {ri[0] - R[3 * j], ri[1] - R[3 * j + 1], ri[2] - R[3 * j + 2]};
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double a = ee_a(s, i, j), b = s->jee_b;
+    acc += pade(a, b, r);
+    const double u1 = pade_d1(a, b, r);
+    for (int x = 0; x < 3; ++x) gg[x] += u1 * d[x] / r;
+  }
+  for (int A = 0; A < s->n_atom; ++A) {
+    const double *c = s->ion_xyz + 3 * A;
+    const double d[3] = {ri[0] - c[0], ri[1] - c[1], ri[2] - c[2]};
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double a = s->jen_a[A], b = s->jen_b;
+    acc += pade(a, b, r);
+    const double u1 = pade_d1(a, b, r);
+    for (int x = 0; x < 3; ++x) gg[x] += u1 * d[x] / r;
+  }
+  *u = acc;
+  for (int x = 0; x < 3; ++x) g[x] = gg[x];
+}
+
+/* ----------------------------------------------------------- potential --- */
+double orc_potential(const orc_system *s, const double *R) {
+  const int ne = s->n_up + s->n_dn;
+  double v = 0.0;
+  for (int i = 0; i < ne; ++i)
+    for (int j = i + 1; j < ne; ++j) {
+      const double d[3] = {R[3 * i] - R[3 * j], R[3 * i + 1] - R[3 * j + 1], R[3 * i + 2] - R[3 * j + 2]};
+      v += 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    }
+  for (int i = 0; i < ne; ++i)
+    for (int A = 0; A < s->n_atom; ++A) {
+      const double *c = s->ion_xyz + 3 * A;
+      const double d[3] = {R[3 * i] - c[0], R[3 * i + 1] - c[1], R[3 * i + 2] - c[2]};
+      v -= s->ion_charge[A] / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    }
+  for (int A = 0; A < s->n_atom; ++A)
+    for (int B = A + 1; B < s->n_atom; ++B) {
+      const double *a = s->ion_xyz + 3 * A, *b = s->ion_xyz + 3 * B;
+      const double d[3] = {a[0] - b[0], a[1] - b[1], a[2] - b[2]};
+      v += s->ion_charge[A] * s->ion_charge[B] / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    }
+  return v;
+}
+
+/* ---------------------------------------------------- walker state ------ */
+typedef struct {
+  int ne, nsig[2];
+  double *rows;      /* [ne][5][nmax]: orbital VGL of each electron */
+  double *A[2];      /* [n][n] value matrices */
+  double *G[2];      /* [n][n] inverses (orbital x electron) */
+  double logdet[2];
+  int sign[2];
+  int nmax;
+} wstate;
+
+static int ws_init(const orc_system *s, wstate *w, const double *R) {
+  w->ne = s->n_up + s->n_dn;
+  w->nsig[0] = s->n_up;
+  w->nsig[1] = s->n_dn;
+  w->nmax = s->n_up > s->n_dn ? s->n_up : s->n_dn;
+  w->rows = (double *)calloc((size_t)w->ne * 5 * w->nmax + 1, sizeof(double));
+  int rc = 0;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = w->nsig[sp];
+    w->A[sp] = (double *)calloc((size_t)n * n + 1, sizeof(double));
+    w->G[sp] = (double *)calloc((size_t)n * n + 1, sizeof(double));
+  }
+  for (int i = 0; i < w->ne; ++i) {
+    const int sp = spin_of(s, i), ii = i - sp * s->n_up, n = w->nsig[sp];
+    double *row = w->rows + (size_t)i * 5 * w->nmax;
+    rc |= orc_orbitals_vgl(s, R + 3 * i, n, row);
+    /* orbitals_vgl packs [5][n]; re-stride to [5][nmax] */
+    if (n != w->nmax)
+      for (int c = 4; c >= 0; --c)
+        for (int j = n - 1; j >= 0; --j) row[c * w->nmax + j] = row[c * n + j];
+    for (int j = 0; j < n; ++j) w->A[sp][(size_t)ii * n + j] = row[j];
+  }
+  for (int sp = 0; sp < 2; ++sp) {
+    if (w->nsig[sp] == 0) { w->logdet[sp] = 0.0; w->sign[sp] = 1; continue; }
+    rc |= orc_lu_slogdet_inv(w->nsig[sp], w->A[sp], &w->logdet[sp], &w->sign[sp], w->G[sp]);
+  }
+  return rc;
+}
+
+static void ws_free(wstate *w) {
+  free(w->rows);
+  for (int sp = 0; sp < 2; ++sp) { free(w->A[sp]); free(w->G[sp]); }
+}
+
+/* (grad D / D) and (lap D / D) for electron i: Eq. 3 with B = grad A, lap A. */
+static void det_derivs(const orc_system *s, const wstate *w, int i, double g[3], double *l) {
+  const int sp = spin_of(s, i), ii = i - sp * s->n_up, n = w->nsig[sp];
+  const double *row = w->rows + (size_t)i * 5 * w->nmax;
+  double acc[4] = {0, 0, 0, 0};
+  for (int j = 0; j < n; ++j) {
+    const double gji = w->G[sp][(size_t)j * n + ii];
+    for (int c = 0; c < 4; ++c) acc[c] += row[(c + 1) * w->nmax + j] * gji;
+  }
+  g[0] = acc[0];
+  g[1] = acc[1];
+  g[2] = acc[2];
+  *l = acc[3];
+}
+
+/* E_L = -1/2 sum_i [lap_i J + |grad_i J|^2 + 2 grad_i J . g_i + l_i] + V */
+static double ws_local_energy(const orc_system *s, const wstate *w, const double *R, double *Jout,
+                              double *drift) {
+  const int ne = w->ne;
+  double *gj = (double *)malloc(sizeof(double) * 3 * ne);
+  double *lj = (double *)malloc(sizeof(double) * ne);
+  double J;
+  orc_jastrow(s, R, &J, gj, lj);
+  double kin = 0.0;
+  for (int i = 0; i < ne; ++i) {
+    double g[3], l;
+    det_derivs(s, w, i, g, &l);
+    const double *q = gj + 3 * i;
+    kin += lj[i] + q[0] * q[0] + q[1] * q[1] + q[2] * q[2] +
+           2.0 * (q[0] * g[0] + q[1] * g[1] + q[2] * g[2]) + l;
+    if (drift)
+      for (int x = 0; x < 3; ++x) drift[3 * i + x] = q[x] + g[x];
+  }
+  if (Jout) *Jout = J;
+  free(gj);
+  free(lj);
+  return -0.5 * kin + orc_potential(s, R);
+}
+
+int orc_evaluate(const orc_system *s, const double *R, double *log_psi, int32_t *sign,
+                 double *e_local, double *drift) {
+  wstate w;
+  int rc = ws_init(s, &w, R);
+  double J = 0.0;
+  const double el = ws_local_energy(s, &w, R, &J, drift);
+  if (log_psi) *log_psi = J + w.logdet[0] + w.logdet[1];
+  if (sign) *sign = w.sign[0] * w.sign[1];
+  if (e_local) *e_local = el;
+  ws_free(&w);
+  return rc;
+}
+
+int orc_evaluate_batch(const orc_system *s, int32_t W, const double *R, double *log_psi,
+                       int32_t *sign, double *e_local, int32_t n_threads) {
+  const int ne = s->n_up + s->n_dn;
+  int rc = 0;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(static) reduction(| : rc)
+  for (int w = 0; w < W; ++w)
+    rc |= orc_evaluate(s, R + (size_t)w * ne * 3, log_psi ? log_psi + w : NULL,
+                       sign ? sign + w : NULL, e_local ? e_local + w : NULL, NULL);
+  return rc;
+}
+
+/* --------------------------------------------------------------- Philox --- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+ * 32x32->64 multiplies with a Weyl-sequence key schedule. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    k0 += W0;
+    k1 += W1;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Counter = (electron, walker, step low 32 bits, draw), key = seed. */
+static void draw_uniform2(uint64_t seed, int64_t step, int32_t walker, int32_t elec, uint32_t draw,
+                          double u[2]) {
+  const uint32_t ctr[4] = {(uint32_t)elec, (uint32_t)walker, (uint32_t)(uint64_t)step, draw};
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t x[4];
+  orc_philox4x32_10(ctr, key, x);
+  const uint64_t a = ((uint64_t)x[0] << 32) | x[1], b = ((uint64_t)x[2] << 32) | x[3];
+  u[0] = (double)(a >> 11) * 0x1.0p-53;
+  u[1] = (double)(b >> 11) * 0x1.0p-53;
+}
+
+/* Box-Muller: (sqrt(-2 ln(1-u1)) cos(2 pi u2), ... sin(2 pi u2)). */
+void orc_move_draws(uint64_t seed, int64_t step, int32_t walker, int32_t elec, double chi[3],
+                    double *u_acc) {
+  const double twopi = 6.283185307179586476925286766559;
+  double u[2];
+  draw_uniform2(seed, step, walker, elec, 0u, u);
+  double rad = sqrt(-2.0 * log(1.0 - u[0]));
+  chi[0] = rad * cos(twopi * u[1]);
+  chi[1] = rad * sin(twopi * u[1]);
+  draw_uniform2(seed, step, walker, elec, 1u, u);
+  rad = sqrt(-2.0 * log(1.0 - u[0]));
+  chi[2] = rad * cos(twopi * u[1]);
+  draw_uniform2(seed, step, walker, elec, 2u, u);
+  *u_acc = u[0];
+}
+
+/* ---------------------------------------------------------------- DMC --- */
+static int walker_run(const orc_system *s, int wi, double *R, double *log_w, double *e_local,
+                      int64_t step0, int32_t n_steps, int32_t mode, double tau, uint64_t seed,
+                      double e_trial, int32_t walker_index, uint8_t *acc_row, size_t acc_stride,
+                      double *e_row, size_t e_stride) {
+  wstate w;
+  int rc = ws_init(s, &w, R);
+  const int ne = w.ne, nmax = w.nmax;
+  double *trial = (double *)malloc(sizeof(double) * 5 * nmax);
+  double e_old = ws_local_energy(s, &w, R, NULL, NULL);
+  const double sqt = sqrt(tau);
+  for (int st = 0; st < n_steps; ++st) {
+    const int64_t step = step0 + st;
+    for (int i = 0; i < ne; ++i) {
+      const int sp = spin_of(s, i), ii = i - sp * s->n_up, n = w.nsig[sp];
+      double *ri = R + 3 * i;
+      double *G = w.G[sp];
+      /* drift at the current position */
+      double uo, gjo[3], gd[3], l_unused;
+      jastrow_one(s, R, i, ri, &uo, gjo);
+      det_derivs(s, &w, i, gd, &l_unused);
+      const double v[3] = {gjo[0] + gd[0], gjo[1] + gd[1], gjo[2] + gd[2]};
+      double chi[3], uacc;
+      orc_move_draws(seed, step, walker_index, i, chi, &uacc);
+      double rn[3];
+      for (int x = 0; x < 3; ++x) rn[x] = ri[x] + tau * v[x] + sqt * chi[x];
+      rc |= orc_orbitals_vgl(s, rn, n, trial);
+      /* determinant ratio: det(A')/det(A) = sum_j phi_j(r') (A^{-1})_{j i} */
+      double rho = 0.0;
+      for (int j = 0; j < n; ++j) rho += trial[j] * G[(size_t)j * n + ii];
+      int accepted = 0;
+      if (!(mode == 1 && !(rho > 0.0))) {
+        double un, gjn[3];
+        jastrow_one(s, R, i, rn, &un, gjn);
+        /* grad ln D' at r': column i of the new inverse is G[:, i] / rho */
+        double gdn[3] = {0, 0, 0};
+        for (int j = 0; j < n; ++j)
+          for (int x = 0; x < 3; ++x) gdn[x] += trial[(1 + x) * n + j] * G[(size_t)j * n + ii];
+        double vn[3];
+        for (int x = 0; x < 3; ++x) vn[x] = gjn[x] + gdn[x] / rho;
+        double fwd = 0.0, bwd = 0.0;
+        for (int x = 0; x < 3; ++x) {
+          const double a = rn[x] - ri[x] - tau * v[x];
+          const double b = ri[x] - rn[x] - tau * vn[x];
+          fwd += a * a;
+          bwd += b * b;
+        }
+        const double lnq = 2.0 * (log(fabs(rho)) + (un - uo)) + (fwd - bwd) / (2.0 * tau);
+        const double p = lnq >= 0.0 ? 1.0 : exp(lnq);
+        accepted = uacc < p;
+      }
+      if (accepted) {
+        for (int x = 0; x < 3; ++x) ri[x] = rn[x];
+        double *row = w.rows + (size_t)i * 5 * nmax;
+        for (int c = 0; c < 5; ++c)
+          for (int j = 0; j < n; ++j) row[c * nmax + j] = trial[c * n + j];
+        for (int j = 0; j < n; ++j) w.A[sp][(size_t)ii * n + j] = trial[j];
+        /* the inverse is always recomputed from scratch (plain definition) */
+        rc |= orc_lu_slogdet_inv(n, w.A[sp], &w.logdet[sp], &w.sign[sp], G);
+      }
+      if (acc_row) acc_row[(size_t)st * acc_stride + i] = (uint8_t)accepted;
+    }
+    const double e_new = ws_local_energy(s, &w, R, NULL, NULL);
+    if (mode == 1) *log_w += -tau * (0.5 * (e_old + e_new) - e_trial);
+    if (e_row) e_row[(size_t)st * e_stride] = e_new;
+    e_old = e_new;
+  }
+  *e_local = e_old;
+  (void)wi;
+  free(trial);
+  ws_free(&w);
+  return rc;
+}
+
+int orc_run(const orc_system *s, int32_t W, double *R, double *log_w, double *e_local,
+            int64_t step0, int32_t n_steps, int32_t mode, double tau, uint64_t seed,
+            double e_trial, int32_t walker_offset, uint8_t *accept_log, double *e_log,
+            int32_t n_threads) {
+  const int ne = s->n_up + s->n_dn;
+  int rc = 0;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(static) reduction(| : rc)
+  for (int w = 0; w < W; ++w) {
+    rc |= walker_run(s, w, R + (size_t)w * ne * 3, log_w + w, e_local + w, step0, n_steps, mode,
+                     tau, seed, e_trial, walker_offset + w,
+                     accept_log ? accept_log + (size_t)w * ne : NULL, (size_t)W * ne,
+                     e_log ? e_log + w : NULL, (size_t)W);
+  }
+  return rc;
+}
+
+/* ---------------------------------------------------------- ion grads --- */
+/* d ln|D_sigma| / dR_{a,x} = tr(G B), B_ij = dA_ij/dR_{a,x}
+ *                          = -sum_{l on atom a} C_lj dPhi_l/dx (r_i)   (Eq. 3)
+ * dJ/dR_a = -sum_i u_a'(r_ia) (r_i - R_a)/r_ia
+ * dV/dR_a = -Z_a sum_i (r_i - R_a)/r_ia^3 - sum_{b != a} Z_a Z_b (R_a - R_b)/R_ab^3 */
+int orc_ion_grads(const orc_system *s, const double *R, double *dlogpsi, double *dV) {
+  wstate w;
+  int rc = ws_init(s, &w, R);
+  const int ne = w.ne, na = s->n_atom, nb = s->n_basis;
+  int *fn_atom = (int *)malloc(sizeof(int) * nb);
+  for (int sh = 0, f = 0; sh < s->n_shell; ++sh)
+    for (int k = 0; k < NCART[s->shell_l[sh]]; ++k) fn_atom[f++] = s->shell_atom[sh];
+  memset(dlogpsi, 0, sizeof(double) * 3 * na);
+  memset(dV, 0, sizeof(double) * 3 * na);
+  double *bvgl = (double *)malloc(sizeof(double) * 5 * nb);
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = w.nsig[sp];
+    if (n == 0) continue;
+    /* B[a][x][i][j] */
+    double *B = (double *)calloc((size_t)na * 3 * n * n + 1, sizeof(double));
+    for (int ii = 0; ii < n; ++ii) {
+      const int i = ii + sp * s->n_up;
+      rc |= orc_basis_vgl(s, R + 3 * i, bvgl);
+      for (int l = 0; l < nb; ++l) {
+        const int a = fn_atom[l];
+        for (int x = 0; x < 3; ++x) {
+          const double dphi = bvgl[5 * l + 1 + x];
+          double *Bax = B + ((size_t)(a * 3 + x) * n + ii) * n;
+          for (int j = 0; j < n; ++j) Bax[j] -= s->mo_coef[(size_t)l * s->n_mo + j] * dphi;
+        }
+      }
+    }
+    for (int a = 0; a < na; ++a)
+      for (int x = 0; x < 3; ++x) {
+        const double *Bax = B + (size_t)(a * 3 + x) * n * n;
+        double tr = 0.0;
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j) tr += w.G[sp][(size_t)j * n + i] * Bax[(size_t)i * n + j];
+        dlogpsi[3 * a + x] += tr;
+      }
+    free(B);
+  }
+  for (int a = 0; a < na; ++a) {
+    const double *c = s->ion_xyz + 3 * a;
+    for (int i = 0; i < ne; ++i) {
+      const double d[3] = {R[3 * i] - c[0], R[3 * i + 1] - c[1], R[3 * i + 2] - c[2]};
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const double u1 = pade_d1(s->jen_a[a], s->jen_b, r);
+      for (int x = 0; x < 3; ++x) {
+        dlogpsi[3 * a + x] -= u1 * d[x] / r;
+        dV[3 * a + x] -= s->ion_charge[a] * d[x] / (r * r * r);
+      }
+    }
+    for (int b = 0; b < na; ++b) {
+      if (b == a) continue;
+      const double *e = s->ion_xyz + 3 * b;
+      const double d[3] = {c[0] - e[0], c[1] - e[1], c[2] - e[2]};
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      for (int x = 0; x < 3; ++x)
+        dV[3 * a + x] -= s->ion_charge[a] * s->ion_charge[b] * d[x] / (r * r * r);
+    }
+  }
+  free(bvgl);
+  free(fn_atom);
+  ws_free(&w);
+  return rc;
+}
+
+int orc_ion_grads_batch(const orc_system *s, int32_t W, const double *R, double *dlogpsi,
+                        double *dV, int32_t n_threads) {
+  const int ne = s->n_up + s->n_dn, na = s->n_atom;
+  int rc = 0;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(static) reduction(| : rc)
+  for (int w = 0; w < W; ++w)
+    rc |= orc_ion_grads(s, R + (size_t)w * ne * 3, dlogpsi + (size_t)w * na * 3,
+                        dV + (size_t)w * na * 3);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ MSD --- */
+/* Psi_MSD / Psi_0 = sum_d c_d (D_d^up / D_0^up)(D_d^dn / D_0^dn), each
+ * excited determinant from its own LU (Eq. 2 with M > 1).  det_exc rows:
+ * [nu, nd, hu0, hu1, pu0, pu1, hd0, hd1, pd0, pd1]; a hole is an occupied
+ * orbital index, a particle the MO index that replaces it. */
+static double det_with_columns(const orc_system *s, const double *R, int sp, const int *cols,
+                               int n, int32_t *sgn) {
+  double *A = (double *)malloc(sizeof(double) * (size_t)n * n + 1);
+  double *ob = (double *)malloc(sizeof(double) * 5 * (size_t)s->n_mo + 1);
+  for (int ii = 0; ii < n; ++ii) {
+    const int i = ii + sp * s->n_up;
+    orc_orbitals_vgl(s, R + 3 * i, s->n_mo, ob);
+    for (int j = 0; j < n; ++j) A[(size_t)ii * n + j] = ob[cols[j]];
+  }
+  double ld;
+  orc_lu_slogdet_inv(n, A, &ld, sgn, NULL);
+  free(A);
+  free(ob);
+  return ld;
+}
+
+int orc_msd_ratio_direct(const orc_system *s, const double *R, double *psi_over_psi0) {
+  const int nsig[2] = {s->n_up, s->n_dn};
+  double ld0[2];
+  int32_t sg0[2];
+  int *cols = (int *)malloc(sizeof(int) * (size_t)(nsig[0] > nsig[1] ? nsig[0] : nsig[1]) + 1);
+  for (int sp = 0; sp < 2; ++sp) {
+    for (int j = 0; j < nsig[sp]; ++j) cols[j] = j;
+    ld0[sp] = det_with_columns(s, R, sp, cols, nsig[sp], &sg0[sp]);
+  }
+  double acc = 0.0;
+  for (int d = 0; d < s->n_det; ++d) {
+    const int32_t *e = s->det_exc + 10 * d;
+    double term = s->ci_coef[d];
+    for (int sp = 0; sp < 2; ++sp) {
+      const int ne = e[sp];
+      if (ne == 0) continue;
+      const int *h = e + (sp == 0 ? 2 : 6), *p = e + (sp == 0 ? 4 : 8);
+      for (int j = 0; j < nsig[sp]; ++j) cols[j] = j;
+      for (int k = 0; k < ne; ++k) cols[h[k]] = p[k];
+      int32_t sg;
+      const double ld = det_with_columns(s, R, sp, cols, nsig[sp], &sg);
+      term *= (double)(sg * sg0[sp]) * exp(ld - ld0[sp]);
+    }
+    acc += term;
+  }
+  free(cols);
+  *psi_over_psi0 = acc;
+  return 0;
+}

@@ -1,0 +1,109 @@
+/*
+ * Plain FP64 CPU oracle for the batched-walker DMC step of a Slater-Jastrow
+ * wavefunction with contracted-Gaussian LCAO orbitals.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  It shares no code, header,
+ * table or helper with the HIP library; both read the same seeded inputs.
+ *
+ * Everything is computed from its plain definition, in double precision,
+ * with no blocking, fusion or delayed update:
+ *   - trial function Psi = exp(J) D_up D_dn (Eq. 2, one determinant; the
+ *     multideterminant sum of Eq. 2 by one direct LU per determinant);
+ *   - orbitals phi_j(r) = sum_l C_lj Phi_l(r) (the LCAO form below Eq. 2);
+ *   - determinant ratios and log-derivatives through A^{-1} of a fresh LU
+ *     (Eq. 3: d ln D / d lambda = tr(A^{-1} dA/d lambda));
+ *   - the DMC step of Eq. 1 under the fixed-node constraint, drift-diffusion
+ *     proposal with Metropolis acceptance, time step tau;
+ *   - ion gradients in forward mode, one tr(A^{-1} dA/dR_{a,x}) per ion
+ *     coordinate (Eq. 3 with lambda = R_{a,x}).
+ */
+#ifndef DMC_ORACLE_H
+#define DMC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t n_atom;
+  const double *ion_xyz;      /* [n_atom][3] */
+  const double *ion_charge;   /* [n_atom]    */
+  int32_t n_shell;
+  const int32_t *shell_atom;  /* [n_shell] */
+  const int32_t *shell_l;     /* [n_shell], 0..2 */
+  const int32_t *shell_nprim; /* [n_shell] */
+  const double *prim_alpha;   /* [sum nprim] */
+  const double *prim_coef;    /* [sum nprim], normalisation folded in */
+  int32_t n_basis, n_mo;
+  const double *mo_coef;      /* [n_basis][n_mo] */
+  int32_t n_up, n_dn;
+  double jee_a_anti, jee_a_para, jee_b;
+  const double *jen_a;        /* [n_atom] */
+  double jen_b;
+  /* multideterminant expansion; n_det == 0 means a single determinant */
+  int32_t n_det;
+  const int32_t *det_exc;     /* [n_det][10] */
+  const double *ci_coef;      /* [n_det] */
+} orc_system;
+
+/* Basis values, gradients and Laplacians at r: out[n_basis][5] =
+ * (Phi, dPhi/dx, dPhi/dy, dPhi/dz, lap Phi), canonical order. */
+int orc_basis_vgl(const orc_system *s, const double r[3], double *out);
+
+/* First n_orb orbitals at r: out[5][n_orb]. */
+int orc_orbitals_vgl(const orc_system *s, const double r[3], int32_t n_orb, double *out);
+
+/* LU with partial pivoting: log|det A|, sign, and A^{-1} (if inv != NULL).
+ * A is [n][n] row-major.  Returns 0, or 1 when a pivot is exactly zero. */
+int orc_lu_slogdet_inv(int32_t n, const double *A, double *logdet, int32_t *sign, double *inv);
+
+/* Jastrow J(R), per-electron gradient grad[n_elec][3] and Laplacian lap[n_elec]. */
+int orc_jastrow(const orc_system *s, const double *R, double *J, double *grad, double *lap);
+
+/* Coulomb potential V(R) (e-e, e-ion, ion-ion). */
+double orc_potential(const orc_system *s, const double *R);
+
+/* Everything at one configuration R[n_elec][3]:
+ * log|Psi|, sign(Psi), E_L and the drift v[n_elec][3] (may be NULL). */
+int orc_evaluate(const orc_system *s, const double *R, double *log_psi, int32_t *sign,
+                 double *e_local, double *drift);
+
+/* Philox4x32-10 block: out = philox(ctr, key). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* The three per-move draws: chi[3] ~ N(0,1), u_acc ~ U[0,1). */
+void orc_move_draws(uint64_t seed, int64_t step, int32_t walker, int32_t elec,
+                    double chi[3], double *u_acc);
+
+/* mode: 0 = VMC, 1 = DMC (fixed node, log-weights). Walkers are updated in
+ * place; log_w[W] accumulates the DMC weight; e_local[W] is written with the
+ * local energy after the last step.  accept_log[n_steps][W][n_elec] and
+ * e_log[n_steps][W] may be NULL.  Walker w uses Philox walker index
+ * walker_offset + w.  n_threads <= 0 lets OpenMP decide. */
+int orc_run(const orc_system *s, int32_t W, double *R, double *log_w, double *e_local,
+            int64_t step0, int32_t n_steps, int32_t mode, double tau, uint64_t seed,
+            double e_trial, int32_t walker_offset, uint8_t *accept_log, double *e_log,
+            int32_t n_threads);
+
+/* Ion gradients of log|Psi| and of V at R, forward mode (Eq. 3):
+ * dlogpsi[n_atom][3], dV[n_atom][3]. */
+int orc_ion_grads(const orc_system *s, const double *R, double *dlogpsi, double *dV);
+
+/* Same for a crowd: R[W][n_elec][3] -> [W][n_atom][3] each. */
+int orc_ion_grads_batch(const orc_system *s, int32_t W, const double *R, double *dlogpsi,
+                        double *dV, int32_t n_threads);
+
+/* Evaluate a crowd without moving it: log|Psi|, sign, E_L per walker. */
+int orc_evaluate_batch(const orc_system *s, int32_t W, const double *R, double *log_psi,
+                       int32_t *sign, double *e_local, int32_t n_threads);
+
+/* Multideterminant value: Psi_MSD / Psi_0 (ratio to the reference product
+ * of determinants), from one direct LU per excited determinant. */
+int orc_msd_ratio_direct(const orc_system *s, const double *R, double *psi_over_psi0);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
