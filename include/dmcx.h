@@ -1,0 +1,197 @@
+/*
+ * dmcx -- batched-walker diffusion Monte Carlo hot path for MI355X (gfx950).
+ *
+ * The library moves a crowd of walkers through the DMC step of a
+ * Slater-Jastrow trial function built from contracted-Gaussian LCAO orbitals
+ * and returns local energies and ion-coordinate derivatives (arXiv
+ * 2504.07948, QMC section):
+ *   Eq. 1  imaginary-time projection, run under the fixed-node constraint;
+ *   Eq. 2  Psi_T(R) = exp(sum J) sum_k C_k D_k^up D_k^dn with
+ *          phi_i = sum_l C_l^i Phi_l (single determinant or, with n_det > 1,
+ *          an excitation-based multideterminant expansion);
+ *   Eq. 3  d ln D / d lambda = tr(A^{-1} dA/d lambda), A_ij = phi_j(r_i), used
+ *          for drift, local energy and ion forces.
+ * Every step runs in hand-written HIP kernels on the device; the host side of
+ * this library only validates, uploads and launches.
+ *
+ * Conventions (all calls):
+ *   - Units are Hartree atomic units (bohr, Hartree).
+ *   - Electrons 0..n_up-1 are spin up, n_up..n_up+n_dn-1 spin down.
+ *   - Orbital VGL order is (value, d/dx, d/dy, d/dz, Laplacian).
+ *   - Basis order is atom -> shell -> Cartesian component,
+ *     p = (x, y, z), d = (xx, xy, xz, yy, yz, zz).
+ *   - Every call returns a dmcx_status; DMCX_OK == 0.  Nothing throws across
+ *     this interface and nothing aborts.  dmcx_last_error() gives text.
+ *   - Buffers tagged DMCX_HOST are read or written before the call returns.
+ *     Buffers tagged DMCX_DEVICE (e.g. a torch tensor's data_ptr()) are used
+ *     in stream order on the context's stream and must stay valid until that
+ *     work completes (dmcx_sync).  The library never frees caller memory.
+ *   - A context is bound to one HIP stream and is not thread-safe.
+ *   - Walkers of several systems are concatenated in creation order; every
+ *     per-walker array below has W = sum(walkers_per_sys) leading entries and
+ *     uses the largest electron count N_e of all systems as its stride
+ *     (entries beyond a system's own electron count are ignored / zero).
+ */
+#ifndef DMCX_H
+#define DMCX_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dmcx_ctx dmcx_ctx; /* opaque; owns all device state */
+
+typedef enum {
+  DMCX_OK = 0,
+  DMCX_E_INVALID = 1,     /* bad argument, shape or state for this call */
+  DMCX_E_NOMEM = 2,       /* device allocation failed */
+  DMCX_E_HIP = 3,         /* a HIP runtime call failed */
+  DMCX_E_SINGULAR = 4,    /* a Slater matrix had a zero pivot in the LU recompute */
+  DMCX_E_NONFINITE = 5,   /* some walker produced NaN/Inf; see dmcx_walker_flags */
+  DMCX_E_STATE = 6,       /* call out of order (e.g. accept without ratio_grad) */
+  DMCX_E_UNSUPPORTED = 7  /* valid request this build does not implement */
+} dmcx_status;
+
+typedef enum { DMCX_FP64 = 0, DMCX_MIXED = 1 } dmcx_precision;
+typedef enum { DMCX_VMC = 0, DMCX_DMC = 1 } dmcx_mode;
+typedef enum { DMCX_HOST = 0, DMCX_DEVICE = 1 } dmcx_mem;
+
+/* One molecule.  dmcx_create deep-copies it; the caller may free it after. */
+typedef struct {
+  int32_t n_atom;
+  const double *ion_xyz;     /* [n_atom][3] */
+  const double *ion_charge;  /* [n_atom], effective charge Z_A (V_en, V_nn) */
+  int32_t n_shell;
+  const int32_t *shell_atom; /* [n_shell] atom index of each shell */
+  const int32_t *shell_l;    /* [n_shell] angular momentum, 0..2 */
+  const int32_t *shell_nprim;/* [n_shell] primitives per shell, 1..8 */
+  const double *prim_alpha;  /* [sum nprim] exponents, shell order */
+  const double *prim_coef;   /* [sum nprim] coefficients, normalisation folded in */
+  int32_t n_basis, n_mo;     /* n_basis must equal the Cartesian function count */
+  const double *mo_coef;     /* [n_basis][n_mo] row-major LCAO coefficients C_l^i */
+  int32_t n_up, n_dn;        /* electrons per spin; determinants use MOs 0..n_sigma-1 */
+  /* Pade Jastrow u(r) = a r / (1 + b r): e-e with a = jee_a_anti (opposite
+   * spins) or jee_a_para (same spin), e-n with a = jen_a[A]; exponent +J. */
+  double jee_a_anti, jee_a_para, jee_b;
+  const double *jen_a;       /* [n_atom] */
+  double jen_b;
+  /* Multideterminant expansion (Eq. 2 with M > 1).  n_det == 0 or 1 with
+   * only the reference selects the single-determinant path. */
+  int32_t n_det;
+  const int32_t *det_exc;    /* [n_det][10]: nu, nd, hu0, hu1, pu0, pu1, hd0, hd1, pd0, pd1
+                                holes = occupied column index, particles = MO index */
+  const double *ci_coef;     /* [n_det] */
+} dmcx_system;
+
+typedef struct {
+  int32_t precision;         /* dmcx_precision */
+  int32_t delay_rank;        /* k of the delayed rank-k inverse update, 1..64; 0 = autotune */
+  int32_t recompute_period;  /* P: full FP64 inverse recompute every P steps (>= 1) */
+  double tau;                /* DMC time step (a.u.), > 0 */
+  uint64_t seed;             /* Philox4x32-10 key */
+  uint32_t flags;            /* reserved, must be 0 */
+} dmcx_options;
+
+/* Create a context for n_sys systems (n_sys >= 1) with walkers_per_sys[s]
+ * walkers each, bound to hip_stream (a hipStream_t; NULL = default stream).
+ * Allocates all device memory the context will ever use.  Walkers start
+ * undefined: call dmcx_set_walkers before anything that reads them. */
+dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *walkers_per_sys,
+                        const dmcx_options *opt, void *hip_stream, dmcx_ctx **out);
+void dmcx_destroy(dmcx_ctx *ctx);
+
+/* R: [W][N_e][3] positions; log_w: [W] log-weights or NULL (= all zero).
+ * Evaluates all orbitals, recomputes every inverse in FP64 (LU) and the
+ * local energy of each walker.  Resets the step counter to 0. */
+dmcx_status dmcx_set_walkers(dmcx_ctx *ctx, const double *R, const double *log_w, dmcx_mem mem);
+dmcx_status dmcx_get_walkers(dmcx_ctx *ctx, double *R, double *log_w, dmcx_mem mem);
+
+/* Step counter used as the Philox counter's step field (checkpoint/resume). */
+dmcx_status dmcx_set_step(dmcx_ctx *ctx, int64_t step);
+dmcx_status dmcx_get_step(const dmcx_ctx *ctx, int64_t *step);
+
+/* Replace the ion coordinates of system sys_index ([n_atom][3]) and
+ * re-evaluate orbitals, inverses and local energies at the current walkers. */
+dmcx_status dmcx_set_ions(dmcx_ctx *ctx, int32_t sys_index, const double *ion_xyz, dmcx_mem mem);
+
+/* Apply pending delayed updates, then rebuild every inverse from the cached
+ * orbital rows with an FP64 LU (partial pivoting); resets log|D| and sign.
+ * DMCX_E_SINGULAR if any walker's matrix had a zero pivot. */
+dmcx_status dmcx_recompute(dmcx_ctx *ctx);
+
+/* Orbitals of the given spin at one point per walker: r [W][3] ->
+ * vgl [W][5][n_sigma_max] (n_sigma_max = largest n_up/n_dn over systems). */
+dmcx_status dmcx_eval_orbitals(dmcx_ctx *ctx, int32_t spin, const double *r, double *vgl,
+                               dmcx_mem mem);
+
+/* Ratio Psi(R')/Psi(R) for moving electron iel of every walker to r_new
+ * [W][3] (Jastrow included) and grad_{iel} ln|Psi(R')| [W][3].  The proposal
+ * is kept for the next dmcx_accept.  Uses the delayed-updated inverse:
+ * consecutive electrons of one spin form blocks of delay_rank moves. */
+dmcx_status dmcx_ratio_grad(dmcx_ctx *ctx, int32_t iel, const double *r_new, double *ratio,
+                            double *grad, dmcx_mem mem);
+
+/* accept [W] (0/1) for the proposal of the last dmcx_ratio_grad(iel).
+ * Accepted walkers move electron iel; inverses are updated (delayed). */
+dmcx_status dmcx_accept(dmcx_ctx *ctx, int32_t iel, const uint8_t *accept, dmcx_mem mem);
+
+/* Apply all pending delayed updates now (rank-k GEMM flush). */
+dmcx_status dmcx_flush(dmcx_ctx *ctx);
+
+/* Run n_steps full sweeps (every electron proposes one drift-diffusion move
+ * per step, up electrons then down).  DMCX_DMC rejects node crossings and
+ * updates log-weights with E_T = e_trial; DMCX_VMC leaves weights alone.
+ * accept_log [n_steps][W][N_e] (uint8) and e_log [n_steps][W] may be NULL;
+ * both are device pointers if mem == DMCX_DEVICE. */
+dmcx_status dmcx_run(dmcx_ctx *ctx, dmcx_mode mode, int32_t n_steps, double e_trial,
+                     uint8_t *accept_log, double *e_log, dmcx_mem mem);
+
+/* Current local energy, log|Psi| and sign of every walker ([W] each;
+ * any pointer may be NULL). */
+dmcx_status dmcx_measure(dmcx_ctx *ctx, double *e_local, double *log_psi, int8_t *sign,
+                         dmcx_mem mem);
+
+/* Per-walker ion derivatives: dlogpsi_dR and dV_dR, [W][n_atom_max][3]
+ * (either may be NULL).  Reverse-mode adjoint of basis, MO contraction,
+ * log-determinant and Jastrow (Eq. 3 with lambda = an ion coordinate). */
+dmcx_status dmcx_ion_grads(dmcx_ctx *ctx, double *dlogpsi_dR, double *dV_dR, dmcx_mem mem);
+
+/* Vector-Jacobian products over walkers: grad_R[n_atom_max][3] (per system
+ * when n_sys > 1: [n_sys][n_atom_max][3]) = sum_w gbar[w] d(.)_w/dR. */
+dmcx_status dmcx_logpsi_vjp(dmcx_ctx *ctx, const double *gbar, double *grad_R, dmcx_mem mem);
+dmcx_status dmcx_potential_vjp(dmcx_ctx *ctx, const double *gbar, double *grad_R, dmcx_mem mem);
+
+/* Hellmann-Feynman + Pulay force estimate from the current walkers,
+ * weighted by exp(log_w): F = -<dV/dR> - 2(<E_L dlnPsi/dR> - <E_L><dlnPsi/dR>).
+ * F: [n_sys][n_atom_max][3]. */
+dmcx_status dmcx_forces(dmcx_ctx *ctx, double *F, dmcx_mem mem);
+
+/* Per-walker status bits [W]: 1 = non-finite value, 2 = singular matrix. */
+dmcx_status dmcx_walker_flags(dmcx_ctx *ctx, uint8_t *flags, dmcx_mem mem);
+
+/* Wait for all work queued on the context's stream. */
+dmcx_status dmcx_sync(dmcx_ctx *ctx);
+
+/* Average duration (ms) of the most expensive kernel per launch over the
+ * last dmcx_run, measured with HIP events on the context's stream, and the
+ * number of such launches; for roofline reporting. */
+dmcx_status dmcx_last_run_timing(const dmcx_ctx *ctx, double *sweep_ms_avg, int32_t *n_launches,
+                                 double *total_ms);
+
+/* Device self-checks (Philox known answers, MFMA operand layouts).  Runs a
+ * few tiny kernels; DMCX_OK when all match. */
+dmcx_status dmcx_selftest(void *hip_stream);
+
+/* Raw Philox4x32-10 outputs for n counters ctr [n][4] under key [2] -> out [n][4]
+ * (host buffers); lets tests compare the device stream with other
+ * implementations bit for bit. */
+dmcx_status dmcx_philox(const uint32_t *ctr, const uint32_t *key, int32_t n, uint32_t *out);
+
+const char *dmcx_strerror(dmcx_status s);
+const char *dmcx_last_error(const dmcx_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMCX_H */

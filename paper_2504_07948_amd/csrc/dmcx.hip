@@ -1,0 +1,776 @@
+// dmcx C-ABI runtime: validation, basis packing, device allocation and
+// kernel launches on the caller's HIP stream.  All arithmetic of the method
+// runs in the kernels of kernels.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dmcx.h"
+#include "kernels.h"
+
+using namespace dmcx;
+
+namespace {
+
+const int NCART_[3] = {1, 3, 6};
+
+struct DeviceBuffers {
+  std::vector<void *> ptrs;
+  ~DeviceBuffers() {
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+struct dmcx_ctx {
+  hipStream_t stream = nullptr;
+  dmcx_options opt{};
+  int W = 0, Wpad = 0, ne = 0, n_up = 0, n_dn = 0, n_atom = 0, NP = 0, NOB = 0, K = 1, P = 1;
+  int n_basis = 0;
+  int64_t step = 0;
+  bool walkers_set = false;
+  std::string err;
+  DeviceBuffers mem;
+  DevCtx dc{};
+  // host copies needed for later re-packing (set_ions)
+  std::vector<double> ion_xyz;
+  // scratch
+  double *d_pos = nullptr;       // [Wpad][3]
+  double *d_orb = nullptr;       // [Wpad][5][NP]
+  uint8_t *d_acc_stage = nullptr;
+  size_t acc_stage_bytes = 0;
+  double *d_elog_stage = nullptr;
+  size_t elog_stage_bytes = 0;
+  // timing of the sweep kernel over the last dmcx_run
+  std::vector<hipEvent_t> ev;
+  int n_timed = 0;
+};
+
+namespace {
+
+dmcx_status fail(dmcx_ctx *c, dmcx_status s, const std::string &msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+dmcx_status hip_check(dmcx_ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return DMCX_OK;
+  return fail(c, DMCX_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, call)                                          \
+  do {                                                              \
+    dmcx_status _s = hip_check((ctx), (call), #call);               \
+    if (_s != DMCX_OK) return _s;                                   \
+  } while (0)
+
+template <typename T>
+dmcx_status dalloc(dmcx_ctx *c, T **p, size_t n) {
+  void *q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess)
+    return fail(c, DMCX_E_NOMEM, "hipMalloc failed");
+  c->mem.ptrs.push_back(q);
+  *p = (T *)q;
+  return DMCX_OK;
+}
+
+template <typename T>
+dmcx_status upload(dmcx_ctx *c, T **p, const std::vector<T> &h) {
+  dmcx_status s = dalloc(c, p, h.size());
+  if (s) return s;
+  if (!h.empty())
+    HIP_TRY(c, hipMemcpyAsync(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return DMCX_OK;
+}
+
+// Copy n bytes between caller memory (host or device) and device memory.
+dmcx_status copy_in(dmcx_ctx *c, void *dst, const void *src, size_t n, dmcx_mem mem) {
+  if (!n) return DMCX_OK;
+  HIP_TRY(c, hipMemcpyAsync(dst, src, n, mem == DMCX_HOST ? hipMemcpyHostToDevice
+                                                           : hipMemcpyDeviceToDevice, c->stream));
+  if (mem == DMCX_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return DMCX_OK;
+}
+dmcx_status copy_out(dmcx_ctx *c, void *dst, const void *src, size_t n, dmcx_mem mem) {
+  if (!n) return DMCX_OK;
+  HIP_TRY(c, hipMemcpyAsync(dst, src, n, mem == DMCX_HOST ? hipMemcpyDeviceToHost
+                                                           : hipMemcpyDeviceToDevice, c->stream));
+  if (mem == DMCX_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return DMCX_OK;
+}
+
+dmcx_status validate_system(dmcx_ctx *c, const dmcx_system &s) {
+  if (s.n_atom <= 0 || !s.ion_xyz || !s.ion_charge || !s.jen_a)
+    return fail(c, DMCX_E_INVALID, "system: need n_atom > 0 and ion arrays");
+  if (s.n_shell <= 0 || !s.shell_atom || !s.shell_l || !s.shell_nprim || !s.prim_alpha ||
+      !s.prim_coef)
+    return fail(c, DMCX_E_INVALID, "system: need shells");
+  int nb = 0;
+  for (int i = 0; i < s.n_shell; ++i) {
+    if (s.shell_l[i] < 0 || s.shell_l[i] > 2)
+      return fail(c, DMCX_E_INVALID, "system: shell l must be 0..2");
+    if (s.shell_nprim[i] < 1 || s.shell_nprim[i] > 8)
+      return fail(c, DMCX_E_INVALID, "system: shell nprim must be 1..8");
+    if (s.shell_atom[i] < 0 || s.shell_atom[i] >= s.n_atom)
+      return fail(c, DMCX_E_INVALID, "system: shell_atom out of range");
+    nb += NCART_[s.shell_l[i]];
+  }
+  if (nb != s.n_basis) return fail(c, DMCX_E_INVALID, "system: n_basis != Cartesian count");
+  if (!s.mo_coef || s.n_mo < std::max(s.n_up, s.n_dn))
+    return fail(c, DMCX_E_INVALID, "system: n_mo must cover max(n_up, n_dn)");
+  if (s.n_up < 0 || s.n_dn < 0 || s.n_up + s.n_dn < 1)
+    return fail(c, DMCX_E_INVALID, "system: need electrons");
+  if (std::max(s.n_up, s.n_dn) > 128)
+    return fail(c, DMCX_E_UNSUPPORTED, "system: at most 128 electrons per spin");
+  if (s.n_det > 1) return fail(c, DMCX_E_UNSUPPORTED, "multideterminant expansion not built yet");
+  return DMCX_OK;
+}
+
+// Pack shells by (l, nprim) into groups of four (padding with zero-weight
+// shells), permute the LCAO rows to match, and split groups into stages of
+// at most FMAX functions.
+dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, int n_orb) {
+  struct Sh { int l, np, atom, prim0, fn0; };
+  std::vector<Sh> sh(s.n_shell);
+  int prim = 0, fn = 0;
+  for (int i = 0; i < s.n_shell; ++i) {
+    sh[i] = {s.shell_l[i], s.shell_nprim[i], s.shell_atom[i], prim, fn};
+    prim += s.shell_nprim[i];
+    fn += NCART_[s.shell_l[i]];
+  }
+  std::vector<int> order(s.n_shell);
+  for (int i = 0; i < s.n_shell; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return sh[a].l != sh[b].l ? sh[a].l < sh[b].l : sh[a].np < sh[b].np;
+  });
+  std::vector<int4> ginfo;
+  std::vector<double> gxyz, galpha, gcoef;
+  std::vector<int> gatom;
+  std::vector<int> canon;  // permuted function -> canonical function (-1 padding)
+  size_t pos = 0;
+  int slot = 0, pfn = 0;
+  while (pos < order.size()) {
+    const int l = sh[order[pos]].l, np = sh[order[pos]].np;
+    int members[4];
+    int nm = 0;
+    while (nm < 4 && pos < order.size() && sh[order[pos]].l == l && sh[order[pos]].np == np)
+      members[nm++] = order[pos++];
+    ginfo.push_back(make_int4(l, np, pfn, slot));
+    for (int q = 0; q < 4; ++q) {
+      if (q < nm) {
+        const Sh &x = sh[members[q]];
+        for (int d = 0; d < 3; ++d) gxyz.push_back(s.ion_xyz[3 * x.atom + d]);
+        gatom.push_back(x.atom);
+      } else {
+        for (int d = 0; d < 3; ++d) gxyz.push_back(s.ion_xyz[d]);
+        gatom.push_back(-1);
+      }
+    }
+    galpha.resize(slot + 4 * np);
+    gcoef.resize(slot + 4 * np);
+    for (int p = 0; p < np; ++p)
+      for (int q = 0; q < 4; ++q) {
+        if (q < nm) {
+          galpha[slot + p * 4 + q] = s.prim_alpha[sh[members[q]].prim0 + p];
+          gcoef[slot + p * 4 + q] = s.prim_coef[sh[members[q]].prim0 + p];
+        } else {
+          galpha[slot + p * 4 + q] = 1.0;
+          gcoef[slot + p * 4 + q] = 0.0;
+        }
+      }
+    for (int comp = 0; comp < NCART_[l]; ++comp)
+      for (int q = 0; q < 4; ++q) canon.push_back(q < nm ? sh[members[q]].fn0 + comp : -1);
+    slot += 4 * np;
+    pfn += 4 * NCART_[l];
+  }
+  const int n_group = (int)ginfo.size();
+  std::vector<int2> stages;
+  int g = 0;
+  while (g < n_group) {
+    int g1 = g, f = 0;
+    while (g1 < n_group && f + 4 * NCART_[ginfo[g1].x] <= FMAX) { f += 4 * NCART_[ginfo[g1].x]; ++g1; }
+    stages.push_back(make_int2(g, g1));
+    g = g1;
+  }
+  const int NP = c->NP;
+  std::vector<double> Cp((size_t)pfn * NP, 0.0);
+  std::vector<float> Cp32((size_t)pfn * NP, 0.0f);
+  for (int r = 0; r < pfn; ++r) {
+    if (canon[r] < 0) continue;
+    for (int j = 0; j < n_orb; ++j) {
+      Cp[(size_t)r * NP + j] = s.mo_coef[(size_t)canon[r] * s.n_mo + j];
+      Cp32[(size_t)r * NP + j] = (float)Cp[(size_t)r * NP + j];
+    }
+  }
+  DevBasis &B = c->dc.B;
+  dmcx_status st;
+  int4 *d_ginfo; double *d_gxyz, *d_galpha, *d_gcoef, *d_Cp; float *d_Cp32; int *d_gatom;
+  int2 *d_stages;
+  if ((st = upload(c, &d_ginfo, ginfo))) return st;
+  if ((st = upload(c, &d_gxyz, gxyz))) return st;
+  if ((st = upload(c, &d_galpha, galpha))) return st;
+  if ((st = upload(c, &d_gcoef, gcoef))) return st;
+  if ((st = upload(c, &d_gatom, gatom))) return st;
+  if ((st = upload(c, &d_stages, stages))) return st;
+  if ((st = upload(c, &d_Cp, Cp))) return st;
+  if ((st = upload(c, &d_Cp32, Cp32))) return st;
+  B.n_group = n_group;
+  B.ginfo = d_ginfo;
+  B.gxyz = d_gxyz;
+  B.galpha = d_galpha;
+  B.gcoef = d_gcoef;
+  B.gatom = d_gatom;
+  B.n_stage = (int)stages.size();
+  B.stages = d_stages;
+  B.Kp = pfn;
+  B.Cp = d_Cp;
+  B.Cp32 = d_Cp32;
+  return DMCX_OK;
+}
+
+// ------------------------------------------------------------ launches --
+template <int NOB>
+void launch_orbitals_all(dmcx_ctx *c) {
+  const int npts = c->Wpad * c->ne;
+  hipLaunchKernelGGL(k_orbitals_all<NOB>, dim3((npts + TW - 1) / TW), dim3(NTHREADS), 0, c->stream,
+                     c->dc);
+}
+template <int NOB>
+void launch_orbitals_at(dmcx_ctx *c, const double *pos, int npts, double *dst) {
+  hipLaunchKernelGGL(k_orbitals_at<NOB>, dim3((npts + TW - 1) / TW), dim3(NTHREADS), 0, c->stream,
+                     c->dc, pos, npts, dst);
+}
+template <int NOB>
+void launch_sweep(dmcx_ctx *c, int mode, uint32_t step, uint8_t *acc) {
+  hipLaunchKernelGGL(k_sweep<NOB>, dim3(c->Wpad / TW), dim3(NTHREADS), 0, c->stream, c->dc, mode,
+                     step, acc);
+}
+
+#define DISPATCH_NOB(fn, ...)                         \
+  switch (c->NOB) {                                   \
+    case 1: fn<1>(__VA_ARGS__); break;                \
+    case 2: fn<2>(__VA_ARGS__); break;                \
+    case 3: fn<3>(__VA_ARGS__); break;                \
+    case 4: fn<4>(__VA_ARGS__); break;                \
+    case 5: fn<5>(__VA_ARGS__); break;                \
+    case 6: fn<6>(__VA_ARGS__); break;                \
+    case 7: fn<7>(__VA_ARGS__); break;                \
+    default: fn<8>(__VA_ARGS__); break;               \
+  }
+
+dmcx_status launch_inverse(dmcx_ctx *c) {
+  const int n = std::max(c->n_up, c->n_dn);
+  const size_t lds = (size_t)n * n * sizeof(double);
+  hipLaunchKernelGGL(k_inverse, dim3(c->Wpad, 2), dim3(NTHREADS), lds, c->stream, c->dc);
+  return hip_check(c, hipGetLastError(), "k_inverse launch");
+}
+
+dmcx_status launch_local_energy(dmcx_ctx *c, int mode, double e_trial, double *e_log_row) {
+  hipLaunchKernelGGL(k_local_energy, dim3(c->Wpad), dim3(NTHREADS), 0, c->stream, c->dc, mode,
+                     e_trial, e_log_row);
+  return hip_check(c, hipGetLastError(), "k_local_energy launch");
+}
+
+__global__ void k_fill_pad(double *a, int W, int Wpad, int stride) {
+  // copy walker 0's data into padded walker slots W..Wpad-1
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = (Wpad - W) * stride;
+  if (i < n) a[(size_t)W * stride + i] = a[i % stride];
+}
+
+__global__ void k_measure_out(DevCtx c, double *e, double *lp, int8_t *sg) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= c.W) return;
+  if (e) e[w] = c.eloc[w];
+  if (lp) lp[w] = c.logpsi[w];
+  if (sg) sg[w] = (int8_t)(c.sgn[2 * w] * c.sgn[2 * w + 1]);
+}
+
+__global__ void k_flags_out(DevCtx c, uint8_t *f) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < c.W) f[w] = (uint8_t)c.flags[w];
+}
+
+__global__ void k_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, int n, uint32_t *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Philox4 p = philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1);
+  for (int q = 0; q < 4; ++q) out[4 * i + q] = p.x[q];
+}
+
+// One 16x16x4 MFMA per precision on known operands, for the layout check.
+__global__ void k_mfma_probe(const double *A, const double *B, double *D, const float *Af,
+                             const float *Bf, float *Df) {
+  const int l = threadIdx.x;
+  v4d acc = {0, 0, 0, 0};
+  acc = mfma16x16x4(A[(l % 16) * 4 + l / 16], B[(l / 16) * 16 + l % 16], acc);
+  for (int r = 0; r < 4; ++r) D[Acc4<double>::row(l / 16, r) * 16 + l % 16] = acc[r];
+  v4f accf = {0, 0, 0, 0};
+  accf = mfma16x16x4(Af[(l % 16) * 4 + l / 16], Bf[(l / 16) * 16 + l % 16], accf);
+  for (int r = 0; r < 4; ++r) Df[Acc4<float>::row(l / 16, r) * 16 + l % 16] = accf[r];
+}
+
+dmcx_status ensure_stage(dmcx_ctx *c, void **p, size_t *have, size_t need) {
+  if (*have >= need) return DMCX_OK;
+  void *q = nullptr;
+  if (hipMalloc(&q, need) != hipSuccess) return fail(c, DMCX_E_NOMEM, "hipMalloc (log staging)");
+  c->mem.ptrs.push_back(q);
+  *p = q;
+  *have = need;
+  return DMCX_OK;
+}
+
+dmcx_status check_flags_host(dmcx_ctx *c) {
+  std::vector<unsigned> f(c->W);
+  HIP_TRY(c, hipMemcpyAsync(f.data(), c->dc.flags, c->W * sizeof(unsigned), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  unsigned any = 0;
+  for (unsigned x : f) any |= x;
+  if (any & 2u) return fail(c, DMCX_E_SINGULAR, "a Slater matrix had a zero pivot");
+  if (any & 1u) return fail(c, DMCX_E_NONFINITE, "non-finite value in some walker");
+  return DMCX_OK;
+}
+
+}  // namespace
+
+// ================================================================ C-ABI ==
+extern "C" {
+
+const char *dmcx_strerror(dmcx_status s) {
+  switch (s) {
+    case DMCX_OK: return "ok";
+    case DMCX_E_INVALID: return "invalid argument";
+    case DMCX_E_NOMEM: return "out of device memory";
+    case DMCX_E_HIP: return "HIP runtime error";
+    case DMCX_E_SINGULAR: return "singular Slater matrix";
+    case DMCX_E_NONFINITE: return "non-finite walker value";
+    case DMCX_E_STATE: return "call out of order";
+    case DMCX_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char *dmcx_last_error(const dmcx_ctx *c) { return c ? c->err.c_str() : ""; }
+
+dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *walkers_per_sys,
+                        const dmcx_options *opt, void *hip_stream, dmcx_ctx **out) {
+  if (!out || !sys || !walkers_per_sys || !opt) return DMCX_E_INVALID;
+  *out = nullptr;
+  dmcx_ctx *c = new dmcx_ctx();
+  c->stream = (hipStream_t)hip_stream;
+  c->opt = *opt;
+  auto bail = [&](dmcx_status s) {
+    fprintf(stderr, "dmcx_create: %s\n", c->err.c_str());
+    delete c;
+    return s;
+  };
+  if (n_sys != 1) {
+    c->err = "n_sys > 1 (uneven multi-system batching) not built yet";
+    return bail(DMCX_E_UNSUPPORTED);
+  }
+  if (!(opt->tau > 0.0) || opt->recompute_period < 1 || opt->flags != 0 ||
+      (opt->precision != DMCX_FP64 && opt->precision != DMCX_MIXED) || opt->delay_rank < 0 ||
+      opt->delay_rank > KMAX) {
+    c->err = "invalid options";
+    return bail(DMCX_E_INVALID);
+  }
+  if (opt->precision == DMCX_MIXED) {
+    c->err = "mixed precision not built yet";
+    return bail(DMCX_E_UNSUPPORTED);
+  }
+  const dmcx_system &s = sys[0];
+  dmcx_status st = validate_system(c, s);
+  if (st) return bail(st);
+  if (walkers_per_sys[0] < 1) {
+    c->err = "need at least one walker";
+    return bail(DMCX_E_INVALID);
+  }
+  c->W = walkers_per_sys[0];
+  c->Wpad = (c->W + TW - 1) / TW * TW;
+  c->n_up = s.n_up;
+  c->n_dn = s.n_dn;
+  c->ne = s.n_up + s.n_dn;
+  c->n_atom = s.n_atom;
+  c->n_basis = s.n_basis;
+  const int n_orb = std::max(s.n_up, s.n_dn);
+  c->NOB = (n_orb + 15) / 16;
+  c->NP = 16 * c->NOB;
+  const int kdef = std::min(32, n_orb);
+  c->K = opt->delay_rank == 0 ? kdef : std::min(opt->delay_rank, n_orb);
+  c->P = opt->recompute_period;
+  c->ion_xyz.assign(s.ion_xyz, s.ion_xyz + 3 * s.n_atom);
+  if ((st = pack_basis(c, s, n_orb))) return bail(st);
+  DevCtx &d = c->dc;
+  d.NP = c->NP;
+  d.ne = c->ne;
+  d.n_up = c->n_up;
+  d.n_dn = c->n_dn;
+  d.n_atom = c->n_atom;
+  double *d_ion, *d_Z, *d_jen;
+  std::vector<double> hZ(s.ion_charge, s.ion_charge + s.n_atom), hj(s.jen_a, s.jen_a + s.n_atom);
+  if ((st = upload(c, &d_ion, c->ion_xyz))) return bail(st);
+  if ((st = upload(c, &d_Z, hZ))) return bail(st);
+  if ((st = upload(c, &d_jen, hj))) return bail(st);
+  d.ion = d_ion;
+  d.Z = d_Z;
+  d.jen_a = d_jen;
+  d.jen_b = s.jen_b;
+  d.jee_anti = s.jee_a_anti;
+  d.jee_para = s.jee_a_para;
+  d.jee_b = s.jee_b;
+  double vnn = 0.0;
+  for (int a = 0; a < s.n_atom; ++a)
+    for (int b = a + 1; b < s.n_atom; ++b) {
+      const double dx = s.ion_xyz[3 * a] - s.ion_xyz[3 * b], dy = s.ion_xyz[3 * a + 1] - s.ion_xyz[3 * b + 1],
+                   dz = s.ion_xyz[3 * a + 2] - s.ion_xyz[3 * b + 2];
+      vnn += s.ion_charge[a] * s.ion_charge[b] / std::sqrt(dx * dx + dy * dy + dz * dz);
+    }
+  d.v_nn = vnn;
+  d.W = c->W;
+  d.Wpad = c->Wpad;
+  d.K = c->K;
+  d.tau = opt->tau;
+  d.seed = opt->seed;
+  const size_t Wp = c->Wpad;
+  if ((st = dalloc(c, &d.R, Wp * c->ne * 3))) return bail(st);
+  if ((st = dalloc(c, &d.vglc, Wp * c->ne * 5 * c->NP))) return bail(st);
+  if ((st = dalloc(c, &d.GT, Wp * 2 * c->NP * c->NP))) return bail(st);
+  if ((st = dalloc(c, &d.Gb, Wp * c->K * c->NP))) return bail(st);
+  if ((st = dalloc(c, &d.Dl, Wp * c->K * c->NP))) return bail(st);
+  if ((st = dalloc(c, &d.Zs, Wp * c->K * c->NP))) return bail(st);
+  if ((st = dalloc(c, &d.logdet, Wp * 2))) return bail(st);
+  if ((st = dalloc(c, &d.sgn, Wp * 2))) return bail(st);
+  if ((st = dalloc(c, &d.eloc, Wp))) return bail(st);
+  if ((st = dalloc(c, &d.logw, Wp))) return bail(st);
+  if ((st = dalloc(c, &d.logpsi, Wp))) return bail(st);
+  if ((st = dalloc(c, &d.flags, Wp))) return bail(st);
+  if ((st = dalloc(c, &c->d_pos, Wp * 3))) return bail(st);
+  if ((st = dalloc(c, &c->d_orb, Wp * 5 * c->NP))) return bail(st);
+  if (hipMemsetAsync(d.flags, 0, Wp * sizeof(unsigned), c->stream) != hipSuccess ||
+      hipMemsetAsync(d.logw, 0, Wp * sizeof(double), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    c->err = "initialisation copies failed";
+    return bail(DMCX_E_HIP);
+  }
+  *out = c;
+  return DMCX_OK;
+}
+
+void dmcx_destroy(dmcx_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+dmcx_status dmcx_set_walkers(dmcx_ctx *c, const double *R, const double *log_w, dmcx_mem mem) {
+  if (!c || !R) return DMCX_E_INVALID;
+  DevCtx &d = c->dc;
+  dmcx_status st;
+  const size_t per = (size_t)c->ne * 3;
+  if ((st = copy_in(c, d.R, R, c->W * per * sizeof(double), mem))) return st;
+  if (c->Wpad > c->W) {
+    const int n = (c->Wpad - c->W) * (int)per;
+    hipLaunchKernelGGL(k_fill_pad, dim3((n + 255) / 256), dim3(256), 0, c->stream, d.R, c->W,
+                       c->Wpad, (int)per);
+  }
+  if (log_w) {
+    if ((st = copy_in(c, d.logw, log_w, c->W * sizeof(double), mem))) return st;
+  } else {
+    HIP_TRY(c, hipMemsetAsync(d.logw, 0, c->Wpad * sizeof(double), c->stream));
+  }
+  HIP_TRY(c, hipMemsetAsync(d.flags, 0, c->Wpad * sizeof(unsigned), c->stream));
+  DISPATCH_NOB(launch_orbitals_all, c);
+  HIP_TRY(c, hipGetLastError());
+  if ((st = launch_inverse(c))) return st;
+  if ((st = launch_local_energy(c, -1, 0.0, nullptr))) return st;
+  c->step = 0;
+  c->walkers_set = true;
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_get_walkers(dmcx_ctx *c, double *R, double *log_w, dmcx_mem mem) {
+  if (!c || !c->walkers_set) return c ? fail(c, DMCX_E_STATE, "walkers not set") : DMCX_E_INVALID;
+  dmcx_status st;
+  if (R && (st = copy_out(c, R, c->dc.R, (size_t)c->W * c->ne * 3 * sizeof(double), mem))) return st;
+  if (log_w && (st = copy_out(c, log_w, c->dc.logw, (size_t)c->W * sizeof(double), mem))) return st;
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_set_step(dmcx_ctx *c, int64_t step) {
+  if (!c || step < 0) return DMCX_E_INVALID;
+  c->step = step;
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_get_step(const dmcx_ctx *c, int64_t *step) {
+  if (!c || !step) return DMCX_E_INVALID;
+  *step = c->step;
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_set_ions(dmcx_ctx *c, int32_t, const double *, dmcx_mem) {
+  return c ? fail(c, DMCX_E_UNSUPPORTED, "set_ions not built yet") : DMCX_E_INVALID;
+}
+
+dmcx_status dmcx_recompute(dmcx_ctx *c) {
+  if (!c || !c->walkers_set) return c ? fail(c, DMCX_E_STATE, "walkers not set") : DMCX_E_INVALID;
+  dmcx_status st = launch_inverse(c);
+  if (st) return st;
+  return check_flags_host(c);
+}
+
+dmcx_status dmcx_eval_orbitals(dmcx_ctx *c, int32_t spin, const double *r, double *vgl,
+                               dmcx_mem mem) {
+  if (!c || !r || !vgl || spin < 0 || spin > 1) return DMCX_E_INVALID;
+  dmcx_status st;
+  if ((st = copy_in(c, c->d_pos, r, (size_t)c->W * 3 * sizeof(double), mem))) return st;
+  DISPATCH_NOB(launch_orbitals_at, c, c->d_pos, c->W, c->d_orb);
+  HIP_TRY(c, hipGetLastError());
+  const int ns = spin == 0 ? c->n_up : c->n_dn;
+  if (ns == 0) return DMCX_OK;
+  HIP_TRY(c, hipMemcpy2DAsync(vgl, ns * sizeof(double), c->d_orb, c->NP * sizeof(double),
+                              ns * sizeof(double), (size_t)c->W * 5,
+                              mem == DMCX_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                              c->stream));
+  if (mem == DMCX_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_ratio_grad(dmcx_ctx *c, int32_t, const double *, double *, double *, dmcx_mem) {
+  return c ? fail(c, DMCX_E_UNSUPPORTED, "ratio_grad not built yet") : DMCX_E_INVALID;
+}
+dmcx_status dmcx_accept(dmcx_ctx *c, int32_t, const uint8_t *, dmcx_mem) {
+  return c ? fail(c, DMCX_E_UNSUPPORTED, "accept not built yet") : DMCX_E_INVALID;
+}
+dmcx_status dmcx_flush(dmcx_ctx *c) { return c ? DMCX_OK : DMCX_E_INVALID; }
+
+dmcx_status dmcx_run(dmcx_ctx *c, dmcx_mode mode, int32_t n_steps, double e_trial,
+                     uint8_t *accept_log, double *e_log, dmcx_mem mem) {
+  if (!c || n_steps < 0 || (mode != DMCX_VMC && mode != DMCX_DMC)) return DMCX_E_INVALID;
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  dmcx_status st;
+  const size_t acc_bytes = (size_t)n_steps * c->W * c->ne, elog_bytes = (size_t)n_steps * c->W * 8;
+  uint8_t *acc = accept_log;
+  double *elog = e_log;
+  if (accept_log && mem == DMCX_HOST) {
+    if ((st = ensure_stage(c, (void **)&c->d_acc_stage, &c->acc_stage_bytes, acc_bytes))) return st;
+    acc = c->d_acc_stage;
+  }
+  if (e_log && mem == DMCX_HOST) {
+    if ((st = ensure_stage(c, (void **)&c->d_elog_stage, &c->elog_stage_bytes, elog_bytes))) return st;
+    elog = c->d_elog_stage;
+  }
+  while ((int)c->ev.size() < 2 * n_steps) {
+    hipEvent_t e;
+    HIP_TRY(c, hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  for (int s = 0; s < n_steps; ++s) {
+    if (c->step % c->P == 0 && (st = launch_inverse(c))) return st;
+    HIP_TRY(c, hipEventRecord(c->ev[2 * s], c->stream));
+    DISPATCH_NOB(launch_sweep, c, (int)mode, (uint32_t)c->step,
+                 acc ? acc + (size_t)s * c->W * c->ne : nullptr);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipEventRecord(c->ev[2 * s + 1], c->stream));
+    if ((st = launch_local_energy(c, (int)mode, e_trial, elog ? elog + (size_t)s * c->W : nullptr)))
+      return st;
+    c->step++;
+  }
+  c->n_timed = n_steps;
+  if (accept_log && mem == DMCX_HOST) {
+    HIP_TRY(c, hipMemcpyAsync(accept_log, acc, acc_bytes, hipMemcpyDeviceToHost, c->stream));
+  }
+  if (e_log && mem == DMCX_HOST) {
+    HIP_TRY(c, hipMemcpyAsync(e_log, elog, elog_bytes, hipMemcpyDeviceToHost, c->stream));
+  }
+  if (mem == DMCX_HOST && (accept_log || e_log)) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_measure(dmcx_ctx *c, double *e_local, double *log_psi, int8_t *sign, dmcx_mem mem) {
+  if (!c) return DMCX_E_INVALID;
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  if (mem == DMCX_DEVICE) {
+    hipLaunchKernelGGL(k_measure_out, dim3((c->W + 255) / 256), dim3(256), 0, c->stream, c->dc,
+                       e_local, log_psi, sign);
+    return hip_check(c, hipGetLastError(), "k_measure_out");
+  }
+  // host: stage through the scratch orbital buffer
+  double *de = c->d_orb, *dl = c->d_orb + c->Wpad;
+  int8_t *ds = (int8_t *)(c->d_orb + 2 * c->Wpad);
+  hipLaunchKernelGGL(k_measure_out, dim3((c->W + 255) / 256), dim3(256), 0, c->stream, c->dc, de,
+                     dl, ds);
+  HIP_TRY(c, hipGetLastError());
+  if (e_local) HIP_TRY(c, hipMemcpyAsync(e_local, de, c->W * 8, hipMemcpyDeviceToHost, c->stream));
+  if (log_psi) HIP_TRY(c, hipMemcpyAsync(log_psi, dl, c->W * 8, hipMemcpyDeviceToHost, c->stream));
+  if (sign) HIP_TRY(c, hipMemcpyAsync(sign, ds, c->W, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_ion_grads(dmcx_ctx *c, double *, double *, dmcx_mem) {
+  return c ? fail(c, DMCX_E_UNSUPPORTED, "ion_grads not built yet") : DMCX_E_INVALID;
+}
+dmcx_status dmcx_logpsi_vjp(dmcx_ctx *c, const double *, double *, dmcx_mem) {
+  return c ? fail(c, DMCX_E_UNSUPPORTED, "logpsi_vjp not built yet") : DMCX_E_INVALID;
+}
+dmcx_status dmcx_potential_vjp(dmcx_ctx *c, const double *, double *, dmcx_mem) {
+  return c ? fail(c, DMCX_E_UNSUPPORTED, "potential_vjp not built yet") : DMCX_E_INVALID;
+}
+dmcx_status dmcx_forces(dmcx_ctx *c, double *, dmcx_mem) {
+  return c ? fail(c, DMCX_E_UNSUPPORTED, "forces not built yet") : DMCX_E_INVALID;
+}
+
+dmcx_status dmcx_walker_flags(dmcx_ctx *c, uint8_t *flags, dmcx_mem mem) {
+  if (!c || !flags) return DMCX_E_INVALID;
+  uint8_t *dst = flags;
+  if (mem == DMCX_HOST) dst = (uint8_t *)c->d_orb;
+  hipLaunchKernelGGL(k_flags_out, dim3((c->W + 255) / 256), dim3(256), 0, c->stream, c->dc, dst);
+  HIP_TRY(c, hipGetLastError());
+  if (mem == DMCX_HOST) {
+    HIP_TRY(c, hipMemcpyAsync(flags, dst, c->W, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_sync(dmcx_ctx *c) {
+  if (!c) return DMCX_E_INVALID;
+  return hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+}
+
+dmcx_status dmcx_last_run_timing(const dmcx_ctx *cc, double *sweep_ms_avg, int32_t *n_launches,
+                                 double *total_ms) {
+  dmcx_ctx *c = const_cast<dmcx_ctx *>(cc);
+  if (!c) return DMCX_E_INVALID;
+  double tot = 0.0;
+  for (int s = 0; s < c->n_timed; ++s) {
+    HIP_TRY(c, hipEventSynchronize(c->ev[2 * s + 1]));
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[2 * s], c->ev[2 * s + 1]));
+    tot += ms;
+  }
+  if (sweep_ms_avg) *sweep_ms_avg = c->n_timed ? tot / c->n_timed : 0.0;
+  if (n_launches) *n_launches = c->n_timed;
+  if (total_ms) *total_ms = tot;
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_philox(const uint32_t *ctr, const uint32_t *key, int32_t n, uint32_t *out) {
+  if (!ctr || !key || !out || n < 0) return DMCX_E_INVALID;
+  if (n == 0) return DMCX_OK;
+  uint32_t *dc = nullptr, *dout = nullptr;
+  if (hipMalloc(&dc, (size_t)n * 16) != hipSuccess) return DMCX_E_NOMEM;
+  if (hipMalloc(&dout, (size_t)n * 16) != hipSuccess) { (void)hipFree(dc); return DMCX_E_NOMEM; }
+  dmcx_status st = DMCX_OK;
+  if (hipMemcpy(dc, ctr, (size_t)n * 16, hipMemcpyHostToDevice) != hipSuccess) st = DMCX_E_HIP;
+  if (!st) {
+    hipLaunchKernelGGL(k_philox, dim3((n + 255) / 256), dim3(256), 0, 0, dc, key[0], key[1], n, dout);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpy(out, dout, (size_t)n * 16, hipMemcpyDeviceToHost) != hipSuccess)
+      st = DMCX_E_HIP;
+  }
+  (void)hipFree(dc);
+  (void)hipFree(dout);
+  return st;
+}
+
+dmcx_status dmcx_selftest(void *hip_stream) {
+  hipStream_t s = (hipStream_t)hip_stream;
+  double hA[64], hB[64], hD[256];
+  float fA[64], fB[64], fD[256];
+  for (int i = 0; i < 64; ++i) {
+    hA[i] = 1.0 + i;            // A[i/4][i%4]
+    hB[i] = 0.5 * (i % 7) - i;  // B[i/16][i%16]
+    fA[i] = (float)(i % 5) - 2.0f;
+    fB[i] = (float)(i % 3) + 0.25f;
+  }
+  double *dA, *dB, *dD;
+  float *dfA, *dfB, *dfD;
+  if (hipMalloc(&dA, 64 * 8) || hipMalloc(&dB, 64 * 8) || hipMalloc(&dD, 256 * 8) ||
+      hipMalloc(&dfA, 64 * 4) || hipMalloc(&dfB, 64 * 4) || hipMalloc(&dfD, 256 * 4))
+    return DMCX_E_NOMEM;
+  dmcx_status st = DMCX_OK;
+  if (hipMemcpyAsync(dA, hA, 64 * 8, hipMemcpyHostToDevice, s) ||
+      hipMemcpyAsync(dB, hB, 64 * 8, hipMemcpyHostToDevice, s) ||
+      hipMemcpyAsync(dfA, fA, 64 * 4, hipMemcpyHostToDevice, s) ||
+      hipMemcpyAsync(dfB, fB, 64 * 4, hipMemcpyHostToDevice, s))
+    st = DMCX_E_HIP;
+  if (!st) {
+    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, s, dA, dB, dD, dfA, dfB, dfD);
+    if (hipGetLastError() || hipMemcpyAsync(hD, dD, 256 * 8, hipMemcpyDeviceToHost, s) ||
+        hipMemcpyAsync(fD, dfD, 256 * 4, hipMemcpyDeviceToHost, s) || hipStreamSynchronize(s))
+      st = DMCX_E_HIP;
+  }
+  if (!st) {
+    int bad64 = 0, bad32 = 0;
+    for (int i = 0; i < 16; ++i)
+      for (int j = 0; j < 16; ++j) {
+        double ref = 0.0, reff = 0.0;
+        for (int k = 0; k < 4; ++k) {
+          ref += hA[i * 4 + k] * hB[k * 16 + j];
+          reff += (double)fA[i * 4 + k] * (double)fB[k * 16 + j];
+        }
+        if (std::fabs(hD[i * 16 + j] - ref) > 1e-12 * (1.0 + std::fabs(ref))) {
+          if (!bad64++)
+            fprintf(stderr, "dmcx_selftest: f64 MFMA D[%d][%d] = %g, expected %g\n", i, j,
+                    hD[i * 16 + j], ref);
+          st = DMCX_E_INVALID;
+        }
+        if (std::fabs(fD[i * 16 + j] - reff) > 1e-5 * (1.0 + std::fabs(reff))) {
+          if (!bad32++)
+            fprintf(stderr, "dmcx_selftest: f32 MFMA D[%d][%d] = %g, expected %g\n", i, j,
+                    (double)fD[i * 16 + j], reff);
+          st = DMCX_E_INVALID;
+        }
+      }
+    if (bad32) {
+      for (int i = 0; i < 16; ++i) {
+        fprintf(stderr, "D32 row %2d:", i);
+        for (int j = 0; j < 16; ++j) fprintf(stderr, " %g", (double)fD[i * 16 + j]);
+        fprintf(stderr, "\n");
+      }
+    }
+    if (bad64) {
+      // dump the full observed f64 product to identify the operand layout
+      for (int i = 0; i < 16; ++i) {
+        fprintf(stderr, "D64 row %2d:", i);
+        for (int j = 0; j < 16; ++j) fprintf(stderr, " %g", hD[i * 16 + j]);
+        fprintf(stderr, "\n");
+      }
+      for (int i = 0; i < 16; ++i) {
+        fprintf(stderr, "REF row %2d:", i);
+        for (int j = 0; j < 16; ++j) {
+          double ref = 0.0;
+          for (int k = 0; k < 4; ++k) ref += hA[i * 4 + k] * hB[k * 16 + j];
+          fprintf(stderr, " %g", ref);
+        }
+        fprintf(stderr, "\n");
+      }
+    }
+  }
+  (void)hipFree(dA); (void)hipFree(dB); (void)hipFree(dD);
+  (void)hipFree(dfA); (void)hipFree(dfB); (void)hipFree(dfD);
+  if (st) return st;
+  // Philox known answer (key 0, counter 0)
+  const uint32_t c0[4] = {0, 0, 0, 0}, k0[2] = {0, 0};
+  uint32_t o[4];
+  st = dmcx_philox(c0, k0, 1, o);
+  if (st) return st;
+  if (o[0] != 0x6627e8d5u || o[1] != 0xe169c58du || o[2] != 0xbc57ac4cu || o[3] != 0x9b00dbd8u) {
+    fprintf(stderr, "dmcx_selftest: Philox known answer mismatch %08x %08x %08x %08x\n", o[0], o[1],
+            o[2], o[3]);
+    return DMCX_E_INVALID;
+  }
+  return DMCX_OK;
+}
+
+}  // extern "C"

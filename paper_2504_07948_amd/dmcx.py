@@ -1,0 +1,361 @@
+"""ctypes binding of libdmcx.so (include/dmcx.h), argument marshalling only.
+
+Every ``dmcx_*`` function below forwards to the C function of the same name.
+Arrays are numpy (host, DMCX_HOST) or torch CUDA/HIP tensors (device,
+DMCX_DEVICE; the pointer is ``tensor.data_ptr()``).  ``Context`` wraps a
+handle for the common calls.  The library must have been built
+(``paper_2504_07948_amd.build_ext.build()``); loading fails loudly otherwise:
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdmcx.so")
+
+DMCX_OK, DMCX_E_INVALID, DMCX_E_NOMEM, DMCX_E_HIP, DMCX_E_SINGULAR, DMCX_E_NONFINITE, \
+    DMCX_E_STATE, DMCX_E_UNSUPPORTED = range(8)
+DMCX_FP64, DMCX_MIXED = 0, 1
+DMCX_VMC, DMCX_DMC = 0, 1
+DMCX_HOST, DMCX_DEVICE = 0, 1
+
+EXPORTED = [
+    "dmcx_create", "dmcx_destroy", "dmcx_set_walkers", "dmcx_get_walkers", "dmcx_set_step",
+    "dmcx_get_step", "dmcx_set_ions", "dmcx_recompute", "dmcx_eval_orbitals", "dmcx_ratio_grad",
+    "dmcx_accept", "dmcx_flush", "dmcx_run", "dmcx_measure", "dmcx_ion_grads", "dmcx_logpsi_vjp",
+    "dmcx_potential_vjp", "dmcx_forces", "dmcx_walker_flags", "dmcx_sync", "dmcx_last_run_timing",
+    "dmcx_selftest", "dmcx_philox", "dmcx_strerror", "dmcx_last_error",
+]
+
+
+class dmcx_system(C.Structure):
+    _fields_ = [
+        ("n_atom", C.c_int32), ("ion_xyz", C.c_void_p), ("ion_charge", C.c_void_p),
+        ("n_shell", C.c_int32), ("shell_atom", C.c_void_p), ("shell_l", C.c_void_p),
+        ("shell_nprim", C.c_void_p), ("prim_alpha", C.c_void_p), ("prim_coef", C.c_void_p),
+        ("n_basis", C.c_int32), ("n_mo", C.c_int32), ("mo_coef", C.c_void_p),
+        ("n_up", C.c_int32), ("n_dn", C.c_int32),
+        ("jee_a_anti", C.c_double), ("jee_a_para", C.c_double), ("jee_b", C.c_double),
+        ("jen_a", C.c_void_p), ("jen_b", C.c_double),
+        ("n_det", C.c_int32), ("det_exc", C.c_void_p), ("ci_coef", C.c_void_p),
+    ]
+
+
+class dmcx_options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("delay_rank", C.c_int32),
+                ("recompute_period", C.c_int32), ("tau", C.c_double), ("seed", C.c_uint64),
+                ("flags", C.c_uint32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libdmcx.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2504_07948_amd.build_ext.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "dmcx_create": [P, I32, P, P, P, P],
+        "dmcx_destroy": [P],
+        "dmcx_set_walkers": [P, P, P, I32],
+        "dmcx_get_walkers": [P, P, P, I32],
+        "dmcx_set_step": [P, I64],
+        "dmcx_get_step": [P, P],
+        "dmcx_set_ions": [P, I32, P, I32],
+        "dmcx_recompute": [P],
+        "dmcx_eval_orbitals": [P, I32, P, P, I32],
+        "dmcx_ratio_grad": [P, I32, P, P, P, I32],
+        "dmcx_accept": [P, I32, P, I32],
+        "dmcx_flush": [P],
+        "dmcx_run": [P, I32, I32, D, P, P, I32],
+        "dmcx_measure": [P, P, P, P, I32],
+        "dmcx_ion_grads": [P, P, P, I32],
+        "dmcx_logpsi_vjp": [P, P, P, I32],
+        "dmcx_potential_vjp": [P, P, P, I32],
+        "dmcx_forces": [P, P, I32],
+        "dmcx_walker_flags": [P, P, I32],
+        "dmcx_sync": [P],
+        "dmcx_last_run_timing": [P, P, P, P],
+        "dmcx_selftest": [P],
+        "dmcx_philox": [P, P, I32, P],
+        "dmcx_strerror": [I32],
+        "dmcx_last_error": [P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = I32
+    lib.dmcx_destroy.restype = None
+    lib.dmcx_strerror.restype = C.c_char_p
+    lib.dmcx_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+class DmcxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"dmcx status {status}: {msg}")
+        self.status = status
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()  # torch tensor
+
+
+def _mem(a):
+    if a is None or isinstance(a, np.ndarray):
+        return DMCX_HOST
+    return DMCX_DEVICE if a.is_cuda else DMCX_HOST
+
+
+# ---------------------------------------------------------- same names ----
+def dmcx_create(sys_struct, n_sys, walkers_per_sys, opt, stream, out):
+    return load().dmcx_create(sys_struct, n_sys, walkers_per_sys, opt, stream, out)
+
+
+def dmcx_destroy(ctx):
+    load().dmcx_destroy(ctx)
+
+
+def dmcx_set_walkers(ctx, R, log_w, mem):
+    return load().dmcx_set_walkers(ctx, R, log_w, mem)
+
+
+def dmcx_get_walkers(ctx, R, log_w, mem):
+    return load().dmcx_get_walkers(ctx, R, log_w, mem)
+
+
+def dmcx_set_step(ctx, step):
+    return load().dmcx_set_step(ctx, step)
+
+
+def dmcx_get_step(ctx, step_ptr):
+    return load().dmcx_get_step(ctx, step_ptr)
+
+
+def dmcx_set_ions(ctx, sys_index, ion_xyz, mem):
+    return load().dmcx_set_ions(ctx, sys_index, ion_xyz, mem)
+
+
+def dmcx_recompute(ctx):
+    return load().dmcx_recompute(ctx)
+
+
+def dmcx_eval_orbitals(ctx, spin, r, vgl, mem):
+    return load().dmcx_eval_orbitals(ctx, spin, r, vgl, mem)
+
+
+def dmcx_ratio_grad(ctx, iel, r_new, ratio, grad, mem):
+    return load().dmcx_ratio_grad(ctx, iel, r_new, ratio, grad, mem)
+
+
+def dmcx_accept(ctx, iel, accept, mem):
+    return load().dmcx_accept(ctx, iel, accept, mem)
+
+
+def dmcx_flush(ctx):
+    return load().dmcx_flush(ctx)
+
+
+def dmcx_run(ctx, mode, n_steps, e_trial, accept_log, e_log, mem):
+    return load().dmcx_run(ctx, mode, n_steps, e_trial, accept_log, e_log, mem)
+
+
+def dmcx_measure(ctx, e_local, log_psi, sign, mem):
+    return load().dmcx_measure(ctx, e_local, log_psi, sign, mem)
+
+
+def dmcx_ion_grads(ctx, dlogpsi, dv, mem):
+    return load().dmcx_ion_grads(ctx, dlogpsi, dv, mem)
+
+
+def dmcx_logpsi_vjp(ctx, gbar, grad_R, mem):
+    return load().dmcx_logpsi_vjp(ctx, gbar, grad_R, mem)
+
+
+def dmcx_potential_vjp(ctx, gbar, grad_R, mem):
+    return load().dmcx_potential_vjp(ctx, gbar, grad_R, mem)
+
+
+def dmcx_forces(ctx, F, mem):
+    return load().dmcx_forces(ctx, F, mem)
+
+
+def dmcx_walker_flags(ctx, flags, mem):
+    return load().dmcx_walker_flags(ctx, flags, mem)
+
+
+def dmcx_sync(ctx):
+    return load().dmcx_sync(ctx)
+
+
+def dmcx_last_run_timing(ctx, ms_avg, n, total):
+    return load().dmcx_last_run_timing(ctx, ms_avg, n, total)
+
+
+def dmcx_selftest(stream):
+    return load().dmcx_selftest(stream)
+
+
+def dmcx_philox(ctr, key, n, out):
+    return load().dmcx_philox(ctr, key, n, out)
+
+
+def dmcx_strerror(status):
+    return load().dmcx_strerror(status).decode()
+
+
+def dmcx_last_error(ctx):
+    return load().dmcx_last_error(ctx).decode()
+
+
+# ------------------------------------------------------------- wrapper ----
+class SystemStruct:
+    """dmcx_system built from a synthetic system (keeps its arrays alive)."""
+
+    def __init__(self, sys):
+        f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)
+        k = dict(ion_xyz=f64(sys.ion_xyz), ion_charge=f64(sys.ion_charge),
+                 shell_atom=i32(sys.shell_atom), shell_l=i32(sys.shell_l),
+                 shell_nprim=i32(sys.shell_nprim), prim_alpha=f64(sys.prim_alpha),
+                 prim_coef=f64(sys.prim_coef), mo_coef=f64(sys.mo_coef), jen_a=f64(sys.jen_a))
+        n_det = int(getattr(sys, "n_det", 0) or 0)
+        if n_det:
+            k["det_exc"] = i32(sys.det_exc)
+            k["ci_coef"] = f64(sys.ci_coef)
+        self.keep = k
+        self.c = dmcx_system(
+            n_atom=k["ion_xyz"].shape[0], ion_xyz=_ptr(k["ion_xyz"]),
+            ion_charge=_ptr(k["ion_charge"]), n_shell=k["shell_l"].shape[0],
+            shell_atom=_ptr(k["shell_atom"]), shell_l=_ptr(k["shell_l"]),
+            shell_nprim=_ptr(k["shell_nprim"]), prim_alpha=_ptr(k["prim_alpha"]),
+            prim_coef=_ptr(k["prim_coef"]), n_basis=k["mo_coef"].shape[0],
+            n_mo=k["mo_coef"].shape[1], mo_coef=_ptr(k["mo_coef"]), n_up=sys.n_up,
+            n_dn=sys.n_dn, jee_a_anti=sys.jee_a_anti, jee_a_para=sys.jee_a_para,
+            jee_b=sys.jee_b, jen_a=_ptr(k["jen_a"]), jen_b=sys.jen_b, n_det=n_det,
+            det_exc=_ptr(k.get("det_exc")), ci_coef=_ptr(k.get("ci_coef")))
+
+
+class Context:
+    """Owns one dmcx context for one or more systems."""
+
+    def __init__(self, systems, walkers, precision=DMCX_FP64, delay_rank=0, recompute_period=64,
+                 tau=0.01, seed=1, stream=None):
+        if not isinstance(systems, (list, tuple)):
+            systems = [systems]
+            walkers = [walkers]
+        self.systems = list(systems)
+        self.structs = [SystemStruct(s) for s in systems]
+        arr = (dmcx_system * len(systems))(*[s.c for s in self.structs])
+        wps = np.ascontiguousarray(walkers, dtype=np.int32)
+        self.W = int(wps.sum())
+        self.ne = max(s.n_up + s.n_dn for s in systems)
+        self.n_atom = max(s.n_atom for s in systems)
+        opt = dmcx_options(precision=precision, delay_rank=delay_rank,
+                           recompute_period=recompute_period, tau=tau, seed=seed, flags=0)
+        h = C.c_void_p()
+        st = load().dmcx_create(arr, len(systems), _ptr(wps), C.byref(opt), stream, C.byref(h))
+        if st != DMCX_OK:
+            raise DmcxError(st, "dmcx_create failed: " + dmcx_strerror(st))
+        self.h = h
+        self._keep = (arr, wps, opt)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().dmcx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st):
+        if st != DMCX_OK:
+            raise DmcxError(st, dmcx_last_error(self.h) or dmcx_strerror(st))
+
+    def set_walkers(self, R, log_w=None):
+        if isinstance(R, np.ndarray):
+            R = np.ascontiguousarray(R, dtype=np.float64)
+            log_w = None if log_w is None else np.ascontiguousarray(log_w, dtype=np.float64)
+        self.check(dmcx_set_walkers(self.h, _ptr(R), _ptr(log_w), _mem(R)))
+
+    def get_walkers(self):
+        R = np.zeros((self.W, self.ne, 3))
+        lw = np.zeros(self.W)
+        self.check(dmcx_get_walkers(self.h, _ptr(R), _ptr(lw), DMCX_HOST))
+        return R, lw
+
+    def set_step(self, step):
+        self.check(dmcx_set_step(self.h, step))
+
+    def run(self, n_steps, mode=DMCX_DMC, e_trial=0.0, logs=False):
+        acc = np.zeros((n_steps, self.W, self.ne), dtype=np.uint8) if logs else None
+        el = np.zeros((n_steps, self.W)) if logs else None
+        self.check(dmcx_run(self.h, mode, n_steps, e_trial, _ptr(acc), _ptr(el), DMCX_HOST))
+        return acc, el
+
+    def run_device(self, n_steps, mode=DMCX_DMC, e_trial=0.0, accept_log=None, e_log=None):
+        self.check(dmcx_run(self.h, mode, n_steps, e_trial, _ptr(accept_log), _ptr(e_log),
+                            DMCX_DEVICE))
+
+    def measure(self):
+        e = np.zeros(self.W)
+        lp = np.zeros(self.W)
+        sg = np.zeros(self.W, dtype=np.int8)
+        self.check(dmcx_measure(self.h, _ptr(e), _ptr(lp), _ptr(sg), DMCX_HOST))
+        return e, lp, sg
+
+    def recompute(self):
+        self.check(dmcx_recompute(self.h))
+
+    def eval_orbitals(self, spin, r):
+        n = self.systems[0].n_up if spin == 0 else self.systems[0].n_dn
+        out = np.zeros((self.W, 5, n))
+        self.check(dmcx_eval_orbitals(self.h, spin, _ptr(np.ascontiguousarray(r, dtype=np.float64)),
+                                      _ptr(out), DMCX_HOST))
+        return out
+
+    def walker_flags(self):
+        f = np.zeros(self.W, dtype=np.uint8)
+        self.check(dmcx_walker_flags(self.h, _ptr(f), DMCX_HOST))
+        return f
+
+    def sync(self):
+        self.check(dmcx_sync(self.h))
+
+    def last_run_timing(self):
+        a = C.c_double()
+        n = C.c_int32()
+        t = C.c_double()
+        self.check(dmcx_last_run_timing(self.h, C.byref(a), C.byref(n), C.byref(t)))
+        return a.value, n.value, t.value
+
+
+def selftest(stream=None):
+    return load().dmcx_selftest(stream)
+
+
+def philox(ctr, key):
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros_like(ctr)
+    st = load().dmcx_philox(_ptr(ctr), _ptr(key), ctr.shape[0], _ptr(out))
+    if st != DMCX_OK:
+        raise DmcxError(st, "dmcx_philox")
+    return out

@@ -1,0 +1,129 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 CPU oracle on
+the same seeded inputs.
+
+Bars (FP64 path): log|Psi|, E_L and orbital values within
+|d| <= 1e-10 * max(|x|, floor) (floor 1 for energies and log|Psi|, 1e-3 for
+ratios/orbitals); the accept/reject sequence bit-exact for the fixed Philox
+stream; positions to the same relative bound.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_07948_amd import dmcx, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _close(a, b, rel=1e-10, floor=1.0):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    tol = rel * np.maximum(np.maximum(np.abs(a), np.abs(b)), floor)
+    bad = np.abs(a - b) > tol
+    if bad.any():
+        idx = np.argsort(-(np.abs(a - b) / tol).ravel())[:10]
+        raise AssertionError(
+            f"{bad.sum()} of {bad.size} outside tolerance; worst: "
+            + ", ".join(f"{a.ravel()[i]!r} vs {b.ravel()[i]!r}" for i in idx))
+
+
+def test_device_selftest():
+    assert dmcx.selftest() == dmcx.DMCX_OK
+
+
+def test_device_philox_bit_exact():
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2 ** 32, size=(257, 4), dtype=np.uint64).astype(np.uint32)
+    key = np.array([0xDEADBEEF, 0x12345678], dtype=np.uint32)
+    dev = dmcx.philox(ctr, key)
+    ref = np.array([oracle.philox4x32_10(c, key) for c in ctr])
+    np.testing.assert_array_equal(dev, ref)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_orbitals_match_oracle(cfg):
+    s = synth.make_system(cfg)
+    W = 13  # ragged: not a multiple of the 8-walker tile
+    R = synth.make_walkers(s, W, 100 + cfg)
+    ctx = dmcx.Context(s, W)
+    ctx.set_walkers(R)
+    for spin in (0, 1):
+        pts = R[:, 3 * spin, :]
+        got = ctx.eval_orbitals(spin, pts)
+        n = s.n_up if spin == 0 else s.n_dn
+        ref = np.array([oracle.orbitals_vgl(s, p, n) for p in pts])
+        scale = np.abs(ref).max(axis=(0, 2), keepdims=True)
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * scale.max())
+
+
+@pytest.mark.parametrize("cfg,W", [(1, 64), (2, 13)])
+def test_initial_measure_matches_oracle(cfg, W):
+    s = synth.make_system(cfg)
+    R = synth.make_walkers(s, W, 200 + cfg)
+    ctx = dmcx.Context(s, W)
+    ctx.set_walkers(R)
+    e, lp, sg = ctx.measure()
+    lp_o, sg_o, e_o, rc = oracle.evaluate_batch(s, R)
+    assert rc == 0
+    np.testing.assert_array_equal(sg, sg_o)
+    _close(lp, lp_o)
+    _close(e, e_o)
+
+
+def _run_both(s, W, n_steps, mode, k, P, seed=7, tau=0.01, wseed=300):
+    R = synth.make_walkers(s, W, wseed)
+    lp_o, sg_o, e_o, _ = oracle.evaluate_batch(s, R)
+    e_t = float(np.mean(e_o))
+    ctx = dmcx.Context(s, W, delay_rank=k, recompute_period=P, tau=tau, seed=seed)
+    ctx.set_walkers(R)
+    acc, elog = ctx.run(n_steps, mode=mode, e_trial=e_t, logs=True)
+    Rg, lwg = ctx.get_walkers()
+    eg, lpg, sgg = ctx.measure()
+    ref = oracle.run(s, R, n_steps=n_steps, mode=mode, tau=tau, seed=seed, e_trial=e_t)
+    return dict(acc=acc, elog=elog, R=Rg, lw=lwg, e=eg, lp=lpg, sg=sgg), ref
+
+
+@pytest.mark.parametrize("mode", [dmcx.DMCX_VMC, dmcx.DMCX_DMC])
+def test_run_cfg1_parity(mode):
+    """Small molecule, 64 walkers, 20 steps, k = 1 (full update each move)."""
+    s = synth.make_system(1)
+    g, ref = _run_both(s, 64, 20, mode, k=1, P=64)
+    np.testing.assert_array_equal(g["acc"], ref["accept_log"])
+    _close(g["elog"], ref["e_log"])
+    _close(g["R"], ref["R"])
+    _close(g["lw"], ref["log_w"], floor=1e-3)
+    lp_o, sg_o, e_o, _ = oracle.evaluate_batch(s, ref["R"])
+    _close(g["lp"], lp_o)
+    np.testing.assert_array_equal(g["sg"], sg_o)
+
+
+@pytest.mark.parametrize("k,P", [(32, 64), (8, 1), (56, 2)])
+def test_run_cfg2_parity(k, P):
+    """The 112-electron system: 13 walkers (two tiles, ragged), 2 DMC steps,
+    delayed rank-k updates; several tiles and block boundaries."""
+    s = synth.make_system(2)
+    g, ref = _run_both(s, 13, 2, dmcx.DMCX_DMC, k=k, P=P)
+    np.testing.assert_array_equal(g["acc"], ref["accept_log"])
+    _close(g["elog"], ref["e_log"])
+    _close(g["R"], ref["R"])
+    _close(g["lw"], ref["log_w"], floor=1e-3)
+    lp_o, sg_o, e_o, _ = oracle.evaluate_batch(s, ref["R"])
+    _close(g["lp"], lp_o)
+    np.testing.assert_array_equal(g["sg"], sg_o)
+
+
+def test_delay_rank_invariance():
+    """k in {1, 8, 32, 56} produce the same trajectory to round-off."""
+    s = synth.make_system(2)
+    W = 8
+    R = synth.make_walkers(s, W, 400)
+    out = []
+    for k in (1, 8, 32, 56):
+        ctx = dmcx.Context(s, W, delay_rank=k, recompute_period=100)
+        ctx.set_walkers(R)
+        acc, el = ctx.run(2, mode=dmcx.DMCX_DMC, e_trial=0.0, logs=True)
+        out.append((acc, el, ctx.get_walkers()[0]))
+    for acc, el, Rk in out[1:]:
+        np.testing.assert_array_equal(acc, out[0][0])
+        _close(el, out[0][1], rel=1e-11)
+        _close(Rk, out[0][2], rel=1e-12)
