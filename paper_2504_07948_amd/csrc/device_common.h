@@ -95,6 +95,37 @@ __device__ inline void move_draws(uint64_t seed, uint32_t step, uint32_t walker,
   uacc = u0;
 }
 
+// Same draws computed by lanes 0, 1, 2 of a 32-lane walker group in
+// parallel (lane d evaluates draw d) and broadcast to the whole group.
+__device__ inline void move_draws_lanes(uint64_t seed, uint32_t step, uint32_t walker,
+                                        uint32_t elec, int t, double chi[3], double &uacc) {
+  const double two_pi = 6.283185307179586476925286766559;
+  double u0, u1;
+  uniform_pair(seed, step, walker, elec, t < 2 ? (uint32_t)t : 2u, u0, u1);
+  const double rad = sqrt(-2.0 * log(1.0 - u0));
+  const double cs = rad * cos(two_pi * u1);
+  const double sn = rad * sin(two_pi * u1);
+  chi[0] = __shfl(cs, 0, 32);
+  chi[1] = __shfl(sn, 0, 32);
+  chi[2] = __shfl(cs, 1, 32);
+  uacc = __shfl(u0, 2, 32);
+}
+
+// As above for a full 64-lane wave serving one walker.
+__device__ inline void move_draws_lanes64(uint64_t seed, uint32_t step, uint32_t walker,
+                                          uint32_t elec, int t, double chi[3], double &uacc) {
+  const double two_pi = 6.283185307179586476925286766559;
+  double u0, u1;
+  uniform_pair(seed, step, walker, elec, t < 2 ? (uint32_t)t : 2u, u0, u1);
+  const double rad = sqrt(-2.0 * log(1.0 - u0));
+  const double cs = rad * cos(two_pi * u1);
+  const double sn = rad * sin(two_pi * u1);
+  chi[0] = __shfl(cs, 0, 64);
+  chi[1] = __shfl(sn, 0, 64);
+  chi[2] = __shfl(cs, 1, 64);
+  uacc = __shfl(u0, 2, 64);
+}
+
 // ---------------------------------------------------------- reductions ----
 // Sum over the 32 lanes of one walker group (aligned halves of a wave).
 __device__ __forceinline__ double sum32(double v) {

@@ -134,7 +134,7 @@ dmcx_status validate_system(dmcx_ctx *c, const dmcx_system &s) {
 
 // Pack shells by (l, nprim) into groups of four (padding with zero-weight
 // shells), permute the LCAO rows to match, and split groups into stages of
-// at most FMAX functions.
+// one (l, nprim) type with at most 4 * stage_ksteps(NOB) functions.
 dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, int n_orb) {
   struct Sh { int l, np, atom, prim0, fn0; };
   std::vector<Sh> sh(s.n_shell);
@@ -190,11 +190,18 @@ dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, int n_orb) {
     pfn += 4 * NCART_[l];
   }
   const int n_group = (int)ginfo.size();
+  // stages: consecutive groups of one (l, nprim) type, at most fmax functions
   std::vector<int2> stages;
   int g = 0;
+  const int fmax = 4 * stage_ksteps(c->NOB);
   while (g < n_group) {
     int g1 = g, f = 0;
-    while (g1 < n_group && f + 4 * NCART_[ginfo[g1].x] <= FMAX) { f += 4 * NCART_[ginfo[g1].x]; ++g1; }
+    const int gmax = stage_max_groups(ginfo[g].x, c->NOB);
+    while (g1 < n_group && ginfo[g1].x == ginfo[g].x && ginfo[g1].y == ginfo[g].y &&
+           f + 4 * NCART_[ginfo[g1].x] <= fmax && g1 - g < gmax) {
+      f += 4 * NCART_[ginfo[g1].x];
+      ++g1;
+    }
     stages.push_back(make_int2(g, g1));
     g = g1;
   }
@@ -228,6 +235,7 @@ dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, int n_orb) {
   B.gatom = d_gatom;
   B.n_stage = (int)stages.size();
   B.stages = d_stages;
+  B.n_slot = slot;
   B.Kp = pfn;
   B.Cp = d_Cp;
   B.Cp32 = d_Cp32;
@@ -235,21 +243,32 @@ dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, int n_orb) {
 }
 
 // ------------------------------------------------------------ launches --
+size_t basis_lds(const dmcx_ctx *c) { return basis_lds_bytes(c->dc.B.n_group, c->dc.B.n_slot); }
+
+template <typename K>
+void allow_lds(K kernel, size_t dyn) {
+  (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)dyn);
+}
+
 template <int NOB>
 void launch_orbitals_all(dmcx_ctx *c) {
   const int npts = c->Wpad * c->ne;
-  hipLaunchKernelGGL(k_orbitals_all<NOB>, dim3((npts + TW - 1) / TW), dim3(NTHREADS), 0, c->stream,
-                     c->dc);
+  allow_lds(k_orbitals_all<NOB>, basis_lds(c));
+  hipLaunchKernelGGL(k_orbitals_all<NOB>, dim3((npts + TW - 1) / TW), dim3(NT_TILE), basis_lds(c),
+                     c->stream, c->dc);
 }
 template <int NOB>
 void launch_orbitals_at(dmcx_ctx *c, const double *pos, int npts, double *dst) {
-  hipLaunchKernelGGL(k_orbitals_at<NOB>, dim3((npts + TW - 1) / TW), dim3(NTHREADS), 0, c->stream,
-                     c->dc, pos, npts, dst);
+  allow_lds(k_orbitals_at<NOB>, basis_lds(c));
+  hipLaunchKernelGGL(k_orbitals_at<NOB>, dim3((npts + TW - 1) / TW), dim3(NT_TILE), basis_lds(c),
+                     c->stream, c->dc, pos, npts, dst);
 }
 template <int NOB>
 void launch_sweep(dmcx_ctx *c, int mode, uint32_t step, uint8_t *acc) {
-  hipLaunchKernelGGL(k_sweep<NOB>, dim3(c->Wpad / TW), dim3(NTHREADS), 0, c->stream, c->dc, mode,
-                     step, acc);
+  allow_lds(k_sweep<NOB>, basis_lds(c));
+  hipLaunchKernelGGL(k_sweep<NOB>, dim3(c->Wpad / TW), dim3(NT_TILE), basis_lds(c), c->stream,
+                     c->dc, mode, step, acc);
 }
 
 #define DISPATCH_NOB(fn, ...)                         \
@@ -267,12 +286,12 @@ void launch_sweep(dmcx_ctx *c, int mode, uint32_t step, uint8_t *acc) {
 dmcx_status launch_inverse(dmcx_ctx *c) {
   const int n = std::max(c->n_up, c->n_dn);
   const size_t lds = (size_t)n * n * sizeof(double);
-  hipLaunchKernelGGL(k_inverse, dim3(c->Wpad, 2), dim3(NTHREADS), lds, c->stream, c->dc);
+  hipLaunchKernelGGL(k_inverse, dim3(c->Wpad, 2), dim3(NT_AUX), lds, c->stream, c->dc);
   return hip_check(c, hipGetLastError(), "k_inverse launch");
 }
 
 dmcx_status launch_local_energy(dmcx_ctx *c, int mode, double e_trial, double *e_log_row) {
-  hipLaunchKernelGGL(k_local_energy, dim3(c->Wpad), dim3(NTHREADS), 0, c->stream, c->dc, mode,
+  hipLaunchKernelGGL(k_local_energy, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc, mode,
                      e_trial, e_log_row);
   return hip_check(c, hipGetLastError(), "k_local_energy launch");
 }
@@ -444,7 +463,10 @@ dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *wa
   if ((st = dalloc(c, &d.GT, Wp * 2 * c->NP * c->NP))) return bail(st);
   if ((st = dalloc(c, &d.Gb, Wp * c->K * c->NP))) return bail(st);
   if ((st = dalloc(c, &d.Dl, Wp * c->K * c->NP))) return bail(st);
-  if ((st = dalloc(c, &d.Zs, Wp * c->K * c->NP))) return bail(st);
+  d.K16 = (c->K + 15) / 16 * 16;
+  if ((st = dalloc(c, &d.Zs, Wp * d.K16 * c->NP))) return bail(st);
+  if ((st = dalloc(c, &d.Vs, Wp * d.K16 * c->NP))) return bail(st);
+  if ((st = dalloc(c, &d.Ms, Wp * c->K * c->K))) return bail(st);
   if ((st = dalloc(c, &d.logdet, Wp * 2))) return bail(st);
   if ((st = dalloc(c, &d.sgn, Wp * 2))) return bail(st);
   if ((st = dalloc(c, &d.eloc, Wp))) return bail(st);
@@ -772,5 +794,14 @@ dmcx_status dmcx_selftest(void *hip_stream) {
   }
   return DMCX_OK;
 }
+
+#ifdef DMCX_PHASE_TIMING
+// Profiling builds only: read and clear the per-phase cycle totals.
+void dmcx_debug_phase_cycles(unsigned long long out[16]) {
+  (void)hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase_cycles), 16 * sizeof(unsigned long long));
+  unsigned long long z[16] = {0};
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(g_phase_cycles), z, sizeof(z));
+}
+#endif
 
 }  // extern "C"

@@ -23,11 +23,59 @@
 
 namespace dmcx {
 
+// Optional per-phase cycle accounting of the sweep (off unless the library
+// is built with -DDMCX_PHASE_TIMING; used for profiling builds only).
+#ifdef DMCX_PHASE_TIMING
+__device__ unsigned long long g_phase_cycles[16];
+#define SUB_T(v) const unsigned long long v = __builtin_readcyclecounter()
+#define SUB_ADD(slot, a, b) \
+  do { if (threadIdx.x == 0) atomicAdd(&g_phase_cycles[slot], (b) - (a)); } while (0)
+#define SUB_ADD_ANY(slot, a, b) atomicAdd(&g_phase_cycles[slot], (b) - (a))
+#define PHASE_BEGIN() unsigned long long _ph_t = __builtin_readcyclecounter(), _ph_acc[8] = {0}
+#define PHASE_MARK(id)                                        \
+  do {                                                        \
+    const unsigned long long _n = __builtin_readcyclecounter(); \
+    _ph_acc[id] += _n - _ph_t;                                \
+    _ph_t = _n;                                               \
+  } while (0)
+#define PHASE_END()                                                            \
+  do {                                                                         \
+    if (threadIdx.x == 0)                                                      \
+      for (int _q = 0; _q < 8; ++_q) atomicAdd(&g_phase_cycles[_q], _ph_acc[_q]); \
+  } while (0)
+#else
+#define SUB_T(v) do {} while (0)
+#define SUB_ADD(slot, a, b) do {} while (0)
+#define SUB_ADD_ANY(slot, a, b) do {} while (0)
+#define PHASE_BEGIN() do {} while (0)
+#define PHASE_MARK(id) do {} while (0)
+#define PHASE_END() do {} while (0)
+#endif
+
 constexpr int TW = 8;        // walkers (or points) per workgroup tile
 constexpr int NCOL = 48;     // 5 VGL rows x 8 walkers = 40 MFMA columns, padded to 3 x 16
-constexpr int FMAX = 96;     // basis functions per LDS stage
-constexpr int NTHREADS = 256;
+constexpr int NT_TILE = 512; // tile kernels: 8 waves (4 MFMA waves + 4 basis waves)
+constexpr int NW_TILE = NT_TILE / 64;
+constexpr int NT_AUX = 256;  // per-walker kernels (inverse, local energy)
 constexpr int KMAX = 64;     // largest delay rank
+
+// K-steps (4 basis functions each) per LDS stage of the orbital tile; the
+// LCAO operands of a stage are held in registers, so wider orbital tiles use
+// shorter stages.
+__host__ __device__ constexpr int stage_ksteps(int nob) { return nob <= 4 ? 24 : 12; }
+
+// Basis work of one shell is split into this many lane tasks (s: whole
+// shell; p: components {x, y} and {z}; d: pairs of the six components).
+__host__ __device__ constexpr int shell_split(int l) { return l == 0 ? 1 : (l == 1 ? 2 : 3); }
+
+// Largest number of 4-shell groups of angular momentum l in one stage, so
+// that a stage has at most one basis task per thread and fits the stage's
+// register-held LCAO operands.
+__host__ __device__ constexpr int stage_max_groups(int l, int nob) {
+  return (NT_TILE / (TW * 4 * shell_split(l))) < (stage_ksteps(nob) / (l == 0 ? 1 : (l == 1 ? 3 : 6)))
+             ? (NT_TILE / (TW * 4 * shell_split(l)))
+             : (stage_ksteps(nob) / (l == 0 ? 1 : (l == 1 ? 3 : 6)));
+}
 
 struct DevBasis {
   int n_group;
@@ -38,10 +86,41 @@ struct DevBasis {
   const int *gatom;      // [n_group*4] atom of each shell, -1 for padding
   int n_stage;
   const int2 *stages;    // [n_stage] (first group, end group)
+  int n_slot;            // primitive slots (4 per primitive of each group)
   int Kp;                // permuted function count
   const double *Cp;      // [Kp][NP] permuted LCAO coefficients (zero padded)
   const float *Cp32;
 };
+
+// Shell tables staged in LDS once per launch, so that evaluating the basis
+// issues no global loads (which would drain the LCAO operand prefetch).
+struct BasisLDS {
+  const int4 *ginfo;
+  const double *xyz, *alpha, *coef;
+};
+
+__host__ __device__ inline size_t basis_lds_bytes(int n_group, int n_slot) {
+  return (size_t)n_group * sizeof(int4) + ((size_t)n_group * 12 + 2 * (size_t)n_slot) * 8;
+}
+
+__device__ inline BasisLDS stage_basis_lds(const DevBasis &B, char *smem) {
+  int4 *gi = (int4 *)smem;
+  double *xyz = (double *)(smem + (size_t)B.n_group * sizeof(int4));
+  double *al = xyz + (size_t)B.n_group * 12;
+  double *co = al + B.n_slot;
+  for (int i = threadIdx.x; i < B.n_group; i += blockDim.x) gi[i] = B.ginfo[i];
+  for (int i = threadIdx.x; i < B.n_group * 12; i += blockDim.x) xyz[i] = B.gxyz[i];
+  for (int i = threadIdx.x; i < B.n_slot; i += blockDim.x) {
+    al[i] = B.galpha[i];
+    co[i] = B.gcoef[i];
+  }
+  BasisLDS L;
+  L.ginfo = gi;
+  L.xyz = xyz;
+  L.alpha = al;
+  L.coef = co;
+  return L;
+}
 
 struct DevCtx {
   DevBasis B;
@@ -51,7 +130,7 @@ struct DevCtx {
   const double *Z;       // [n_atom]
   const double *jen_a;   // [n_atom]
   double jen_b, jee_anti, jee_para, jee_b, v_nn;
-  int W, Wpad, K;
+  int W, Wpad, K, K16;  // delay rank and its multiple-of-16 padding
   double tau;
   uint64_t seed;
   // walker state
@@ -60,7 +139,9 @@ struct DevCtx {
   double *GT;      // [Wpad][2][NP][NP]
   double *Gb;      // [Wpad][K][NP] current inverse columns of the electron block
   double *Dl;      // [Wpad][K][NP] value-row changes of the block's moves
-  double *Zs;      // [Wpad][K][NP] flush scratch
+  double *Zs;      // [Wpad][K16][NP] flush scratch: Z = Delta G0 (16-row padded)
+  double *Vs;      // [Wpad][K16][NP] flush scratch: Z' = M Z
+  double *Ms;      // [Wpad][K][K] M = (I + L)^{-1}, L[l][p] = Delta_l . u_p (p < l)
   double *logdet;  // [Wpad][2]
   double *sgn;     // [Wpad][2]
   double *eloc;    // [Wpad]
@@ -80,123 +161,292 @@ __device__ __forceinline__ size_t blk_off(const DevCtx &c, int w) {
 }
 
 // ------------------------------------------------------------ basis ----
-// Cartesian monomial P, its gradient and Laplacian for component `comp` of
-// angular momentum l at displacement (x, y, z); order p: x y z,
-// d: xx xy xz yy yz zz.
-__device__ __forceinline__ void cart_poly(int l, int comp, double x, double y, double z, double &P,
-                                          double &Px, double &Py, double &Pz, double &L) {
-  P = 1.0; Px = 0.0; Py = 0.0; Pz = 0.0; L = 0.0;
-  if (l == 1) {
-    if (comp == 0) { P = x; Px = 1.0; }
-    else if (comp == 1) { P = y; Py = 1.0; }
+// Cartesian monomial data for component COMP of angular momentum L.
+template <int L, int COMP>
+__device__ __forceinline__ void cart_poly_t(double x, double y, double z, double &P, double &Px,
+                                            double &Py, double &Pz, double &Lp) {
+  Px = 0.0; Py = 0.0; Pz = 0.0; Lp = 0.0;
+  if constexpr (L == 0) { P = 1.0; }
+  else if constexpr (L == 1) {
+    if constexpr (COMP == 0) { P = x; Px = 1.0; }
+    else if constexpr (COMP == 1) { P = y; Py = 1.0; }
     else { P = z; Pz = 1.0; }
-  } else if (l == 2) {
-    switch (comp) {
-      case 0: P = x * x; Px = 2.0 * x; L = 2.0; break;
-      case 1: P = x * y; Px = y; Py = x; break;
-      case 2: P = x * z; Px = z; Pz = x; break;
-      case 3: P = y * y; Py = 2.0 * y; L = 2.0; break;
-      case 4: P = y * z; Py = z; Pz = y; break;
-      default: P = z * z; Pz = 2.0 * z; L = 2.0; break;
+  } else {
+    if constexpr (COMP == 0) { P = x * x; Px = 2.0 * x; Lp = 2.0; }
+    else if constexpr (COMP == 1) { P = x * y; Px = y; Py = x; }
+    else if constexpr (COMP == 2) { P = x * z; Px = z; Pz = x; }
+    else if constexpr (COMP == 3) { P = y * y; Py = 2.0 * y; Lp = 2.0; }
+    else if constexpr (COMP == 4) { P = y * z; Py = z; Pz = y; }
+    else { P = z * z; Pz = 2.0 * z; Lp = 2.0; }
+  }
+}
+
+// VGL of one Cartesian function from the radial sums R0 = sum c e^{-a s2},
+// R1 = dR/d(s2), R2 = d2R/d(s2)^2:  grad = grad P R0 + 2 r R1 P,
+// lap = lap P R0 + 4 R1 (grad P . r) + P (6 R1 + 4 s2 R2).
+template <typename T, int L, int COMP>
+__device__ __forceinline__ void store_vgl(T *dst, double x, double y, double z, double s2,
+                                          double R0, double R1, double R2) {
+  double P, Px, Py, Pz, Lp;
+  cart_poly_t<L, COMP>(x, y, z, P, Px, Py, Pz, Lp);
+  const double tr = 2.0 * R1 * P;
+  dst[0] = (T)(P * R0);
+  dst[1] = (T)(Px * R0 + x * tr);
+  dst[2] = (T)(Py * R0 + y * tr);
+  dst[3] = (T)(Pz * R0 + z * tr);
+  dst[4] = (T)(Lp * R0 + 4.0 * R1 * (Px * x + Py * y + Pz * z) + P * (6.0 * R1 + 4.0 * s2 * R2));
+}
+
+// Basis values of one stage (groups g_begin..g_end, all with angular
+// momentum L and NPR primitives) at the tile's points into Bs[f][w*5 + q].
+// Tasks: s -> (point, shell); p -> (point, shell, {x,y} or {z});
+// d -> (point, shell, one of three component pairs).  A task evaluates its
+// shell's radial part (NPR independent exponentials) and its components.
+template <typename T, int L, int NPR>
+__device__ void basis_stage_t(const BasisLDS &B, int g_begin, int g_end, int fn_begin,
+                              const double (*pts)[3], T *Bs, int vt, int nvt, int npr_rt = NPR) {
+  constexpr int SPLIT = shell_split(L);
+  const int nsh = 4 * (g_end - g_begin);
+  const int ntask = TW * nsh * SPLIT;
+  for (int task = vt; task < ntask; task += nvt) {
+    const int w = task & (TW - 1);
+    const int rest = task >> 3;
+    const int sl = rest % nsh, part = rest / nsh;
+    const int g = g_begin + (sl >> 2), s = sl & 3;
+    const int4 gi = B.ginfo[g];
+    const double *cxyz = B.xyz + (size_t)(g * 4 + s) * 3;
+    const double x = pts[w][0] - cxyz[0], y = pts[w][1] - cxyz[1], z = pts[w][2] - cxyz[2];
+    const double s2 = x * x + y * y + z * z;
+    double R0 = 0.0, R1 = 0.0, R2 = 0.0;
+    if constexpr (NPR > 0) {
+      double e[NPR], a[NPR];
+#pragma unroll
+      for (int p = 0; p < NPR; ++p) {
+        a[p] = B.alpha[gi.w + p * 4 + s];
+        e[p] = B.coef[gi.w + p * 4 + s] * exp(-a[p] * s2);
+      }
+#pragma unroll
+      for (int p = 0; p < NPR; ++p) {
+        R0 += e[p];
+        R1 -= a[p] * e[p];
+        R2 += a[p] * a[p] * e[p];
+      }
+    } else {  // generic contraction depth
+      for (int p = 0; p < npr_rt; ++p) {
+        const double ap = B.alpha[gi.w + p * 4 + s];
+        const double ep = B.coef[gi.w + p * 4 + s] * exp(-ap * s2);
+        R0 += ep;
+        R1 -= ap * ep;
+        R2 += ap * ap * ep;
+      }
+    }
+    T *base = Bs + (size_t)(gi.z - fn_begin + s) * NCOL + w * 5;  // comp 0 of this shell
+    if constexpr (L == 0) {
+      store_vgl<T, 0, 0>(base, x, y, z, s2, R0, R1, R2);
+    } else if constexpr (L == 1) {
+      if (part == 0) {
+        store_vgl<T, 1, 0>(base, x, y, z, s2, R0, R1, R2);
+        store_vgl<T, 1, 1>(base + 4 * NCOL, x, y, z, s2, R0, R1, R2);
+      } else {
+        store_vgl<T, 1, 2>(base + 8 * NCOL, x, y, z, s2, R0, R1, R2);
+      }
+    } else {
+      if (part == 0) {
+        store_vgl<T, 2, 0>(base, x, y, z, s2, R0, R1, R2);
+        store_vgl<T, 2, 1>(base + 4 * NCOL, x, y, z, s2, R0, R1, R2);
+      } else if (part == 1) {
+        store_vgl<T, 2, 2>(base + 8 * NCOL, x, y, z, s2, R0, R1, R2);
+        store_vgl<T, 2, 3>(base + 12 * NCOL, x, y, z, s2, R0, R1, R2);
+      } else {
+        store_vgl<T, 2, 4>(base + 16 * NCOL, x, y, z, s2, R0, R1, R2);
+        store_vgl<T, 2, 5>(base + 20 * NCOL, x, y, z, s2, R0, R1, R2);
+      }
     }
   }
 }
 
-// Evaluate the stage's shells at the tile's points into Bs[f][w*5 + q].
+// Dispatch a uniform stage to its (l, nprim) specialisation.
 template <typename T>
-__device__ void basis_stage(const DevBasis &B, int g_begin, int g_end, int fn_begin,
-                            const double (*pts)[3], T *Bs) {
-  const int nsh = 4 * (g_end - g_begin);
-  for (int task = threadIdx.x; task < TW * nsh; task += NTHREADS) {
-    const int w = task & (TW - 1);
-    const int sl = task >> 3;
-    const int g = g_begin + (sl >> 2), s = sl & 3;
-    const int4 gi = B.ginfo[g];
-    const double *cxyz = B.gxyz + (size_t)(g * 4 + s) * 3;
-    const double x = pts[w][0] - cxyz[0], y = pts[w][1] - cxyz[1], z = pts[w][2] - cxyz[2];
-    const double s2 = x * x + y * y + z * z;
-    double R0 = 0.0, R1 = 0.0, R2 = 0.0;
-    for (int p = 0; p < gi.y; ++p) {
-      const double a = B.galpha[gi.w + p * 4 + s];
-      const double e = B.gcoef[gi.w + p * 4 + s] * exp(-a * s2);
-      R0 += e;
-      R1 -= a * e;
-      R2 += a * a * e;
+__device__ void basis_stage(const BasisLDS &B, int g_begin, int g_end, int fn_begin,
+                            const double (*pts)[3], T *Bs, int vt, int nvt) {
+  const int4 gi = B.ginfo[g_begin];
+#define DMCX_BASIS_CASE(LL, NN) \
+  case LL * 16 + NN: basis_stage_t<T, LL, NN>(B, g_begin, g_end, fn_begin, pts, Bs, vt, nvt); break;
+  switch (gi.x * 16 + (gi.y <= 4 ? gi.y : 0)) {
+    DMCX_BASIS_CASE(0, 1) DMCX_BASIS_CASE(0, 2) DMCX_BASIS_CASE(0, 3) DMCX_BASIS_CASE(0, 4)
+    DMCX_BASIS_CASE(1, 1) DMCX_BASIS_CASE(1, 2) DMCX_BASIS_CASE(1, 3) DMCX_BASIS_CASE(1, 4)
+    DMCX_BASIS_CASE(2, 1) DMCX_BASIS_CASE(2, 2) DMCX_BASIS_CASE(2, 3) DMCX_BASIS_CASE(2, 4)
+    case 0: basis_stage_t<T, 0, 0>(B, g_begin, g_end, fn_begin, pts, Bs, vt, nvt, gi.y); break;
+    case 16: basis_stage_t<T, 1, 0>(B, g_begin, g_end, fn_begin, pts, Bs, vt, nvt, gi.y); break;
+    case 32: basis_stage_t<T, 2, 0>(B, g_begin, g_end, fn_begin, pts, Bs, vt, nvt, gi.y); break;
+    default: break;
+  }
+#undef DMCX_BASIS_CASE
+}
+
+// Workgroup barrier that orders LDS traffic only: waits for this wave's LDS
+// operations, then synchronises.  Outstanding global loads stay in flight
+// (a plain __syncthreads would drain them), which lets the LCAO operands of
+// a stage load while the basis is being evaluated.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt, expcnt untouched
+  __builtin_amdgcn_s_barrier();
+}
+
+// LCAO operands of one stage for this wave's orbital blocks and K-parity
+// half kh (A operand; lane l holds C[f0 + 4 kk + l/16][ob*16 + l%16] for
+// K-steps kk = 2 i + kh).
+template <typename T, int NOB, int KH>
+__device__ __forceinline__ void load_stage_a(const T *Cp, int fn_begin, int nk, int ob0, int kh,
+                                             int kq, int col, T (&a)[(NOB + 3) / 4][KH]) {
+  constexpr int NQ = (NOB + 3) / 4;
+  constexpr int NP = NOB * 16;
+  const T *abase = Cp + (size_t)(fn_begin + 4 * kh + kq) * NP + col;
+#pragma unroll
+  for (int i = 0; i < KH; ++i)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int ob = ob0 + 4 * q;
+      a[q][i] = (2 * i + kh < nk && (NOB % 4 == 0 || ob < NOB))
+                    ? abase[(size_t)(8 * i) * NP + ob * 16]
+                    : (T)0;
     }
-    // grad R = 2 r R1 ; lap R = 6 R1 + 4 s2 R2
-    const double lapR = 6.0 * R1 + 4.0 * s2 * R2;
-    const int ncomp = gi.x == 0 ? 1 : (gi.x == 1 ? 3 : 6);
-    for (int comp = 0; comp < ncomp; ++comp) {
-      double P, Px, Py, Pz, L;
-      cart_poly(gi.x, comp, x, y, z, P, Px, Py, Pz, L);
-      T *dst = Bs + (size_t)(gi.z - fn_begin + comp * 4 + s) * NCOL + w * 5;
-      dst[0] = (T)(P * R0);
-      dst[1] = (T)(Px * R0 + 2.0 * x * R1 * P);
-      dst[2] = (T)(Py * R0 + 2.0 * y * R1 * P);
-      dst[3] = (T)(Pz * R0 + 2.0 * z * R1 * P);
-      dst[4] = (T)(L * R0 + 4.0 * R1 * (Px * x + Py * y + Pz * z) + P * lapR);
+}
+
+// This wave's K-steps of one stage: acc[q][cb] += A(block) * B(column block).
+// B operands come from LDS one K-step ahead of the MFMAs that use them.
+template <typename T, int NOB, int KH>
+__device__ __forceinline__ void mfma_stage(typename Acc4<T>::type (&acc)[(NOB + 3) / 4][3],
+                                           const T (&a)[(NOB + 3) / 4][KH], const T *Bsb, int nk,
+                                           int ob0, int kh, int kq, int col) {
+  constexpr int NQ = (NOB + 3) / 4;
+  if (kh >= nk) return;
+  const T *bbase = Bsb + (4 * kh + kq) * NCOL + col;
+  T bn0 = bbase[0], bn1 = bbase[16], bn2 = bbase[32];
+#pragma unroll
+  for (int i = 0; i < KH; ++i) {
+    if (2 * i + kh < nk) {
+      const T b0 = bn0, b1 = bn1, b2 = bn2;
+      if (2 * i + 2 + kh < nk) {
+        const T *brow = bbase + 8 * (i + 1) * NCOL;
+        bn0 = brow[0];
+        bn1 = brow[16];
+        bn2 = brow[32];
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        if (NOB % 4 == 0 || ob0 + 4 * q < NOB) {
+          acc[q][0] = mfma16x16x4(a[q][i], b0, acc[q][0]);
+          acc[q][1] = mfma16x16x4(a[q][i], b1, acc[q][1]);
+          acc[q][2] = mfma16x16x4(a[q][i], b2, acc[q][2]);
+        }
+      }
     }
   }
 }
 
 // Orbital VGL of the tile's TW points: out[w][q][orbital] (LDS, FP64).
-// All 256 threads must call.  Bs must hold FMAX*NCOL elements; its padding
-// columns 40..47 are cleared here.
+// All NT_TILE threads must call.  Stages of basis functions flow through two
+// LDS buffers: in each phase every wave runs its MFMAs on stage s (wave w
+// owns orbital blocks w%4 (+4, ...) and the K-steps of parity w/4) and then
+// all 512 threads evaluate the basis of stage s+1 into the other buffer;
+// the LCAO operands of stage s+1 are loaded into registers right after the
+// MFMAs of stage s are issued, so they arrive during the basis evaluation
+// and the barrier.  One barrier per stage; the two K-parity partial sums
+// are added once at the end.
 template <typename T, int NOB>
-__device__ void mo_tile(const DevCtx &c, const double (*pts)[3], T *Bs, double *out) {
-  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+__device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)[3], T *Bs0,
+                        T *Bs1, double *out) {
   constexpr int NQ = (NOB + 3) / 4;
   constexpr int NP = NOB * 16;
+  constexpr int KS = stage_ksteps(NOB);
+  constexpr int KH = KS / 2;
+  constexpr int FM = 4 * KS;
   typedef typename Acc4<T>::type acc_t;
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+  const int ob0 = wid & 3, kh = wid >> 2;
+  const int kq = lane >> 4, col = lane & 15;
+  const int S = c.B.n_stage;
+  const T *Cp;
+  if constexpr (sizeof(T) == 8) Cp = (const T *)c.B.Cp; else Cp = (const T *)c.B.Cp32;
   acc_t acc[NQ][3];
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int cb = 0; cb < 3; ++cb) acc[q][cb] = acc_t{0, 0, 0, 0};
-  const T *Cp;
-  if constexpr (sizeof(T) == 8) Cp = (const T *)c.B.Cp; else Cp = (const T *)c.B.Cp32;
-  for (int i = tid; i < FMAX * (NCOL - 40); i += NTHREADS)
-    Bs[(i / (NCOL - 40)) * NCOL + 40 + i % (NCOL - 40)] = (T)0;
-  const int kq = lane >> 4, col = lane & 15;
-  for (int st = 0; st < c.B.n_stage; ++st) {
-    const int2 sg = c.B.stages[st];
-    const int fn_begin = c.B.ginfo[sg.x].z;
-    const int fn_end = sg.y < c.B.n_group ? c.B.ginfo[sg.y].z : c.B.Kp;
-    __syncthreads();
-    basis_stage<T>(c.B, sg.x, sg.y, fn_begin, pts, Bs);
-    __syncthreads();
-    const int nk = (fn_end - fn_begin) >> 2;
-    for (int kk = 0; kk < nk; ++kk) {
-      const T *brow = Bs + (4 * kk + kq) * NCOL + col;
-      const T b0 = brow[0], b1 = brow[16], b2 = brow[32];
-      const T *arow = Cp + (size_t)(fn_begin + 4 * kk + kq) * NP + col;
+  T a0[NQ][KH], a1[NQ][KH];
+  int g0, g1, fb, nk;
+  auto stage_range = [&](int s) {
+    const int2 sg = c.B.stages[s];
+    g0 = sg.x;
+    g1 = sg.y;
+    fb = BL.ginfo[sg.x].z;
+    const int fe = sg.y < c.B.n_group ? BL.ginfo[sg.y].z : c.B.Kp;
+    nk = (fe - fb) >> 2;
+  };
+  stage_range(0);
+  load_stage_a<T, NOB, KH>(Cp, fb, nk, ob0, kh, kq, col, a0);
+  for (int i = tid; i < FM * (NCOL - 40); i += NT_TILE) {
+    Bs0[(i >> 3) * NCOL + 40 + (i & 7)] = (T)0;
+    Bs1[(i >> 3) * NCOL + 40 + (i & 7)] = (T)0;
+  }
+  basis_stage<T>(BL, g0, g1, fb, pts, Bs0, tid, NT_TILE);
+  lds_barrier();
+  for (int st = 0; st < S; st += 2) {
+    {  // MFMAs of stage st (a0, Bs0); stage st+1 -> (a1, Bs1)
+      SUB_T(tm0);
+      mfma_stage<T, NOB, KH>(acc, a0, Bs0, nk, ob0, kh, kq, col);
+      SUB_T(tm1);
+      if (st + 1 < S) {
+        stage_range(st + 1);
+        load_stage_a<T, NOB, KH>(Cp, fb, nk, ob0, kh, kq, col, a1);
+        basis_stage<T>(BL, g0, g1, fb, pts, Bs1, tid, NT_TILE);
+      }
+      SUB_T(tm2);
+      SUB_ADD(11, tm0, tm1);
+      SUB_ADD(9, tm1, tm2);
+      lds_barrier();
+    }
+    if (st + 1 >= S) break;
+    {  // MFMAs of stage st+1 (a1, Bs1); stage st+2 -> (a0, Bs0)
+      SUB_T(tm0);
+      mfma_stage<T, NOB, KH>(acc, a1, Bs1, nk, ob0, kh, kq, col);
+      SUB_T(tm1);
+      if (st + 2 < S) {
+        stage_range(st + 2);
+        load_stage_a<T, NOB, KH>(Cp, fb, nk, ob0, kh, kq, col, a0);
+        basis_stage<T>(BL, g0, g1, fb, pts, Bs0, tid, NT_TILE);
+      }
+      SUB_T(tm2);
+      SUB_ADD(11, tm0, tm1);
+      SUB_ADD(9, tm1, tm2);
+      lds_barrier();
+    }
+  }
+  // sum the two K-parity halves into out
+#pragma unroll
+  for (int half = 1; half >= 0; --half) {
+    if (kh == half) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int ob = wid + 4 * q;
-        if (ob < NOB) {
-          const T a = arow[ob * 16];
-          acc[q][0] = mfma16x16x4(a, b0, acc[q][0]);
-          acc[q][1] = mfma16x16x4(a, b1, acc[q][1]);
-          acc[q][2] = mfma16x16x4(a, b2, acc[q][2]);
+        const int ob = ob0 + 4 * q;
+        if (NOB % 4 == 0 || ob < NOB) {
+#pragma unroll
+          for (int cb = 0; cb < 3; ++cb) {
+            const int n = cb * 16 + col;
+            if (n < 40) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                double *o = out + n * NP + ob * 16 + Acc4<T>::row(kq, r);
+                *o = (half ? 0.0 : *o) + (double)acc[q][cb][r];
+              }
+            }
+          }
         }
       }
     }
+    __syncthreads();
   }
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int ob = wid + 4 * q;
-    if (ob < NOB) {
-#pragma unroll
-      for (int cb = 0; cb < 3; ++cb) {
-        const int n = cb * 16 + col;
-        if (n < 40) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) out[n * NP + ob * 16 + Acc4<T>::row(kq, r)] = (double)acc[q][cb][r];
-        }
-      }
-    }
-  }
-  __syncthreads();
 }
 
 // ---------------------------------------------------------- Jastrow ----
@@ -234,9 +484,13 @@ __device__ __forceinline__ void jastrow_one_partial(const DevCtx &c, const doubl
 // ------------------------------------------------------------ kernels ----
 // Orbital VGL at (walker, electron) points -> vglc (all electrons).
 template <int NOB>
-__global__ __launch_bounds__(NTHREADS) void k_orbitals_all(DevCtx c) {
-  __shared__ double Bs[FMAX * NCOL];
-  __shared__ double out[TW * 5 * NOB * 16];
+__global__ __launch_bounds__(NT_TILE) void k_orbitals_all(DevCtx c) {
+  constexpr int NP = NOB * 16;
+  constexpr int FM = 4 * stage_ksteps(NOB);
+  extern __shared__ __align__(16) char smem_basis[];
+  const BasisLDS BL = stage_basis_lds(c.B, smem_basis);
+  __shared__ double Bs0[FM * NCOL], Bs1[FM * NCOL];
+  __shared__ double out[TW * 5 * NP];
   __shared__ double pts[TW][3];
   const int npts = c.Wpad * c.ne;
   const int p0 = blockIdx.x * TW;
@@ -245,9 +499,8 @@ __global__ __launch_bounds__(NTHREADS) void k_orbitals_all(DevCtx c) {
     pts[threadIdx.x / 3][threadIdx.x % 3] = c.R[(size_t)p * 3 + threadIdx.x % 3];
   }
   __syncthreads();
-  mo_tile<double, NOB>(c, pts, Bs, out);
-  constexpr int NP = NOB * 16;
-  for (int i = threadIdx.x; i < TW * 5 * NP; i += NTHREADS) {
+  mo_tile<double, NOB>(c, BL, pts, Bs0, Bs1, out);
+  for (int i = threadIdx.x; i < TW * 5 * NP; i += NT_TILE) {
     const int w = i / (5 * NP);
     const int p = p0 + w;
     if (p < npts) c.vglc[(size_t)p * 5 * NP + (i - w * 5 * NP)] = out[i];
@@ -256,10 +509,14 @@ __global__ __launch_bounds__(NTHREADS) void k_orbitals_all(DevCtx c) {
 
 // Orbital VGL at one point per walker: pos [W][3] -> dst [W][5][NP].
 template <int NOB>
-__global__ __launch_bounds__(NTHREADS) void k_orbitals_at(DevCtx c, const double *pos, int npts,
-                                                          double *dst) {
-  __shared__ double Bs[FMAX * NCOL];
-  __shared__ double out[TW * 5 * NOB * 16];
+__global__ __launch_bounds__(NT_TILE) void k_orbitals_at(DevCtx c, const double *pos, int npts,
+                                                         double *dst) {
+  constexpr int NP = NOB * 16;
+  constexpr int FM = 4 * stage_ksteps(NOB);
+  extern __shared__ __align__(16) char smem_basis[];
+  const BasisLDS BL = stage_basis_lds(c.B, smem_basis);
+  __shared__ double Bs0[FM * NCOL], Bs1[FM * NCOL];
+  __shared__ double out[TW * 5 * NP];
   __shared__ double pts[TW][3];
   const int p0 = blockIdx.x * TW;
   if (threadIdx.x < TW * 3) {
@@ -267,9 +524,8 @@ __global__ __launch_bounds__(NTHREADS) void k_orbitals_at(DevCtx c, const double
     pts[threadIdx.x / 3][threadIdx.x % 3] = pos[(size_t)p * 3 + threadIdx.x % 3];
   }
   __syncthreads();
-  mo_tile<double, NOB>(c, pts, Bs, out);
-  constexpr int NP = NOB * 16;
-  for (int i = threadIdx.x; i < TW * 5 * NP; i += NTHREADS) {
+  mo_tile<double, NOB>(c, BL, pts, Bs0, Bs1, out);
+  for (int i = threadIdx.x; i < TW * 5 * NP; i += NT_TILE) {
     const int w = i / (5 * NP);
     if (p0 + w < npts) dst[(size_t)(p0 + w) * 5 * NP + (i - w * 5 * NP)] = out[i];
   }
@@ -279,12 +535,12 @@ __global__ __launch_bounds__(NTHREADS) void k_orbitals_at(DevCtx c, const double
 // elimination with partial pivoting, built from the cached value rows.
 // grid (Wpad, 2); dynamic LDS n*n doubles.  Writes GT (transposed, zero
 // padded), log|det| and sign; flags singular matrices.
-__global__ __launch_bounds__(NTHREADS) void k_inverse(DevCtx c) {
+__global__ __launch_bounds__(NT_AUX) void k_inverse(DevCtx c) {
   extern __shared__ double A[];
   __shared__ int piv[128];
   __shared__ double fcol[128];
-  __shared__ double pv_val[NTHREADS / 64];
-  __shared__ int pv_idx[NTHREADS / 64];
+  __shared__ double pv_val[NT_AUX / 64];
+  __shared__ int pv_idx[NT_AUX / 64];
   __shared__ double s_logdet;
   __shared__ int s_sign, s_sing;
   const int w = blockIdx.x, sp = blockIdx.y;
@@ -293,12 +549,12 @@ __global__ __launch_bounds__(NTHREADS) void k_inverse(DevCtx c) {
   const int tid = threadIdx.x;
   double *GT = c.GT + gt_off(c, w, sp);
   if (n == 0) {
-    for (int i = tid; i < NP * NP; i += NTHREADS) GT[i] = 0.0;
+    for (int i = tid; i < NP * NP; i += NT_AUX) GT[i] = 0.0;
     if (tid == 0) { c.logdet[w * 2 + sp] = 0.0; c.sgn[w * 2 + sp] = 1.0; }
     return;
   }
   const int e0 = sp == 0 ? 0 : c.n_up;
-  for (int i = tid; i < n * n; i += NTHREADS) {
+  for (int i = tid; i < n * n; i += NT_AUX) {
     const int r = i / n, j = i % n;
     A[i] = c.vglc[vglc_off(c, w, e0 + r) + j];
   }
@@ -308,7 +564,7 @@ __global__ __launch_bounds__(NTHREADS) void k_inverse(DevCtx c) {
     // pivot search over rows k..n-1 of column k
     double best = -1.0;
     int bi = k;
-    for (int i = k + tid; i < n; i += NTHREADS) {
+    for (int i = k + tid; i < n; i += NT_AUX) {
       const double v = fabs(A[i * n + k]);
       if (v > best) { best = v; bi = i; }
     }
@@ -322,7 +578,7 @@ __global__ __launch_bounds__(NTHREADS) void k_inverse(DevCtx c) {
     if (tid == 0) {
       double b = pv_val[0];
       int p = pv_idx[0];
-      for (int q = 1; q < NTHREADS / 64; ++q)
+      for (int q = 1; q < NT_AUX / 64; ++q)
         if (pv_val[q] > b || (pv_val[q] == b && pv_idx[q] < p)) { b = pv_val[q]; p = pv_idx[q]; }
       piv[k] = p;
       if (p != k) s_sign = -s_sign;
@@ -337,18 +593,18 @@ __global__ __launch_bounds__(NTHREADS) void k_inverse(DevCtx c) {
     if (s_sing) break;
     const int p = piv[k];
     if (p != k)
-      for (int j = tid; j < n; j += NTHREADS) {
+      for (int j = tid; j < n; j += NT_AUX) {
         const double t = A[k * n + j];
         A[k * n + j] = A[p * n + j];
         A[p * n + j] = t;
       }
     __syncthreads();
     const double dinv = 1.0 / A[k * n + k];
-    for (int r = tid; r < n; r += NTHREADS) fcol[r] = A[r * n + k];
+    for (int r = tid; r < n; r += NT_AUX) fcol[r] = A[r * n + k];
     __syncthreads();
-    for (int j = tid; j < n; j += NTHREADS) A[k * n + j] = (j == k ? 1.0 : A[k * n + j]) * dinv;
+    for (int j = tid; j < n; j += NT_AUX) A[k * n + j] = (j == k ? 1.0 : A[k * n + j]) * dinv;
     __syncthreads();
-    for (int i = tid; i < n * n; i += NTHREADS) {
+    for (int i = tid; i < n * n; i += NT_AUX) {
       const int r = i / n, j = i % n;
       if (r == k) continue;
       A[i] = (j == k ? 0.0 : A[i]) - fcol[r] * A[k * n + j];
@@ -367,7 +623,7 @@ __global__ __launch_bounds__(NTHREADS) void k_inverse(DevCtx c) {
   for (int k = n - 1; k >= 0; --k) {
     const int p = piv[k];
     if (p != k)
-      for (int r = tid; r < n; r += NTHREADS) {
+      for (int r = tid; r < n; r += NT_AUX) {
         const double t = A[r * n + k];
         A[r * n + k] = A[r * n + p];
         A[r * n + p] = t;
@@ -375,7 +631,7 @@ __global__ __launch_bounds__(NTHREADS) void k_inverse(DevCtx c) {
     __syncthreads();
   }
   // GT[b][j] = Ainv[j][b]
-  for (int i = tid; i < NP * NP; i += NTHREADS) {
+  for (int i = tid; i < NP * NP; i += NT_AUX) {
     const int b = i / NP, j = i % NP;
     GT[i] = (b < n && j < n) ? A[j * n + b] : 0.0;
   }
@@ -390,15 +646,15 @@ __global__ __launch_bounds__(NTHREADS) void k_inverse(DevCtx c) {
 //   g_i = sum_j grad phi_j(r_i) A^{-1}_{j i},  l_i = sum_j lap phi_j(r_i) A^{-1}_{j i}.
 // One workgroup per walker.  mode: -1 = measure only, 0 = VMC step, 1 = DMC
 // step (log w += -tau ((E_old + E_new)/2 - E_T)).
-__global__ __launch_bounds__(NTHREADS) void k_local_energy(DevCtx c, int mode, double e_trial,
+__global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int mode, double e_trial,
                                                            double *e_log_row) {
-  __shared__ double part[NTHREADS / 64][3];
+  __shared__ double part[NT_AUX / 64][3];
   const int w = blockIdx.x;
   const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
   const int NP = c.NP;
   const double *Rw = c.R + (size_t)w * c.ne * 3;
   double kin = 0.0, pot = 0.0, jv = 0.0;
-  for (int i = wid; i < c.ne; i += NTHREADS / 64) {
+  for (int i = wid; i < c.ne; i += NT_AUX / 64) {
     const int sp = i < c.n_up ? 0 : 1, ii = i - sp * c.n_up;
     const double *row = c.vglc + vglc_off(c, w, i);
     const double *gcol = c.GT + gt_off(c, w, sp) + (size_t)ii * NP;
@@ -452,7 +708,7 @@ __global__ __launch_bounds__(NTHREADS) void k_local_energy(DevCtx c, int mode, d
   __syncthreads();
   if (tid == 0) {
     double K = 0.0, V = 0.0, J = 0.0;
-    for (int q = 0; q < NTHREADS / 64; ++q) { K += part[q][0]; V += part[q][1]; J += part[q][2]; }
+    for (int q = 0; q < NT_AUX / 64; ++q) { K += part[q][0]; V += part[q][1]; J += part[q][2]; }
     const double e = -0.5 * K + V + c.v_nn;
     const double eold = c.eloc[w];
     if (mode == 1) c.logw[w] += -c.tau * (0.5 * (eold + e) - e_trial);
@@ -460,6 +716,77 @@ __global__ __launch_bounds__(NTHREADS) void k_local_energy(DevCtx c, int mode, d
     c.logpsi[w] = J + c.logdet[w * 2] + c.logdet[w * 2 + 1];
     if (!isfinite(e) || !isfinite(c.logpsi[w])) c.flags[w] |= 1u;
     if (e_log_row && w < c.W) e_log_row[w] = e;
+  }
+}
+
+// One 16x16 FP64 MFMA tile: sum over k < K (multiple of 4) of A(i, k) B(k, j)
+// with A(i, k) = fa(i0 + i, k) and B(k, j) = fb(k, j0 + j).
+template <typename FA, typename FB>
+__device__ __forceinline__ v4d mfma_tile_f64(int K, FA fa, FB fb) {
+  const int lane = threadIdx.x & 63, kq = lane >> 4, cl = lane & 15;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+  for (int k0 = 0; k0 < K; k0 += 4) acc = mfma16x16x4(fa(cl, k0 + kq), fb(k0 + kq, cl), acc);
+  return acc;
+}
+
+// Rank-k flush at the end of an electron block (delayed update).
+// The block's moves were applied one by one as G_l = G_{l-1} - u_l z_l^T,
+// z_l^T = Delta_l G_{l-1}, with u_l = Gb[l] (the moved electron's inverse
+// column over its ratio) and Delta_l = Dl[l] (its orbital-row change, zero
+// when rejected).  Expanding G_{l-1} gives z_l = Z_l - sum_{p<l} C[l][p] z_p
+// with Z = Delta G0 and C[l][p] = Delta_l . u_p, so z = M Z with
+// M = (I + L)^{-1} (L the strictly lower part of C), which the sweep builds
+// row by row.  Here: Z = Delta G0, Z' = M Z and G = G0 - Z'^T U, three
+// MFMA GEMMs per walker (all four waves share each walker's tiles).
+template <int NOB>
+__device__ void flush_block(const DevCtx &c, int w0, int sp, int kb) {
+  constexpr int NP = NOB * 16;
+  const int tid = threadIdx.x, wid = tid >> 6;
+  const int lane = tid & 63, kq = lane >> 4, cl = lane & 15;
+  const int K = c.K;
+  const int KBP = (kb + 15) & ~15;
+  const int nlt = KBP / 16;
+  __syncthreads();  // Dl, Gb, Ms of every walker complete
+  for (int wv = 0; wv < TW; ++wv) {
+    const int w = w0 + wv;
+    const double *Dl = c.Dl + blk_off(c, w);
+    const double *Gb = c.Gb + blk_off(c, w);
+    const double *Ms = c.Ms + (size_t)w * K * K;
+    double *Zs = c.Zs + (size_t)w * c.K16 * NP;
+    double *Z2 = c.Vs + (size_t)w * c.K16 * NP;
+    double *GT = c.GT + gt_off(c, w, sp);
+    // Z[l][b] = sum_j Dl[l][j] GT[b][j]
+    for (int tt = wid; tt < nlt * NOB; tt += NW_TILE) {
+      const int l0 = (tt / NOB) * 16, b0 = (tt % NOB) * 16;
+      const v4d z = mfma_tile_f64(
+          NP, [&](int i, int k) { return (l0 + i < kb) ? Dl[(l0 + i) * NP + k] : 0.0; },
+          [&](int k, int j) { return GT[(size_t)(b0 + j) * NP + k]; });
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Zs[(l0 + Acc4<double>::row(kq, r)) * NP + b0 + cl] = z[r];
+    }
+    __syncthreads();
+    // Z'[l][b] = sum_{p <= l} M[l][p] Z[p][b]
+    for (int tt = wid; tt < nlt * NOB; tt += NW_TILE) {
+      const int l0 = (tt / NOB) * 16, b0 = (tt % NOB) * 16;
+      const v4d z = mfma_tile_f64(
+          KBP,
+          [&](int i, int k) { return (k <= l0 + i && l0 + i < kb) ? Ms[(l0 + i) * K + k] : 0.0; },
+          [&](int k, int j) { return Zs[k * NP + b0 + j]; });
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Z2[(l0 + Acc4<double>::row(kq, r)) * NP + b0 + cl] = z[r];
+    }
+    __syncthreads();
+    // GT[b][j] -= sum_l Z'[l][b] Gb[l][j]
+    for (int tt = wid; tt < NOB * NOB; tt += NW_TILE) {
+      const int b0 = (tt / NOB) * 16, j0 = (tt % NOB) * 16;
+      const v4d s = mfma_tile_f64(
+          KBP, [&](int i, int k) { return Z2[k * NP + b0 + i]; },
+          [&](int k, int j) { return (k < kb) ? Gb[k * NP + j0 + j] : 0.0; });
+#pragma unroll
+      for (int r = 0; r < 4; ++r) GT[(size_t)(b0 + Acc4<double>::row(kq, r)) * NP + j0 + cl] -= s[r];
+    }
+    __syncthreads();
   }
 }
 
@@ -471,10 +798,13 @@ __global__ __launch_bounds__(NTHREADS) void k_local_energy(DevCtx c, int mode, d
 // updated by Sherman-Morrison, and at the block end the full inverse takes
 // all k changes at once (rank-k Woodbury form, see flush_block).
 template <int NOB>
-__global__ __launch_bounds__(NTHREADS) void k_sweep(DevCtx c, int mode, uint32_t step,
+__global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, int mode, uint32_t step,
                                                     uint8_t *acc_log /* [W][ne] or null */) {
   constexpr int NP = NOB * 16;
-  __shared__ double Bs[FMAX * NCOL];
+  constexpr int FM = 4 * stage_ksteps(NOB);
+  extern __shared__ __align__(16) char smem_basis[];
+  const BasisLDS BL = stage_basis_lds(c.B, smem_basis);
+  __shared__ double Bs0[FM * NCOL], Bs1[FM * NCOL];
   __shared__ double vnew[TW * 5 * NP];
   __shared__ double colm[TW][NP];
   __shared__ double aold[TW][NP];
@@ -482,13 +812,15 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(DevCtx c, int mode, uint32_t
   __shared__ double s_v[TW][3];
   __shared__ double s_uacc[TW], s_uold[TW], s_rho[TW];
   __shared__ int s_acc[TW];
+  __shared__ double crow[TW][KMAX];
   const int tid = threadIdx.x;
-  const int ws = tid >> 5, t = tid & 31;
+  const int ws = tid >> 6, t = tid & 63;  // one wave per walker
   const int w = blockIdx.x * TW + ws;
   double *Rw = c.R + (size_t)w * c.ne * 3;
   double *Gb = c.Gb + blk_off(c, w);
   double *Dl = c.Dl + blk_off(c, w);
   const double tau = c.tau, sqt = sqrt(c.tau);
+  PHASE_BEGIN();
   for (int i = 0; i < c.ne; ++i) {
     const int sp = i < c.n_up ? 0 : 1;
     const int ii = i - sp * c.n_up;
@@ -499,12 +831,13 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(DevCtx c, int mode, uint32_t
     if (m == 0) {
       // block start: copy the block's inverse columns
       for (int b = 0; b < kb; ++b)
-        for (int j = t; j < NP; j += 32) Gb[b * NP + j] = GT[(size_t)(b0 + b) * NP + j];
+        for (int j = t; j < NP; j += 64) Gb[b * NP + j] = GT[(size_t)(b0 + b) * NP + j];
     }
+    PHASE_MARK(0);
     // ---- P1: drift at the current position, proposal
     const double *row = c.vglc + vglc_off(c, w, i);
     double gd0 = 0.0, gd1 = 0.0, gd2 = 0.0;
-    for (int j = t; j < NP; j += 32) {
+    for (int j = t; j < NP; j += 64) {
       const double gj = Gb[m * NP + j];
       colm[ws][j] = gj;
       aold[ws][j] = row[j];
@@ -514,13 +847,13 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(DevCtx c, int mode, uint32_t
     }
     double ro[3] = {Rw[3 * i], Rw[3 * i + 1], Rw[3 * i + 2]};
     double uo = 0.0, gj[3] = {0.0, 0.0, 0.0};
-    jastrow_one_partial(c, Rw, i, ro, t, 32, uo, gj);
-    gd0 = sum32(gd0); gd1 = sum32(gd1); gd2 = sum32(gd2);
-    uo = sum32(uo); gj[0] = sum32(gj[0]); gj[1] = sum32(gj[1]); gj[2] = sum32(gj[2]);
+    jastrow_one_partial(c, Rw, i, ro, t, 64, uo, gj);
+    gd0 = sum64(gd0); gd1 = sum64(gd1); gd2 = sum64(gd2);
+    uo = sum64(uo); gj[0] = sum64(gj[0]); gj[1] = sum64(gj[1]); gj[2] = sum64(gj[2]);
+    double chi[3], ua;
+    move_draws_lanes64(c.seed, step, (uint32_t)w, (uint32_t)i, t, chi, ua);
     if (t == 0) {
       const double v[3] = {gj[0] + gd0, gj[1] + gd1, gj[2] + gd2};
-      double chi[3], ua;
-      move_draws(c.seed, step, (uint32_t)w, (uint32_t)i, chi, ua);
       for (int x = 0; x < 3; ++x) {
         pts[ws][x] = ro[x] + tau * v[x] + sqt * chi[x];
         s_v[ws][x] = v[x];
@@ -529,12 +862,14 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(DevCtx c, int mode, uint32_t
       s_uold[ws] = uo;
     }
     __syncthreads();
+    PHASE_MARK(1);
     // ---- P2: orbitals at the proposed positions (MFMA)
-    mo_tile<double, NOB>(c, pts, Bs, vnew);
+    mo_tile<double, NOB>(c, BL, pts, Bs0, Bs1, vnew);
+    PHASE_MARK(2);
     // ---- P3: ratio, new drift, Metropolis-Hastings decision
     const double *vw = vnew + ws * 5 * NP;
     double rho = 0.0, gn0 = 0.0, gn1 = 0.0, gn2 = 0.0;
-    for (int j = t; j < NP; j += 32) {
+    for (int j = t; j < NP; j += 64) {
       const double gjj = colm[ws][j];
       rho += vw[j] * gjj;
       gn0 += vw[NP + j] * gjj;
@@ -543,9 +878,9 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(DevCtx c, int mode, uint32_t
     }
     const double rn[3] = {pts[ws][0], pts[ws][1], pts[ws][2]};
     double un = 0.0, gjn[3] = {0.0, 0.0, 0.0};
-    jastrow_one_partial(c, Rw, i, rn, t, 32, un, gjn);
-    rho = sum32(rho); gn0 = sum32(gn0); gn1 = sum32(gn1); gn2 = sum32(gn2);
-    un = sum32(un); gjn[0] = sum32(gjn[0]); gjn[1] = sum32(gjn[1]); gjn[2] = sum32(gjn[2]);
+    jastrow_one_partial(c, Rw, i, rn, t, 64, un, gjn);
+    rho = sum64(rho); gn0 = sum64(gn0); gn1 = sum64(gn1); gn2 = sum64(gn2);
+    un = sum64(un); gjn[0] = sum64(gjn[0]); gjn[1] = sum64(gjn[1]); gjn[2] = sum64(gjn[2]);
     int accepted = 0;
     if (!(mode == 1 && !(rho > 0.0))) {
       const double vn[3] = {gjn[0] + gn0 / rho, gjn[1] + gn1 / rho, gjn[2] + gn2 / rho};
@@ -561,68 +896,70 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(DevCtx c, int mode, uint32_t
       accepted = s_uacc[ws] < p;
     }
     if (!isfinite(rho)) c.flags[w] |= 1u;
-    // ---- P4: delayed update of the block (lanes of this walker only)
+    PHASE_MARK(3);
+    // ---- P4: delayed update of the block (lanes of this walker only).
+    // Lane b owns block row b: it forms z_b = Delta . Gb[b] on its own
+    // (contiguous row, no cross-lane reduction).  Later rows take the
+    // Sherman-Morrison correction Gb[b] -= z_b / rho * Gb[m]; earlier rows'
+    // z_b are the coefficients C[m][b] = Delta_m . u_b the flush needs.
+    double *Ms = c.Ms + (size_t)w * c.K * c.K;
     if (accepted) {
       const double irho = 1.0 / rho;
-      constexpr int NJ = (NP + 31) / 32;
-      double dlt[NJ];
-#pragma unroll
-      for (int q = 0; q < NJ; ++q) {
-        const int j = t + 32 * q;
-        dlt[q] = j < NP ? vw[j] - aold[ws][j] : 0.0;
-        if (j < NP) Dl[m * NP + j] = dlt[q];
+      for (int j = t; j < NP; j += 64) {
+        const double d = vw[j] - aold[ws][j];
+        aold[ws][j] = d;  // aold now holds Delta (read across this walker's lanes)
+        Dl[m * NP + j] = d;
       }
-      for (int b = m + 1; b < kb; ++b) {
-        double z = 0.0;
-#pragma unroll
-        for (int q = 0; q < NJ; ++q) {
-          const int j = t + 32 * q;
-          if (j < NP) z += dlt[q] * Gb[b * NP + j];
+      for (int b = t; b < kb; b += 64) {
+        if (b == m) continue;
+        double *row = Gb + b * NP;
+        double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
+#pragma unroll 4
+        for (int j = 0; j < NP; j += 4) {
+          z0 += aold[ws][j] * row[j];
+          z1 += aold[ws][j + 1] * row[j + 1];
+          z2 += aold[ws][j + 2] * row[j + 2];
+          z3 += aold[ws][j + 3] * row[j + 3];
         }
-        z = sum32(z) * irho;
-        for (int j = t; j < NP; j += 32) Gb[b * NP + j] -= z * colm[ws][j];
+        const double z = (z0 + z1) + (z2 + z3);
+        if (b > m) {
+          const double f = z * irho;
+#pragma unroll 8
+          for (int j = 0; j < NP; ++j) row[j] -= f * colm[ws][j];
+        } else {
+          crow[ws][b] = z;  // C[m][b] = Delta_m . u_b
+        }
       }
-      for (int j = t; j < NP; j += 32) Gb[m * NP + j] = colm[ws][j] * irho;
+      // Row m of M = (I + L)^{-1} (L strictly lower, L[m][p] = C[m][p]):
+      // M[m][q] = -sum_{p=q}^{m-1} C[m][p] M[p][q]; lane q owns column q.
+      for (int q = t; q < m; q += 64) {
+        double s = 0.0;
+        for (int p = q; p < m; ++p) s += crow[ws][p] * Ms[p * c.K + q];
+        Ms[m * c.K + q] = -s;
+      }
+      if (t == 0) Ms[m * c.K + m] = 1.0;
+      for (int j = t; j < NP; j += 64) Gb[m * NP + j] = colm[ws][j] * irho;
       double *dst = c.vglc + vglc_off(c, w, i);
-      for (int j = t; j < 5 * NP; j += 32) dst[j] = vw[j];
+      for (int j = t; j < 5 * NP; j += 64) dst[j] = vw[j];
       if (t < 3) Rw[3 * i + t] = rn[t];
       if (t == 0) {
         c.logdet[w * 2 + sp] += log(fabs(rho));
         if (rho < 0.0) c.sgn[w * 2 + sp] = -c.sgn[w * 2 + sp];
       }
     } else {
-      for (int j = t; j < NP; j += 32) Dl[m * NP + j] = 0.0;
+      for (int j = t; j < NP; j += 64) Dl[m * NP + j] = 0.0;
+      for (int q = t; q < m; q += 64) Ms[m * c.K + q] = 0.0;
+      if (t == 0) Ms[m * c.K + m] = 1.0;
     }
     if (acc_log && t == 0 && w < c.W) acc_log[(size_t)w * c.ne + i] = (uint8_t)accepted;
+    PHASE_MARK(4);
     // ---- P5: block end -> rank-k flush of the full inverse
-    if (m == kb - 1) {
-      __syncthreads();
-      // Z[l][b] = Dl[l] . GT[b]  (row l of Delta times the old inverse)
-      double *Zs = c.Zs + blk_off(c, w);
-      for (int l = 0; l < kb; ++l)
-        for (int b = t; b < nsig; b += 32) {
-          double z = 0.0;
-          for (int j = 0; j < nsig; ++j) z += Dl[l * NP + j] * GT[(size_t)b * NP + j];
-          Zs[l * NP + b] = z;
-        }
-      // z'_l = Z_l - sum_{p<l} (Dl[l] . u_p) z'_p, u_p = Gb[p]
-      for (int l = 1; l < kb; ++l)
-        for (int p = 0; p < l; ++p) {
-          double cc = 0.0;
-          for (int j = t; j < nsig; j += 32) cc += Dl[l * NP + j] * Gb[p * NP + j];
-          cc = sum32(cc);
-          for (int b = t; b < nsig; b += 32) Zs[l * NP + b] -= cc * Zs[p * NP + b];
-        }
-      // GT[b][:] -= sum_l z'_l[b] u_l
-      for (int b = t; b < nsig; b += 32)
-        for (int j = 0; j < nsig; ++j) {
-          double s = 0.0;
-          for (int l = 0; l < kb; ++l) s += Zs[l * NP + b] * Gb[l * NP + j];
-          GT[(size_t)b * NP + j] -= s;
-        }
-    }
+    if (m == kb - 1) flush_block<NOB>(c, blockIdx.x * TW, sp, kb);
+    PHASE_MARK(5);
     __syncthreads();
+    PHASE_MARK(6);
   }
+  PHASE_END();
 }
 
 }  // namespace dmcx
