@@ -39,6 +39,73 @@ def flops_per_move(n_basis, n_prim, n_sigma, n_elec, n_atom, k):
             + 40 * (n_elec + n_atom))
 
 
+def mixed_leg(s, torch, dmcx, stream, args, W=4096, steps=10, P=32, k=32):
+    """Mixed precision on the same system: 4096 walkers, FP64 LU recompute every
+    32 steps.  Reports moves/s, the speedup over FP64 per move, and the local
+    energy error per electron at identical configurations, taking the FP64 GPU
+    path (held to the oracle within 1e-10 by the tests) as the reference."""
+    from paper_2504_07948_amd import synth
+    R0 = synth.make_walkers(s, W, 2026)
+    ctx = dmcx.Context(s, W, precision=dmcx.DMCX_MIXED, delay_rank=k, recompute_period=P,
+                       tau=0.01, seed=19, stream=stream)
+    ctx.set_walkers(torch.from_numpy(R0).cuda())
+    e0, _, _ = ctx.measure()
+    e_t = float(np.mean(e0[np.isfinite(e0)]))
+    ctx.run_device(1, mode=dmcx.DMCX_DMC, e_trial=e_t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.run_device(steps, mode=dmcx.DMCX_DMC, e_trial=e_t)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_sweep, _, _ = ctx.last_run_timing()
+    Rm, _ = ctx.get_walkers()
+    em, lpm, _ = ctx.measure()
+    ref = dmcx.Context(s, W, precision=dmcx.DMCX_FP64, stream=stream)
+    ref.set_walkers(torch.from_numpy(Rm).cuda())
+    ef, lpf, _ = ref.measure()
+    ok = np.isfinite(em) & np.isfinite(ef)
+    de = (em - ef)[ok]
+    rate = W * s.n_elec * steps / dt
+    return {"walkers": W, "steps": steps, "recompute_period": P, "delay_rank": k,
+            "value": rate, "unit": "electron-moves/s", "sweep_ms_avg": ms_sweep,
+            "e_err_per_electron_mean": float(abs(de.mean()) / s.n_elec),
+            "e_err_per_electron_max_walker": float(np.abs(de).max() / s.n_elec),
+            "logpsi_err_max": float(np.abs((lpm - lpf)[ok]).max()),
+            "reference": "FP64 GPU path at the mixed run's final configurations"}
+
+
+def forces_leg(s, torch, dmcx, stream, args, W=1024, steps=5):
+    """Forces every step (192 components, Hellmann-Feynman + Pulay via the
+    adjoint) vs energy-only steps, 1024 walkers, FP64."""
+    from paper_2504_07948_amd import synth
+    R0 = synth.make_walkers(s, W, 2027)
+    out = {"walkers": W, "steps": steps, "components": 3 * s.n_atom}
+    for prec, name in ((dmcx.DMCX_FP64, "fp64"), (dmcx.DMCX_MIXED, "mixed")):
+        ctx = dmcx.Context(s, W, precision=prec, delay_rank=32, recompute_period=64, tau=0.01,
+                           seed=23, stream=stream)
+        ctx.set_walkers(torch.from_numpy(R0).cuda())
+        e0, _, _ = ctx.measure()
+        e_t = float(np.mean(e0[np.isfinite(e0)]))
+        F = torch.empty((s.n_atom, 3), dtype=torch.float64, device="cuda")
+        ctx.run_device(1, mode=dmcx.DMCX_DMC, e_trial=e_t)
+        ctx.check(dmcx.dmcx_forces(ctx.h, F.data_ptr(), dmcx.DMCX_DEVICE))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.run_device(1, mode=dmcx.DMCX_DMC, e_trial=e_t)
+        torch.cuda.synchronize()
+        t_e = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.run_device(1, mode=dmcx.DMCX_DMC, e_trial=e_t)
+            ctx.check(dmcx.dmcx_forces(ctx.h, F.data_ptr(), dmcx.DMCX_DEVICE))
+        torch.cuda.synchronize()
+        t_f = time.perf_counter() - t0
+        out[name] = {"ms_step_energy": 1e3 * t_e / steps, "ms_step_with_forces": 1e3 * t_f / steps,
+                     "force_energy_cost_ratio": t_f / t_e}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +117,11 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--skip-extras", action="store_true",
+                    help="only the FP64 leg (no mixed-precision and forces legs)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the timed region, run one device copy of this many MiB "
+                         "(a known-size kernel for scaling FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); "
@@ -68,6 +140,13 @@ def main():
     prec = dmcx.DMCX_FP64 if args.precision == "fp64" else dmcx.DMCX_MIXED
     ctx = dmcx.Context(s, W, precision=prec, delay_rank=args.delay,
                        recompute_period=args.recompute, tau=0.01, seed=17, stream=stream)
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     Rd = torch.from_numpy(R0).cuda()
     ctx.set_walkers(Rd)
     e0, _, _ = ctx.measure()
@@ -81,6 +160,11 @@ def main():
     dt = time.perf_counter() - t0
     sweep_ms, n_launch, sweep_total = ctx.last_run_timing()
     flags = ctx.walker_flags()
+
+    mixed = forces = None
+    if not args.skip_extras:
+        mixed = mixed_leg(s, torch, dmcx, stream, args)
+        forces = forces_leg(s, torch, dmcx, stream, args)
 
     ne, ns = s.n_elec, max(s.n_up, s.n_dn)
     moves = W * ne * args.steps
@@ -134,6 +218,8 @@ def main():
                      "kernel": "k_sweep", "kernel_ms_avg": sweep_ms, "launches": n_launch,
                      "flop_per_launch": sweep_flops, "flop_per_move": fpm},
         "cpu_baseline": cpu,
+        "mixed": mixed,
+        "forces": forces,
         "walker_flags_nonzero": int((flags != 0).sum()),
     }
     print(json.dumps(out))

@@ -152,6 +152,10 @@ dmcx_status dmcx_run(dmcx_ctx *ctx, dmcx_mode mode, int32_t n_steps, double e_tr
 dmcx_status dmcx_measure(dmcx_ctx *ctx, double *e_local, double *log_psi, int8_t *sign,
                          dmcx_mem mem);
 
+/* Coulomb potential V(R) of each walker's current configuration, [W]
+ * (electron-electron + electron-ion + ion-ion). */
+dmcx_status dmcx_potential(dmcx_ctx *ctx, double *v, dmcx_mem mem);
+
 /* Per-walker ion derivatives: dlogpsi_dR and dV_dR, [W][n_atom_max][3]
  * (either may be NULL).  Reverse-mode adjoint of basis, MO contraction,
  * log-determinant and Jastrow (Eq. 3 with lambda = an ion coordinate). */

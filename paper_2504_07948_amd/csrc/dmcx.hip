@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "dmcx.h"
+#include "forces.h"
 #include "kernels.h"
 
 using namespace dmcx;
@@ -33,16 +34,33 @@ struct dmcx_ctx {
   dmcx_options opt{};
   int W = 0, Wpad = 0, ne = 0, n_up = 0, n_dn = 0, n_atom = 0, NP = 0, NOB = 0, K = 1, P = 1;
   int n_basis = 0;
+  bool mixed = false;  // FP32 working precision (mixed path)
+  size_t es = 8;       // bytes per working-precision element
   int64_t step = 0;
   bool walkers_set = false;
   std::string err;
   DeviceBuffers mem;
   DevCtx dc{};
   // host copies needed for later re-packing (set_ions)
-  std::vector<double> ion_xyz;
+  std::vector<double> ion_xyz, ion_Z;
+  std::vector<int> gatom_host;  // atom of each packed (group, shell) slot, -1 padding
+  double *d_gxyz = nullptr, *d_ion = nullptr;
+  // forces: per-walker derivatives, cached per configuration version
+  double *d_partial = nullptr, *d_dl = nullptr, *d_dv = nullptr, *d_gbar = nullptr,
+         *d_red = nullptr;
+  uint64_t version = 1, grads_version = 0;
+  // move-by-move interface: current electron block and pending proposal
+  bool blk_active = false, eloc_dirty = false;
+  int blk_sp = 0, blk_b0 = 0, blk_kb = 0, blk_m = 0, prop_iel = -1;
+  void *d_prop = nullptr;          // [Wpad][5][NP] working precision
+  double *d_prop_rho = nullptr;    // [Wpad]
+  double *d_rnew = nullptr;        // [Wpad][3]
+  double *d_rg = nullptr;          // [W][4] ratio + gradient staging
+  uint8_t *d_acc8 = nullptr;       // [Wpad]
   // scratch
   double *d_pos = nullptr;       // [Wpad][3]
-  double *d_orb = nullptr;       // [Wpad][5][NP]
+  double *d_orb = nullptr;       // [Wpad][5][NP] (working precision) / small staging
+  double *d_orb_out = nullptr;   // [Wpad][5][NP] doubles
   uint8_t *d_acc_stage = nullptr;
   size_t acc_stage_bytes = 0;
   double *d_elog_stage = nullptr;
@@ -227,6 +245,8 @@ dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, int n_orb) {
   if ((st = upload(c, &d_stages, stages))) return st;
   if ((st = upload(c, &d_Cp, Cp))) return st;
   if ((st = upload(c, &d_Cp32, Cp32))) return st;
+  c->gatom_host = gatom;
+  c->d_gxyz = d_gxyz;
   B.n_group = n_group;
   B.ginfo = d_ginfo;
   B.gxyz = d_gxyz;
@@ -251,48 +271,66 @@ void allow_lds(K kernel, size_t dyn) {
                             (int)dyn);
 }
 
-template <int NOB>
-void launch_orbitals_all(dmcx_ctx *c) {
+template <typename T, int NOB>
+void launch_orbitals_all_t(dmcx_ctx *c) {
   const int npts = c->Wpad * c->ne;
-  allow_lds(k_orbitals_all<NOB>, basis_lds(c));
-  hipLaunchKernelGGL(k_orbitals_all<NOB>, dim3((npts + TW - 1) / TW), dim3(NT_TILE), basis_lds(c),
-                     c->stream, c->dc);
+  allow_lds(k_orbitals_all<T, NOB>, basis_lds(c));
+  k_orbitals_all<T, NOB><<<dim3((npts + TW - 1) / TW), dim3(NT_TILE), basis_lds(c), c->stream>>>(c->dc);
 }
-template <int NOB>
-void launch_orbitals_at(dmcx_ctx *c, const double *pos, int npts, double *dst) {
-  allow_lds(k_orbitals_at<NOB>, basis_lds(c));
-  hipLaunchKernelGGL(k_orbitals_at<NOB>, dim3((npts + TW - 1) / TW), dim3(NT_TILE), basis_lds(c),
-                     c->stream, c->dc, pos, npts, dst);
+template <typename T, int NOB>
+void launch_orbitals_at_t(dmcx_ctx *c, const double *pos, int npts, T *dst) {
+  allow_lds(k_orbitals_at<T, NOB>, basis_lds(c));
+  k_orbitals_at<T, NOB><<<dim3((npts + TW - 1) / TW), dim3(NT_TILE), basis_lds(c), c->stream>>>(c->dc, pos, npts, dst);
 }
-template <int NOB>
-void launch_sweep(dmcx_ctx *c, int mode, uint32_t step, uint8_t *acc) {
-  allow_lds(k_sweep<NOB>, basis_lds(c));
-  hipLaunchKernelGGL(k_sweep<NOB>, dim3(c->Wpad / TW), dim3(NT_TILE), basis_lds(c), c->stream,
-                     c->dc, mode, step, acc);
+template <typename T, int NOB>
+void launch_sweep_t(dmcx_ctx *c, int mode, uint32_t step, uint8_t *acc) {
+  allow_lds(k_sweep<T, NOB>, basis_lds(c));
+  k_sweep<T, NOB><<<dim3(c->Wpad / TW), dim3(NT_TILE), basis_lds(c), c->stream>>>(c->dc, mode, step, acc);
 }
 
-#define DISPATCH_NOB(fn, ...)                         \
+#define DISPATCH_NOB_T(T, fn, ...)                    \
   switch (c->NOB) {                                   \
-    case 1: fn<1>(__VA_ARGS__); break;                \
-    case 2: fn<2>(__VA_ARGS__); break;                \
-    case 3: fn<3>(__VA_ARGS__); break;                \
-    case 4: fn<4>(__VA_ARGS__); break;                \
-    case 5: fn<5>(__VA_ARGS__); break;                \
-    case 6: fn<6>(__VA_ARGS__); break;                \
-    case 7: fn<7>(__VA_ARGS__); break;                \
-    default: fn<8>(__VA_ARGS__); break;               \
+    case 1: fn<T, 1>(__VA_ARGS__); break;             \
+    case 2: fn<T, 2>(__VA_ARGS__); break;             \
+    case 3: fn<T, 3>(__VA_ARGS__); break;             \
+    case 4: fn<T, 4>(__VA_ARGS__); break;             \
+    case 5: fn<T, 5>(__VA_ARGS__); break;             \
+    case 6: fn<T, 6>(__VA_ARGS__); break;             \
+    case 7: fn<T, 7>(__VA_ARGS__); break;             \
+    default: fn<T, 8>(__VA_ARGS__); break;            \
   }
+
+void launch_orbitals_all(dmcx_ctx *c) {
+  if (c->mixed) { DISPATCH_NOB_T(float, launch_orbitals_all_t, c); }
+  else { DISPATCH_NOB_T(double, launch_orbitals_all_t, c); }
+}
+// orbitals at one point per walker -> d_orb (working precision)
+void launch_orbitals_at(dmcx_ctx *c, const double *pos, int npts, void *dst) {
+  if (c->mixed) { DISPATCH_NOB_T(float, launch_orbitals_at_t, c, pos, npts, (float *)dst); }
+  else { DISPATCH_NOB_T(double, launch_orbitals_at_t, c, pos, npts, (double *)dst); }
+}
+void launch_sweep(dmcx_ctx *c, int mode, uint32_t step, uint8_t *acc) {
+  if (c->mixed) { DISPATCH_NOB_T(float, launch_sweep_t, c, mode, step, acc); }
+  else { DISPATCH_NOB_T(double, launch_sweep_t, c, mode, step, acc); }
+}
 
 dmcx_status launch_inverse(dmcx_ctx *c) {
   const int n = std::max(c->n_up, c->n_dn);
   const size_t lds = (size_t)n * n * sizeof(double);
-  hipLaunchKernelGGL(k_inverse, dim3(c->Wpad, 2), dim3(NT_AUX), lds, c->stream, c->dc);
+  if (c->mixed)
+    hipLaunchKernelGGL(k_inverse<float>, dim3(c->Wpad, 2), dim3(NT_AUX), lds, c->stream, c->dc);
+  else
+    hipLaunchKernelGGL(k_inverse<double>, dim3(c->Wpad, 2), dim3(NT_AUX), lds, c->stream, c->dc);
   return hip_check(c, hipGetLastError(), "k_inverse launch");
 }
 
 dmcx_status launch_local_energy(dmcx_ctx *c, int mode, double e_trial, double *e_log_row) {
-  hipLaunchKernelGGL(k_local_energy, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc, mode,
-                     e_trial, e_log_row);
+  if (c->mixed)
+    hipLaunchKernelGGL(k_local_energy<float>, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc,
+                       mode, e_trial, e_log_row);
+  else
+    hipLaunchKernelGGL(k_local_energy<double>, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc,
+                       mode, e_trial, e_log_row);
   return hip_check(c, hipGetLastError(), "k_local_energy launch");
 }
 
@@ -309,6 +347,15 @@ __global__ void k_measure_out(DevCtx c, double *e, double *lp, int8_t *sg) {
   if (e) e[w] = c.eloc[w];
   if (lp) lp[w] = c.logpsi[w];
   if (sg) sg[w] = (int8_t)(c.sgn[2 * w] * c.sgn[2 * w + 1]);
+}
+
+// [W][5][NP] working-precision orbital rows -> [W][5][ns] doubles
+template <typename T>
+__global__ void k_orb_out(const T *src, int W, int NP, int ns, double *dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= W * 5 * ns) return;
+  const int j = i % ns, rq = i / ns;
+  dst[i] = (double)src[(size_t)rq * NP + j];
 }
 
 __global__ void k_flags_out(DevCtx c, uint8_t *f) {
@@ -357,6 +404,106 @@ dmcx_status check_flags_host(dmcx_ctx *c) {
   return DMCX_OK;
 }
 
+template <typename T, int NOB>
+void launch_ion_grad_det_t(dmcx_ctx *c, int ntile, size_t lds) {
+  allow_lds(k_ion_grad_det<T, NOB>, lds);
+  k_ion_grad_det<T, NOB><<<dim3(c->Wpad * ntile), dim3(NT_FORCE), lds, c->stream>>>(c->dc, c->d_partial);
+}
+
+double nuclear_repulsion(const std::vector<double> &xyz, const std::vector<double> &Z) {
+  double v = 0.0;
+  const size_t n = Z.size();
+  for (size_t a = 0; a < n; ++a)
+    for (size_t b = a + 1; b < n; ++b) {
+      const double dx = xyz[3 * a] - xyz[3 * b], dy = xyz[3 * a + 1] - xyz[3 * b + 1],
+                   dz = xyz[3 * a + 2] - xyz[3 * b + 2];
+      v += Z[a] * Z[b] / std::sqrt(dx * dx + dy * dy + dz * dz);
+    }
+  return v;
+}
+
+template <typename T, int NOB>
+void launch_block_init_t(dmcx_ctx *c) {
+  k_block_init<T, NOB><<<dim3(c->Wpad), dim3(256), 0, c->stream>>>(c->dc, c->blk_sp, c->blk_b0,
+                                                                     c->blk_kb);
+}
+template <typename T, int NOB>
+void launch_ratio_grad_t(dmcx_ctx *c, int iel, const double *r_new, double *ratio, double *grad) {
+  allow_lds(k_ratio_grad<T, NOB>, basis_lds(c));
+  k_ratio_grad<T, NOB><<<dim3(c->Wpad / TW), dim3(NT_TILE), basis_lds(c), c->stream>>>(
+      c->dc, iel, c->blk_m, r_new, ratio, grad, (T *)c->d_prop, c->d_prop_rho);
+}
+template <typename T, int NOB>
+void launch_accept_t(dmcx_ctx *c, int iel, const double *r_new) {
+  k_accept<T, NOB><<<dim3(c->Wpad), dim3(64), 0, c->stream>>>(
+      c->dc, iel, c->blk_sp, c->blk_m, c->blk_kb, c->d_acc8, (const T *)c->d_prop, c->d_prop_rho,
+      r_new);
+}
+template <typename T, int NOB>
+void launch_flush_t(dmcx_ctx *c, int kb) {
+  k_flush<T, NOB><<<dim3(c->Wpad / TW), dim3(NT_TILE), 0, c->stream>>>(c->dc, c->blk_sp, kb);
+}
+
+// Apply the pending moves of an open electron block (rank-k flush).
+dmcx_status flush_pending(dmcx_ctx *c) {
+  if (!c->blk_active) return DMCX_OK;
+  if (c->blk_m > 0) {
+    if (c->mixed) { DISPATCH_NOB_T(float, launch_flush_t, c, c->blk_m); }
+    else { DISPATCH_NOB_T(double, launch_flush_t, c, c->blk_m); }
+    HIP_TRY(c, hipGetLastError());
+  }
+  c->blk_active = false;
+  c->prop_iel = -1;
+  return DMCX_OK;
+}
+
+// Bring E_L, V and log|Psi| up to date after move-by-move updates.
+dmcx_status refresh_after_moves(dmcx_ctx *c) {
+  dmcx_status st = flush_pending(c);
+  if (st) return st;
+  if (c->eloc_dirty) {
+    if ((st = launch_local_energy(c, -1, 0.0, nullptr))) return st;
+    c->eloc_dirty = false;
+  }
+  return DMCX_OK;
+}
+
+// Per-walker ion derivatives for the current configuration (cached).
+dmcx_status compute_ion_grads(dmcx_ctx *c) {
+  dmcx_status st0 = refresh_after_moves(c);
+  if (st0) return st0;
+  if (c->grads_version == c->version) return DMCX_OK;
+  const int ntile = (c->ne + FPTS - 1) / FPTS;
+  const size_t lds = basis_lds(c);
+  if (c->mixed) {
+    DISPATCH_NOB_T(float, launch_ion_grad_det_t, c, ntile, lds);
+  } else {
+    DISPATCH_NOB_T(double, launch_ion_grad_det_t, c, ntile, lds);
+  }
+  HIP_TRY(c, hipGetLastError());
+  hipLaunchKernelGGL(k_ion_grad_finalize, dim3(c->Wpad), dim3(64), 0, c->stream, c->dc,
+                     c->d_partial, c->d_dl, c->d_dv);
+  HIP_TRY(c, hipGetLastError());
+  c->grads_version = c->version;
+  return DMCX_OK;
+}
+
+dmcx_status walker_vjp(dmcx_ctx *c, const double *src, const double *gbar, double *grad_R,
+                       dmcx_mem mem) {
+  if (!c || !gbar || !grad_R) return DMCX_E_INVALID;
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  dmcx_status st;
+  if ((st = copy_in(c, c->d_gbar, gbar, (size_t)c->W * sizeof(double), mem))) return st;
+  if ((st = compute_ion_grads(c))) return st;
+  const int ncomp = c->n_atom * 3;
+  double *dst = mem == DMCX_DEVICE ? grad_R : c->d_red;
+  hipLaunchKernelGGL(k_walker_vjp, dim3(ncomp), dim3(256), 0, c->stream, src, c->d_gbar, c->W,
+                     ncomp, dst);
+  HIP_TRY(c, hipGetLastError());
+  if (mem == DMCX_HOST) return copy_out(c, grad_R, c->d_red, ncomp * sizeof(double), mem);
+  return DMCX_OK;
+}
+
 }  // namespace
 
 // ================================================================ C-ABI ==
@@ -400,10 +547,8 @@ dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *wa
     c->err = "invalid options";
     return bail(DMCX_E_INVALID);
   }
-  if (opt->precision == DMCX_MIXED) {
-    c->err = "mixed precision not built yet";
-    return bail(DMCX_E_UNSUPPORTED);
-  }
+  c->mixed = opt->precision == DMCX_MIXED;
+  c->es = c->mixed ? sizeof(float) : sizeof(double);
   const dmcx_system &s = sys[0];
   dmcx_status st = validate_system(c, s);
   if (st) return bail(st);
@@ -434,7 +579,13 @@ dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *wa
   d.n_atom = c->n_atom;
   double *d_ion, *d_Z, *d_jen;
   std::vector<double> hZ(s.ion_charge, s.ion_charge + s.n_atom), hj(s.jen_a, s.jen_a + s.n_atom);
+  if (s.n_atom > MAX_ATOM) {
+    c->err = "at most 256 atoms per system";
+    return bail(DMCX_E_UNSUPPORTED);
+  }
+  c->ion_Z.assign(s.ion_charge, s.ion_charge + s.n_atom);
   if ((st = upload(c, &d_ion, c->ion_xyz))) return bail(st);
+  c->d_ion = d_ion;
   if ((st = upload(c, &d_Z, hZ))) return bail(st);
   if ((st = upload(c, &d_jen, hj))) return bail(st);
   d.ion = d_ion;
@@ -459,22 +610,47 @@ dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *wa
   d.seed = opt->seed;
   const size_t Wp = c->Wpad;
   if ((st = dalloc(c, &d.R, Wp * c->ne * 3))) return bail(st);
-  if ((st = dalloc(c, &d.vglc, Wp * c->ne * 5 * c->NP))) return bail(st);
-  if ((st = dalloc(c, &d.GT, Wp * 2 * c->NP * c->NP))) return bail(st);
-  if ((st = dalloc(c, &d.Gb, Wp * c->K * c->NP))) return bail(st);
-  if ((st = dalloc(c, &d.Dl, Wp * c->K * c->NP))) return bail(st);
+  const size_t es = c->es;
+  char *pv;
+  if ((st = dalloc(c, &pv, es * Wp * c->ne * 5 * c->NP))) return bail(st);
+  d.vglc = pv;
+  if ((st = dalloc(c, &pv, es * Wp * 2 * c->NP * c->NP))) return bail(st);
+  d.GT = pv;
+  if ((st = dalloc(c, &pv, es * Wp * c->K * c->NP))) return bail(st);
+  d.Gb = pv;
+  if ((st = dalloc(c, &pv, es * Wp * c->K * c->NP))) return bail(st);
+  d.Dl = pv;
   d.K16 = (c->K + 15) / 16 * 16;
-  if ((st = dalloc(c, &d.Zs, Wp * d.K16 * c->NP))) return bail(st);
-  if ((st = dalloc(c, &d.Vs, Wp * d.K16 * c->NP))) return bail(st);
-  if ((st = dalloc(c, &d.Ms, Wp * c->K * c->K))) return bail(st);
+  if ((st = dalloc(c, &pv, es * Wp * d.K16 * c->NP))) return bail(st);
+  d.Zs = pv;
+  if ((st = dalloc(c, &pv, es * Wp * d.K16 * c->NP))) return bail(st);
+  d.Vs = pv;
+  if ((st = dalloc(c, &pv, es * Wp * c->K * c->K))) return bail(st);
+  d.Ms = pv;
   if ((st = dalloc(c, &d.logdet, Wp * 2))) return bail(st);
   if ((st = dalloc(c, &d.sgn, Wp * 2))) return bail(st);
   if ((st = dalloc(c, &d.eloc, Wp))) return bail(st);
   if ((st = dalloc(c, &d.logw, Wp))) return bail(st);
   if ((st = dalloc(c, &d.logpsi, Wp))) return bail(st);
+  if ((st = dalloc(c, &d.vpot, Wp))) return bail(st);
+  {
+    const size_t ntile = (c->ne + FPTS - 1) / FPTS, na3 = (size_t)s.n_atom * 3;
+    if ((st = dalloc(c, &c->d_partial, Wp * ntile * na3))) return bail(st);
+    if ((st = dalloc(c, &c->d_dl, Wp * na3))) return bail(st);
+    if ((st = dalloc(c, &c->d_dv, Wp * na3))) return bail(st);
+    if ((st = dalloc(c, &c->d_gbar, Wp))) return bail(st);
+    if ((st = dalloc(c, &c->d_red, na3))) return bail(st);
+  }
+  if ((st = dalloc(c, &pv, es * Wp * 5 * c->NP))) return bail(st);
+  c->d_prop = pv;
+  if ((st = dalloc(c, &c->d_prop_rho, Wp))) return bail(st);
+  if ((st = dalloc(c, &c->d_rnew, Wp * 3))) return bail(st);
+  if ((st = dalloc(c, &c->d_rg, Wp * 4))) return bail(st);
+  if ((st = dalloc(c, &c->d_acc8, Wp))) return bail(st);
   if ((st = dalloc(c, &d.flags, Wp))) return bail(st);
   if ((st = dalloc(c, &c->d_pos, Wp * 3))) return bail(st);
   if ((st = dalloc(c, &c->d_orb, Wp * 5 * c->NP))) return bail(st);
+  if ((st = dalloc(c, &c->d_orb_out, Wp * 5 * c->NP))) return bail(st);
   if (hipMemsetAsync(d.flags, 0, Wp * sizeof(unsigned), c->stream) != hipSuccess ||
       hipMemsetAsync(d.logw, 0, Wp * sizeof(double), c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -509,12 +685,16 @@ dmcx_status dmcx_set_walkers(dmcx_ctx *c, const double *R, const double *log_w, 
     HIP_TRY(c, hipMemsetAsync(d.logw, 0, c->Wpad * sizeof(double), c->stream));
   }
   HIP_TRY(c, hipMemsetAsync(d.flags, 0, c->Wpad * sizeof(unsigned), c->stream));
-  DISPATCH_NOB(launch_orbitals_all, c);
+  launch_orbitals_all(c);
   HIP_TRY(c, hipGetLastError());
   if ((st = launch_inverse(c))) return st;
   if ((st = launch_local_energy(c, -1, 0.0, nullptr))) return st;
   c->step = 0;
   c->walkers_set = true;
+  c->blk_active = false;
+  c->prop_iel = -1;
+  c->eloc_dirty = false;
+  c->version++;
   return DMCX_OK;
 }
 
@@ -538,13 +718,45 @@ dmcx_status dmcx_get_step(const dmcx_ctx *c, int64_t *step) {
   return DMCX_OK;
 }
 
-dmcx_status dmcx_set_ions(dmcx_ctx *c, int32_t, const double *, dmcx_mem) {
-  return c ? fail(c, DMCX_E_UNSUPPORTED, "set_ions not built yet") : DMCX_E_INVALID;
+dmcx_status dmcx_set_ions(dmcx_ctx *c, int32_t sys_index, const double *ion_xyz, dmcx_mem mem) {
+  if (!c || !ion_xyz) return DMCX_E_INVALID;
+  if (sys_index != 0) return fail(c, DMCX_E_INVALID, "sys_index out of range");
+  const size_t n = (size_t)c->n_atom * 3;
+  std::vector<double> h(n);
+  if (mem == DMCX_HOST) {
+    std::copy(ion_xyz, ion_xyz + n, h.begin());
+  } else {
+    HIP_TRY(c, hipMemcpyAsync(h.data(), ion_xyz, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  c->ion_xyz = h;
+  std::vector<double> gxyz(c->gatom_host.size() * 3);
+  for (size_t q = 0; q < c->gatom_host.size(); ++q) {
+    const int a = c->gatom_host[q] >= 0 ? c->gatom_host[q] : 0;
+    for (int d = 0; d < 3; ++d) gxyz[3 * q + d] = h[3 * a + d];
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->d_gxyz, gxyz.data(), gxyz.size() * sizeof(double),
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_ion, h.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->dc.v_nn = nuclear_repulsion(c->ion_xyz, c->ion_Z);
+  c->version++;
+  c->blk_active = false;  // everything below is rebuilt from the positions
+  c->prop_iel = -1;
+  c->eloc_dirty = false;
+  if (!c->walkers_set) return DMCX_OK;
+  launch_orbitals_all(c);
+  HIP_TRY(c, hipGetLastError());
+  dmcx_status st;
+  if ((st = launch_inverse(c))) return st;
+  return launch_local_energy(c, -1, 0.0, nullptr);
 }
 
 dmcx_status dmcx_recompute(dmcx_ctx *c) {
   if (!c || !c->walkers_set) return c ? fail(c, DMCX_E_STATE, "walkers not set") : DMCX_E_INVALID;
-  dmcx_status st = launch_inverse(c);
+  dmcx_status st = flush_pending(c);
+  if (st) return st;
+  st = launch_inverse(c);
   if (st) return st;
   return check_flags_host(c);
 }
@@ -554,31 +766,94 @@ dmcx_status dmcx_eval_orbitals(dmcx_ctx *c, int32_t spin, const double *r, doubl
   if (!c || !r || !vgl || spin < 0 || spin > 1) return DMCX_E_INVALID;
   dmcx_status st;
   if ((st = copy_in(c, c->d_pos, r, (size_t)c->W * 3 * sizeof(double), mem))) return st;
-  DISPATCH_NOB(launch_orbitals_at, c, c->d_pos, c->W, c->d_orb);
+  launch_orbitals_at(c, c->d_pos, c->W, c->d_orb);
   HIP_TRY(c, hipGetLastError());
   const int ns = spin == 0 ? c->n_up : c->n_dn;
   if (ns == 0) return DMCX_OK;
-  HIP_TRY(c, hipMemcpy2DAsync(vgl, ns * sizeof(double), c->d_orb, c->NP * sizeof(double),
-                              ns * sizeof(double), (size_t)c->W * 5,
-                              mem == DMCX_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
-                              c->stream));
-  if (mem == DMCX_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  // convert in place order: rows are read from d_orb, written to d_orb_out
+  const int n = c->W * 5 * ns;
+  double *dst = mem == DMCX_DEVICE ? vgl : c->d_orb_out;
+  if (c->mixed)
+    hipLaunchKernelGGL(k_orb_out<float>, dim3((n + 255) / 256), dim3(256), 0, c->stream,
+                       (const float *)c->d_orb, c->W, c->NP, ns, dst);
+  else
+    hipLaunchKernelGGL(k_orb_out<double>, dim3((n + 255) / 256), dim3(256), 0, c->stream,
+                       (const double *)c->d_orb, c->W, c->NP, ns, dst);
+  HIP_TRY(c, hipGetLastError());
+  if (mem == DMCX_HOST) return copy_out(c, vgl, dst, (size_t)n * sizeof(double), mem);
   return DMCX_OK;
 }
 
-dmcx_status dmcx_ratio_grad(dmcx_ctx *c, int32_t, const double *, double *, double *, dmcx_mem) {
-  return c ? fail(c, DMCX_E_UNSUPPORTED, "ratio_grad not built yet") : DMCX_E_INVALID;
+dmcx_status dmcx_ratio_grad(dmcx_ctx *c, int32_t iel, const double *r_new, double *ratio,
+                            double *grad, dmcx_mem mem) {
+  if (!c || !r_new || !ratio || !grad) return DMCX_E_INVALID;
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  if (iel < 0 || iel >= c->ne) return fail(c, DMCX_E_INVALID, "electron index out of range");
+  const int sp = iel < c->n_up ? 0 : 1, ii = iel - sp * c->n_up;
+  const int nsig = sp == 0 ? c->n_up : c->n_dn;
+  dmcx_status st;
+  // the move must be the next one of the open block, else start a new block
+  if (c->blk_active && (sp != c->blk_sp || ii != c->blk_b0 + c->blk_m || c->prop_iel >= 0))
+    if ((st = flush_pending(c))) return st;
+  if (!c->blk_active) {
+    c->blk_sp = sp;
+    c->blk_b0 = ii;
+    c->blk_kb = std::min(c->K, nsig - ii);
+    c->blk_m = 0;
+    c->blk_active = true;
+    if (c->mixed) { DISPATCH_NOB_T(float, launch_block_init_t, c); }
+    else { DISPATCH_NOB_T(double, launch_block_init_t, c); }
+    HIP_TRY(c, hipGetLastError());
+  }
+  const double *rn = r_new;
+  if (mem == DMCX_HOST) {
+    if ((st = copy_in(c, c->d_rnew, r_new, (size_t)c->W * 3 * sizeof(double), mem))) return st;
+    rn = c->d_rnew;
+  }
+  double *dr = mem == DMCX_DEVICE ? ratio : c->d_rg;
+  double *dg = mem == DMCX_DEVICE ? grad : c->d_rg + c->W;
+  if (c->mixed) { DISPATCH_NOB_T(float, launch_ratio_grad_t, c, iel, rn, dr, dg); }
+  else { DISPATCH_NOB_T(double, launch_ratio_grad_t, c, iel, rn, dr, dg); }
+  HIP_TRY(c, hipGetLastError());
+  if (rn != c->d_rnew)  // keep the proposed positions for dmcx_accept
+    HIP_TRY(c, hipMemcpyAsync(c->d_rnew, rn, (size_t)c->W * 3 * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+  c->prop_iel = iel;
+  if (mem == DMCX_HOST) {
+    if ((st = copy_out(c, ratio, dr, (size_t)c->W * sizeof(double), mem))) return st;
+    if ((st = copy_out(c, grad, dg, (size_t)c->W * 3 * sizeof(double), mem))) return st;
+  }
+  return DMCX_OK;
 }
-dmcx_status dmcx_accept(dmcx_ctx *c, int32_t, const uint8_t *, dmcx_mem) {
-  return c ? fail(c, DMCX_E_UNSUPPORTED, "accept not built yet") : DMCX_E_INVALID;
+
+dmcx_status dmcx_accept(dmcx_ctx *c, int32_t iel, const uint8_t *accept, dmcx_mem mem) {
+  if (!c || !accept) return DMCX_E_INVALID;
+  if (!c->blk_active || c->prop_iel != iel)
+    return fail(c, DMCX_E_STATE, "dmcx_accept needs the preceding dmcx_ratio_grad of this electron");
+  dmcx_status st;
+  if ((st = copy_in(c, c->d_acc8, accept, (size_t)c->W, mem))) return st;
+  if (c->mixed) { DISPATCH_NOB_T(float, launch_accept_t, c, iel, c->d_rnew); }
+  else { DISPATCH_NOB_T(double, launch_accept_t, c, iel, c->d_rnew); }
+  HIP_TRY(c, hipGetLastError());
+  c->prop_iel = -1;
+  c->blk_m++;
+  c->version++;
+  c->eloc_dirty = true;
+  if (c->blk_m == c->blk_kb) return flush_pending(c);
+  return DMCX_OK;
 }
-dmcx_status dmcx_flush(dmcx_ctx *c) { return c ? DMCX_OK : DMCX_E_INVALID; }
+
+dmcx_status dmcx_flush(dmcx_ctx *c) {
+  if (!c) return DMCX_E_INVALID;
+  return flush_pending(c);
+}
 
 dmcx_status dmcx_run(dmcx_ctx *c, dmcx_mode mode, int32_t n_steps, double e_trial,
                      uint8_t *accept_log, double *e_log, dmcx_mem mem) {
   if (!c || n_steps < 0 || (mode != DMCX_VMC && mode != DMCX_DMC)) return DMCX_E_INVALID;
   if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
   dmcx_status st;
+  if ((st = refresh_after_moves(c))) return st;
   const size_t acc_bytes = (size_t)n_steps * c->W * c->ne, elog_bytes = (size_t)n_steps * c->W * 8;
   uint8_t *acc = accept_log;
   double *elog = e_log;
@@ -598,14 +873,14 @@ dmcx_status dmcx_run(dmcx_ctx *c, dmcx_mode mode, int32_t n_steps, double e_tria
   for (int s = 0; s < n_steps; ++s) {
     if (c->step % c->P == 0 && (st = launch_inverse(c))) return st;
     HIP_TRY(c, hipEventRecord(c->ev[2 * s], c->stream));
-    DISPATCH_NOB(launch_sweep, c, (int)mode, (uint32_t)c->step,
-                 acc ? acc + (size_t)s * c->W * c->ne : nullptr);
+    launch_sweep(c, (int)mode, (uint32_t)c->step, acc ? acc + (size_t)s * c->W * c->ne : nullptr);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipEventRecord(c->ev[2 * s + 1], c->stream));
     if ((st = launch_local_energy(c, (int)mode, e_trial, elog ? elog + (size_t)s * c->W : nullptr)))
       return st;
     c->step++;
   }
+  if (n_steps > 0) c->version++;
   c->n_timed = n_steps;
   if (accept_log && mem == DMCX_HOST) {
     HIP_TRY(c, hipMemcpyAsync(accept_log, acc, acc_bytes, hipMemcpyDeviceToHost, c->stream));
@@ -620,6 +895,8 @@ dmcx_status dmcx_run(dmcx_ctx *c, dmcx_mode mode, int32_t n_steps, double e_tria
 dmcx_status dmcx_measure(dmcx_ctx *c, double *e_local, double *log_psi, int8_t *sign, dmcx_mem mem) {
   if (!c) return DMCX_E_INVALID;
   if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  dmcx_status st0 = refresh_after_moves(c);
+  if (st0) return st0;
   if (mem == DMCX_DEVICE) {
     hipLaunchKernelGGL(k_measure_out, dim3((c->W + 255) / 256), dim3(256), 0, c->stream, c->dc,
                        e_local, log_psi, sign);
@@ -638,17 +915,45 @@ dmcx_status dmcx_measure(dmcx_ctx *c, double *e_local, double *log_psi, int8_t *
   return DMCX_OK;
 }
 
-dmcx_status dmcx_ion_grads(dmcx_ctx *c, double *, double *, dmcx_mem) {
-  return c ? fail(c, DMCX_E_UNSUPPORTED, "ion_grads not built yet") : DMCX_E_INVALID;
+dmcx_status dmcx_ion_grads(dmcx_ctx *c, double *dlogpsi_dR, double *dV_dR, dmcx_mem mem) {
+  if (!c) return DMCX_E_INVALID;
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  dmcx_status st;
+  if ((st = compute_ion_grads(c))) return st;
+  const size_t bytes = (size_t)c->W * c->n_atom * 3 * sizeof(double);
+  if (dlogpsi_dR && (st = copy_out(c, dlogpsi_dR, c->d_dl, bytes, mem))) return st;
+  if (dV_dR && (st = copy_out(c, dV_dR, c->d_dv, bytes, mem))) return st;
+  return DMCX_OK;
 }
-dmcx_status dmcx_logpsi_vjp(dmcx_ctx *c, const double *, double *, dmcx_mem) {
-  return c ? fail(c, DMCX_E_UNSUPPORTED, "logpsi_vjp not built yet") : DMCX_E_INVALID;
+
+dmcx_status dmcx_logpsi_vjp(dmcx_ctx *c, const double *gbar, double *grad_R, dmcx_mem mem) {
+  return walker_vjp(c, c ? c->d_dl : nullptr, gbar, grad_R, mem);
 }
-dmcx_status dmcx_potential_vjp(dmcx_ctx *c, const double *, double *, dmcx_mem) {
-  return c ? fail(c, DMCX_E_UNSUPPORTED, "potential_vjp not built yet") : DMCX_E_INVALID;
+
+dmcx_status dmcx_potential_vjp(dmcx_ctx *c, const double *gbar, double *grad_R, dmcx_mem mem) {
+  return walker_vjp(c, c ? c->d_dv : nullptr, gbar, grad_R, mem);
 }
-dmcx_status dmcx_forces(dmcx_ctx *c, double *, dmcx_mem) {
-  return c ? fail(c, DMCX_E_UNSUPPORTED, "forces not built yet") : DMCX_E_INVALID;
+
+dmcx_status dmcx_forces(dmcx_ctx *c, double *F, dmcx_mem mem) {
+  if (!c || !F) return DMCX_E_INVALID;
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  dmcx_status st;
+  if ((st = compute_ion_grads(c))) return st;
+  const int ncomp = c->n_atom * 3;
+  double *dst = mem == DMCX_DEVICE ? F : c->d_red;
+  hipLaunchKernelGGL(k_force_estimator, dim3(ncomp), dim3(256), 0, c->stream, c->dc, c->d_dl,
+                     c->d_dv, dst);
+  HIP_TRY(c, hipGetLastError());
+  if (mem == DMCX_HOST) return copy_out(c, F, c->d_red, ncomp * sizeof(double), mem);
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_potential(dmcx_ctx *c, double *v, dmcx_mem mem) {
+  if (!c || !v) return DMCX_E_INVALID;
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  dmcx_status st = refresh_after_moves(c);
+  if (st) return st;
+  return copy_out(c, v, c->dc.vpot, (size_t)c->W * sizeof(double), mem);
 }
 
 dmcx_status dmcx_walker_flags(dmcx_ctx *c, uint8_t *flags, dmcx_mem mem) {

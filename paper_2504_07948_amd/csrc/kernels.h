@@ -135,18 +135,21 @@ struct DevCtx {
   uint64_t seed;
   // walker state
   double *R;       // [Wpad][ne][3]
-  double *vglc;    // [Wpad][ne][5][NP] orbital VGL rows at the current positions
-  double *GT;      // [Wpad][2][NP][NP]
-  double *Gb;      // [Wpad][K][NP] current inverse columns of the electron block
-  double *Dl;      // [Wpad][K][NP] value-row changes of the block's moves
-  double *Zs;      // [Wpad][K16][NP] flush scratch: Z = Delta G0 (16-row padded)
-  double *Vs;      // [Wpad][K16][NP] flush scratch: Z' = M Z
-  double *Ms;      // [Wpad][K][K] M = (I + L)^{-1}, L[l][p] = Delta_l . u_p (p < l)
+  // Arrays below hold elements of the working precision T (double for the
+  // FP64 path, float for the mixed path); kernels cast them to T*.
+  void *vglc;      // [Wpad][ne][5][NP] orbital VGL rows at the current positions
+  void *GT;        // [Wpad][2][NP][NP]
+  void *Gb;        // [Wpad][K][NP] current inverse columns of the electron block
+  void *Dl;        // [Wpad][K][NP] value-row changes of the block's moves
+  void *Zs;        // [Wpad][K16][NP] flush scratch: Z = Delta G0 (16-row padded)
+  void *Vs;        // [Wpad][K16][NP] flush scratch: Z' = M Z
+  void *Ms;        // [Wpad][K][K] M = (I + L)^{-1}, L[l][p] = Delta_l . u_p (p < l)
   double *logdet;  // [Wpad][2]
   double *sgn;     // [Wpad][2]
   double *eloc;    // [Wpad]
   double *logw;    // [Wpad]
   double *logpsi;  // [Wpad]
+  double *vpot;    // [Wpad] Coulomb potential V(R) of the current configuration
   unsigned *flags; // [Wpad] bit 0 non-finite, bit 1 singular
 };
 
@@ -161,10 +164,12 @@ __device__ __forceinline__ size_t blk_off(const DevCtx &c, int w) {
 }
 
 // ------------------------------------------------------------ basis ----
+__device__ __forceinline__ double texp(double x) { return exp(x); }
+__device__ __forceinline__ float texp(float x) { return expf(x); }
+
 // Cartesian monomial data for component COMP of angular momentum L.
-template <int L, int COMP>
-__device__ __forceinline__ void cart_poly_t(double x, double y, double z, double &P, double &Px,
-                                            double &Py, double &Pz, double &Lp) {
+template <int L, int COMP, typename R = double>
+__device__ __forceinline__ void cart_poly_t(R x, R y, R z, R &P, R &Px, R &Py, R &Pz, R &Lp) {
   Px = 0.0; Py = 0.0; Pz = 0.0; Lp = 0.0;
   if constexpr (L == 0) { P = 1.0; }
   else if constexpr (L == 1) {
@@ -185,16 +190,15 @@ __device__ __forceinline__ void cart_poly_t(double x, double y, double z, double
 // R1 = dR/d(s2), R2 = d2R/d(s2)^2:  grad = grad P R0 + 2 r R1 P,
 // lap = lap P R0 + 4 R1 (grad P . r) + P (6 R1 + 4 s2 R2).
 template <typename T, int L, int COMP>
-__device__ __forceinline__ void store_vgl(T *dst, double x, double y, double z, double s2,
-                                          double R0, double R1, double R2) {
-  double P, Px, Py, Pz, Lp;
-  cart_poly_t<L, COMP>(x, y, z, P, Px, Py, Pz, Lp);
-  const double tr = 2.0 * R1 * P;
-  dst[0] = (T)(P * R0);
-  dst[1] = (T)(Px * R0 + x * tr);
-  dst[2] = (T)(Py * R0 + y * tr);
-  dst[3] = (T)(Pz * R0 + z * tr);
-  dst[4] = (T)(Lp * R0 + 4.0 * R1 * (Px * x + Py * y + Pz * z) + P * (6.0 * R1 + 4.0 * s2 * R2));
+__device__ __forceinline__ void store_vgl(T *dst, T x, T y, T z, T s2, T R0, T R1, T R2) {
+  T P, Px, Py, Pz, Lp;
+  cart_poly_t<L, COMP, T>(x, y, z, P, Px, Py, Pz, Lp);
+  const T tr = (T)2 * R1 * P;
+  dst[0] = P * R0;
+  dst[1] = Px * R0 + x * tr;
+  dst[2] = Py * R0 + y * tr;
+  dst[3] = Pz * R0 + z * tr;
+  dst[4] = Lp * R0 + (T)4 * R1 * (Px * x + Py * y + Pz * z) + P * ((T)6 * R1 + (T)4 * s2 * R2);
 }
 
 // Basis values of one stage (groups g_begin..g_end, all with angular
@@ -215,15 +219,15 @@ __device__ void basis_stage_t(const BasisLDS &B, int g_begin, int g_end, int fn_
     const int g = g_begin + (sl >> 2), s = sl & 3;
     const int4 gi = B.ginfo[g];
     const double *cxyz = B.xyz + (size_t)(g * 4 + s) * 3;
-    const double x = pts[w][0] - cxyz[0], y = pts[w][1] - cxyz[1], z = pts[w][2] - cxyz[2];
-    const double s2 = x * x + y * y + z * z;
-    double R0 = 0.0, R1 = 0.0, R2 = 0.0;
+    const T x = (T)(pts[w][0] - cxyz[0]), y = (T)(pts[w][1] - cxyz[1]), z = (T)(pts[w][2] - cxyz[2]);
+    const T s2 = x * x + y * y + z * z;
+    T R0 = 0, R1 = 0, R2 = 0;
     if constexpr (NPR > 0) {
-      double e[NPR], a[NPR];
+      T e[NPR], a[NPR];
 #pragma unroll
       for (int p = 0; p < NPR; ++p) {
-        a[p] = B.alpha[gi.w + p * 4 + s];
-        e[p] = B.coef[gi.w + p * 4 + s] * exp(-a[p] * s2);
+        a[p] = (T)B.alpha[gi.w + p * 4 + s];
+        e[p] = (T)B.coef[gi.w + p * 4 + s] * texp(-a[p] * s2);
       }
 #pragma unroll
       for (int p = 0; p < NPR; ++p) {
@@ -233,8 +237,8 @@ __device__ void basis_stage_t(const BasisLDS &B, int g_begin, int g_end, int fn_
       }
     } else {  // generic contraction depth
       for (int p = 0; p < npr_rt; ++p) {
-        const double ap = B.alpha[gi.w + p * 4 + s];
-        const double ep = B.coef[gi.w + p * 4 + s] * exp(-ap * s2);
+        const T ap = (T)B.alpha[gi.w + p * 4 + s];
+        const T ep = (T)B.coef[gi.w + p * 4 + s] * texp(-ap * s2);
         R0 += ep;
         R1 -= ap * ep;
         R2 += ap * ap * ep;
@@ -345,7 +349,7 @@ __device__ __forceinline__ void mfma_stage(typename Acc4<T>::type (&acc)[(NOB + 
   }
 }
 
-// Orbital VGL of the tile's TW points: out[w][q][orbital] (LDS, FP64).
+// Orbital VGL of the tile's TW points: out[w][q][orbital] (LDS, precision T).
 // All NT_TILE threads must call.  Stages of basis functions flow through two
 // LDS buffers: in each phase every wave runs its MFMAs on stage s (wave w
 // owns orbital blocks w%4 (+4, ...) and the K-steps of parity w/4) and then
@@ -356,7 +360,7 @@ __device__ __forceinline__ void mfma_stage(typename Acc4<T>::type (&acc)[(NOB + 
 // are added once at the end.
 template <typename T, int NOB>
 __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)[3], T *Bs0,
-                        T *Bs1, double *out) {
+                        T *Bs1, T *out) {
   constexpr int NQ = (NOB + 3) / 4;
   constexpr int NP = NOB * 16;
   constexpr int KS = stage_ksteps(NOB);
@@ -437,8 +441,8 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
             if (n < 40) {
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                double *o = out + n * NP + ob * 16 + Acc4<T>::row(kq, r);
-                *o = (half ? 0.0 : *o) + (double)acc[q][cb][r];
+                T *o = out + n * NP + ob * 16 + Acc4<T>::row(kq, r);
+                *o = (half ? (T)0 : *o) + (T)acc[q][cb][r];
               }
             }
           }
@@ -483,14 +487,14 @@ __device__ __forceinline__ void jastrow_one_partial(const DevCtx &c, const doubl
 
 // ------------------------------------------------------------ kernels ----
 // Orbital VGL at (walker, electron) points -> vglc (all electrons).
-template <int NOB>
+template <typename T, int NOB>
 __global__ __launch_bounds__(NT_TILE) void k_orbitals_all(DevCtx c) {
   constexpr int NP = NOB * 16;
   constexpr int FM = 4 * stage_ksteps(NOB);
   extern __shared__ __align__(16) char smem_basis[];
   const BasisLDS BL = stage_basis_lds(c.B, smem_basis);
-  __shared__ double Bs0[FM * NCOL], Bs1[FM * NCOL];
-  __shared__ double out[TW * 5 * NP];
+  __shared__ T Bs0[FM * NCOL], Bs1[FM * NCOL];
+  __shared__ T out[TW * 5 * NP];
   __shared__ double pts[TW][3];
   const int npts = c.Wpad * c.ne;
   const int p0 = blockIdx.x * TW;
@@ -499,24 +503,24 @@ __global__ __launch_bounds__(NT_TILE) void k_orbitals_all(DevCtx c) {
     pts[threadIdx.x / 3][threadIdx.x % 3] = c.R[(size_t)p * 3 + threadIdx.x % 3];
   }
   __syncthreads();
-  mo_tile<double, NOB>(c, BL, pts, Bs0, Bs1, out);
+  mo_tile<T, NOB>(c, BL, pts, Bs0, Bs1, out);
   for (int i = threadIdx.x; i < TW * 5 * NP; i += NT_TILE) {
     const int w = i / (5 * NP);
     const int p = p0 + w;
-    if (p < npts) c.vglc[(size_t)p * 5 * NP + (i - w * 5 * NP)] = out[i];
+    if (p < npts) ((T *)c.vglc)[(size_t)p * 5 * NP + (i - w * 5 * NP)] = out[i];
   }
 }
 
 // Orbital VGL at one point per walker: pos [W][3] -> dst [W][5][NP].
-template <int NOB>
+template <typename T, int NOB>
 __global__ __launch_bounds__(NT_TILE) void k_orbitals_at(DevCtx c, const double *pos, int npts,
-                                                         double *dst) {
+                                                         T *dst) {
   constexpr int NP = NOB * 16;
   constexpr int FM = 4 * stage_ksteps(NOB);
   extern __shared__ __align__(16) char smem_basis[];
   const BasisLDS BL = stage_basis_lds(c.B, smem_basis);
-  __shared__ double Bs0[FM * NCOL], Bs1[FM * NCOL];
-  __shared__ double out[TW * 5 * NP];
+  __shared__ T Bs0[FM * NCOL], Bs1[FM * NCOL];
+  __shared__ T out[TW * 5 * NP];
   __shared__ double pts[TW][3];
   const int p0 = blockIdx.x * TW;
   if (threadIdx.x < TW * 3) {
@@ -524,7 +528,7 @@ __global__ __launch_bounds__(NT_TILE) void k_orbitals_at(DevCtx c, const double 
     pts[threadIdx.x / 3][threadIdx.x % 3] = pos[(size_t)p * 3 + threadIdx.x % 3];
   }
   __syncthreads();
-  mo_tile<double, NOB>(c, BL, pts, Bs0, Bs1, out);
+  mo_tile<T, NOB>(c, BL, pts, Bs0, Bs1, out);
   for (int i = threadIdx.x; i < TW * 5 * NP; i += NT_TILE) {
     const int w = i / (5 * NP);
     if (p0 + w < npts) dst[(size_t)(p0 + w) * 5 * NP + (i - w * 5 * NP)] = out[i];
@@ -535,6 +539,7 @@ __global__ __launch_bounds__(NT_TILE) void k_orbitals_at(DevCtx c, const double 
 // elimination with partial pivoting, built from the cached value rows.
 // grid (Wpad, 2); dynamic LDS n*n doubles.  Writes GT (transposed, zero
 // padded), log|det| and sign; flags singular matrices.
+template <typename T>
 __global__ __launch_bounds__(NT_AUX) void k_inverse(DevCtx c) {
   extern __shared__ double A[];
   __shared__ int piv[128];
@@ -547,16 +552,16 @@ __global__ __launch_bounds__(NT_AUX) void k_inverse(DevCtx c) {
   const int n = sp == 0 ? c.n_up : c.n_dn;
   const int NP = c.NP;
   const int tid = threadIdx.x;
-  double *GT = c.GT + gt_off(c, w, sp);
+  T *GT = (T *)c.GT + gt_off(c, w, sp);
   if (n == 0) {
-    for (int i = tid; i < NP * NP; i += NT_AUX) GT[i] = 0.0;
+    for (int i = tid; i < NP * NP; i += NT_AUX) GT[i] = (T)0;
     if (tid == 0) { c.logdet[w * 2 + sp] = 0.0; c.sgn[w * 2 + sp] = 1.0; }
     return;
   }
   const int e0 = sp == 0 ? 0 : c.n_up;
   for (int i = tid; i < n * n; i += NT_AUX) {
     const int r = i / n, j = i % n;
-    A[i] = c.vglc[vglc_off(c, w, e0 + r) + j];
+    A[i] = (double)((const T *)c.vglc)[vglc_off(c, w, e0 + r) + j];
   }
   if (tid == 0) { s_logdet = 0.0; s_sign = 1; s_sing = 0; }
   __syncthreads();
@@ -633,7 +638,7 @@ __global__ __launch_bounds__(NT_AUX) void k_inverse(DevCtx c) {
   // GT[b][j] = Ainv[j][b]
   for (int i = tid; i < NP * NP; i += NT_AUX) {
     const int b = i / NP, j = i % NP;
-    GT[i] = (b < n && j < n) ? A[j * n + b] : 0.0;
+    GT[i] = (T)((b < n && j < n) ? A[j * n + b] : 0.0);
   }
   if (tid == 0) {
     c.logdet[w * 2 + sp] = s_logdet;
@@ -646,6 +651,7 @@ __global__ __launch_bounds__(NT_AUX) void k_inverse(DevCtx c) {
 //   g_i = sum_j grad phi_j(r_i) A^{-1}_{j i},  l_i = sum_j lap phi_j(r_i) A^{-1}_{j i}.
 // One workgroup per walker.  mode: -1 = measure only, 0 = VMC step, 1 = DMC
 // step (log w += -tau ((E_old + E_new)/2 - E_T)).
+template <typename T>
 __global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int mode, double e_trial,
                                                            double *e_log_row) {
   __shared__ double part[NT_AUX / 64][3];
@@ -656,15 +662,15 @@ __global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int mode, dou
   double kin = 0.0, pot = 0.0, jv = 0.0;
   for (int i = wid; i < c.ne; i += NT_AUX / 64) {
     const int sp = i < c.n_up ? 0 : 1, ii = i - sp * c.n_up;
-    const double *row = c.vglc + vglc_off(c, w, i);
-    const double *gcol = c.GT + gt_off(c, w, sp) + (size_t)ii * NP;
+    const T *row = (const T *)c.vglc + vglc_off(c, w, i);
+    const T *gcol = (const T *)c.GT + gt_off(c, w, sp) + (size_t)ii * NP;
     double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0;
     for (int j = lane; j < NP; j += 64) {
-      const double gj = gcol[j];
-      g0 += row[NP + j] * gj;
-      g1 += row[2 * NP + j] * gj;
-      g2 += row[3 * NP + j] * gj;
-      l += row[4 * NP + j] * gj;
+      const double gj = (double)gcol[j];
+      g0 += (double)row[NP + j] * gj;
+      g1 += (double)row[2 * NP + j] * gj;
+      g2 += (double)row[3 * NP + j] * gj;
+      l += (double)row[4 * NP + j] * gj;
     }
     // Jastrow gradient / Laplacian, value (pairs counted once) and potential
     const double *ri = Rw + 3 * i;
@@ -713,18 +719,19 @@ __global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int mode, dou
     const double eold = c.eloc[w];
     if (mode == 1) c.logw[w] += -c.tau * (0.5 * (eold + e) - e_trial);
     c.eloc[w] = e;
+    c.vpot[w] = V + c.v_nn;
     c.logpsi[w] = J + c.logdet[w * 2] + c.logdet[w * 2 + 1];
     if (!isfinite(e) || !isfinite(c.logpsi[w])) c.flags[w] |= 1u;
     if (e_log_row && w < c.W) e_log_row[w] = e;
   }
 }
 
-// One 16x16 FP64 MFMA tile: sum over k < K (multiple of 4) of A(i, k) B(k, j)
+// One 16x16 MFMA tile in precision T: sum over k < K (multiple of 4) of A(i, k) B(k, j)
 // with A(i, k) = fa(i0 + i, k) and B(k, j) = fb(k, j0 + j).
-template <typename FA, typename FB>
-__device__ __forceinline__ v4d mfma_tile_f64(int K, FA fa, FB fb) {
+template <typename T, typename FA, typename FB>
+__device__ __forceinline__ typename Acc4<T>::type mfma_tile(int K, FA fa, FB fb) {
   const int lane = threadIdx.x & 63, kq = lane >> 4, cl = lane & 15;
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  typename Acc4<T>::type acc = {0, 0, 0, 0};
 #pragma unroll 8
   for (int k0 = 0; k0 < K; k0 += 4) acc = mfma16x16x4(fa(cl, k0 + kq), fb(k0 + kq, cl), acc);
   return acc;
@@ -739,7 +746,7 @@ __device__ __forceinline__ v4d mfma_tile_f64(int K, FA fa, FB fb) {
 // M = (I + L)^{-1} (L the strictly lower part of C), which the sweep builds
 // row by row.  Here: Z = Delta G0, Z' = M Z and G = G0 - Z'^T U, three
 // MFMA GEMMs per walker (all four waves share each walker's tiles).
-template <int NOB>
+template <typename T, int NOB>
 __device__ void flush_block(const DevCtx &c, int w0, int sp, int kb) {
   constexpr int NP = NOB * 16;
   const int tid = threadIdx.x, wid = tid >> 6;
@@ -750,44 +757,117 @@ __device__ void flush_block(const DevCtx &c, int w0, int sp, int kb) {
   __syncthreads();  // Dl, Gb, Ms of every walker complete
   for (int wv = 0; wv < TW; ++wv) {
     const int w = w0 + wv;
-    const double *Dl = c.Dl + blk_off(c, w);
-    const double *Gb = c.Gb + blk_off(c, w);
-    const double *Ms = c.Ms + (size_t)w * K * K;
-    double *Zs = c.Zs + (size_t)w * c.K16 * NP;
-    double *Z2 = c.Vs + (size_t)w * c.K16 * NP;
-    double *GT = c.GT + gt_off(c, w, sp);
+    const T *Dl = (const T *)c.Dl + blk_off(c, w);
+    const T *Gb = (const T *)c.Gb + blk_off(c, w);
+    const T *Ms = (const T *)c.Ms + (size_t)w * K * K;
+    T *Zs = (T *)c.Zs + (size_t)w * c.K16 * NP;
+    T *Z2 = (T *)c.Vs + (size_t)w * c.K16 * NP;
+    T *GT = (T *)c.GT + gt_off(c, w, sp);
     // Z[l][b] = sum_j Dl[l][j] GT[b][j]
     for (int tt = wid; tt < nlt * NOB; tt += NW_TILE) {
       const int l0 = (tt / NOB) * 16, b0 = (tt % NOB) * 16;
-      const v4d z = mfma_tile_f64(
-          NP, [&](int i, int k) { return (l0 + i < kb) ? Dl[(l0 + i) * NP + k] : 0.0; },
+      const auto z = mfma_tile<T>(
+          NP, [&](int i, int k) { return (l0 + i < kb) ? Dl[(l0 + i) * NP + k] : (T)0; },
           [&](int k, int j) { return GT[(size_t)(b0 + j) * NP + k]; });
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Zs[(l0 + Acc4<double>::row(kq, r)) * NP + b0 + cl] = z[r];
+      for (int r = 0; r < 4; ++r) Zs[(l0 + Acc4<T>::row(kq, r)) * NP + b0 + cl] = z[r];
     }
     __syncthreads();
     // Z'[l][b] = sum_{p <= l} M[l][p] Z[p][b]
     for (int tt = wid; tt < nlt * NOB; tt += NW_TILE) {
       const int l0 = (tt / NOB) * 16, b0 = (tt % NOB) * 16;
-      const v4d z = mfma_tile_f64(
+      const auto z = mfma_tile<T>(
           KBP,
-          [&](int i, int k) { return (k <= l0 + i && l0 + i < kb) ? Ms[(l0 + i) * K + k] : 0.0; },
+          [&](int i, int k) { return (k <= l0 + i && l0 + i < kb) ? Ms[(l0 + i) * K + k] : (T)0; },
           [&](int k, int j) { return Zs[k * NP + b0 + j]; });
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Z2[(l0 + Acc4<double>::row(kq, r)) * NP + b0 + cl] = z[r];
+      for (int r = 0; r < 4; ++r) Z2[(l0 + Acc4<T>::row(kq, r)) * NP + b0 + cl] = z[r];
     }
     __syncthreads();
     // GT[b][j] -= sum_l Z'[l][b] Gb[l][j]
     for (int tt = wid; tt < NOB * NOB; tt += NW_TILE) {
       const int b0 = (tt / NOB) * 16, j0 = (tt % NOB) * 16;
-      const v4d s = mfma_tile_f64(
+      const auto s = mfma_tile<T>(
           KBP, [&](int i, int k) { return Z2[k * NP + b0 + i]; },
-          [&](int k, int j) { return (k < kb) ? Gb[k * NP + j0 + j] : 0.0; });
+          [&](int k, int j) { return (k < kb) ? Gb[k * NP + j0 + j] : (T)0; });
 #pragma unroll
-      for (int r = 0; r < 4; ++r) GT[(size_t)(b0 + Acc4<double>::row(kq, r)) * NP + j0 + cl] -= s[r];
+      for (int r = 0; r < 4; ++r) GT[(size_t)(b0 + Acc4<T>::row(kq, r)) * NP + j0 + cl] -= s[r];
     }
     __syncthreads();
   }
+}
+
+// Block update after a move of electron i (block position m of kb) of walker
+// w, served by the 64 lanes t of one wave.  Accepted: Delta = a' - a_old
+// enters Dl[m]; lane b owns block row b and forms z_b = Delta . Gb[b] on its
+// own (contiguous row, no cross-lane reduction); later rows take the
+// Sherman-Morrison correction Gb[b] -= z_b / rho * Gb[m], earlier rows' z_b
+// are the coefficients C[m][b] = Delta_m . u_b, from which row m of
+// M = (I + L)^{-1} is formed; Gb[m] becomes u_m = col / rho; the orbital row,
+// position and log|D| follow.  Rejected: Dl[m] = 0 and M row m = e_m.
+// vw: proposal VGL [5][NP]; colm: current inverse column of i (Gb[m]);
+// aold: old value row of i (overwritten with Delta); crow: scratch [KMAX].
+template <typename T, int NOB>
+__device__ void block_accept(const DevCtx &c, int w, int t, int i, int sp, int m, int kb,
+                             int accepted, double rho, const T *vw, T *colm_w, T *aold_w,
+                             T *crow_w, const double rn[3]) {
+  constexpr int NP = NOB * 16;
+  T *Gb = (T *)c.Gb + blk_off(c, w);
+  T *Dl = (T *)c.Dl + blk_off(c, w);
+  double *Rw = c.R + (size_t)w * c.ne * 3;
+    // Lane b owns block row b: it forms z_b = Delta . Gb[b] on its own
+    // (contiguous row, no cross-lane reduction).  Later rows take the
+    // Sherman-Morrison correction Gb[b] -= z_b / rho * Gb[m]; earlier rows'
+    // z_b are the coefficients C[m][b] = Delta_m . u_b the flush needs.
+    T *Ms = (T *)c.Ms + (size_t)w * c.K * c.K;
+    if (accepted) {
+      const double irho = 1.0 / rho;
+      for (int j = t; j < NP; j += 64) {
+        const T d = vw[j] - aold_w[j];
+        aold_w[j] = d;  // aold now holds Delta (read across this walker's lanes)
+        Dl[m * NP + j] = d;
+      }
+      for (int b = t; b < kb; b += 64) {
+        if (b == m) continue;
+        T *row = Gb + b * NP;
+        double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
+#pragma unroll 4
+        for (int j = 0; j < NP; j += 4) {
+          z0 += (double)aold_w[j] * (double)row[j];
+          z1 += (double)aold_w[j + 1] * (double)row[j + 1];
+          z2 += (double)aold_w[j + 2] * (double)row[j + 2];
+          z3 += (double)aold_w[j + 3] * (double)row[j + 3];
+        }
+        const double z = (z0 + z1) + (z2 + z3);
+        if (b > m) {
+          const T f = (T)(z * irho);
+#pragma unroll 8
+          for (int j = 0; j < NP; ++j) row[j] -= f * colm_w[j];
+        } else {
+          crow_w[b] = (T)z;  // C[m][b] = Delta_m . u_b
+        }
+      }
+      // Row m of M = (I + L)^{-1} (L strictly lower, L[m][p] = C[m][p]):
+      // M[m][q] = -sum_{p=q}^{m-1} C[m][p] M[p][q]; lane q owns column q.
+      for (int q = t; q < m; q += 64) {
+        double s = 0.0;
+        for (int p = q; p < m; ++p) s += (double)crow_w[p] * (double)Ms[p * c.K + q];
+        Ms[m * c.K + q] = (T)(-s);
+      }
+      if (t == 0) Ms[m * c.K + m] = (T)1;
+      for (int j = t; j < NP; j += 64) Gb[m * NP + j] = (T)((double)colm_w[j] * irho);
+      T *dst = (T *)c.vglc + vglc_off(c, w, i);
+      for (int j = t; j < 5 * NP; j += 64) dst[j] = vw[j];
+      if (t < 3) Rw[3 * i + t] = rn[t];
+      if (t == 0) {
+        c.logdet[w * 2 + sp] += log(fabs(rho));
+        if (rho < 0.0) c.sgn[w * 2 + sp] = -c.sgn[w * 2 + sp];
+      }
+    } else {
+      for (int j = t; j < NP; j += 64) Dl[m * NP + j] = (T)0;
+      for (int q = t; q < m; q += 64) Ms[m * c.K + q] = (T)0;
+      if (t == 0) Ms[m * c.K + m] = (T)1;
+    }
 }
 
 // One full sweep: every electron of every walker in the tile proposes a
@@ -797,28 +877,28 @@ __device__ void flush_block(const DevCtx &c, int w0, int sp, int kb) {
 // of k consecutive electrons of one spin, the block's inverse columns are
 // updated by Sherman-Morrison, and at the block end the full inverse takes
 // all k changes at once (rank-k Woodbury form, see flush_block).
-template <int NOB>
+template <typename T, int NOB>
 __global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, int mode, uint32_t step,
                                                     uint8_t *acc_log /* [W][ne] or null */) {
   constexpr int NP = NOB * 16;
   constexpr int FM = 4 * stage_ksteps(NOB);
   extern __shared__ __align__(16) char smem_basis[];
   const BasisLDS BL = stage_basis_lds(c.B, smem_basis);
-  __shared__ double Bs0[FM * NCOL], Bs1[FM * NCOL];
-  __shared__ double vnew[TW * 5 * NP];
-  __shared__ double colm[TW][NP];
-  __shared__ double aold[TW][NP];
+  __shared__ T Bs0[FM * NCOL], Bs1[FM * NCOL];
+  __shared__ T vnew[TW * 5 * NP];
+  __shared__ T colm[TW][NP];
+  __shared__ T aold[TW][NP];
   __shared__ double pts[TW][3];
   __shared__ double s_v[TW][3];
   __shared__ double s_uacc[TW], s_uold[TW], s_rho[TW];
   __shared__ int s_acc[TW];
-  __shared__ double crow[TW][KMAX];
+  __shared__ T crow[TW][KMAX];
   const int tid = threadIdx.x;
   const int ws = tid >> 6, t = tid & 63;  // one wave per walker
   const int w = blockIdx.x * TW + ws;
   double *Rw = c.R + (size_t)w * c.ne * 3;
-  double *Gb = c.Gb + blk_off(c, w);
-  double *Dl = c.Dl + blk_off(c, w);
+  T *Gb = (T *)c.Gb + blk_off(c, w);
+  T *Dl = (T *)c.Dl + blk_off(c, w);
   const double tau = c.tau, sqt = sqrt(c.tau);
   PHASE_BEGIN();
   for (int i = 0; i < c.ne; ++i) {
@@ -827,7 +907,7 @@ __global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, int mode, uint32_t 
     const int nsig = sp == 0 ? c.n_up : c.n_dn;
     const int m = ii % c.K, b0 = ii - m;
     const int kb = min(c.K, nsig - b0);
-    double *GT = c.GT + gt_off(c, w, sp);
+    T *GT = (T *)c.GT + gt_off(c, w, sp);
     if (m == 0) {
       // block start: copy the block's inverse columns
       for (int b = 0; b < kb; ++b)
@@ -835,15 +915,16 @@ __global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, int mode, uint32_t 
     }
     PHASE_MARK(0);
     // ---- P1: drift at the current position, proposal
-    const double *row = c.vglc + vglc_off(c, w, i);
+    const T *row = (const T *)c.vglc + vglc_off(c, w, i);
     double gd0 = 0.0, gd1 = 0.0, gd2 = 0.0;
     for (int j = t; j < NP; j += 64) {
-      const double gj = Gb[m * NP + j];
-      colm[ws][j] = gj;
+      const T gjt = Gb[m * NP + j];
+      const double gj = (double)gjt;
+      colm[ws][j] = gjt;
       aold[ws][j] = row[j];
-      gd0 += row[NP + j] * gj;
-      gd1 += row[2 * NP + j] * gj;
-      gd2 += row[3 * NP + j] * gj;
+      gd0 += (double)row[NP + j] * gj;
+      gd1 += (double)row[2 * NP + j] * gj;
+      gd2 += (double)row[3 * NP + j] * gj;
     }
     double ro[3] = {Rw[3 * i], Rw[3 * i + 1], Rw[3 * i + 2]};
     double uo = 0.0, gj[3] = {0.0, 0.0, 0.0};
@@ -864,17 +945,17 @@ __global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, int mode, uint32_t 
     __syncthreads();
     PHASE_MARK(1);
     // ---- P2: orbitals at the proposed positions (MFMA)
-    mo_tile<double, NOB>(c, BL, pts, Bs0, Bs1, vnew);
+    mo_tile<T, NOB>(c, BL, pts, Bs0, Bs1, vnew);
     PHASE_MARK(2);
     // ---- P3: ratio, new drift, Metropolis-Hastings decision
-    const double *vw = vnew + ws * 5 * NP;
+    const T *vw = vnew + ws * 5 * NP;
     double rho = 0.0, gn0 = 0.0, gn1 = 0.0, gn2 = 0.0;
     for (int j = t; j < NP; j += 64) {
-      const double gjj = colm[ws][j];
-      rho += vw[j] * gjj;
-      gn0 += vw[NP + j] * gjj;
-      gn1 += vw[2 * NP + j] * gjj;
-      gn2 += vw[3 * NP + j] * gjj;
+      const double gjj = (double)colm[ws][j];
+      rho += (double)vw[j] * gjj;
+      gn0 += (double)vw[NP + j] * gjj;
+      gn1 += (double)vw[2 * NP + j] * gjj;
+      gn2 += (double)vw[3 * NP + j] * gjj;
     }
     const double rn[3] = {pts[ws][0], pts[ws][1], pts[ws][2]};
     double un = 0.0, gjn[3] = {0.0, 0.0, 0.0};
@@ -897,69 +978,116 @@ __global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, int mode, uint32_t 
     }
     if (!isfinite(rho)) c.flags[w] |= 1u;
     PHASE_MARK(3);
-    // ---- P4: delayed update of the block (lanes of this walker only).
-    // Lane b owns block row b: it forms z_b = Delta . Gb[b] on its own
-    // (contiguous row, no cross-lane reduction).  Later rows take the
-    // Sherman-Morrison correction Gb[b] -= z_b / rho * Gb[m]; earlier rows'
-    // z_b are the coefficients C[m][b] = Delta_m . u_b the flush needs.
-    double *Ms = c.Ms + (size_t)w * c.K * c.K;
-    if (accepted) {
-      const double irho = 1.0 / rho;
-      for (int j = t; j < NP; j += 64) {
-        const double d = vw[j] - aold[ws][j];
-        aold[ws][j] = d;  // aold now holds Delta (read across this walker's lanes)
-        Dl[m * NP + j] = d;
-      }
-      for (int b = t; b < kb; b += 64) {
-        if (b == m) continue;
-        double *row = Gb + b * NP;
-        double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
-#pragma unroll 4
-        for (int j = 0; j < NP; j += 4) {
-          z0 += aold[ws][j] * row[j];
-          z1 += aold[ws][j + 1] * row[j + 1];
-          z2 += aold[ws][j + 2] * row[j + 2];
-          z3 += aold[ws][j + 3] * row[j + 3];
-        }
-        const double z = (z0 + z1) + (z2 + z3);
-        if (b > m) {
-          const double f = z * irho;
-#pragma unroll 8
-          for (int j = 0; j < NP; ++j) row[j] -= f * colm[ws][j];
-        } else {
-          crow[ws][b] = z;  // C[m][b] = Delta_m . u_b
-        }
-      }
-      // Row m of M = (I + L)^{-1} (L strictly lower, L[m][p] = C[m][p]):
-      // M[m][q] = -sum_{p=q}^{m-1} C[m][p] M[p][q]; lane q owns column q.
-      for (int q = t; q < m; q += 64) {
-        double s = 0.0;
-        for (int p = q; p < m; ++p) s += crow[ws][p] * Ms[p * c.K + q];
-        Ms[m * c.K + q] = -s;
-      }
-      if (t == 0) Ms[m * c.K + m] = 1.0;
-      for (int j = t; j < NP; j += 64) Gb[m * NP + j] = colm[ws][j] * irho;
-      double *dst = c.vglc + vglc_off(c, w, i);
-      for (int j = t; j < 5 * NP; j += 64) dst[j] = vw[j];
-      if (t < 3) Rw[3 * i + t] = rn[t];
-      if (t == 0) {
-        c.logdet[w * 2 + sp] += log(fabs(rho));
-        if (rho < 0.0) c.sgn[w * 2 + sp] = -c.sgn[w * 2 + sp];
-      }
-    } else {
-      for (int j = t; j < NP; j += 64) Dl[m * NP + j] = 0.0;
-      for (int q = t; q < m; q += 64) Ms[m * c.K + q] = 0.0;
-      if (t == 0) Ms[m * c.K + m] = 1.0;
-    }
+    // ---- P4: delayed update of the block (lanes of this walker only)
+    block_accept<T, NOB>(c, w, t, i, sp, m, kb, accepted, rho, vw, colm[ws], aold[ws], crow[ws], rn);
     if (acc_log && t == 0 && w < c.W) acc_log[(size_t)w * c.ne + i] = (uint8_t)accepted;
     PHASE_MARK(4);
     // ---- P5: block end -> rank-k flush of the full inverse
-    if (m == kb - 1) flush_block<NOB>(c, blockIdx.x * TW, sp, kb);
+    if (m == kb - 1) flush_block<T, NOB>(c, blockIdx.x * TW, sp, kb);
     PHASE_MARK(5);
     __syncthreads();
     PHASE_MARK(6);
   }
   PHASE_END();
+}
+
+
+// ------------------------------------------- move-by-move interface ----
+// The same block machinery as k_sweep, driven one call at a time by the
+// caller's own proposals (dmcx_ratio_grad / dmcx_accept / dmcx_flush).
+
+// Block start: Gb[b] = GT[b0 + b] for the block's kb electrons.
+template <typename T, int NOB>
+__global__ void k_block_init(DevCtx c, int sp, int b0, int kb) {
+  constexpr int NP = NOB * 16;
+  const int w = blockIdx.x;
+  T *Gb = (T *)c.Gb + blk_off(c, w);
+  const T *GT = (const T *)c.GT + gt_off(c, w, sp);
+  for (int i = threadIdx.x; i < kb * NP; i += blockDim.x)
+    Gb[i] = GT[(size_t)(b0 + i / NP) * NP + i % NP];
+}
+
+// Psi(R')/Psi(R) and grad_i ln|Psi(R')| for moving electron i (block
+// position m) of every walker to r_new [W][3]; keeps the proposal's orbital
+// VGL and determinant ratio for k_accept.
+template <typename T, int NOB>
+__global__ __launch_bounds__(NT_TILE) void k_ratio_grad(DevCtx c, int i, int m,
+                                                        const double *r_new, double *ratio,
+                                                        double *grad, T *prop, double *prop_rho) {
+  constexpr int NP = NOB * 16;
+  constexpr int FM = 4 * stage_ksteps(NOB);
+  extern __shared__ __align__(16) char smem_basis[];
+  const BasisLDS BL = stage_basis_lds(c.B, smem_basis);
+  __shared__ T Bs0[FM * NCOL], Bs1[FM * NCOL];
+  __shared__ T vnew[TW * 5 * NP];
+  __shared__ double pts[TW][3];
+  const int tid = threadIdx.x, ws = tid >> 6, t = tid & 63;
+  const int w = blockIdx.x * TW + ws;
+  if (tid < TW * 3) {
+    const int q = min((int)(blockIdx.x * TW) + tid / 3, c.W - 1);
+    pts[tid / 3][tid % 3] = r_new[(size_t)q * 3 + tid % 3];
+  }
+  __syncthreads();
+  mo_tile<T, NOB>(c, BL, pts, Bs0, Bs1, vnew);
+  const T *vw = vnew + ws * 5 * NP;
+  const T *col = (const T *)c.Gb + blk_off(c, w) + (size_t)m * NP;
+  double rho = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int j = t; j < NP; j += 64) {
+    const double cj = (double)col[j];
+    rho += (double)vw[j] * cj;
+    g0 += (double)vw[NP + j] * cj;
+    g1 += (double)vw[2 * NP + j] * cj;
+    g2 += (double)vw[3 * NP + j] * cj;
+  }
+  const double *Rw = c.R + (size_t)w * c.ne * 3;
+  const double ro[3] = {Rw[3 * i], Rw[3 * i + 1], Rw[3 * i + 2]};
+  const double rn[3] = {pts[ws][0], pts[ws][1], pts[ws][2]};
+  double uo = 0.0, un = 0.0, go[3] = {0.0, 0.0, 0.0}, gn[3] = {0.0, 0.0, 0.0};
+  jastrow_one_partial(c, Rw, i, ro, t, 64, uo, go);
+  jastrow_one_partial(c, Rw, i, rn, t, 64, un, gn);
+  rho = sum64(rho); g0 = sum64(g0); g1 = sum64(g1); g2 = sum64(g2);
+  uo = sum64(uo); un = sum64(un); gn[0] = sum64(gn[0]); gn[1] = sum64(gn[1]); gn[2] = sum64(gn[2]);
+  T *pw = prop + (size_t)w * 5 * NP;
+  for (int j = t; j < 5 * NP; j += 64) pw[j] = vw[j];
+  if (t == 0) {
+    prop_rho[w] = rho;
+    if (w < c.W) {
+      ratio[w] = rho * exp(un - uo);
+      grad[3 * w + 0] = gn[0] + g0 / rho;
+      grad[3 * w + 1] = gn[1] + g1 / rho;
+      grad[3 * w + 2] = gn[2] + g2 / rho;
+    }
+  }
+}
+
+// Apply accept[w] for the proposal of electron i (block position m of kb);
+// one 64-lane block per walker.
+template <typename T, int NOB>
+__global__ __launch_bounds__(64) void k_accept(DevCtx c, int i, int sp, int m, int kb,
+                                               const uint8_t *acc, const T *prop,
+                                               const double *prop_rho, const double *r_new) {
+  constexpr int NP = NOB * 16;
+  __shared__ T colm[NP], aold[NP], crow[KMAX];
+  const int w = blockIdx.x, t = threadIdx.x;
+  const T *Gb = (const T *)c.Gb + blk_off(c, w);
+  const T *row = (const T *)c.vglc + vglc_off(c, w, i);
+  for (int j = t; j < NP; j += 64) {
+    colm[j] = Gb[m * NP + j];
+    aold[j] = row[j];
+  }
+  const int accepted = (w < c.W) ? (int)(acc[w] != 0) : 0;
+  const double rho = prop_rho[w];
+  const int q = min(w, c.W - 1);
+  const double rn[3] = {r_new[3 * q], r_new[3 * q + 1], r_new[3 * q + 2]};
+  if (accepted && !isfinite(rho)) c.flags[w] |= 1u;
+  block_accept<T, NOB>(c, w, t, i, sp, m, kb, accepted && rho != 0.0, rho,
+                       prop + (size_t)w * 5 * NP, colm, aold, crow, rn);
+}
+
+// Rank-k flush of the pending moves of the current block (kb of them).
+template <typename T, int NOB>
+__global__ __launch_bounds__(NT_TILE) void k_flush(DevCtx c, int sp, int kb) {
+  flush_block<T, NOB>(c, blockIdx.x * TW, sp, kb);
 }
 
 }  // namespace dmcx

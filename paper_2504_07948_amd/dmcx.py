@@ -27,7 +27,7 @@ EXPORTED = [
     "dmcx_create", "dmcx_destroy", "dmcx_set_walkers", "dmcx_get_walkers", "dmcx_set_step",
     "dmcx_get_step", "dmcx_set_ions", "dmcx_recompute", "dmcx_eval_orbitals", "dmcx_ratio_grad",
     "dmcx_accept", "dmcx_flush", "dmcx_run", "dmcx_measure", "dmcx_ion_grads", "dmcx_logpsi_vjp",
-    "dmcx_potential_vjp", "dmcx_forces", "dmcx_walker_flags", "dmcx_sync", "dmcx_last_run_timing",
+    "dmcx_potential_vjp", "dmcx_forces", "dmcx_potential", "dmcx_walker_flags", "dmcx_sync", "dmcx_last_run_timing",
     "dmcx_selftest", "dmcx_philox", "dmcx_strerror", "dmcx_last_error",
 ]
 
@@ -82,6 +82,7 @@ def load():
         "dmcx_logpsi_vjp": [P, P, P, I32],
         "dmcx_potential_vjp": [P, P, P, I32],
         "dmcx_forces": [P, P, I32],
+        "dmcx_potential": [P, P, I32],
         "dmcx_walker_flags": [P, P, I32],
         "dmcx_sync": [P],
         "dmcx_last_run_timing": [P, P, P, P],
@@ -192,6 +193,10 @@ def dmcx_potential_vjp(ctx, gbar, grad_R, mem):
 
 def dmcx_forces(ctx, F, mem):
     return load().dmcx_forces(ctx, F, mem)
+
+
+def dmcx_potential(ctx, v, mem):
+    return load().dmcx_potential(ctx, v, mem)
 
 
 def dmcx_walker_flags(ctx, flags, mem):
@@ -330,6 +335,53 @@ class Context:
         self.check(dmcx_eval_orbitals(self.h, spin, _ptr(np.ascontiguousarray(r, dtype=np.float64)),
                                       _ptr(out), DMCX_HOST))
         return out
+
+    def ratio_grad(self, iel, r_new):
+        r_new = np.ascontiguousarray(r_new, dtype=np.float64)
+        ratio = np.zeros(self.W)
+        grad = np.zeros((self.W, 3))
+        self.check(dmcx_ratio_grad(self.h, iel, _ptr(r_new), _ptr(ratio), _ptr(grad), DMCX_HOST))
+        return ratio, grad
+
+    def accept(self, iel, mask):
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        self.check(dmcx_accept(self.h, iel, _ptr(mask), DMCX_HOST))
+
+    def flush(self):
+        self.check(dmcx_flush(self.h))
+
+    def potential(self):
+        v = np.zeros(self.W)
+        self.check(dmcx_potential(self.h, _ptr(v), DMCX_HOST))
+        return v
+
+    def set_ions(self, ion_xyz, sys_index=0):
+        if isinstance(ion_xyz, np.ndarray):
+            ion_xyz = np.ascontiguousarray(ion_xyz, dtype=np.float64)
+        self.check(dmcx_set_ions(self.h, sys_index, _ptr(ion_xyz), _mem(ion_xyz)))
+
+    def ion_grads(self):
+        dl = np.zeros((self.W, self.n_atom, 3))
+        dv = np.zeros((self.W, self.n_atom, 3))
+        self.check(dmcx_ion_grads(self.h, _ptr(dl), _ptr(dv), DMCX_HOST))
+        return dl, dv
+
+    def logpsi_vjp(self, gbar):
+        out = np.zeros((self.n_atom, 3))
+        self.check(dmcx_logpsi_vjp(self.h, _ptr(np.ascontiguousarray(gbar, dtype=np.float64)),
+                                   _ptr(out), DMCX_HOST))
+        return out
+
+    def potential_vjp(self, gbar):
+        out = np.zeros((self.n_atom, 3))
+        self.check(dmcx_potential_vjp(self.h, _ptr(np.ascontiguousarray(gbar, dtype=np.float64)),
+                                      _ptr(out), DMCX_HOST))
+        return out
+
+    def forces(self):
+        F = np.zeros((self.n_atom, 3))
+        self.check(dmcx_forces(self.h, _ptr(F), DMCX_HOST))
+        return F
 
     def walker_flags(self):
         f = np.zeros(self.W, dtype=np.uint8)

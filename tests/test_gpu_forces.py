@@ -1,0 +1,125 @@
+"""GPU parity of the ion-force path (reverse-mode adjoint) against the CPU
+oracle's forward-mode Eq. 3 gradients, central finite differences of the
+library's own log|Psi| and V, the VJP definitions and the force estimator."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_07948_amd import dmcx, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _close(a, b, rel=1e-10, floor=1.0):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    tol = rel * np.maximum(np.maximum(np.abs(a), np.abs(b)), floor)
+    bad = np.abs(a - b) > tol
+    assert not bad.any(), (f"{bad.sum()}/{bad.size} outside; max rel "
+                           f"{(np.abs(a - b) / np.maximum(np.abs(b), floor)).max():.3e}")
+
+
+@pytest.mark.parametrize("cfg,W", [(1, 16), (2, 9)])
+def test_ion_grads_match_oracle_forward_mode(cfg, W):
+    s = synth.make_system(cfg)
+    R = synth.make_walkers(s, W, 500 + cfg)
+    ctx = dmcx.Context(s, W)
+    ctx.set_walkers(R)
+    dl, dv = ctx.ion_grads()
+    dl_o, dv_o, rc = oracle.ion_grads_batch(s, R)
+    assert rc == 0
+    _close(dv, dv_o)
+    _close(dl, dl_o)
+
+
+def test_ion_grads_after_moves_match_oracle():
+    """Gradients use the delayed-updated inverse after a DMC step."""
+    s = synth.make_system(2)
+    W = 8
+    R = synth.make_walkers(s, W, 510)
+    ctx = dmcx.Context(s, W, delay_rank=32, recompute_period=100)
+    ctx.set_walkers(R)
+    ctx.run(1, mode=dmcx.DMCX_DMC, e_trial=-100.0)
+    Rg, _ = ctx.get_walkers()
+    dl, dv = ctx.ion_grads()
+    dl_o, dv_o, _ = oracle.ion_grads_batch(s, Rg)
+    _close(dl, dl_o, rel=1e-9)
+    _close(dv, dv_o)
+
+
+def test_ion_grads_vs_finite_differences():
+    s = synth.make_system(1)
+    W = 8
+    R = synth.make_walkers(s, W, 520)
+    ctx = dmcx.Context(s, W)
+    ctx.set_walkers(R)
+    dl, dv = ctx.ion_grads()
+    base = s.ion_xyz.copy()
+
+    def central(a, x, h):
+        vals = []
+        for sgn in (+1, -1):
+            xyz = base.copy()
+            xyz[a, x] += sgn * h
+            ctx.set_ions(xyz)
+            _, lp, _ = ctx.measure()
+            vals.append((lp, ctx.potential()))
+        return ((vals[0][0] - vals[1][0]) / (2 * h), (vals[0][1] - vals[1][1]) / (2 * h))
+
+    for a, x in [(0, 0), (1, 2), (3, 1)]:
+        # central differences at h = 1e-4 and 2e-4, Richardson-extrapolated (O(h^4))
+        l1, v1 = central(a, x, 2e-4)
+        l2, v2 = central(a, x, 1e-4)
+        fd_l = (4 * l2 - l1) / 3
+        fd_v = (4 * v2 - v1) / 3
+        np.testing.assert_allclose(dl[:, a, x], fd_l, rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(dv[:, a, x], fd_v, rtol=1e-6, atol=1e-6)
+    ctx.set_ions(base)
+
+
+def test_translation_sum_rule():
+    """sum_A dlnPsi/dR_A = -sum_i grad_i lnPsi (the oracle's drift)."""
+    s = synth.make_system(1)
+    W = 4
+    R = synth.make_walkers(s, W, 530)
+    ctx = dmcx.Context(s, W)
+    ctx.set_walkers(R)
+    dl, _ = ctx.ion_grads()
+    for w in range(W):
+        drift = oracle.evaluate(s, R[w])[3]
+        np.testing.assert_allclose(dl[w].sum(0), -drift.sum(0), rtol=1e-9, atol=1e-9)
+
+
+def test_vjps_and_force_estimator():
+    s = synth.make_system(1)
+    W = 24
+    R = synth.make_walkers(s, W, 540)
+    lw = np.random.default_rng(0).normal(0, 0.3, W)
+    ctx = dmcx.Context(s, W)
+    ctx.set_walkers(R, lw)
+    dl, dv = ctx.ion_grads()
+    g = np.random.default_rng(1).standard_normal(W)
+    _close(ctx.logpsi_vjp(g), np.einsum("w,wak->ak", g, dl), rel=1e-12)
+    _close(ctx.potential_vjp(g), np.einsum("w,wak->ak", g, dv), rel=1e-12)
+    e, _, _ = ctx.measure()
+    om = np.exp(lw - lw.max())
+    om /= om.sum()
+    mean = lambda x: np.einsum("w,w...->...", om, x)
+    F_ref = -mean(dv) - 2 * (mean(e[:, None, None] * dl) - mean(e) * mean(dl))
+    _close(ctx.forces(), F_ref, rel=1e-11)
+
+
+def test_autograd_function_matches_vjp():
+    torch = pytest.importorskip("torch")
+    from paper_2504_07948_amd.autograd import IonGradFn, force_objective
+    s = synth.make_system(1)
+    W = 16
+    R = synth.make_walkers(s, W, 550)
+    ctx = dmcx.Context(s, W)
+    ctx.set_walkers(R)
+    ion = torch.tensor(s.ion_xyz, dtype=torch.float64, requires_grad=True)
+    lp, v, e = IonGradFn.apply(ion, ctx)
+    om = torch.ones(W, dtype=torch.float64)
+    obj = force_objective(lp, v, e, om)
+    obj.backward()
+    _close(-ion.grad.numpy(), ctx.forces(), rel=1e-11)
