@@ -29,8 +29,9 @@
  *   - A context is bound to one HIP stream and is not thread-safe.
  *   - Walkers of several systems are concatenated in creation order; every
  *     per-walker array below has W = sum(walkers_per_sys) leading entries and
- *     uses the largest electron count N_e of all systems as its stride
- *     (entries beyond a system's own electron count are ignored / zero).
+ *     uses the largest electron count N_e (atom count n_atom_max) of all
+ *     systems as its stride.  Entries beyond a system's own count are not
+ *     read on input and not written on output (host accept logs: zero).
  */
 #ifndef DMCX_H
 #define DMCX_H
@@ -84,19 +85,32 @@ typedef struct {
   const double *ci_coef;     /* [n_det] */
 } dmcx_system;
 
+/* dmcx_options.flags */
+#define DMCX_FLAG_GRAPH 1u  /* dmcx_run replays one captured step graph per step */
+
 typedef struct {
   int32_t precision;         /* dmcx_precision */
-  int32_t delay_rank;        /* k of the delayed rank-k inverse update, 1..64; 0 = autotune */
+  int32_t delay_rank;        /* k of the delayed rank-k inverse update, 1..64 (capped at
+                                n_sigma); 0 = chosen by the autotuner at the first run */
   int32_t recompute_period;  /* P: full FP64 inverse recompute every P steps (>= 1) */
   double tau;                /* DMC time step (a.u.), > 0 */
   uint64_t seed;             /* Philox4x32-10 key */
-  uint32_t flags;            /* reserved, must be 0 */
+  uint32_t flags;            /* DMCX_FLAG_*; other bits must be 0 */
 } dmcx_options;
 
 /* Create a context for n_sys systems (n_sys >= 1) with walkers_per_sys[s]
  * walkers each, bound to hip_stream (a hipStream_t; NULL = default stream).
- * Allocates all device memory the context will ever use.  Walkers start
- * undefined: call dmcx_set_walkers before anything that reads them. */
+ * Allocates all device memory the context will ever use (the delay-rank
+ * autotuner and the first graph capture allocate small temporaries once).
+ * Walkers start undefined: call dmcx_set_walkers before anything that reads
+ * them.  Every system runs with the same options; walker w of system s uses
+ * the Philox counter (electron, w, step) under the shared key, so a system
+ * in a group moves exactly as it would in a context of its own.
+ * With n_sys > 1 the systems may differ in electron, atom and basis counts;
+ * dmcx_run forks them onto streams of their own (default priority) and
+ * joins them back into hip_stream.  The move-by-move calls
+ * (dmcx_eval_orbitals, dmcx_ratio_grad, dmcx_accept) need n_sys == 1 and
+ * return DMCX_E_UNSUPPORTED otherwise. */
 dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *walkers_per_sys,
                         const dmcx_options *opt, void *hip_stream, dmcx_ctx **out);
 void dmcx_destroy(dmcx_ctx *ctx);
@@ -143,9 +157,34 @@ dmcx_status dmcx_flush(dmcx_ctx *ctx);
  * per step, up electrons then down).  DMCX_DMC rejects node crossings and
  * updates log-weights with E_T = e_trial; DMCX_VMC leaves weights alone.
  * accept_log [n_steps][W][N_e] (uint8) and e_log [n_steps][W] may be NULL;
- * both are device pointers if mem == DMCX_DEVICE. */
+ * both are device pointers if mem == DMCX_DEVICE.  Each step is: FP64
+ * inverse recompute when step = 0 (mod P), the sweep, local energies and
+ * weights.  With DMCX_FLAG_GRAPH the step (of every system) is captured once
+ * into a hipGraph and replayed n_steps times; the capture is redone when
+ * the log pointers, the delay rank or the ions change.  Results are the same
+ * bits as without the flag.  With delay_rank == 0 the first run first
+ * times 2 sweeps per candidate rank (dmcx_autotune) and restores the
+ * walkers (inverses are then freshly recomputed). */
 dmcx_status dmcx_run(dmcx_ctx *ctx, dmcx_mode mode, int32_t n_steps, double e_trial,
                      uint8_t *accept_log, double *e_log, dmcx_mem mem);
+
+/* Delay-rank autotuner: for every system, time `steps` sweeps (after one
+ * untimed sweep) at each candidate rank k in {8, 16, 24, 32, 48, 64} below
+ * n_sigma plus n_sigma itself, limited to the rank the buffers were sized
+ * for at create (min(64, n_sigma) with delay_rank == 0, else delay_rank),
+ * keep the fastest, restore the walkers and recompute the inverses.
+ * chosen_k [n_sys] may be NULL.  The walker configurations and weights are
+ * unchanged; the step counter is unchanged. */
+dmcx_status dmcx_autotune(dmcx_ctx *ctx, int32_t steps, int32_t *chosen_k);
+
+/* The autotuner's last measurements for system sys_index: up to max_n
+ * candidate ranks and their average sweep times (ms); *n_cand = number of
+ * candidates (0 if the tuner has not run).  ranks / ms may be NULL. */
+dmcx_status dmcx_autotune_report(const dmcx_ctx *ctx, int32_t sys_index, int32_t max_n,
+                                 int32_t *ranks, float *ms_per_sweep, int32_t *n_cand);
+
+/* Delay rank currently used by system sys_index. */
+dmcx_status dmcx_get_delay_rank(const dmcx_ctx *ctx, int32_t sys_index, int32_t *k);
 
 /* Current local energy, log|Psi| and sign of every walker ([W] each;
  * any pointer may be NULL). */
@@ -177,9 +216,10 @@ dmcx_status dmcx_walker_flags(dmcx_ctx *ctx, uint8_t *flags, dmcx_mem mem);
 /* Wait for all work queued on the context's stream. */
 dmcx_status dmcx_sync(dmcx_ctx *ctx);
 
-/* Average duration (ms) of the most expensive kernel per launch over the
- * last dmcx_run, measured with HIP events on the context's stream, and the
- * number of such launches; for roofline reporting. */
+/* Average duration (ms) of the most expensive kernel (the sweep) per launch
+ * over the last dmcx_run, measured with HIP events on the stream it ran on,
+ * and the number of such launches (all systems of a group); for roofline
+ * reporting.  Graph runs (DMCX_FLAG_GRAPH) are not timed: 0 launches. */
 dmcx_status dmcx_last_run_timing(const dmcx_ctx *ctx, double *sweep_ms_avg, int32_t *n_launches,
                                  double *total_ms);
 

@@ -68,6 +68,30 @@ struct dmcx_ctx {
   // timing of the sweep kernel over the last dmcx_run
   std::vector<hipEvent_t> ev;
   int n_timed = 0;
+  // device run parameters (step counter, mode, E_T) read by the step kernels
+  RunState *d_run = nullptr;
+  // delay rank: buffers are sized for K_alloc; with delay_rank == 0 the rank
+  // is chosen by timing candidate ranks at the first run
+  int K_alloc = 1;
+  bool tune_pending = false;
+  std::vector<int> tune_cand;
+  std::vector<float> tune_ms;
+  // kernel arguments baked into a captured graph change with this counter
+  uint64_t dc_version = 1;
+  // several systems: this context is a group of single-system contexts that
+  // share the caller's stream; runs fork them onto streams of their own
+  std::vector<dmcx_ctx *> subs;
+  std::vector<int> sub_off;  // first walker of each system, creation order
+  hipStream_t own = nullptr; // this system's run stream (groups, graphs)
+  std::vector<hipEvent_t> fj;      // fork/join events of eager and graph runs
+  std::vector<hipEvent_t> cap_ev;  // fork/join events inside a graph capture
+  // captured step graph and the arguments it was captured with
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  uint8_t *g_acc = nullptr;
+  double *g_elog = nullptr;
+  uint64_t g_version = 0;
+  bool is_group() const { return !subs.empty(); }
 };
 
 namespace {
@@ -283,9 +307,10 @@ void launch_orbitals_at_t(dmcx_ctx *c, const double *pos, int npts, T *dst) {
   k_orbitals_at<T, NOB><<<dim3((npts + TW - 1) / TW), dim3(NT_TILE), basis_lds(c), c->stream>>>(c->dc, pos, npts, dst);
 }
 template <typename T, int NOB>
-void launch_sweep_t(dmcx_ctx *c, int mode, uint32_t step, uint8_t *acc) {
+void launch_sweep_t(dmcx_ctx *c, uint8_t *acc, long long acc_ss, int acc_ws) {
   allow_lds(k_sweep<T, NOB>, basis_lds(c));
-  k_sweep<T, NOB><<<dim3(c->Wpad / TW), dim3(NT_TILE), basis_lds(c), c->stream>>>(c->dc, mode, step, acc);
+  k_sweep<T, NOB><<<dim3(c->Wpad / TW), dim3(NT_TILE), basis_lds(c), c->stream>>>(c->dc, acc, acc_ss,
+                                                                                  acc_ws);
 }
 
 #define DISPATCH_NOB_T(T, fn, ...)                    \
@@ -309,29 +334,51 @@ void launch_orbitals_at(dmcx_ctx *c, const double *pos, int npts, void *dst) {
   if (c->mixed) { DISPATCH_NOB_T(float, launch_orbitals_at_t, c, pos, npts, (float *)dst); }
   else { DISPATCH_NOB_T(double, launch_orbitals_at_t, c, pos, npts, (double *)dst); }
 }
-void launch_sweep(dmcx_ctx *c, int mode, uint32_t step, uint8_t *acc) {
-  if (c->mixed) { DISPATCH_NOB_T(float, launch_sweep_t, c, mode, step, acc); }
-  else { DISPATCH_NOB_T(double, launch_sweep_t, c, mode, step, acc); }
+void launch_sweep(dmcx_ctx *c, uint8_t *acc, long long acc_ss, int acc_ws) {
+  if (c->mixed) { DISPATCH_NOB_T(float, launch_sweep_t, c, acc, acc_ss, acc_ws); }
+  else { DISPATCH_NOB_T(double, launch_sweep_t, c, acc, acc_ss, acc_ws); }
 }
 
-dmcx_status launch_inverse(dmcx_ctx *c) {
+// periodic != 0: the kernel itself skips steps that are not multiples of P
+dmcx_status launch_inverse(dmcx_ctx *c, int periodic = 0) {
   const int n = std::max(c->n_up, c->n_dn);
   const size_t lds = (size_t)n * n * sizeof(double);
   if (c->mixed)
-    hipLaunchKernelGGL(k_inverse<float>, dim3(c->Wpad, 2), dim3(NT_AUX), lds, c->stream, c->dc);
+    hipLaunchKernelGGL(k_inverse<float>, dim3(c->Wpad, 2), dim3(NT_AUX), lds, c->stream, c->dc,
+                       periodic);
   else
-    hipLaunchKernelGGL(k_inverse<double>, dim3(c->Wpad, 2), dim3(NT_AUX), lds, c->stream, c->dc);
+    hipLaunchKernelGGL(k_inverse<double>, dim3(c->Wpad, 2), dim3(NT_AUX), lds, c->stream, c->dc,
+                       periodic);
   return hip_check(c, hipGetLastError(), "k_inverse launch");
 }
 
-dmcx_status launch_local_energy(dmcx_ctx *c, int mode, double e_trial, double *e_log_row) {
+// measure_only != 0: E_L, V, log|Psi| only; else the end of a step (weights,
+// e_log row s_in_run of a table with row stride elog_ss)
+dmcx_status launch_local_energy(dmcx_ctx *c, int measure_only, double *e_log = nullptr,
+                                long long elog_ss = 0) {
   if (c->mixed)
     hipLaunchKernelGGL(k_local_energy<float>, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc,
-                       mode, e_trial, e_log_row);
+                       measure_only, e_log, elog_ss);
   else
     hipLaunchKernelGGL(k_local_energy<double>, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc,
-                       mode, e_trial, e_log_row);
+                       measure_only, e_log, elog_ss);
   return hip_check(c, hipGetLastError(), "k_local_energy launch");
+}
+
+__global__ void k_set_run(RunState *r, unsigned long long step, int mode, double e_trial) {
+  if (threadIdx.x == 0) {
+    r->step = step;
+    r->s_in_run = 0;
+    r->mode = mode;
+    r->e_trial = e_trial;
+  }
+}
+
+__global__ void k_advance(RunState *r) {
+  if (threadIdx.x == 0) {
+    r->step += 1ull;
+    r->s_in_run += 1;
+  }
 }
 
 __global__ void k_fill_pad(double *a, int W, int Wpad, int stride) {
@@ -462,7 +509,7 @@ dmcx_status refresh_after_moves(dmcx_ctx *c) {
   dmcx_status st = flush_pending(c);
   if (st) return st;
   if (c->eloc_dirty) {
-    if ((st = launch_local_energy(c, -1, 0.0, nullptr))) return st;
+    if ((st = launch_local_energy(c, 1))) return st;
     c->eloc_dirty = false;
   }
   return DMCX_OK;
@@ -525,38 +572,31 @@ const char *dmcx_strerror(dmcx_status s) {
 
 const char *dmcx_last_error(const dmcx_ctx *c) { return c ? c->err.c_str() : ""; }
 
-dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *walkers_per_sys,
-                        const dmcx_options *opt, void *hip_stream, dmcx_ctx **out) {
-  if (!out || !sys || !walkers_per_sys || !opt) return DMCX_E_INVALID;
+}  // extern "C"
+
+namespace {
+
+// One system's context (the unit every kernel works on).
+dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_options *opt,
+                       hipStream_t stream, dmcx_ctx **out, std::string *err_out) {
   *out = nullptr;
   dmcx_ctx *c = new dmcx_ctx();
-  c->stream = (hipStream_t)hip_stream;
+  c->stream = stream;
   c->opt = *opt;
-  auto bail = [&](dmcx_status s) {
-    fprintf(stderr, "dmcx_create: %s\n", c->err.c_str());
+  auto bail = [&](dmcx_status st) {
+    *err_out = c->err;
     delete c;
-    return s;
+    return st;
   };
-  if (n_sys != 1) {
-    c->err = "n_sys > 1 (uneven multi-system batching) not built yet";
-    return bail(DMCX_E_UNSUPPORTED);
-  }
-  if (!(opt->tau > 0.0) || opt->recompute_period < 1 || opt->flags != 0 ||
-      (opt->precision != DMCX_FP64 && opt->precision != DMCX_MIXED) || opt->delay_rank < 0 ||
-      opt->delay_rank > KMAX) {
-    c->err = "invalid options";
-    return bail(DMCX_E_INVALID);
-  }
   c->mixed = opt->precision == DMCX_MIXED;
   c->es = c->mixed ? sizeof(float) : sizeof(double);
-  const dmcx_system &s = sys[0];
   dmcx_status st = validate_system(c, s);
   if (st) return bail(st);
-  if (walkers_per_sys[0] < 1) {
+  if (n_walkers < 1) {
     c->err = "need at least one walker";
     return bail(DMCX_E_INVALID);
   }
-  c->W = walkers_per_sys[0];
+  c->W = n_walkers;
   c->Wpad = (c->W + TW - 1) / TW * TW;
   c->n_up = s.n_up;
   c->n_dn = s.n_dn;
@@ -566,8 +606,14 @@ dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *wa
   const int n_orb = std::max(s.n_up, s.n_dn);
   c->NOB = (n_orb + 15) / 16;
   c->NP = 16 * c->NOB;
-  const int kdef = std::min(32, n_orb);
-  c->K = opt->delay_rank == 0 ? kdef : std::min(opt->delay_rank, n_orb);
+  if (opt->delay_rank == 0) {
+    // candidates are timed at the first run; start from min(32, n_sigma)
+    c->K = std::min(32, n_orb);
+    c->K_alloc = std::min(KMAX, n_orb);
+    c->tune_pending = true;
+  } else {
+    c->K = c->K_alloc = std::min(opt->delay_rank, n_orb);
+  }
   c->P = opt->recompute_period;
   c->ion_xyz.assign(s.ion_xyz, s.ion_xyz + 3 * s.n_atom);
   if ((st = pack_basis(c, s, n_orb))) return bail(st);
@@ -606,6 +652,7 @@ dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *wa
   d.W = c->W;
   d.Wpad = c->Wpad;
   d.K = c->K;
+  d.P = c->P;
   d.tau = opt->tau;
   d.seed = opt->seed;
   const size_t Wp = c->Wpad;
@@ -616,17 +663,20 @@ dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *wa
   d.vglc = pv;
   if ((st = dalloc(c, &pv, es * Wp * 2 * c->NP * c->NP))) return bail(st);
   d.GT = pv;
-  if ((st = dalloc(c, &pv, es * Wp * c->K * c->NP))) return bail(st);
+  const size_t KA = c->K_alloc, KA16 = (KA + 15) / 16 * 16;
+  if ((st = dalloc(c, &pv, es * Wp * KA * c->NP))) return bail(st);
   d.Gb = pv;
-  if ((st = dalloc(c, &pv, es * Wp * c->K * c->NP))) return bail(st);
+  if ((st = dalloc(c, &pv, es * Wp * KA * c->NP))) return bail(st);
   d.Dl = pv;
   d.K16 = (c->K + 15) / 16 * 16;
-  if ((st = dalloc(c, &pv, es * Wp * d.K16 * c->NP))) return bail(st);
+  if ((st = dalloc(c, &pv, es * Wp * KA16 * c->NP))) return bail(st);
   d.Zs = pv;
-  if ((st = dalloc(c, &pv, es * Wp * d.K16 * c->NP))) return bail(st);
+  if ((st = dalloc(c, &pv, es * Wp * KA16 * c->NP))) return bail(st);
   d.Vs = pv;
-  if ((st = dalloc(c, &pv, es * Wp * c->K * c->K))) return bail(st);
+  if ((st = dalloc(c, &pv, es * Wp * KA * KA))) return bail(st);
   d.Ms = pv;
+  if ((st = dalloc(c, &c->d_run, 1))) return bail(st);
+  d.run = c->d_run;
   if ((st = dalloc(c, &d.logdet, Wp * 2))) return bail(st);
   if ((st = dalloc(c, &d.sgn, Wp * 2))) return bail(st);
   if ((st = dalloc(c, &d.eloc, Wp))) return bail(st);
@@ -653,6 +703,7 @@ dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *wa
   if ((st = dalloc(c, &c->d_orb_out, Wp * 5 * c->NP))) return bail(st);
   if (hipMemsetAsync(d.flags, 0, Wp * sizeof(unsigned), c->stream) != hipSuccess ||
       hipMemsetAsync(d.logw, 0, Wp * sizeof(double), c->stream) != hipSuccess ||
+      hipMemsetAsync(c->d_run, 0, sizeof(RunState), c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     c->err = "initialisation copies failed";
     return bail(DMCX_E_HIP);
@@ -661,34 +712,112 @@ dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *wa
   return DMCX_OK;
 }
 
-void dmcx_destroy(dmcx_ctx *c) {
+void destroy_one(dmcx_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  if (c->own) (void)hipStreamSynchronize(c->own);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->fj) (void)hipEventDestroy(e);
+  if (c->own) (void)hipStreamDestroy(c->own);
   delete c;
 }
 
-dmcx_status dmcx_set_walkers(dmcx_ctx *c, const double *R, const double *log_w, dmcx_mem mem) {
-  if (!c || !R) return DMCX_E_INVALID;
-  DevCtx &d = c->dc;
-  dmcx_status st;
-  const size_t per = (size_t)c->ne * 3;
-  if ((st = copy_in(c, d.R, R, c->W * per * sizeof(double), mem))) return st;
-  if (c->Wpad > c->W) {
-    const int n = (c->Wpad - c->W) * (int)per;
-    hipLaunchKernelGGL(k_fill_pad, dim3((n + 255) / 256), dim3(256), 0, c->stream, d.R, c->W,
-                       c->Wpad, (int)per);
+}  // namespace
+
+extern "C" {
+
+dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *walkers_per_sys,
+                        const dmcx_options *opt, void *hip_stream, dmcx_ctx **out) {
+  if (!out || !sys || !walkers_per_sys || !opt || n_sys < 1) return DMCX_E_INVALID;
+  *out = nullptr;
+  if (!(opt->tau > 0.0) || opt->recompute_period < 1 || (opt->flags & ~DMCX_FLAG_GRAPH) != 0 ||
+      (opt->precision != DMCX_FP64 && opt->precision != DMCX_MIXED) || opt->delay_rank < 0 ||
+      opt->delay_rank > KMAX) {
+    fprintf(stderr, "dmcx_create: invalid options\n");
+    return DMCX_E_INVALID;
   }
-  if (log_w) {
-    if ((st = copy_in(c, d.logw, log_w, c->W * sizeof(double), mem))) return st;
-  } else {
-    HIP_TRY(c, hipMemsetAsync(d.logw, 0, c->Wpad * sizeof(double), c->stream));
+  const hipStream_t stream = (hipStream_t)hip_stream;
+  std::string err;
+  if (n_sys == 1) {
+    dmcx_status st = create_one(sys[0], walkers_per_sys[0], opt, stream, out, &err);
+    if (st) fprintf(stderr, "dmcx_create: %s\n", err.c_str());
+    return st;
   }
-  HIP_TRY(c, hipMemsetAsync(d.flags, 0, c->Wpad * sizeof(unsigned), c->stream));
+  // a group: one context per system, all on the caller's stream between runs
+  dmcx_ctx *g = new dmcx_ctx();
+  g->stream = stream;
+  g->opt = *opt;
+  g->mixed = opt->precision == DMCX_MIXED;
+  for (int i = 0; i < n_sys; ++i) {
+    dmcx_ctx *c = nullptr;
+    dmcx_status st = create_one(sys[i], walkers_per_sys[i], opt, stream, &c, &err);
+    if (st) {
+      fprintf(stderr, "dmcx_create: system %d: %s\n", i, err.c_str());
+      for (dmcx_ctx *q : g->subs) destroy_one(q);
+      delete g;
+      return st;
+    }
+    g->sub_off.push_back(g->W);
+    g->subs.push_back(c);
+    g->W += c->W;
+    g->ne = std::max(g->ne, c->ne);
+    g->n_atom = std::max(g->n_atom, c->n_atom);
+  }
+  *out = g;
+  return DMCX_OK;
+}
+
+void dmcx_destroy(dmcx_ctx *c) {
+  if (!c) return;
+  for (dmcx_ctx *q : c->subs) destroy_one(q);
+  c->subs.clear();
+  destroy_one(c);
+}
+
+}  // extern "C"
+
+namespace {
+
+std::vector<dmcx_ctx *> members(dmcx_ctx *c) {
+  return c->is_group() ? c->subs : std::vector<dmcx_ctx *>{c};
+}
+
+// Strided copy between a caller array with row pitch spitch/dpitch (bytes)
+// and device memory; host buffers complete before return.
+dmcx_status copy2d(dmcx_ctx *c, void *dst, size_t dpitch, const void *src, size_t spitch,
+                   size_t width, size_t height, dmcx_mem mem, bool to_device) {
+  if (!width || !height) return DMCX_OK;
+  const hipMemcpyKind kind = mem == DMCX_DEVICE ? hipMemcpyDeviceToDevice
+                             : to_device        ? hipMemcpyHostToDevice
+                                                : hipMemcpyDeviceToHost;
+  HIP_TRY(c, hipMemcpy2DAsync(dst, dpitch, src, spitch, width, height, kind, c->stream));
+  if (mem == DMCX_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return DMCX_OK;
+}
+
+// Rebuild orbitals, inverses (FP64 LU) and E_L from the positions.
+dmcx_status rebuild_state(dmcx_ctx *c) {
   launch_orbitals_all(c);
   HIP_TRY(c, hipGetLastError());
+  dmcx_status st;
   if ((st = launch_inverse(c))) return st;
-  if ((st = launch_local_energy(c, -1, 0.0, nullptr))) return st;
+  return launch_local_energy(c, 1);
+}
+
+// Positions are in c->dc.R (log-weights in c->dc.logw): pad, rebuild, reset.
+dmcx_status set_walkers_core(dmcx_ctx *c) {
+  DevCtx &d = c->dc;
+  const int per = c->ne * 3;
+  if (c->Wpad > c->W) {
+    const int n = (c->Wpad - c->W) * per;
+    hipLaunchKernelGGL(k_fill_pad, dim3((n + 255) / 256), dim3(256), 0, c->stream, d.R, c->W,
+                       c->Wpad, per);
+  }
+  HIP_TRY(c, hipMemsetAsync(d.flags, 0, c->Wpad * sizeof(unsigned), c->stream));
+  dmcx_status st = rebuild_state(c);
+  if (st) return st;
   c->step = 0;
   c->walkers_set = true;
   c->blk_active = false;
@@ -698,9 +827,304 @@ dmcx_status dmcx_set_walkers(dmcx_ctx *c, const double *R, const double *log_w, 
   return DMCX_OK;
 }
 
+void set_delay_rank(dmcx_ctx *c, int k) {
+  c->K = k;
+  c->dc.K = k;
+  c->dc.K16 = (k + 15) / 16 * 16;
+  c->dc_version++;
+}
+
+// Enqueue one step of a single-system context on c->stream: periodic FP64
+// recompute, the sweep, local energies + weights, step counter advance.
+// graph: the recompute test is left to the kernel (device step counter).
+dmcx_status enqueue_step(dmcx_ctx *c, bool graph, uint8_t *acc, long long acc_ss, int acc_ws,
+                         double *elog, long long elog_ss, hipEvent_t e0, hipEvent_t e1) {
+  dmcx_status st;
+  if (graph) {
+    if ((st = launch_inverse(c, 1))) return st;
+  } else if (c->step % c->P == 0) {
+    if ((st = launch_inverse(c, 0))) return st;
+  }
+  if (e0) HIP_TRY(c, hipEventRecord(e0, c->stream));
+  launch_sweep(c, acc, acc_ss, acc_ws);
+  HIP_TRY(c, hipGetLastError());
+  if (e1) HIP_TRY(c, hipEventRecord(e1, c->stream));
+  if ((st = launch_local_energy(c, 0, elog, elog_ss))) return st;
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->d_run);
+  return hip_check(c, hipGetLastError(), "k_advance launch");
+}
+
+dmcx_status ensure_events(dmcx_ctx *c, std::vector<hipEvent_t> &v, size_t n, bool timing) {
+  while (v.size() < n) {
+    hipEvent_t e;
+    HIP_TRY(c, timing ? hipEventCreate(&e) : hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    v.push_back(e);
+  }
+  return DMCX_OK;
+}
+
+dmcx_status ensure_own_stream(dmcx_ctx *c) {
+  if (!c->own) HIP_TRY(c, hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+  return DMCX_OK;
+}
+
+// Delay-rank autotuner: time `steps` sweeps for each candidate rank (after
+// one untimed sweep) from the same walker state, keep the fastest, and
+// restore the walkers.  Candidates: 8, 16, 24, 32, 48, 64 below n_sigma, and
+// n_sigma itself, within the rank the buffers were sized for.
+dmcx_status autotune_one(dmcx_ctx *c, int steps) {
+  const int nsig = std::max(c->n_up, c->n_dn);
+  const int kmax = std::min(nsig, c->K_alloc);
+  std::vector<int> cand;
+  for (int k : {8, 16, 24, 32, 48, 64})
+    if (k < kmax) cand.push_back(k);
+  cand.push_back(kmax);
+  c->tune_cand = cand;
+  c->tune_ms.assign(cand.size(), 0.f);
+  c->tune_pending = false;
+  if (cand.size() == 1) {
+    if (c->K != kmax) set_delay_rank(c, kmax);
+    return DMCX_OK;
+  }
+  dmcx_status st = DMCX_OK;
+  const size_t nR = (size_t)c->Wpad * c->ne * 3;
+  double *Rb = nullptr, *Lb = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipMalloc(&Rb, nR * sizeof(double)) != hipSuccess ||
+      hipMalloc(&Lb, c->Wpad * sizeof(double)) != hipSuccess)
+    st = fail(c, DMCX_E_NOMEM, "autotune: hipMalloc");
+  if (!st && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    st = fail(c, DMCX_E_HIP, "autotune: hipEventCreate");
+  auto restore = [&]() -> dmcx_status {
+    HIP_TRY(c, hipMemcpyAsync(c->dc.R, Rb, nR * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->dc.logw, Lb, c->Wpad * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream));
+    return rebuild_state(c);
+  };
+  if (!st && (hipMemcpyAsync(Rb, c->dc.R, nR * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream) != hipSuccess ||
+              hipMemcpyAsync(Lb, c->dc.logw, c->Wpad * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream) != hipSuccess))
+    st = fail(c, DMCX_E_HIP, "autotune: backup copy");
+  size_t best = 0;
+  for (size_t q = 0; q < cand.size() && !st; ++q) {
+    set_delay_rank(c, cand[q]);
+    if ((st = restore())) break;
+    hipLaunchKernelGGL(k_set_run, dim3(1), dim3(64), 0, c->stream, c->d_run,
+                       (unsigned long long)c->step, 0, 0.0);
+    launch_sweep(c, nullptr, 0, 0);  // untimed
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->d_run);
+    if (hipEventRecord(e0, c->stream) != hipSuccess) { st = fail(c, DMCX_E_HIP, "autotune: event"); break; }
+    for (int s = 0; s < steps; ++s) {
+      launch_sweep(c, nullptr, 0, 0);
+      hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->d_run);
+    }
+    if (hipGetLastError() != hipSuccess || hipEventRecord(e1, c->stream) != hipSuccess ||
+        hipEventSynchronize(e1) != hipSuccess) {
+      st = fail(c, DMCX_E_HIP, "autotune: timed sweeps");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    c->tune_ms[q] = ms / steps;
+    if (c->tune_ms[q] < c->tune_ms[best]) best = q;
+  }
+  if (!st) {
+    set_delay_rank(c, cand[best]);
+    st = restore();
+  }
+  if (!st) st = hip_check(c, hipStreamSynchronize(c->stream), "autotune: sync");
+  if (Rb) (void)hipFree(Rb);
+  if (Lb) (void)hipFree(Lb);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  c->version++;
+  return st;
+}
+
+// Capture one step of every member (forked onto the members' own streams)
+// into a graph.  Log pointers and strides are baked in; the step index,
+// mode and E_T are read from each member's device run state.
+dmcx_status build_graph(dmcx_ctx *top, const std::vector<dmcx_ctx *> &ms, uint8_t *acc,
+                        double *elog, uint64_t key) {
+  if (top->gexec) { (void)hipGraphExecDestroy(top->gexec); top->gexec = nullptr; }
+  if (top->graph) { (void)hipGraphDestroy(top->graph); top->graph = nullptr; }
+  dmcx_status st;
+  if ((st = ensure_events(top, top->cap_ev, 1 + ms.size(), false))) return st;
+  const hipStream_t s0 = ms[0]->own;
+  HIP_TRY(top, hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed));
+  const long long acc_ss = (long long)top->W * top->ne, elog_ss = top->W;
+  if (hipEventRecord(top->cap_ev[0], s0) != hipSuccess) st = fail(top, DMCX_E_HIP, "capture: fork event");
+  for (size_t i = 1; i < ms.size() && !st; ++i)
+    if (hipStreamWaitEvent(ms[i]->own, top->cap_ev[0], 0) != hipSuccess)
+      st = fail(top, DMCX_E_HIP, "capture: fork wait");
+  for (size_t i = 0; i < ms.size() && !st; ++i) {
+    dmcx_ctx *m = ms[i];
+    const size_t off = top->is_group() ? top->sub_off[i] : 0;
+    const hipStream_t keep = m->stream;
+    m->stream = m->own;
+    st = enqueue_step(m, true, acc ? acc + off * top->ne : nullptr, acc_ss, top->ne,
+                      elog ? elog + off : nullptr, elog_ss, nullptr, nullptr);
+    m->stream = keep;
+    if (st) top->err = m->err;
+    if (!st && i > 0 && (hipEventRecord(top->cap_ev[i], m->own) != hipSuccess ||
+                         hipStreamWaitEvent(s0, top->cap_ev[i], 0) != hipSuccess))
+      st = fail(top, DMCX_E_HIP, "capture: join");
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(s0, &g);
+  if (!st && ee != hipSuccess) st = hip_check(top, ee, "hipStreamEndCapture");
+  if (st) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  top->graph = g;
+  HIP_TRY(top, hipGraphInstantiate(&top->gexec, g, nullptr, nullptr, 0));
+  top->g_acc = acc;
+  top->g_elog = elog;
+  top->g_version = key;
+  return DMCX_OK;
+}
+
+// n_steps full steps of every member.  acc / elog are device pointers (or
+// null) to [n_steps][W][N_e] and [n_steps][W] tables.
+dmcx_status run_impl(dmcx_ctx *top, int mode, int n_steps, double e_trial, uint8_t *acc,
+                     double *elog) {
+  const std::vector<dmcx_ctx *> ms = members(top);
+  dmcx_status st;
+  for (dmcx_ctx *m : ms) {
+    if ((st = refresh_after_moves(m))) { top->err = m->err; return st; }
+    if (m->tune_pending && (st = autotune_one(m, 2))) { top->err = m->err; return st; }
+  }
+  for (dmcx_ctx *m : ms) {
+    hipLaunchKernelGGL(k_set_run, dim3(1), dim3(64), 0, top->stream, m->d_run,
+                       (unsigned long long)m->step, mode, e_trial);
+    HIP_TRY(top, hipGetLastError());
+  }
+  if (n_steps == 0) return DMCX_OK;
+  const bool graph = (top->opt.flags & DMCX_FLAG_GRAPH) != 0;
+  const long long acc_ss = (long long)top->W * top->ne, elog_ss = top->W;
+  if (!graph && !top->is_group()) {
+    // one system, eager, on the caller's stream; the sweep is timed with events
+    dmcx_ctx *c = top;
+    if ((st = ensure_events(c, c->ev, 2 * (size_t)n_steps, true))) return st;
+    for (int s = 0; s < n_steps; ++s) {
+      if ((st = enqueue_step(c, false, acc, acc_ss, c->ne, elog, elog_ss, c->ev[2 * s],
+                             c->ev[2 * s + 1])))
+        return st;
+      c->step++;
+    }
+    c->n_timed = n_steps;
+    c->version++;
+    return DMCX_OK;
+  }
+  for (dmcx_ctx *m : ms)
+    if ((st = ensure_own_stream(m))) { top->err = m->err; return st; }
+  if ((st = ensure_events(top, top->fj, 2 + ms.size(), false))) return st;
+  HIP_TRY(top, hipEventRecord(top->fj[0], top->stream));
+  if (graph) {
+    uint64_t key = top->dc_version;
+    for (dmcx_ctx *m : ms) key += m->dc_version;
+    if (!top->gexec || top->g_acc != acc || top->g_elog != elog || top->g_version != key)
+      if ((st = build_graph(top, ms, acc, elog, key))) return st;
+    const hipStream_t s0 = ms[0]->own;
+    HIP_TRY(top, hipStreamWaitEvent(s0, top->fj[0], 0));
+    for (int s = 0; s < n_steps; ++s) HIP_TRY(top, hipGraphLaunch(top->gexec, s0));
+    HIP_TRY(top, hipEventRecord(top->fj[1], s0));
+    HIP_TRY(top, hipStreamWaitEvent(top->stream, top->fj[1], 0));
+    for (dmcx_ctx *m : ms) {
+      m->step += n_steps;
+      m->n_timed = 0;
+      m->version++;
+    }
+  } else {
+    // several systems, eager: each on its own stream, joined into the caller's
+    for (size_t i = 0; i < ms.size(); ++i) {
+      dmcx_ctx *m = ms[i];
+      const size_t off = top->sub_off[i];
+      HIP_TRY(top, hipStreamWaitEvent(m->own, top->fj[0], 0));
+      if ((st = ensure_events(m, m->ev, 2 * (size_t)n_steps, true))) { top->err = m->err; return st; }
+      const hipStream_t keep = m->stream;
+      m->stream = m->own;
+      for (int s = 0; s < n_steps && !st; ++s) {
+        st = enqueue_step(m, false, acc ? acc + off * top->ne : nullptr, acc_ss, top->ne,
+                          elog ? elog + off : nullptr, elog_ss, m->ev[2 * s], m->ev[2 * s + 1]);
+        m->step++;
+      }
+      m->stream = keep;
+      if (st) { top->err = m->err; return st; }
+      m->n_timed = n_steps;
+      m->version++;
+      HIP_TRY(top, hipEventRecord(top->fj[1 + i], m->own));
+      HIP_TRY(top, hipStreamWaitEvent(top->stream, top->fj[1 + i], 0));
+    }
+  }
+  top->step = ms[0]->step;
+  top->version++;
+  return DMCX_OK;
+}
+
+dmcx_status group_unsupported(dmcx_ctx *c, const char *what) {
+  return fail(c, DMCX_E_UNSUPPORTED,
+              std::string(what) + " needs a single-system context (create one per system)");
+}
+
+}  // namespace
+
+extern "C" {
+
+dmcx_status dmcx_set_walkers(dmcx_ctx *c, const double *R, const double *log_w, dmcx_mem mem) {
+  if (!c || !R) return DMCX_E_INVALID;
+  dmcx_status st;
+  if (c->is_group()) {
+    const size_t pitch = (size_t)c->ne * 3 * sizeof(double);
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      dmcx_ctx *m = c->subs[i];
+      const size_t off = c->sub_off[i];
+      if ((st = copy2d(m, m->dc.R, (size_t)m->ne * 3 * sizeof(double), R + off * c->ne * 3, pitch,
+                       (size_t)m->ne * 3 * sizeof(double), m->W, mem, true)))
+        return c->err = m->err, st;
+      if (log_w) {
+        if ((st = copy_in(m, m->dc.logw, log_w + off, m->W * sizeof(double), mem)))
+          return c->err = m->err, st;
+      } else {
+        HIP_TRY(c, hipMemsetAsync(m->dc.logw, 0, m->Wpad * sizeof(double), c->stream));
+      }
+      if ((st = set_walkers_core(m))) return c->err = m->err, st;
+    }
+    c->step = 0;
+    c->walkers_set = true;
+    c->version++;
+    return DMCX_OK;
+  }
+  DevCtx &d = c->dc;
+  const size_t per = (size_t)c->ne * 3;
+  if ((st = copy_in(c, d.R, R, c->W * per * sizeof(double), mem))) return st;
+  if (log_w) {
+    if ((st = copy_in(c, d.logw, log_w, c->W * sizeof(double), mem))) return st;
+  } else {
+    HIP_TRY(c, hipMemsetAsync(d.logw, 0, c->Wpad * sizeof(double), c->stream));
+  }
+  return set_walkers_core(c);
+}
+
 dmcx_status dmcx_get_walkers(dmcx_ctx *c, double *R, double *log_w, dmcx_mem mem) {
   if (!c || !c->walkers_set) return c ? fail(c, DMCX_E_STATE, "walkers not set") : DMCX_E_INVALID;
   dmcx_status st;
+  if (c->is_group()) {
+    const size_t pitch = (size_t)c->ne * 3 * sizeof(double);
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      dmcx_ctx *m = c->subs[i];
+      const size_t off = c->sub_off[i];
+      if (R && (st = copy2d(m, R + off * c->ne * 3, pitch, m->dc.R,
+                            (size_t)m->ne * 3 * sizeof(double), (size_t)m->ne * 3 * sizeof(double),
+                            m->W, mem, false)))
+        return c->err = m->err, st;
+      if (log_w && (st = copy_out(m, log_w + off, m->dc.logw, m->W * sizeof(double), mem)))
+        return c->err = m->err, st;
+    }
+    return DMCX_OK;
+  }
   if (R && (st = copy_out(c, R, c->dc.R, (size_t)c->W * c->ne * 3 * sizeof(double), mem))) return st;
   if (log_w && (st = copy_out(c, log_w, c->dc.logw, (size_t)c->W * sizeof(double), mem))) return st;
   return DMCX_OK;
@@ -708,6 +1132,7 @@ dmcx_status dmcx_get_walkers(dmcx_ctx *c, double *R, double *log_w, dmcx_mem mem
 
 dmcx_status dmcx_set_step(dmcx_ctx *c, int64_t step) {
   if (!c || step < 0) return DMCX_E_INVALID;
+  for (dmcx_ctx *m : members(c)) m->step = step;
   c->step = step;
   return DMCX_OK;
 }
@@ -720,6 +1145,15 @@ dmcx_status dmcx_get_step(const dmcx_ctx *c, int64_t *step) {
 
 dmcx_status dmcx_set_ions(dmcx_ctx *c, int32_t sys_index, const double *ion_xyz, dmcx_mem mem) {
   if (!c || !ion_xyz) return DMCX_E_INVALID;
+  if (c->is_group()) {
+    if (sys_index < 0 || sys_index >= (int)c->subs.size())
+      return fail(c, DMCX_E_INVALID, "sys_index out of range");
+    dmcx_ctx *m = c->subs[sys_index];
+    const dmcx_status st = dmcx_set_ions(m, 0, ion_xyz, mem);
+    if (st) c->err = m->err;
+    c->version++;
+    return st;
+  }
   if (sys_index != 0) return fail(c, DMCX_E_INVALID, "sys_index out of range");
   const size_t n = (size_t)c->n_atom * 3;
   std::vector<double> h(n);
@@ -740,20 +1174,24 @@ dmcx_status dmcx_set_ions(dmcx_ctx *c, int32_t sys_index, const double *ion_xyz,
   HIP_TRY(c, hipMemcpyAsync(c->d_ion, h.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->dc.v_nn = nuclear_repulsion(c->ion_xyz, c->ion_Z);
+  c->dc_version++;  // v_nn is a kernel argument
   c->version++;
   c->blk_active = false;  // everything below is rebuilt from the positions
   c->prop_iel = -1;
   c->eloc_dirty = false;
   if (!c->walkers_set) return DMCX_OK;
-  launch_orbitals_all(c);
-  HIP_TRY(c, hipGetLastError());
-  dmcx_status st;
-  if ((st = launch_inverse(c))) return st;
-  return launch_local_energy(c, -1, 0.0, nullptr);
+  return rebuild_state(c);
 }
 
 dmcx_status dmcx_recompute(dmcx_ctx *c) {
   if (!c || !c->walkers_set) return c ? fail(c, DMCX_E_STATE, "walkers not set") : DMCX_E_INVALID;
+  if (c->is_group()) {
+    for (dmcx_ctx *m : c->subs) {
+      const dmcx_status st = dmcx_recompute(m);
+      if (st) return c->err = m->err, st;
+    }
+    return DMCX_OK;
+  }
   dmcx_status st = flush_pending(c);
   if (st) return st;
   st = launch_inverse(c);
@@ -764,6 +1202,7 @@ dmcx_status dmcx_recompute(dmcx_ctx *c) {
 dmcx_status dmcx_eval_orbitals(dmcx_ctx *c, int32_t spin, const double *r, double *vgl,
                                dmcx_mem mem) {
   if (!c || !r || !vgl || spin < 0 || spin > 1) return DMCX_E_INVALID;
+  if (c->is_group()) return group_unsupported(c, "dmcx_eval_orbitals");
   dmcx_status st;
   if ((st = copy_in(c, c->d_pos, r, (size_t)c->W * 3 * sizeof(double), mem))) return st;
   launch_orbitals_at(c, c->d_pos, c->W, c->d_orb);
@@ -787,6 +1226,7 @@ dmcx_status dmcx_eval_orbitals(dmcx_ctx *c, int32_t spin, const double *r, doubl
 dmcx_status dmcx_ratio_grad(dmcx_ctx *c, int32_t iel, const double *r_new, double *ratio,
                             double *grad, dmcx_mem mem) {
   if (!c || !r_new || !ratio || !grad) return DMCX_E_INVALID;
+  if (c->is_group()) return group_unsupported(c, "dmcx_ratio_grad");
   if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
   if (iel < 0 || iel >= c->ne) return fail(c, DMCX_E_INVALID, "electron index out of range");
   const int sp = iel < c->n_up ? 0 : 1, ii = iel - sp * c->n_up;
@@ -828,6 +1268,7 @@ dmcx_status dmcx_ratio_grad(dmcx_ctx *c, int32_t iel, const double *r_new, doubl
 
 dmcx_status dmcx_accept(dmcx_ctx *c, int32_t iel, const uint8_t *accept, dmcx_mem mem) {
   if (!c || !accept) return DMCX_E_INVALID;
+  if (c->is_group()) return group_unsupported(c, "dmcx_accept");
   if (!c->blk_active || c->prop_iel != iel)
     return fail(c, DMCX_E_STATE, "dmcx_accept needs the preceding dmcx_ratio_grad of this electron");
   dmcx_status st;
@@ -845,7 +1286,11 @@ dmcx_status dmcx_accept(dmcx_ctx *c, int32_t iel, const uint8_t *accept, dmcx_me
 
 dmcx_status dmcx_flush(dmcx_ctx *c) {
   if (!c) return DMCX_E_INVALID;
-  return flush_pending(c);
+  for (dmcx_ctx *m : members(c)) {
+    const dmcx_status st = flush_pending(m);
+    if (st) return c->err = m->err, st;
+  }
+  return DMCX_OK;
 }
 
 dmcx_status dmcx_run(dmcx_ctx *c, dmcx_mode mode, int32_t n_steps, double e_trial,
@@ -853,48 +1298,86 @@ dmcx_status dmcx_run(dmcx_ctx *c, dmcx_mode mode, int32_t n_steps, double e_tria
   if (!c || n_steps < 0 || (mode != DMCX_VMC && mode != DMCX_DMC)) return DMCX_E_INVALID;
   if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
   dmcx_status st;
-  if ((st = refresh_after_moves(c))) return st;
   const size_t acc_bytes = (size_t)n_steps * c->W * c->ne, elog_bytes = (size_t)n_steps * c->W * 8;
   uint8_t *acc = accept_log;
   double *elog = e_log;
   if (accept_log && mem == DMCX_HOST) {
     if ((st = ensure_stage(c, (void **)&c->d_acc_stage, &c->acc_stage_bytes, acc_bytes))) return st;
     acc = c->d_acc_stage;
+    // entries of systems with fewer electrons than the stride stay zero
+    if (c->is_group()) HIP_TRY(c, hipMemsetAsync(acc, 0, acc_bytes, c->stream));
   }
   if (e_log && mem == DMCX_HOST) {
     if ((st = ensure_stage(c, (void **)&c->d_elog_stage, &c->elog_stage_bytes, elog_bytes))) return st;
     elog = c->d_elog_stage;
   }
-  while ((int)c->ev.size() < 2 * n_steps) {
-    hipEvent_t e;
-    HIP_TRY(c, hipEventCreate(&e));
-    c->ev.push_back(e);
-  }
-  for (int s = 0; s < n_steps; ++s) {
-    if (c->step % c->P == 0 && (st = launch_inverse(c))) return st;
-    HIP_TRY(c, hipEventRecord(c->ev[2 * s], c->stream));
-    launch_sweep(c, (int)mode, (uint32_t)c->step, acc ? acc + (size_t)s * c->W * c->ne : nullptr);
-    HIP_TRY(c, hipGetLastError());
-    HIP_TRY(c, hipEventRecord(c->ev[2 * s + 1], c->stream));
-    if ((st = launch_local_energy(c, (int)mode, e_trial, elog ? elog + (size_t)s * c->W : nullptr)))
-      return st;
-    c->step++;
-  }
-  if (n_steps > 0) c->version++;
-  c->n_timed = n_steps;
-  if (accept_log && mem == DMCX_HOST) {
+  if ((st = run_impl(c, (int)mode, n_steps, e_trial, acc, elog))) return st;
+  if (accept_log && mem == DMCX_HOST)
     HIP_TRY(c, hipMemcpyAsync(accept_log, acc, acc_bytes, hipMemcpyDeviceToHost, c->stream));
-  }
-  if (e_log && mem == DMCX_HOST) {
+  if (e_log && mem == DMCX_HOST)
     HIP_TRY(c, hipMemcpyAsync(e_log, elog, elog_bytes, hipMemcpyDeviceToHost, c->stream));
-  }
   if (mem == DMCX_HOST && (accept_log || e_log)) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_autotune(dmcx_ctx *c, int32_t steps, int32_t *chosen_k) {
+  if (!c || steps < 1) return DMCX_E_INVALID;
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  const std::vector<dmcx_ctx *> ms = members(c);
+  for (size_t i = 0; i < ms.size(); ++i) {
+    dmcx_ctx *m = ms[i];
+    dmcx_status st = refresh_after_moves(m);
+    if (!st) st = autotune_one(m, steps);
+    if (st) return c->err = m->err, st;
+    if (chosen_k) chosen_k[i] = m->K;
+  }
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_autotune_report(const dmcx_ctx *c, int32_t sys_index, int32_t max_n,
+                                 int32_t *ranks, float *ms_per_sweep, int32_t *n_cand) {
+  if (!c || !n_cand || max_n < 0) return DMCX_E_INVALID;
+  const dmcx_ctx *m = c;
+  if (c->is_group()) {
+    if (sys_index < 0 || sys_index >= (int)c->subs.size()) return DMCX_E_INVALID;
+    m = c->subs[sys_index];
+  } else if (sys_index != 0) {
+    return DMCX_E_INVALID;
+  }
+  const int n = (int)m->tune_cand.size();
+  *n_cand = n;
+  for (int q = 0; q < n && q < max_n; ++q) {
+    if (ranks) ranks[q] = m->tune_cand[q];
+    if (ms_per_sweep) ms_per_sweep[q] = m->tune_ms[q];
+  }
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_get_delay_rank(const dmcx_ctx *c, int32_t sys_index, int32_t *k) {
+  if (!c || !k) return DMCX_E_INVALID;
+  if (c->is_group()) {
+    if (sys_index < 0 || sys_index >= (int)c->subs.size()) return DMCX_E_INVALID;
+    *k = c->subs[sys_index]->K;
+  } else {
+    if (sys_index != 0) return DMCX_E_INVALID;
+    *k = c->K;
+  }
   return DMCX_OK;
 }
 
 dmcx_status dmcx_measure(dmcx_ctx *c, double *e_local, double *log_psi, int8_t *sign, dmcx_mem mem) {
   if (!c) return DMCX_E_INVALID;
   if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  if (c->is_group()) {
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      const size_t off = c->sub_off[i];
+      const dmcx_status st = dmcx_measure(c->subs[i], e_local ? e_local + off : nullptr,
+                                          log_psi ? log_psi + off : nullptr,
+                                          sign ? sign + off : nullptr, mem);
+      if (st) return c->err = c->subs[i]->err, st;
+    }
+    return DMCX_OK;
+  }
   dmcx_status st0 = refresh_after_moves(c);
   if (st0) return st0;
   if (mem == DMCX_DEVICE) {
@@ -919,6 +1402,22 @@ dmcx_status dmcx_ion_grads(dmcx_ctx *c, double *dlogpsi_dR, double *dV_dR, dmcx_
   if (!c) return DMCX_E_INVALID;
   if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
   dmcx_status st;
+  if (c->is_group()) {
+    // [W][n_atom_max][3]: each system fills its walkers' rows up to its own atom count
+    const size_t pitch = (size_t)c->n_atom * 3 * sizeof(double);
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      dmcx_ctx *m = c->subs[i];
+      const size_t off = c->sub_off[i], w = (size_t)m->n_atom * 3 * sizeof(double);
+      if ((st = compute_ion_grads(m))) return c->err = m->err, st;
+      if (dlogpsi_dR && (st = copy2d(m, dlogpsi_dR + off * c->n_atom * 3, pitch, m->d_dl, w, w,
+                                     m->W, mem, false)))
+        return c->err = m->err, st;
+      if (dV_dR && (st = copy2d(m, dV_dR + off * c->n_atom * 3, pitch, m->d_dv, w, w, m->W, mem,
+                                false)))
+        return c->err = m->err, st;
+    }
+    return DMCX_OK;
+  }
   if ((st = compute_ion_grads(c))) return st;
   const size_t bytes = (size_t)c->W * c->n_atom * 3 * sizeof(double);
   if (dlogpsi_dR && (st = copy_out(c, dlogpsi_dR, c->d_dl, bytes, mem))) return st;
@@ -927,10 +1426,28 @@ dmcx_status dmcx_ion_grads(dmcx_ctx *c, double *dlogpsi_dR, double *dV_dR, dmcx_
 }
 
 dmcx_status dmcx_logpsi_vjp(dmcx_ctx *c, const double *gbar, double *grad_R, dmcx_mem mem) {
+  if (c && c->is_group() && gbar && grad_R) {
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      dmcx_ctx *m = c->subs[i];
+      const dmcx_status st = walker_vjp(m, m->d_dl, gbar + c->sub_off[i],
+                                        grad_R + i * (size_t)c->n_atom * 3, mem);
+      if (st) return c->err = m->err, st;
+    }
+    return DMCX_OK;
+  }
   return walker_vjp(c, c ? c->d_dl : nullptr, gbar, grad_R, mem);
 }
 
 dmcx_status dmcx_potential_vjp(dmcx_ctx *c, const double *gbar, double *grad_R, dmcx_mem mem) {
+  if (c && c->is_group() && gbar && grad_R) {
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      dmcx_ctx *m = c->subs[i];
+      const dmcx_status st = walker_vjp(m, m->d_dv, gbar + c->sub_off[i],
+                                        grad_R + i * (size_t)c->n_atom * 3, mem);
+      if (st) return c->err = m->err, st;
+    }
+    return DMCX_OK;
+  }
   return walker_vjp(c, c ? c->d_dv : nullptr, gbar, grad_R, mem);
 }
 
@@ -938,6 +1455,13 @@ dmcx_status dmcx_forces(dmcx_ctx *c, double *F, dmcx_mem mem) {
   if (!c || !F) return DMCX_E_INVALID;
   if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
   dmcx_status st;
+  if (c->is_group()) {
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      dmcx_ctx *m = c->subs[i];
+      if ((st = dmcx_forces(m, F + i * (size_t)c->n_atom * 3, mem))) return c->err = m->err, st;
+    }
+    return DMCX_OK;
+  }
   if ((st = compute_ion_grads(c))) return st;
   const int ncomp = c->n_atom * 3;
   double *dst = mem == DMCX_DEVICE ? F : c->d_red;
@@ -951,6 +1475,13 @@ dmcx_status dmcx_forces(dmcx_ctx *c, double *F, dmcx_mem mem) {
 dmcx_status dmcx_potential(dmcx_ctx *c, double *v, dmcx_mem mem) {
   if (!c || !v) return DMCX_E_INVALID;
   if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  if (c->is_group()) {
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      const dmcx_status st = dmcx_potential(c->subs[i], v + c->sub_off[i], mem);
+      if (st) return c->err = c->subs[i]->err, st;
+    }
+    return DMCX_OK;
+  }
   dmcx_status st = refresh_after_moves(c);
   if (st) return st;
   return copy_out(c, v, c->dc.vpot, (size_t)c->W * sizeof(double), mem);
@@ -958,6 +1489,13 @@ dmcx_status dmcx_potential(dmcx_ctx *c, double *v, dmcx_mem mem) {
 
 dmcx_status dmcx_walker_flags(dmcx_ctx *c, uint8_t *flags, dmcx_mem mem) {
   if (!c || !flags) return DMCX_E_INVALID;
+  if (c->is_group()) {
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      const dmcx_status st = dmcx_walker_flags(c->subs[i], flags + c->sub_off[i], mem);
+      if (st) return c->err = c->subs[i]->err, st;
+    }
+    return DMCX_OK;
+  }
   uint8_t *dst = flags;
   if (mem == DMCX_HOST) dst = (uint8_t *)c->d_orb;
   hipLaunchKernelGGL(k_flags_out, dim3((c->W + 255) / 256), dim3(256), 0, c->stream, c->dc, dst);
@@ -979,14 +1517,18 @@ dmcx_status dmcx_last_run_timing(const dmcx_ctx *cc, double *sweep_ms_avg, int32
   dmcx_ctx *c = const_cast<dmcx_ctx *>(cc);
   if (!c) return DMCX_E_INVALID;
   double tot = 0.0;
-  for (int s = 0; s < c->n_timed; ++s) {
-    HIP_TRY(c, hipEventSynchronize(c->ev[2 * s + 1]));
-    float ms = 0.f;
-    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[2 * s], c->ev[2 * s + 1]));
-    tot += ms;
+  int n = 0;
+  for (dmcx_ctx *m : members(c)) {
+    for (int s = 0; s < m->n_timed; ++s) {
+      HIP_TRY(c, hipEventSynchronize(m->ev[2 * s + 1]));
+      float ms = 0.f;
+      HIP_TRY(c, hipEventElapsedTime(&ms, m->ev[2 * s], m->ev[2 * s + 1]));
+      tot += ms;
+    }
+    n += m->n_timed;
   }
-  if (sweep_ms_avg) *sweep_ms_avg = c->n_timed ? tot / c->n_timed : 0.0;
-  if (n_launches) *n_launches = c->n_timed;
+  if (sweep_ms_avg) *sweep_ms_avg = n ? tot / n : 0.0;
+  if (n_launches) *n_launches = n;
   if (total_ms) *total_ms = tot;
   return DMCX_OK;
 }

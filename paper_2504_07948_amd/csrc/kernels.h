@@ -122,6 +122,18 @@ __device__ inline BasisLDS stage_basis_lds(const DevBasis &B, char *smem) {
   return L;
 }
 
+// Per-context run parameters kept in device memory, so that one captured
+// step (a hipGraph) stays valid across replays: kernels read the step index
+// (Philox counter field, recompute phase), the mode and E_T from here, and a
+// one-thread kernel advances the counters at the end of each step.
+struct RunState {
+  unsigned long long step;      // global step index
+  long long s_in_run;           // step index within the current run (log rows)
+  double e_trial;               // E_T of the DMC weight update
+  int mode;                     // 0 = VMC, 1 = DMC
+  int pad_;
+};
+
 struct DevCtx {
   DevBasis B;
   int NP;                // padded orbital count (multiple of 16)
@@ -131,6 +143,8 @@ struct DevCtx {
   const double *jen_a;   // [n_atom]
   double jen_b, jee_anti, jee_para, jee_b, v_nn;
   int W, Wpad, K, K16;  // delay rank and its multiple-of-16 padding
+  int P;                // FP64 inverse recompute period (steps)
+  RunState *run;        // device run parameters
   double tau;
   uint64_t seed;
   // walker state
@@ -539,8 +553,10 @@ __global__ __launch_bounds__(NT_TILE) void k_orbitals_at(DevCtx c, const double 
 // elimination with partial pivoting, built from the cached value rows.
 // grid (Wpad, 2); dynamic LDS n*n doubles.  Writes GT (transposed, zero
 // padded), log|det| and sign; flags singular matrices.
+// periodic != 0: runs only at steps s = 0 (mod P) of the device step counter
+// (the form captured into a step graph); periodic == 0: always.
 template <typename T>
-__global__ __launch_bounds__(NT_AUX) void k_inverse(DevCtx c) {
+__global__ __launch_bounds__(NT_AUX) void k_inverse(DevCtx c, int periodic) {
   extern __shared__ double A[];
   __shared__ int piv[128];
   __shared__ double fcol[128];
@@ -548,6 +564,7 @@ __global__ __launch_bounds__(NT_AUX) void k_inverse(DevCtx c) {
   __shared__ int pv_idx[NT_AUX / 64];
   __shared__ double s_logdet;
   __shared__ int s_sign, s_sing;
+  if (periodic && (c.run->step % (unsigned long long)c.P) != 0ull) return;
   const int w = blockIdx.x, sp = blockIdx.y;
   const int n = sp == 0 ? c.n_up : c.n_dn;
   const int NP = c.NP;
@@ -649,11 +666,16 @@ __global__ __launch_bounds__(NT_AUX) void k_inverse(DevCtx c) {
 // Local energy of each walker from the cached orbital rows and inverses:
 //   E_L = -1/2 sum_i [lap_i J + |grad_i J|^2 + 2 grad_i J . g_i + l_i] + V,
 //   g_i = sum_j grad phi_j(r_i) A^{-1}_{j i},  l_i = sum_j lap phi_j(r_i) A^{-1}_{j i}.
-// One workgroup per walker.  mode: -1 = measure only, 0 = VMC step, 1 = DMC
-// step (log w += -tau ((E_old + E_new)/2 - E_T)).
+// One workgroup per walker.  measure_only != 0: E_L only; otherwise the end
+// of a step in the run state's mode: DMC updates the log-weight
+// (log w += -tau ((E_old + E_new)/2 - E_T)); e_log (may be null) receives
+// E_L in row s_in_run of a table with row stride elog_stride.
 template <typename T>
-__global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int mode, double e_trial,
-                                                           double *e_log_row) {
+__global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int measure_only, double *e_log,
+                                                           long long elog_stride) {
+  const int mode = measure_only ? -1 : c.run->mode;
+  const double e_trial = c.run->e_trial;
+  double *e_log_row = (e_log && !measure_only) ? e_log + c.run->s_in_run * elog_stride : nullptr;
   __shared__ double part[NT_AUX / 64][3];
   const int w = blockIdx.x;
   const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
@@ -877,9 +899,12 @@ __device__ void block_accept(const DevCtx &c, int w, int t, int i, int sp, int m
 // of k consecutive electrons of one spin, the block's inverse columns are
 // updated by Sherman-Morrison, and at the block end the full inverse takes
 // all k changes at once (rank-k Woodbury form, see flush_block).
+// The step index and mode come from the device run state; acc_log (may be
+// null) receives the accept decisions at
+// acc_log[s_in_run * acc_step_stride + w * acc_w_stride + i].
 template <typename T, int NOB>
-__global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, int mode, uint32_t step,
-                                                    uint8_t *acc_log /* [W][ne] or null */) {
+__global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, uint8_t *acc_log,
+                                                    long long acc_step_stride, int acc_w_stride) {
   constexpr int NP = NOB * 16;
   constexpr int FM = 4 * stage_ksteps(NOB);
   extern __shared__ __align__(16) char smem_basis[];
@@ -900,6 +925,9 @@ __global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, int mode, uint32_t 
   T *Gb = (T *)c.Gb + blk_off(c, w);
   T *Dl = (T *)c.Dl + blk_off(c, w);
   const double tau = c.tau, sqt = sqrt(c.tau);
+  const uint32_t step = (uint32_t)c.run->step;
+  const int mode = c.run->mode;
+  if (acc_log) acc_log += c.run->s_in_run * acc_step_stride + (long long)w * acc_w_stride;
   PHASE_BEGIN();
   for (int i = 0; i < c.ne; ++i) {
     const int sp = i < c.n_up ? 0 : 1;
@@ -980,7 +1008,7 @@ __global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, int mode, uint32_t 
     PHASE_MARK(3);
     // ---- P4: delayed update of the block (lanes of this walker only)
     block_accept<T, NOB>(c, w, t, i, sp, m, kb, accepted, rho, vw, colm[ws], aold[ws], crow[ws], rn);
-    if (acc_log && t == 0 && w < c.W) acc_log[(size_t)w * c.ne + i] = (uint8_t)accepted;
+    if (acc_log && t == 0 && w < c.W) acc_log[i] = (uint8_t)accepted;
     PHASE_MARK(4);
     // ---- P5: block end -> rank-k flush of the full inverse
     if (m == kb - 1) flush_block<T, NOB>(c, blockIdx.x * TW, sp, kb);

@@ -22,13 +22,15 @@ DMCX_OK, DMCX_E_INVALID, DMCX_E_NOMEM, DMCX_E_HIP, DMCX_E_SINGULAR, DMCX_E_NONFI
 DMCX_FP64, DMCX_MIXED = 0, 1
 DMCX_VMC, DMCX_DMC = 0, 1
 DMCX_HOST, DMCX_DEVICE = 0, 1
+DMCX_FLAG_GRAPH = 1
 
 EXPORTED = [
     "dmcx_create", "dmcx_destroy", "dmcx_set_walkers", "dmcx_get_walkers", "dmcx_set_step",
     "dmcx_get_step", "dmcx_set_ions", "dmcx_recompute", "dmcx_eval_orbitals", "dmcx_ratio_grad",
     "dmcx_accept", "dmcx_flush", "dmcx_run", "dmcx_measure", "dmcx_ion_grads", "dmcx_logpsi_vjp",
     "dmcx_potential_vjp", "dmcx_forces", "dmcx_potential", "dmcx_walker_flags", "dmcx_sync", "dmcx_last_run_timing",
-    "dmcx_selftest", "dmcx_philox", "dmcx_strerror", "dmcx_last_error",
+    "dmcx_selftest", "dmcx_philox", "dmcx_strerror", "dmcx_last_error", "dmcx_autotune",
+    "dmcx_autotune_report", "dmcx_get_delay_rank",
 ]
 
 
@@ -61,6 +63,15 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2504_07948_amd.build_ext.build()")
+    # PyTorch ships its own HIP runtime; when both live in one process, torch's
+    # must initialise the device before this library's does, or torch later
+    # finds no device.  Start it first when torch and a GPU are present.
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     sig = {
@@ -90,6 +101,9 @@ def load():
         "dmcx_philox": [P, P, I32, P],
         "dmcx_strerror": [I32],
         "dmcx_last_error": [P],
+        "dmcx_autotune": [P, I32, P],
+        "dmcx_autotune_report": [P, I32, I32, P, P, P],
+        "dmcx_get_delay_rank": [P, I32, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -219,6 +233,18 @@ def dmcx_philox(ctr, key, n, out):
     return load().dmcx_philox(ctr, key, n, out)
 
 
+def dmcx_autotune(ctx, steps, chosen_k):
+    return load().dmcx_autotune(ctx, steps, chosen_k)
+
+
+def dmcx_autotune_report(ctx, sys_index, max_n, ranks, ms, n_cand):
+    return load().dmcx_autotune_report(ctx, sys_index, max_n, ranks, ms, n_cand)
+
+
+def dmcx_get_delay_rank(ctx, sys_index, k):
+    return load().dmcx_get_delay_rank(ctx, sys_index, k)
+
+
 def dmcx_strerror(status):
     return load().dmcx_strerror(status).decode()
 
@@ -258,8 +284,8 @@ class SystemStruct:
 class Context:
     """Owns one dmcx context for one or more systems."""
 
-    def __init__(self, systems, walkers, precision=DMCX_FP64, delay_rank=0, recompute_period=64,
-                 tau=0.01, seed=1, stream=None):
+    def __init__(self, systems, walkers, precision=DMCX_FP64, delay_rank=32, recompute_period=64,
+                 tau=0.01, seed=1, stream=None, graph=False):
         if not isinstance(systems, (list, tuple)):
             systems = [systems]
             walkers = [walkers]
@@ -270,8 +296,12 @@ class Context:
         self.W = int(wps.sum())
         self.ne = max(s.n_up + s.n_dn for s in systems)
         self.n_atom = max(s.n_atom for s in systems)
+        self.n_sys = len(systems)
+        self.walkers = [int(x) for x in wps]
+        self.offsets = np.concatenate([[0], np.cumsum(wps)[:-1]]).astype(int).tolist()
         opt = dmcx_options(precision=precision, delay_rank=delay_rank,
-                           recompute_period=recompute_period, tau=tau, seed=seed, flags=0)
+                           recompute_period=recompute_period, tau=tau, seed=seed,
+                           flags=DMCX_FLAG_GRAPH if graph else 0)
         h = C.c_void_p()
         st = load().dmcx_create(arr, len(systems), _ptr(wps), C.byref(opt), stream, C.byref(h))
         if st != DMCX_OK:
@@ -366,20 +396,24 @@ class Context:
         self.check(dmcx_ion_grads(self.h, _ptr(dl), _ptr(dv), DMCX_HOST))
         return dl, dv
 
+    def _per_system(self):
+        # [n_atom][3] for one system, [n_sys][n_atom_max][3] for a group
+        return np.zeros((self.n_atom, 3) if self.n_sys == 1 else (self.n_sys, self.n_atom, 3))
+
     def logpsi_vjp(self, gbar):
-        out = np.zeros((self.n_atom, 3))
+        out = self._per_system()
         self.check(dmcx_logpsi_vjp(self.h, _ptr(np.ascontiguousarray(gbar, dtype=np.float64)),
                                    _ptr(out), DMCX_HOST))
         return out
 
     def potential_vjp(self, gbar):
-        out = np.zeros((self.n_atom, 3))
+        out = self._per_system()
         self.check(dmcx_potential_vjp(self.h, _ptr(np.ascontiguousarray(gbar, dtype=np.float64)),
                                       _ptr(out), DMCX_HOST))
         return out
 
     def forces(self):
-        F = np.zeros((self.n_atom, 3))
+        F = self._per_system()
         self.check(dmcx_forces(self.h, _ptr(F), DMCX_HOST))
         return F
 
@@ -390,6 +424,23 @@ class Context:
 
     def sync(self):
         self.check(dmcx_sync(self.h))
+
+    def autotune(self, steps=2):
+        k = np.zeros(self.n_sys, dtype=np.int32)
+        self.check(dmcx_autotune(self.h, steps, _ptr(k)))
+        return k
+
+    def autotune_report(self, sys_index=0):
+        r = np.zeros(16, dtype=np.int32)
+        t = np.zeros(16, dtype=np.float32)
+        n = C.c_int32()
+        self.check(dmcx_autotune_report(self.h, sys_index, 16, _ptr(r), _ptr(t), C.byref(n)))
+        return r[:n.value].copy(), t[:n.value].copy()
+
+    def delay_rank(self, sys_index=0):
+        k = C.c_int32()
+        self.check(dmcx_get_delay_rank(self.h, sys_index, C.byref(k)))
+        return k.value
 
     def last_run_timing(self):
         a = C.c_double()
