@@ -340,8 +340,12 @@ static double ws_local_energy(const orc_system *s, const wstate *w, const double
   return -0.5 * kin + orc_potential(s, R);
 }
 
+int orc_msd_evaluate(const orc_system *s, const double *R, double *log_psi, int32_t *sign,
+                     double *e_local, double *drift);
+
 int orc_evaluate(const orc_system *s, const double *R, double *log_psi, int32_t *sign,
                  double *e_local, double *drift) {
+  if (s->n_det > 1) return orc_msd_evaluate(s, R, log_psi, sign, e_local, drift);
   wstate w;
   int rc = ws_init(s, &w, R);
   double J = 0.0;
@@ -415,10 +419,18 @@ void orc_move_draws(uint64_t seed, int64_t step, int32_t walker, int32_t elec, d
 }
 
 /* ---------------------------------------------------------------- DMC --- */
+static int msd_walker_run(const orc_system *s, double *R, double *log_w, double *e_local,
+                          int64_t step0, int32_t n_steps, int32_t mode, double tau, uint64_t seed,
+                          double e_trial, int32_t walker_index, uint8_t *acc_row, size_t acc_stride,
+                          double *e_row, size_t e_stride);
+
 static int walker_run(const orc_system *s, int wi, double *R, double *log_w, double *e_local,
                       int64_t step0, int32_t n_steps, int32_t mode, double tau, uint64_t seed,
                       double e_trial, int32_t walker_index, uint8_t *acc_row, size_t acc_stride,
                       double *e_row, size_t e_stride) {
+  if (s->n_det > 1)
+    return msd_walker_run(s, R, log_w, e_local, step0, n_steps, mode, tau, seed, e_trial,
+                          walker_index, acc_row, acc_stride, e_row, e_stride);
   wstate w;
   int rc = ws_init(s, &w, R);
   const int ne = w.ne, nmax = w.nmax;
@@ -638,4 +650,277 @@ int orc_msd_ratio_direct(const orc_system *s, const double *R, double *psi_over_
   free(cols);
   *psi_over_psi0 = acc;
   return 0;
+}
+
+/* ----------------------------------------- multideterminant value, E_L --- */
+/* Psi = exp(J) Phi, Phi = sum_d c_d D_d^up D_d^dn (Eq. 2 with M > 1).  Every
+ * determinant is built from its own columns and gets its own LU inverse; its
+ * per-electron log-derivatives follow from Eq. 3 with that inverse:
+ *   grad_i D_d / D_d = sum_j grad phi_{c_j}(r_i) (A_d^{-1})_{j i}, same for lap.
+ * With R_d^s = D_d^s / D_0^s and S = sum_d c_d R_d^up R_d^dn:
+ *   grad_i Phi / Phi = sum_d c_d R_d^up R_d^dn grad_i D_d / D_d / S,
+ *   lap_i Phi / Phi  = sum_d c_d R_d^up R_d^dn lap_i D_d / D_d / S,
+ *   E_L = -1/2 sum_i [lap_i J + |grad_i J|^2 + 2 grad_i J . grad_i Phi/Phi
+ *                     + lap_i Phi/Phi] + V. */
+
+/* highest MO index the expansion refers to, plus one */
+static int msd_n_mo(const orc_system *s) {
+  int nmo = s->n_up > s->n_dn ? s->n_up : s->n_dn;
+  for (int d = 0; d < s->n_det; ++d)
+    for (int k = 0; k < 4; ++k) {
+      const int p = s->det_exc[10 * d + (k < 2 ? 4 + k : 6 + k)];
+      if (p + 1 > nmo) nmo = p + 1;
+    }
+  return nmo;
+}
+
+/* one spin of every determinant at the orbital table orb[ne][5][nmo] */
+typedef struct {
+  int n;            /* electrons of this spin */
+  double ld0;       /* log|D_0| */
+  int sg0;          /* sign D_0 */
+  double *ratio;    /* [n_det] D_d / D_0 */
+  double *g;        /* [n_det][n][3] grad_i D_d / D_d */
+  double *l;        /* [n_det][n] lap_i D_d / D_d */
+} msd_spin;
+
+static void msd_spin_alloc(const orc_system *s, msd_spin *m, int sp) {
+  m->n = sp == 0 ? s->n_up : s->n_dn;
+  m->ratio = (double *)calloc((size_t)s->n_det + 1, sizeof(double));
+  m->g = (double *)calloc((size_t)s->n_det * m->n * 3 + 1, sizeof(double));
+  m->l = (double *)calloc((size_t)s->n_det * m->n + 1, sizeof(double));
+}
+
+static void msd_spin_free(msd_spin *m) {
+  free(m->ratio);
+  free(m->g);
+  free(m->l);
+}
+
+static void msd_spin_copy(const orc_system *s, msd_spin *dst, const msd_spin *src) {
+  dst->ld0 = src->ld0;
+  dst->sg0 = src->sg0;
+  memcpy(dst->ratio, src->ratio, sizeof(double) * s->n_det);
+  memcpy(dst->g, src->g, sizeof(double) * s->n_det * src->n * 3);
+  memcpy(dst->l, src->l, sizeof(double) * s->n_det * src->n);
+}
+
+static int msd_spin_eval(const orc_system *s, const double *orb, int nmo, int sp, msd_spin *m) {
+  const int n = m->n, e0 = sp == 0 ? 0 : s->n_up;
+  int rc = 0;
+  if (n == 0) {
+    m->ld0 = 0.0;
+    m->sg0 = 1;
+    for (int d = 0; d < s->n_det; ++d) m->ratio[d] = 1.0;
+    return 0;
+  }
+  double *A = (double *)malloc(sizeof(double) * (size_t)n * n);
+  double *G = (double *)malloc(sizeof(double) * (size_t)n * n);
+  int *cols = (int *)malloc(sizeof(int) * (size_t)n);
+  for (int d = 0; d < s->n_det; ++d) {
+    const int32_t *e = s->det_exc + 10 * d;
+    const int nx = e[sp];
+    if (d > 0 && nx == 0) {  /* same columns as the reference */
+      m->ratio[d] = 1.0;
+      memcpy(m->g + (size_t)d * n * 3, m->g, sizeof(double) * n * 3);
+      memcpy(m->l + (size_t)d * n, m->l, sizeof(double) * n);
+      continue;
+    }
+    for (int j = 0; j < n; ++j) cols[j] = j;
+    const int *h = e + (sp == 0 ? 2 : 6), *p = e + (sp == 0 ? 4 : 8);
+    for (int k = 0; k < nx; ++k) cols[h[k]] = p[k];
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = orb[((size_t)(e0 + i) * 5) * nmo + cols[j]];
+    double ld;
+    int32_t sg;
+    const int sing = orc_lu_slogdet_inv(n, A, &ld, &sg, G);
+    if (d == 0) {
+      rc |= sing;
+      m->ld0 = ld;
+      m->sg0 = sg;
+    }
+    if (sing) {  /* a vanishing excited determinant drops out of the sum */
+      m->ratio[d] = 0.0;
+      continue;
+    }
+    m->ratio[d] = d == 0 ? 1.0 : (double)(sg * m->sg0) * exp(ld - m->ld0);
+    for (int i = 0; i < n; ++i) {
+      const double *row = orb + (size_t)(e0 + i) * 5 * nmo;
+      double acc[4] = {0, 0, 0, 0};
+      for (int j = 0; j < n; ++j) {
+        const double gji = G[(size_t)j * n + i];
+        for (int c = 0; c < 4; ++c) acc[c] += row[(size_t)(c + 1) * nmo + cols[j]] * gji;
+      }
+      for (int x = 0; x < 3; ++x) m->g[((size_t)d * n + i) * 3 + x] = acc[x];
+      m->l[(size_t)d * n + i] = acc[3];
+    }
+  }
+  free(A);
+  free(G);
+  free(cols);
+  return rc;
+}
+
+/* log|Phi|, sign(Phi), and (if dphi/lphi) grad_i Phi / Phi, lap_i Phi / Phi */
+static void msd_combine(const orc_system *s, const msd_spin m[2], double *logabs, int *sign,
+                        double *dphi, double *lphi) {
+  double S = 0.0;
+  for (int d = 0; d < s->n_det; ++d) S += s->ci_coef[d] * m[0].ratio[d] * m[1].ratio[d];
+  *logabs = m[0].ld0 + m[1].ld0 + log(fabs(S));
+  *sign = m[0].sg0 * m[1].sg0 * (S > 0.0 ? 1 : (S < 0.0 ? -1 : 0));
+  if (!dphi && !lphi) return;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = m[sp].n, e0 = sp == 0 ? 0 : s->n_up;
+    for (int i = 0; i < n; ++i) {
+      double g[3] = {0, 0, 0}, l = 0.0;
+      for (int d = 0; d < s->n_det; ++d) {
+        const double w = s->ci_coef[d] * m[0].ratio[d] * m[1].ratio[d];
+        for (int x = 0; x < 3; ++x) g[x] += w * m[sp].g[((size_t)d * n + i) * 3 + x];
+        l += w * m[sp].l[(size_t)d * n + i];
+      }
+      if (dphi)
+        for (int x = 0; x < 3; ++x) dphi[3 * (e0 + i) + x] = g[x] / S;
+      if (lphi) lphi[e0 + i] = l / S;
+    }
+  }
+}
+
+static int msd_orbital_table(const orc_system *s, const double *R, int nmo, double *orb) {
+  const int ne = s->n_up + s->n_dn;
+  int rc = 0;
+  for (int i = 0; i < ne; ++i) rc |= orc_orbitals_vgl(s, R + 3 * i, nmo, orb + (size_t)i * 5 * nmo);
+  return rc;
+}
+
+static double msd_local_energy(const orc_system *s, const double *R, const msd_spin m[2],
+                               double *J, double *logabs, int *sign, double *drift) {
+  const int ne = s->n_up + s->n_dn;
+  double *dphi = (double *)malloc(sizeof(double) * 3 * ne);
+  double *lphi = (double *)malloc(sizeof(double) * ne);
+  double *gj = (double *)malloc(sizeof(double) * 3 * ne);
+  double *lj = (double *)malloc(sizeof(double) * ne);
+  msd_combine(s, m, logabs, sign, dphi, lphi);
+  orc_jastrow(s, R, J, gj, lj);
+  double kin = 0.0;
+  for (int i = 0; i < ne; ++i) {
+    const double *q = gj + 3 * i, *g = dphi + 3 * i;
+    kin += lj[i] + q[0] * q[0] + q[1] * q[1] + q[2] * q[2] +
+           2.0 * (q[0] * g[0] + q[1] * g[1] + q[2] * g[2]) + lphi[i];
+    if (drift)
+      for (int x = 0; x < 3; ++x) drift[3 * i + x] = q[x] + g[x];
+  }
+  free(dphi);
+  free(lphi);
+  free(gj);
+  free(lj);
+  return -0.5 * kin + orc_potential(s, R);
+}
+
+int orc_msd_evaluate(const orc_system *s, const double *R, double *log_psi, int32_t *sign,
+                     double *e_local, double *drift) {
+  const int ne = s->n_up + s->n_dn, nmo = msd_n_mo(s);
+  double *orb = (double *)malloc(sizeof(double) * (size_t)ne * 5 * nmo);
+  int rc = msd_orbital_table(s, R, nmo, orb);
+  msd_spin m[2];
+  for (int sp = 0; sp < 2; ++sp) {
+    msd_spin_alloc(s, &m[sp], sp);
+    rc |= msd_spin_eval(s, orb, nmo, sp, &m[sp]);
+  }
+  double J, la;
+  int sg;
+  const double el = msd_local_energy(s, R, m, &J, &la, &sg, drift);
+  if (log_psi) *log_psi = J + la;
+  if (sign) *sign = sg;
+  if (e_local) *e_local = el;
+  for (int sp = 0; sp < 2; ++sp) msd_spin_free(&m[sp]);
+  free(orb);
+  return rc;
+}
+
+/* The DMC step of walker_run with the multideterminant Psi: every proposal
+ * re-evaluates all determinants of the mover's spin at R' from scratch, the
+ * ratio is Phi(R')/Phi(R) exp(J(R') - J(R)), and the drift at R' comes from
+ * the same evaluation. */
+static int msd_walker_run(const orc_system *s, double *R, double *log_w, double *e_local,
+                          int64_t step0, int32_t n_steps, int32_t mode, double tau, uint64_t seed,
+                          double e_trial, int32_t walker_index, uint8_t *acc_row, size_t acc_stride,
+                          double *e_row, size_t e_stride) {
+  const int ne = s->n_up + s->n_dn, nmo = msd_n_mo(s);
+  double *orb = (double *)malloc(sizeof(double) * (size_t)ne * 5 * nmo);
+  double *orb_t = (double *)malloc(sizeof(double) * (size_t)ne * 5 * nmo);
+  double *dphi = (double *)malloc(sizeof(double) * 3 * ne);
+  double *dphi_t = (double *)malloc(sizeof(double) * 3 * ne);
+  int rc = msd_orbital_table(s, R, nmo, orb);
+  msd_spin m[2], t[2];
+  for (int sp = 0; sp < 2; ++sp) {
+    msd_spin_alloc(s, &m[sp], sp);
+    msd_spin_alloc(s, &t[sp], sp);
+    rc |= msd_spin_eval(s, orb, nmo, sp, &m[sp]);
+  }
+  double J, la;
+  int sg;
+  double e_old = msd_local_energy(s, R, m, &J, &la, &sg, NULL);
+  const double sqt = sqrt(tau);
+  for (int st = 0; st < n_steps; ++st) {
+    const int64_t step = step0 + st;
+    for (int i = 0; i < ne; ++i) {
+      const int sp = spin_of(s, i);
+      double *ri = R + 3 * i;
+      double logabs, uo, gjo[3];
+      int sgn;
+      msd_combine(s, m, &logabs, &sgn, dphi, NULL);
+      jastrow_one(s, R, i, ri, &uo, gjo);
+      const double v[3] = {gjo[0] + dphi[3 * i], gjo[1] + dphi[3 * i + 1], gjo[2] + dphi[3 * i + 2]};
+      double chi[3], uacc;
+      orc_move_draws(seed, step, walker_index, i, chi, &uacc);
+      double rn[3];
+      for (int x = 0; x < 3; ++x) rn[x] = ri[x] + tau * v[x] + sqt * chi[x];
+      /* trial state: electron i at r', the other spin's determinants unchanged */
+      memcpy(orb_t, orb, sizeof(double) * (size_t)ne * 5 * nmo);
+      rc |= orc_orbitals_vgl(s, rn, nmo, orb_t + (size_t)i * 5 * nmo);
+      msd_spin_copy(s, &t[1 - sp], &m[1 - sp]);
+      msd_spin_eval(s, orb_t, nmo, sp, &t[sp]);
+      double logabs_t;
+      int sgn_t;
+      msd_combine(s, t, &logabs_t, &sgn_t, dphi_t, NULL);
+      const double rho_sign = (double)(sgn_t * sgn);
+      int accepted = 0;
+      if (!(mode == 1 && !(rho_sign > 0.0)) && sgn_t != 0) {
+        double un, gjn[3];
+        jastrow_one(s, R, i, rn, &un, gjn);
+        double vn[3];
+        for (int x = 0; x < 3; ++x) vn[x] = gjn[x] + dphi_t[3 * i + x];
+        double fwd = 0.0, bwd = 0.0;
+        for (int x = 0; x < 3; ++x) {
+          const double a = rn[x] - ri[x] - tau * v[x];
+          const double b = ri[x] - rn[x] - tau * vn[x];
+          fwd += a * a;
+          bwd += b * b;
+        }
+        const double lnq = 2.0 * ((logabs_t - logabs) + (un - uo)) + (fwd - bwd) / (2.0 * tau);
+        const double p = lnq >= 0.0 ? 1.0 : exp(lnq);
+        accepted = uacc < p;
+      }
+      if (accepted) {
+        for (int x = 0; x < 3; ++x) ri[x] = rn[x];
+        memcpy(orb, orb_t, sizeof(double) * (size_t)ne * 5 * nmo);
+        msd_spin_copy(s, &m[sp], &t[sp]);
+      }
+      if (acc_row) acc_row[(size_t)st * acc_stride + i] = (uint8_t)accepted;
+    }
+    const double e_new = msd_local_energy(s, R, m, &J, &la, &sg, NULL);
+    if (mode == 1) *log_w += -tau * (0.5 * (e_old + e_new) - e_trial);
+    if (e_row) e_row[(size_t)st * e_stride] = e_new;
+    e_old = e_new;
+  }
+  *e_local = e_old;
+  for (int sp = 0; sp < 2; ++sp) {
+    msd_spin_free(&m[sp]);
+    msd_spin_free(&t[sp]);
+  }
+  free(orb);
+  free(orb_t);
+  free(dphi);
+  free(dphi_t);
+  return rc;
 }

@@ -103,6 +103,13 @@ int orc_evaluate_batch(const orc_system *s, int32_t W, const double *R, double *
  * of determinants), from one direct LU per excited determinant. */
 int orc_msd_ratio_direct(const orc_system *s, const double *R, double *psi_over_psi0);
 
+/* log|Psi|, sign, E_L and drift of the multideterminant trial function, every
+ * determinant with its own LU inverse.  orc_evaluate and orc_run take this
+ * path by themselves when n_det > 1 (each proposal then re-evaluates all
+ * determinants of the mover's spin from scratch). */
+int orc_msd_evaluate(const orc_system *s, const double *R, double *log_psi, int32_t *sign,
+                     double *e_local, double *drift);
+
 #ifdef __cplusplus
 }
 #endif
