@@ -11,8 +11,10 @@
 #include <vector>
 
 #include "dmcx.h"
-#include "forces.h"
+#include "forces_aux.h"
 #include "kernels.h"
+#include "launch.h"
+#include "msd.h"
 
 using namespace dmcx;
 
@@ -170,14 +172,35 @@ dmcx_status validate_system(dmcx_ctx *c, const dmcx_system &s) {
     return fail(c, DMCX_E_INVALID, "system: need electrons");
   if (std::max(s.n_up, s.n_dn) > 128)
     return fail(c, DMCX_E_UNSUPPORTED, "system: at most 128 electrons per spin");
-  if (s.n_det > 1) return fail(c, DMCX_E_UNSUPPORTED, "multideterminant expansion not built yet");
+  if (s.n_det > 1) {
+    if (!s.det_exc || !s.ci_coef) return fail(c, DMCX_E_INVALID, "system: n_det > 1 needs det_exc, ci_coef");
+    const int nsig[2] = {s.n_up, s.n_dn};
+    for (int d = 0; d < s.n_det; ++d) {
+      const int32_t *e = s.det_exc + 10 * d;
+      if (!std::isfinite(s.ci_coef[d])) return fail(c, DMCX_E_INVALID, "system: non-finite CI coefficient");
+      if (d == 0 && (e[0] != 0 || e[1] != 0))
+        return fail(c, DMCX_E_INVALID, "system: determinant 0 must be the reference");
+      for (int sp = 0; sp < 2; ++sp) {
+        const int n = e[sp];
+        const int32_t *h = e + (sp == 0 ? 2 : 6), *p = e + (sp == 0 ? 4 : 8);
+        if (n < 0 || n > 2) return fail(c, DMCX_E_INVALID, "system: at most two excitations per spin");
+        for (int k = 0; k < n; ++k) {
+          if (h[k] < 0 || h[k] >= nsig[sp] || p[k] < nsig[sp] || p[k] >= s.n_mo)
+            return fail(c, DMCX_E_INVALID, "system: excitation hole/particle out of range");
+        }
+        if (n == 2 && (h[0] == h[1] || p[0] == p[1]))
+          return fail(c, DMCX_E_INVALID, "system: repeated hole or particle");
+      }
+    }
+  }
   return DMCX_OK;
 }
 
 // Pack shells by (l, nprim) into groups of four (padding with zero-weight
 // shells), permute the LCAO rows to match, and split groups into stages of
 // one (l, nprim) type with at most 4 * stage_ksteps(NOB) functions.
-dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, int n_orb) {
+// colmo[j]: MO index packed into orbital column j (-1: zero column).
+dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, const std::vector<int> &colmo) {
   struct Sh { int l, np, atom, prim0, fn0; };
   std::vector<Sh> sh(s.n_shell);
   int prim = 0, fn = 0;
@@ -252,8 +275,9 @@ dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, int n_orb) {
   std::vector<float> Cp32((size_t)pfn * NP, 0.0f);
   for (int r = 0; r < pfn; ++r) {
     if (canon[r] < 0) continue;
-    for (int j = 0; j < n_orb; ++j) {
-      Cp[(size_t)r * NP + j] = s.mo_coef[(size_t)canon[r] * s.n_mo + j];
+    for (int j = 0; j < NP; ++j) {
+      if (colmo[j] < 0) continue;
+      Cp[(size_t)r * NP + j] = s.mo_coef[(size_t)canon[r] * s.n_mo + colmo[j]];
       Cp32[(size_t)r * NP + j] = (float)Cp[(size_t)r * NP + j];
     }
   }
@@ -289,54 +313,47 @@ dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, int n_orb) {
 // ------------------------------------------------------------ launches --
 size_t basis_lds(const dmcx_ctx *c) { return basis_lds_bytes(c->dc.B.n_group, c->dc.B.n_slot); }
 
-template <typename K>
-void allow_lds(K kernel, size_t dyn) {
-  (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)dyn);
-}
-
-template <typename T, int NOB>
-void launch_orbitals_all_t(dmcx_ctx *c) {
-  const int npts = c->Wpad * c->ne;
-  allow_lds(k_orbitals_all<T, NOB>, basis_lds(c));
-  k_orbitals_all<T, NOB><<<dim3((npts + TW - 1) / TW), dim3(NT_TILE), basis_lds(c), c->stream>>>(c->dc);
-}
-template <typename T, int NOB>
-void launch_orbitals_at_t(dmcx_ctx *c, const double *pos, int npts, T *dst) {
-  allow_lds(k_orbitals_at<T, NOB>, basis_lds(c));
-  k_orbitals_at<T, NOB><<<dim3((npts + TW - 1) / TW), dim3(NT_TILE), basis_lds(c), c->stream>>>(c->dc, pos, npts, dst);
-}
-template <typename T, int NOB>
-void launch_sweep_t(dmcx_ctx *c, uint8_t *acc, long long acc_ss, int acc_ws) {
-  allow_lds(k_sweep<T, NOB>, basis_lds(c));
-  k_sweep<T, NOB><<<dim3(c->Wpad / TW), dim3(NT_TILE), basis_lds(c), c->stream>>>(c->dc, acc, acc_ss,
-                                                                                  acc_ws);
-}
-
-#define DISPATCH_NOB_T(T, fn, ...)                    \
-  switch (c->NOB) {                                   \
-    case 1: fn<T, 1>(__VA_ARGS__); break;             \
-    case 2: fn<T, 2>(__VA_ARGS__); break;             \
-    case 3: fn<T, 3>(__VA_ARGS__); break;             \
-    case 4: fn<T, 4>(__VA_ARGS__); break;             \
-    case 5: fn<T, 5>(__VA_ARGS__); break;             \
-    case 6: fn<T, 6>(__VA_ARGS__); break;             \
-    case 7: fn<T, 7>(__VA_ARGS__); break;             \
-    default: fn<T, 8>(__VA_ARGS__); break;            \
-  }
+// The working precision picks the launcher instantiation.
+#define DMCX_BY_PRECISION(c, CALL)  \
+  do {                              \
+    if ((c)->mixed) {               \
+      using WT = float;             \
+      CALL;                         \
+    } else {                        \
+      using WT = double;            \
+      CALL;                         \
+    }                               \
+  } while (0)
 
 void launch_orbitals_all(dmcx_ctx *c) {
-  if (c->mixed) { DISPATCH_NOB_T(float, launch_orbitals_all_t, c); }
-  else { DISPATCH_NOB_T(double, launch_orbitals_all_t, c); }
+  DMCX_BY_PRECISION(c, NobLaunch<WT>::orbitals_all(c->NOB, c->dc, basis_lds(c), c->stream));
 }
-// orbitals at one point per walker -> d_orb (working precision)
+// orbitals at one point per walker -> dst (working precision)
 void launch_orbitals_at(dmcx_ctx *c, const double *pos, int npts, void *dst) {
-  if (c->mixed) { DISPATCH_NOB_T(float, launch_orbitals_at_t, c, pos, npts, (float *)dst); }
-  else { DISPATCH_NOB_T(double, launch_orbitals_at_t, c, pos, npts, (double *)dst); }
+  DMCX_BY_PRECISION(c, NobLaunch<WT>::orbitals_at(c->NOB, c->dc, pos, npts, (WT *)dst,
+                                                   basis_lds(c), c->stream));
 }
 void launch_sweep(dmcx_ctx *c, uint8_t *acc, long long acc_ss, int acc_ws) {
-  if (c->mixed) { DISPATCH_NOB_T(float, launch_sweep_t, c, acc, acc_ss, acc_ws); }
-  else { DISPATCH_NOB_T(double, launch_sweep_t, c, acc, acc_ss, acc_ws); }
+  if (c->dc.M.on)
+    DMCX_BY_PRECISION(c, MsdLaunch<WT>::sweep(c->NOB, c->dc, acc, acc_ss, acc_ws, basis_lds(c),
+                                              c->stream));
+  else
+    DMCX_BY_PRECISION(c, NobLaunch<WT>::sweep(c->NOB, c->dc, acc, acc_ss, acc_ws, basis_lds(c),
+                                              c->stream));
+}
+
+// Multideterminant: table T = A^{-1} M and every determinant ratio, from
+// the current inverses (after an FP64 recompute).
+dmcx_status launch_msd_rebuild(dmcx_ctx *c, int periodic = 0) {
+  if (!c->dc.M.on) return DMCX_OK;
+  if (c->mixed) {
+    hipLaunchKernelGGL(k_msd_table<float>, dim3(c->Wpad, 2), dim3(NT_AUX), 0, c->stream, c->dc, periodic);
+    hipLaunchKernelGGL(k_msd_dets<float>, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc, periodic);
+  } else {
+    hipLaunchKernelGGL(k_msd_table<double>, dim3(c->Wpad, 2), dim3(NT_AUX), 0, c->stream, c->dc, periodic);
+    hipLaunchKernelGGL(k_msd_dets<double>, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc, periodic);
+  }
+  return hip_check(c, hipGetLastError(), "multideterminant table launch");
 }
 
 // periodic != 0: the kernel itself skips steps that are not multiples of P
@@ -393,7 +410,7 @@ __global__ void k_measure_out(DevCtx c, double *e, double *lp, int8_t *sg) {
   if (w >= c.W) return;
   if (e) e[w] = c.eloc[w];
   if (lp) lp[w] = c.logpsi[w];
-  if (sg) sg[w] = (int8_t)(c.sgn[2 * w] * c.sgn[2 * w + 1]);
+  if (sg) sg[w] = (int8_t)(c.sgn[2 * w] * c.sgn[2 * w + 1] * (c.M.on && c.M.S[w] < 0.0 ? -1.0 : 1.0));
 }
 
 // [W][5][NP] working-precision orbital rows -> [W][5][ns] doubles
@@ -451,12 +468,6 @@ dmcx_status check_flags_host(dmcx_ctx *c) {
   return DMCX_OK;
 }
 
-template <typename T, int NOB>
-void launch_ion_grad_det_t(dmcx_ctx *c, int ntile, size_t lds) {
-  allow_lds(k_ion_grad_det<T, NOB>, lds);
-  k_ion_grad_det<T, NOB><<<dim3(c->Wpad * ntile), dim3(NT_FORCE), lds, c->stream>>>(c->dc, c->d_partial);
-}
-
 double nuclear_repulsion(const std::vector<double> &xyz, const std::vector<double> &Z) {
   double v = 0.0;
   const size_t n = Z.size();
@@ -469,34 +480,11 @@ double nuclear_repulsion(const std::vector<double> &xyz, const std::vector<doubl
   return v;
 }
 
-template <typename T, int NOB>
-void launch_block_init_t(dmcx_ctx *c) {
-  k_block_init<T, NOB><<<dim3(c->Wpad), dim3(256), 0, c->stream>>>(c->dc, c->blk_sp, c->blk_b0,
-                                                                     c->blk_kb);
-}
-template <typename T, int NOB>
-void launch_ratio_grad_t(dmcx_ctx *c, int iel, const double *r_new, double *ratio, double *grad) {
-  allow_lds(k_ratio_grad<T, NOB>, basis_lds(c));
-  k_ratio_grad<T, NOB><<<dim3(c->Wpad / TW), dim3(NT_TILE), basis_lds(c), c->stream>>>(
-      c->dc, iel, c->blk_m, r_new, ratio, grad, (T *)c->d_prop, c->d_prop_rho);
-}
-template <typename T, int NOB>
-void launch_accept_t(dmcx_ctx *c, int iel, const double *r_new) {
-  k_accept<T, NOB><<<dim3(c->Wpad), dim3(64), 0, c->stream>>>(
-      c->dc, iel, c->blk_sp, c->blk_m, c->blk_kb, c->d_acc8, (const T *)c->d_prop, c->d_prop_rho,
-      r_new);
-}
-template <typename T, int NOB>
-void launch_flush_t(dmcx_ctx *c, int kb) {
-  k_flush<T, NOB><<<dim3(c->Wpad / TW), dim3(NT_TILE), 0, c->stream>>>(c->dc, c->blk_sp, kb);
-}
-
 // Apply the pending moves of an open electron block (rank-k flush).
 dmcx_status flush_pending(dmcx_ctx *c) {
   if (!c->blk_active) return DMCX_OK;
   if (c->blk_m > 0) {
-    if (c->mixed) { DISPATCH_NOB_T(float, launch_flush_t, c, c->blk_m); }
-    else { DISPATCH_NOB_T(double, launch_flush_t, c, c->blk_m); }
+    DMCX_BY_PRECISION(c, NobLaunch<WT>::flush(c->NOB, c->dc, c->blk_sp, c->blk_m, c->stream));
     HIP_TRY(c, hipGetLastError());
   }
   c->blk_active = false;
@@ -517,15 +505,17 @@ dmcx_status refresh_after_moves(dmcx_ctx *c) {
 
 // Per-walker ion derivatives for the current configuration (cached).
 dmcx_status compute_ion_grads(dmcx_ctx *c) {
+  if (c->dc.M.on)
+    return fail(c, DMCX_E_UNSUPPORTED, "ion derivatives of a multideterminant expansion");
   dmcx_status st0 = refresh_after_moves(c);
   if (st0) return st0;
   if (c->grads_version == c->version) return DMCX_OK;
   const int ntile = (c->ne + FPTS - 1) / FPTS;
   const size_t lds = basis_lds(c);
   if (c->mixed) {
-    DISPATCH_NOB_T(float, launch_ion_grad_det_t, c, ntile, lds);
+    NobLaunch<float>::ion_grad_det(c->NOB, c->dc, c->d_partial, ntile, lds, c->stream);
   } else {
-    DISPATCH_NOB_T(double, launch_ion_grad_det_t, c, ntile, lds);
+    NobLaunch<double>::ion_grad_det(c->NOB, c->dc, c->d_partial, ntile, lds, c->stream);
   }
   HIP_TRY(c, hipGetLastError());
   hipLaunchKernelGGL(k_ion_grad_finalize, dim3(c->Wpad), dim3(64), 0, c->stream, c->dc,
@@ -576,6 +566,75 @@ const char *dmcx_last_error(const dmcx_ctx *c) { return c ? c->err.c_str() : "";
 
 namespace {
 
+// Multideterminant tables: per-determinant excitations in table
+// coordinates (hole = occupied column, virtual = table column), the lists of
+// determinants with / without an excitation of each spin, and the per-walker
+// table, ratios and sums.
+dmcx_status setup_msd(dmcx_ctx *c, const dmcx_system &s, const std::vector<int> &vmo,
+                      const std::vector<int> &vcol) {
+  DevMsd &M = c->dc.M;
+  M.on = 1;
+  M.n_det = s.n_det;
+  M.nv = (int)vmo.size();
+  M.ldt = std::max(4, (M.nv + 3) / 4 * 4);
+  auto slot = [&](int mo) { return (int)(std::lower_bound(vmo.begin(), vmo.end(), mo) - vmo.begin()); };
+  std::vector<int4> dexc(2 * (size_t)s.n_det), lst[2];
+  std::vector<double> lcoef[2], rcoef[2];
+  std::vector<int> rlst[2];
+  for (int d = 0; d < s.n_det; ++d) {
+    const int32_t *e = s.det_exc + 10 * d;
+    for (int sp = 0; sp < 2; ++sp) {
+      const int n = e[sp];
+      const int32_t *h = e + (sp == 0 ? 2 : 6), *p = e + (sp == 0 ? 4 : 8);
+      const int hh = n == 0 ? 0 : (h[0] | ((n == 2 ? h[1] : 0) << 16));
+      const int vv = n == 0 ? 0 : (slot(p[0]) | ((n == 2 ? slot(p[1]) : 0) << 16));
+      dexc[2 * d + sp] = make_int4(n, hh, vv, 0);
+      if (n > 0) {
+        lst[sp].push_back(make_int4(d, n, hh, vv));
+        lcoef[sp].push_back(s.ci_coef[d]);
+      } else {
+        rlst[sp].push_back(d);
+        rcoef[sp].push_back(s.ci_coef[d]);
+      }
+    }
+  }
+  dmcx_status st;
+  int *d_vcol;
+  double *d_coef;
+  int4 *d_dexc;
+  if ((st = upload(c, &d_vcol, vcol))) return st;
+  if ((st = upload(c, &d_coef, std::vector<double>(s.ci_coef, s.ci_coef + s.n_det)))) return st;
+  if ((st = upload(c, &d_dexc, dexc))) return st;
+  M.vcol = d_vcol;
+  M.coef = d_coef;
+  M.dexc = d_dexc;
+  M.max_lst = 1;
+  for (int sp = 0; sp < 2; ++sp) {
+    int4 *dl;
+    double *dc, *drc;
+    int *dr;
+    if ((st = upload(c, &dl, lst[sp]))) return st;
+    if ((st = upload(c, &dc, lcoef[sp]))) return st;
+    if ((st = upload(c, &dr, rlst[sp]))) return st;
+    if ((st = upload(c, &drc, rcoef[sp]))) return st;
+    M.n_lst[sp] = (int)lst[sp].size();
+    M.lst[sp] = dl;
+    M.lcoef[sp] = dc;
+    M.n_ref[sp] = (int)rlst[sp].size();
+    M.rlst[sp] = dr;
+    M.rcoef[sp] = drc;
+    M.max_lst = std::max(M.max_lst, M.n_lst[sp]);
+  }
+  const size_t Wp = c->Wpad;
+  char *pv;
+  if ((st = dalloc(c, &pv, c->es * Wp * 2 * c->NP * M.ldt))) return st;
+  M.Tt = pv;
+  if ((st = dalloc(c, &M.Rdet, Wp * 2 * s.n_det))) return st;
+  if ((st = dalloc(c, &M.S, Wp))) return st;
+  if ((st = dalloc(c, &M.Rnew, Wp * M.max_lst))) return st;
+  return DMCX_OK;
+}
+
 // One system's context (the unit every kernel works on).
 dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_options *opt,
                        hipStream_t stream, dmcx_ctx **out, std::string *err_out) {
@@ -604,8 +663,33 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
   c->n_atom = s.n_atom;
   c->n_basis = s.n_basis;
   const int n_orb = std::max(s.n_up, s.n_dn);
-  c->NOB = (n_orb + 15) / 16;
+  // Orbital columns: the occupied MOs 0..n_orb-1, then the virtual MOs a
+  // multideterminant expansion refers to (its particles).
+  std::vector<int> vmo;  // table column -> MO, sorted
+  if (s.n_det > 1) {
+    for (int d = 0; d < s.n_det; ++d)
+      for (int sp = 0; sp < 2; ++sp)
+        for (int k = 0; k < s.det_exc[10 * d + sp]; ++k)
+          vmo.push_back(s.det_exc[10 * d + (sp == 0 ? 4 : 8) + k]);
+    std::sort(vmo.begin(), vmo.end());
+    vmo.erase(std::unique(vmo.begin(), vmo.end()), vmo.end());
+  }
+  std::vector<int> vcol(vmo.size());
+  int n_extra = 0;
+  for (size_t v = 0; v < vmo.size(); ++v) vcol[v] = vmo[v] < n_orb ? vmo[v] : n_orb + n_extra++;
+  c->NOB = (n_orb + n_extra + 15) / 16;
   c->NP = 16 * c->NOB;
+  if (c->NOB > NOB_MAX) {
+    c->err = "at most 160 orbital columns (occupied + virtual) per system";
+    return bail(DMCX_E_UNSUPPORTED);
+  }
+  if ((int)vmo.size() > MSD_NV_MAX) {
+    c->err = "at most 144 distinct virtual orbitals in a multideterminant expansion";
+    return bail(DMCX_E_UNSUPPORTED);
+  }
+  std::vector<int> colmo(c->NP, -1);
+  for (int j = 0; j < n_orb; ++j) colmo[j] = j;
+  for (size_t v = 0; v < vmo.size(); ++v) colmo[vcol[v]] = vmo[v];
   if (opt->delay_rank == 0) {
     // candidates are timed at the first run; start from min(32, n_sigma)
     c->K = std::min(32, n_orb);
@@ -616,7 +700,7 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
   }
   c->P = opt->recompute_period;
   c->ion_xyz.assign(s.ion_xyz, s.ion_xyz + 3 * s.n_atom);
-  if ((st = pack_basis(c, s, n_orb))) return bail(st);
+  if ((st = pack_basis(c, s, colmo))) return bail(st);
   DevCtx &d = c->dc;
   d.NP = c->NP;
   d.ne = c->ne;
@@ -701,6 +785,20 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
   if ((st = dalloc(c, &c->d_pos, Wp * 3))) return bail(st);
   if ((st = dalloc(c, &c->d_orb, Wp * 5 * c->NP))) return bail(st);
   if ((st = dalloc(c, &c->d_orb_out, Wp * 5 * c->NP))) return bail(st);
+  if (s.n_det > 1 && (st = setup_msd(c, s, vmo, vcol))) return bail(st);
+  {
+    // the sweep's LDS (static arrays + staged basis tables) must fit a CU
+    size_t stat = 0;
+    if (c->dc.M.on)
+      DMCX_BY_PRECISION(c, stat = MsdLaunch<WT>::sweep_lds(c->NOB));
+    else
+      DMCX_BY_PRECISION(c, stat = NobLaunch<WT>::sweep_lds(c->NOB));
+    if (stat + basis_lds(c) > 160 * 1024) {
+      c->err = "orbital tile and basis tables exceed the 160 KB of LDS (use the mixed precision "
+               "form or a smaller basis)";
+      return bail(DMCX_E_UNSUPPORTED);
+    }
+  }
   if (hipMemsetAsync(d.flags, 0, Wp * sizeof(unsigned), c->stream) != hipSuccess ||
       hipMemsetAsync(d.logw, 0, Wp * sizeof(double), c->stream) != hipSuccess ||
       hipMemsetAsync(c->d_run, 0, sizeof(RunState), c->stream) != hipSuccess ||
@@ -803,6 +901,7 @@ dmcx_status rebuild_state(dmcx_ctx *c) {
   HIP_TRY(c, hipGetLastError());
   dmcx_status st;
   if ((st = launch_inverse(c))) return st;
+  if ((st = launch_msd_rebuild(c))) return st;
   return launch_local_energy(c, 1);
 }
 
@@ -842,8 +941,10 @@ dmcx_status enqueue_step(dmcx_ctx *c, bool graph, uint8_t *acc, long long acc_ss
   dmcx_status st;
   if (graph) {
     if ((st = launch_inverse(c, 1))) return st;
+    if ((st = launch_msd_rebuild(c, 1))) return st;
   } else if (c->step % c->P == 0) {
     if ((st = launch_inverse(c, 0))) return st;
+    if ((st = launch_msd_rebuild(c, 0))) return st;
   }
   if (e0) HIP_TRY(c, hipEventRecord(e0, c->stream));
   launch_sweep(c, acc, acc_ss, acc_ws);
@@ -1195,6 +1296,8 @@ dmcx_status dmcx_recompute(dmcx_ctx *c) {
   dmcx_status st = flush_pending(c);
   if (st) return st;
   st = launch_inverse(c);
+  if (!st) st = launch_msd_rebuild(c);
+  if (!st && c->dc.M.on) st = launch_local_energy(c, 1);  // S and log|Psi| follow the new table
   if (st) return st;
   return check_flags_host(c);
 }
@@ -1227,6 +1330,8 @@ dmcx_status dmcx_ratio_grad(dmcx_ctx *c, int32_t iel, const double *r_new, doubl
                             double *grad, dmcx_mem mem) {
   if (!c || !r_new || !ratio || !grad) return DMCX_E_INVALID;
   if (c->is_group()) return group_unsupported(c, "dmcx_ratio_grad");
+  if (c->dc.M.on)
+    return fail(c, DMCX_E_UNSUPPORTED, "move-by-move calls with a multideterminant expansion");
   if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
   if (iel < 0 || iel >= c->ne) return fail(c, DMCX_E_INVALID, "electron index out of range");
   const int sp = iel < c->n_up ? 0 : 1, ii = iel - sp * c->n_up;
@@ -1241,8 +1346,8 @@ dmcx_status dmcx_ratio_grad(dmcx_ctx *c, int32_t iel, const double *r_new, doubl
     c->blk_kb = std::min(c->K, nsig - ii);
     c->blk_m = 0;
     c->blk_active = true;
-    if (c->mixed) { DISPATCH_NOB_T(float, launch_block_init_t, c); }
-    else { DISPATCH_NOB_T(double, launch_block_init_t, c); }
+    DMCX_BY_PRECISION(c, NobLaunch<WT>::block_init(c->NOB, c->dc, c->blk_sp, c->blk_b0, c->blk_kb,
+                                                   c->stream));
     HIP_TRY(c, hipGetLastError());
   }
   const double *rn = r_new;
@@ -1252,8 +1357,9 @@ dmcx_status dmcx_ratio_grad(dmcx_ctx *c, int32_t iel, const double *r_new, doubl
   }
   double *dr = mem == DMCX_DEVICE ? ratio : c->d_rg;
   double *dg = mem == DMCX_DEVICE ? grad : c->d_rg + c->W;
-  if (c->mixed) { DISPATCH_NOB_T(float, launch_ratio_grad_t, c, iel, rn, dr, dg); }
-  else { DISPATCH_NOB_T(double, launch_ratio_grad_t, c, iel, rn, dr, dg); }
+  DMCX_BY_PRECISION(c, NobLaunch<WT>::ratio_grad(c->NOB, c->dc, iel, c->blk_m, rn, dr, dg,
+                                                 (WT *)c->d_prop, c->d_prop_rho, basis_lds(c),
+                                                 c->stream));
   HIP_TRY(c, hipGetLastError());
   if (rn != c->d_rnew)  // keep the proposed positions for dmcx_accept
     HIP_TRY(c, hipMemcpyAsync(c->d_rnew, rn, (size_t)c->W * 3 * sizeof(double),
@@ -1273,8 +1379,9 @@ dmcx_status dmcx_accept(dmcx_ctx *c, int32_t iel, const uint8_t *accept, dmcx_me
     return fail(c, DMCX_E_STATE, "dmcx_accept needs the preceding dmcx_ratio_grad of this electron");
   dmcx_status st;
   if ((st = copy_in(c, c->d_acc8, accept, (size_t)c->W, mem))) return st;
-  if (c->mixed) { DISPATCH_NOB_T(float, launch_accept_t, c, iel, c->d_rnew); }
-  else { DISPATCH_NOB_T(double, launch_accept_t, c, iel, c->d_rnew); }
+  DMCX_BY_PRECISION(c, NobLaunch<WT>::accept(c->NOB, c->dc, iel, c->blk_sp, c->blk_m, c->blk_kb,
+                                             c->d_acc8, (const WT *)c->d_prop, c->d_prop_rho,
+                                             c->d_rnew, c->stream));
   HIP_TRY(c, hipGetLastError());
   c->prop_iel = -1;
   c->blk_m++;
@@ -1642,13 +1749,5 @@ dmcx_status dmcx_selftest(void *hip_stream) {
   return DMCX_OK;
 }
 
-#ifdef DMCX_PHASE_TIMING
-// Profiling builds only: read and clear the per-phase cycle totals.
-void dmcx_debug_phase_cycles(unsigned long long out[16]) {
-  (void)hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase_cycles), 16 * sizeof(unsigned long long));
-  unsigned long long z[16] = {0};
-  (void)hipMemcpyToSymbol(HIP_SYMBOL(g_phase_cycles), z, sizeof(z));
-}
-#endif
 
 }  // extern "C"

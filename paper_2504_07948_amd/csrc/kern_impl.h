@@ -1,0 +1,114 @@
+// Definitions of the NobLaunch members (see launch.h); included once per
+// working precision.
+#pragma once
+#include "forces.h"
+#include "launch.h"
+
+namespace dmcx {
+
+template <typename K>
+inline void allow_lds(K kernel, size_t dyn) {
+  (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)dyn);
+}
+
+#define DMCX_NOB_SWITCH(nob, CALL) \
+  switch (nob) {                   \
+    case 1: CALL(1); break;        \
+    case 2: CALL(2); break;        \
+    case 3: CALL(3); break;        \
+    case 4: CALL(4); break;        \
+    case 5: CALL(5); break;        \
+    case 6: CALL(6); break;        \
+    case 7: CALL(7); break;        \
+    case 8: CALL(8); break;        \
+    case 9: CALL(9); break;        \
+    default: CALL(10); break;      \
+  }
+
+template <typename T>
+void NobLaunch<T>::orbitals_all(int nob, const DevCtx &c, size_t lds, hipStream_t s) {
+  const int npts = c.Wpad * c.ne;
+#define DMCX_CALL(N)                                                                   \
+  allow_lds(k_orbitals_all<T, N>, lds);                                                \
+  k_orbitals_all<T, N><<<dim3((npts + TW - 1) / TW), dim3(NT_TILE), lds, s>>>(c)
+  DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+}
+
+template <typename T>
+void NobLaunch<T>::orbitals_at(int nob, const DevCtx &c, const double *pos, int npts, T *dst,
+                               size_t lds, hipStream_t s) {
+#define DMCX_CALL(N)                                                                   \
+  allow_lds(k_orbitals_at<T, N>, lds);                                                 \
+  k_orbitals_at<T, N><<<dim3((npts + TW - 1) / TW), dim3(NT_TILE), lds, s>>>(c, pos, npts, dst)
+  DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+}
+
+template <typename T>
+void NobLaunch<T>::sweep(int nob, const DevCtx &c, uint8_t *acc, long long acc_ss, int acc_ws,
+                         size_t lds, hipStream_t s) {
+#define DMCX_CALL(N)                                                                   \
+  allow_lds(k_sweep<T, N>, lds);                                                       \
+  k_sweep<T, N><<<dim3(c.Wpad / TW), dim3(NT_TILE), lds, s>>>(c, acc, acc_ss, acc_ws)
+  DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+}
+
+template <typename T>
+size_t NobLaunch<T>::sweep_lds(int nob) {
+  hipFuncAttributes a{};
+#define DMCX_CALL(N) (void)hipFuncGetAttributes(&a, (const void *)k_sweep<T, N>)
+  DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+  return a.sharedSizeBytes;
+}
+
+template <typename T>
+void NobLaunch<T>::ion_grad_det(int nob, const DevCtx &c, double *partial, int ntile, size_t lds,
+                                hipStream_t s) {
+#define DMCX_CALL(N)                                                                   \
+  allow_lds(k_ion_grad_det<T, N>, lds);                                                \
+  k_ion_grad_det<T, N><<<dim3(c.Wpad * ntile), dim3(NT_FORCE), lds, s>>>(c, partial)
+  DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+}
+
+template <typename T>
+void NobLaunch<T>::block_init(int nob, const DevCtx &c, int sp, int b0, int kb, hipStream_t s) {
+#define DMCX_CALL(N) k_block_init<T, N><<<dim3(c.Wpad), dim3(256), 0, s>>>(c, sp, b0, kb)
+  DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+}
+
+template <typename T>
+void NobLaunch<T>::ratio_grad(int nob, const DevCtx &c, int iel, int m, const double *r_new,
+                              double *ratio, double *grad, T *prop, double *prop_rho, size_t lds,
+                              hipStream_t s) {
+#define DMCX_CALL(N)                                                                   \
+  allow_lds(k_ratio_grad<T, N>, lds);                                                  \
+  k_ratio_grad<T, N><<<dim3(c.Wpad / TW), dim3(NT_TILE), lds, s>>>(c, iel, m, r_new, ratio, grad, \
+                                                                   prop, prop_rho)
+  DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+}
+
+template <typename T>
+void NobLaunch<T>::accept(int nob, const DevCtx &c, int iel, int sp, int m, int kb,
+                          const uint8_t *acc8, const T *prop, const double *prop_rho,
+                          const double *r_new, hipStream_t s) {
+#define DMCX_CALL(N)                                                                   \
+  k_accept<T, N><<<dim3(c.Wpad), dim3(64), 0, s>>>(c, iel, sp, m, kb, acc8, prop, prop_rho, r_new)
+  DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+}
+
+template <typename T>
+void NobLaunch<T>::flush(int nob, const DevCtx &c, int sp, int kb, hipStream_t s) {
+#define DMCX_CALL(N) k_flush<T, N><<<dim3(c.Wpad / TW), dim3(NT_TILE), 0, s>>>(c, sp, kb)
+  DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+}
+
+}  // namespace dmcx

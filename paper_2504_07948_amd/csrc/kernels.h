@@ -26,7 +26,7 @@ namespace dmcx {
 // Optional per-phase cycle accounting of the sweep (off unless the library
 // is built with -DDMCX_PHASE_TIMING; used for profiling builds only).
 #ifdef DMCX_PHASE_TIMING
-__device__ unsigned long long g_phase_cycles[16];
+static __device__ unsigned long long g_phase_cycles[16];
 #define SUB_T(v) const unsigned long long v = __builtin_readcyclecounter()
 #define SUB_ADD(slot, a, b) \
   do { if (threadIdx.x == 0) atomicAdd(&g_phase_cycles[slot], (b) - (a)); } while (0)
@@ -54,10 +54,11 @@ __device__ unsigned long long g_phase_cycles[16];
 
 constexpr int TW = 8;        // walkers (or points) per workgroup tile
 constexpr int NCOL = 48;     // 5 VGL rows x 8 walkers = 40 MFMA columns, padded to 3 x 16
-constexpr int NT_TILE = 512; // tile kernels: 8 waves (4 MFMA waves + 4 basis waves)
+constexpr int NT_TILE = 512; // tile kernels: 8 waves
 constexpr int NW_TILE = NT_TILE / 64;
 constexpr int NT_AUX = 256;  // per-walker kernels (inverse, local energy)
-constexpr int KMAX = 64;     // largest delay rank
+constexpr int KMAX = 64;         // largest delay rank
+constexpr int MSD_NV_MAX = 144;  // virtual orbitals of a multideterminant expansion
 
 // K-steps (4 basis functions each) per LDS stage of the orbital tile; the
 // LCAO operands of a stage are held in registers, so wider orbital tiles use
@@ -134,6 +135,33 @@ struct RunState {
   int pad_;
 };
 
+// Multideterminant expansion (Eq. 2 with M > 1) by the table method.  With
+// A_ij = phi_j(r_i) over the occupied orbitals and M_iv = phi_v(r_i) over
+// the virtual orbitals the expansion refers to, T = A^{-1} M (orbital x
+// virtual) gives every excited-determinant ratio as a minor of T:
+// D_{h->v} / D_0 = T_hv and D_{h1 h2 -> v1 v2} / D_0 = T_h1v1 T_h2v2 - T_h1v2 T_h2v1
+// (holes replaced in place).  A move of electron i changes T by rank one.
+struct DevMsd {
+  int on;                 // 0: single determinant
+  int n_det;
+  int nv;                 // virtual orbitals referenced (table columns)
+  int ldt;                // row stride of the table
+  const int *vcol;        // [nv] column of virtual v in the orbital rows
+  const double *coef;     // [n_det] CI coefficients
+  const int4 *dexc;       // [n_det][2] per spin {n_exc, h0 | h1 << 16, v0 | v1 << 16, 0}
+  int n_lst[2];           // determinants with an excitation of spin s
+  const int4 *lst[2];     // {det, n_exc, h0 | h1 << 16, v0 | v1 << 16}
+  const double *lcoef[2]; // their coefficients
+  int n_ref[2];           // determinants without an excitation of spin s
+  const int *rlst[2];
+  const double *rcoef[2];
+  int max_lst;
+  void *Tt;               // [Wpad][2][NP][ldt] the table (working precision)
+  double *Rdet;           // [Wpad][2][n_det] D_d^s / D_0^s
+  double *S;              // [Wpad] sum_d c_d R_d^up R_d^dn
+  double *Rnew;           // [Wpad][max_lst] proposal scratch
+};
+
 struct DevCtx {
   DevBasis B;
   int NP;                // padded orbital count (multiple of 16)
@@ -165,6 +193,7 @@ struct DevCtx {
   double *logpsi;  // [Wpad]
   double *vpot;    // [Wpad] Coulomb potential V(R) of the current configuration
   unsigned *flags; // [Wpad] bit 0 non-finite, bit 1 singular
+  DevMsd M;        // multideterminant expansion (M.on == 0: none)
 };
 
 __device__ __forceinline__ size_t vglc_off(const DevCtx &c, int w, int e) {
@@ -677,6 +706,7 @@ __global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int measure_o
   const double e_trial = c.run->e_trial;
   double *e_log_row = (e_log && !measure_only) ? e_log + c.run->s_in_run * elog_stride : nullptr;
   __shared__ double part[NT_AUX / 64][3];
+  __shared__ double msx_le[NT_AUX / 64][4 * MSD_NV_MAX];  // MSD: w (3 rows) and y per wave
   const int w = blockIdx.x;
   const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
   const int NP = c.NP;
@@ -728,7 +758,71 @@ __global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int measure_o
     g0 = sum64(g0); g1 = sum64(g1); g2 = sum64(g2); l = sum64(l);
     jg0 = sum64(jg0); jg1 = sum64(jg1); jg2 = sum64(jg2); jl = sum64(jl);
     ju = sum64(ju); v = sum64(v);
-    kin += jl + jg0 * jg0 + jg1 * jg1 + jg2 * jg2 + 2.0 * (jg0 * g0 + jg1 * g1 + jg2 * g2) + l;
+    double msd_k = 0.0;
+    if (c.M.on) {
+      // grad_i T_hv = g_hi w_v and lap_i T_hv = g_hi y_v with
+      //   w = grad m_i - T^T grad a_i,  y = lap m_i - T^T lap a_i - 2 w . grad ln D_0,
+      // give grad_i S and lap_i S; per electron the kinetic sum gains
+      //   2 (grad J + grad ln D_0) . grad S / S + lap S / S.
+      const DevMsd &M = c.M;
+      const int nsig = sp == 0 ? c.n_up : c.n_dn;
+      const T *Tw = (const T *)M.Tt + ((size_t)w * 2 + sp) * NP * M.ldt;
+      const double *Ro = M.Rdet + ((size_t)w * 2 + (1 - sp)) * M.n_det;
+      double *sx = msx_le[wid];
+      for (int q = lane; q < M.nv; q += 64) {
+        const int cv = M.vcol[q];
+        double w0 = (double)row[NP + cv], w1 = (double)row[2 * NP + cv], w2 = (double)row[3 * NP + cv],
+               y = (double)row[4 * NP + cv];
+        for (int j = 0; j < nsig; ++j) {
+          const double tj = (double)Tw[(size_t)j * M.ldt + q];
+          w0 -= tj * (double)row[NP + j];
+          w1 -= tj * (double)row[2 * NP + j];
+          w2 -= tj * (double)row[3 * NP + j];
+          y -= tj * (double)row[4 * NP + j];
+        }
+        y -= 2.0 * (w0 * g0 + w1 * g1 + w2 * g2);
+        sx[q] = w0;
+        sx[MSD_NV_MAX + q] = w1;
+        sx[2 * MSD_NV_MAX + q] = w2;
+        sx[3 * MSD_NV_MAX + q] = y;
+      }
+      __builtin_amdgcn_s_waitcnt(0xC07F);
+      __builtin_amdgcn_wave_barrier();
+      double d0 = 0.0, d1 = 0.0, d2 = 0.0, lq = 0.0;
+      for (int q = lane; q < M.n_lst[sp]; q += 64) {
+        const int4 e = M.lst[sp][q];
+        const int n = e.y, h0 = e.z & 0xffff, h1 = (unsigned)e.z >> 16, v0 = e.w & 0xffff,
+                  v1 = (unsigned)e.w >> 16;
+        const double cr = M.lcoef[sp][q] * Ro[e.x];
+        const double ga = (double)gcol[h0];
+        if (n == 1) {
+          d0 += cr * ga * sx[v0];
+          d1 += cr * ga * sx[MSD_NV_MAX + v0];
+          d2 += cr * ga * sx[2 * MSD_NV_MAX + v0];
+          lq += cr * ga * sx[3 * MSD_NV_MAX + v0];
+        } else {
+          const double gb = (double)gcol[h1];
+          const double t00 = (double)Tw[(size_t)h0 * M.ldt + v0], t01 = (double)Tw[(size_t)h0 * M.ldt + v1];
+          const double t10 = (double)Tw[(size_t)h1 * M.ldt + v0], t11 = (double)Tw[(size_t)h1 * M.ldt + v1];
+          double dr[4];
+          for (int x = 0; x < 4; ++x) {
+            const double a = sx[x * MSD_NV_MAX + v0], b = sx[x * MSD_NV_MAX + v1];
+            // rank-one change of the 2x2 minor: the second-order cross terms cancel
+            dr[x] = ga * a * t11 + t00 * gb * b - ga * b * t10 - t01 * gb * a;
+          }
+          d0 += cr * dr[0];
+          d1 += cr * dr[1];
+          d2 += cr * dr[2];
+          lq += cr * dr[3];
+        }
+      }
+      d0 = sum64(d0); d1 = sum64(d1); d2 = sum64(d2); lq = sum64(lq);
+      const double iS = 1.0 / M.S[w];
+      msd_k = 2.0 * ((jg0 + g0) * d0 + (jg1 + g1) * d1 + (jg2 + g2) * d2) * iS + lq * iS;
+      __builtin_amdgcn_s_waitcnt(0xC07F);
+      __builtin_amdgcn_wave_barrier();
+    }
+    kin += jl + jg0 * jg0 + jg1 * jg1 + jg2 * jg2 + 2.0 * (jg0 * g0 + jg1 * g1 + jg2 * g2) + l + msd_k;
     pot += v;
     jv += ju;
   }
@@ -742,7 +836,7 @@ __global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int measure_o
     if (mode == 1) c.logw[w] += -c.tau * (0.5 * (eold + e) - e_trial);
     c.eloc[w] = e;
     c.vpot[w] = V + c.v_nn;
-    c.logpsi[w] = J + c.logdet[w * 2] + c.logdet[w * 2 + 1];
+    c.logpsi[w] = J + c.logdet[w * 2] + c.logdet[w * 2 + 1] + (c.M.on ? log(fabs(c.M.S[w])) : 0.0);
     if (!isfinite(e) || !isfinite(c.logpsi[w])) c.flags[w] |= 1u;
     if (e_log_row && w < c.W) e_log_row[w] = e;
   }
@@ -892,6 +986,23 @@ __device__ void block_accept(const DevCtx &c, int w, int t, int i, int sp, int m
     }
 }
 
+// Excited-determinant ratio from table entries: n = 0 -> 1, one hole -> T_hv,
+// two holes -> the 2x2 minor (holes replaced in place).
+__device__ __forceinline__ void msd_unpack(int4 e, int &n, int &h0, int &h1, int &v0, int &v1) {
+  n = e.y;
+  h0 = e.z & 0xffff;
+  h1 = (unsigned)e.z >> 16;
+  v0 = e.w & 0xffff;
+  v1 = (unsigned)e.w >> 16;
+}
+
+// Wave-local LDS visibility: lanes of one wave read what other lanes of the
+// same wave just wrote (LDS operations of a wave complete in order).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_wave_barrier();
+}
+
 // One full sweep: every electron of every walker in the tile proposes a
 // drift-diffusion move r' = r + tau v + sqrt(tau) chi, is accepted with the
 // Metropolis-Hastings probability (fixed node: DMC rejects sign changes),
@@ -899,17 +1010,26 @@ __device__ void block_accept(const DevCtx &c, int w, int t, int i, int sp, int m
 // of k consecutive electrons of one spin, the block's inverse columns are
 // updated by Sherman-Morrison, and at the block end the full inverse takes
 // all k changes at once (rank-k Woodbury form, see flush_block).
-// The step index and mode come from the device run state; acc_log (may be
-// null) receives the accept decisions at
-// acc_log[s_in_run * acc_step_stride + w * acc_w_stride + i].
-template <typename T, int NOB>
-__global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, uint8_t *acc_log,
-                                                    long long acc_step_stride, int acc_w_stride) {
+//
+// MSD (multideterminant form, Eq. 2 with M > 1): Psi = exp(J) D_0^up D_0^dn S
+// with S = sum_d c_d R_d^up R_d^dn, R_d = minors of the table T = A^{-1} M.
+// For a move of electron i (spin s) to r', with a', m' its occupied and
+// virtual orbital rows there, g_i = column i of A^{-1} and rho_0 = a'.g_i:
+//   T' = T + g_i q^T,  q = (m' - T^T a') / rho_0,
+// so every R_d' follows from a few entries of T, the column g_i and q, and
+// grad_{r'} T'_hv = g_hi grad q_v.  At the current position the same form
+// with q = 0 gives grad_i T_hv = g_hi w_v, w = grad m_i - T^T grad a_i.
+// The full ratio is rho_0 S'/S e^{dJ}; the drift adds grad S / S.  An
+// accepted move applies T += g_i q^T and keeps the new R_d^s and S.
+template <typename T, int NOB, bool MSD>
+__device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
+                                           long long acc_step_stride, int acc_w_stride) {
   constexpr int NP = NOB * 16;
   constexpr int FM = 4 * stage_ksteps(NOB);
   extern __shared__ __align__(16) char smem_basis[];
   const BasisLDS BL = stage_basis_lds(c.B, smem_basis);
-  __shared__ T Bs0[FM * NCOL], Bs1[FM * NCOL];
+  __shared__ T Bs[2 * FM * NCOL];  // basis tiles; MSD scratch between tiles
+  T *Bs0 = Bs, *Bs1 = Bs + FM * NCOL;
   __shared__ T vnew[TW * 5 * NP];
   __shared__ T colm[TW][NP];
   __shared__ T aold[TW][NP];
@@ -918,15 +1038,18 @@ __global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, uint8_t *acc_log,
   __shared__ double s_uacc[TW], s_uold[TW], s_rho[TW];
   __shared__ int s_acc[TW];
   __shared__ T crow[TW][KMAX];
+  __shared__ double s_S[TW], s_C0[TW];
   const int tid = threadIdx.x;
   const int ws = tid >> 6, t = tid & 63;  // one wave per walker
   const int w = blockIdx.x * TW + ws;
   double *Rw = c.R + (size_t)w * c.ne * 3;
   T *Gb = (T *)c.Gb + blk_off(c, w);
-  T *Dl = (T *)c.Dl + blk_off(c, w);
   const double tau = c.tau, sqt = sqrt(c.tau);
   const uint32_t step = (uint32_t)c.run->step;
   const int mode = c.run->mode;
+  const DevMsd &M = c.M;
+  // MSD scratch per walker: [4][nv] (q, grad q) or [3][nv] (w)
+  T *msx = Bs + (size_t)ws * 4 * (MSD ? M.nv : 0);
   if (acc_log) acc_log += c.run->s_in_run * acc_step_stride + (long long)w * acc_w_stride;
   PHASE_BEGIN();
   for (int i = 0; i < c.ne; ++i) {
@@ -959,10 +1082,63 @@ __global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, uint8_t *acc_log,
     jastrow_one_partial(c, Rw, i, ro, t, 64, uo, gj);
     gd0 = sum64(gd0); gd1 = sum64(gd1); gd2 = sum64(gd2);
     uo = sum64(uo); gj[0] = sum64(gj[0]); gj[1] = sum64(gj[1]); gj[2] = sum64(gj[2]);
+    double gs[3] = {0.0, 0.0, 0.0};  // grad_i S / S (MSD)
+    if constexpr (MSD) {
+      const T *Tw = (const T *)M.Tt + ((size_t)w * 2 + sp) * NP * M.ldt;
+      const double *Ro = M.Rdet + ((size_t)w * 2 + (1 - sp)) * M.n_det;
+      if (ii == 0) {
+        // spin start: the determinants without an excitation of this spin
+        double c0 = 0.0;
+        for (int q = t; q < M.n_ref[sp]; q += 64) c0 += M.rcoef[sp][q] * Ro[M.rlst[sp][q]];
+        c0 = sum64(c0);
+        if (t == 0) {
+          s_C0[ws] = c0;
+          s_S[ws] = M.S[w];
+        }
+      }
+      // w_v = grad m_v - sum_j T_jv grad a_j at the current position
+      for (int v = t; v < M.nv; v += 64) {
+        const int cv = M.vcol[v];
+        double w0 = (double)row[NP + cv], w1 = (double)row[2 * NP + cv], w2 = (double)row[3 * NP + cv];
+        for (int j = 0; j < nsig; ++j) {
+          const double tj = (double)Tw[(size_t)j * M.ldt + v];
+          w0 -= tj * (double)row[NP + j];
+          w1 -= tj * (double)row[2 * NP + j];
+          w2 -= tj * (double)row[3 * NP + j];
+        }
+        msx[v] = (T)w0;
+        msx[M.nv + v] = (T)w1;
+        msx[2 * M.nv + v] = (T)w2;
+      }
+      wave_lds_sync();
+      for (int q = t; q < M.n_lst[sp]; q += 64) {
+        int n, h0, h1, v0, v1;
+        msd_unpack(M.lst[sp][q], n, h0, h1, v0, v1);
+        const double cr = M.lcoef[sp][q] * Ro[M.lst[sp][q].x];
+        const double g0 = (double)colm[ws][h0];
+        double dr[3];
+        if (n == 1) {
+          for (int x = 0; x < 3; ++x) dr[x] = g0 * (double)msx[x * M.nv + v0];
+        } else {
+          const double g1 = (double)colm[ws][h1];
+          const double t00 = (double)Tw[(size_t)h0 * M.ldt + v0], t01 = (double)Tw[(size_t)h0 * M.ldt + v1];
+          const double t10 = (double)Tw[(size_t)h1 * M.ldt + v0], t11 = (double)Tw[(size_t)h1 * M.ldt + v1];
+          for (int x = 0; x < 3; ++x) {
+            const double wa = (double)msx[x * M.nv + v0], wb = (double)msx[x * M.nv + v1];
+            dr[x] = g0 * wa * t11 + t00 * g1 * wb - g0 * wb * t10 - t01 * g1 * wa;
+          }
+        }
+        for (int x = 0; x < 3; ++x) gs[x] += cr * dr[x];
+      }
+      gs[0] = sum64(gs[0]); gs[1] = sum64(gs[1]); gs[2] = sum64(gs[2]);
+      __syncthreads();  // s_S / s_C0 of the spin start; scratch reuse below
+      const double iS = 1.0 / s_S[ws];
+      gs[0] *= iS; gs[1] *= iS; gs[2] *= iS;
+    }
     double chi[3], ua;
     move_draws_lanes64(c.seed, step, (uint32_t)w, (uint32_t)i, t, chi, ua);
     if (t == 0) {
-      const double v[3] = {gj[0] + gd0, gj[1] + gd1, gj[2] + gd2};
+      const double v[3] = {gj[0] + gd0 + gs[0], gj[1] + gd1 + gs[1], gj[2] + gd2 + gs[2]};
       for (int x = 0; x < 3; ++x) {
         pts[ws][x] = ro[x] + tau * v[x] + sqt * chi[x];
         s_v[ws][x] = v[x];
@@ -990,9 +1166,69 @@ __global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, uint8_t *acc_log,
     jastrow_one_partial(c, Rw, i, rn, t, 64, un, gjn);
     rho = sum64(rho); gn0 = sum64(gn0); gn1 = sum64(gn1); gn2 = sum64(gn2);
     un = sum64(un); gjn[0] = sum64(gjn[0]); gjn[1] = sum64(gjn[1]); gjn[2] = sum64(gjn[2]);
+    // rho is the reference determinant's ratio; rho_all includes S'/S (MSD)
+    double rho_all = rho, gsn[3] = {0.0, 0.0, 0.0}, s_new = 0.0;
+    if constexpr (MSD) {
+      const T *Tw = (const T *)M.Tt + ((size_t)w * 2 + sp) * NP * M.ldt;
+      const double *Ro = M.Rdet + ((size_t)w * 2 + (1 - sp)) * M.n_det;
+      const double ir = 1.0 / rho;
+      // q_v = (m'_v - sum_j T_jv a'_j) / rho_0, grad q_v = (grad u_v - q_v grad rho_0) / rho_0
+      for (int v = t; v < M.nv; v += 64) {
+        const int cv = M.vcol[v];
+        double u0 = (double)vw[cv], u1 = (double)vw[NP + cv], u2 = (double)vw[2 * NP + cv],
+               u3 = (double)vw[3 * NP + cv];
+        for (int j = 0; j < nsig; ++j) {
+          const double tj = (double)Tw[(size_t)j * M.ldt + v];
+          u0 -= tj * (double)vw[j];
+          u1 -= tj * (double)vw[NP + j];
+          u2 -= tj * (double)vw[2 * NP + j];
+          u3 -= tj * (double)vw[3 * NP + j];
+        }
+        const double q = u0 * ir;
+        msx[v] = (T)q;
+        msx[M.nv + v] = (T)((u1 - q * gn0) * ir);
+        msx[2 * M.nv + v] = (T)((u2 - q * gn1) * ir);
+        msx[3 * M.nv + v] = (T)((u3 - q * gn2) * ir);
+      }
+      wave_lds_sync();
+      double sn = 0.0;
+      double *Rn = M.Rnew + (size_t)w * M.max_lst;
+      for (int q = t; q < M.n_lst[sp]; q += 64) {
+        int n, h0, h1, v0, v1;
+        msd_unpack(M.lst[sp][q], n, h0, h1, v0, v1);
+        const double cr = M.lcoef[sp][q] * Ro[M.lst[sp][q].x];
+        const double g0 = (double)colm[ws][h0];
+        double r, dr[3];
+        if (n == 1) {
+          r = (double)Tw[(size_t)h0 * M.ldt + v0] + g0 * (double)msx[v0];
+          for (int x = 0; x < 3; ++x) dr[x] = g0 * (double)msx[(x + 1) * M.nv + v0];
+        } else {
+          const double g1 = (double)colm[ws][h1];
+          const double qa = (double)msx[v0], qb = (double)msx[v1];
+          const double t00 = (double)Tw[(size_t)h0 * M.ldt + v0] + g0 * qa;
+          const double t01 = (double)Tw[(size_t)h0 * M.ldt + v1] + g0 * qb;
+          const double t10 = (double)Tw[(size_t)h1 * M.ldt + v0] + g1 * qa;
+          const double t11 = (double)Tw[(size_t)h1 * M.ldt + v1] + g1 * qb;
+          r = t00 * t11 - t01 * t10;
+          for (int x = 0; x < 3; ++x) {
+            const double da = (double)msx[(x + 1) * M.nv + v0], db = (double)msx[(x + 1) * M.nv + v1];
+            dr[x] = g0 * da * t11 + t00 * g1 * db - g0 * db * t10 - t01 * g1 * da;
+          }
+        }
+        Rn[q] = r;
+        sn += cr * r;
+        for (int x = 0; x < 3; ++x) gsn[x] += cr * dr[x];
+      }
+      s_new = s_C0[ws] + sum64(sn);
+      gsn[0] = sum64(gsn[0]); gsn[1] = sum64(gsn[1]); gsn[2] = sum64(gsn[2]);
+      const double iS = 1.0 / s_new;
+      gsn[0] *= iS; gsn[1] *= iS; gsn[2] *= iS;
+      rho_all = rho * (s_new / s_S[ws]);
+    }
     int accepted = 0;
-    if (!(mode == 1 && !(rho > 0.0))) {
-      const double vn[3] = {gjn[0] + gn0 / rho, gjn[1] + gn1 / rho, gjn[2] + gn2 / rho};
+    if (!(mode == 1 && !(rho_all > 0.0))) {
+      const double vn[3] = {gjn[0] + gn0 / rho + gsn[0], gjn[1] + gn1 / rho + gsn[1],
+                            gjn[2] + gn2 / rho + gsn[2]};
       double fwd = 0.0, bwd = 0.0;
       for (int x = 0; x < 3; ++x) {
         const double a = rn[x] - ro[x] - tau * s_v[ws][x];
@@ -1000,14 +1236,31 @@ __global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, uint8_t *acc_log,
         fwd += a * a;
         bwd += b * b;
       }
-      const double lnq = 2.0 * (log(fabs(rho)) + (un - s_uold[ws])) + (fwd - bwd) / (2.0 * tau);
+      const double lnq = 2.0 * (log(fabs(rho_all)) + (un - s_uold[ws])) + (fwd - bwd) / (2.0 * tau);
       const double p = lnq >= 0.0 ? 1.0 : exp(lnq);
       accepted = s_uacc[ws] < p;
     }
-    if (!isfinite(rho)) c.flags[w] |= 1u;
+    if (!isfinite(rho_all)) c.flags[w] |= 1u;
     PHASE_MARK(3);
     // ---- P4: delayed update of the block (lanes of this walker only)
     block_accept<T, NOB>(c, w, t, i, sp, m, kb, accepted, rho, vw, colm[ws], aold[ws], crow[ws], rn);
+    if constexpr (MSD) {
+      if (accepted) {
+        // T += g_i q^T (g_i: the column before the move), keep R_d' and S'
+        T *Tw = (T *)M.Tt + ((size_t)w * 2 + sp) * NP * M.ldt;
+        for (int v = t; v < M.nv; v += 64) {
+          const T q = msx[v];
+          for (int j = 0; j < nsig; ++j) Tw[(size_t)j * M.ldt + v] += colm[ws][j] * q;
+        }
+        double *Rs = M.Rdet + ((size_t)w * 2 + sp) * M.n_det;
+        const double *Rn = M.Rnew + (size_t)w * M.max_lst;
+        for (int q = t; q < M.n_lst[sp]; q += 64) Rs[M.lst[sp][q].x] = Rn[q];
+        if (t == 0) {
+          s_S[ws] = s_new;
+          if (w < c.W) M.S[w] = s_new;
+        }
+      }
+    }
     if (acc_log && t == 0 && w < c.W) acc_log[i] = (uint8_t)accepted;
     PHASE_MARK(4);
     // ---- P5: block end -> rank-k flush of the full inverse
@@ -1017,6 +1270,22 @@ __global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, uint8_t *acc_log,
     PHASE_MARK(6);
   }
   PHASE_END();
+}
+
+// The step index and mode come from the device run state; acc_log (may be
+// null) receives the accept decisions at
+// acc_log[s_in_run * acc_step_stride + w * acc_w_stride + i].
+template <typename T, int NOB>
+__global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, uint8_t *acc_log,
+                                                    long long acc_step_stride, int acc_w_stride) {
+  sweep_body<T, NOB, false>(c, acc_log, acc_step_stride, acc_w_stride);
+}
+
+// The same sweep for a multideterminant trial function (table method).
+template <typename T, int NOB>
+__global__ __launch_bounds__(NT_TILE) void k_sweep_msd(DevCtx c, uint8_t *acc_log,
+                                                        long long acc_step_stride, int acc_w_stride) {
+  sweep_body<T, NOB, true>(c, acc_log, acc_step_stride, acc_w_stride);
 }
 
 

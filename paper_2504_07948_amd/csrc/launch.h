@@ -1,0 +1,41 @@
+// Host-side launchers of the kernels that are templated on the number of
+// 16-orbital blocks (NOB).  Each working precision is instantiated in a
+// translation unit of its own (kern_f64.hip, kern_f32.hip), so the builds of
+// the many NOB variants run in parallel; the runtime (dmcx.hip) calls these
+// with the context's NOB and never instantiates the kernels itself.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace dmcx {
+
+constexpr int NOB_MAX = 10;  // up to 160 orbital columns per tile
+
+template <typename T>
+struct NobLaunch {
+  // orbital VGL rows of every electron of every walker -> vglc
+  static void orbitals_all(int nob, const DevCtx &c, size_t lds, hipStream_t s);
+  // orbitals at one point per walker -> dst [Wpad][5][NP]
+  static void orbitals_at(int nob, const DevCtx &c, const double *pos, int npts, T *dst,
+                          size_t lds, hipStream_t s);
+  // one full sweep of the single-determinant trial function
+  static void sweep(int nob, const DevCtx &c, uint8_t *acc, long long acc_ss, int acc_ws,
+                    size_t lds, hipStream_t s);
+  // static LDS bytes of that sweep kernel
+  static size_t sweep_lds(int nob);
+  // per-tile determinant part of the ion derivatives
+  static void ion_grad_det(int nob, const DevCtx &c, double *partial, int ntile, size_t lds,
+                           hipStream_t s);
+  // move-by-move interface
+  static void block_init(int nob, const DevCtx &c, int sp, int b0, int kb, hipStream_t s);
+  static void ratio_grad(int nob, const DevCtx &c, int iel, int m, const double *r_new,
+                         double *ratio, double *grad, T *prop, double *prop_rho, size_t lds,
+                         hipStream_t s);
+  static void accept(int nob, const DevCtx &c, int iel, int sp, int m, int kb,
+                     const uint8_t *acc8, const T *prop, const double *prop_rho,
+                     const double *r_new, hipStream_t s);
+  static void flush(int nob, const DevCtx &c, int sp, int kb, hipStream_t s);
+};
+
+}  // namespace dmcx

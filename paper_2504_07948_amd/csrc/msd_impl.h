@@ -1,0 +1,28 @@
+// MsdLaunch members (the multideterminant sweep); included once per working
+// precision.
+#pragma once
+#include "kern_impl.h"
+#include "msd.h"
+
+namespace dmcx {
+
+template <typename T>
+void MsdLaunch<T>::sweep(int nob, const DevCtx &c, uint8_t *acc, long long acc_ss, int acc_ws,
+                         size_t lds, hipStream_t s) {
+#define DMCX_CALL(N)                                                                   \
+  allow_lds(k_sweep_msd<T, N>, lds);                                                   \
+  k_sweep_msd<T, N><<<dim3(c.Wpad / TW), dim3(NT_TILE), lds, s>>>(c, acc, acc_ss, acc_ws)
+  DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+}
+
+template <typename T>
+size_t MsdLaunch<T>::sweep_lds(int nob) {
+  hipFuncAttributes a{};
+#define DMCX_CALL(N) (void)hipFuncGetAttributes(&a, (const void *)k_sweep_msd<T, N>)
+  DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+  return a.sharedSizeBytes;
+}
+
+}  // namespace dmcx
