@@ -1168,10 +1168,13 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
     un = sum64(un); gjn[0] = sum64(gjn[0]); gjn[1] = sum64(gjn[1]); gjn[2] = sum64(gjn[2]);
     // rho is the reference determinant's ratio; rho_all includes S'/S (MSD)
     double rho_all = rho, gsn[3] = {0.0, 0.0, 0.0}, s_new = 0.0;
+    // (MSD) a proposal where the reference determinant vanishes (every
+    // orbital underflows far from the molecule) is rejected like any other
+    // zero ratio; the table update would divide by it
     if constexpr (MSD) {
       const T *Tw = (const T *)M.Tt + ((size_t)w * 2 + sp) * NP * M.ldt;
       const double *Ro = M.Rdet + ((size_t)w * 2 + (1 - sp)) * M.n_det;
-      const double ir = 1.0 / rho;
+      const double ir = rho != 0.0 ? 1.0 / rho : 0.0;
       // q_v = (m'_v - sum_j T_jv a'_j) / rho_0, grad q_v = (grad u_v - q_v grad rho_0) / rho_0
       for (int v = t; v < M.nv; v += 64) {
         const int cv = M.vcol[v];
@@ -1223,7 +1226,7 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
       gsn[0] = sum64(gsn[0]); gsn[1] = sum64(gsn[1]); gsn[2] = sum64(gsn[2]);
       const double iS = 1.0 / s_new;
       gsn[0] *= iS; gsn[1] *= iS; gsn[2] *= iS;
-      rho_all = rho * (s_new / s_S[ws]);
+      rho_all = rho != 0.0 ? rho * (s_new / s_S[ws]) : 0.0;
     }
     int accepted = 0;
     if (!(mode == 1 && !(rho_all > 0.0))) {
@@ -1257,7 +1260,7 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
         for (int q = t; q < M.n_lst[sp]; q += 64) Rs[M.lst[sp][q].x] = Rn[q];
         if (t == 0) {
           s_S[ws] = s_new;
-          if (w < c.W) M.S[w] = s_new;
+          M.S[w] = s_new;
         }
       }
     }
