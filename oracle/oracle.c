@@ -524,6 +524,8 @@ int orc_run(const orc_system *s, int32_t W, double *R, double *log_w, double *e_
  *                          = -sum_{l on atom a} C_lj dPhi_l/dx (r_i)   (Eq. 3)
  * dJ/dR_a = -sum_i u_a'(r_ia) (r_i - R_a)/r_ia
  * dV/dR_a = -Z_a sum_i (r_i - R_a)/r_ia^3 - sum_{b != a} Z_a Z_b (R_a - R_b)/R_ab^3 */
+static int msd_ion_det_grads(const orc_system *s, const double *R, double *dlogpsi);
+
 int orc_ion_grads(const orc_system *s, const double *R, double *dlogpsi, double *dV) {
   wstate w;
   int rc = ws_init(s, &w, R);
@@ -534,7 +536,8 @@ int orc_ion_grads(const orc_system *s, const double *R, double *dlogpsi, double 
   memset(dlogpsi, 0, sizeof(double) * 3 * na);
   memset(dV, 0, sizeof(double) * 3 * na);
   double *bvgl = (double *)malloc(sizeof(double) * 5 * nb);
-  for (int sp = 0; sp < 2; ++sp) {
+  if (s->n_det > 1) rc |= msd_ion_det_grads(s, R, dlogpsi);
+  for (int sp = 0; sp < 2 && s->n_det <= 1; ++sp) {
     const int n = w.nsig[sp];
     if (n == 0) continue;
     /* B[a][x][i][j] */
@@ -922,5 +925,94 @@ static int msd_walker_run(const orc_system *s, double *R, double *log_w, double 
   free(orb_t);
   free(dphi);
   free(dphi_t);
+  return rc;
+}
+
+/* Ion gradient of ln|Phi|, Phi = sum_d c_d D_d^up D_d^dn, forward mode per
+ * determinant (Eq. 3 with lambda = R_{a,x} for each determinant's own
+ * matrix):  d ln|D_d| = tr(A_d^{-1} dA_d),
+ *   dA_d[i][j] = -sum_{l on a} C_{l, c_j} dPhi_l/dx (r_i),
+ *   d ln|Phi| = sum_d c_d R_d^up R_d^dn (d ln|D_d^up| + d ln|D_d^dn|) / S. */
+static int msd_ion_det_grads(const orc_system *s, const double *R, double *dlogpsi) {
+  const int na = s->n_atom, nb = s->n_basis, nmo = msd_n_mo(s), nd = s->n_det;
+  int rc = 0;
+  int *fn_atom = (int *)malloc(sizeof(int) * nb);
+  for (int sh = 0, f = 0; sh < s->n_shell; ++sh)
+    for (int k = 0; k < NCART[s->shell_l[sh]]; ++k) fn_atom[f++] = s->shell_atom[sh];
+  double *bvgl = (double *)malloc(sizeof(double) * 5 * nb);
+  double *ratio = (double *)malloc(sizeof(double) * 2 * nd);     /* [2][nd] */
+  double *dl = (double *)calloc((size_t)2 * nd * na * 3, sizeof(double)); /* [2][nd][na*3] */
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = sp == 0 ? s->n_up : s->n_dn, e0 = sp == 0 ? 0 : s->n_up;
+    if (n == 0) {
+      for (int d = 0; d < nd; ++d) ratio[sp * nd + d] = 1.0;
+      continue;
+    }
+    /* values phi_p(r_i) and derivatives dphi[i][a*3+x][p] of every MO used */
+    double *val = (double *)calloc((size_t)n * nmo, sizeof(double));
+    double *dphi = (double *)calloc((size_t)n * na * 3 * nmo, sizeof(double));
+    for (int ii = 0; ii < n; ++ii) {
+      rc |= orc_basis_vgl(s, R + 3 * (e0 + ii), bvgl);
+      for (int l = 0; l < nb; ++l) {
+        const int a = fn_atom[l];
+        for (int p = 0; p < nmo; ++p) {
+          const double c = s->mo_coef[(size_t)l * s->n_mo + p];
+          val[(size_t)ii * nmo + p] += c * bvgl[5 * l];
+          for (int x = 0; x < 3; ++x)
+            dphi[((size_t)ii * na * 3 + a * 3 + x) * nmo + p] -= c * bvgl[5 * l + 1 + x];
+        }
+      }
+    }
+    double *A = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *G = (double *)malloc(sizeof(double) * (size_t)n * n);
+    int *cols = (int *)malloc(sizeof(int) * (size_t)n);
+    double ld0 = 0.0;
+    int32_t sg0 = 1;
+    for (int d = 0; d < nd; ++d) {
+      const int32_t *e = s->det_exc + 10 * d;
+      const int nx = e[sp];
+      for (int j = 0; j < n; ++j) cols[j] = j;
+      const int *h = e + (sp == 0 ? 2 : 6), *p = e + (sp == 0 ? 4 : 8);
+      for (int k = 0; k < nx; ++k) cols[h[k]] = p[k];
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = val[(size_t)i * nmo + cols[j]];
+      double ld;
+      int32_t sg;
+      const int sing = orc_lu_slogdet_inv(n, A, &ld, &sg, G);
+      if (d == 0) {
+        rc |= sing;
+        ld0 = ld;
+        sg0 = sg;
+      }
+      if (sing) {
+        ratio[sp * nd + d] = 0.0;
+        continue;
+      }
+      ratio[sp * nd + d] = d == 0 ? 1.0 : (double)(sg * sg0) * exp(ld - ld0);
+      for (int k = 0; k < na * 3; ++k) {
+        double tr = 0.0;
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j)
+            tr += G[(size_t)j * n + i] * dphi[((size_t)i * na * 3 + k) * nmo + cols[j]];
+        dl[((size_t)sp * nd + d) * na * 3 + k] = tr;
+      }
+    }
+    free(A);
+    free(G);
+    free(cols);
+    free(val);
+    free(dphi);
+  }
+  double S = 0.0;
+  for (int d = 0; d < nd; ++d) S += s->ci_coef[d] * ratio[d] * ratio[nd + d];
+  for (int d = 0; d < nd; ++d) {
+    const double wgt = s->ci_coef[d] * ratio[d] * ratio[nd + d] / S;
+    for (int k = 0; k < na * 3; ++k)
+      dlogpsi[k] += wgt * (dl[(size_t)d * na * 3 + k] + dl[((size_t)nd + d) * na * 3 + k]);
+  }
+  free(ratio);
+  free(dl);
+  free(bvgl);
+  free(fn_atom);
   return rc;
 }

@@ -170,3 +170,52 @@ def test_exchange_of_two_same_spin_electrons():
         assert abs(l1 - l0) <= 1e-12 * max(1.0, abs(l0))
         assert abs(e1 - e0) <= 1e-10 * max(1.0, abs(e0))
         np.testing.assert_allclose(d1[[2, 0]], d0[[0, 2]], rtol=1e-10, atol=1e-10)
+
+
+def test_ion_gradients_sum_to_one_determinant():
+    """Forward-mode ion gradients of the 16-determinant expansion equal those
+    of the single determinant with the mixed columns (multilinearity)."""
+    s = _base()
+    (h1, p1, a), (h2, p2, b) = (1, 6, 0.35), (2, 8, -0.27)
+    per_spin = [([0, 0] + [-1] * 8, 1.0)]
+
+    def rows_for(spin):
+        return [(_single(spin, h1, p1), a), (_single(spin, h2, p2), b),
+                (_double_same(spin, h1, h2, p1, p2), a * b)]
+
+    rows, coef = [], []
+    for ru, cu in per_spin + rows_for(0):
+        for rd, cd in per_spin + rows_for(1):
+            if cu == 1.0 and cd == 1.0 and ru[0] == 0 and rd[1] == 0:
+                continue
+            rows.append(_combine(ru, rd))
+            coef.append(cu * cd)
+    m = _with_exc(s, rows, coef)
+    mo = s.mo_coef.copy()
+    mo[:, h1] += a * s.mo_coef[:, p1]
+    mo[:, h2] += b * s.mo_coef[:, p2]
+    eq = dataclasses.replace(s, mo_coef=mo)
+    for Rw in synth.make_walkers(s, 3, 12):
+        dl_m, dv_m = oracle.ion_grads(m, Rw)[:2]
+        dl_e, dv_e = oracle.ion_grads(eq, Rw)[:2]
+        np.testing.assert_allclose(dl_m, dl_e, rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(dv_m, dv_e, rtol=1e-12, atol=1e-12)
+
+
+def test_ion_gradients_vs_finite_differences():
+    m = _random_msd()
+    Rw = synth.make_walkers(m, 1, 13)[0]
+    dl = oracle.ion_grads(m, Rw)[0]
+
+    def lp_at(xyz):
+        return oracle.evaluate(dataclasses.replace(m, ion_xyz=xyz), Rw)[0]
+
+    for a in range(m.n_atom):
+        for x in range(3):
+            est = {}
+            for h in (2e-4, 1e-4):
+                xp = m.ion_xyz.copy(); xp[a, x] += h
+                xm = m.ion_xyz.copy(); xm[a, x] -= h
+                est[h] = (lp_at(xp) - lp_at(xm)) / (2 * h)
+            fd = (4 * est[1e-4] - est[2e-4]) / 3
+            assert abs(fd - dl[a, x]) <= 1e-6 * max(1.0, abs(fd)), (a, x, fd, dl[a, x])
