@@ -134,6 +134,15 @@ def batch5_leg(torch, dmcx, stream, steps=5, W=512, n_det=1000, n_active=100, P=
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     moves = W * sum(x.n_elec for x in systems) * steps
+    # the same steps with the force estimate of every molecule after each step
+    F = torch.zeros((len(systems), ctx.n_atom, 3), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.run_device(1, mode=dmcx.DMCX_DMC, e_trial=e_t)
+        ctx.check(dmcx.dmcx_forces(ctx.h, F.data_ptr(), dmcx.DMCX_DEVICE))
+    torch.cuda.synchronize()
+    dt_f = time.perf_counter() - t0
     return {"molecules": [x.name for x in systems], "electrons": [x.n_elec for x in systems],
             "walkers_each": W, "determinants": n_det, "active_orbitals": n_active,
             "steps": steps, "recompute_period": P, "precision": "mixed", "graph": True,
@@ -141,7 +150,8 @@ def batch5_leg(torch, dmcx, stream, steps=5, W=512, n_det=1000, n_active=100, P=
             "warmup_s_incl_autotune": t_warm,
             "value": moves / dt, "unit": "electron-moves/s", "ms_per_step": 1e3 * dt / steps,
             "walker_flags_nonzero": int((ctx.walker_flags() != 0).sum()),
-            "forces": "not built for multideterminant expansions"}
+            "ms_per_step_with_forces": 1e3 * dt_f / steps,
+            "force_energy_cost_ratio": dt_f / dt}
 
 
 def forces_leg(s, torch, dmcx, stream, args, W=1024, steps=5):

@@ -50,6 +50,7 @@ struct dmcx_ctx {
   // forces: per-walker derivatives, cached per configuration version
   double *d_partial = nullptr, *d_dl = nullptr, *d_dv = nullptr, *d_gbar = nullptr,
          *d_red = nullptr;
+  void *d_wt = nullptr;  // multideterminant: adjoint weights in GT layout (on first use)
   uint64_t version = 1, grads_version = 0;
   // move-by-move interface: current electron block and pending proposal
   bool blk_active = false, eloc_dirty = false;
@@ -505,17 +506,35 @@ dmcx_status refresh_after_moves(dmcx_ctx *c) {
 
 // Per-walker ion derivatives for the current configuration (cached).
 dmcx_status compute_ion_grads(dmcx_ctx *c) {
-  if (c->dc.M.on)
-    return fail(c, DMCX_E_UNSUPPORTED, "ion derivatives of a multideterminant expansion");
   dmcx_status st0 = refresh_after_moves(c);
   if (st0) return st0;
   if (c->grads_version == c->version) return DMCX_OK;
   const int ntile = (c->ne + FPTS - 1) / FPTS;
   const size_t lds = basis_lds(c);
+  DevCtx dc = c->dc;
+  if (dc.M.on) {
+    // the reference determinant's weights (GT rows) become the expansion's
+    const size_t wl = 2 * (size_t)std::max(c->n_up, c->n_dn) * dc.M.nv * sizeof(double);
+    if (wl > 160 * 1024)
+      return fail(c, DMCX_E_UNSUPPORTED, "ion derivatives: expansion table too large for LDS");
+    if (!c->d_wt && (st0 = dalloc(c, (char **)&c->d_wt, c->es * c->Wpad * 2 * c->NP * c->NP)))
+      return st0;
+    if (c->mixed) {
+      allow_lds(k_msd_force_weights<float>, wl);
+      hipLaunchKernelGGL(k_msd_force_weights<float>, dim3(c->Wpad, 2), dim3(NT_AUX), wl, c->stream,
+                         c->dc, (float *)c->d_wt);
+    } else {
+      allow_lds(k_msd_force_weights<double>, wl);
+      hipLaunchKernelGGL(k_msd_force_weights<double>, dim3(c->Wpad, 2), dim3(NT_AUX), wl,
+                         c->stream, c->dc, (double *)c->d_wt);
+    }
+    HIP_TRY(c, hipGetLastError());
+    dc.GT = c->d_wt;
+  }
   if (c->mixed) {
-    NobLaunch<float>::ion_grad_det(c->NOB, c->dc, c->d_partial, ntile, lds, c->stream);
+    NobLaunch<float>::ion_grad_det(c->NOB, dc, c->d_partial, ntile, lds, c->stream);
   } else {
-    NobLaunch<double>::ion_grad_det(c->NOB, c->dc, c->d_partial, ntile, lds, c->stream);
+    NobLaunch<double>::ion_grad_det(c->NOB, dc, c->d_partial, ntile, lds, c->stream);
   }
   HIP_TRY(c, hipGetLastError());
   hipLaunchKernelGGL(k_ion_grad_finalize, dim3(c->Wpad), dim3(64), 0, c->stream, c->dc,

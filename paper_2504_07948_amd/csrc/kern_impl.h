@@ -6,12 +6,6 @@
 
 namespace dmcx {
 
-template <typename K>
-inline void allow_lds(K kernel, size_t dyn) {
-  (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)dyn);
-}
-
 #define DMCX_NOB_SWITCH(nob, CALL) \
   switch (nob) {                   \
     case 1: CALL(1); break;        \

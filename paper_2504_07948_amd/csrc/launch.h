@@ -12,6 +12,13 @@ namespace dmcx {
 
 constexpr int NOB_MAX = 10;  // up to 160 orbital columns per tile
 
+// Let a kernel use `dyn` bytes of dynamic LDS (beyond the 64 KB default).
+template <typename K>
+inline void allow_lds(K kernel, size_t dyn) {
+  (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)dyn);
+}
+
 template <typename T>
 struct NobLaunch {
   // orbital VGL rows of every electron of every walker -> vglc

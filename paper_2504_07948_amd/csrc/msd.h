@@ -66,6 +66,68 @@ __global__ __launch_bounds__(NT_AUX) void k_msd_dets(DevCtx c, int periodic) {
   }
 }
 
+// Orbital-space weights of the ion-force adjoint with the expansion.  With
+// S = sum_d c_d R_d^up R_d^dn and dT = A^{-1} (dM - dA T) for a change of
+// the orbitals,
+//   d ln S = sum_i [ sum_v X_iv dM_iv - sum_j Y_ij dA_ij ],
+//   Gamma_hv = d ln S / dT_hv = sum_d c_d R_d^other dR_d/dT_hv / S,
+//   X = A^{-T} Gamma (X_iv = sum_h G_hi Gamma_hv),  Y = X T^T,
+// so the reference determinant's weights g_i (row i of GT) become
+//   W[i][j] = g_i[j] - Y_ij (occupied j),  W[i][vcol[v]] = X_iv,
+// and the same contraction with the basis gradients (forces.h) gives
+// d ln|D_0 S| / dR.  grid (Wpad, 2), dynamic LDS 2 n_sigma nv doubles.
+template <typename T>
+__global__ __launch_bounds__(NT_AUX) void k_msd_force_weights(DevCtx c, T *WT) {
+  extern __shared__ double gx[];  // Gamma [n][nv], then X [n][nv]
+  const int w = blockIdx.x, sp = blockIdx.y, tid = threadIdx.x;
+  const DevMsd &M = c.M;
+  const int n = sp == 0 ? c.n_up : c.n_dn, NP = c.NP, nv = M.nv, ldt = M.ldt;
+  double *Gam = gx, *X = gx + (size_t)n * nv;
+  const T *GT = (const T *)c.GT + gt_off(c, w, sp);
+  const T *Tw = (const T *)M.Tt + ((size_t)w * 2 + sp) * NP * ldt;
+  const double *Ro = M.Rdet + ((size_t)w * 2 + (1 - sp)) * M.n_det;
+  T *Wo = WT + gt_off(c, w, sp);
+  for (int q = tid; q < n * nv; q += NT_AUX) Gam[q] = 0.0;
+  __syncthreads();
+  const double iS = 1.0 / M.S[w];
+  for (int q = tid; q < M.n_lst[sp]; q += NT_AUX) {
+    const int4 e = M.lst[sp][q];
+    const int ne = e.y, h0 = e.z & 0xffff, h1 = (unsigned)e.z >> 16, v0 = e.w & 0xffff,
+              v1 = (unsigned)e.w >> 16;
+    const double cr = M.lcoef[sp][q] * Ro[e.x] * iS;
+    if (ne == 1) {
+      atomicAdd(&Gam[h0 * nv + v0], cr);
+    } else {
+      atomicAdd(&Gam[h0 * nv + v0], cr * (double)Tw[(size_t)h1 * ldt + v1]);
+      atomicAdd(&Gam[h1 * nv + v1], cr * (double)Tw[(size_t)h0 * ldt + v0]);
+      atomicAdd(&Gam[h0 * nv + v1], -cr * (double)Tw[(size_t)h1 * ldt + v0]);
+      atomicAdd(&Gam[h1 * nv + v0], -cr * (double)Tw[(size_t)h0 * ldt + v1]);
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < n * nv; q += NT_AUX) {
+    const int i = q / nv, v = q - i * nv;
+    double x = 0.0;
+    for (int h = 0; h < n; ++h) x += (double)GT[(size_t)i * NP + h] * Gam[h * nv + v];
+    X[q] = x;
+  }
+  __syncthreads();
+  for (int q = tid; q < NP * NP; q += NT_AUX) {
+    const int i = q / NP, j = q - i * NP;
+    double wv = 0.0;
+    if (i < n && j < n) {
+      wv = (double)GT[(size_t)i * NP + j];
+      for (int v = 0; v < nv; ++v) wv -= X[i * nv + v] * (double)Tw[(size_t)j * ldt + v];
+    }
+    Wo[q] = (T)wv;
+  }
+  __syncthreads();
+  for (int q = tid; q < n * nv; q += NT_AUX) {
+    const int i = q / nv, v = q - i * nv;
+    Wo[(size_t)i * NP + M.vcol[v]] = (T)X[q];
+  }
+}
+
 template <typename T>
 struct MsdLaunch {
   static void sweep(int nob, const DevCtx &c, uint8_t *acc, long long acc_ss, int acc_ws,

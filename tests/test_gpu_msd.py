@@ -217,10 +217,67 @@ def test_msd_mixed_precision_error():
     assert np.abs(lp_m - lp_f).max() <= 1e-2
 
 
-def test_msd_forces_not_built():
+@pytest.mark.parametrize("which,W", [("cfg1", 8), ("cfg2", 3)])
+def test_msd_ion_grads_match_oracle(which, W):
+    """Reverse mode through the table (adjoint weights X, Y of the minors)
+    against the oracle's forward mode per determinant."""
+    s = _msd_cfg1() if which == "cfg1" else _msd_cfg2()
+    R = synth.make_walkers(s, W, 919)
+    ctx = dmcx.Context(s, W)
+    ctx.set_walkers(R)
+    dl, dv = ctx.ion_grads()
+    dl_o, dv_o, rc = oracle.ion_grads_batch(s, R)
+    assert rc == 0
+    _close(dv, dv_o, rel=1e-12)
+    amp = np.array([max(1.0, np.prod(_conditioning(s, Rw)) / 100.0) for Rw in R])
+    err = np.abs(dl - dl_o).max(axis=(1, 2)) / max(1.0, np.abs(dl_o).max())
+    print(f"[msd] {which} ion grads: max rel err {err.max():.2e}", flush=True)
+    assert np.all(err <= 1e-10 * amp)
+
+
+def test_msd_ion_grads_after_moves_and_fd():
     s = _msd_cfg1()
-    ctx = dmcx.Context(s, 8)
-    ctx.set_walkers(synth.make_walkers(s, 8, 918))
-    with pytest.raises(dmcx.DmcxError) as e:
-        ctx.ion_grads()
-    assert e.value.status == dmcx.DMCX_E_UNSUPPORTED
+    W = 8
+    R = synth.make_walkers(s, W, 920)
+    ctx = dmcx.Context(s, W, delay_rank=2, recompute_period=100, seed=26)
+    ctx.set_walkers(R)
+    ctx.run(2, mode=dmcx.DMCX_DMC, e_trial=-8.0)
+    Rg, _ = ctx.get_walkers()
+    dl, _ = ctx.ion_grads()
+    dl_o, _, _ = oracle.ion_grads_batch(s, Rg)
+    amp = np.array([max(1.0, np.prod(_conditioning(s, Rw)) / 100.0) for Rw in Rg])
+    err = np.abs(dl - dl_o).max(axis=(1, 2)) / max(1.0, np.abs(dl_o).max())
+    assert np.all(err <= 1e-9 * amp), err
+    # central differences of the library's own log|Psi| (Richardson, h = 2e-4, 1e-4)
+    ctx.set_walkers(Rg)
+    dl0, _ = ctx.ion_grads()
+    base = s.ion_xyz.copy()
+    for a, x in [(0, 0), (2, 1), (3, 2)]:
+        est = {}
+        for h in (2e-4, 1e-4):
+            vals = []
+            for sgn in (1, -1):
+                xyz = base.copy()
+                xyz[a, x] += sgn * h
+                ctx.set_ions(xyz)
+                vals.append(ctx.measure()[1])
+            est[h] = (vals[0] - vals[1]) / (2 * h)
+        fd = (4 * est[1e-4] - est[2e-4]) / 3
+        np.testing.assert_allclose(dl0[:, a, x], fd, rtol=1e-6, atol=1e-6)
+    ctx.set_ions(base)
+
+
+def test_msd_forces_estimator_runs_in_a_group():
+    systems = [synth.make_msd(synth.alkane(3, 80), 100, 30, 81), _msd_cfg1()]
+    walkers = [8, 8]
+    ne_max = max(x.n_elec for x in systems)
+    R = np.zeros((16, ne_max, 3))
+    for i, x in enumerate(systems):
+        R[i * 8:(i + 1) * 8, :x.n_elec] = synth.make_walkers(x, 8, 921 + i)
+    grp = dmcx.Context(systems, walkers)
+    grp.set_walkers(R)
+    F = grp.forces()
+    for i, x in enumerate(systems):
+        one = dmcx.Context(x, 8)
+        one.set_walkers(R[i * 8:(i + 1) * 8, :x.n_elec])
+        _close(F[i, :x.n_atom], one.forces(), rel=1e-10)
