@@ -947,7 +947,8 @@ __device__ void block_accept(const DevCtx &c, int w, int t, int i, int sp, int m
         if (b == m) continue;
         T *row = Gb + b * NP;
         double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
-#pragma unroll 4
+        // deep unroll: more of the row's loads in flight per round trip
+#pragma unroll 16
         for (int j = 0; j < NP; j += 4) {
           z0 += (double)aold_w[j] * (double)row[j];
           z1 += (double)aold_w[j + 1] * (double)row[j + 1];
@@ -957,7 +958,7 @@ __device__ void block_accept(const DevCtx &c, int w, int t, int i, int sp, int m
         const double z = (z0 + z1) + (z2 + z3);
         if (b > m) {
           const T f = (T)(z * irho);
-#pragma unroll 8
+#pragma unroll 16
           for (int j = 0; j < NP; ++j) row[j] -= f * colm_w[j];
         } else {
           crow_w[b] = (T)z;  // C[m][b] = Delta_m . u_b
