@@ -595,6 +595,9 @@ dmcx_status setup_msd(dmcx_ctx *c, const dmcx_system &s, const std::vector<int> 
   M.on = 1;
   M.n_det = s.n_det;
   M.nv = (int)vmo.size();
+  // the sweep keeps q and grad q of every walker in its basis-tile buffers
+  if (TW * 4 * M.nv > 2 * 4 * stage_ksteps(c->NOB) * NCOL)
+    return fail(c, DMCX_E_UNSUPPORTED, "too many virtual orbitals for this orbital-tile width");
   M.ldt = std::max(4, (M.nv + 3) / 4 * 4);
   auto slot = [&](int mo) { return (int)(std::lower_bound(vmo.begin(), vmo.end(), mo) - vmo.begin()); };
   std::vector<int4> dexc(2 * (size_t)s.n_det), lst[2];

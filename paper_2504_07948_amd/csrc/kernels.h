@@ -52,10 +52,23 @@ static __device__ unsigned long long g_phase_cycles[16];
 #define PHASE_END() do {} while (0)
 #endif
 
-constexpr int TW = 8;        // walkers (or points) per workgroup tile
-constexpr int NCOL = 48;     // 5 VGL rows x 8 walkers = 40 MFMA columns, padded to 3 x 16
-constexpr int NT_TILE = 512; // tile kernels: 8 waves
-constexpr int NW_TILE = NT_TILE / 64;
+// Walkers (or points) per workgroup tile: 8 (one workgroup of 8 waves per
+// CU at 2048 walkers) or 4 (two workgroups of 4 waves per CU, whose
+// latency-bound per-walker phases overlap each other's orbital tiles).
+#ifndef DMCX_TW
+#define DMCX_TW 8
+#endif
+constexpr int TW = DMCX_TW;
+static_assert(TW == 4 || TW == 8, "tile width");
+constexpr int NVALID = 5 * TW;              // MFMA columns in use: 5 VGL rows per walker
+constexpr int NCB = (NVALID + 15) / 16;     // 16-column MFMA blocks (3 or 2)
+constexpr int NCOL = 16 * NCB;              // padded column count (48 or 32)
+constexpr int NT_TILE = 64 * TW;            // tile kernels: one wave per walker
+constexpr int NW_TILE = TW;
+constexpr int NKH = NW_TILE / 4;            // K-parity groups of the orbital tile (2 or 1)
+// Tile kernels keep two waves per SIMD (at most 256 registers per lane), so
+// that two four-wave workgroups can share a CU.
+#define DMCX_TILE_KERNEL __global__ __launch_bounds__(NT_TILE) __attribute__((amdgpu_waves_per_eu(2)))
 constexpr int NT_AUX = 256;  // per-walker kernels (inverse, local energy)
 constexpr int KMAX = 64;         // largest delay rank
 constexpr int MSD_NV_MAX = 144;  // virtual orbitals of a multideterminant expansion
@@ -63,7 +76,9 @@ constexpr int MSD_NV_MAX = 144;  // virtual orbitals of a multideterminant expan
 // K-steps (4 basis functions each) per LDS stage of the orbital tile; the
 // LCAO operands of a stage are held in registers, so wider orbital tiles use
 // shorter stages.
-__host__ __device__ constexpr int stage_ksteps(int nob) { return nob <= 4 ? 24 : 12; }
+__host__ __device__ constexpr int stage_ksteps(int nob) {
+  return NKH == 2 ? (nob <= 4 ? 24 : 12) : (nob <= 4 ? 12 : 6);
+}
 
 // Basis work of one shell is split into this many lane tasks (s: whole
 // shell; p: components {x, y} and {z}; d: pairs of the six components).
@@ -257,7 +272,7 @@ __device__ void basis_stage_t(const BasisLDS &B, int g_begin, int g_end, int fn_
   const int ntask = TW * nsh * SPLIT;
   for (int task = vt; task < ntask; task += nvt) {
     const int w = task & (TW - 1);
-    const int rest = task >> 3;
+    const int rest = task / TW;
     const int sl = rest % nsh, part = rest / nsh;
     const int g = g_begin + (sl >> 2), s = sl & 3;
     const int4 gi = B.ginfo[g];
@@ -341,8 +356,8 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // LCAO operands of one stage for this wave's orbital blocks and K-parity
-// half kh (A operand; lane l holds C[f0 + 4 kk + l/16][ob*16 + l%16] for
-// K-steps kk = 2 i + kh).
+// group kh (A operand; lane l holds C[f0 + 4 kk + l/16][ob*16 + l%16] for
+// K-steps kk = NKH i + kh).
 template <typename T, int NOB, int KH>
 __device__ __forceinline__ void load_stage_a(const T *Cp, int fn_begin, int nk, int ob0, int kh,
                                              int kq, int col, T (&a)[(NOB + 3) / 4][KH]) {
@@ -354,8 +369,8 @@ __device__ __forceinline__ void load_stage_a(const T *Cp, int fn_begin, int nk, 
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int ob = ob0 + 4 * q;
-      a[q][i] = (2 * i + kh < nk && (NOB % 4 == 0 || ob < NOB))
-                    ? abase[(size_t)(8 * i) * NP + ob * 16]
+      a[q][i] = (NKH * i + kh < nk && (NOB % 4 == 0 || ob < NOB))
+                    ? abase[(size_t)(4 * NKH * i) * NP + ob * 16]
                     : (T)0;
     }
 }
@@ -363,29 +378,31 @@ __device__ __forceinline__ void load_stage_a(const T *Cp, int fn_begin, int nk, 
 // This wave's K-steps of one stage: acc[q][cb] += A(block) * B(column block).
 // B operands come from LDS one K-step ahead of the MFMAs that use them.
 template <typename T, int NOB, int KH>
-__device__ __forceinline__ void mfma_stage(typename Acc4<T>::type (&acc)[(NOB + 3) / 4][3],
+__device__ __forceinline__ void mfma_stage(typename Acc4<T>::type (&acc)[(NOB + 3) / 4][NCB],
                                            const T (&a)[(NOB + 3) / 4][KH], const T *Bsb, int nk,
                                            int ob0, int kh, int kq, int col) {
   constexpr int NQ = (NOB + 3) / 4;
   if (kh >= nk) return;
   const T *bbase = Bsb + (4 * kh + kq) * NCOL + col;
-  T bn0 = bbase[0], bn1 = bbase[16], bn2 = bbase[32];
+  T bn[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) bn[cb] = bbase[16 * cb];
 #pragma unroll
   for (int i = 0; i < KH; ++i) {
-    if (2 * i + kh < nk) {
-      const T b0 = bn0, b1 = bn1, b2 = bn2;
-      if (2 * i + 2 + kh < nk) {
-        const T *brow = bbase + 8 * (i + 1) * NCOL;
-        bn0 = brow[0];
-        bn1 = brow[16];
-        bn2 = brow[32];
+    if (NKH * i + kh < nk) {
+      T b[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) b[cb] = bn[cb];
+      if (NKH * (i + 1) + kh < nk) {
+        const T *brow = bbase + 4 * NKH * (i + 1) * NCOL;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) bn[cb] = brow[16 * cb];
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         if (NOB % 4 == 0 || ob0 + 4 * q < NOB) {
-          acc[q][0] = mfma16x16x4(a[q][i], b0, acc[q][0]);
-          acc[q][1] = mfma16x16x4(a[q][i], b1, acc[q][1]);
-          acc[q][2] = mfma16x16x4(a[q][i], b2, acc[q][2]);
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) acc[q][cb] = mfma16x16x4(a[q][i], b[cb], acc[q][cb]);
         }
       }
     }
@@ -395,7 +412,8 @@ __device__ __forceinline__ void mfma_stage(typename Acc4<T>::type (&acc)[(NOB + 
 // Orbital VGL of the tile's TW points: out[w][q][orbital] (LDS, precision T).
 // All NT_TILE threads must call.  Stages of basis functions flow through two
 // LDS buffers: in each phase every wave runs its MFMAs on stage s (wave w
-// owns orbital blocks w%4 (+4, ...) and the K-steps of parity w/4) and then
+// owns orbital blocks w%4 (+4, ...) and the K-steps of parity w/4 when there
+// are eight waves, all K-steps when there are four) and then
 // all 512 threads evaluate the basis of stage s+1 into the other buffer;
 // the LCAO operands of stage s+1 are loaded into registers right after the
 // MFMAs of stage s are issued, so they arrive during the basis evaluation
@@ -407,7 +425,7 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
   constexpr int NQ = (NOB + 3) / 4;
   constexpr int NP = NOB * 16;
   constexpr int KS = stage_ksteps(NOB);
-  constexpr int KH = KS / 2;
+  constexpr int KH = KS / NKH;
   constexpr int FM = 4 * KS;
   typedef typename Acc4<T>::type acc_t;
   const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
@@ -416,11 +434,11 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
   const int S = c.B.n_stage;
   const T *Cp;
   if constexpr (sizeof(T) == 8) Cp = (const T *)c.B.Cp; else Cp = (const T *)c.B.Cp32;
-  acc_t acc[NQ][3];
+  acc_t acc[NQ][NCB];
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
-    for (int cb = 0; cb < 3; ++cb) acc[q][cb] = acc_t{0, 0, 0, 0};
+    for (int cb = 0; cb < NCB; ++cb) acc[q][cb] = acc_t{0, 0, 0, 0};
   T a0[NQ][KH], a1[NQ][KH];
   int g0, g1, fb, nk;
   auto stage_range = [&](int s) {
@@ -433,9 +451,10 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
   };
   stage_range(0);
   load_stage_a<T, NOB, KH>(Cp, fb, nk, ob0, kh, kq, col, a0);
-  for (int i = tid; i < FM * (NCOL - 40); i += NT_TILE) {
-    Bs0[(i >> 3) * NCOL + 40 + (i & 7)] = (T)0;
-    Bs1[(i >> 3) * NCOL + 40 + (i & 7)] = (T)0;
+  constexpr int NPADC = NCOL - NVALID;  // padding columns, zero for every stage
+  for (int i = tid; i < FM * NPADC; i += NT_TILE) {
+    Bs0[(i / NPADC) * NCOL + NVALID + i % NPADC] = (T)0;
+    Bs1[(i / NPADC) * NCOL + NVALID + i % NPADC] = (T)0;
   }
   basis_stage<T>(BL, g0, g1, fb, pts, Bs0, tid, NT_TILE);
   lds_barrier();
@@ -470,22 +489,22 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
       lds_barrier();
     }
   }
-  // sum the two K-parity halves into out
+  // sum the K-parity partial results into out
 #pragma unroll
-  for (int half = 1; half >= 0; --half) {
+  for (int half = NKH - 1; half >= 0; --half) {
     if (kh == half) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int ob = ob0 + 4 * q;
         if (NOB % 4 == 0 || ob < NOB) {
 #pragma unroll
-          for (int cb = 0; cb < 3; ++cb) {
+          for (int cb = 0; cb < NCB; ++cb) {
             const int n = cb * 16 + col;
-            if (n < 40) {
+            if (n < NVALID) {
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 T *o = out + n * NP + ob * 16 + Acc4<T>::row(kq, r);
-                *o = (half ? (T)0 : *o) + (T)acc[q][cb][r];
+                *o = (half == NKH - 1 ? (T)0 : *o) + (T)acc[q][cb][r];
               }
             }
           }
@@ -1280,14 +1299,14 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
 // null) receives the accept decisions at
 // acc_log[s_in_run * acc_step_stride + w * acc_w_stride + i].
 template <typename T, int NOB>
-__global__ __launch_bounds__(NT_TILE) void k_sweep(DevCtx c, uint8_t *acc_log,
+DMCX_TILE_KERNEL void k_sweep(DevCtx c, uint8_t *acc_log,
                                                     long long acc_step_stride, int acc_w_stride) {
   sweep_body<T, NOB, false>(c, acc_log, acc_step_stride, acc_w_stride);
 }
 
 // The same sweep for a multideterminant trial function (table method).
 template <typename T, int NOB>
-__global__ __launch_bounds__(NT_TILE) void k_sweep_msd(DevCtx c, uint8_t *acc_log,
+DMCX_TILE_KERNEL void k_sweep_msd(DevCtx c, uint8_t *acc_log,
                                                         long long acc_step_stride, int acc_w_stride) {
   sweep_body<T, NOB, true>(c, acc_log, acc_step_stride, acc_w_stride);
 }
