@@ -259,10 +259,13 @@ dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, const std::vector<int>
   // stages: consecutive groups of one (l, nprim) type, at most fmax functions
   std::vector<int2> stages;
   int g = 0;
-  const int fmax = 4 * stage_ksteps(c->NOB);
+  // stage depth of this context's sweep kernel (shallower for the FP32
+  // single-determinant sweep, two workgroups per CU)
+  const int ks = c->mixed && s.n_det <= 1 ? stage_ksteps_w4(c->NOB) : stage_ksteps(c->NOB);
+  const int fmax = 4 * ks;
   while (g < n_group) {
     int g1 = g, f = 0;
-    const int gmax = stage_max_groups(ginfo[g].x, c->NOB);
+    const int gmax = stage_max_groups(ginfo[g].x, ks);
     while (g1 < n_group && ginfo[g1].x == ginfo[g].x && ginfo[g1].y == ginfo[g].y &&
            f + 4 * NCART_[ginfo[g1].x] <= fmax && g1 - g < gmax) {
       f += 4 * NCART_[ginfo[g1].x];

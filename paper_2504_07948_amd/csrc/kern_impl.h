@@ -43,19 +43,33 @@ void NobLaunch<T>::orbitals_at(int nob, const DevCtx &c, const double *pos, int 
 template <typename T>
 void NobLaunch<T>::sweep(int nob, const DevCtx &c, uint8_t *acc, long long acc_ss, int acc_ws,
                          size_t lds, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+#define DMCX_CALL(N)                                                                   \
+  allow_lds(k_sweep_w4<T, N>, lds);                                                    \
+  k_sweep_w4<T, N><<<dim3(c.Wpad / TW), dim3(NT_TILE), lds, s>>>(c, acc, acc_ss, acc_ws)
+    DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+  } else {
 #define DMCX_CALL(N)                                                                   \
   allow_lds(k_sweep<T, N>, lds);                                                       \
   k_sweep<T, N><<<dim3(c.Wpad / TW), dim3(NT_TILE), lds, s>>>(c, acc, acc_ss, acc_ws)
-  DMCX_NOB_SWITCH(nob, DMCX_CALL)
+    DMCX_NOB_SWITCH(nob, DMCX_CALL)
 #undef DMCX_CALL
+  }
 }
 
 template <typename T>
 size_t NobLaunch<T>::sweep_lds(int nob) {
   hipFuncAttributes a{};
-#define DMCX_CALL(N) (void)hipFuncGetAttributes(&a, (const void *)k_sweep<T, N>)
-  DMCX_NOB_SWITCH(nob, DMCX_CALL)
+  if constexpr (sizeof(T) == 4) {
+#define DMCX_CALL(N) (void)hipFuncGetAttributes(&a, (const void *)k_sweep_w4<T, N>)
+    DMCX_NOB_SWITCH(nob, DMCX_CALL)
 #undef DMCX_CALL
+  } else {
+#define DMCX_CALL(N) (void)hipFuncGetAttributes(&a, (const void *)k_sweep<T, N>)
+    DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+  }
   return a.sharedSizeBytes;
 }
 

@@ -69,13 +69,21 @@ constexpr int NKH = NW_TILE / 4;            // K-parity groups of the orbital ti
 // Tile kernels keep two waves per SIMD (at most 256 registers per lane), so
 // that two four-wave workgroups can share a CU.
 #define DMCX_TILE_KERNEL __global__ __launch_bounds__(NT_TILE) __attribute__((amdgpu_waves_per_eu(2)))
+// The FP32 single-determinant sweep: four waves per SIMD (128 registers,
+// some spilled) and half-depth basis stages (half the LDS), so two 8-walker
+// workgroups share a CU and one's latency-bound per-walker phases overlap
+// the other's orbital tile.
+#define DMCX_TILE_KERNEL_W4 \
+  __global__ __launch_bounds__(NT_TILE) __attribute__((amdgpu_waves_per_eu(4)))
 constexpr int NT_AUX = 256;  // per-walker kernels (inverse, local energy)
 constexpr int KMAX = 64;         // largest delay rank
 constexpr int MSD_NV_MAX = 144;  // virtual orbitals of a multideterminant expansion
 
 // K-steps (4 basis functions each) per LDS stage of the orbital tile; the
 // LCAO operands of a stage are held in registers, so wider orbital tiles use
-// shorter stages.
+// shorter stages.  This is the capacity every kernel sizes its buffers for;
+// a context packs its stages for its sweep kernel (stage_ksteps, or half of
+// it for the FP32 single-determinant sweep), never deeper.
 __host__ __device__ constexpr int stage_ksteps(int nob) {
   return NKH == 2 ? (nob <= 4 ? 24 : 12) : (nob <= 4 ? 12 : 6);
 }
@@ -87,10 +95,13 @@ __host__ __device__ constexpr int shell_split(int l) { return l == 0 ? 1 : (l ==
 // Largest number of 4-shell groups of angular momentum l in one stage, so
 // that a stage has at most one basis task per thread and fits the stage's
 // register-held LCAO operands.
-__host__ __device__ constexpr int stage_max_groups(int l, int nob) {
-  return (NT_TILE / (TW * 4 * shell_split(l))) < (stage_ksteps(nob) / (l == 0 ? 1 : (l == 1 ? 3 : 6)))
+__host__ __device__ constexpr int stage_ksteps_w4(int nob) { return stage_ksteps(nob) / 2; }
+// groups of one (l, nprim) type per stage of ks K-steps (every task of a
+// stage gets a thread of its own)
+__host__ __device__ constexpr int stage_max_groups(int l, int ks) {
+  return (NT_TILE / (TW * 4 * shell_split(l))) < (ks / (l == 0 ? 1 : (l == 1 ? 3 : 6)))
              ? (NT_TILE / (TW * 4 * shell_split(l)))
-             : (stage_ksteps(nob) / (l == 0 ? 1 : (l == 1 ? 3 : 6)));
+             : (ks / (l == 0 ? 1 : (l == 1 ? 3 : 6)));
 }
 
 struct DevBasis {
@@ -419,12 +430,11 @@ __device__ __forceinline__ void mfma_stage(typename Acc4<T>::type (&acc)[(NOB + 
 // MFMAs of stage s are issued, so they arrive during the basis evaluation
 // and the barrier.  One barrier per stage; the two K-parity partial sums
 // are added once at the end.
-template <typename T, int NOB>
+template <typename T, int NOB, int KS = stage_ksteps(NOB)>
 __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)[3], T *Bs0,
                         T *Bs1, T *out) {
   constexpr int NQ = (NOB + 3) / 4;
   constexpr int NP = NOB * 16;
-  constexpr int KS = stage_ksteps(NOB);
   constexpr int KH = KS / NKH;
   constexpr int FM = 4 * KS;
   typedef typename Acc4<T>::type acc_t;
@@ -1041,11 +1051,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 // with q = 0 gives grad_i T_hv = g_hi w_v, w = grad m_i - T^T grad a_i.
 // The full ratio is rho_0 S'/S e^{dJ}; the drift adds grad S / S.  An
 // accepted move applies T += g_i q^T and keeps the new R_d^s and S.
-template <typename T, int NOB, bool MSD>
+template <typename T, int NOB, bool MSD, int KS = stage_ksteps(NOB)>
 __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
                                            long long acc_step_stride, int acc_w_stride) {
   constexpr int NP = NOB * 16;
-  constexpr int FM = 4 * stage_ksteps(NOB);
+  constexpr int FM = 4 * KS;
   extern __shared__ __align__(16) char smem_basis[];
   const BasisLDS BL = stage_basis_lds(c.B, smem_basis);
   __shared__ T Bs[2 * FM * NCOL];  // basis tiles; MSD scratch between tiles
@@ -1169,7 +1179,7 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
     __syncthreads();
     PHASE_MARK(1);
     // ---- P2: orbitals at the proposed positions (MFMA)
-    mo_tile<T, NOB>(c, BL, pts, Bs0, Bs1, vnew);
+    mo_tile<T, NOB, KS>(c, BL, pts, Bs0, Bs1, vnew);
     PHASE_MARK(2);
     // ---- P3: ratio, new drift, Metropolis-Hastings decision
     const T *vw = vnew + ws * 5 * NP;
@@ -1302,6 +1312,13 @@ template <typename T, int NOB>
 DMCX_TILE_KERNEL void k_sweep(DevCtx c, uint8_t *acc_log,
                                                     long long acc_step_stride, int acc_w_stride) {
   sweep_body<T, NOB, false>(c, acc_log, acc_step_stride, acc_w_stride);
+}
+
+// The FP32 single-determinant sweep (two workgroups per CU).
+template <typename T, int NOB>
+DMCX_TILE_KERNEL_W4 void k_sweep_w4(DevCtx c, uint8_t *acc_log, long long acc_step_stride,
+                                    int acc_w_stride) {
+  sweep_body<T, NOB, false, stage_ksteps_w4(NOB)>(c, acc_log, acc_step_stride, acc_w_stride);
 }
 
 // The same sweep for a multideterminant trial function (table method).
