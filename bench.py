@@ -198,7 +198,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--skip-extras", action="store_true",
-                    help="only the FP64 leg (no mixed-precision and forces legs)")
+                    help="only the FP64 leg (same as --extras none)")
+    ap.add_argument("--extras", default="mixed,forces,batch",
+                    help="comma list of the extra legs to run after the FP64 leg: mixed, forces, "
+                         "batch (eight multideterminant alkanes), or none")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed region, run one device copy of this many MiB "
                          "(a known-size kernel for scaling FETCH_SIZE/WRITE_SIZE counters)")
@@ -214,7 +217,7 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
-    s = synth.make_system(2)
+    s = synth.large_molecule()
     W = args.walkers
     R0 = synth.make_walkers(s, W, 2025)
     prec = dmcx.DMCX_FP64 if args.precision == "fp64" else dmcx.DMCX_MIXED
@@ -242,9 +245,15 @@ def main():
     flags = ctx.walker_flags()
 
     mixed = forces = batch5 = None
-    if not args.skip_extras:
+    extras = set() if args.skip_extras else set(args.extras.split(",")) - {"none", ""}
+    unknown = extras - {"mixed", "forces", "batch"}
+    if unknown:
+        sys.exit(f"bench.py: unknown extra legs {sorted(unknown)}")
+    if "mixed" in extras:
         mixed = mixed_leg(s, torch, dmcx, stream, args)
+    if "forces" in extras:
         forces = forces_leg(s, torch, dmcx, stream, args)
+    if "batch" in extras:
         batch5 = batch5_leg(torch, dmcx, stream)
 
     ne, ns = s.n_elec, max(s.n_up, s.n_dn)

@@ -138,31 +138,39 @@ def _orthonormal_mos(rng, n_basis, n_mo):
     return q * s[None, :]
 
 
-def make_system(cfg: int) -> System:
-    """Synthetic systems standing in for the paper's molecules.
-
-    cfg 1: 4 ions, Z=2, uniform in a 6 bohr box (min spacing 1.0), 8 e,
-           per atom 4s + 2p single-primitive shells, alpha log-U[0.2, 20].
-    cfg 2: 64 ions (16 with Z_eff=4, 48 with Z=1) in a 16 bohr cube, min
-           spacing 1.5 bohr C-C and 1.1 bohr otherwise, 112 e;
-           "C" 4s4p2d, "H" 3s1p1d, three primitives per shell,
-           alpha log-U[0.05, 50]  -> 1024 Cartesian functions, 400 shells.
-    """
-    ss = np.random.SeedSequence(BASE_SEED + cfg)
+def small_molecule() -> System:
+    """4 ions, Z=2, uniform in a 6 bohr box (min spacing 1.0), 8 e (4/4),
+    per atom 4s + 2p single-primitive shells, alpha log-U[0.2, 20] (40
+    functions), 4 MOs per spin; Pade b_ee = 1.0, b_en = 0.8."""
+    ss = np.random.SeedSequence(BASE_SEED + 1)
     s_geo, s_bas, s_mo = [np.random.default_rng(s) for s in ss.spawn(3)]
-    if cfg == 1:
-        xyz = _place_ions(s_geo, 4, 6.0, lambda i, j: 1.0)
-        z = np.full(4, 2.0)
-        sa, sl, sn, al, co = _shells_for(s_bas, [[0, 0, 0, 0, 1, 1]] * 4, 0.2, 20.0, 1)
-        nb = int(sum(NCART[l] for l in sl))
-        mo = _orthonormal_mos(s_mo, nb, 4)
-        return System("cfg1", xyz, z, sa, sl, sn, al, co, mo, 4, 4, jee_b=1.0, jen_b=0.8)
-    if cfg in (2, 3, 4):
-        return _cfg2_system()
-    raise ValueError(f"unknown config {cfg}")
+    xyz = _place_ions(s_geo, 4, 6.0, lambda i, j: 1.0)
+    z = np.full(4, 2.0)
+    sa, sl, sn, al, co = _shells_for(s_bas, [[0, 0, 0, 0, 1, 1]] * 4, 0.2, 20.0, 1)
+    nb = int(sum(NCART[l] for l in sl))
+    mo = _orthonormal_mos(s_mo, nb, 4)
+    return System("small-4ion-8e", xyz, z, sa, sl, sn, al, co, mo, 4, 4, jee_b=1.0, jen_b=0.8)
 
 
-def _cfg2_system() -> System:
+def molecule(name: str) -> System:
+    """The two synthetic molecules by name: "small" (8 electrons, 40
+    functions) or "large" (112 electrons, 1024 functions)."""
+    if name == "small":
+        return small_molecule()
+    if name == "large":
+        return large_molecule()
+    raise ValueError(f"unknown molecule {name!r}")
+
+
+# per-molecule offsets of the seeds the tests and benchmark draw walkers with
+SEED_OFFSET = {"small": 1, "large": 2}
+
+
+def large_molecule() -> System:
+    """64 ions (16 "C" with Z_eff = 4, 48 H) in a 16 bohr cube, min spacing
+    1.5 bohr C-C and 1.1 bohr otherwise, 112 e (56/56); "C" 4s4p2d, "H"
+    3s1p1d, three primitives per shell, alpha log-U[0.05, 50] -> 400 shells,
+    1200 primitives, 1024 Cartesian functions; 56 MOs per spin."""
     ss = np.random.SeedSequence(BASE_SEED + 2)
     s_geo, s_bas, s_mo = [np.random.default_rng(s) for s in ss.spawn(3)]
     n_c, n_h = 16, 48
@@ -179,7 +187,7 @@ def _cfg2_system() -> System:
         s_bas, [c_sh if k == 0 else h_sh for k in kind], 0.05, 50.0, 3)
     nb = int(sum(NCART[l] for l in sl))
     mo = _orthonormal_mos(s_mo, nb, 56)
-    return System("cfg2", xyz, z, sa, sl, sn, al, co, mo, 56, 56, jee_b=1.0, jen_b=0.8)
+    return System("large-64ion-112e", xyz, z, sa, sl, sn, al, co, mo, 56, 56, jee_b=1.0, jen_b=0.8)
 
 
 def make_walkers(sys: System, n_walkers: int, seed: int, sigma: float = 0.6) -> np.ndarray:
@@ -309,7 +317,7 @@ def make_msd(sys: System, n_det: int, n_active: int, seed: int,
 
 def alkane(n_c: int, seed: int) -> System:
     """C_nH_(2n+2) stand-in: a zig-zag carbon chain (1.54 bohr-scaled steps)
-    with hydrogens placed around it; Z_eff = 4 for C, basis as in cfg 2."""
+    with hydrogens placed around it; Z_eff = 4 for C, basis as in the large molecule."""
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(1)[0])
     bond = 2.9  # bohr
     cpos = []

@@ -27,10 +27,10 @@ def _close(a, b, rel=1e-10, floor=1.0):
 
 def _group_systems():
     """Three systems with 8, 6 and 112 electrons (uneven shapes, ragged walkers)."""
-    return [synth.make_system(1),
+    return [synth.small_molecule(),
             synth.small_random_system(71, n_atom=3, n_up=3, n_dn=3, shells=(0, 0, 1, 2),
                                       nprim=3, charge=2.0),
-            synth.make_system(2)], [13, 21, 9]
+            synth.large_molecule()], [13, 21, 9]
 
 
 def _pad(R, ne_max):
@@ -39,16 +39,16 @@ def _pad(R, ne_max):
     return out
 
 
-@pytest.mark.parametrize("cfg,W,P", [(1, 24, 3), (2, 11, 2)])
-def test_graph_matches_eager(cfg, W, P):
+@pytest.mark.parametrize("mol,W,P", [("small", 24, 3), ("large", 11, 2)])
+def test_graph_matches_eager(mol, W, P):
     """Replays of the captured step graph reproduce eager steps bit for bit,
     with eager work (a measure) between replays and a recompute period that
     the graph's kernels decide from the device step counter."""
-    s = synth.make_system(cfg)
-    R = synth.make_walkers(s, W, 700 + cfg)
+    s = synth.molecule(mol)
+    R = synth.make_walkers(s, W, 700 + synth.SEED_OFFSET[mol])
     out = {}
     for graph in (False, True):
-        print(f"[batching] cfg{cfg} W={W} P={P} graph={graph}", flush=True)
+        print(f"[batching] {mol} W={W} P={P} graph={graph}", flush=True)
         ctx = dmcx.Context(s, W, delay_rank=8, recompute_period=P, seed=5, graph=graph)
         ctx.set_walkers(R)
         a1, e1 = ctx.run(2, mode=dmcx.DMCX_DMC, e_trial=-10.0, logs=True)
@@ -67,7 +67,7 @@ def test_graph_matches_eager(cfg, W, P):
 
 def test_graph_device_logs():
     torch = pytest.importorskip("torch")
-    s = synth.make_system(1)
+    s = synth.small_molecule()
     W = 16
     R = synth.make_walkers(s, W, 710)
     res = []
@@ -154,7 +154,7 @@ def test_group_rejects_move_by_move_calls():
 
 
 def test_autotuner_picks_a_candidate_and_preserves_the_run():
-    s = synth.make_system(2)
+    s = synth.large_molecule()
     W = 16
     R = synth.make_walkers(s, W, 760)
     ctx = dmcx.Context(s, W, delay_rank=0, recompute_period=64, seed=13)

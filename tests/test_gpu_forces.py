@@ -19,10 +19,10 @@ def _close(a, b, rel=1e-10, floor=1.0):
                            f"{(np.abs(a - b) / np.maximum(np.abs(b), floor)).max():.3e}")
 
 
-@pytest.mark.parametrize("cfg,W", [(1, 16), (2, 9)])
-def test_ion_grads_match_oracle_forward_mode(cfg, W):
-    s = synth.make_system(cfg)
-    R = synth.make_walkers(s, W, 500 + cfg)
+@pytest.mark.parametrize("mol,W", [("small", 16), ("large", 9)])
+def test_ion_grads_match_oracle_forward_mode(mol, W):
+    s = synth.molecule(mol)
+    R = synth.make_walkers(s, W, 500 + synth.SEED_OFFSET[mol])
     ctx = dmcx.Context(s, W)
     ctx.set_walkers(R)
     dl, dv = ctx.ion_grads()
@@ -34,7 +34,7 @@ def test_ion_grads_match_oracle_forward_mode(cfg, W):
 
 def test_ion_grads_after_moves_match_oracle():
     """Gradients use the delayed-updated inverse after a DMC step."""
-    s = synth.make_system(2)
+    s = synth.large_molecule()
     W = 8
     R = synth.make_walkers(s, W, 510)
     ctx = dmcx.Context(s, W, delay_rank=32, recompute_period=100)
@@ -48,7 +48,7 @@ def test_ion_grads_after_moves_match_oracle():
 
 
 def test_ion_grads_vs_finite_differences():
-    s = synth.make_system(1)
+    s = synth.small_molecule()
     W = 8
     R = synth.make_walkers(s, W, 520)
     ctx = dmcx.Context(s, W)
@@ -79,7 +79,7 @@ def test_ion_grads_vs_finite_differences():
 
 def test_translation_sum_rule():
     """sum_A dlnPsi/dR_A = -sum_i grad_i lnPsi (the oracle's drift)."""
-    s = synth.make_system(1)
+    s = synth.small_molecule()
     W = 4
     R = synth.make_walkers(s, W, 530)
     ctx = dmcx.Context(s, W)
@@ -91,7 +91,7 @@ def test_translation_sum_rule():
 
 
 def test_vjps_and_force_estimator():
-    s = synth.make_system(1)
+    s = synth.small_molecule()
     W = 24
     R = synth.make_walkers(s, W, 540)
     lw = np.random.default_rng(0).normal(0, 0.3, W)
@@ -112,7 +112,7 @@ def test_vjps_and_force_estimator():
 def test_autograd_function_matches_vjp():
     torch = pytest.importorskip("torch")
     from paper_2504_07948_amd.autograd import IonGradFn, force_objective
-    s = synth.make_system(1)
+    s = synth.small_molecule()
     W = 16
     R = synth.make_walkers(s, W, 550)
     ctx = dmcx.Context(s, W)

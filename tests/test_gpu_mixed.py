@@ -24,17 +24,17 @@ def _report(name, x):
     print(f"[mixed] {name}: max {np.max(np.abs(x)):.3e} rms {np.sqrt(np.mean(np.square(x))):.3e}")
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
-def test_mixed_orbitals(cfg):
-    s = synth.make_system(cfg)
+@pytest.mark.parametrize("mol", ["small", "large"])
+def test_mixed_orbitals(mol):
+    s = synth.molecule(mol)
     W = 16
-    R = synth.make_walkers(s, W, 600 + cfg)
+    R = synth.make_walkers(s, W, 600 + synth.SEED_OFFSET[mol])
     ctx = dmcx.Context(s, W, precision=dmcx.DMCX_MIXED)
     ctx.set_walkers(R)
     got = ctx.eval_orbitals(0, R[:, 0, :])
     ref = np.array([oracle.orbitals_vgl(s, p, s.n_up) for p in R[:, 0, :]])
     err = (got - ref) / np.abs(ref).max(axis=(0, 2), keepdims=True)
-    _report(f"cfg{cfg} orbital VGL (rel. to row max)", err)
+    _report(f"{mol} orbital VGL (rel. to row max)", err)
     assert np.abs(err).max() <= 1e-5
 
 
@@ -51,7 +51,7 @@ def _conds(s, R):
 
 def test_mixed_replay_energy_error():
     """Config-2 system, identical configurations: FP32 orbitals + FP64 LU."""
-    s = synth.make_system(2)
+    s = synth.large_molecule()
     W = 64
     R = synth.make_walkers(s, W, 610)
     ctx = dmcx.Context(s, W, precision=dmcx.DMCX_MIXED)
@@ -78,7 +78,7 @@ def test_mixed_steps_energy_error():
     """After DMC steps with FP32 delayed updates (recompute every 32 steps,
     so the inverses carry FP32 rank-k updates): compare at the GPU's own
     configurations."""
-    s = synth.make_system(2)
+    s = synth.large_molecule()
     W = 32
     R = synth.make_walkers(s, W, 620)
     ctx = dmcx.Context(s, W, precision=dmcx.DMCX_MIXED, delay_rank=32, recompute_period=32)
@@ -100,7 +100,7 @@ def test_mixed_steps_energy_error():
 
 
 def test_mixed_ion_grads():
-    s = synth.make_system(2)
+    s = synth.large_molecule()
     W = 8
     R = synth.make_walkers(s, W, 630)
     ctx = dmcx.Context(s, W, precision=dmcx.DMCX_MIXED)

@@ -11,18 +11,18 @@ from paper_2504_07948_amd import dmcx, synth
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("cfg,k", [(1, 1), (1, 3), (2, 32), (2, 8)])
-def test_moves_match_brute_force(cfg, k):
-    s = synth.make_system(cfg)
+@pytest.mark.parametrize("mol,k", [("small", 1), ("small", 3), ("large", 32), ("large", 8)])
+def test_moves_match_brute_force(mol, k):
+    s = synth.molecule(mol)
     W = 9
-    rng = np.random.default_rng(700 + cfg + k)
-    R = synth.make_walkers(s, W, 700 + cfg)
+    rng = np.random.default_rng(700 + synth.SEED_OFFSET[mol] + k)
+    R = synth.make_walkers(s, W, 700 + synth.SEED_OFFSET[mol])
     ctx = dmcx.Context(s, W, delay_rank=k, recompute_period=1000)
     ctx.set_walkers(R)
     cur = R.copy()
     # electrons in sweep order for the small system; a slice crossing the
     # spin boundary and a block boundary for the large one
-    elecs = list(range(s.n_elec)) if cfg == 1 else list(range(s.n_up - 40, s.n_up + 6))
+    elecs = list(range(s.n_elec)) if mol == "small" else list(range(s.n_up - 40, s.n_up + 6))
     for i in elecs:
         r_new = cur[:, i, :] + 0.3 * rng.standard_normal((W, 3))
         ratio, grad = ctx.ratio_grad(i, r_new)
@@ -48,7 +48,7 @@ def test_moves_match_brute_force(cfg, k):
 
 
 def test_accept_requires_ratio_grad():
-    s = synth.make_system(1)
+    s = synth.small_molecule()
     ctx = dmcx.Context(s, 4)
     ctx.set_walkers(synth.make_walkers(s, 4, 1))
     with pytest.raises(dmcx.DmcxError) as e:
@@ -65,7 +65,7 @@ def test_accept_requires_ratio_grad():
 def test_run_after_moves_matches_oracle():
     """A manual partial sweep followed by dmcx_run: pending updates are
     flushed and the run continues from the moved configuration."""
-    s = synth.make_system(1)
+    s = synth.small_molecule()
     W = 8
     R = synth.make_walkers(s, W, 710)
     ctx = dmcx.Context(s, W, delay_rank=2, recompute_period=100, seed=5)

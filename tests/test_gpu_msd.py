@@ -67,17 +67,17 @@ def _close_conditioned(a, b, s, R, label, rel=1e-10):
     assert np.all(err <= rel * amp)
 
 
-def _msd_cfg1(n_det=30, n_active=12):
-    return synth.make_msd(synth.make_system(1), n_det, n_active, 901)
+def _msd_small(n_det=30, n_active=12):
+    return synth.make_msd(synth.small_molecule(), n_det, n_active, 901)
 
 
-def _msd_cfg2(n_det=120, n_active=40):
-    return synth.make_msd(synth.make_system(2), n_det, n_active, 902)
+def _msd_large(n_det=120, n_active=40):
+    return synth.make_msd(synth.large_molecule(), n_det, n_active, 902)
 
 
-@pytest.mark.parametrize("which,W", [("cfg1", 13), ("cfg2", 5)])
+@pytest.mark.parametrize("which,W", [("small", 13), ("large", 5)])
 def test_msd_measure_matches_oracle(which, W):
-    s = _msd_cfg1() if which == "cfg1" else _msd_cfg2()
+    s = _msd_small() if which == "small" else _msd_large()
     R = synth.make_walkers(s, W, 910)
     print(f"[msd] measure {which}: {s.n_elec} e, {s.n_det} dets, W={W}", flush=True)
     ctx = dmcx.Context(s, W)
@@ -92,10 +92,10 @@ def test_msd_measure_matches_oracle(which, W):
 
 @pytest.mark.parametrize("mode,k,P", [(dmcx.DMCX_DMC, 2, 2), (dmcx.DMCX_VMC, 4, 64),
                                       (dmcx.DMCX_DMC, 1, 1)])
-def test_msd_run_cfg1_matches_oracle(mode, k, P):
+def test_msd_run_small_matches_oracle(mode, k, P):
     """Three steps, compared step by step (the E_L bar of each walker is
     scaled by the conditioning at that step's configuration)."""
-    s = _msd_cfg1()
+    s = _msd_small()
     W = 16
     R = synth.make_walkers(s, W, 911)
     e_t = -8.0
@@ -117,20 +117,20 @@ def test_msd_run_cfg1_matches_oracle(mode, k, P):
     np.testing.assert_array_equal(sg, sg_o)
 
 
-def test_msd_run_cfg2_matches_oracle():
+def test_msd_run_large_matches_oracle():
     """112 electrons, 120 determinants over 40 active orbitals, 8 walkers,
     one DMC step with delayed rank-16 updates."""
-    s = _msd_cfg2()
+    s = _msd_large()
     W = 8
     R = synth.make_walkers(s, W, 912)
     ctx = dmcx.Context(s, W, delay_rank=16, recompute_period=64, seed=22)
     ctx.set_walkers(R)
-    print(f"[msd] cfg2 run: {s.n_det} dets", flush=True)
+    print(f"[msd] large run: {s.n_det} dets", flush=True)
     acc, el = ctx.run(1, mode=dmcx.DMCX_DMC, e_trial=-100.0, logs=True)
     Rg, _ = ctx.get_walkers()
     ref = oracle.run(s, R, n_steps=1, mode=dmcx.DMCX_DMC, tau=0.01, seed=22, e_trial=-100.0)
     np.testing.assert_array_equal(acc, ref["accept_log"])
-    _close_conditioned(el[0], ref["e_log"][0], s, ref["R"], "cfg2 step E_L")
+    _close_conditioned(el[0], ref["e_log"][0], s, ref["R"], "large step E_L")
     _close(Rg, ref["R"])
 
 
@@ -138,7 +138,7 @@ def test_msd_equals_single_determinant_with_mixed_column():
     """D + c D_{h->p} per spin is one determinant with column h = phi_h + c phi_p
     (multilinearity): the table path and the plain single-determinant path
     agree on whole runs."""
-    base = synth.make_system(1)
+    base = synth.small_molecule()
     s0 = synth.make_msd(base, 2, 12, 913)  # extends the MO set
     h, p, c = 2, 6, 0.31
     single = lambda sp: ([1, 0, h, -1, p, -1, -1, -1, -1, -1] if sp == 0 else
@@ -162,7 +162,7 @@ def test_msd_equals_single_determinant_with_mixed_column():
 
 
 def test_msd_graph_matches_eager():
-    s = _msd_cfg1()
+    s = _msd_small()
     W = 16
     R = synth.make_walkers(s, W, 915)
     res = []
@@ -200,7 +200,7 @@ def test_msd_group_of_alkanes_matches_individual_and_oracle():
 
 
 def test_msd_mixed_precision_error():
-    s = _msd_cfg2()
+    s = _msd_large()
     W = 16
     R = synth.make_walkers(s, W, 917)
     mx = dmcx.Context(s, W, precision=dmcx.DMCX_MIXED)
@@ -217,11 +217,11 @@ def test_msd_mixed_precision_error():
     assert np.abs(lp_m - lp_f).max() <= 1e-2
 
 
-@pytest.mark.parametrize("which,W", [("cfg1", 8), ("cfg2", 3)])
+@pytest.mark.parametrize("which,W", [("small", 8), ("large", 3)])
 def test_msd_ion_grads_match_oracle(which, W):
     """Reverse mode through the table (adjoint weights X, Y of the minors)
     against the oracle's forward mode per determinant."""
-    s = _msd_cfg1() if which == "cfg1" else _msd_cfg2()
+    s = _msd_small() if which == "small" else _msd_large()
     R = synth.make_walkers(s, W, 919)
     ctx = dmcx.Context(s, W)
     ctx.set_walkers(R)
@@ -236,7 +236,7 @@ def test_msd_ion_grads_match_oracle(which, W):
 
 
 def test_msd_ion_grads_after_moves_and_fd():
-    s = _msd_cfg1()
+    s = _msd_small()
     W = 8
     R = synth.make_walkers(s, W, 920)
     ctx = dmcx.Context(s, W, delay_rank=2, recompute_period=100, seed=26)
@@ -268,7 +268,7 @@ def test_msd_ion_grads_after_moves_and_fd():
 
 
 def test_msd_forces_estimator_runs_in_a_group():
-    systems = [synth.make_msd(synth.alkane(3, 80), 100, 30, 81), _msd_cfg1()]
+    systems = [synth.make_msd(synth.alkane(3, 80), 100, 30, 81), _msd_small()]
     walkers = [8, 8]
     ne_max = max(x.n_elec for x in systems)
     R = np.zeros((16, ne_max, 3))

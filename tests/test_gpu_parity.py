@@ -40,11 +40,11 @@ def test_device_philox_bit_exact():
     np.testing.assert_array_equal(dev, ref)
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
-def test_orbitals_match_oracle(cfg):
-    s = synth.make_system(cfg)
+@pytest.mark.parametrize("mol", ["small", "large"])
+def test_orbitals_match_oracle(mol):
+    s = synth.molecule(mol)
     W = 13  # ragged: not a multiple of the 8-walker tile
-    R = synth.make_walkers(s, W, 100 + cfg)
+    R = synth.make_walkers(s, W, 100 + synth.SEED_OFFSET[mol])
     ctx = dmcx.Context(s, W)
     ctx.set_walkers(R)
     for spin in (0, 1):
@@ -56,10 +56,10 @@ def test_orbitals_match_oracle(cfg):
         np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * scale.max())
 
 
-@pytest.mark.parametrize("cfg,W", [(1, 64), (2, 13)])
-def test_initial_measure_matches_oracle(cfg, W):
-    s = synth.make_system(cfg)
-    R = synth.make_walkers(s, W, 200 + cfg)
+@pytest.mark.parametrize("mol,W", [("small", 64), ("large", 13)])
+def test_initial_measure_matches_oracle(mol, W):
+    s = synth.molecule(mol)
+    R = synth.make_walkers(s, W, 200 + synth.SEED_OFFSET[mol])
     ctx = dmcx.Context(s, W)
     ctx.set_walkers(R)
     e, lp, sg = ctx.measure()
@@ -84,9 +84,9 @@ def _run_both(s, W, n_steps, mode, k, P, seed=7, tau=0.01, wseed=300):
 
 
 @pytest.mark.parametrize("mode", [dmcx.DMCX_VMC, dmcx.DMCX_DMC])
-def test_run_cfg1_parity(mode):
+def test_run_small_parity(mode):
     """Small molecule, 64 walkers, 20 steps, k = 1 (full update each move)."""
-    s = synth.make_system(1)
+    s = synth.small_molecule()
     g, ref = _run_both(s, 64, 20, mode, k=1, P=64)
     np.testing.assert_array_equal(g["acc"], ref["accept_log"])
     _close(g["elog"], ref["e_log"])
@@ -98,10 +98,10 @@ def test_run_cfg1_parity(mode):
 
 
 @pytest.mark.parametrize("k,P", [(32, 64), (8, 1), (56, 2)])
-def test_run_cfg2_parity(k, P):
+def test_run_large_parity(k, P):
     """The 112-electron system: 13 walkers (two tiles, ragged), 2 DMC steps,
     delayed rank-k updates; several tiles and block boundaries."""
-    s = synth.make_system(2)
+    s = synth.large_molecule()
     g, ref = _run_both(s, 13, 2, dmcx.DMCX_DMC, k=k, P=P)
     np.testing.assert_array_equal(g["acc"], ref["accept_log"])
     _close(g["elog"], ref["e_log"])
@@ -114,7 +114,7 @@ def test_run_cfg2_parity(k, P):
 
 def test_delay_rank_invariance():
     """k in {1, 8, 32, 56} produce the same trajectory to round-off."""
-    s = synth.make_system(2)
+    s = synth.large_molecule()
     W = 8
     R = synth.make_walkers(s, W, 400)
     out = []
