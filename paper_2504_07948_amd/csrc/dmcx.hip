@@ -1068,6 +1068,20 @@ dmcx_status autotune_one(dmcx_ctx *c, int steps) {
   return st;
 }
 
+// Members in launch order: most orbital-tile work per step first (walkers x
+// electrons x orbital columns x basis functions), so the longest chain of
+// a group starts before the short ones fill the remaining CUs.
+std::vector<size_t> launch_order(const std::vector<dmcx_ctx *> &ms) {
+  std::vector<size_t> order(ms.size());
+  std::vector<double> cost(ms.size());
+  for (size_t i = 0; i < ms.size(); ++i) {
+    order[i] = i;
+    cost[i] = (double)ms[i]->Wpad * ms[i]->ne * ms[i]->NP * ms[i]->dc.B.Kp;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  return order;
+}
+
 // Capture one step of every member (forked onto the members' own streams)
 // into a graph.  Log pointers and strides are baked in; the step index,
 // mode and E_T are read from each member's device run state.
@@ -1077,14 +1091,16 @@ dmcx_status build_graph(dmcx_ctx *top, const std::vector<dmcx_ctx *> &ms, uint8_
   if (top->graph) { (void)hipGraphDestroy(top->graph); top->graph = nullptr; }
   dmcx_status st;
   if ((st = ensure_events(top, top->cap_ev, 1 + ms.size(), false))) return st;
-  const hipStream_t s0 = ms[0]->own;
+  const std::vector<size_t> order = launch_order(ms);
+  const hipStream_t s0 = ms[order[0]]->own;
   HIP_TRY(top, hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed));
   const long long acc_ss = (long long)top->W * top->ne, elog_ss = top->W;
   if (hipEventRecord(top->cap_ev[0], s0) != hipSuccess) st = fail(top, DMCX_E_HIP, "capture: fork event");
-  for (size_t i = 1; i < ms.size() && !st; ++i)
-    if (hipStreamWaitEvent(ms[i]->own, top->cap_ev[0], 0) != hipSuccess)
+  for (size_t ii = 1; ii < ms.size() && !st; ++ii)
+    if (hipStreamWaitEvent(ms[order[ii]]->own, top->cap_ev[0], 0) != hipSuccess)
       st = fail(top, DMCX_E_HIP, "capture: fork wait");
-  for (size_t i = 0; i < ms.size() && !st; ++i) {
+  for (size_t ii = 0; ii < ms.size() && !st; ++ii) {
+    const size_t i = order[ii];
     dmcx_ctx *m = ms[i];
     const size_t off = top->is_group() ? top->sub_off[i] : 0;
     const hipStream_t keep = m->stream;
@@ -1093,8 +1109,8 @@ dmcx_status build_graph(dmcx_ctx *top, const std::vector<dmcx_ctx *> &ms, uint8_
                       elog ? elog + off : nullptr, elog_ss, nullptr, nullptr);
     m->stream = keep;
     if (st) top->err = m->err;
-    if (!st && i > 0 && (hipEventRecord(top->cap_ev[i], m->own) != hipSuccess ||
-                         hipStreamWaitEvent(s0, top->cap_ev[i], 0) != hipSuccess))
+    if (!st && ii > 0 && (hipEventRecord(top->cap_ev[ii], m->own) != hipSuccess ||
+                          hipStreamWaitEvent(s0, top->cap_ev[ii], 0) != hipSuccess))
       st = fail(top, DMCX_E_HIP, "capture: join");
   }
   hipGraph_t g = nullptr;
@@ -1153,7 +1169,7 @@ dmcx_status run_impl(dmcx_ctx *top, int mode, int n_steps, double e_trial, uint8
     for (dmcx_ctx *m : ms) key += m->dc_version;
     if (!top->gexec || top->g_acc != acc || top->g_elog != elog || top->g_version != key)
       if ((st = build_graph(top, ms, acc, elog, key))) return st;
-    const hipStream_t s0 = ms[0]->own;
+    const hipStream_t s0 = ms[launch_order(ms)[0]]->own;  // the capture stream
     HIP_TRY(top, hipStreamWaitEvent(s0, top->fj[0], 0));
     for (int s = 0; s < n_steps; ++s) HIP_TRY(top, hipGraphLaunch(top->gexec, s0));
     HIP_TRY(top, hipEventRecord(top->fj[1], s0));
@@ -1164,21 +1180,30 @@ dmcx_status run_impl(dmcx_ctx *top, int mode, int n_steps, double e_trial, uint8
       m->version++;
     }
   } else {
-    // several systems, eager: each on its own stream, joined into the caller's
-    for (size_t i = 0; i < ms.size(); ++i) {
-      dmcx_ctx *m = ms[i];
-      const size_t off = top->sub_off[i];
+    // several systems, eager: each on its own stream, joined into the caller's.
+    // Streams share a few hardware queues, so the steps are enqueued step by
+    // step across systems (a system's whole run enqueued at once would hold
+    // up every system behind it on its queue).
+    const std::vector<size_t> order = launch_order(ms);
+    for (dmcx_ctx *m : ms) {
       HIP_TRY(top, hipStreamWaitEvent(m->own, top->fj[0], 0));
       if ((st = ensure_events(m, m->ev, 2 * (size_t)n_steps, true))) { top->err = m->err; return st; }
-      const hipStream_t keep = m->stream;
-      m->stream = m->own;
-      for (int s = 0; s < n_steps && !st; ++s) {
+    }
+    for (int s = 0; s < n_steps; ++s)
+      for (size_t ii = 0; ii < ms.size(); ++ii) {
+        const size_t i = order[ii];
+        dmcx_ctx *m = ms[i];
+        const size_t off = top->sub_off[i];
+        const hipStream_t keep = m->stream;
+        m->stream = m->own;
         st = enqueue_step(m, false, acc ? acc + off * top->ne : nullptr, acc_ss, top->ne,
                           elog ? elog + off : nullptr, elog_ss, m->ev[2 * s], m->ev[2 * s + 1]);
+        m->stream = keep;
         m->step++;
+        if (st) { top->err = m->err; return st; }
       }
-      m->stream = keep;
-      if (st) { top->err = m->err; return st; }
+    for (size_t i = 0; i < ms.size(); ++i) {
+      dmcx_ctx *m = ms[i];
       m->n_timed = n_steps;
       m->version++;
       HIP_TRY(top, hipEventRecord(top->fj[1 + i], m->own));
