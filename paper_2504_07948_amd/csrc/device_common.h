@@ -133,10 +133,27 @@ __device__ __forceinline__ double sum32(double v) {
   for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
   return v;
 }
+// A 64-bit value moved between lanes with one DPP control (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+// Sum over the 64 lanes of a wave; every lane must be active.  Within each
+// 16-lane row: quad permutations (lane ^ 1, lane ^ 2), then row rotations by
+// 4 and 8, after which every lane holds its row's sum; the four row sums are
+// read out and added (a wave-uniform result).
 __device__ __forceinline__ double sum64(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x124>(v);  // row_ror 4
+  v += dpp_f64<0x128>(v);  // row_ror 8
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
 // Pade factor u(r) = a r / (1 + b r) and its first two radial derivatives.
