@@ -944,8 +944,8 @@ __device__ void flush_block(const DevCtx &c, int w0, int sp, int kb) {
 
 // Block update after a move of electron i (block position m of kb) of walker
 // w, served by the 64 lanes t of one wave.  Accepted: Delta = a' - a_old
-// enters Dl[m]; lane b owns block row b and forms z_b = Delta . Gb[b] on its
-// own (contiguous row, no cross-lane reduction); later rows take the
+// enters Dl[m]; each block row b is formed z_b = Delta . Gb[b] by a pair of
+// lanes (one half of the row each); later rows take the
 // Sherman-Morrison correction Gb[b] -= z_b / rho * Gb[m], earlier rows' z_b
 // are the coefficients C[m][b] = Delta_m . u_b, from which row m of
 // M = (I + L)^{-1} is formed; Gb[m] becomes u_m = col / rho; the orbital row,
@@ -960,10 +960,9 @@ __device__ void block_accept(const DevCtx &c, int w, int t, int i, int sp, int m
   T *Gb = (T *)c.Gb + blk_off(c, w);
   T *Dl = (T *)c.Dl + blk_off(c, w);
   double *Rw = c.R + (size_t)w * c.ne * 3;
-    // Lane b owns block row b: it forms z_b = Delta . Gb[b] on its own
-    // (contiguous row, no cross-lane reduction).  Later rows take the
-    // Sherman-Morrison correction Gb[b] -= z_b / rho * Gb[m]; earlier rows'
-    // z_b are the coefficients C[m][b] = Delta_m . u_b the flush needs.
+    // Later rows take the Sherman-Morrison correction
+    // Gb[b] -= z_b / rho * Gb[m]; earlier rows' z_b are the coefficients
+    // C[m][b] = Delta_m . u_b the flush needs.
     T *Ms = (T *)c.Ms + (size_t)w * c.K * c.K;
     if (accepted) {
       const double irho = 1.0 / rho;
@@ -972,25 +971,52 @@ __device__ void block_accept(const DevCtx &c, int w, int t, int i, int sp, int m
         aold_w[j] = d;  // aold now holds Delta (read across this walker's lanes)
         Dl[m * NP + j] = d;
       }
-      for (int b = t; b < kb; b += 64) {
-        if (b == m) continue;
-        T *row = Gb + b * NP;
-        double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
-        // deep unroll: more of the row's loads in flight per round trip
-#pragma unroll 16
-        for (int j = 0; j < NP; j += 4) {
-          z0 += (double)aold_w[j] * (double)row[j];
-          z1 += (double)aold_w[j + 1] * (double)row[j + 1];
-          z2 += (double)aold_w[j + 2] * (double)row[j + 2];
-          z3 += (double)aold_w[j + 3] * (double)row[j + 3];
+      // Two lanes per row: lane t takes row b0 + (t & 31), half h = t >> 5
+      // (HALF entries, 16-byte loads); the half dot products meet across
+      // the wave halves.  Rows of up to 64 orbitals keep their half in
+      // registers between the dot product and the correction.
+      constexpr int HALF = NP / 2;
+      constexpr int VW = 16 / (int)sizeof(T);
+      typedef T vecT __attribute__((ext_vector_type(VW)));
+      constexpr bool KEEP = HALF <= 32;
+      const int h = t >> 5;
+      const T *dl = aold_w + h * HALF;
+      const T *cm = colm_w + h * HALF;
+      for (int b0 = 0; b0 < kb; b0 += 32) {
+        const int b = b0 + (t & 31);
+        const bool live = b < kb && b != m;  // row m (u_m) is rewritten below
+        vecT *row = (vecT *)(Gb + (size_t)(live ? b : 0) * NP + h * HALF);
+        vecT keep[KEEP ? HALF / VW : 1];
+        double zp = 0.0;
+        if (live) {
+          double za = 0.0, zb = 0.0;
+#pragma unroll
+          for (int q = 0; q < HALF / VW; ++q) {
+            const vecT x = row[q];
+            if constexpr (KEEP) keep[q] = x;
+#pragma unroll
+            for (int e = 0; e < VW; e += 2) {
+              za += (double)dl[q * VW + e] * (double)x[e];
+              zb += (double)dl[q * VW + e + 1] * (double)x[e + 1];
+            }
+          }
+          zp = za + zb;
         }
-        const double z = (z0 + z1) + (z2 + z3);
-        if (b > m) {
-          const T f = (T)(z * irho);
-#pragma unroll 16
-          for (int j = 0; j < NP; ++j) row[j] -= f * colm_w[j];
-        } else {
-          crow_w[b] = (T)z;  // C[m][b] = Delta_m . u_b
+        const double z = zp + __shfl_xor(zp, 32, 64);
+        if (live) {
+          if (b > m) {
+            const T f = (T)(z * irho);
+#pragma unroll
+            for (int q = 0; q < HALF / VW; ++q) {
+              vecT x;
+              if constexpr (KEEP) x = keep[q]; else x = row[q];
+#pragma unroll
+              for (int e = 0; e < VW; ++e) x[e] -= f * cm[q * VW + e];
+              row[q] = x;
+            }
+          } else if (h == 0) {
+            crow_w[b] = (T)z;  // C[m][b] = Delta_m . u_b
+          }
         }
       }
       // Row m of M = (I + L)^{-1} (L strictly lower, L[m][p] = C[m][p]):
