@@ -275,8 +275,12 @@ dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, const std::vector<int>
     g = g1;
   }
   const int NP = c->NP;
-  std::vector<double> Cp((size_t)pfn * NP, 0.0);
-  std::vector<float> Cp32((size_t)pfn * NP, 0.0f);
+  // Zero rows past the last function: the orbital tile loads a whole stage
+  // depth of LCAO rows (4 stage_ksteps) and four orbital blocks per wave
+  // without bounds tests; loads past a stage's end are never used.
+  const int pad_rows = 4 * stage_ksteps(c->NOB) + 4;
+  std::vector<double> Cp((size_t)(pfn + pad_rows) * NP, 0.0);
+  std::vector<float> Cp32((size_t)(pfn + pad_rows) * NP, 0.0f);
   for (int r = 0; r < pfn; ++r) {
     if (canon[r] < 0) continue;
     for (int j = 0; j < NP; ++j) {
@@ -315,7 +319,9 @@ dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, const std::vector<int>
 }
 
 // ------------------------------------------------------------ launches --
-size_t basis_lds(const dmcx_ctx *c) { return basis_lds_bytes(c->dc.B.n_group, c->dc.B.n_slot); }
+size_t basis_lds(const dmcx_ctx *c) {
+  return basis_lds_bytes(c->dc.B.n_group, c->dc.B.n_slot, c->dc.B.n_stage);
+}
 
 // The working precision picks the launcher instantiation.
 #define DMCX_BY_PRECISION(c, CALL)  \

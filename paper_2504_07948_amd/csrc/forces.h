@@ -148,7 +148,7 @@ __global__ __launch_bounds__(NT_FORCE) void k_ion_grad_det(DevCtx c, double *par
   }
   __syncthreads();
   for (int st = 0; st < c.B.n_stage; ++st) {
-    const int2 sg = c.B.stages[st];
+    const int2 sg = BL.stages[st];
     const int fb = BL.ginfo[sg.x].z;
     const int fe = sg.y < c.B.n_group ? BL.ginfo[sg.y].z : c.B.Kp;
     const int nft = (fe - fb + 15) / 16;  // 16-row function tiles (stage size is a multiple of 4)

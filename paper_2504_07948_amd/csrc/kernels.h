@@ -124,10 +124,12 @@ struct DevBasis {
 struct BasisLDS {
   const int4 *ginfo;
   const double *xyz, *alpha, *coef;
+  const int2 *stages;
 };
 
-__host__ __device__ inline size_t basis_lds_bytes(int n_group, int n_slot) {
-  return (size_t)n_group * sizeof(int4) + ((size_t)n_group * 12 + 2 * (size_t)n_slot) * 8;
+__host__ __device__ inline size_t basis_lds_bytes(int n_group, int n_slot, int n_stage) {
+  return (size_t)n_group * sizeof(int4) + ((size_t)n_group * 12 + 2 * (size_t)n_slot) * 8 +
+         (size_t)n_stage * sizeof(int2);
 }
 
 __device__ inline BasisLDS stage_basis_lds(const DevBasis &B, char *smem) {
@@ -135,7 +137,9 @@ __device__ inline BasisLDS stage_basis_lds(const DevBasis &B, char *smem) {
   double *xyz = (double *)(smem + (size_t)B.n_group * sizeof(int4));
   double *al = xyz + (size_t)B.n_group * 12;
   double *co = al + B.n_slot;
+  int2 *sg = (int2 *)(co + B.n_slot);
   for (int i = threadIdx.x; i < B.n_group; i += blockDim.x) gi[i] = B.ginfo[i];
+  for (int i = threadIdx.x; i < B.n_stage; i += blockDim.x) sg[i] = B.stages[i];
   for (int i = threadIdx.x; i < B.n_group * 12; i += blockDim.x) xyz[i] = B.gxyz[i];
   for (int i = threadIdx.x; i < B.n_slot; i += blockDim.x) {
     al[i] = B.galpha[i];
@@ -146,6 +150,7 @@ __device__ inline BasisLDS stage_basis_lds(const DevBasis &B, char *smem) {
   L.xyz = xyz;
   L.alpha = al;
   L.coef = co;
+  L.stages = sg;
   return L;
 }
 
@@ -370,20 +375,19 @@ __device__ __forceinline__ void lds_barrier() {
 // group kh (A operand; lane l holds C[f0 + 4 kk + l/16][ob*16 + l%16] for
 // K-steps kk = NKH i + kh).
 template <typename T, int NOB, int KH>
-__device__ __forceinline__ void load_stage_a(const T *Cp, int fn_begin, int nk, int ob0, int kh,
+__device__ __forceinline__ void load_stage_a(const T *Cp, int fn_begin, int ob0, int kh,
                                              int kq, int col, T (&a)[(NOB + 3) / 4][KH]) {
   constexpr int NQ = (NOB + 3) / 4;
   constexpr int NP = NOB * 16;
-  const T *abase = Cp + (size_t)(fn_begin + 4 * kh + kq) * NP + col;
+  // Unconditional loads: the LCAO array carries zero rows past its end, so
+  // K-steps past the stage and orbital blocks past NOB read valid memory
+  // (mfma_stage never uses those registers), and the loads form one
+  // straight run whose completion the MFMAs can wait for one at a time.
+  const T *abase = Cp + (size_t)(fn_begin + 4 * kh + kq) * NP + col + ob0 * 16;
 #pragma unroll
   for (int i = 0; i < KH; ++i)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int ob = ob0 + 4 * q;
-      a[q][i] = (NKH * i + kh < nk && (NOB % 4 == 0 || ob < NOB))
-                    ? abase[(size_t)(4 * NKH * i) * NP + ob * 16]
-                    : (T)0;
-    }
+    for (int q = 0; q < NQ; ++q) a[q][i] = abase[(size_t)(4 * NKH * i) * NP + 64 * q];
 }
 
 // This wave's K-steps of one stage: acc[q][cb] += A(block) * B(column block).
@@ -426,10 +430,10 @@ __device__ __forceinline__ void mfma_stage(typename Acc4<T>::type (&acc)[(NOB + 
 // owns orbital blocks w%4 (+4, ...) and the K-steps of parity w/4 when there
 // are eight waves, all K-steps when there are four) and then
 // all 512 threads evaluate the basis of stage s+1 into the other buffer;
-// the LCAO operands of stage s+1 are loaded into registers right after the
-// MFMAs of stage s are issued, so they arrive during the basis evaluation
-// and the barrier.  One barrier per stage; the two K-parity partial sums
-// are added once at the end.
+// the LCAO operands of stage s+1 are requested just before the MFMAs of
+// stage s, so they arrive during those MFMAs, the basis evaluation and the
+// barrier.  One barrier per stage; the two K-parity partial sums are added
+// once at the end.
 template <typename T, int NOB, int KS = stage_ksteps(NOB)>
 __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)[3], T *Bs0,
                         T *Bs1, T *out) {
@@ -452,7 +456,7 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
   T a0[NQ][KH], a1[NQ][KH];
   int g0, g1, fb, nk;
   auto stage_range = [&](int s) {
-    const int2 sg = c.B.stages[s];
+    const int2 sg = BL.stages[s];
     g0 = sg.x;
     g1 = sg.y;
     fb = BL.ginfo[sg.x].z;
@@ -460,7 +464,7 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
     nk = (fe - fb) >> 2;
   };
   stage_range(0);
-  load_stage_a<T, NOB, KH>(Cp, fb, nk, ob0, kh, kq, col, a0);
+  load_stage_a<T, NOB, KH>(Cp, fb, ob0, kh, kq, col, a0);
   constexpr int NPADC = NCOL - NVALID;  // padding columns, zero for every stage
   for (int i = tid; i < FM * NPADC; i += NT_TILE) {
     Bs0[(i / NPADC) * NCOL + NVALID + i % NPADC] = (T)0;
@@ -468,31 +472,36 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
   }
   basis_stage<T>(BL, g0, g1, fb, pts, Bs0, tid, NT_TILE);
   lds_barrier();
+  // The LCAO operands of stage s+1 are requested before the MFMAs of stage s
+  // (their registers are free by then), so they have the MFMAs, the basis
+  // evaluation and the barrier to arrive.
   for (int st = 0; st < S; st += 2) {
-    {  // MFMAs of stage st (a0, Bs0); stage st+1 -> (a1, Bs1)
-      SUB_T(tm0);
-      mfma_stage<T, NOB, KH>(acc, a0, Bs0, nk, ob0, kh, kq, col);
-      SUB_T(tm1);
+    {  // stage st+1 -> a1; MFMAs of stage st (a0, Bs0); basis st+1 -> Bs1
+      const int nk_cur = nk;
       if (st + 1 < S) {
         stage_range(st + 1);
-        load_stage_a<T, NOB, KH>(Cp, fb, nk, ob0, kh, kq, col, a1);
-        basis_stage<T>(BL, g0, g1, fb, pts, Bs1, tid, NT_TILE);
+        load_stage_a<T, NOB, KH>(Cp, fb, ob0, kh, kq, col, a1);
       }
+      SUB_T(tm0);
+      mfma_stage<T, NOB, KH>(acc, a0, Bs0, nk_cur, ob0, kh, kq, col);
+      SUB_T(tm1);
+      if (st + 1 < S) basis_stage<T>(BL, g0, g1, fb, pts, Bs1, tid, NT_TILE);
       SUB_T(tm2);
       SUB_ADD(11, tm0, tm1);
       SUB_ADD(9, tm1, tm2);
       lds_barrier();
     }
     if (st + 1 >= S) break;
-    {  // MFMAs of stage st+1 (a1, Bs1); stage st+2 -> (a0, Bs0)
-      SUB_T(tm0);
-      mfma_stage<T, NOB, KH>(acc, a1, Bs1, nk, ob0, kh, kq, col);
-      SUB_T(tm1);
+    {  // stage st+2 -> a0; MFMAs of stage st+1 (a1, Bs1); basis st+2 -> Bs0
+      const int nk_cur = nk;
       if (st + 2 < S) {
         stage_range(st + 2);
-        load_stage_a<T, NOB, KH>(Cp, fb, nk, ob0, kh, kq, col, a0);
-        basis_stage<T>(BL, g0, g1, fb, pts, Bs0, tid, NT_TILE);
+        load_stage_a<T, NOB, KH>(Cp, fb, ob0, kh, kq, col, a0);
       }
+      SUB_T(tm0);
+      mfma_stage<T, NOB, KH>(acc, a1, Bs1, nk_cur, ob0, kh, kq, col);
+      SUB_T(tm1);
+      if (st + 2 < S) basis_stage<T>(BL, g0, g1, fb, pts, Bs0, tid, NT_TILE);
       SUB_T(tm2);
       SUB_ADD(11, tm0, tm1);
       SUB_ADD(9, tm1, tm2);
