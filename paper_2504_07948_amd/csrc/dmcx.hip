@@ -277,7 +277,8 @@ dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, const std::vector<int>
   const int NP = c->NP;
   // Zero rows past the last function: the orbital tile loads a whole stage
   // depth of LCAO rows (4 stage_ksteps) and four orbital blocks per wave
-  // without bounds tests; loads past a stage's end are never used.
+  // without bounds tests, and the force kernel's 16-row function tiles run
+  // up to 15 rows past a stage; loads past a stage's end are never used.
   const int pad_rows = 4 * stage_ksteps(c->NOB) + 4;
   std::vector<double> Cp((size_t)(pfn + pad_rows) * NP, 0.0);
   std::vector<float> Cp32((size_t)(pfn + pad_rows) * NP, 0.0f);

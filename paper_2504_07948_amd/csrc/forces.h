@@ -156,7 +156,13 @@ __global__ __launch_bounds__(NT_FORCE) void k_ion_grad_det(DevCtx c, double *par
     for (int tt = wid; tt < nft * (FPTS / 16); tt += NT_FORCE / 64) {
       const int f0 = (tt / (FPTS / 16)) * 16, n0 = (tt % (FPTS / 16)) * 16;
       const auto y = mfma_tile<T>(
-          NP, [&](int i, int k) { return (fb + f0 + i < fe) ? Cp[(size_t)(fb + f0 + i) * NP + k] : (T)0; },
+          NP,
+          [&](int i, int k) {
+            // rows past the stage are read (the LCAO array has zero rows past
+            // its end) and masked, so the loads carry no branches
+            const T v = Cp[(size_t)(fb + f0 + i) * NP + k];
+            return (fb + f0 + i < fe) ? v : (T)0;
+          },
           [&](int k, int j) { return Gp[k * FPTS + n0 + j]; });
 #pragma unroll
       for (int r = 0; r < 4; ++r) {

@@ -880,14 +880,23 @@ __global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int measure_o
   }
 }
 
-// One 16x16 MFMA tile in precision T: sum over k < K (multiple of 4) of A(i, k) B(k, j)
-// with A(i, k) = fa(i0 + i, k) and B(k, j) = fb(k, j0 + j).
+// One 16x16 MFMA tile in precision T: sum over k < K (multiple of 16) of A(i, k) B(k, j)
+// with A(i, k) = fa(i0 + i, k) and B(k, j) = fb(k, j0 + j).  The operands of
+// four K-steps are fetched before their four MFMAs, so their loads overlap.
 template <typename T, typename FA, typename FB>
 __device__ __forceinline__ typename Acc4<T>::type mfma_tile(int K, FA fa, FB fb) {
   const int lane = threadIdx.x & 63, kq = lane >> 4, cl = lane & 15;
   typename Acc4<T>::type acc = {0, 0, 0, 0};
-#pragma unroll 8
-  for (int k0 = 0; k0 < K; k0 += 4) acc = mfma16x16x4(fa(cl, k0 + kq), fb(k0 + kq, cl), acc);
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    T av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      av[u] = fa(cl, k0 + 4 * u + kq);
+      bv[u] = fb(k0 + 4 * u + kq, cl);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = mfma16x16x4(av[u], bv[u], acc);
+  }
   return acc;
 }
 
@@ -899,7 +908,10 @@ __device__ __forceinline__ typename Acc4<T>::type mfma_tile(int K, FA fa, FB fb)
 // with Z = Delta G0 and C[l][p] = Delta_l . u_p, so z = M Z with
 // M = (I + L)^{-1} (L the strictly lower part of C), which the sweep builds
 // row by row.  Here: Z = Delta G0, Z' = M Z and G = G0 - Z'^T U, three
-// MFMA GEMMs per walker (all four waves share each walker's tiles).
+// MFMA GEMMs per walker.  Each GEMM runs over the tiles of all the tile's
+// walkers at once (one barrier per GEMM); operands outside the block are
+// read from a clamped row and zeroed by a select, so the K loop's loads
+// carry no branches and can be issued ahead of their MFMAs.
 template <typename T, int NOB>
 __device__ void flush_block(const DevCtx &c, int w0, int sp, int kb) {
   constexpr int NP = NOB * 16;
@@ -908,47 +920,62 @@ __device__ void flush_block(const DevCtx &c, int w0, int sp, int kb) {
   const int K = c.K;
   const int KBP = (kb + 15) & ~15;
   const int nlt = KBP / 16;
+  const int kl = kb - 1;  // last row of the block
+  const int nz = nlt * NOB;
   __syncthreads();  // Dl, Gb, Ms of every walker complete
-  for (int wv = 0; wv < TW; ++wv) {
-    const int w = w0 + wv;
+  // Z[l][b] = sum_j Dl[l][j] GT[b][j]
+  for (int tt = wid; tt < TW * nz; tt += NW_TILE) {
+    const int w = w0 + tt / nz, r = tt % nz;
+    const int l0 = (r / NOB) * 16, b0 = (r % NOB) * 16;
     const T *Dl = (const T *)c.Dl + blk_off(c, w);
-    const T *Gb = (const T *)c.Gb + blk_off(c, w);
-    const T *Ms = (const T *)c.Ms + (size_t)w * K * K;
+    const T *GT = (const T *)c.GT + gt_off(c, w, sp);
     T *Zs = (T *)c.Zs + (size_t)w * c.K16 * NP;
-    T *Z2 = (T *)c.Vs + (size_t)w * c.K16 * NP;
-    T *GT = (T *)c.GT + gt_off(c, w, sp);
-    // Z[l][b] = sum_j Dl[l][j] GT[b][j]
-    for (int tt = wid; tt < nlt * NOB; tt += NW_TILE) {
-      const int l0 = (tt / NOB) * 16, b0 = (tt % NOB) * 16;
-      const auto z = mfma_tile<T>(
-          NP, [&](int i, int k) { return (l0 + i < kb) ? Dl[(l0 + i) * NP + k] : (T)0; },
-          [&](int k, int j) { return GT[(size_t)(b0 + j) * NP + k]; });
+    const auto z = mfma_tile<T>(
+        NP,
+        [&](int i, int k) {
+          const T v = Dl[min(l0 + i, kl) * NP + k];
+          return (l0 + i < kb) ? v : (T)0;
+        },
+        [&](int k, int j) { return GT[(size_t)(b0 + j) * NP + k]; });
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Zs[(l0 + Acc4<T>::row(kq, r)) * NP + b0 + cl] = z[r];
-    }
-    __syncthreads();
-    // Z'[l][b] = sum_{p <= l} M[l][p] Z[p][b]
-    for (int tt = wid; tt < nlt * NOB; tt += NW_TILE) {
-      const int l0 = (tt / NOB) * 16, b0 = (tt % NOB) * 16;
-      const auto z = mfma_tile<T>(
-          KBP,
-          [&](int i, int k) { return (k <= l0 + i && l0 + i < kb) ? Ms[(l0 + i) * K + k] : (T)0; },
-          [&](int k, int j) { return Zs[k * NP + b0 + j]; });
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Z2[(l0 + Acc4<T>::row(kq, r)) * NP + b0 + cl] = z[r];
-    }
-    __syncthreads();
-    // GT[b][j] -= sum_l Z'[l][b] Gb[l][j]
-    for (int tt = wid; tt < NOB * NOB; tt += NW_TILE) {
-      const int b0 = (tt / NOB) * 16, j0 = (tt % NOB) * 16;
-      const auto s = mfma_tile<T>(
-          KBP, [&](int i, int k) { return Z2[k * NP + b0 + i]; },
-          [&](int k, int j) { return (k < kb) ? Gb[k * NP + j0 + j] : (T)0; });
-#pragma unroll
-      for (int r = 0; r < 4; ++r) GT[(size_t)(b0 + Acc4<T>::row(kq, r)) * NP + j0 + cl] -= s[r];
-    }
-    __syncthreads();
+    for (int q = 0; q < 4; ++q) Zs[(l0 + Acc4<T>::row(kq, q)) * NP + b0 + cl] = z[q];
   }
+  __syncthreads();
+  // Z'[l][b] = sum_{p <= l} M[l][p] Z[p][b]
+  for (int tt = wid; tt < TW * nz; tt += NW_TILE) {
+    const int w = w0 + tt / nz, r = tt % nz;
+    const int l0 = (r / NOB) * 16, b0 = (r % NOB) * 16;
+    const T *Ms = (const T *)c.Ms + (size_t)w * K * K;
+    const T *Zs = (const T *)c.Zs + (size_t)w * c.K16 * NP;
+    T *Z2 = (T *)c.Vs + (size_t)w * c.K16 * NP;
+    const auto z = mfma_tile<T>(
+        KBP,
+        [&](int i, int k) {
+          const T v = Ms[min(l0 + i, kl) * K + min(k, kl)];
+          return (k <= l0 + i && l0 + i < kb) ? v : (T)0;
+        },
+        [&](int k, int j) { return Zs[k * NP + b0 + j]; });
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Z2[(l0 + Acc4<T>::row(kq, q)) * NP + b0 + cl] = z[q];
+  }
+  __syncthreads();
+  // GT[b][j] -= sum_l Z'[l][b] Gb[l][j]
+  for (int tt = wid; tt < TW * NOB * NOB; tt += NW_TILE) {
+    const int w = w0 + tt / (NOB * NOB), r = tt % (NOB * NOB);
+    const int b0 = (r / NOB) * 16, j0 = (r % NOB) * 16;
+    const T *Gb = (const T *)c.Gb + blk_off(c, w);
+    const T *Z2 = (const T *)c.Vs + (size_t)w * c.K16 * NP;
+    T *GT = (T *)c.GT + gt_off(c, w, sp);
+    const auto s = mfma_tile<T>(
+        KBP, [&](int i, int k) { return Z2[k * NP + b0 + i]; },
+        [&](int k, int j) {
+          const T v = Gb[min(k, kl) * NP + j0 + j];
+          return (k < kb) ? v : (T)0;
+        });
+#pragma unroll
+    for (int q = 0; q < 4; ++q) GT[(size_t)(b0 + Acc4<T>::row(kq, q)) * NP + j0 + cl] -= s[q];
+  }
+  __syncthreads();
 }
 
 // Block update after a move of electron i (block position m of kb) of walker
