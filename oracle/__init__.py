@@ -72,6 +72,7 @@ def _load():
         lib.orc_ion_grads_batch.argtypes = [P, C.c_int32, P, P, P, C.c_int32]
         lib.orc_evaluate_batch.argtypes = [P, C.c_int32, P, P, P, P, C.c_int32]
         lib.orc_msd_ratio_direct.argtypes = [P, P, P]
+        lib.orc_reconfigure.argtypes = [C.c_int32, P, C.c_double, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -238,3 +239,17 @@ def msd_ratio_direct(sys, R):
     _load().orc_msd_ratio_direct(o.ref, _ptr(np.ascontiguousarray(R, dtype=np.float64)),
                                  C.byref(out))
     return float(out.value)
+
+
+def reconfigure(log_w, u):
+    """Comb reconfiguration at fixed population (see oracle.h).
+    Returns (copies[W] int32, pairs[n, 2] (destination, source), log_wbar, rc)."""
+    lw = np.ascontiguousarray(log_w, dtype=np.float64)
+    W = lw.shape[0]
+    copies = np.zeros(W, dtype=np.int32)
+    pairs = np.zeros((max(W, 1), 2), dtype=np.int32)
+    n = C.c_int32(0)
+    lwbar = C.c_double(0.0)
+    rc = _load().orc_reconfigure(W, _ptr(lw), float(u), _ptr(copies), _ptr(pairs), C.byref(n),
+                                 C.byref(lwbar))
+    return copies, pairs[: n.value].copy(), float(lwbar.value), rc

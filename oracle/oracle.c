@@ -1016,3 +1016,56 @@ static int msd_ion_det_grads(const orc_system *s, const double *R, double *dlogp
   free(fn_atom);
   return rc;
 }
+
+/* ------------------------------------------------------ population control */
+/* Comb reconfiguration at fixed population (see oracle.h): the DMC weights of
+ * Eq. 1 decide how many copies of each walker the next population holds. */
+int orc_reconfigure(int32_t W, const double *log_w, double u, int32_t *copies, int32_t *pairs,
+                    int32_t *n_pairs, double *log_wbar) {
+  if (W < 1 || !(u >= 0.0 && u < 1.0)) return -1;
+  double m = -INFINITY;
+  for (int32_t j = 0; j < W; ++j)
+    if (isfinite(log_w[j]) && log_w[j] > m) m = log_w[j];
+  *n_pairs = 0;
+  if (!isfinite(m)) {
+    for (int32_t j = 0; j < W; ++j) copies[j] = 1;
+    *log_wbar = NAN;
+    return 0;
+  }
+  double *C = (double *)malloc(sizeof(double) * (size_t)W);
+  double acc = 0.0;
+  int32_t last = 0;
+  for (int32_t j = 0; j < W; ++j) {
+    const double w = isfinite(log_w[j]) ? exp(log_w[j] - m) : 0.0;
+    if (w > 0.0) last = j;
+    acc += w;
+    C[j] = acc;
+    copies[j] = 0;
+  }
+  const double S = acc;
+  const double step = S / (double)W;
+  /* each tooth: the first walker whose cumulative weight exceeds it */
+  for (int32_t k = 0; k < W; ++k) {
+    const double t = ((double)k + u) * step;
+    int32_t sel = last;
+    for (int32_t j = 0; j < W; ++j) {
+      if (t < C[j]) { sel = j; break; }
+    }
+    copies[sel] += 1;
+  }
+  free(C);
+  /* extra copies, walkers in order, into the free slots, lowest first */
+  int32_t p = 0, f = 0;
+  for (int32_t j = 0; j < W; ++j) {
+    for (int32_t e = 1; e < copies[j]; ++e) {
+      while (copies[f] != 0) ++f;
+      pairs[2 * p] = f;
+      pairs[2 * p + 1] = j;
+      ++p;
+      ++f;
+    }
+  }
+  *n_pairs = p;
+  *log_wbar = m + log(S / (double)W);
+  return 0;
+}

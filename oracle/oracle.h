@@ -110,6 +110,23 @@ int orc_msd_ratio_direct(const orc_system *s, const double *R, double *psi_over_
 int orc_msd_evaluate(const orc_system *s, const double *R, double *log_psi, int32_t *sign,
                      double *e_local, double *drift);
 
+/* Population control at fixed population by comb reconfiguration (the
+ * published systematic-resampling scheme; the paper fixes the DMC weights of
+ * Eq. 1, not how the population is controlled).  Walker j has weight
+ * w_j = exp(log_w[j] - m), m the largest finite log_w (a non-finite log_w
+ * counts as weight 0); C_j = w_0 + ... + w_j summed in walker order,
+ * S = C_{W-1}.  Tooth k = 0..W-1 sits at t_k = (k + u) * (S / W) and selects
+ * the first j with t_k < C_j (the last positive-weight walker if rounding
+ * leaves none).  copies[j] = teeth selecting j.  The slots of walkers with no
+ * copy are filled, lowest slot first, by the extra copies of the walkers in
+ * walker order: pairs[2p] = destination, pairs[2p + 1] = source, p < *n_pairs.
+ * *log_wbar = m + log(S / W), the log of the mean weight, which every walker
+ * carries afterwards.  With no positive weight nothing is selected: copies
+ * are all 1, *n_pairs = 0 and *log_wbar = NaN.  Returns -1 for u outside
+ * [0, 1) or W < 1. */
+int orc_reconfigure(int32_t W, const double *log_w, double u, int32_t *copies, int32_t *pairs,
+                    int32_t *n_pairs, double *log_wbar);
+
 #ifdef __cplusplus
 }
 #endif
