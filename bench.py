@@ -188,6 +188,50 @@ def forces_leg(s, torch, dmcx, stream, args, W=1024, steps=5):
     return out
 
 
+def population_leg(s, torch, dmcx, stream, W=2048, steps=10, sigma=0.5):
+    """Comb reconfiguration (fixed population) of the 2048 walkers, FP64,
+    after one DMC step.  Before each timed call the log-weights are set to a
+    seeded normal spread (sigma 0.5; with this synthetic trial function and
+    no local-energy cutoff, weights accumulated by the steps themselves
+    collapse onto a few walkers within a few steps).  The copy of a replaced
+    walker moves its whole carried state; bytes = 2 x that x walkers
+    replaced."""
+    from paper_2504_07948_amd import synth
+    ctx = dmcx.Context(s, W, delay_rank=32, recompute_period=64, tau=0.01, seed=29, stream=stream)
+    ctx.set_walkers(torch.from_numpy(synth.make_walkers(s, W, 2029)).cuda())
+    e0, _, _ = ctx.measure()
+    e_t = float(np.mean(e0[np.isfinite(e0)]))
+    ctx.run_device(1, mode=dmcx.DMCX_DMC, e_trial=e_t)
+    R1 = torch.from_numpy(ctx.get_walkers()[0]).cuda()
+    rng = np.random.default_rng(31)
+    u_host = rng.uniform(0.0, 1.0, steps + 1)
+    copies = torch.zeros((steps + 1, W), dtype=torch.int32, device="cuda")
+    lwbar = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
+    cur = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps + 1)]
+    for i in range(steps + 1):  # call 0 is a warm-up
+        ctx.set_walkers(R1, torch.from_numpy(rng.normal(0.0, sigma, W)).cuda())
+        u = np.ascontiguousarray(u_host[i:i + 1])
+        ev[i][0].record(cur)
+        ctx.check(dmcx.dmcx_reconfigure(ctx.h, u.ctypes.data, copies[i].data_ptr(),
+                                        lwbar[i:i + 1].data_ptr(), dmcx.DMCX_DEVICE))
+        ev[i][1].record(cur)
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in ev[1:]])
+    replaced = (copies[1:] == 0).sum(dim=1).cpu().numpy()
+    NP = (max(s.n_up, s.n_dn) + 15) // 16 * 16
+    ne = s.n_elec
+    state = ne * 3 * 8 + ne * 5 * NP * 8 + 2 * NP * NP * 8 + 8 * 8
+    gbs = 2.0 * state * replaced / (ms * 1e-3) / 1e9
+    return {"walkers": W, "calls": steps, "log_w_sigma": sigma,
+            "reconfigure_ms_avg": float(ms.mean()),
+            "walkers_replaced_avg": float(replaced.mean()),
+            "state_bytes_per_walker": state,
+            "copy_GB_per_s_avg": float(gbs.mean()),
+            "hbm_fraction": float(gbs.mean() / 8000.0)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,7 +245,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the FP64 leg (same as --extras none)")
-    ap.add_argument("--extras", default="mixed,forces,batch",
+    ap.add_argument("--extras", default="mixed,forces,batch,population",
                     help="comma list of the extra legs to run after the FP64 leg: mixed, forces, "
                          "batch (eight multideterminant alkanes), or none")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -246,9 +290,9 @@ def main():
     sweep_ms, n_launch, sweep_total = ctx.last_run_timing()
     flags = ctx.walker_flags()
 
-    mixed = forces = batch5 = None
+    mixed = forces = batch5 = population = None
     extras = set() if args.skip_extras else set(args.extras.split(",")) - {"none", ""}
-    unknown = extras - {"mixed", "forces", "batch"}
+    unknown = extras - {"mixed", "forces", "batch", "population"}
     if unknown:
         sys.exit(f"bench.py: unknown extra legs {sorted(unknown)}")
     if "mixed" in extras:
@@ -257,6 +301,8 @@ def main():
         forces = forces_leg(s, torch, dmcx, stream, args)
     if "batch" in extras:
         batch5 = batch5_leg(torch, dmcx, stream)
+    if "population" in extras:
+        population = population_leg(s, torch, dmcx, stream)
 
     ne, ns = s.n_elec, max(s.n_up, s.n_dn)
     moves = W * ne * args.steps
@@ -322,6 +368,7 @@ def main():
         "mixed": mixed,
         "forces": forces,
         "batch_multideterminant": batch5,
+        "population_control": population,
         "walker_flags_nonzero": int((flags != 0).sum()),
     }
     print(json.dumps(out))

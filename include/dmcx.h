@@ -213,6 +213,30 @@ dmcx_status dmcx_forces(dmcx_ctx *ctx, double *F, dmcx_mem mem);
 /* Per-walker status bits [W]: 1 = non-finite value, 2 = singular matrix. */
 dmcx_status dmcx_walker_flags(dmcx_ctx *ctx, uint8_t *flags, dmcx_mem mem);
 
+/* Population control at fixed population: comb reconfiguration of each
+ * system's walkers by their DMC weights (the weights of Eq. 1; the paper does
+ * not fix the control scheme, this is the published systematic resampling).
+ * For system s with W_s walkers: w_j = exp(log_w_j - m), m the largest finite
+ * log_w (a non-finite log_w is weight 0); C_j = w_0 + ... + w_j in walker
+ * order; S = C_{W_s - 1}.  Tooth k = 0..W_s-1 at t_k = (k + u[s]) * (S / W_s)
+ * selects the first walker with t_k < C_j.  Walkers without a copy are
+ * replaced, lowest slot first, by the extra copies of the others in walker
+ * order; a copy takes every state the walker carries between steps
+ * (positions, inverses, cached orbital rows, log|D| and sign, E_L, log|Psi|,
+ * V, flags, multideterminant table).  Every walker of system s then has
+ * log_w = log(S / W_s) + m, so the total weight is kept.  With no positive
+ * weight the population is left as it is and log_wbar[s] is NaN.
+ * u: [n_sys] comb offsets in [0, 1) (host memory; the caller draws them).
+ * copies: [W] int32 copies of each walker, or NULL.  log_wbar: [n_sys] log
+ * of the mean weight before the call, or NULL.  mem applies to copies and
+ * log_wbar; host outputs are complete on return.  The walker step counter is
+ * unchanged, so copies draw different Philox streams from their next step on
+ * (the walker index is part of the counter).  Errors: DMCX_E_INVALID (u
+ * outside [0, 1)), DMCX_E_STATE (walkers not set, or an electron block of the
+ * move-by-move calls pending). */
+dmcx_status dmcx_reconfigure(dmcx_ctx *ctx, const double *u, int32_t *copies, double *log_wbar,
+                             dmcx_mem mem);
+
 /* Wait for all work queued on the context's stream. */
 dmcx_status dmcx_sync(dmcx_ctx *ctx);
 

@@ -15,6 +15,7 @@
 #include "kernels.h"
 #include "launch.h"
 #include "msd.h"
+#include "population.h"
 
 using namespace dmcx;
 
@@ -60,6 +61,8 @@ struct dmcx_ctx {
   double *d_rnew = nullptr;        // [Wpad][3]
   double *d_rg = nullptr;          // [W][4] ratio + gradient staging
   uint8_t *d_acc8 = nullptr;       // [Wpad]
+  // population control (comb reconfiguration) scratch
+  PopScratch pop{};
   // scratch
   double *d_pos = nullptr;       // [Wpad][3]
   double *d_orb = nullptr;       // [Wpad][5][NP] (working precision) / small staging
@@ -814,6 +817,13 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
   if ((st = dalloc(c, &c->d_rg, Wp * 4))) return bail(st);
   if ((st = dalloc(c, &c->d_acc8, Wp))) return bail(st);
   if ((st = dalloc(c, &d.flags, Wp))) return bail(st);
+  if ((st = dalloc(c, &c->pop.w, Wp))) return bail(st);
+  if ((st = dalloc(c, &c->pop.copies, Wp))) return bail(st);
+  if ((st = dalloc(c, &c->pop.dead, Wp))) return bail(st);
+  if ((st = dalloc(c, &c->pop.ex, Wp))) return bail(st);
+  if ((st = dalloc(c, &c->pop.pairs, Wp))) return bail(st);
+  if ((st = dalloc(c, &c->pop.n_pairs, 1))) return bail(st);
+  if ((st = dalloc(c, &c->pop.lwbar, 1))) return bail(st);
   if ((st = dalloc(c, &c->d_pos, Wp * 3))) return bail(st);
   if ((st = dalloc(c, &c->d_orb, Wp * 5 * c->NP))) return bail(st);
   if ((st = dalloc(c, &c->d_orb_out, Wp * 5 * c->NP))) return bail(st);
@@ -1649,6 +1659,36 @@ dmcx_status dmcx_potential(dmcx_ctx *c, double *v, dmcx_mem mem) {
   dmcx_status st = refresh_after_moves(c);
   if (st) return st;
   return copy_out(c, v, c->dc.vpot, (size_t)c->W * sizeof(double), mem);
+}
+
+dmcx_status dmcx_reconfigure(dmcx_ctx *c, const double *u, int32_t *copies, double *log_wbar,
+                             dmcx_mem mem) {
+  if (!c || !u) return DMCX_E_INVALID;
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  if (c->blk_active) return fail(c, DMCX_E_STATE, "an electron block is pending (dmcx_flush)");
+  const std::vector<dmcx_ctx *> ms = members(c);
+  for (size_t i = 0; i < ms.size(); ++i)
+    if (!(u[i] >= 0.0 && u[i] < 1.0)) return fail(c, DMCX_E_INVALID, "comb offset outside [0, 1)");
+  for (size_t i = 0; i < ms.size(); ++i) {
+    dmcx_ctx *m = ms[i];
+    const size_t off = c->is_group() ? (size_t)c->sub_off[i] : 0;
+    HIP_TRY(c, launch_reconfigure(m->dc, m->es, u[i], m->pop, m->stream));
+    if (copies) {
+      HIP_TRY(c, hipMemcpyAsync(copies + off, m->pop.copies, (size_t)m->W * sizeof(int32_t),
+                                mem == DMCX_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                                m->stream));
+    }
+    if (log_wbar) {
+      HIP_TRY(c, hipMemcpyAsync(log_wbar + i, m->pop.lwbar, sizeof(double),
+                                mem == DMCX_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                                m->stream));
+    }
+    m->version++;
+  }
+  c->version++;
+  if (mem == DMCX_HOST && (copies || log_wbar))
+    for (dmcx_ctx *m : ms) HIP_TRY(c, hipStreamSynchronize(m->stream));
+  return DMCX_OK;
 }
 
 dmcx_status dmcx_walker_flags(dmcx_ctx *c, uint8_t *flags, dmcx_mem mem) {

@@ -30,7 +30,7 @@ EXPORTED = [
     "dmcx_accept", "dmcx_flush", "dmcx_run", "dmcx_measure", "dmcx_ion_grads", "dmcx_logpsi_vjp",
     "dmcx_potential_vjp", "dmcx_forces", "dmcx_potential", "dmcx_walker_flags", "dmcx_sync", "dmcx_last_run_timing",
     "dmcx_selftest", "dmcx_philox", "dmcx_strerror", "dmcx_last_error", "dmcx_autotune",
-    "dmcx_autotune_report", "dmcx_get_delay_rank",
+    "dmcx_autotune_report", "dmcx_get_delay_rank", "dmcx_reconfigure",
 ]
 
 
@@ -95,6 +95,7 @@ def load():
         "dmcx_forces": [P, P, I32],
         "dmcx_potential": [P, P, I32],
         "dmcx_walker_flags": [P, P, I32],
+        "dmcx_reconfigure": [P, P, P, P, I32],
         "dmcx_sync": [P],
         "dmcx_last_run_timing": [P, P, P, P],
         "dmcx_selftest": [P],
@@ -215,6 +216,10 @@ def dmcx_potential(ctx, v, mem):
 
 def dmcx_walker_flags(ctx, flags, mem):
     return load().dmcx_walker_flags(ctx, flags, mem)
+
+
+def dmcx_reconfigure(ctx, u, copies, log_wbar, mem):
+    return load().dmcx_reconfigure(ctx, u, copies, log_wbar, mem)
 
 
 def dmcx_sync(ctx):
@@ -421,6 +426,21 @@ class Context:
         f = np.zeros(self.W, dtype=np.uint8)
         self.check(dmcx_walker_flags(self.h, _ptr(f), DMCX_HOST))
         return f
+
+    def get_step(self):
+        s = C.c_int64(0)
+        self.check(dmcx_get_step(self.h, C.byref(s)))
+        return int(s.value)
+
+    def reconfigure(self, u):
+        """Comb reconfiguration of each system's walkers (fixed population).
+        u: comb offset(s) in [0, 1), one per system.  Returns (copies[W],
+        log_wbar[n_sys])."""
+        uu = np.ascontiguousarray(np.broadcast_to(np.asarray(u, dtype=np.float64), (self.n_sys,)))
+        copies = np.zeros(self.W, dtype=np.int32)
+        lwbar = np.zeros(self.n_sys)
+        self.check(dmcx_reconfigure(self.h, _ptr(uu), _ptr(copies), _ptr(lwbar), DMCX_HOST))
+        return copies, lwbar
 
     def sync(self):
         self.check(dmcx_sync(self.h))

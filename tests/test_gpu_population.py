@@ -1,0 +1,206 @@
+"""Population control on the GPU (comb reconfiguration at fixed population)
+against the oracle.
+
+* Selection: the copies of every walker are bit-exact against the oracle's
+  comb on the same log-weights (integer work; both sides sum the weights in
+  walker order, and the tests assert that no tooth lies within 1e-12 S of a
+  cumulative weight, where the two exp implementations could round apart).
+* State: after the call, every copy carries its source's state.  Further
+  DMC steps from the reconfigured population agree with the oracle run from
+  the copied positions (accept sequence bit-exact, E_L and positions to the
+  FP64 bar), which fails if any copied inverse, orbital row, log|D| or E_L
+  were wrong.  For the mixed and multideterminant forms the measured E_L,
+  log|Psi| and sign of each copy equal its source's bit for bit.
+* Groups (several systems, one offset each), the identity case, zero and
+  non-finite weights, the full 2048-walker workload, and invalid offsets.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_07948_amd import dmcx, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _close(a, b, rel=1e-10, floor=1.0):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    tol = rel * np.maximum(np.maximum(np.abs(a), np.abs(b)), floor)
+    err = np.abs(a - b) / np.maximum(np.maximum(np.abs(a), np.abs(b)), floor)
+    print(f"[population] max rel err {err.max():.2e}", flush=True)
+    assert np.all(np.abs(a - b) <= tol)
+
+
+def _margin(log_w, u):
+    """Smallest distance of a tooth to a cumulative weight, relative to S."""
+    fin = np.isfinite(log_w)
+    m = log_w[fin].max()
+    w = np.where(fin, np.exp(np.where(fin, log_w, 0.0) - m), 0.0)
+    C = np.cumsum(w)
+    S = C[-1]
+    W = len(log_w)
+    t = (np.arange(W) + u) * (S / W)
+    return np.min(np.abs(t[:, None] - C[None, :])) / S
+
+
+def _check_selection(copies, lwbar, log_w, u):
+    assert _margin(log_w, u) > 1e-12, "near tie: choose another offset"
+    ref_c, ref_p, ref_l, rc = oracle.reconfigure(log_w, u)
+    assert rc == 0
+    np.testing.assert_array_equal(copies, ref_c)
+    assert abs(lwbar - ref_l) <= 1e-13 * max(1.0, abs(ref_l))
+    return ref_p
+
+
+def _apply(pairs, X):
+    Y = np.array(X, copy=True)
+    for d, s in pairs:
+        Y[d] = X[s]
+    return Y
+
+
+@pytest.mark.parametrize("k", [1, 4])
+def test_reconfigure_then_run_matches_oracle(k):
+    s = synth.small_molecule()
+    W, tau, seed, et = 37, 0.02, 41, -8.0
+    R0 = synth.make_walkers(s, W, 501)
+    ctx = dmcx.Context(s, W, delay_rank=k, recompute_period=3, tau=tau, seed=seed)
+    ctx.set_walkers(R0)
+    ctx.run(3, mode=dmcx.DMCX_DMC, e_trial=et)
+    R1, lw1 = ctx.get_walkers()
+    step = ctx.get_step()
+    # spread the weights so that the comb has work to do
+    lw1 = lw1 + np.random.default_rng(5).normal(0.0, 0.7, W)
+    ctx.set_walkers(R1, lw1)
+    ctx.set_step(step)
+    e_before, lp_before, sg_before = ctx.measure()
+    u = 0.3141
+    copies, lwbar = ctx.reconfigure(u)
+    pairs = _check_selection(copies, lwbar[0], lw1, u)
+    assert pairs.shape[0] > 0
+    R2, lw2 = ctx.get_walkers()
+    np.testing.assert_array_equal(R2, _apply(pairs, R1))
+    np.testing.assert_array_equal(lw2, np.full(W, lwbar[0]))
+    e_after, lp_after, sg_after = ctx.measure()
+    np.testing.assert_array_equal(e_after, _apply(pairs, e_before))
+    np.testing.assert_array_equal(lp_after, _apply(pairs, lp_before))
+    np.testing.assert_array_equal(sg_after, _apply(pairs, sg_before))
+    # continue: the copied inverses and orbital rows must carry the run on
+    acc, el = ctx.run(3, mode=dmcx.DMCX_DMC, e_trial=et, logs=True)
+    ref = oracle.run(s, R2, log_w=lw2, step0=step, n_steps=3, mode=1, tau=tau, seed=seed,
+                     e_trial=et)
+    np.testing.assert_array_equal(acc, ref["accept_log"])
+    _close(el, ref["e_log"])
+    R3, lw3 = ctx.get_walkers()
+    _close(R3, ref["R"])
+    _close(lw3, ref["log_w"])
+
+
+def test_large_molecule_full_population():
+    """The 2048-walker workload: selection bit-exact for every walker, and
+    every copy's E_L, log|Psi| and sign equal to its source's."""
+    s = synth.large_molecule()
+    W = 2048
+    ctx = dmcx.Context(s, W, delay_rank=32, recompute_period=64, seed=9)
+    ctx.set_walkers(synth.make_walkers(s, W, 2025))
+    ctx.run(1, mode=dmcx.DMCX_DMC, e_trial=-150.0)
+    R1, lw1 = ctx.get_walkers()
+    e_b, lp_b, sg_b = ctx.measure()
+    print(f"[population] log_w spread {lw1.std():.3e}", flush=True)
+    u = 0.61803
+    copies, lwbar = ctx.reconfigure(u)
+    pairs = _check_selection(copies, lwbar[0], lw1, u)
+    print(f"[population] {pairs.shape[0]} walkers replaced", flush=True)
+    R2, _ = ctx.get_walkers()
+    np.testing.assert_array_equal(R2, _apply(pairs, R1))
+    e_a, lp_a, sg_a = ctx.measure()
+    np.testing.assert_array_equal(e_a, _apply(pairs, e_b))
+    np.testing.assert_array_equal(lp_a, _apply(pairs, lp_b))
+    np.testing.assert_array_equal(sg_a, _apply(pairs, sg_b))
+
+
+@pytest.mark.parametrize("form", ["mixed", "msd"])
+def test_copies_carry_state_mixed_and_multideterminant(form):
+    base = synth.small_random_system(77, n_atom=2, n_up=3, n_dn=3, shells=(0, 0, 1, 2), nprim=2,
+                                     n_mo=10)
+    if form == "msd":
+        s = synth.make_msd(base, n_det=15, n_active=6, seed=78)
+        prec = dmcx.DMCX_MIXED
+    else:
+        s = base
+        prec = dmcx.DMCX_MIXED
+    W = 29
+    ctx = dmcx.Context(s, W, precision=prec, delay_rank=2, recompute_period=4, seed=3)
+    ctx.set_walkers(synth.make_walkers(s, W, 79))
+    ctx.run(2, mode=dmcx.DMCX_DMC, e_trial=-4.0)
+    R1, lw1 = ctx.get_walkers()
+    lw1 = lw1 + np.random.default_rng(6).normal(0.0, 1.0, W)
+    step = ctx.get_step()
+    ctx.set_walkers(R1, lw1)
+    ctx.set_step(step)
+    e_b, lp_b, sg_b = ctx.measure()
+    u = 0.77
+    copies, lwbar = ctx.reconfigure(u)
+    pairs = _check_selection(copies, lwbar[0], lw1, u)
+    assert pairs.shape[0] > 0
+    e_a, lp_a, sg_a = ctx.measure()
+    np.testing.assert_array_equal(e_a, _apply(pairs, e_b))
+    np.testing.assert_array_equal(lp_a, _apply(pairs, lp_b))
+    np.testing.assert_array_equal(sg_a, _apply(pairs, sg_b))
+    # and the run continues without flagged walkers
+    ctx.run(2, mode=dmcx.DMCX_DMC, e_trial=-4.0)
+    assert not ctx.walker_flags().any()
+
+
+def test_group_of_systems_one_offset_each():
+    a = synth.small_molecule()
+    b = synth.small_random_system(91, n_atom=2, n_up=2, n_dn=1, shells=(0, 1), nprim=1,
+                                  charge=1.5)
+    Ws = [24, 17]
+    ctx = dmcx.Context([a, b], Ws, delay_rank=1, seed=12)
+    Ra = synth.make_walkers(a, Ws[0], 92)
+    Rb = synth.make_walkers(b, Ws[1], 93)
+    ne = max(a.n_up + a.n_dn, b.n_up + b.n_dn)
+    R = np.zeros((sum(Ws), ne, 3))
+    R[: Ws[0], : a.n_up + a.n_dn] = Ra
+    R[Ws[0]:, : b.n_up + b.n_dn] = Rb
+    lw = np.random.default_rng(13).normal(0.0, 1.2, sum(Ws))
+    ctx.set_walkers(R, lw)
+    u = [0.12, 0.87]
+    copies, lwbar = ctx.reconfigure(u)
+    for i, (o, n) in enumerate(((0, Ws[0]), (Ws[0], Ws[1]))):
+        pairs = _check_selection(copies[o:o + n], lwbar[i], lw[o:o + n], u[i])
+        R2, lw2 = ctx.get_walkers()
+        np.testing.assert_array_equal(R2[o:o + n], _apply(pairs, R[o:o + n]))
+        np.testing.assert_array_equal(lw2[o:o + n], np.full(n, lwbar[i]))
+
+
+def test_identity_and_dead_weights():
+    s = synth.small_molecule()
+    W = 16
+    R = synth.make_walkers(s, W, 301)
+    ctx = dmcx.Context(s, W)
+    ctx.set_walkers(R, np.full(W, -1.25))
+    copies, lwbar = ctx.reconfigure(0.5)
+    np.testing.assert_array_equal(copies, np.ones(W))
+    assert abs(lwbar[0] + 1.25) < 1e-15
+    np.testing.assert_array_equal(ctx.get_walkers()[0], R)
+    lw = np.linspace(-1.0, 1.0, W)
+    lw[[2, 7]] = -np.inf
+    lw[5] = np.nan
+    ctx.set_walkers(R, lw)
+    copies, lwbar = ctx.reconfigure(0.25)
+    assert copies[2] == 0 and copies[5] == 0 and copies[7] == 0
+    _check_selection(copies, lwbar[0], lw, 0.25)
+
+
+def test_invalid_offset_rejected():
+    s = synth.small_molecule()
+    ctx = dmcx.Context(s, 8)
+    ctx.set_walkers(synth.make_walkers(s, 8, 1))
+    for u in (-0.5, 1.0, math.nan):
+        with pytest.raises(dmcx.DmcxError):
+            ctx.reconfigure(u)
