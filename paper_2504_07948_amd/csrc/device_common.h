@@ -126,6 +126,11 @@ __device__ inline void move_draws_lanes64(uint64_t seed, uint32_t step, uint32_t
   uacc = __shfl(u0, 2, 64);
 }
 
+// Index of the calling wave within its workgroup, as a scalar (wave-uniform
+// tests on it compile to scalar branches, addresses built from it to scalar
+// arithmetic).
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // ---------------------------------------------------------- reductions ----
 // Sum over the 32 lanes of one walker group (aligned halves of a wave).
 __device__ __forceinline__ double sum32(double v) {

@@ -128,7 +128,7 @@ __global__ __launch_bounds__(NT_FORCE) void k_ion_grad_det(DevCtx c, double *par
   const int ntile = (c.ne + FPTS - 1) / FPTS;
   const int w = blockIdx.x / ntile, tile = blockIdx.x % ntile;
   const int e0 = tile * FPTS, npts = min(FPTS, c.ne - e0);
-  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wid = wave_id(), lane = tid & 63;
   const int kq = lane >> 4, cl = lane & 15;
   const T *Cp;
   if constexpr (sizeof(T) == 8) Cp = (const T *)c.B.Cp; else Cp = (const T *)c.B.Cp32;

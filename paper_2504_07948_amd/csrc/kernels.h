@@ -391,33 +391,37 @@ __device__ __forceinline__ void load_stage_a(const T *Cp, int fn_begin, int ob0,
 }
 
 // This wave's K-steps of one stage: acc[q][cb] += A(block) * B(column block).
-// B operands come from LDS one K-step ahead of the MFMAs that use them.
+// B operands come from LDS one K-step ahead of the MFMAs that use them.  The
+// K-step and block tests use wave-uniform values read into scalars (scalar
+// branches, no exec-mask work); the look-ahead read is unconditional (every
+// row it touches lies inside the stage buffer, and rows past the stage are
+// never multiplied), so the unrolled K-steps need no operand copies.
 template <typename T, int NOB, int KH>
 __device__ __forceinline__ void mfma_stage(typename Acc4<T>::type (&acc)[(NOB + 3) / 4][NCB],
                                            const T (&a)[(NOB + 3) / 4][KH], const T *Bsb, int nk,
                                            int ob0, int kh, int kq, int col) {
   constexpr int NQ = (NOB + 3) / 4;
-  if (kh >= nk) return;
-  const T *bbase = Bsb + (4 * kh + kq) * NCOL + col;
-  T bn[NCB];
+  const int khs = __builtin_amdgcn_readfirstlane(kh);
+  const int nks = __builtin_amdgcn_readfirstlane(nk);
+  const int obs = __builtin_amdgcn_readfirstlane(ob0);
+  if (khs >= nks) return;
+  const T *bbase = Bsb + (4 * khs + kq) * NCOL + col;
+  T bv[KH][NCB];
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) bn[cb] = bbase[16 * cb];
+  for (int cb = 0; cb < NCB; ++cb) bv[0][cb] = bbase[16 * cb];
 #pragma unroll
   for (int i = 0; i < KH; ++i) {
-    if (NKH * i + kh < nk) {
-      T b[NCB];
+    if (i + 1 < KH) {
+      const T *brow = bbase + 4 * NKH * (i + 1) * NCOL;
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) b[cb] = bn[cb];
-      if (NKH * (i + 1) + kh < nk) {
-        const T *brow = bbase + 4 * NKH * (i + 1) * NCOL;
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) bn[cb] = brow[16 * cb];
-      }
+      for (int cb = 0; cb < NCB; ++cb) bv[i + 1][cb] = brow[16 * cb];
+    }
+    if (NKH * i + khs < nks) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        if (NOB % 4 == 0 || ob0 + 4 * q < NOB) {
+        if (NOB % 4 == 0 || obs + 4 * q < NOB) {
 #pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) acc[q][cb] = mfma16x16x4(a[q][i], b[cb], acc[q][cb]);
+          for (int cb = 0; cb < NCB; ++cb) acc[q][cb] = mfma16x16x4(a[q][i], bv[i][cb], acc[q][cb]);
         }
       }
     }
@@ -442,7 +446,7 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
   constexpr int KH = KS / NKH;
   constexpr int FM = 4 * KS;
   typedef typename Acc4<T>::type acc_t;
-  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wid = wave_id(), lane = tid & 63;
   const int ob0 = wid & 3, kh = wid >> 2;
   const int kq = lane >> 4, col = lane & 15;
   const int S = c.B.n_stage;
@@ -746,7 +750,7 @@ __global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int measure_o
   __shared__ double part[NT_AUX / 64][3];
   __shared__ double msx_le[NT_AUX / 64][4 * MSD_NV_MAX];  // MSD: w (3 rows) and y per wave
   const int w = blockIdx.x;
-  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wid = wave_id(), lane = tid & 63;
   const int NP = c.NP;
   const double *Rw = c.R + (size_t)w * c.ne * 3;
   double kin = 0.0, pot = 0.0, jv = 0.0;
@@ -915,7 +919,7 @@ __device__ __forceinline__ typename Acc4<T>::type mfma_tile(int K, FA fa, FB fb)
 template <typename T, int NOB>
 __device__ void flush_block(const DevCtx &c, int w0, int sp, int kb) {
   constexpr int NP = NOB * 16;
-  const int tid = threadIdx.x, wid = tid >> 6;
+  const int tid = threadIdx.x, wid = wave_id();
   const int lane = tid & 63, kq = lane >> 4, cl = lane & 15;
   const int K = c.K;
   const int KBP = (kb + 15) & ~15;
@@ -1132,7 +1136,7 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
   __shared__ T crow[TW][KMAX];
   __shared__ double s_S[TW], s_C0[TW];
   const int tid = threadIdx.x;
-  const int ws = tid >> 6, t = tid & 63;  // one wave per walker
+  const int ws = wave_id(), t = tid & 63;  // one wave per walker
   const int w = blockIdx.x * TW + ws;
   double *Rw = c.R + (size_t)w * c.ne * 3;
   T *Gb = (T *)c.Gb + blk_off(c, w);
@@ -1420,7 +1424,7 @@ __global__ __launch_bounds__(NT_TILE) void k_ratio_grad(DevCtx c, int i, int m,
   __shared__ T Bs0[FM * NCOL], Bs1[FM * NCOL];
   __shared__ T vnew[TW * 5 * NP];
   __shared__ double pts[TW][3];
-  const int tid = threadIdx.x, ws = tid >> 6, t = tid & 63;
+  const int tid = threadIdx.x, ws = wave_id(), t = tid & 63;
   const int w = blockIdx.x * TW + ws;
   if (tid < TW * 3) {
     const int q = min((int)(blockIdx.x * TW) + tid / 3, c.W - 1);

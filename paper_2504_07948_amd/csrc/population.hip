@@ -18,24 +18,35 @@ constexpr int NT_SEL = 1024;
 constexpr int NT_COPY = 256;
 constexpr int COPY_SPLIT = 8;  // workgroups sharing one walker's copy
 
-// Block-wide inclusive scan of one int per thread (NT_SEL threads).
+// Block-wide inclusive scan of one int per thread (NT_SEL threads): a scan
+// within each wave, then wave 0 scans the wave totals (three barriers).
 __device__ int block_scan_incl(int v, int *sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int o = 1; o < NT_SEL; o <<= 1) {
-    const int a = t >= o ? sh[t - o] : 0;
-    __syncthreads();
-    sh[t] += a;
-    __syncthreads();
+  constexpr int NWV = NT_SEL / 64;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(v, o, 64);
+    if (lane >= o) v += y;
   }
-  const int r = sh[t];
+  if (lane == 63) sh[wv] = v;
+  __syncthreads();
+  if (wv == 0) {
+    int x = lane < NWV ? sh[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < NWV; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane < NWV) sh[lane] = x;
+  }
+  __syncthreads();
+  const int r = v + (wv > 0 ? sh[wv - 1] : 0);
   __syncthreads();
   return r;
 }
 
 __global__ __launch_bounds__(NT_SEL) void k_pop_select(DevCtx c, double u, PopScratch p) {
-  __shared__ int sh[NT_SEL];
+  __shared__ int sh[NT_SEL / 64];
   __shared__ double cw[NT_SEL];  // one chunk of weights, then of cumulative sums
   __shared__ double red[NT_SEL / 64];
   __shared__ double s_m, s_S;
