@@ -88,9 +88,11 @@ __host__ __device__ constexpr int stage_ksteps(int nob) {
   return NKH == 2 ? (nob <= 4 ? 24 : 12) : (nob <= 4 ? 12 : 6);
 }
 
-// Basis work of one shell is split into this many lane tasks (s: whole
-// shell; p: components {x, y} and {z}; d: pairs of the six components).
-__host__ __device__ constexpr int shell_split(int l) { return l == 0 ? 1 : (l == 1 ? 2 : 3); }
+// Basis work of one shell is split into this many lane tasks (s and p: the
+// whole shell; d: components {xx, xy, xz} and {yy, yz, zz}).  Every task
+// evaluates its shell's radial part, so fewer tasks per shell means fewer
+// repeated exponentials; a stage still fits one task per thread.
+__host__ __device__ constexpr int shell_split(int l) { return l == 2 ? 2 : 1; }
 
 // Largest number of 4-shell groups of angular momentum l in one stage, so
 // that a stage has at most one basis task per thread and fits the stage's
@@ -277,8 +279,8 @@ __device__ __forceinline__ void store_vgl(T *dst, T x, T y, T z, T s2, T R0, T R
 
 // Basis values of one stage (groups g_begin..g_end, all with angular
 // momentum L and NPR primitives) at the tile's points into Bs[f][w*5 + q].
-// Tasks: s -> (point, shell); p -> (point, shell, {x,y} or {z});
-// d -> (point, shell, one of three component pairs).  A task evaluates its
+// Tasks: s and p -> (point, shell); d -> (point, shell, {xx, xy, xz} or
+// {yy, yz, zz}).  A task evaluates its
 // shell's radial part (NPR independent exponentials) and its components.
 template <typename T, int L, int NPR>
 __device__ void basis_stage_t(const BasisLDS &B, int g_begin, int g_end, int fn_begin,
@@ -322,20 +324,16 @@ __device__ void basis_stage_t(const BasisLDS &B, int g_begin, int g_end, int fn_
     if constexpr (L == 0) {
       store_vgl<T, 0, 0>(base, x, y, z, s2, R0, R1, R2);
     } else if constexpr (L == 1) {
-      if (part == 0) {
-        store_vgl<T, 1, 0>(base, x, y, z, s2, R0, R1, R2);
-        store_vgl<T, 1, 1>(base + 4 * NCOL, x, y, z, s2, R0, R1, R2);
-      } else {
-        store_vgl<T, 1, 2>(base + 8 * NCOL, x, y, z, s2, R0, R1, R2);
-      }
+      store_vgl<T, 1, 0>(base, x, y, z, s2, R0, R1, R2);
+      store_vgl<T, 1, 1>(base + 4 * NCOL, x, y, z, s2, R0, R1, R2);
+      store_vgl<T, 1, 2>(base + 8 * NCOL, x, y, z, s2, R0, R1, R2);
     } else {
       if (part == 0) {
         store_vgl<T, 2, 0>(base, x, y, z, s2, R0, R1, R2);
         store_vgl<T, 2, 1>(base + 4 * NCOL, x, y, z, s2, R0, R1, R2);
-      } else if (part == 1) {
         store_vgl<T, 2, 2>(base + 8 * NCOL, x, y, z, s2, R0, R1, R2);
-        store_vgl<T, 2, 3>(base + 12 * NCOL, x, y, z, s2, R0, R1, R2);
       } else {
+        store_vgl<T, 2, 3>(base + 12 * NCOL, x, y, z, s2, R0, R1, R2);
         store_vgl<T, 2, 4>(base + 16 * NCOL, x, y, z, s2, R0, R1, R2);
         store_vgl<T, 2, 5>(base + 20 * NCOL, x, y, z, s2, R0, R1, R2);
       }
