@@ -539,32 +539,75 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
 // ---------------------------------------------------------- Jastrow ----
 // Lane-partial sums for electron i at position r against the other
 // electrons of walker positions Rw and all ions: value u and gradient g.
+// BATCHED: three partners per lane and round, their loads issued before the
+// arithmetic (the single-determinant sweeps); otherwise one partner per
+// iteration (the multideterminant sweep, where the batched form measured
+// slower).
+template <bool BATCHED = false>
 __device__ __forceinline__ void jastrow_one_partial(const DevCtx &c, const double *Rw, int i,
                                                     const double r[3], int t, int nt, double &u,
                                                     double g[3]) {
-  const int si = i < c.n_up ? 0 : 1;
-  for (int j = t; j < c.ne + c.n_atom; j += nt) {
-    const double *p;
-    double a, b;
-    if (j < c.ne) {
-      if (j == i) continue;
-      p = Rw + 3 * j;
-      a = ((j < c.n_up ? 0 : 1) == si) ? c.jee_para : c.jee_anti;
-      b = c.jee_b;
-    } else {
-      const int A = j - c.ne;
-      p = c.ion + 3 * A;
-      a = c.jen_a[A];
-      b = c.jen_b;
+  if constexpr (BATCHED) {
+    const int si = i < c.n_up ? 0 : 1;
+    const int N = c.ne + c.n_atom;
+    // three partners per lane and round: their loads go out together (a clamped
+    // index and a branch-free address select), then the terms are added for
+    // the partners that exist and differ from i
+    for (int j0 = t; j0 < N; j0 += 3 * nt) {
+      double px[3], py[3], pz[3], pa[3], pb[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int jc = min(j0 + q * nt, N - 1);
+        const bool el = jc < c.ne;
+        const int A = el ? 0 : jc - c.ne;
+        const double *p = el ? Rw + 3 * jc : c.ion + 3 * A;
+        px[q] = p[0];
+        py[q] = p[1];
+        pz[q] = p[2];
+        const double aen = c.jen_a[A];
+        pa[q] = el ? (((jc < c.n_up ? 0 : 1) == si) ? c.jee_para : c.jee_anti) : aen;
+        pb[q] = el ? c.jee_b : c.jen_b;
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int j = j0 + q * nt;
+        if (j < N && j != i) {
+          const double dx = r[0] - px[q], dy = r[1] - py[q], dz = r[2] - pz[q];
+          const double rr = sqrt(dx * dx + dy * dy + dz * dz);
+          const Pade pd = pade(pa[q], pb[q], rr);
+          const double f = pd.d1 / rr;
+          u += pd.u;
+          g[0] += f * dx;
+          g[1] += f * dy;
+          g[2] += f * dz;
+        }
+      }
     }
-    const double dx = r[0] - p[0], dy = r[1] - p[1], dz = r[2] - p[2];
-    const double rr = sqrt(dx * dx + dy * dy + dz * dz);
-    const Pade pd = pade(a, b, rr);
-    const double f = pd.d1 / rr;
-    u += pd.u;
-    g[0] += f * dx;
-    g[1] += f * dy;
-    g[2] += f * dz;
+  } else {
+    const int si = i < c.n_up ? 0 : 1;
+    for (int j = t; j < c.ne + c.n_atom; j += nt) {
+      const double *p;
+      double a, b;
+      if (j < c.ne) {
+        if (j == i) continue;
+        p = Rw + 3 * j;
+        a = ((j < c.n_up ? 0 : 1) == si) ? c.jee_para : c.jee_anti;
+        b = c.jee_b;
+      } else {
+        const int A = j - c.ne;
+        p = c.ion + 3 * A;
+        a = c.jen_a[A];
+        b = c.jen_b;
+      }
+      const double dx = r[0] - p[0], dy = r[1] - p[1], dz = r[2] - p[2];
+      const double rr = sqrt(dx * dx + dy * dy + dz * dz);
+      const Pade pd = pade(a, b, rr);
+      const double f = pd.d1 / rr;
+      u += pd.u;
+      g[0] += f * dx;
+      g[1] += f * dy;
+      g[2] += f * dz;
+    }
   }
 }
 
@@ -1059,10 +1102,26 @@ __device__ void block_accept(const DevCtx &c, int w, int t, int i, int sp, int m
       }
       // Row m of M = (I + L)^{-1} (L strictly lower, L[m][p] = C[m][p]):
       // M[m][q] = -sum_{p=q}^{m-1} C[m][p] M[p][q]; lane q owns column q.
+      // Eight terms per round (their loads issued together; past m the row
+      // index is clamped and the weight is zero), so a column costs at most
+      // ceil(m / 8) memory round trips instead of m.
       for (int q = t; q < m; q += 64) {
-        double s = 0.0;
-        for (int p = q; p < m; ++p) s += (double)crow_w[p] * (double)Ms[p * c.K + q];
-        Ms[m * c.K + q] = (T)(-s);
+        double s0 = 0.0, s1 = 0.0;
+        for (int p0 = q; p0 < m; p0 += 8) {
+          T mv[8], cv[8];
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const int pr = p0 + r < m ? p0 + r : q;
+            mv[r] = Ms[pr * c.K + q];
+            cv[r] = p0 + r < m ? crow_w[pr] : (T)0;
+          }
+#pragma unroll
+          for (int r = 0; r < 8; r += 2) {
+            s0 += (double)cv[r] * (double)mv[r];
+            s1 += (double)cv[r + 1] * (double)mv[r + 1];
+          }
+        }
+        Ms[m * c.K + q] = (T)(-(s0 + s1));
       }
       if (t == 0) Ms[m * c.K + m] = (T)1;
       for (int j = t; j < NP; j += 64) Gb[m * NP + j] = (T)((double)colm_w[j] * irho);
@@ -1173,7 +1232,7 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
     }
     double ro[3] = {Rw[3 * i], Rw[3 * i + 1], Rw[3 * i + 2]};
     double uo = 0.0, gj[3] = {0.0, 0.0, 0.0};
-    jastrow_one_partial(c, Rw, i, ro, t, 64, uo, gj);
+    jastrow_one_partial<!MSD>(c, Rw, i, ro, t, 64, uo, gj);
     gd0 = sum64(gd0); gd1 = sum64(gd1); gd2 = sum64(gd2);
     uo = sum64(uo); gj[0] = sum64(gj[0]); gj[1] = sum64(gj[1]); gj[2] = sum64(gj[2]);
     double gs[3] = {0.0, 0.0, 0.0};  // grad_i S / S (MSD)
@@ -1257,7 +1316,7 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
     }
     const double rn[3] = {pts[ws][0], pts[ws][1], pts[ws][2]};
     double un = 0.0, gjn[3] = {0.0, 0.0, 0.0};
-    jastrow_one_partial(c, Rw, i, rn, t, 64, un, gjn);
+    jastrow_one_partial<!MSD>(c, Rw, i, rn, t, 64, un, gjn);
     rho = sum64(rho); gn0 = sum64(gn0); gn1 = sum64(gn1); gn2 = sum64(gn2);
     un = sum64(un); gjn[0] = sum64(gjn[0]); gjn[1] = sum64(gjn[1]); gjn[2] = sum64(gjn[2]);
     // rho is the reference determinant's ratio; rho_all includes S'/S (MSD)
