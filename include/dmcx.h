@@ -115,45 +115,67 @@ dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *wa
                         const dmcx_options *opt, void *hip_stream, dmcx_ctx **out);
 void dmcx_destroy(dmcx_ctx *ctx);
 
-/* R: [W][N_e][3] positions; log_w: [W] log-weights or NULL (= all zero).
+/* Passage: QMC section, Eq. 2 (the trial function evaluated at each walker's
+ * configuration) and Eq. 1 (each walker carries the weight of the projection).
+ * R: [W][N_e][3] positions; log_w: [W] log-weights or NULL (= all zero).
  * Evaluates all orbitals, recomputes every inverse in FP64 (LU) and the
  * local energy of each walker.  Resets the step counter to 0. */
 dmcx_status dmcx_set_walkers(dmcx_ctx *ctx, const double *R, const double *log_w, dmcx_mem mem);
 dmcx_status dmcx_get_walkers(dmcx_ctx *ctx, double *R, double *log_w, dmcx_mem mem);
 
-/* Step counter used as the Philox counter's step field (checkpoint/resume). */
+/* Step counter used as the Philox counter's step field (checkpoint/resume: a
+ * run resumed with dmcx_set_walkers + dmcx_set_step at the saved step draws
+ * the same random numbers as an uninterrupted one).  The paper does not fix
+ * the random stream; these calls carry no physics. */
 dmcx_status dmcx_set_step(dmcx_ctx *ctx, int64_t step);
 dmcx_status dmcx_get_step(const dmcx_ctx *ctx, int64_t *step);
 
-/* Replace the ion coordinates of system sys_index ([n_atom][3]) and
+/* Passage: Single Determinant QMC Forces (the ion coordinates R_a that Eq. 3
+ * and Eq. 4 differentiate).
+ * Replace the ion coordinates of system sys_index ([n_atom][3]) and
  * re-evaluate orbitals, inverses and local energies at the current walkers. */
 dmcx_status dmcx_set_ions(dmcx_ctx *ctx, int32_t sys_index, const double *ion_xyz, dmcx_mem mem);
 
-/* Apply pending delayed updates, then rebuild every inverse from the cached
+/* Passage: Single Determinant QMC Forces (A_ij = phi_j(r_i) and its inverse,
+ * Eq. 3); ln|D| and its sign enter Eq. 2.
+ * Apply pending delayed updates, then rebuild every inverse from the cached
  * orbital rows with an FP64 LU (partial pivoting); resets log|D| and sign.
  * DMCX_E_SINGULAR if any walker's matrix had a zero pivot. */
 dmcx_status dmcx_recompute(dmcx_ctx *ctx);
 
-/* Orbitals of the given spin at one point per walker: r [W][3] ->
+/* Passage: QMC section, Eq. 2 (phi_i = sum_l C_l^i Phi_l, with the value,
+ * gradient and Laplacian of every orbital).
+ * Orbitals of the given spin at one point per walker: r [W][3] ->
  * vgl [W][5][n_sigma_max] (n_sigma_max = largest n_up/n_dn over systems). */
 dmcx_status dmcx_eval_orbitals(dmcx_ctx *ctx, int32_t spin, const double *r, double *vgl,
                                dmcx_mem mem);
 
-/* Ratio Psi(R')/Psi(R) for moving electron iel of every walker to r_new
+/* Passage: Single Determinant QMC Forces, Eq. 3 with lambda = the moved
+ * electron's coordinate (the ratio det(A')/det(A) is the row of A' dotted
+ * with a column of A^{-1}; the drift is tr(A^{-1} dA/dr)), times the Jastrow
+ * factor of Eq. 2.
+ * Ratio Psi(R')/Psi(R) for moving electron iel of every walker to r_new
  * [W][3] (Jastrow included) and grad_{iel} ln|Psi(R')| [W][3].  The proposal
  * is kept for the next dmcx_accept.  Uses the delayed-updated inverse:
  * consecutive electrons of one spin form blocks of delay_rank moves. */
 dmcx_status dmcx_ratio_grad(dmcx_ctx *ctx, int32_t iel, const double *r_new, double *ratio,
                             double *grad, dmcx_mem mem);
 
-/* accept [W] (0/1) for the proposal of the last dmcx_ratio_grad(iel).
+/* Passage: QMC section, Eq. 1 under the fixed-node constraint (the accepted
+ * move changes one row of A of Eq. 3, so A^{-1} changes by rank one).
+ * accept [W] (0/1) for the proposal of the last dmcx_ratio_grad(iel).
  * Accepted walkers move electron iel; inverses are updated (delayed). */
 dmcx_status dmcx_accept(dmcx_ctx *ctx, int32_t iel, const uint8_t *accept, dmcx_mem mem);
 
-/* Apply all pending delayed updates now (rank-k GEMM flush). */
+/* Passage: Single Determinant QMC Forces (the inverse A^{-1} of Eq. 3 after
+ * the accepted moves; the rank-k form is the published Woodbury identity).
+ * Apply all pending delayed updates now (rank-k GEMM flush). */
 dmcx_status dmcx_flush(dmcx_ctx *ctx);
 
-/* Run n_steps full sweeps (every electron proposes one drift-diffusion move
+/* Passage: QMC section, Eq. 1 (imaginary-time projection as drift-diffusion
+ * moves with fixed-node rejection and weights), trial function of Eq. 2,
+ * walker-level batching of QMC Energy and Wavefunction Evaluation.
+ * Run n_steps full sweeps (every electron proposes one drift-diffusion move
  * per step, up electrons then down).  DMCX_DMC rejects node crossings and
  * updates log-weights with E_T = e_trial; DMCX_VMC leaves weights alone.
  * accept_log [n_steps][W][N_e] (uint8) and e_log [n_steps][W] may be NULL;
@@ -168,7 +190,9 @@ dmcx_status dmcx_flush(dmcx_ctx *ctx);
 dmcx_status dmcx_run(dmcx_ctx *ctx, dmcx_mode mode, int32_t n_steps, double e_trial,
                      uint8_t *accept_log, double *e_log, dmcx_mem mem);
 
-/* Delay-rank autotuner: for every system, time `steps` sweeps (after one
+/* Passage: QMC Energy and Wavefunction Evaluation (batching chosen to keep
+ * the GPU busy); the delay rank itself is not in the paper.
+ * Delay-rank autotuner: for every system, time `steps` sweeps (after one
  * untimed sweep) at each candidate rank k in {8, 16, 24, 32, 48, 64} below
  * n_sigma plus n_sigma itself, limited to the rank the buffers were sized
  * for at create (min(64, n_sigma) with delay_rank == 0, else delay_rank),
@@ -186,34 +210,70 @@ dmcx_status dmcx_autotune_report(const dmcx_ctx *ctx, int32_t sys_index, int32_t
 /* Delay rank currently used by system sys_index. */
 dmcx_status dmcx_get_delay_rank(const dmcx_ctx *ctx, int32_t sys_index, int32_t *k);
 
-/* Current local energy, log|Psi| and sign of every walker ([W] each;
+/* Passage: QMC section, Eq. 2 (log|Psi_T| and sign) and Single Determinant
+ * QMC Forces (E_L through tr(A^{-1} B) with B the Laplacian rows, Eq. 3).
+ * Current local energy, log|Psi| and sign of every walker ([W] each;
  * any pointer may be NULL). */
 dmcx_status dmcx_measure(dmcx_ctx *ctx, double *e_local, double *log_psi, int8_t *sign,
                          dmcx_mem mem);
 
-/* Coulomb potential V(R) of each walker's current configuration, [W]
+/* Passage: QMC section (the many-body Hamiltonian's potential; its ion
+ * derivative is the Hellmann-Feynman term of Single Determinant QMC Forces).
+ * Coulomb potential V(R) of each walker's current configuration, [W]
  * (electron-electron + electron-ion + ion-ion). */
 dmcx_status dmcx_potential(dmcx_ctx *ctx, double *v, dmcx_mem mem);
 
-/* Per-walker ion derivatives: dlogpsi_dR and dV_dR, [W][n_atom_max][3]
+/* Passage: Single Determinant QMC Forces, Eq. 3 with lambda = an ion
+ * coordinate R_a (Pulay term) and dV/dR_a (Hellmann-Feynman term);
+ * Multideterminant QMC Forces for n_det > 1.
+ * Per-walker ion derivatives: dlogpsi_dR and dV_dR, [W][n_atom_max][3]
  * (either may be NULL).  Reverse-mode adjoint of basis, MO contraction,
  * log-determinant and Jastrow (Eq. 3 with lambda = an ion coordinate). */
 dmcx_status dmcx_ion_grads(dmcx_ctx *ctx, double *dlogpsi_dR, double *dV_dR, dmcx_mem mem);
 
-/* Vector-Jacobian products over walkers: grad_R[n_atom_max][3] (per system
+/* Passage: Single Determinant QMC Forces, Eq. 3 (the same derivatives as
+ * dmcx_ion_grads, contracted with a caller's cotangent per walker).
+ * Vector-Jacobian products over walkers: grad_R[n_atom_max][3] (per system
  * when n_sys > 1: [n_sys][n_atom_max][3]) = sum_w gbar[w] d(.)_w/dR. */
 dmcx_status dmcx_logpsi_vjp(dmcx_ctx *ctx, const double *gbar, double *grad_R, dmcx_mem mem);
 dmcx_status dmcx_potential_vjp(dmcx_ctx *ctx, const double *gbar, double *grad_R, dmcx_mem mem);
 
-/* Hellmann-Feynman + Pulay force estimate from the current walkers,
+/* Passage: Single Determinant QMC Forces (force estimator built from Eq. 3)
+ * with the walker weights of Eq. 1.
+ * Hellmann-Feynman + Pulay force estimate from the current walkers,
  * weighted by exp(log_w): F = -<dV/dR> - 2(<E_L dlnPsi/dR> - <E_L><dlnPsi/dR>).
  * F: [n_sys][n_atom_max][3]. */
 dmcx_status dmcx_forces(dmcx_ctx *ctx, double *F, dmcx_mem mem);
 
-/* Per-walker status bits [W]: 1 = non-finite value, 2 = singular matrix. */
+/* Passage: QMC section, Eq. 1 (the walker weights of the projection) and the
+ * fixed-node DMC estimators built on them.
+ * Weighted estimators of each system's walkers, in FP64: out[n_sys][11] with
+ *   [0]  walkers counted (finite log w and E_L, no status flag),
+ *   [1]  m = largest log w of those walkers (the log-sum-exp shift),
+ *   [2]  S0 = sum omega,  omega = exp(log w - m),
+ *   [3]  S1 = sum omega E_L,  [4] S2 = sum omega E_L^2,  [5] Q = sum omega^2,
+ *   [6]  <E_L> = S1 / S0 (the weighted mixed energy estimate),
+ *   [7]  weighted variance of E_L, from centred moments merged block by block
+ *        (never S2/S0 - <E_L>^2),
+ *   [8]  smallest log w of the counted walkers,
+ *   [9]  acceptance ratio: accepted / proposed moves since the previous
+ *        dmcx_estimators call (or dmcx_set_walkers); NaN if none,
+ *   [10] moves proposed in that span (dmcx_run sweeps and dmcx_accept calls).
+ * log of the total weight is m + log S0; the effective walker count is
+ * S0^2 / Q.  With no walker counted, [1]..[8] are NaN.  The call clears the
+ * move counters.  It enqueues two kernels on the context's stream and
+ * allocates nothing; with DMCX_DEVICE it does not synchronise (out is
+ * written in stream order).  Errors: DMCX_E_STATE (walkers not set). */
+#define DMCX_N_ESTIMATORS 11
+dmcx_status dmcx_estimators(dmcx_ctx *ctx, double *out, dmcx_mem mem);
+
+/* Per-walker status bits [W]: 1 = non-finite value, 2 = singular matrix
+ * (a zero pivot of A of Eq. 3 in the FP64 recompute).  Bits stay set until
+ * the next dmcx_set_walkers. */
 dmcx_status dmcx_walker_flags(dmcx_ctx *ctx, uint8_t *flags, dmcx_mem mem);
 
-/* Population control at fixed population: comb reconfiguration of each
+/* Passage: QMC section, Eq. 1 (walker weights of the projection).
+ * Population control at fixed population: comb reconfiguration of each
  * system's walkers by their DMC weights (the weights of Eq. 1; the paper does
  * not fix the control scheme, this is the published systematic resampling).
  * For system s with W_s walkers: w_j = exp(log_w_j - m), m the largest finite

@@ -253,3 +253,34 @@ def reconfigure(log_w, u):
     rc = _load().orc_reconfigure(W, _ptr(lw), float(u), _ptr(copies), _ptr(pairs), C.byref(n),
                                  C.byref(lwbar))
     return copies, pairs[: n.value].copy(), float(lwbar.value), rc
+
+
+def estimators(log_w, e_local, flags=None, n_accepted=0, n_proposed=0):
+    """Weighted walker estimators of the fixed-node DMC population (QMC section,
+    Eq. 1: each walker carries the weight w = exp(log w)), written out from their
+    definitions with numpy.  A walker counts when log w and E_L are finite and its
+    status flag (if given) is zero.  m is the largest counted log w and
+    omega = exp(log w - m).  Returns the 11 numbers
+      [n, m, sum omega, sum omega E, sum omega E^2, sum omega^2,
+       <E> = sum omega E / sum omega,
+       var = sum omega (E - <E>)^2 / sum omega,
+       min log w, accepted / proposed, proposed]
+    (NaN where undefined).  The move counts are passed in: they are counts of the
+    accept decisions of the run, not arithmetic of the method."""
+    lw = np.asarray(log_w, dtype=np.float64)
+    e = np.asarray(e_local, dtype=np.float64)
+    ok = np.isfinite(lw) & np.isfinite(e)
+    if flags is not None:
+        ok &= np.asarray(flags) == 0
+    nan = float("nan")
+    acc = float(n_accepted) / float(n_proposed) if n_proposed else nan
+    if not ok.any():
+        return np.array([0.0, nan, nan, nan, nan, nan, nan, nan, nan, acc, float(n_proposed)])
+    lw, e = lw[ok], e[ok]
+    m = lw.max()
+    om = np.exp(lw - m)
+    s0 = om.sum()
+    mean = (om * e).sum() / s0
+    var = (om * (e - mean) ** 2).sum() / s0
+    return np.array([float(ok.sum()), m, s0, (om * e).sum(), (om * e * e).sum(), (om * om).sum(),
+                     mean, var, lw.min(), acc, float(n_proposed)])

@@ -1,51 +1,58 @@
 """torch.autograd.Function over the library's ion-coordinate adjoint.
 
 ``IonGradFn.apply(ion_xyz, ctx)`` moves the ions of a dmcx Context to
-``ion_xyz`` (re-evaluating orbitals, inverses and local energies at the
-current walkers) and returns per-walker ``(log_psi, v_pot, e_local)``.  The
+``ion_xyz`` (the library re-evaluates orbitals, inverses and local energies at
+the current walkers) and returns per-walker ``(log_psi, v_pot, e_local)``.  The
 backward pass calls the library's hand-written reverse-mode adjoint
 (dmcx_logpsi_vjp / dmcx_potential_vjp): Eq. 3 of arXiv 2504.07948 with
 lambda = an ion coordinate, i.e. the Pulay term through basis, MO
 contraction, log-determinant and Jastrow, plus the Hellmann-Feynman term
 through V.  E_L is returned as a non-differentiable output.
 
-With walker weights omega and E_L held fixed, the force estimate
-F = -<dV/dR> - 2 (<E_L dlnPsi/dR> - <E_L><dlnPsi/dR>) is minus the gradient of
-``force_objective(log_psi, v_pot, e_local, omega)``.
+This module only marshals arguments.  With CUDA tensors every buffer is handed
+to the library as a device pointer on the context's stream (the caller keeps
+torch's current stream equal to the stream the context was created on), so
+nothing crosses to the host; CPU tensors are passed as host buffers.
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
+
+from . import dmcx
+
+
+def _f64(t):
+    return t.detach().to(torch.float64).contiguous()
 
 
 class IonGradFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, ion_xyz, dmc):
-        dmc.set_ions(ion_xyz.detach().to("cpu", torch.float64).numpy())
-        e, lp, _ = dmc.measure()
-        v = dmc.potential()
+        dev = ion_xyz.device
+        ion = _f64(ion_xyz)
+        mem = dmcx.DMCX_DEVICE if ion.is_cuda else dmcx.DMCX_HOST
+        dmc.check(dmcx.dmcx_set_ions(dmc.h, 0, ion.data_ptr(), mem))
+        e = torch.empty(dmc.W, dtype=torch.float64, device=dev)
+        lp = torch.empty_like(e)
+        v = torch.empty_like(e)
+        dmc.check(dmcx.dmcx_measure(dmc.h, e.data_ptr(), lp.data_ptr(), None, mem))
+        dmc.check(dmcx.dmcx_potential(dmc.h, v.data_ptr(), mem))
         ctx.dmc = dmc
-        ctx.device = ion_xyz.device
-        out = [torch.from_numpy(a).to(ion_xyz.device) for a in (lp, v, e)]
-        ctx.mark_non_differentiable(out[2])
-        return out[0], out[1], out[2]
+        ctx.keep = ion  # the library reads it in stream order
+        ctx.mark_non_differentiable(e)
+        return lp, v, e
 
     @staticmethod
     def backward(ctx, g_lp, g_v, g_e):
         dmc = ctx.dmc
-        grad = np.zeros((dmc.n_atom, 3))
-        if g_lp is not None:
-            grad += dmc.logpsi_vjp(g_lp.detach().to("cpu", torch.float64).numpy())
-        if g_v is not None:
-            grad += dmc.potential_vjp(g_v.detach().to("cpu", torch.float64).numpy())
-        return torch.from_numpy(grad).to(ctx.device), None
-
-
-def force_objective(log_psi, v_pot, e_local, omega):
-    """<V> + 2 (<E_L lnPsi> - <E_L><lnPsi>) with E_L and omega constant;
-    minus its gradient w.r.t. the ions is the Hellmann-Feynman + Pulay force."""
-    wsum = omega.sum()
-    e = e_local.detach()
-    e_mean = (omega * e).sum() / wsum
-    return (omega * v_pot).sum() / wsum + 2.0 * ((omega * (e - e_mean) * log_psi).sum() / wsum)
+        dev = ctx.keep.device
+        mem = dmcx.DMCX_DEVICE if ctx.keep.is_cuda else dmcx.DMCX_HOST
+        grad = torch.zeros((dmc.n_atom, 3), dtype=torch.float64, device=dev)
+        part = torch.empty_like(grad)
+        for g, call in ((g_lp, dmcx.dmcx_logpsi_vjp), (g_v, dmcx.dmcx_potential_vjp)):
+            if g is None:
+                continue
+            gg = _f64(g.to(dev))
+            dmc.check(call(dmc.h, gg.data_ptr(), part.data_ptr(), mem))
+            grad += part
+        return grad.to(ctx.keep.dtype), None

@@ -8,7 +8,8 @@
 //   with row = l/16 + 4 r for FP64 and row = 4 (l/16) + r for FP32.
 // - Philox4x32-10 counter-based generator (Salmon et al., SC'11) and the
 //   per-move draws: counter = (electron, walker, step, draw), key = seed.
-// - Reductions across the 32 lanes that serve one walker.
+// - Wave reductions: 64 lanes (one walker per wave in the tile kernels) and
+//   32-lane halves (two points per wave in the force kernel).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -79,39 +80,9 @@ __device__ inline void uniform_pair(uint64_t seed, uint32_t step, uint32_t walke
 }
 
 // Gaussian displacement chi (3 normals, Box-Muller on 1-u) and the
-// acceptance uniform for one proposed move.
-__device__ inline void move_draws(uint64_t seed, uint32_t step, uint32_t walker, uint32_t elec,
-                                  double chi[3], double &uacc) {
-  const double two_pi = 6.283185307179586476925286766559;
-  double u0, u1;
-  uniform_pair(seed, step, walker, elec, 0u, u0, u1);
-  double rad = sqrt(-2.0 * log(1.0 - u0));
-  chi[0] = rad * cos(two_pi * u1);
-  chi[1] = rad * sin(two_pi * u1);
-  uniform_pair(seed, step, walker, elec, 1u, u0, u1);
-  rad = sqrt(-2.0 * log(1.0 - u0));
-  chi[2] = rad * cos(two_pi * u1);
-  uniform_pair(seed, step, walker, elec, 2u, u0, u1);
-  uacc = u0;
-}
-
-// Same draws computed by lanes 0, 1, 2 of a 32-lane walker group in
-// parallel (lane d evaluates draw d) and broadcast to the whole group.
-__device__ inline void move_draws_lanes(uint64_t seed, uint32_t step, uint32_t walker,
-                                        uint32_t elec, int t, double chi[3], double &uacc) {
-  const double two_pi = 6.283185307179586476925286766559;
-  double u0, u1;
-  uniform_pair(seed, step, walker, elec, t < 2 ? (uint32_t)t : 2u, u0, u1);
-  const double rad = sqrt(-2.0 * log(1.0 - u0));
-  const double cs = rad * cos(two_pi * u1);
-  const double sn = rad * sin(two_pi * u1);
-  chi[0] = __shfl(cs, 0, 32);
-  chi[1] = __shfl(sn, 0, 32);
-  chi[2] = __shfl(cs, 1, 32);
-  uacc = __shfl(u0, 2, 32);
-}
-
-// As above for a full 64-lane wave serving one walker.
+// acceptance uniform of one proposed move, computed by lanes 0, 1, 2 of the
+// 64-lane wave that serves the walker (lane d evaluates draw d: draw 0 gives
+// chi_x, chi_y; draw 1 chi_z; draw 2 the uniform) and broadcast to the wave.
 __device__ inline void move_draws_lanes64(uint64_t seed, uint32_t step, uint32_t walker,
                                           uint32_t elec, int t, double chi[3], double &uacc) {
   const double two_pi = 6.283185307179586476925286766559;
@@ -132,7 +103,7 @@ __device__ inline void move_draws_lanes64(uint64_t seed, uint32_t step, uint32_t
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // ---------------------------------------------------------- reductions ----
-// Sum over the 32 lanes of one walker group (aligned halves of a wave).
+// Sum over one aligned 32-lane half of a wave.
 __device__ __forceinline__ double sum32(double v) {
 #pragma unroll
   for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);

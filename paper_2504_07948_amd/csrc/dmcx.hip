@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "dmcx.h"
+#include "estimators.h"
 #include "forces_aux.h"
 #include "kernels.h"
 #include "launch.h"
@@ -63,6 +64,8 @@ struct dmcx_ctx {
   uint8_t *d_acc8 = nullptr;       // [Wpad]
   // population control (comb reconfiguration) scratch
   PopScratch pop{};
+  // weighted estimators: block records [est_blocks(W)][EST_PART], host staging [EST_OUT]
+  double *d_est_part = nullptr, *d_est_out = nullptr;
   // scratch
   double *d_pos = nullptr;       // [Wpad][3]
   double *d_orb = nullptr;       // [Wpad][5][NP] (working precision) / small staging
@@ -533,11 +536,11 @@ dmcx_status compute_ion_grads(dmcx_ctx *c) {
     if (!c->d_wt && (st0 = dalloc(c, (char **)&c->d_wt, c->es * c->Wpad * 2 * c->NP * c->NP)))
       return st0;
     if (c->mixed) {
-      allow_lds(k_msd_force_weights<float>, wl);
+      HIP_TRY(c, allow_lds(k_msd_force_weights<float>, wl));
       hipLaunchKernelGGL(k_msd_force_weights<float>, dim3(c->Wpad, 2), dim3(NT_AUX), wl, c->stream,
                          c->dc, (float *)c->d_wt);
     } else {
-      allow_lds(k_msd_force_weights<double>, wl);
+      HIP_TRY(c, allow_lds(k_msd_force_weights<double>, wl));
       hipLaunchKernelGGL(k_msd_force_weights<double>, dim3(c->Wpad, 2), dim3(NT_AUX), wl,
                          c->stream, c->dc, (double *)c->d_wt);
     }
@@ -817,6 +820,10 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
   if ((st = dalloc(c, &c->d_rg, Wp * 4))) return bail(st);
   if ((st = dalloc(c, &c->d_acc8, Wp))) return bail(st);
   if ((st = dalloc(c, &d.flags, Wp))) return bail(st);
+  if ((st = dalloc(c, &d.nacc, Wp))) return bail(st);
+  if ((st = dalloc(c, &d.nprop, Wp))) return bail(st);
+  if ((st = dalloc(c, &c->d_est_part, (size_t)est_blocks(c->W) * EST_PART))) return bail(st);
+  if ((st = dalloc(c, &c->d_est_out, EST_OUT))) return bail(st);
   if ((st = dalloc(c, &c->pop.w, Wp))) return bail(st);
   if ((st = dalloc(c, &c->pop.copies, Wp))) return bail(st);
   if ((st = dalloc(c, &c->pop.dead, Wp))) return bail(st);
@@ -842,6 +849,8 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
     }
   }
   if (hipMemsetAsync(d.flags, 0, Wp * sizeof(unsigned), c->stream) != hipSuccess ||
+      hipMemsetAsync(d.nacc, 0, Wp * sizeof(unsigned), c->stream) != hipSuccess ||
+      hipMemsetAsync(d.nprop, 0, Wp * sizeof(unsigned), c->stream) != hipSuccess ||
       hipMemsetAsync(d.logw, 0, Wp * sizeof(double), c->stream) != hipSuccess ||
       hipMemsetAsync(c->d_run, 0, sizeof(RunState), c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -957,6 +966,8 @@ dmcx_status set_walkers_core(dmcx_ctx *c) {
                        c->Wpad, per);
   }
   HIP_TRY(c, hipMemsetAsync(d.flags, 0, c->Wpad * sizeof(unsigned), c->stream));
+  HIP_TRY(c, hipMemsetAsync(d.nacc, 0, c->Wpad * sizeof(unsigned), c->stream));
+  HIP_TRY(c, hipMemsetAsync(d.nprop, 0, c->Wpad * sizeof(unsigned), c->stream));
   dmcx_status st = rebuild_state(c);
   if (st) return st;
   c->step = 0;
@@ -1643,6 +1654,29 @@ dmcx_status dmcx_forces(dmcx_ctx *c, double *F, dmcx_mem mem) {
                      c->d_dv, dst);
   HIP_TRY(c, hipGetLastError());
   if (mem == DMCX_HOST) return copy_out(c, F, c->d_red, ncomp * sizeof(double), mem);
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_estimators(dmcx_ctx *c, double *out, dmcx_mem mem) {
+  if (!c || !out) return DMCX_E_INVALID;
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  if (c->is_group()) {
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      dmcx_ctx *m = c->subs[i];
+      const dmcx_status st = dmcx_estimators(m, out + i * (size_t)EST_OUT, mem);
+      if (st) return c->err = m->err, st;
+    }
+    return DMCX_OK;
+  }
+  dmcx_status st = refresh_after_moves(c);
+  if (st) return st;
+  const int nblk = est_blocks(c->W);
+  hipLaunchKernelGGL(k_est_partial, dim3(nblk), dim3(EST_NB), 0, c->stream, c->dc, c->d_est_part);
+  HIP_TRY(c, hipGetLastError());
+  double *dst = mem == DMCX_DEVICE ? out : c->d_est_out;
+  hipLaunchKernelGGL(k_est_final, dim3(1), dim3(64), 0, c->stream, nblk, c->d_est_part, dst);
+  HIP_TRY(c, hipGetLastError());
+  if (mem == DMCX_HOST) return copy_out(c, out, c->d_est_out, EST_OUT * sizeof(double), mem);
   return DMCX_OK;
 }
 

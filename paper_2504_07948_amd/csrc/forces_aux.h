@@ -60,13 +60,19 @@ __global__ void k_walker_vjp(const double *d, const double *gbar, int W, int nco
 
 // Force estimate with weights omega_w = exp(log w_w - max log w):
 //   F = -<dV> - 2 (<E_L dlnPsi> - <E_L><dlnPsi>),  <x> = sum omega x / sum omega.
-// One block (256 threads) per component.
+// A walker with a status flag, or a non-finite log-weight or E_L, has weight
+// zero (as in the comb of population control); with no such walker left the
+// result is NaN.  One block (256 threads) per component.
+__device__ __forceinline__ bool est_walker_ok(const DevCtx &c, int w) {
+  return c.flags[w] == 0u && isfinite(c.logw[w]) && isfinite(c.eloc[w]);
+}
 __global__ void k_force_estimator(DevCtx c, const double *dl, const double *dv, double *F) {
   __shared__ double part[5][256];
   __shared__ double s_max;
   const int k = blockIdx.x, ncomp = c.n_atom * 3;
   double m = -INFINITY;
-  for (int w = threadIdx.x; w < c.W; w += blockDim.x) m = fmax(m, c.logw[w]);
+  for (int w = threadIdx.x; w < c.W; w += blockDim.x)
+    if (est_walker_ok(c, w)) m = fmax(m, c.logw[w]);
   part[0][threadIdx.x] = m;
   __syncthreads();
   for (int o = blockDim.x / 2; o > 0; o >>= 1) {
@@ -77,6 +83,7 @@ __global__ void k_force_estimator(DevCtx c, const double *dl, const double *dv, 
   __syncthreads();
   double sw = 0.0, se = 0.0, sd = 0.0, sed = 0.0, sv = 0.0;
   for (int w = threadIdx.x; w < c.W; w += blockDim.x) {
+    if (!est_walker_ok(c, w)) continue;
     const double om = exp(c.logw[w] - s_max), e = c.eloc[w];
     const double d = dl[(size_t)w * ncomp + k];
     sw += om;

@@ -24,7 +24,7 @@ template <typename T>
 void NobLaunch<T>::orbitals_all(int nob, const DevCtx &c, size_t lds, hipStream_t s) {
   const int npts = c.Wpad * c.ne;
 #define DMCX_CALL(N)                                                                   \
-  allow_lds(k_orbitals_all<T, N>, lds);                                                \
+  if (allow_lds(k_orbitals_all<T, N>, lds) == hipSuccess) \
   k_orbitals_all<T, N><<<dim3((npts + TW - 1) / TW), dim3(NT_TILE), lds, s>>>(c)
   DMCX_NOB_SWITCH(nob, DMCX_CALL)
 #undef DMCX_CALL
@@ -34,7 +34,7 @@ template <typename T>
 void NobLaunch<T>::orbitals_at(int nob, const DevCtx &c, const double *pos, int npts, T *dst,
                                size_t lds, hipStream_t s) {
 #define DMCX_CALL(N)                                                                   \
-  allow_lds(k_orbitals_at<T, N>, lds);                                                 \
+  if (allow_lds(k_orbitals_at<T, N>, lds) == hipSuccess) \
   k_orbitals_at<T, N><<<dim3((npts + TW - 1) / TW), dim3(NT_TILE), lds, s>>>(c, pos, npts, dst)
   DMCX_NOB_SWITCH(nob, DMCX_CALL)
 #undef DMCX_CALL
@@ -45,13 +45,13 @@ void NobLaunch<T>::sweep(int nob, const DevCtx &c, uint8_t *acc, long long acc_s
                          size_t lds, hipStream_t s) {
   if constexpr (sizeof(T) == 4) {
 #define DMCX_CALL(N)                                                                   \
-  allow_lds(k_sweep_w4<T, N>, lds);                                                    \
+  if (allow_lds(k_sweep_w4<T, N>, lds) == hipSuccess) \
   k_sweep_w4<T, N><<<dim3(c.Wpad / TW), dim3(NT_TILE), lds, s>>>(c, acc, acc_ss, acc_ws)
     DMCX_NOB_SWITCH(nob, DMCX_CALL)
 #undef DMCX_CALL
   } else {
 #define DMCX_CALL(N)                                                                   \
-  allow_lds(k_sweep<T, N>, lds);                                                       \
+  if (allow_lds(k_sweep<T, N>, lds) == hipSuccess) \
   k_sweep<T, N><<<dim3(c.Wpad / TW), dim3(NT_TILE), lds, s>>>(c, acc, acc_ss, acc_ws)
     DMCX_NOB_SWITCH(nob, DMCX_CALL)
 #undef DMCX_CALL
@@ -77,7 +77,7 @@ template <typename T>
 void NobLaunch<T>::ion_grad_det(int nob, const DevCtx &c, double *partial, int ntile, size_t lds,
                                 hipStream_t s) {
 #define DMCX_CALL(N)                                                                   \
-  allow_lds(k_ion_grad_det<T, N>, lds);                                                \
+  if (allow_lds(k_ion_grad_det<T, N>, lds) == hipSuccess) \
   k_ion_grad_det<T, N><<<dim3(c.Wpad * ntile), dim3(NT_FORCE), lds, s>>>(c, partial)
   DMCX_NOB_SWITCH(nob, DMCX_CALL)
 #undef DMCX_CALL
@@ -95,7 +95,7 @@ void NobLaunch<T>::ratio_grad(int nob, const DevCtx &c, int iel, int m, const do
                               double *ratio, double *grad, T *prop, double *prop_rho, size_t lds,
                               hipStream_t s) {
 #define DMCX_CALL(N)                                                                   \
-  allow_lds(k_ratio_grad<T, N>, lds);                                                  \
+  if (allow_lds(k_ratio_grad<T, N>, lds) == hipSuccess) \
   k_ratio_grad<T, N><<<dim3(c.Wpad / TW), dim3(NT_TILE), lds, s>>>(c, iel, m, r_new, ratio, grad, \
                                                                    prop, prop_rho)
   DMCX_NOB_SWITCH(nob, DMCX_CALL)

@@ -1,11 +1,12 @@
 // dmcx kernels for gfx950.
 //
-// Work decomposition: a workgroup of 256 threads (4 waves) owns a tile of
-// TW = 8 walkers.  Walkers are independent Markov chains, so a whole sweep
-// (every electron of every walker in the tile) runs inside one launch with
-// workgroup barriers only.  The 32 lanes tid/32 == slot serve walker `slot`
-// for per-walker vector work (dot products over orbitals, Jastrow sums);
-// the four waves cooperate on the orbital contraction, which is an MFMA GEMM
+// Work decomposition: a workgroup of 64*TW threads (TW = 8 walkers: 512
+// threads, 8 waves) owns a tile of TW walkers.  Walkers are independent
+// Markov chains, so a whole sweep (every electron of every walker in the
+// tile) runs inside one launch with workgroup barriers only.  Wave `ws`
+// serves walker `ws` of the tile for per-walker vector work (dot products
+// over orbitals, Jastrow sums; 64-lane wave reductions); all waves
+// cooperate on the orbital contraction, which is an MFMA GEMM
 //   out[(walker, vgl), orbital] = sum_l Phi[(walker, vgl), l] C[l, orbital]
 // with the basis values Phi produced in LDS stage by stage (never in HBM).
 //
@@ -226,6 +227,8 @@ struct DevCtx {
   double *logpsi;  // [Wpad]
   double *vpot;    // [Wpad] Coulomb potential V(R) of the current configuration
   unsigned *flags; // [Wpad] bit 0 non-finite, bit 1 singular
+  unsigned *nacc;  // [Wpad] moves accepted since the last estimator call
+  unsigned *nprop; // [Wpad] moves proposed since the last estimator call
   DevMsd M;        // multideterminant expansion (M.on == 0: none)
 };
 
@@ -1204,6 +1207,7 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
   // MSD scratch per walker: [4][nv] (q, grad q) or [3][nv] (w)
   T *msx = Bs + (size_t)ws * 4 * (MSD ? M.nv : 0);
   if (acc_log) acc_log += c.run->s_in_run * acc_step_stride + (long long)w * acc_w_stride;
+  unsigned n_accepted = 0;  // this walker's accepted moves in the sweep
   PHASE_BEGIN();
   for (int i = 0; i < c.ne; ++i) {
     const int sp = i < c.n_up ? 0 : 1;
@@ -1418,6 +1422,7 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
       }
     }
     if (acc_log && t == 0 && w < c.W) acc_log[i] = (uint8_t)accepted;
+    n_accepted += (unsigned)accepted;
     PHASE_MARK(4);
     // ---- P5: block end -> rank-k flush of the full inverse
     if (m == kb - 1) flush_block<T, NOB>(c, blockIdx.x * TW, sp, kb);
@@ -1426,6 +1431,10 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
     PHASE_MARK(6);
   }
   PHASE_END();
+  if (t == 0 && w < c.W) {
+    c.nacc[w] += n_accepted;
+    c.nprop[w] += (unsigned)c.ne;
+  }
 }
 
 // The step index and mode come from the device run state; acc_log (may be
@@ -1540,6 +1549,10 @@ __global__ __launch_bounds__(64) void k_accept(DevCtx c, int i, int sp, int m, i
   const int q = min(w, c.W - 1);
   const double rn[3] = {r_new[3 * q], r_new[3 * q + 1], r_new[3 * q + 2]};
   if (accepted && !isfinite(rho)) c.flags[w] |= 1u;
+  if (t == 0 && w < c.W) {
+    c.nacc[w] += (unsigned)(accepted && rho != 0.0);
+    c.nprop[w] += 1u;
+  }
   block_accept<T, NOB>(c, w, t, i, sp, m, kb, accepted && rho != 0.0, rho,
                        prop + (size_t)w * 5 * NP, colm, aold, crow, rn);
 }

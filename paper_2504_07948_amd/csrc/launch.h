@@ -13,10 +13,13 @@ namespace dmcx {
 constexpr int NOB_MAX = 10;  // up to 160 orbital columns per tile
 
 // Let a kernel use `dyn` bytes of dynamic LDS (beyond the 64 KB default).
+// The launchers below launch only when this succeeds; a failure stays the
+// thread's last HIP error, which the runtime's hipGetLastError() after every
+// launcher call reports as DMCX_E_HIP.
 template <typename K>
-inline void allow_lds(K kernel, size_t dyn) {
-  (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)dyn);
+inline hipError_t allow_lds(K kernel, size_t dyn) {
+  return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)dyn);
 }
 
 template <typename T>

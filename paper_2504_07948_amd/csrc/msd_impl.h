@@ -10,7 +10,7 @@ template <typename T>
 void MsdLaunch<T>::sweep(int nob, const DevCtx &c, uint8_t *acc, long long acc_ss, int acc_ws,
                          size_t lds, hipStream_t s) {
 #define DMCX_CALL(N)                                                                   \
-  allow_lds(k_sweep_msd<T, N>, lds);                                                   \
+  if (allow_lds(k_sweep_msd<T, N>, lds) == hipSuccess) \
   k_sweep_msd<T, N><<<dim3(c.Wpad / TW), dim3(NT_TILE), lds, s>>>(c, acc, acc_ss, acc_ws)
   DMCX_NOB_SWITCH(nob, DMCX_CALL)
 #undef DMCX_CALL

@@ -23,6 +23,7 @@ DMCX_FP64, DMCX_MIXED = 0, 1
 DMCX_VMC, DMCX_DMC = 0, 1
 DMCX_HOST, DMCX_DEVICE = 0, 1
 DMCX_FLAG_GRAPH = 1
+DMCX_N_ESTIMATORS = 11
 
 EXPORTED = [
     "dmcx_create", "dmcx_destroy", "dmcx_set_walkers", "dmcx_get_walkers", "dmcx_set_step",
@@ -30,7 +31,7 @@ EXPORTED = [
     "dmcx_accept", "dmcx_flush", "dmcx_run", "dmcx_measure", "dmcx_ion_grads", "dmcx_logpsi_vjp",
     "dmcx_potential_vjp", "dmcx_forces", "dmcx_potential", "dmcx_walker_flags", "dmcx_sync", "dmcx_last_run_timing",
     "dmcx_selftest", "dmcx_philox", "dmcx_strerror", "dmcx_last_error", "dmcx_autotune",
-    "dmcx_autotune_report", "dmcx_get_delay_rank", "dmcx_reconfigure",
+    "dmcx_autotune_report", "dmcx_get_delay_rank", "dmcx_reconfigure", "dmcx_estimators",
 ]
 
 
@@ -105,6 +106,7 @@ def load():
         "dmcx_autotune": [P, I32, P],
         "dmcx_autotune_report": [P, I32, I32, P, P, P],
         "dmcx_get_delay_rank": [P, I32, P],
+        "dmcx_estimators": [P, P, I32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -208,6 +210,10 @@ def dmcx_potential_vjp(ctx, gbar, grad_R, mem):
 
 def dmcx_forces(ctx, F, mem):
     return load().dmcx_forces(ctx, F, mem)
+
+
+def dmcx_estimators(ctx, out, mem):
+    return load().dmcx_estimators(ctx, out, mem)
 
 
 def dmcx_potential(ctx, v, mem):
@@ -421,6 +427,12 @@ class Context:
         F = self._per_system()
         self.check(dmcx_forces(self.h, _ptr(F), DMCX_HOST))
         return F
+
+    def estimators(self):
+        """[n_sys][DMCX_N_ESTIMATORS] weighted estimators (see include/dmcx.h)."""
+        out = np.zeros((self.n_sys, DMCX_N_ESTIMATORS))
+        self.check(dmcx_estimators(self.h, _ptr(out), DMCX_HOST))
+        return out
 
     def walker_flags(self):
         f = np.zeros(self.W, dtype=np.uint8)

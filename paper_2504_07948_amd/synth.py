@@ -350,10 +350,12 @@ def alkane(n_c: int, seed: int) -> System:
 ALKANE_NC = (3, 7, 11, 16, 20, 24, 29, 33)
 
 
+def batch5_member(k: int, n_det: int = 1000, n_active: int = 100) -> System:
+    """Molecule k (0..7) of the eight-alkane workload, with its MSD expansion."""
+    s = alkane(ALKANE_NC[k], BASE_SEED + 5 + 1000 * k)
+    return make_msd(s, n_det, n_active, BASE_SEED + 5 + 1000 * k + 1)
+
+
 def make_batch5(n_det: int = 1000, n_active: int = 100) -> List[System]:
     """Eight alkanes with 20..200 electrons, each with an MSD expansion."""
-    out = []
-    for k, n in enumerate(ALKANE_NC):
-        s = alkane(n, BASE_SEED + 5 + 1000 * k)
-        out.append(make_msd(s, n_det, n_active, BASE_SEED + 5 + 1000 * k + 1))
-    return out
+    return [batch5_member(k, n_det, n_active) for k in range(len(ALKANE_NC))]

@@ -1,0 +1,171 @@
+"""Weighted walker estimators (QMC section, Eq. 1) and the error paths of the
+C-ABI on the GPU.
+
+Estimators: dmcx_estimators against the oracle's plain-definition estimators
+evaluated on the oracle's own run (log-weights, local energies and accept
+decisions of the same seeded DMC run; the accept sequence is bit-exact, so the
+move counts agree exactly and the weighted sums to the 1e-10 bar of the run).
+Large and ragged walker counts (several partial-record blocks), VMC, groups,
+graph replays and excluded walkers are covered.
+
+Error paths (numerical conditions, not device faults): an electron far from
+every nucleus makes every orbital underflow to zero, so its Slater matrix has
+a zero row and dmcx_recompute reports DMCX_E_SINGULAR with walker flag 2; an
+electron exactly on a nucleus makes V and the e-n Jastrow gradient infinite,
+so E_L is not finite and dmcx_recompute reports DMCX_E_NONFINITE with flag 1.
+Flagged walkers and non-finite log-weights get weight zero in the estimators
+and in the force estimate.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_07948_amd import dmcx, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _close(a, b, rel=1e-10, floor=1.0):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    assert a.shape == b.shape
+    both_nan = np.isnan(a) & np.isnan(b)
+    tol = rel * np.maximum(np.maximum(np.abs(a), np.abs(b)), floor)
+    bad = ~both_nan & ~(np.abs(a - b) <= tol)
+    assert not bad.any(), f"{bad.sum()} of {bad.size} outside tolerance: {a[bad]} vs {b[bad]}"
+
+
+@pytest.mark.parametrize("mode,graph", [(dmcx.DMCX_DMC, False), (dmcx.DMCX_DMC, True),
+                                        (dmcx.DMCX_VMC, False)])
+def test_estimators_match_oracle_run(mode, graph):
+    s = synth.small_molecule()
+    W, n, tau, seed = 300, 6, 0.01, 13   # two blocks of 256, the second ragged
+    R = synth.make_walkers(s, W, 5150)
+    lw0 = np.random.default_rng(5).normal(0.0, 0.5, W)
+    _, _, e0, _ = oracle.evaluate_batch(s, R)
+    e_t = float(np.mean(e0))
+    ctx = dmcx.Context(s, W, delay_rank=1, recompute_period=4, tau=tau, seed=seed, graph=graph)
+    ctx.set_walkers(R, lw0)
+    acc, _ = ctx.run(n, mode=mode, e_trial=e_t, logs=True)
+    got = ctx.estimators()[0]
+    ref_run = oracle.run(s, R, log_w=lw0, n_steps=n, mode=mode, tau=tau, seed=seed, e_trial=e_t)
+    np.testing.assert_array_equal(acc, ref_run["accept_log"])
+    ref = oracle.estimators(ref_run["log_w"], ref_run["e_local"],
+                            n_accepted=int(ref_run["accept_log"].sum()),
+                            n_proposed=W * s.n_elec * n)
+    assert got[0] == W and got[10] == W * s.n_elec * n
+    assert got[9] == ref[9]  # exact: integer counts
+    _close(got[1:9], ref[1:9])
+    # the call cleared the move counters; the weights are unchanged
+    again = ctx.estimators()[0]
+    assert again[10] == 0 and np.isnan(again[9])
+    _close(again[1:9], got[1:9], rel=0.0)
+    if mode == dmcx.DMCX_VMC:
+        _close(got[6], np.mean(ref_run["e_local"]))
+
+
+def test_estimators_large_population_spread_weights():
+    """1000 walkers (four blocks, ragged), log-weights spread by sigma = 3."""
+    s = synth.small_molecule()
+    W = 1000
+    R = synth.make_walkers(s, W, 5151)
+    lw = np.random.default_rng(6).normal(2.0, 3.0, W)
+    ctx = dmcx.Context(s, W)
+    ctx.set_walkers(R, lw)
+    got = ctx.estimators()[0]
+    _, _, e_o, _ = oracle.evaluate_batch(s, R)
+    ref = oracle.estimators(lw, e_o)
+    _close(got[:9], ref[:9])
+
+
+def test_estimators_group_matches_single_contexts():
+    systems = [synth.small_molecule(),
+               synth.small_random_system(71, n_atom=3, n_up=3, n_dn=3, shells=(0, 0, 1, 2),
+                                         nprim=3, charge=2.0)]
+    walkers = [37, 270]
+    ne = max(x.n_elec for x in systems)
+    Rs = [synth.make_walkers(x, w, 5152 + i) for i, (x, w) in enumerate(zip(systems, walkers))]
+    Rg = np.zeros((sum(walkers), ne, 3))
+    Rg[:37, :systems[0].n_elec] = Rs[0]
+    Rg[37:, :systems[1].n_elec] = Rs[1]
+    g = dmcx.Context(systems, walkers, delay_rank=2, recompute_period=3, seed=3)
+    g.set_walkers(Rg)
+    g.run(3, mode=dmcx.DMCX_DMC, e_trial=-5.0)
+    out = g.estimators()
+    for i, (x, w) in enumerate(zip(systems, walkers)):
+        c = dmcx.Context(x, w, delay_rank=2, recompute_period=3, seed=3)
+        c.set_walkers(Rs[i])
+        c.run(3, mode=dmcx.DMCX_DMC, e_trial=-5.0)
+        np.testing.assert_array_equal(out[i], c.estimators()[0])
+
+
+def _far_and_nucleus_walkers(s, W):
+    R = synth.make_walkers(s, W, 5153)
+    far, nuc = R.copy(), R.copy()
+    far[3, 0] = [1.0e4, 0.0, 0.0]        # every orbital underflows: zero row of A
+    nuc[5, 1] = s.ion_xyz[0]             # electron on nucleus 0: V and grad J infinite
+    return R, far, nuc
+
+
+def test_singular_walker_reported_and_excluded():
+    s = synth.small_molecule()
+    W = 16
+    R, far, _ = _far_and_nucleus_walkers(s, W)
+    ctx = dmcx.Context(s, W)
+    ctx.set_walkers(far)
+    with pytest.raises(dmcx.DmcxError) as ex:
+        ctx.recompute()
+    assert ex.value.status == dmcx.DMCX_E_SINGULAR
+    f = ctx.walker_flags()
+    assert f[3] & 2 and (np.delete(f, 3) == 0).all()
+    e, _, _ = ctx.measure()
+    _, _, e_o, _ = oracle.evaluate_batch(s, np.delete(far, 3, axis=0))
+    _close(np.delete(e, 3), e_o)
+    got = ctx.estimators()[0]
+    ref = oracle.estimators(np.zeros(W), np.where(f == 0, e, np.nan))
+    assert got[0] == W - 1
+    _close(got[1:9], ref[1:9])
+    # the other walkers' forces are unaffected by the singular one
+    dl, dv = ctx.ion_grads()
+    ok = f == 0
+    mean = lambda x: x[ok].mean(axis=0)
+    F_ref = -mean(dv) - 2 * (mean(e[:, None, None] * dl) - mean(e) * mean(dl))
+    F = ctx.forces()
+    assert np.isfinite(F).all()
+    _close(F, F_ref, rel=1e-11)
+
+
+def test_nonfinite_walker_reported_and_excluded():
+    s = synth.small_molecule()
+    W = 16
+    R, _, nuc = _far_and_nucleus_walkers(s, W)
+    ctx = dmcx.Context(s, W)
+    ctx.set_walkers(nuc)
+    with pytest.raises(dmcx.DmcxError) as ex:
+        ctx.recompute()
+    assert ex.value.status == dmcx.DMCX_E_NONFINITE
+    f = ctx.walker_flags()
+    assert f[5] == 1 and (np.delete(f, 5) == 0).all()
+    e, _, _ = ctx.measure()
+    assert not np.isfinite(e[5])
+    got = ctx.estimators()[0]
+    assert got[0] == W - 1 and np.isfinite(got[1:9]).all()
+
+
+def test_nan_log_weight_gets_zero_weight_in_forces():
+    s = synth.small_molecule()
+    W = 16
+    R = synth.make_walkers(s, W, 5154)
+    lw = np.random.default_rng(7).normal(0.0, 0.3, W)
+    lw[2] = np.nan
+    ctx = dmcx.Context(s, W)
+    ctx.set_walkers(R, lw)
+    e, _, _ = ctx.measure()
+    dl, dv = ctx.ion_grads()
+    ok = np.isfinite(lw)
+    om = np.exp(lw[ok] - lw[ok].max())
+    mean = lambda x: np.einsum("w,w...->...", om, x[ok]) / om.sum()
+    F_ref = -mean(dv) - 2 * (mean(e[:, None, None] * dl) - mean(e) * mean(dl))
+    _close(ctx.forces(), F_ref, rel=1e-11)
+    got = ctx.estimators()[0]
+    _close(got[:9], oracle.estimators(lw, e)[:9])

@@ -127,3 +127,24 @@ def test_delay_rank_invariance():
         np.testing.assert_array_equal(acc, out[0][0])
         _close(el, out[0][1], rel=1e-11)
         _close(Rk, out[0][2], rel=1e-12)
+
+
+def test_run_large_full_recompute_period():
+    """The FP64 benchmark's update schedule over a whole recompute period: 8
+    walkers x 65 DMC steps at k = 32, P = 64, so the delayed rank-32 updates
+    run for 64 steps before the FP64 recompute at step 64 and one step after
+    it.  Accept sequence bit-exact; E_L of every step, positions and weights
+    at the 1e-10 bar (the largest error is printed)."""
+    s = synth.large_molecule()
+    print("[parity] 8 walkers x 65 steps, k=32, P=64", flush=True)
+    g, ref = _run_both(s, 8, 65, dmcx.DMCX_DMC, k=32, P=64, wseed=310)
+    np.testing.assert_array_equal(g["acc"], ref["accept_log"])
+    err = np.abs(g["elog"] - ref["e_log"]) / np.maximum(np.abs(ref["e_log"]), 1.0)
+    print(f"[parity] E_L max rel err per step: first {err[0].max():.2e}, step 63 "
+          f"{err[63].max():.2e}, step 64 {err[64].max():.2e}, overall {err.max():.2e}", flush=True)
+    _close(g["elog"], ref["e_log"])
+    _close(g["R"], ref["R"])
+    _close(g["lw"], ref["log_w"], floor=1e-3)
+    lp_o, sg_o, _, _ = oracle.evaluate_batch(s, ref["R"])
+    _close(g["lp"], lp_o)
+    np.testing.assert_array_equal(g["sg"], sg_o)

@@ -347,6 +347,53 @@ def test_dmc_weights_exact_for_zero_variance():
     np.testing.assert_allclose(out["e_log"], -Z * Z / 2, atol=1e-12)
 
 
+def _msd_small_system():
+    """3+3 electrons, 10 MOs, a reference plus singles and doubles of both spins."""
+    import dataclasses
+    s = synth.small_random_system(31, n_atom=2, n_up=3, n_dn=3, shells=(0, 0, 1, 2), nprim=2,
+                                  n_mo=10)
+    exc = np.array([[0, 0] + [-1] * 8,
+                    [1, 0, 1, -1, 5, -1, -1, -1, -1, -1],
+                    [0, 1, -1, -1, -1, -1, 2, -1, 4, -1],
+                    [2, 0, 0, 2, 4, 6, -1, -1, -1, -1],
+                    [1, 1, 0, -1, 7, -1, 1, -1, 3, -1]], dtype=np.int32)
+    return dataclasses.replace(s, n_det=len(exc), det_exc=exc,
+                               ci_coef=np.array([1.0, 0.4, -0.3, 0.2, -0.25]))
+
+
+@pytest.mark.parametrize("msd", [False, True])
+def test_dmc_log_weights_rebuilt_from_step_end_energies(msd):
+    """Eq. 1 weight update, log w += -tau((E_L,old + E_L,new)/2 - E_T), rebuilt
+    from E_L evaluated afresh (oracle.evaluate, pinned by the E_L tests above)
+    at the configuration before step 0 and at every step end, for walkers whose
+    E_L varies from step to step.  An update that used only E_new or only E_old
+    differs from the rebuilt weights by tau/2 |E_first - E_last|, which the test
+    asserts is far above its tolerance."""
+    s = _msd_small_system() if msd else synth.small_random_system(
+        19, n_atom=2, n_up=3, n_dn=2, shells=(0, 0, 1, 2), nprim=2)
+    W, n, tau, seed, e_t = 3, 5, 0.05, 41, -1.25
+    R0 = synth.make_walkers(s, W, 8)
+    lw0 = np.array([0.3, -0.7, 1.1])
+    out = oracle.run(s, R0, log_w=lw0, n_steps=n, mode=1, tau=tau, seed=seed, e_trial=e_t)
+    R = R0.copy()
+    e_prev = np.array([oracle.evaluate(s, R[w])[2] for w in range(W)])
+    e_first = e_prev.copy()
+    expect = lw0.copy()
+    for st in range(n):
+        R = oracle.run(s, R, n_steps=1, step0=st, mode=1, tau=tau, seed=seed, e_trial=e_t)["R"]
+        e_new = np.array([oracle.evaluate(s, R[w])[2] for w in range(W)])
+        np.testing.assert_allclose(out["e_log"][st], e_new, rtol=1e-12, atol=1e-12)
+        expect += -tau * (0.5 * (e_prev + e_new) - e_t)
+        e_prev = e_new
+    np.testing.assert_allclose(out["R"], R, rtol=0, atol=1e-13)
+    tol = 1e-13 * np.maximum(1.0, np.abs(expect))
+    assert np.all(np.abs(out["log_w"] - expect) <= tol)
+    # the trapezoid is distinguishable from the one-sided updates on these walkers
+    one_sided = 0.5 * tau * np.abs(e_first - e_prev)
+    assert np.all(one_sided > 1e3 * tol), one_sided
+    assert out["accept_log"].mean() > 0.3
+
+
 def test_vmc_variational_bound_hydrogen():
     """VMC of H with a non-exact Jastrow exponent (b > 0): <E> >= -1/2."""
     s = _one_electron_system(0, 0, 0.0, Z=1.0, jen_a=-1.0, jen_b=0.3)
