@@ -73,6 +73,11 @@ def _load():
         lib.orc_evaluate_batch.argtypes = [P, C.c_int32, P, P, P, P, C.c_int32]
         lib.orc_msd_ratio_direct.argtypes = [P, P, P]
         lib.orc_reconfigure.argtypes = [C.c_int32, P, C.c_double, P, P, P, P]
+        lib.orc_local_energy_dir.argtypes = [P, P, P, P, P, P]
+        lib.orc_zv_grads.argtypes = [P, P, C.c_int32, P, P, P]
+        lib.orc_zv_grads_batch.argtypes = [P, C.c_int32, P, C.c_int32, P, P, P, C.c_int32]
+        lib.orc_basis_d3.argtypes = [P, P, P]
+        lib.orc_warp_weights.argtypes = [P, P, P, P]
         _lib = lib
     return _lib
 
@@ -284,3 +289,67 @@ def estimators(log_w, e_local, flags=None, n_accepted=0, n_proposed=0):
     var = (om * (e - mean) ** 2).sum() / s0
     return np.array([float(ok.sum()), m, s0, (om * e).sum(), (om * e * e).sum(), (om * om).sum(),
                      mean, var, lw.min(), acc, float(n_proposed)])
+
+
+def basis_d3(sys, r):
+    """Basis value, gradient, Hessian (xx, xy, xz, yy, yz, zz), Laplacian and
+    gradient of the Laplacian at r: [n_basis][14]."""
+    o = _osys(sys)
+    out = np.zeros((o.n_basis, 14))
+    _load().orc_basis_d3(o.ref, _ptr(np.ascontiguousarray(r, dtype=np.float64)), _ptr(out))
+    return out
+
+
+def warp_weights(sys, r):
+    """Space-warp weights omega_a(r) [n_atom] and their gradients [n_atom][3]."""
+    o = _osys(sys)
+    om = np.zeros(o.n_atom)
+    dom = np.zeros((o.n_atom, 3))
+    _load().orc_warp_weights(o.ref, _ptr(np.ascontiguousarray(r, dtype=np.float64)), _ptr(om),
+                             _ptr(dom))
+    return om, dom
+
+
+def local_energy_dir(sys, R, dion, del_):
+    """Eq. 4 derivative of E_L and Eq. 3 derivative of ln|Psi| along the
+    direction (ion displacements dion [n_atom][3], electron displacements
+    del_ [n_elec][3]).  Returns (dE_L, dln|Psi|, rc)."""
+    o = _osys(sys)
+    de = C.c_double()
+    dl = C.c_double()
+    rc = _load().orc_local_energy_dir(o.ref, _ptr(np.ascontiguousarray(R, dtype=np.float64)),
+                                      _ptr(np.ascontiguousarray(dion, dtype=np.float64)),
+                                      _ptr(np.ascontiguousarray(del_, dtype=np.float64)),
+                                      C.byref(de), C.byref(dl))
+    return float(de.value), float(dl.value), rc
+
+
+def zv_grads_batch(sys, R, warp, n_threads=0):
+    """Per walker and ion coordinate: dE_L, d ln|Psi| and d ln(Jacobian)
+    [W][n_atom][3] each, along the ion displacement alone (warp=False) or with
+    the space warp (warp=True)."""
+    o = _osys(sys)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    W = R.shape[0]
+    de = np.zeros((W, o.n_atom, 3))
+    dl = np.zeros((W, o.n_atom, 3))
+    dj = np.zeros((W, o.n_atom, 3))
+    rc = _load().orc_zv_grads_batch(o.ref, W, _ptr(R), int(bool(warp)), _ptr(de), _ptr(dl),
+                                    _ptr(dj), n_threads)
+    return de, dl, dj, rc
+
+
+def zv_force_estimator(log_w, e_local, dEL, dlogpsi, dlogjac):
+    """F = -<dE_L> - <(E_L - <E_L>)(2 dln|Psi| + dln J)> over the walkers,
+    weights exp(log w - max) (zero-variance force with the Pulay covariance;
+    dln J = 0 without the space warp).  Walkers with a non-finite log w or E_L
+    are left out."""
+    lw = np.asarray(log_w, dtype=np.float64)
+    e = np.asarray(e_local, dtype=np.float64)
+    ok = np.isfinite(lw) & np.isfinite(e)
+    om = np.exp(lw[ok] - lw[ok].max())
+    om /= om.sum()
+    mean = lambda x: np.einsum("w,w...->...", om, np.asarray(x)[ok])
+    em = mean(e)
+    de = e - em
+    return -mean(dEL) - mean(de[:, None, None] * (2.0 * np.asarray(dlogpsi) + np.asarray(dlogjac)))

@@ -1069,3 +1069,420 @@ int orc_reconfigure(int32_t W, const double *log_w, double u, int32_t *copies, i
   *log_wbar = m + log(S / (double)W);
   return 0;
 }
+
+/* ======================================================================
+ * Derivative of the local energy with respect to the ions (Single
+ * Determinant QMC Forces, Eq. 4) and the space-warp transformation.
+ *
+ * E_L = -1/2 sum_sigma tr(A^{-1} B) - 1/2 sum_i [lap_i J + |grad_i J|^2] + V
+ * with the one-body operator matrix of each spin
+ *   B_ij = lap phi_j(r_i) + 2 sum_y (d_y J)(r_i) d_y phi_j(r_i)
+ * (so that tr(A^{-1} B) = sum_i [l_i + 2 grad_i J . g_i]).  Along any
+ * direction lambda of the ions and electrons, Eq. 4 gives
+ *   d tr(A^{-1} B) = tr(A^{-1} dB - X dA),  X = A^{-1} B A^{-1},
+ * and Eq. 3 gives d ln|D| = tr(A^{-1} dA).  The Jastrow, its derivatives and
+ * V are differentiated pair by pair.  Single determinant only.
+ *
+ * Space warp (Filippi and Umrigar, PRB 61 R16291): when ion a moves by dR,
+ * every electron moves by omega_a(r_i) dR with
+ *   omega_a(r) = F(|r - R_a|) / sum_b F(|r - R_b|),  F(d) = d^-4,
+ * which changes the sampled density by the Jacobian of r -> r + omega dR;
+ * d ln(Jacobian) = sum_i d omega_a(r_i) / d r_i,x for component x.
+ * ==================================================================== */
+
+/* d^k/dx^k of x^n. */
+static double mono_d(double x, int n, int k) {
+  if (k > n) return 0.0;
+  double c = 1.0;
+  for (int q = 0; q < k; ++q) c *= (double)(n - q);
+  return c * mono(x, n - k);
+}
+
+/* Basis derivatives of function Phi = P(d) R(s^2) by the Leibniz rule over
+ * the derivative axes ax[0..n-1] (n <= 3): sum over subsets S of the axes of
+ * (d_S P)(d_{rest} R), with
+ *   R_a = 2 d_a R',  R_ab = 2 delta_ab R' + 4 d_a d_b R'',
+ *   R_abc = 4 (delta_ab d_c + delta_ac d_b + delta_bc d_a) R'' + 8 d_a d_b d_c R'''. */
+static double radial_d(const double d[3], const double Rk[4], const int *ax, int n) {
+  if (n == 0) return Rk[0];
+  if (n == 1) return 2.0 * d[ax[0]] * Rk[1];
+  if (n == 2) return 2.0 * (ax[0] == ax[1]) * Rk[1] + 4.0 * d[ax[0]] * d[ax[1]] * Rk[2];
+  const int a = ax[0], b = ax[1], c = ax[2];
+  return 4.0 * ((a == b) * d[c] + (a == c) * d[b] + (b == c) * d[a]) * Rk[2] +
+         8.0 * d[a] * d[b] * d[c] * Rk[3];
+}
+static double poly_d(const double d[3], const int *e, const int *ax, int n) {
+  int k[3] = {0, 0, 0};
+  for (int q = 0; q < n; ++q) k[ax[q]]++;
+  return mono_d(d[0], e[0], k[0]) * mono_d(d[1], e[1], k[1]) * mono_d(d[2], e[2], k[2]);
+}
+static double leibniz(const double d[3], const int *e, const double Rk[4], const int *ax, int n) {
+  double acc = 0.0;
+  for (int m = 0; m < (1 << n); ++m) {
+    int sa[3], ra[3], ns = 0, nr = 0;
+    for (int q = 0; q < n; ++q) {
+      if (m & (1 << q)) sa[ns++] = ax[q];
+      else ra[nr++] = ax[q];
+    }
+    acc += poly_d(d, e, sa, ns) * radial_d(d, Rk, ra, nr);
+  }
+  return acc;
+}
+
+/* Hessian component order (xx, xy, xz, yy, yz, zz). */
+static const int HESS[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+static int hidx(int a, int b) {
+  for (int q = 0; q < 6; ++q)
+    if ((HESS[q][0] == a && HESS[q][1] == b) || (HESS[q][0] == b && HESS[q][1] == a)) return q;
+  return -1;
+}
+
+/* out[n_basis][14]: value, gradient (3), Hessian (6), Laplacian, gradient of
+ * the Laplacian (3), at r. */
+int orc_basis_d3(const orc_system *s, const double r[3], double *out) {
+  int prim = 0, fn = 0;
+  for (int sh = 0; sh < s->n_shell; ++sh) {
+    const int l = s->shell_l[sh];
+    if (l < 0 || l > 2) return 1;
+    const double *c = s->ion_xyz + 3 * s->shell_atom[sh];
+    const double d[3] = {r[0] - c[0], r[1] - c[1], r[2] - c[2]};
+    const double s2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double Rk[4] = {0, 0, 0, 0};
+    for (int p = 0; p < s->shell_nprim[sh]; ++p, ++prim) {
+      const double a = s->prim_alpha[prim];
+      const double e = s->prim_coef[prim] * exp(-a * s2);
+      Rk[0] += e;
+      Rk[1] += -a * e;
+      Rk[2] += a * a * e;
+      Rk[3] += -a * a * a * e;
+    }
+    for (int k = 0; k < NCART[l]; ++k, ++fn) {
+      const int *e = CART[l][k];
+      double *o = out + 14 * fn;
+      o[0] = leibniz(d, e, Rk, NULL, 0);
+      for (int a = 0; a < 3; ++a) o[1 + a] = leibniz(d, e, Rk, &a, 1);
+      for (int q = 0; q < 6; ++q) o[4 + q] = leibniz(d, e, Rk, HESS[q], 2);
+      o[10] = o[4] + o[7] + o[9];
+      for (int cc = 0; cc < 3; ++cc) {
+        double g = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          const int ax[3] = {a, a, cc};
+          g += leibniz(d, e, Rk, ax, 3);
+        }
+        o[11 + cc] = g;
+      }
+    }
+  }
+  return fn == s->n_basis ? 0 : 1;
+}
+
+/* Pade u(r) = a r/(1 + b r) as a function of the vector d (r = |d|):
+ * gradient u' d/r, Hessian u'' dd^T/r^2 + (u'/r)(I - dd^T/r^2), Laplacian
+ * u'' + 2u'/r, gradient of the Laplacian (u''' + 2u''/r - 2u'/r^2) d/r,
+ * with u''' = 6 a b^2 / (1 + b r)^4. */
+typedef struct { double u, g[3], H[3][3], lap, glap[3]; } pair_d;
+static pair_d pade_vec(double a, double b, const double d[3]) {
+  pair_d p;
+  const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  const double t = 1.0 + b * r;
+  const double u1 = a / (t * t), u2 = -2.0 * a * b / (t * t * t), u3 = 6.0 * a * b * b / (t * t * t * t);
+  p.u = a * r / t;
+  for (int x = 0; x < 3; ++x) {
+    p.g[x] = u1 * d[x] / r;
+    for (int y = 0; y < 3; ++y)
+      p.H[x][y] = u2 * d[x] * d[y] / (r * r) + (u1 / r) * ((x == y) - d[x] * d[y] / (r * r));
+    p.glap[x] = (u3 + 2.0 * u2 / r - 2.0 * u1 / (r * r)) * d[x] / r;
+  }
+  p.lap = u2 + 2.0 * u1 / r;
+  return p;
+}
+
+/* Space-warp weight omega_a(r) of every atom and its gradient in r. */
+static void warp_weights(const orc_system *s, const double r[3], double *om, double *dom) {
+  const int na = s->n_atom;
+  double S = 0.0, dS[3] = {0, 0, 0};
+  for (int a = 0; a < na; ++a) {
+    const double *c = s->ion_xyz + 3 * a;
+    const double d[3] = {r[0] - c[0], r[1] - c[1], r[2] - c[2]};
+    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const double F = 1.0 / (r2 * r2);
+    om[a] = F;
+    for (int x = 0; x < 3; ++x) {
+      dom[3 * a + x] = -4.0 * F / r2 * d[x]; /* dF/dr_x = -4 d_x / |d|^6 */
+      dS[x] += dom[3 * a + x];
+    }
+    S += F;
+  }
+  for (int a = 0; a < na; ++a) {
+    for (int x = 0; x < 3; ++x) dom[3 * a + x] = (dom[3 * a + x] * S - om[a] * dS[x]) / (S * S);
+    om[a] /= S;
+  }
+}
+
+int orc_warp_weights(const orc_system *s, const double r[3], double *omega, double *domega) {
+  warp_weights(s, r, omega, domega);
+  return 0;
+}
+
+/* Everything the directional derivatives need at one configuration. */
+typedef struct {
+  int ne, nb, na, nmax, nsig[2];
+  double *bd;   /* [ne][n_basis][14] basis derivatives */
+  double *od;   /* [ne][14][nmax] orbital derivatives (MOs 0..n_sigma-1) */
+  double *G[2]; /* [n][n] inverses, G[j][i] = (A^{-1})_{ji} */
+  double *X[2]; /* X = G B G */
+  double *Bm[2];/* B (one-body operator matrix, electron row i, orbital j) */
+  double *cj;   /* [ne][3] grad_i J */
+  double logdet[2];
+  int sign[2];
+  int *fn_atom;
+} zvstate;
+
+static void zv_free(zvstate *z) {
+  free(z->bd); free(z->od); free(z->cj); free(z->fn_atom);
+  for (int sp = 0; sp < 2; ++sp) { free(z->G[sp]); free(z->X[sp]); free(z->Bm[sp]); }
+}
+
+static int zv_init(const orc_system *s, const double *R, zvstate *z) {
+  int rc = 0;
+  z->ne = s->n_up + s->n_dn;
+  z->nb = s->n_basis;
+  z->na = s->n_atom;
+  z->nsig[0] = s->n_up;
+  z->nsig[1] = s->n_dn;
+  z->nmax = s->n_up > s->n_dn ? s->n_up : s->n_dn;
+  const int ne = z->ne, nb = z->nb, nm = z->nmax;
+  z->bd = (double *)malloc(sizeof(double) * (size_t)ne * nb * 14 + 1);
+  z->od = (double *)calloc((size_t)ne * 14 * nm + 1, sizeof(double));
+  z->cj = (double *)malloc(sizeof(double) * 3 * ne + 1);
+  z->fn_atom = (int *)malloc(sizeof(int) * nb + 1);
+  for (int sh = 0, f = 0; sh < s->n_shell; ++sh)
+    for (int k = 0; k < NCART[s->shell_l[sh]]; ++k) z->fn_atom[f++] = s->shell_atom[sh];
+  for (int i = 0; i < ne; ++i) {
+    double *b = z->bd + (size_t)i * nb * 14;
+    rc |= orc_basis_d3(s, R + 3 * i, b);
+    const int n = z->nsig[spin_of(s, i)];
+    double *o = z->od + (size_t)i * 14 * nm;
+    for (int q = 0; q < 14; ++q)
+      for (int j = 0; j < n; ++j) {
+        double acc = 0.0;
+        for (int l = 0; l < nb; ++l) acc += s->mo_coef[(size_t)l * s->n_mo + j] * b[14 * l + q];
+        o[q * nm + j] = acc;
+      }
+  }
+  orc_jastrow(s, R, NULL, z->cj, NULL);
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = z->nsig[sp];
+    z->G[sp] = (double *)calloc((size_t)n * n + 1, sizeof(double));
+    z->X[sp] = (double *)calloc((size_t)n * n + 1, sizeof(double));
+    z->Bm[sp] = (double *)calloc((size_t)n * n + 1, sizeof(double));
+    if (n == 0) { z->logdet[sp] = 0.0; z->sign[sp] = 1; continue; }
+    double *A = (double *)malloc(sizeof(double) * (size_t)n * n);
+    for (int ii = 0; ii < n; ++ii) {
+      const int i = ii + sp * s->n_up;
+      const double *o = z->od + (size_t)i * 14 * nm;
+      for (int j = 0; j < n; ++j) {
+        A[(size_t)ii * n + j] = o[j];
+        /* B_ij = lap phi_j + 2 grad J . grad phi_j */
+        z->Bm[sp][(size_t)ii * n + j] =
+            o[10 * nm + j] + 2.0 * (z->cj[3 * i] * o[1 * nm + j] + z->cj[3 * i + 1] * o[2 * nm + j] +
+                                    z->cj[3 * i + 2] * o[3 * nm + j]);
+      }
+    }
+    rc |= orc_lu_slogdet_inv(n, A, &z->logdet[sp], &z->sign[sp], z->G[sp]);
+    /* X = G B G (orbital x electron, like G) */
+    double *T = (double *)calloc((size_t)n * n, sizeof(double));
+    for (int i = 0; i < n; ++i)      /* T = B G : electron x electron */
+      for (int k = 0; k < n; ++k) {
+        double acc = 0.0;
+        for (int j = 0; j < n; ++j) acc += z->Bm[sp][(size_t)i * n + j] * z->G[sp][(size_t)j * n + k];
+        T[(size_t)i * n + k] = acc;
+      }
+    for (int j = 0; j < n; ++j)      /* X = G T : orbital x electron */
+      for (int k = 0; k < n; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i < n; ++i) acc += z->G[sp][(size_t)j * n + i] * T[(size_t)i * n + k];
+        z->X[sp][(size_t)j * n + k] = acc;
+      }
+    free(T);
+    free(A);
+  }
+  return rc;
+}
+
+/* Directional derivative of E_L and ln|Psi| when the ions move by dion
+ * [n_atom][3] and the electrons by del [ne][3] (both per unit lambda). */
+static void zv_direction(const orc_system *s, const double *R, const zvstate *z,
+                         const double *dion, const double *del, double *dEL, double *dlogpsi) {
+  const int ne = z->ne, nb = z->nb, na = z->na, nm = z->nmax;
+  /* ---- determinant part: Eq. 3 and Eq. 4 per spin */
+  double det_e = 0.0, det_l = 0.0;
+  double *dA = (double *)malloc(sizeof(double) * (size_t)nm + 1);
+  double *dBl = (double *)malloc(sizeof(double) * (size_t)nm + 1);
+  double *dBg = (double *)malloc(sizeof(double) * 3 * (size_t)nm + 1);
+  double *dcj = (double *)calloc((size_t)3 * ne + 1, sizeof(double));
+  /* d(grad_i J) along the direction (needed inside dB) */
+  for (int i = 0; i < ne; ++i) {
+    for (int j = 0; j < ne; ++j) {
+      if (j == i) continue;
+      const double d[3] = {R[3 * i] - R[3 * j], R[3 * i + 1] - R[3 * j + 1], R[3 * i + 2] - R[3 * j + 2]};
+      const pair_d p = pade_vec(ee_a(s, i, j), s->jee_b, d);
+      for (int x = 0; x < 3; ++x)
+        for (int y = 0; y < 3; ++y) dcj[3 * i + x] += p.H[x][y] * (del[3 * i + y] - del[3 * j + y]);
+    }
+    for (int A = 0; A < na; ++A) {
+      const double *c = s->ion_xyz + 3 * A;
+      const double d[3] = {R[3 * i] - c[0], R[3 * i + 1] - c[1], R[3 * i + 2] - c[2]};
+      const pair_d p = pade_vec(s->jen_a[A], s->jen_b, d);
+      for (int x = 0; x < 3; ++x)
+        for (int y = 0; y < 3; ++y) dcj[3 * i + x] += p.H[x][y] * (del[3 * i + y] - dion[3 * A + y]);
+    }
+  }
+  for (int i = 0; i < ne; ++i) {
+    const int sp = spin_of(s, i), ii = i - sp * s->n_up, n = z->nsig[sp];
+    const double *o = z->od + (size_t)i * 14 * nm;
+    const double *b = z->bd + (size_t)i * nb * 14;
+    const double *dr = del + 3 * i;
+    /* row i of dA, d(grad A) and d(lap A): electron part through the orbital
+     * derivatives, ion part through the basis functions of each moving atom */
+    for (int j = 0; j < n; ++j) {
+      double a = 0.0, lp = 0.0, g[3] = {0, 0, 0};
+      for (int x = 0; x < 3; ++x) {
+        a += o[(1 + x) * nm + j] * dr[x];
+        lp += o[(11 + x) * nm + j] * dr[x];
+        for (int y = 0; y < 3; ++y) g[y] += o[(4 + hidx(x, y)) * nm + j] * dr[x];
+      }
+      dA[j] = a;
+      dBl[j] = lp;
+      for (int y = 0; y < 3; ++y) dBg[y * nm + j] = g[y];
+    }
+    for (int l = 0; l < nb; ++l) {
+      const double *dR = dion + 3 * z->fn_atom[l];
+      if (dR[0] == 0.0 && dR[1] == 0.0 && dR[2] == 0.0) continue;
+      const double *bl = b + 14 * l;
+      double a = 0.0, lp = 0.0, g[3] = {0, 0, 0};
+      for (int x = 0; x < 3; ++x) {
+        a -= bl[1 + x] * dR[x];
+        lp -= bl[11 + x] * dR[x];
+        for (int y = 0; y < 3; ++y) g[y] -= bl[4 + hidx(x, y)] * dR[x];
+      }
+      for (int j = 0; j < n; ++j) {
+        const double C = s->mo_coef[(size_t)l * s->n_mo + j];
+        dA[j] += C * a;
+        dBl[j] += C * lp;
+        for (int y = 0; y < 3; ++y) dBg[y * nm + j] += C * g[y];
+      }
+    }
+    /* tr(G dA), tr(G dB) and tr(X dA) restricted to row i */
+    const double *ci = z->cj + 3 * i, *dci = dcj + 3 * i;
+    for (int j = 0; j < n; ++j) {
+      const double gji = z->G[sp][(size_t)j * n + ii], xji = z->X[sp][(size_t)j * n + ii];
+      double dB = dBl[j];
+      for (int y = 0; y < 3; ++y) dB += 2.0 * (dci[y] * o[(1 + y) * nm + j] + ci[y] * dBg[y * nm + j]);
+      det_l += gji * dA[j];
+      det_e += gji * dB - xji * dA[j];
+    }
+  }
+  /* ---- Jastrow and potential, pair by pair */
+  double jl = 0.0, jq = 0.0, dJ = 0.0, dV = 0.0;
+  for (int i = 0; i < ne; ++i) {
+    const double *ci = z->cj + 3 * i, *dci = dcj + 3 * i;
+    jq += 2.0 * (ci[0] * dci[0] + ci[1] * dci[1] + ci[2] * dci[2]); /* d |grad_i J|^2 */
+    for (int j = 0; j < ne; ++j) {
+      if (j == i) continue;
+      const double d[3] = {R[3 * i] - R[3 * j], R[3 * i + 1] - R[3 * j + 1], R[3 * i + 2] - R[3 * j + 2]};
+      const double dd[3] = {del[3 * i] - del[3 * j], del[3 * i + 1] - del[3 * j + 1],
+                            del[3 * i + 2] - del[3 * j + 2]};
+      const pair_d p = pade_vec(ee_a(s, i, j), s->jee_b, d);
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      for (int x = 0; x < 3; ++x) {
+        jl += p.glap[x] * dd[x];
+        if (j > i) {
+          dJ += p.g[x] * dd[x];
+          dV -= d[x] / (r * r * r) * dd[x];
+        }
+      }
+    }
+    for (int A = 0; A < na; ++A) {
+      const double *c = s->ion_xyz + 3 * A;
+      const double d[3] = {R[3 * i] - c[0], R[3 * i + 1] - c[1], R[3 * i + 2] - c[2]};
+      const double dd[3] = {del[3 * i] - dion[3 * A], del[3 * i + 1] - dion[3 * A + 1],
+                            del[3 * i + 2] - dion[3 * A + 2]};
+      const pair_d p = pade_vec(s->jen_a[A], s->jen_b, d);
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      for (int x = 0; x < 3; ++x) {
+        jl += p.glap[x] * dd[x];
+        dJ += p.g[x] * dd[x];
+        dV += s->ion_charge[A] * d[x] / (r * r * r) * dd[x];
+      }
+    }
+  }
+  for (int A = 0; A < na; ++A)
+    for (int B = A + 1; B < na; ++B) {
+      const double *a = s->ion_xyz + 3 * A, *b = s->ion_xyz + 3 * B;
+      const double d[3] = {a[0] - b[0], a[1] - b[1], a[2] - b[2]};
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      for (int x = 0; x < 3; ++x)
+        dV -= s->ion_charge[A] * s->ion_charge[B] * d[x] / (r * r * r) * (dion[3 * A + x] - dion[3 * B + x]);
+    }
+  *dEL = -0.5 * (det_e + jl + jq) + dV;
+  *dlogpsi = det_l + dJ;
+  free(dA); free(dBl); free(dBg); free(dcj);
+}
+
+int orc_local_energy_dir(const orc_system *s, const double *R, const double *dion,
+                         const double *del, double *dEL, double *dlogpsi) {
+  if (s->n_det > 1) return 4;
+  zvstate z;
+  int rc = zv_init(s, R, &z);
+  zv_direction(s, R, &z, dion, del, dEL, dlogpsi);
+  zv_free(&z);
+  return rc;
+}
+
+/* Per ion coordinate (a, x): dE_L, d ln|Psi| and d ln(Jacobian) along the
+ * ion displacement alone (warp = 0) or with the space warp (warp = 1).
+ * Outputs [n_atom][3] each. */
+int orc_zv_grads(const orc_system *s, const double *R, int32_t warp, double *dEL,
+                 double *dlogpsi, double *dlogjac) {
+  if (s->n_det > 1) return 4;
+  const int ne = s->n_up + s->n_dn, na = s->n_atom;
+  zvstate z;
+  int rc = zv_init(s, R, &z);
+  double *om = (double *)calloc((size_t)ne * na + 1, sizeof(double));
+  double *dom = (double *)calloc((size_t)ne * na * 3 + 1, sizeof(double));
+  if (warp)
+    for (int i = 0; i < ne; ++i) warp_weights(s, R + 3 * i, om + (size_t)i * na, dom + (size_t)i * na * 3);
+  double *dion = (double *)calloc((size_t)na * 3 + 1, sizeof(double));
+  double *del = (double *)calloc((size_t)ne * 3 + 1, sizeof(double));
+  for (int a = 0; a < na; ++a)
+    for (int x = 0; x < 3; ++x) {
+      memset(dion, 0, sizeof(double) * na * 3);
+      memset(del, 0, sizeof(double) * ne * 3);
+      dion[3 * a + x] = 1.0;
+      double jac = 0.0;
+      for (int i = 0; i < ne; ++i) {
+        del[3 * i + x] = om[(size_t)i * na + a];
+        jac += dom[((size_t)i * na + a) * 3 + x];
+      }
+      zv_direction(s, R, &z, dion, del, dEL + 3 * a + x, dlogpsi + 3 * a + x);
+      dlogjac[3 * a + x] = jac;
+    }
+  free(om); free(dom); free(dion); free(del);
+  zv_free(&z);
+  return rc;
+}
+
+int orc_zv_grads_batch(const orc_system *s, int32_t W, const double *R, int32_t warp, double *dEL,
+                       double *dlogpsi, double *dlogjac, int32_t n_threads) {
+  const int ne = s->n_up + s->n_dn, na = s->n_atom;
+  int rc = 0;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(dynamic) reduction(| : rc)
+  for (int w = 0; w < W; ++w)
+    rc |= orc_zv_grads(s, R + (size_t)w * ne * 3, warp, dEL + (size_t)w * na * 3,
+                       dlogpsi + (size_t)w * na * 3, dlogjac + (size_t)w * na * 3);
+  return rc;
+}

@@ -127,6 +127,24 @@ int orc_msd_evaluate(const orc_system *s, const double *R, double *log_psi, int3
 int orc_reconfigure(int32_t W, const double *log_w, double u, int32_t *copies, int32_t *pairs,
                     int32_t *n_pairs, double *log_wbar);
 
+
+/* Derivative of the local energy (Single Determinant QMC Forces, Eq. 4) and
+ * of ln|Psi| (Eq. 3) along a direction of the ions (dion [n_atom][3]) and
+ * electrons (del [ne][3]); single determinant only (4 otherwise). */
+int orc_local_energy_dir(const orc_system *s, const double *R, const double *dion,
+                         const double *del, double *dEL, double *dlogpsi);
+/* Per ion coordinate: dE_L, d ln|Psi|, d ln(Jacobian) [n_atom][3], with
+ * (warp = 1) or without the space warp. */
+int orc_zv_grads(const orc_system *s, const double *R, int32_t warp, double *dEL,
+                 double *dlogpsi, double *dlogjac);
+int orc_zv_grads_batch(const orc_system *s, int32_t W, const double *R, int32_t warp, double *dEL,
+                       double *dlogpsi, double *dlogjac, int32_t n_threads);
+/* Basis value, gradient, Hessian (xx,xy,xz,yy,yz,zz), Laplacian and
+ * gradient of the Laplacian: out[n_basis][14]. */
+int orc_basis_d3(const orc_system *s, const double r[3], double *out);
+/* Space-warp weights omega_a(r) [n_atom] and their gradients [n_atom][3]. */
+int orc_warp_weights(const orc_system *s, const double r[3], double *omega, double *domega);
+
 #ifdef __cplusplus
 }
 #endif
