@@ -157,8 +157,9 @@ def batch5_leg(torch, dmcx, stream, steps=5, W=512, n_det=1000, n_active=100, P=
 
 
 def forces_leg(s, torch, dmcx, stream, args, W=1024, steps=5):
-    """Forces every step (192 components, Hellmann-Feynman + Pulay via the
-    adjoint) vs energy-only steps, 1024 walkers, FP64."""
+    """Forces every step (192 components) vs energy-only steps, 1024 walkers,
+    FP64 and mixed: Hellmann-Feynman + Pulay via the Eq. 3 adjoint, and the
+    zero-variance estimator (Eq. 4 derivative of E_L) with the space warp."""
     from paper_2504_07948_amd import synth
     R0 = synth.make_walkers(s, W, 2027)
     out = {"walkers": W, "steps": steps, "components": 3 * s.n_atom}
@@ -183,8 +184,19 @@ def forces_leg(s, torch, dmcx, stream, args, W=1024, steps=5):
             ctx.check(dmcx.dmcx_forces(ctx.h, F.data_ptr(), dmcx.DMCX_DEVICE))
         torch.cuda.synchronize()
         t_f = time.perf_counter() - t0
+        # zero-variance force (Eq. 4 derivative of E_L) with the space warp, every step
+        ctx.check(dmcx.dmcx_forces_zv(ctx.h, 1, F.data_ptr(), dmcx.DMCX_DEVICE))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.run_device(1, mode=dmcx.DMCX_DMC, e_trial=e_t)
+            ctx.check(dmcx.dmcx_forces_zv(ctx.h, 1, F.data_ptr(), dmcx.DMCX_DEVICE))
+        torch.cuda.synchronize()
+        t_z = time.perf_counter() - t0
         out[name] = {"ms_step_energy": 1e3 * t_e / steps, "ms_step_with_forces": 1e3 * t_f / steps,
-                     "force_energy_cost_ratio": t_f / t_e}
+                     "force_energy_cost_ratio": t_f / t_e,
+                     "ms_step_with_zv_warp_forces": 1e3 * t_z / steps,
+                     "zv_warp_force_energy_cost_ratio": t_z / t_e}
     return out
 
 

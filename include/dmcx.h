@@ -245,6 +245,32 @@ dmcx_status dmcx_potential_vjp(dmcx_ctx *ctx, const double *gbar, double *grad_R
  * F: [n_sys][n_atom_max][3]. */
 dmcx_status dmcx_forces(dmcx_ctx *ctx, double *F, dmcx_mem mem);
 
+/* Passage: Single Determinant QMC Forces, Eq. 4 (d E_L / d R_a =
+ * tr(A^{-1} dB/dR_a - X dA/dR_a), X = A^{-1} B A^{-1}, with B read as the
+ * one-body operator matrix B_ij = lap phi_j(r_i) + 2 grad_i J . grad phi_j(r_i)
+ * so that tr(A^{-1} B) carries the determinant part of the kinetic energy)
+ * and the space-warp transformation of the same section (Filippi-Umrigar
+ * warp: electrons follow ion a with weight omega_a(r) = F_a / sum_b F_b,
+ * F_b = |r - R_b|^-4).
+ * Per-walker derivatives along every ion coordinate, [W][n_atom_max][3] each
+ * (any pointer may be NULL): dEL = dE_L/dR (zero-variance term, kinetic and
+ * potential parts), dlogpsi = d ln|Psi|/dR, dlogjac = d ln(Jacobian)/dR of
+ * the warp.  warp = 0: the ion coordinate alone (dlogjac = 0); warp = 1:
+ * ion plus warped electrons.  Reverse-mode adjoint through the inverse, the
+ * MO contraction (two MFMA products per electron) and third derivatives of
+ * the basis.  Single-determinant systems only (DMCX_E_UNSUPPORTED
+ * otherwise); DMCX_E_INVALID for warp outside {0, 1}. */
+dmcx_status dmcx_zv_grads(dmcx_ctx *ctx, int32_t warp, double *dEL, double *dlogpsi,
+                          double *dlogjac, dmcx_mem mem);
+
+/* Passage: Single Determinant QMC Forces (zero-variance force estimator of
+ * Eq. 4 with the Pulay covariance and the space warp), walker weights of Eq. 1.
+ * F[n_sys][n_atom_max][3] = -<dE_L/dR> - (<E_L q> - <E_L><q>),
+ * q = 2 d ln|Psi|/dR + d ln(Jacobian)/dR, weights exp(log w); walkers with a
+ * status flag or a non-finite log w or E_L have weight zero.  Errors as
+ * dmcx_zv_grads. */
+dmcx_status dmcx_forces_zv(dmcx_ctx *ctx, int32_t warp, double *F, dmcx_mem mem);
+
 /* Passage: QMC section, Eq. 1 (the walker weights of the projection) and the
  * fixed-node DMC estimators built on them.
  * Weighted estimators of each system's walkers, in FP64: out[n_sys][11] with

@@ -64,6 +64,14 @@ struct dmcx_ctx {
   uint8_t *d_acc8 = nullptr;       // [Wpad]
   // population control (comb reconfiguration) scratch
   PopScratch pop{};
+  // zero-variance forces (single determinant): c_i and g_i [Wpad][ne][6], electron and
+  // direct ion gradients of the Jastrow part [Wpad][ne][3] / [Wpad][n_atom][3], X^T and its
+  // first product [Wpad][2][NP][NP], tile and per-electron sums, and the per-walker results
+  double *d_zcg = nullptr, *d_zgjv = nullptr, *d_zdjv = nullptr, *d_zpart = nullptr,
+         *d_zs = nullptr, *d_zel = nullptr, *d_zlp = nullptr, *d_zj = nullptr;
+  void *d_ztp = nullptr, *d_zxt = nullptr;
+  uint64_t zv_version = 0;
+  int zv_warp = -1;
   // weighted estimators: block records [est_blocks(W)][EST_PART], host staging [EST_OUT]
   double *d_est_part = nullptr, *d_est_out = nullptr;
   // scratch
@@ -560,6 +568,44 @@ dmcx_status compute_ion_grads(dmcx_ctx *c) {
   return DMCX_OK;
 }
 
+// Per-walker zero-variance derivatives (Eq. 4, optionally space-warped) for
+// the current configuration (cached per configuration version and warp flag).
+dmcx_status compute_zv(dmcx_ctx *c, int warp) {
+  if (c->dc.M.on)
+    return fail(c, DMCX_E_UNSUPPORTED, "zero-variance forces: single-determinant systems only");
+  dmcx_status st = compute_ion_grads(c);  // also brings E_L and the inverses up to date
+  if (st) return st;
+  if (c->zv_version == c->version && c->zv_warp == warp) return DMCX_OK;
+  const int ntile = (c->ne + FPTS - 1) / FPTS;
+  const size_t lds_prep = (size_t)c->ne * 6 * sizeof(double);
+  const size_t lds_fin = warp ? (size_t)c->ne * 4 * sizeof(double) : 0;
+  if (c->mixed) {
+    hipLaunchKernelGGL(k_zv_prep<float>, dim3(c->Wpad), dim3(NT_AUX), lds_prep, c->stream, c->dc,
+                       c->d_zcg, c->d_zgjv, c->d_zdjv);
+    hipLaunchKernelGGL(k_zv_x<float>, dim3(c->Wpad, 2), dim3(NT_AUX), 0, c->stream, c->dc,
+                       c->d_zcg, (float *)c->d_ztp, (float *)c->d_zxt);
+    HIP_TRY(c, hipGetLastError());
+    NobLaunch<float>::zv_det(c->NOB, c->dc, (const float *)c->d_zxt, c->d_zcg, c->d_zpart, c->d_zs,
+                             ntile, basis_lds(c), c->stream);
+  } else {
+    hipLaunchKernelGGL(k_zv_prep<double>, dim3(c->Wpad), dim3(NT_AUX), lds_prep, c->stream, c->dc,
+                       c->d_zcg, c->d_zgjv, c->d_zdjv);
+    hipLaunchKernelGGL(k_zv_x<double>, dim3(c->Wpad, 2), dim3(NT_AUX), 0, c->stream, c->dc,
+                       c->d_zcg, (double *)c->d_ztp, (double *)c->d_zxt);
+    HIP_TRY(c, hipGetLastError());
+    NobLaunch<double>::zv_det(c->NOB, c->dc, (const double *)c->d_zxt, c->d_zcg, c->d_zpart,
+                              c->d_zs, ntile, basis_lds(c), c->stream);
+  }
+  HIP_TRY(c, hipGetLastError());
+  hipLaunchKernelGGL(k_zv_finalize, dim3(c->Wpad), dim3(64), lds_fin, c->stream, c->dc, warp,
+                     c->d_zpart, c->d_zs, c->d_zcg, c->d_zgjv, c->d_zdjv, c->d_dl, c->d_dv,
+                     c->d_zel, c->d_zlp, c->d_zj);
+  HIP_TRY(c, hipGetLastError());
+  c->zv_version = c->version;
+  c->zv_warp = warp;
+  return DMCX_OK;
+}
+
 dmcx_status walker_vjp(dmcx_ctx *c, const double *src, const double *gbar, double *grad_R,
                        dmcx_mem mem) {
   if (!c || !gbar || !grad_R) return DMCX_E_INVALID;
@@ -820,6 +866,21 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
   if ((st = dalloc(c, &c->d_rg, Wp * 4))) return bail(st);
   if ((st = dalloc(c, &c->d_acc8, Wp))) return bail(st);
   if ((st = dalloc(c, &d.flags, Wp))) return bail(st);
+  if (s.n_det <= 1) {
+    const size_t ntile = (c->ne + FPTS - 1) / FPTS, na3 = (size_t)s.n_atom * 3;
+    if ((st = dalloc(c, &c->d_zcg, Wp * c->ne * 6))) return bail(st);
+    if ((st = dalloc(c, &c->d_zgjv, Wp * c->ne * 3))) return bail(st);
+    if ((st = dalloc(c, &c->d_zdjv, Wp * na3))) return bail(st);
+    if ((st = dalloc(c, &c->d_zpart, Wp * ntile * na3))) return bail(st);
+    if ((st = dalloc(c, &c->d_zs, Wp * c->ne * 3))) return bail(st);
+    if ((st = dalloc(c, &c->d_zel, Wp * na3))) return bail(st);
+    if ((st = dalloc(c, &c->d_zlp, Wp * na3))) return bail(st);
+    if ((st = dalloc(c, &c->d_zj, Wp * na3))) return bail(st);
+    if ((st = dalloc(c, &pv, es * Wp * 2 * c->NP * c->NP))) return bail(st);
+    c->d_ztp = pv;
+    if ((st = dalloc(c, &pv, es * Wp * 2 * c->NP * c->NP))) return bail(st);
+    c->d_zxt = pv;
+  }
   if ((st = dalloc(c, &d.nacc, Wp))) return bail(st);
   if ((st = dalloc(c, &d.nprop, Wp))) return bail(st);
   if ((st = dalloc(c, &c->d_est_part, (size_t)est_blocks(c->W) * EST_PART))) return bail(st);
@@ -1652,6 +1713,55 @@ dmcx_status dmcx_forces(dmcx_ctx *c, double *F, dmcx_mem mem) {
   double *dst = mem == DMCX_DEVICE ? F : c->d_red;
   hipLaunchKernelGGL(k_force_estimator, dim3(ncomp), dim3(256), 0, c->stream, c->dc, c->d_dl,
                      c->d_dv, dst);
+  HIP_TRY(c, hipGetLastError());
+  if (mem == DMCX_HOST) return copy_out(c, F, c->d_red, ncomp * sizeof(double), mem);
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_zv_grads(dmcx_ctx *c, int32_t warp, double *dEL, double *dlogpsi,
+                          double *dlogjac, dmcx_mem mem) {
+  if (!c || (warp != 0 && warp != 1)) return DMCX_E_INVALID;
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  dmcx_status st;
+  if (c->is_group()) {
+    const size_t pitch = (size_t)c->n_atom * 3 * sizeof(double);
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      dmcx_ctx *m = c->subs[i];
+      const size_t off = c->sub_off[i] * (size_t)c->n_atom * 3, wb = (size_t)m->n_atom * 3 * sizeof(double);
+      if ((st = compute_zv(m, warp))) return c->err = m->err, st;
+      double *dst[3] = {dEL, dlogpsi, dlogjac};
+      const double *src[3] = {m->d_zel, m->d_zlp, m->d_zj};
+      for (int q = 0; q < 3; ++q)
+        if (dst[q] && (st = copy2d(m, dst[q] + off, pitch, src[q], wb, wb, m->W, mem, false)))
+          return c->err = m->err, st;
+    }
+    return DMCX_OK;
+  }
+  if ((st = compute_zv(c, warp))) return st;
+  const size_t bytes = (size_t)c->W * c->n_atom * 3 * sizeof(double);
+  if (dEL && (st = copy_out(c, dEL, c->d_zel, bytes, mem))) return st;
+  if (dlogpsi && (st = copy_out(c, dlogpsi, c->d_zlp, bytes, mem))) return st;
+  if (dlogjac && (st = copy_out(c, dlogjac, c->d_zj, bytes, mem))) return st;
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_forces_zv(dmcx_ctx *c, int32_t warp, double *F, dmcx_mem mem) {
+  if (!c || !F || (warp != 0 && warp != 1)) return DMCX_E_INVALID;
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  dmcx_status st;
+  if (c->is_group()) {
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      dmcx_ctx *m = c->subs[i];
+      if ((st = dmcx_forces_zv(m, warp, F + i * (size_t)c->n_atom * 3, mem)))
+        return c->err = m->err, st;
+    }
+    return DMCX_OK;
+  }
+  if ((st = compute_zv(c, warp))) return st;
+  const int ncomp = c->n_atom * 3;
+  double *dst = mem == DMCX_DEVICE ? F : c->d_red;
+  hipLaunchKernelGGL(k_zv_force_estimator, dim3(ncomp), dim3(256), 0, c->stream, c->dc, c->d_zel,
+                     c->d_zlp, c->d_zj, dst);
   HIP_TRY(c, hipGetLastError());
   if (mem == DMCX_HOST) return copy_out(c, F, c->d_red, ncomp * sizeof(double), mem);
   return DMCX_OK;

@@ -56,8 +56,10 @@ __global__ __launch_bounds__(EST_NB) void k_est_partial(DevCtx c, double *part) 
   __shared__ double red[EST_NB / 64];
   const int w = blockIdx.x * EST_NB + threadIdx.x;
   const bool real = w < c.W;
-  const double lw = real ? c.logw[w] : 0.0, e = real ? c.eloc[w] : 0.0;
-  const bool ok = real && c.flags[w] == 0u && isfinite(lw) && isfinite(e);
+  const double lw_in = real ? c.logw[w] : 0.0, e_in = real ? c.eloc[w] : 0.0;
+  const bool ok = real && c.flags[w] == 0u && isfinite(lw_in) && isfinite(e_in);
+  // excluded walkers enter every sum as exact zeros (0 * NaN would not be)
+  const double lw = ok ? lw_in : 0.0, e = ok ? e_in : 0.0;
   double na = 0.0, np = 0.0;
   if (real) {
     na = (double)c.nacc[w];

@@ -3,6 +3,7 @@
 #pragma once
 #include "forces.h"
 #include "launch.h"
+#include "zv.h"
 
 namespace dmcx {
 
@@ -79,6 +80,16 @@ void NobLaunch<T>::ion_grad_det(int nob, const DevCtx &c, double *partial, int n
 #define DMCX_CALL(N)                                                                   \
   if (allow_lds(k_ion_grad_det<T, N>, lds) == hipSuccess) \
   k_ion_grad_det<T, N><<<dim3(c.Wpad * ntile), dim3(NT_FORCE), lds, s>>>(c, partial)
+  DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+}
+
+template <typename T>
+void NobLaunch<T>::zv_det(int nob, const DevCtx &c, const T *xt, const double *cg, double *zpart,
+                          double *zs, int ntile, size_t lds, hipStream_t s) {
+#define DMCX_CALL(N)                                                                   \
+  if (allow_lds(k_zv_det<T, N>, lds) == hipSuccess) \
+  k_zv_det<T, N><<<dim3(c.Wpad * ntile), dim3(NT_FORCE), lds, s>>>(c, xt, cg, zpart, zs)
   DMCX_NOB_SWITCH(nob, DMCX_CALL)
 #undef DMCX_CALL
 }

@@ -37,6 +37,9 @@ struct NobLaunch {
   // per-tile determinant part of the ion derivatives
   static void ion_grad_det(int nob, const DevCtx &c, double *partial, int ntile, size_t lds,
                            hipStream_t s);
+  // determinant adjoint of the Eq. 4 local-energy derivative (zero-variance forces)
+  static void zv_det(int nob, const DevCtx &c, const T *xt, const double *cg, double *zpart,
+                     double *zs, int ntile, size_t lds, hipStream_t s);
   // move-by-move interface
   static void block_init(int nob, const DevCtx &c, int sp, int b0, int kb, hipStream_t s);
   static void ratio_grad(int nob, const DevCtx &c, int iel, int m, const double *r_new,

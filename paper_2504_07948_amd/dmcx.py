@@ -32,6 +32,7 @@ EXPORTED = [
     "dmcx_potential_vjp", "dmcx_forces", "dmcx_potential", "dmcx_walker_flags", "dmcx_sync", "dmcx_last_run_timing",
     "dmcx_selftest", "dmcx_philox", "dmcx_strerror", "dmcx_last_error", "dmcx_autotune",
     "dmcx_autotune_report", "dmcx_get_delay_rank", "dmcx_reconfigure", "dmcx_estimators",
+    "dmcx_zv_grads", "dmcx_forces_zv",
 ]
 
 
@@ -107,6 +108,8 @@ def load():
         "dmcx_autotune_report": [P, I32, I32, P, P, P],
         "dmcx_get_delay_rank": [P, I32, P],
         "dmcx_estimators": [P, P, I32],
+        "dmcx_zv_grads": [P, I32, P, P, P, I32],
+        "dmcx_forces_zv": [P, I32, P, I32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -210,6 +213,14 @@ def dmcx_potential_vjp(ctx, gbar, grad_R, mem):
 
 def dmcx_forces(ctx, F, mem):
     return load().dmcx_forces(ctx, F, mem)
+
+
+def dmcx_zv_grads(ctx, warp, dEL, dlogpsi, dlogjac, mem):
+    return load().dmcx_zv_grads(ctx, warp, dEL, dlogpsi, dlogjac, mem)
+
+
+def dmcx_forces_zv(ctx, warp, F, mem):
+    return load().dmcx_forces_zv(ctx, warp, F, mem)
 
 
 def dmcx_estimators(ctx, out, mem):
@@ -426,6 +437,17 @@ class Context:
     def forces(self):
         F = self._per_system()
         self.check(dmcx_forces(self.h, _ptr(F), DMCX_HOST))
+        return F
+
+    def zv_grads(self, warp=True):
+        """Per-walker (dE_L/dR, d ln|Psi|/dR, d ln J/dR), [W][n_atom][3] each."""
+        out = [np.zeros((self.W, self.n_atom, 3)) for _ in range(3)]
+        self.check(dmcx_zv_grads(self.h, int(bool(warp)), *[_ptr(a) for a in out], DMCX_HOST))
+        return tuple(out)
+
+    def forces_zv(self, warp=True):
+        F = self._per_system()
+        self.check(dmcx_forces_zv(self.h, int(bool(warp)), _ptr(F), DMCX_HOST))
         return F
 
     def estimators(self):

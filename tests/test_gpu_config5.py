@@ -91,7 +91,7 @@ def test_c3h8_full_expansion_runs_match_oracle(prec):
     ref = oracle.run(s, R, n_steps=steps, mode=1, tau=0.01, seed=41, e_trial=e_t)
     np.testing.assert_array_equal(acc, ref["accept_log"])
     Rg, _ = ctx.get_walkers()
-    _close(Rg, ref["R"], rel=1e-10 if prec == dmcx.DMCX_FP64 else 1e-5)
+    _close(Rg, ref["R"], rel=rel)
     _check(el[-1], ref["e_log"][-1], s, ref["R"], "E_L after the run", rel)
 
 

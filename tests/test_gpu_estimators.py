@@ -41,7 +41,10 @@ def test_estimators_match_oracle_run(mode, graph):
     s = synth.small_molecule()
     W, n, tau, seed = 300, 6, 0.01, 13   # two blocks of 256, the second ragged
     R = synth.make_walkers(s, W, 5150)
-    lw0 = np.random.default_rng(5).normal(0.0, 0.5, W)
+    # VMC leaves the weights alone: start it from equal weights so its estimate
+    # is also the plain mean of E_L
+    lw0 = (np.random.default_rng(5).normal(0.0, 0.5, W) if mode == dmcx.DMCX_DMC
+           else np.zeros(W))
     _, _, e0, _ = oracle.evaluate_batch(s, R)
     e_t = float(np.mean(e0))
     ctx = dmcx.Context(s, W, delay_rank=1, recompute_period=4, tau=tau, seed=seed, graph=graph)
