@@ -19,14 +19,29 @@ constexpr int FPTS = 32;        // electron points per force tile
 constexpr int MAX_ATOM = 256;   // per-tile atom accumulators in LDS
 constexpr int NT_FORCE = 256;
 
+// Shell totals of one stage, binned by atom: slot[sl][3] holds the total of
+// the stage's shell slot sl and satom[sl] its atom (-1: padding).  Thread i
+// (i < 3 n_atom) adds the totals of atom i / 3 in slot order, so the sums do
+// not depend on how the waves were scheduled (no atomics).
+__device__ __forceinline__ void bin_slots(int nsh, const double *slot, const int *satom,
+                                          double *bin, int n_atom) {
+  for (int i = threadIdx.x; i < n_atom * 3; i += NT_FORCE) {
+    const int a = i / 3, x = i % 3;
+    double s = bin[i];
+    for (int sl = 0; sl < nsh; ++sl)
+      if (satom[sl] == a) s += slot[sl * 3 + x];
+    bin[i] = s;
+  }
+}
+
 // Gradient-only evaluation of one stage's shells at the tile's points,
-// weighted by Ys[f][n] and summed per atom into fbin (LDS, FP64 atomics).
-// Lane task (point n = lane % 32, shell); the 32 points of a shell are
-// reduced across lanes before one atomic per atom component.
+// weighted by Ys[f][n]; lane task (point n = lane % 32, shell).  The 32
+// points of a shell are reduced across lanes into the shell's slot total
+// (slot, satom; binned by atom with bin_slots after a barrier).
 template <typename T, int L, int NPR>
 __device__ void force_stage_t(const BasisLDS &B, const int *gatom, int g_begin, int g_end,
                               int fn_begin, const double (*pts)[3], int npts, const T *Ys,
-                              double *fbin, int npr_rt = NPR) {
+                              double *slot, int *satom, int npr_rt = NPR) {
   constexpr int NC = L == 0 ? 1 : (L == 1 ? 3 : 6);
   const int nsh = 4 * (g_end - g_begin);
   const int tid = threadIdx.x;
@@ -82,11 +97,11 @@ __device__ void force_stage_t(const BasisLDS &B, const int *gatom, int g_begin, 
     f0 = sum32(f0);
     f1 = sum32(f1);
     f2 = sum32(f2);
-    const int atom = gatom[g * 4 + s];
-    if (n == 0 && atom >= 0) {
-      atomicAdd(&fbin[atom * 3 + 0], f0);
-      atomicAdd(&fbin[atom * 3 + 1], f1);
-      atomicAdd(&fbin[atom * 3 + 2], f2);
+    if (n == 0) {
+      slot[sl * 3 + 0] = f0;
+      slot[sl * 3 + 1] = f1;
+      slot[sl * 3 + 2] = f2;
+      satom[sl] = gatom[g * 4 + s];
     }
   }
 }
@@ -94,18 +109,18 @@ __device__ void force_stage_t(const BasisLDS &B, const int *gatom, int g_begin, 
 template <typename T>
 __device__ inline void force_stage(const BasisLDS &B, const int *gatom, int g_begin, int g_end,
                                    int fn_begin, const double (*pts)[3], int npts,
-                                   const T *Ys, double *fbin) {
+                                   const T *Ys, double *slot, int *satom) {
   const int4 gi = B.ginfo[g_begin];
 #define DMCX_FORCE_CASE(LL, NN)                                                              \
   case LL * 16 + NN:                                                                         \
-    force_stage_t<T, LL, NN>(B, gatom, g_begin, g_end, fn_begin, pts, npts, Ys, fbin); break;
+    force_stage_t<T, LL, NN>(B, gatom, g_begin, g_end, fn_begin, pts, npts, Ys, slot, satom); break;
   switch (gi.x * 16 + (gi.y <= 4 ? gi.y : 0)) {
     DMCX_FORCE_CASE(0, 1) DMCX_FORCE_CASE(0, 2) DMCX_FORCE_CASE(0, 3) DMCX_FORCE_CASE(0, 4)
     DMCX_FORCE_CASE(1, 1) DMCX_FORCE_CASE(1, 2) DMCX_FORCE_CASE(1, 3) DMCX_FORCE_CASE(1, 4)
     DMCX_FORCE_CASE(2, 1) DMCX_FORCE_CASE(2, 2) DMCX_FORCE_CASE(2, 3) DMCX_FORCE_CASE(2, 4)
-    case 0: force_stage_t<T, 0, 0>(B, gatom, g_begin, g_end, fn_begin, pts, npts, Ys, fbin, gi.y); break;
-    case 16: force_stage_t<T, 1, 0>(B, gatom, g_begin, g_end, fn_begin, pts, npts, Ys, fbin, gi.y); break;
-    case 32: force_stage_t<T, 2, 0>(B, gatom, g_begin, g_end, fn_begin, pts, npts, Ys, fbin, gi.y); break;
+    case 0: force_stage_t<T, 0, 0>(B, gatom, g_begin, g_end, fn_begin, pts, npts, Ys, slot, satom, gi.y); break;
+    case 16: force_stage_t<T, 1, 0>(B, gatom, g_begin, g_end, fn_begin, pts, npts, Ys, slot, satom, gi.y); break;
+    case 32: force_stage_t<T, 2, 0>(B, gatom, g_begin, g_end, fn_begin, pts, npts, Ys, slot, satom, gi.y); break;
     default: break;
   }
 #undef DMCX_FORCE_CASE
@@ -124,6 +139,8 @@ __global__ __launch_bounds__(NT_FORCE) void k_ion_grad_det(DevCtx c, double *par
   __shared__ T Gp[NP * FPTS];   // B operand: Gp[k][n] = g_n[k]
   __shared__ T Ys[FM * FPTS];   // y of the stage's functions
   __shared__ double fbin[MAX_ATOM * 3];
+  __shared__ double slot[FM * 3];  // shell totals of the current stage
+  __shared__ int satom[FM];
   __shared__ double pts[FPTS][3];
   const int ntile = (c.ne + FPTS - 1) / FPTS;
   const int w = blockIdx.x / ntile, tile = blockIdx.x % ntile;
@@ -171,8 +188,9 @@ __global__ __launch_bounds__(NT_FORCE) void k_ion_grad_det(DevCtx c, double *par
       }
     }
     __syncthreads();
-    force_stage<T>(BL, c.B.gatom, sg.x, sg.y, fb, pts, npts, Ys, fbin);
+    force_stage<T>(BL, c.B.gatom, sg.x, sg.y, fb, pts, npts, Ys, slot, satom);
     __syncthreads();
+    bin_slots(4 * (sg.y - sg.x), slot, satom, fbin, c.n_atom);
   }
   double *out = partial + ((size_t)w * ntile + tile) * c.n_atom * 3;
   for (int i = tid; i < c.n_atom * 3; i += NT_FORCE) out[i] = fbin[i];

@@ -225,8 +225,10 @@ __device__ __forceinline__ void cart_poly_h(R x, R y, R z, R &P, R (&Pg)[3], R (
 // One stage of the determinant adjoint: for the tile's points n (lane % 32)
 // and the stage's shells, q_n^x = sum over the shell's functions of
 //   y1 (d_x lap Phi + 2 c_n . H_x Phi) - y2 d_x Phi,
-// reduced over the 32 points into per-atom bins (pbin, FP64 atomics) and
-// accumulated per point (sbin).  Radial part R(s^2) with derivatives R1..R3:
+// reduced over the 32 points into the shell's slot total (slot, satom;
+// binned by atom with bin_slots after a barrier) and accumulated per point in
+// the thread's own registers (sacc: each thread serves one point), so no sum
+// depends on how the waves were scheduled.  Radial part R(s^2) with derivatives R1..R3:
 //   d_a Phi = P_a R + 2 d_a P R1,
 //   d_ab Phi = P_ab R + 2 (P_a d_b + P_b d_a) R1 + 2 delta_ab P R1 + 4 d_a d_b P R2,
 //   d_c lap Phi = 2 lapP d_c R1 + 4 R1 (H_P d)_c + 4 P_c R1 + 8 d_c R2 (grad P . d)
@@ -234,7 +236,8 @@ __device__ __forceinline__ void cart_poly_h(R x, R y, R z, R &P, R (&Pg)[3], R (
 template <typename T, int L, int NPR>
 __device__ void zv_stage_t(const BasisLDS &B, const int *gatom, int g_begin, int g_end,
                            int fn_begin, const double (*pts)[3], const double (*cj)[3], int npts,
-                           const T *Ys, double *pbin, double *sbin, int npr_rt = NPR) {
+                           const T *Ys, double *slot, int *satom, double (&sacc)[3],
+                           int npr_rt = NPR) {
   constexpr int NC = L == 0 ? 1 : (L == 1 ? 3 : 6);
   const int nsh = 4 * (g_end - g_begin);
   const int tid = threadIdx.x;
@@ -315,18 +318,18 @@ __device__ void zv_stage_t(const BasisLDS &B, const int *gatom, int g_begin, int
         for (int x = 0; x < 3; ++x)
           f[x] += y1 * (double)(gl[x] + (T)2 * hc[x]) - y2 * (double)gr[x];
       }
-      atomicAdd(&sbin[n * 3 + 0], f[0]);
-      atomicAdd(&sbin[n * 3 + 1], f[1]);
-      atomicAdd(&sbin[n * 3 + 2], f[2]);
+      sacc[0] += f[0];
+      sacc[1] += f[1];
+      sacc[2] += f[2];
     }
     f[0] = sum32(f[0]);
     f[1] = sum32(f[1]);
     f[2] = sum32(f[2]);
-    const int atom = gatom[g * 4 + s];
-    if (n == 0 && atom >= 0) {
-      atomicAdd(&pbin[atom * 3 + 0], f[0]);
-      atomicAdd(&pbin[atom * 3 + 1], f[1]);
-      atomicAdd(&pbin[atom * 3 + 2], f[2]);
+    if (n == 0) {
+      slot[sl * 3 + 0] = f[0];
+      slot[sl * 3 + 1] = f[1];
+      slot[sl * 3 + 2] = f[2];
+      satom[sl] = gatom[g * 4 + s];
     }
   }
 }
@@ -334,19 +337,20 @@ __device__ void zv_stage_t(const BasisLDS &B, const int *gatom, int g_begin, int
 template <typename T>
 __device__ inline void zv_stage(const BasisLDS &B, const int *gatom, int g_begin, int g_end,
                                 int fn_begin, const double (*pts)[3], const double (*cj)[3],
-                                int npts, const T *Ys, double *pbin, double *sbin) {
+                                int npts, const T *Ys, double *slot, int *satom,
+                                double (&sacc)[3]) {
   const int4 gi = B.ginfo[g_begin];
 #define DMCX_ZV_CASE(LL, NN)                                                                 \
   case LL * 16 + NN:                                                                         \
-    zv_stage_t<T, LL, NN>(B, gatom, g_begin, g_end, fn_begin, pts, cj, npts, Ys, pbin, sbin); \
+    zv_stage_t<T, LL, NN>(B, gatom, g_begin, g_end, fn_begin, pts, cj, npts, Ys, slot, satom, sacc); \
     break;
   switch (gi.x * 16 + (gi.y <= 4 ? gi.y : 0)) {
     DMCX_ZV_CASE(0, 1) DMCX_ZV_CASE(0, 2) DMCX_ZV_CASE(0, 3) DMCX_ZV_CASE(0, 4)
     DMCX_ZV_CASE(1, 1) DMCX_ZV_CASE(1, 2) DMCX_ZV_CASE(1, 3) DMCX_ZV_CASE(1, 4)
     DMCX_ZV_CASE(2, 1) DMCX_ZV_CASE(2, 2) DMCX_ZV_CASE(2, 3) DMCX_ZV_CASE(2, 4)
-    case 0: zv_stage_t<T, 0, 0>(B, gatom, g_begin, g_end, fn_begin, pts, cj, npts, Ys, pbin, sbin, gi.y); break;
-    case 16: zv_stage_t<T, 1, 0>(B, gatom, g_begin, g_end, fn_begin, pts, cj, npts, Ys, pbin, sbin, gi.y); break;
-    case 32: zv_stage_t<T, 2, 0>(B, gatom, g_begin, g_end, fn_begin, pts, cj, npts, Ys, pbin, sbin, gi.y); break;
+    case 0: zv_stage_t<T, 0, 0>(B, gatom, g_begin, g_end, fn_begin, pts, cj, npts, Ys, slot, satom, sacc, gi.y); break;
+    case 16: zv_stage_t<T, 1, 0>(B, gatom, g_begin, g_end, fn_begin, pts, cj, npts, Ys, slot, satom, sacc, gi.y); break;
+    case 32: zv_stage_t<T, 2, 0>(B, gatom, g_begin, g_end, fn_begin, pts, cj, npts, Ys, slot, satom, sacc, gi.y); break;
     default: break;
   }
 #undef DMCX_ZV_CASE
@@ -368,7 +372,9 @@ __global__ __launch_bounds__(NT_FORCE) void k_zv_det(DevCtx c, const T *xt, cons
   __shared__ T Gp[NP * NC2];   // B operand: Gp[k][n] = g_n[k], Gp[k][FPTS + n] = x_n[k]
   __shared__ T Ys[FM * NC2];
   __shared__ double pbin[MAX_ATOM * 3];
-  __shared__ double sbin[FPTS * 3];
+  __shared__ double slot[FM * 3];  // shell totals of the current stage
+  __shared__ int satom[FM];
+  __shared__ double sred[NT_FORCE / 32][FPTS * 3];  // per-point sums of each half-wave
   __shared__ double pts[FPTS][3];
   __shared__ double cj[FPTS][3];
   const int ntile = (c.ne + FPTS - 1) / FPTS;
@@ -394,8 +400,8 @@ __global__ __launch_bounds__(NT_FORCE) void k_zv_det(DevCtx c, const T *xt, cons
     const int e = e0 + min(n, npts - 1);
     pts[n][x] = c.R[((size_t)w * c.ne + e) * 3 + x];
     cj[n][x] = cg[((size_t)w * c.ne + e) * 6 + x];
-    sbin[tid] = 0.0;
   }
+  double sacc[3] = {0.0, 0.0, 0.0};  // point tid % 32, shells of half-wave tid / 32
   __syncthreads();
   for (int st = 0; st < c.B.n_stage; ++st) {
     const int2 sg = BL.stages[st];
@@ -418,12 +424,21 @@ __global__ __launch_bounds__(NT_FORCE) void k_zv_det(DevCtx c, const T *xt, cons
       }
     }
     __syncthreads();
-    zv_stage<T>(BL, c.B.gatom, sg.x, sg.y, fb, pts, cj, npts, Ys, pbin, sbin);
+    zv_stage<T>(BL, c.B.gatom, sg.x, sg.y, fb, pts, cj, npts, Ys, slot, satom, sacc);
     __syncthreads();
+    bin_slots(4 * (sg.y - sg.x), slot, satom, pbin, c.n_atom);
   }
   double *out = zpart + ((size_t)w * ntile + tile) * c.n_atom * 3;
   for (int i = tid; i < c.n_atom * 3; i += NT_FORCE) out[i] = pbin[i];
-  for (int i = tid; i < npts * 3; i += NT_FORCE) zs[((size_t)w * c.ne + e0) * 3 + i] = sbin[i];
+  // per-point sums: the half-waves' partial sums added in half-wave order
+  for (int x = 0; x < 3; ++x) sred[tid >> 5][(tid & 31) * 3 + x] = sacc[x];
+  __syncthreads();
+  for (int i = tid; i < npts * 3; i += NT_FORCE) {
+    double v = 0.0;
+#pragma unroll
+    for (int h = 0; h < NT_FORCE / 32; ++h) v += sred[h][i];
+    zs[((size_t)w * c.ne + e0) * 3 + i] = v;
+  }
 }
 
 }  // namespace dmcx
