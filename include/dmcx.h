@@ -293,6 +293,38 @@ dmcx_status dmcx_forces_zv(dmcx_ctx *ctx, int32_t warp, double *F, dmcx_mem mem)
 #define DMCX_N_ESTIMATORS 11
 dmcx_status dmcx_estimators(dmcx_ctx *ctx, double *out, dmcx_mem mem);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * estimators of dmcx_estimators over plain per-walker device arrays, with no
+ * context and no allocation.  The block records of the first pass live in a
+ * scratch array of the library's own, one per GPU for the life of the
+ * process, sized for at most DMCX_NOALLOC_MAX_WALKERS walkers (4096 records
+ * of 80 bytes, 320 KiB); its device address is looked up once per device,
+ * on the first call with that device current.
+ *   n_walkers   0..DMCX_NOALLOC_MAX_WALKERS; more is DMCX_E_INVALID.
+ *   log_w       [n_walkers] FP64 log-weights, device memory.
+ *   e_local     [n_walkers] FP64 local energies, device memory.
+ *   flags       [n_walkers] status bytes as written by dmcx_walker_flags, or
+ *               NULL; a walker with a nonzero byte is not counted.
+ *   n_accepted, n_proposed
+ *               [n_walkers] move counters (uint32), both or neither (NULL:
+ *               out[9] is NaN and out[10] is 0); read and cleared.
+ *   out         [11] doubles in device memory, laid out as one system's
+ *               record of dmcx_estimators.
+ *   hip_stream  the stream (of the current device) the two kernels are
+ *               enqueued on; nothing synchronises.
+ * Inputs and outputs are borrowed until that work completes.  Every call on
+ * one GPU shares the one scratch array, so calls that overlap on a GPU (on
+ * different streams or host threads) race and must be ordered by the caller.
+ * Every record the second pass reads is written by the first pass of the
+ * same call, so nothing needs clearing between calls.  Errors:
+ * DMCX_E_INVALID (sizes, null pointers), DMCX_E_HIP (launch or symbol
+ * lookup); dmcx_last_error(NULL) gives the text. */
+#define DMCX_NOALLOC_MAX_WALKERS 1048576
+dmcx_status dmcx_estimators_noalloc(int32_t n_walkers, const double *log_w, const double *e_local,
+                                    const uint8_t *flags, uint32_t *n_accepted,
+                                    uint32_t *n_proposed, double *out, void *hip_stream);
+
 /* Per-walker status bits [W]: 1 = non-finite value, 2 = singular matrix
  * (a zero pivot of A of Eq. 3 in the FP64 recompute).  Bits stay set until
  * the next dmcx_set_walkers. */
@@ -343,6 +375,8 @@ dmcx_status dmcx_selftest(void *hip_stream);
 dmcx_status dmcx_philox(const uint32_t *ctr, const uint32_t *key, int32_t n, uint32_t *out);
 
 const char *dmcx_strerror(dmcx_status s);
+/* Text of the context's last error; with ctx == NULL, of this thread's last
+ * context-free call. */
 const char *dmcx_last_error(const dmcx_ctx *ctx);
 
 #ifdef __cplusplus

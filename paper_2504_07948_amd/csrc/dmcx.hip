@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -23,6 +24,9 @@ using namespace dmcx;
 namespace {
 
 const int NCART_[3] = {1, 3, 6};
+
+// Text of the last error of a context-free call (dmcx_last_error(NULL)).
+thread_local std::string g_free_err;
 
 struct DeviceBuffers {
   std::vector<void *> ptrs;
@@ -641,7 +645,7 @@ const char *dmcx_strerror(dmcx_status s) {
   return "unknown status";
 }
 
-const char *dmcx_last_error(const dmcx_ctx *c) { return c ? c->err.c_str() : ""; }
+const char *dmcx_last_error(const dmcx_ctx *c) { return c ? c->err.c_str() : g_free_err.c_str(); }
 
 }  // extern "C"
 
@@ -1781,12 +1785,87 @@ dmcx_status dmcx_estimators(dmcx_ctx *c, double *out, dmcx_mem mem) {
   dmcx_status st = refresh_after_moves(c);
   if (st) return st;
   const int nblk = est_blocks(c->W);
-  hipLaunchKernelGGL(k_est_partial, dim3(nblk), dim3(EST_NB), 0, c->stream, c->dc, c->d_est_part);
+  hipLaunchKernelGGL(k_est_partial<unsigned>, dim3(nblk), dim3(EST_NB), 0, c->stream, est_in(c->dc),
+                     c->d_est_part);
   HIP_TRY(c, hipGetLastError());
   double *dst = mem == DMCX_DEVICE ? out : c->d_est_out;
   hipLaunchKernelGGL(k_est_final, dim3(1), dim3(64), 0, c->stream, nblk, c->d_est_part, dst);
   HIP_TRY(c, hipGetLastError());
   if (mem == DMCX_HOST) return copy_out(c, out, c->d_est_out, EST_OUT * sizeof(double), mem);
+  return DMCX_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------ allocation-free estimators ----
+// Block records of dmcx_estimators_noalloc's first pass, for up to
+// DMCX_NOALLOC_MAX_WALKERS walkers.  Each GPU holds its own copy for the life
+// of the process.  In host code this name is only a stand-in for the device
+// copy: kernels and copies take the address that hipGetSymbolAddress returns
+// for the current device (scratch_ptr below), never the name itself.
+constexpr int NOALLOC_BLOCKS = (DMCX_NOALLOC_MAX_WALKERS + EST_NB - 1) / EST_NB;
+static __device__ __align__(256) double scratch[(size_t)NOALLOC_BLOCKS * EST_PART];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[SCRATCH_MAX_DEVICES] = {};  // device address of scratch, per GPU
+
+dmcx_status free_fail(dmcx_status st, const std::string &msg) {
+  g_free_err = msg;
+  return st;
+}
+
+// Device address of scratch on the current device, looked up once per device
+// (with that device current) and kept.
+dmcx_status scratch_ptr(double **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0)
+    return free_fail(DMCX_E_HIP, "hipGetDevice failed");
+  if (dev >= SCRATCH_MAX_DEVICES) return free_fail(DMCX_E_UNSUPPORTED, "device ordinal above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return free_fail(DMCX_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = (double *)p;
+  }
+  *out = g_scratch_dev[dev];
+  return DMCX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dmcx_status dmcx_estimators_noalloc(int32_t n_walkers, const double *log_w, const double *e_local,
+                                    const uint8_t *flags, uint32_t *n_accepted,
+                                    uint32_t *n_proposed, double *out, void *hip_stream) {
+  if (n_walkers < 0 || n_walkers > DMCX_NOALLOC_MAX_WALKERS)
+    return free_fail(DMCX_E_INVALID, "dmcx_estimators_noalloc: n_walkers " +
+                                         std::to_string(n_walkers) + " outside [0, " +
+                                         std::to_string(DMCX_NOALLOC_MAX_WALKERS) + "]");
+  if (!out || (n_walkers > 0 && (!log_w || !e_local)))
+    return free_fail(DMCX_E_INVALID, "dmcx_estimators_noalloc: null log_w, e_local or out");
+  if ((n_accepted == nullptr) != (n_proposed == nullptr))
+    return free_fail(DMCX_E_INVALID,
+                     "dmcx_estimators_noalloc: n_accepted and n_proposed go together");
+  double *part = nullptr;
+  dmcx_status st = scratch_ptr(&part);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int nblk = est_blocks(n_walkers);
+  if (nblk > 0) {
+    const EstIn<uint8_t> in{n_walkers, log_w, e_local, flags, n_accepted, n_proposed};
+    hipLaunchKernelGGL(k_est_partial<uint8_t>, dim3(nblk), dim3(EST_NB), 0, s, in, part);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return free_fail(DMCX_E_HIP, hipGetErrorString(e));
+  }
+  hipLaunchKernelGGL(k_est_final, dim3(1), dim3(64), 0, s, nblk, part, out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return free_fail(DMCX_E_HIP, hipGetErrorString(e));
   return DMCX_OK;
 }
 

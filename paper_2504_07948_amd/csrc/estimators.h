@@ -49,23 +49,38 @@ __device__ __forceinline__ double block_reduce(double v, double *red) {
   return r;
 }
 
+// Inputs of the first pass: one system's per-walker arrays (device
+// pointers).  F is the element type of the status flags (the context's own
+// flags are 32-bit; an array from dmcx_walker_flags is 8-bit).  flags may be
+// null (no walker flagged); nacc and nprop are both given or both null (no
+// move counters: nothing accepted, nothing proposed).
+template <typename F>
+struct EstIn {
+  int W;
+  const double *logw, *eloc;
+  const F *flags;
+  unsigned *nacc, *nprop;
+};
+
 // Record of block b: {m_b, S0, S1, S2, Q, M2, n, min log w, accepted, proposed}
 // with S0 = sum omega, S1 = sum omega E, S2 = sum omega E^2, Q = sum omega^2,
 // M2 = sum omega (E - S1/S0)^2, omega = exp(log w - m_b).
-__global__ __launch_bounds__(EST_NB) void k_est_partial(DevCtx c, double *part) {
+template <typename F>
+__global__ __launch_bounds__(EST_NB) void k_est_partial(EstIn<F> in, double *part) {
   __shared__ double red[EST_NB / 64];
   const int w = blockIdx.x * EST_NB + threadIdx.x;
-  const bool real = w < c.W;
-  const double lw_in = real ? c.logw[w] : 0.0, e_in = real ? c.eloc[w] : 0.0;
-  const bool ok = real && c.flags[w] == 0u && isfinite(lw_in) && isfinite(e_in);
+  const bool real = w < in.W;
+  const double lw_in = real ? in.logw[w] : 0.0, e_in = real ? in.eloc[w] : 0.0;
+  const bool clear = !real || !in.flags || in.flags[w] == (F)0;
+  const bool ok = real && clear && isfinite(lw_in) && isfinite(e_in);
   // excluded walkers enter every sum as exact zeros (0 * NaN would not be)
   const double lw = ok ? lw_in : 0.0, e = ok ? e_in : 0.0;
   double na = 0.0, np = 0.0;
-  if (real) {
-    na = (double)c.nacc[w];
-    np = (double)c.nprop[w];
-    c.nacc[w] = 0u;
-    c.nprop[w] = 0u;
+  if (real && in.nacc) {
+    na = (double)in.nacc[w];
+    np = (double)in.nprop[w];
+    in.nacc[w] = 0u;
+    in.nprop[w] = 0u;
   }
   const double mb = block_reduce<1>(ok ? lw : -INFINITY, red);
   const double lmin = block_reduce<2>(ok ? lw : INFINITY, red);
@@ -138,5 +153,10 @@ __global__ void k_est_final(int nblk, const double *part, double *out) {
 }
 
 inline int est_blocks(int W) { return (W + EST_NB - 1) / EST_NB; }
+
+// The first-pass inputs of a context: its own walker arrays and counters.
+inline EstIn<unsigned> est_in(const DevCtx &c) {
+  return EstIn<unsigned>{c.W, c.logw, c.eloc, c.flags, c.nacc, c.nprop};
+}
 
 }  // namespace dmcx

@@ -24,6 +24,7 @@ DMCX_VMC, DMCX_DMC = 0, 1
 DMCX_HOST, DMCX_DEVICE = 0, 1
 DMCX_FLAG_GRAPH = 1
 DMCX_N_ESTIMATORS = 11
+DMCX_NOALLOC_MAX_WALKERS = 1048576
 
 EXPORTED = [
     "dmcx_create", "dmcx_destroy", "dmcx_set_walkers", "dmcx_get_walkers", "dmcx_set_step",
@@ -32,7 +33,7 @@ EXPORTED = [
     "dmcx_potential_vjp", "dmcx_forces", "dmcx_potential", "dmcx_walker_flags", "dmcx_sync", "dmcx_last_run_timing",
     "dmcx_selftest", "dmcx_philox", "dmcx_strerror", "dmcx_last_error", "dmcx_autotune",
     "dmcx_autotune_report", "dmcx_get_delay_rank", "dmcx_reconfigure", "dmcx_estimators",
-    "dmcx_zv_grads", "dmcx_forces_zv",
+    "dmcx_zv_grads", "dmcx_forces_zv", "dmcx_estimators_noalloc",
 ]
 
 
@@ -110,6 +111,7 @@ def load():
         "dmcx_estimators": [P, P, I32],
         "dmcx_zv_grads": [P, I32, P, P, P, I32],
         "dmcx_forces_zv": [P, I32, P, I32],
+        "dmcx_estimators_noalloc": [I32, P, P, P, P, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -225,6 +227,12 @@ def dmcx_forces_zv(ctx, warp, F, mem):
 
 def dmcx_estimators(ctx, out, mem):
     return load().dmcx_estimators(ctx, out, mem)
+
+
+def dmcx_estimators_noalloc(n_walkers, log_w, e_local, flags, n_accepted, n_proposed, out,
+                            hip_stream):
+    return load().dmcx_estimators_noalloc(n_walkers, log_w, e_local, flags, n_accepted,
+                                          n_proposed, out, hip_stream)
 
 
 def dmcx_potential(ctx, v, mem):
