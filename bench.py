@@ -54,6 +54,30 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
+def host_cpu_info():
+    """Sockets, physical cores and logical CPUs of the host, and the CPUs this
+    process may run on."""
+    info = {"logical_cpus": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0))}
+    try:
+        phys, cores = set(), set()
+        pid = cid = None
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("physical id"):
+                    pid = line.split(":")[1].strip()
+                    phys.add(pid)
+                elif line.startswith("core id"):
+                    cid = line.split(":")[1].strip()
+                    cores.add((pid, cid))
+                elif line.startswith("model name") and "model" not in info:
+                    info["model"] = line.split(":", 1)[1].strip()
+        info["sockets"] = len(phys) or None
+        info["physical_cores"] = len(cores) or None
+    except OSError:
+        pass
+    return info
+
+
 def flops_per_move(n_basis, n_prim, n_sigma, n_elec, n_atom, k):
     """Algorithmic FLOP per proposed single-electron move:
     MO VGL contraction 2*5*N_b*N_s, basis assembly ~20*N_b plus one per
@@ -65,15 +89,12 @@ def flops_per_move(n_basis, n_prim, n_sigma, n_elec, n_atom, k):
             + 40 * (n_elec + n_atom))
 
 
-def mixed_leg(s, torch, dmcx, stream, args, W=4096, steps=10, P=32, k=32):
-    """Mixed precision on the same system: 4096 walkers, FP64 LU recompute every
-    32 steps.  Reports moves/s, the speedup over FP64 per move, and the local
-    energy error per electron at identical configurations, taking the FP64 GPU
-    path (held to the oracle within 1e-10 by the tests) as the reference."""
+def _timed_ctx(s, torch, dmcx, stream, W, steps, seed, **kw):
+    """Context on W walkers of s, one warm-up step, then `steps` timed steps;
+    returns (ctx, ms per step, sweep kernel ms)."""
     from paper_2504_07948_amd import synth
     R0 = synth.make_walkers(s, W, 2026)
-    ctx = dmcx.Context(s, W, precision=dmcx.DMCX_MIXED, delay_rank=k, recompute_period=P,
-                       tau=0.01, seed=19, stream=stream)
+    ctx = dmcx.Context(s, W, tau=0.01, seed=seed, stream=stream, **kw)
     ctx.set_walkers(torch.from_numpy(R0).cuda())
     e0, _, _ = ctx.measure()
     e_t = float(np.mean(e0[np.isfinite(e0)]))
@@ -84,30 +105,63 @@ def mixed_leg(s, torch, dmcx, stream, args, W=4096, steps=10, P=32, k=32):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_sweep, _, _ = ctx.last_run_timing()
+    return ctx, dt * 1e3 / steps, ms_sweep
+
+
+def _energy_errors(s, torch, dmcx, stream, ctx, W):
+    """E_L and log|Psi| of ctx against the FP64 GPU path (held to the oracle
+    within 1e-10 by the tests) at ctx's own configurations."""
     Rm, _ = ctx.get_walkers()
     em, lpm, _ = ctx.measure()
     ref = dmcx.Context(s, W, precision=dmcx.DMCX_FP64, stream=stream)
     ref.set_walkers(torch.from_numpy(Rm).cuda())
     ef, lpf, _ = ref.measure()
+    ref.close()
     ok = np.isfinite(em) & np.isfinite(ef)
     de = (em - ef)[ok]
     dl = (lpm - lpf)[ok]
-    # near-node walkers (A nearly singular) carry errors ~ cond(A) x FP32 epsilon
-    # and dominate the plain mean; the trimmed mean drops the 1% of walkers whose
-    # FP64 E_L lies farthest from the median, identically for both precisions
-    efk = ef[ok]
-    keep = np.abs(efk - np.median(efk)) <= np.quantile(np.abs(efk - np.median(efk)), 0.99)
-    rate = W * s.n_elec * steps / dt
-    return {"walkers": W, "steps": steps, "recompute_period": P, "delay_rank": k,
-            "value": rate, "unit": "electron-moves/s", "sweep_ms_avg": ms_sweep,
-            "e_err_per_electron_mean": float(abs(de.mean()) / s.n_elec),
-            "e_err_per_electron_mean_trimmed_1pct": float(abs(de[keep].mean()) / s.n_elec),
+    return {"e_err_per_electron_mean": float(abs(de.mean()) / s.n_elec),
             "e_err_per_electron_median_walker": float(np.median(np.abs(de)) / s.n_elec),
             "e_err_per_electron_rms_walker": float(np.sqrt(np.mean(de ** 2)) / s.n_elec),
             "e_err_per_electron_max_walker": float(np.abs(de).max() / s.n_elec),
             "logpsi_err_median": float(np.median(np.abs(dl))),
-            "logpsi_err_max": float(np.abs(dl).max()),
-            "reference": "FP64 GPU path at the mixed run's final configurations"}
+            "logpsi_err_max": float(np.abs(dl).max())}
+
+
+def mixed_leg(s, torch, dmcx, stream, args, W=4096, steps=10, P=32, k=32):
+    """Mixed precision on the same system at 4096 walkers against FP64 at the
+    same 4096 walkers.  Two forms: the default (FP32 sweep, FP64 value rows,
+    inverse and E_L at the end of every step) and the FP32-energy variant
+    (E_L from the FP32 rows and inverse, FP64 recompute every 32 steps).
+    Reports moves/s and ms per step of each, the speedup over FP64 at equal
+    walker count, the FP32 sweep kernel's fraction of the FP32 peak, and the
+    energy error per electron at identical configurations."""
+    from paper_2504_07948_amd import synth  # noqa: F401
+    ne, ns = s.n_elec, max(s.n_up, s.n_dn)
+    fpm = flops_per_move(s.n_basis, len(s.prim_alpha), ns, ne, s.n_atom, k)
+    c64, ms64, sw64 = _timed_ctx(s, torch, dmcx, stream, W, steps, 19, precision=dmcx.DMCX_FP64,
+                                 delay_rank=k, recompute_period=64)
+    c64.close()
+    out = {"walkers": W, "steps": steps, "delay_rank": k, "unit": "electron-moves/s",
+           "fp64_same_walkers": {"ms_per_step": ms64, "value": W * ne / (ms64 * 1e-3),
+                                 "sweep_ms_avg": sw64, "recompute_period": 64}}
+    for name, fp32e in (("fp64_energy", False), ("fp32_energy", True)):
+        ctx, ms, sw = _timed_ctx(s, torch, dmcx, stream, W, steps, 19, precision=dmcx.DMCX_MIXED,
+                                 delay_rank=k, recompute_period=P, fp32_energy=fp32e)
+        n_esc = ctx.energy_escalations()
+        ach = fpm * W * ne / (sw * 1e-3) / 1e12
+        rec = {"ms_per_step": ms, "value": W * ne / (ms * 1e-3), "speedup_vs_fp64_same_walkers":
+               ms64 / ms, "sweep_ms_avg": sw,
+               "sweep_roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS},
+               "recompute_period": 1 if not fp32e else P,
+               "walkers_with_fp64_derivative_rows_last_step": n_esc}
+        rec.update(_energy_errors(s, torch, dmcx, stream, ctx, W))
+        ctx.close()
+        out[name] = rec
+    out["value"] = out["fp64_energy"]["value"]
+    out["reference"] = "FP64 GPU path at each mixed run's final configurations"
+    return out
 
 
 def batch5_leg(torch, dmcx, stream, steps=5, W=512, n_det=1000, n_active=100, P=32):
@@ -301,6 +355,17 @@ def main():
     dt = time.perf_counter() - t0
     sweep_ms, n_launch, sweep_total = ctx.last_run_timing()
     flags = ctx.walker_flags()
+    # A window shorter than the recompute period holds no FP64 recompute; time
+    # one whole period as well (aligned so that it starts with the recompute).
+    step_now = ctx.get_step()
+    align = (-step_now) % args.recompute
+    if align:
+        ctx.run_device(align, mode=dmcx.DMCX_DMC, e_trial=e_t)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    ctx.run_device(args.recompute, mode=dmcx.DMCX_DMC, e_trial=e_t)
+    torch.cuda.synchronize()
+    dt_period = time.perf_counter() - tp0
 
     mixed = forces = batch5 = population = None
     extras = set() if args.skip_extras else set(args.extras.split(",")) - {"none", ""}
@@ -336,7 +401,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        n_threads = min(16, os.cpu_count() or 1)
+        host = host_cpu_info()
+        n_threads = min(16, host["affinity_cpus"])
         # pilot: one step of n_threads walkers, then size the sample to ~cpu-seconds
         pilot = R0[:n_threads]
         tp = time.perf_counter()
@@ -349,10 +415,18 @@ def main():
         oracle.run(s, R0[:w_sample], n_steps=1, mode=1, tau=0.01, seed=17, e_trial=e_t,
                    want_logs=False, n_threads=n_threads)
         tcpu = time.perf_counter() - tc
+        # one thread: one DMC step of two walkers
+        t1 = time.perf_counter()
+        oracle.run(s, R0[:2], n_steps=1, mode=1, tau=0.01, seed=17, e_trial=e_t,
+                   want_logs=False, n_threads=1)
+        t1 = time.perf_counter() - t1
         cpu = {"value": w_sample * ne / tcpu, "unit": "electron-moves/s", "cores": n_threads,
                "kind": "oracle",
                "sample": f"1 DMC step of the first {w_sample} of {W} walkers "
-                         f"({w_sample * ne} moves, {tcpu:.1f} s, FP64, k=1 with fresh LU)"}
+                         f"({w_sample * ne} moves, {tcpu:.1f} s, FP64, k=1 with fresh LU)",
+               "one_thread_value": 2 * ne / t1,
+               "one_thread_sample": f"1 DMC step of 2 walkers ({2 * ne} moves, {t1:.1f} s)",
+               "host": host}
 
     out = {
         "metric": "electron-moves/s, FP64 vs mixed at stated error; forces-vs-energy cost ratio",
@@ -362,6 +436,10 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": dt * 1e3 / args.steps,
+        "full_recompute_period": {"steps": args.recompute, "ms_per_step":
+                                  dt_period * 1e3 / args.recompute,
+                                  "value": W * ne * args.recompute / dt_period,
+                                  "note": "one FP64 recompute (every P steps) inside the window"},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

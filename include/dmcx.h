@@ -54,6 +54,16 @@ typedef enum {
   DMCX_E_UNSUPPORTED = 7  /* valid request this build does not implement */
 } dmcx_status;
 
+/* DMCX_FP64: every step in FP64.
+ * DMCX_MIXED: the sweep (basis, orbital GEMM, ratios, delayed updates) runs
+ * in FP32 on MFMA with FP32 accumulation; at the end of every step the value
+ * rows of A are evaluated again in FP64 (FP64 basis and MFMA GEMM), inverted
+ * in FP64 (which also resets the FP32 inverse and log|D|), and E_L is taken
+ * from that FP64 inverse with the FP32 derivative rows, so the energy error
+ * does not grow with cond(A); the recompute period then has no effect.  With
+ * DMCX_FLAG_FP32_ENERGY, or with a multideterminant expansion, E_L comes from
+ * the FP32 rows and inverse, and the FP64 recompute runs every
+ * recompute_period steps. */
 typedef enum { DMCX_FP64 = 0, DMCX_MIXED = 1 } dmcx_precision;
 typedef enum { DMCX_VMC = 0, DMCX_DMC = 1 } dmcx_mode;
 typedef enum { DMCX_HOST = 0, DMCX_DEVICE = 1 } dmcx_mem;
@@ -87,6 +97,10 @@ typedef struct {
 
 /* dmcx_options.flags */
 #define DMCX_FLAG_GRAPH 1u  /* dmcx_run replays one captured step graph per step */
+/* Mixed form only: take E_L, log|Psi| and the weights from the FP32 orbital
+ * rows and the FP32 inverse, with the FP64 recompute every recompute_period
+ * steps (faster; its energy error grows with cond(A), see DMCX_MIXED). */
+#define DMCX_FLAG_FP32_ENERGY 2u
 
 typedef struct {
   int32_t precision;         /* dmcx_precision */
@@ -324,6 +338,15 @@ dmcx_status dmcx_estimators(dmcx_ctx *ctx, double *out, dmcx_mem mem);
 dmcx_status dmcx_estimators_noalloc(int32_t n_walkers, const double *log_w, const double *e_local,
                                     const uint8_t *flags, uint32_t *n_accepted,
                                     uint32_t *n_proposed, double *out, void *hip_stream);
+
+/* Mixed form (DMCX_MIXED without DMCX_FLAG_FP32_ENERGY): the number of
+ * walkers whose E_L the last energy evaluation (step end, measure or
+ * recompute) recomputed from FP64 derivative rows because their first-order
+ * error bound from the FP32 rows, (u / 2) sum_ij (|lap phi_j(r_i)| +
+ * 2 |grad_i J|_1 |grad phi_j(r_i)|_1) |(A^{-1})_ji| with u = 2^-24, exceeded
+ * 1e-4 Ha per electron (Eq. 2 trial function, E_L of Eq. 3 form).  0 for the
+ * other forms.  Synchronises the context's stream. */
+dmcx_status dmcx_energy_escalations(dmcx_ctx *ctx, int32_t *n);
 
 /* Per-walker status bits [W]: 1 = non-finite value, 2 = singular matrix
  * (a zero pivot of A of Eq. 3 in the FP64 recompute).  Bits stay set until

@@ -25,6 +25,14 @@ namespace {
 
 const int NCART_[3] = {1, 3, 6};
 
+// Mixed form: a walker whose first-order energy error bound from its FP32
+// derivative rows exceeds this (Ha per electron) has its E_L recomputed from
+// FP64 rows.  The bound takes every derivative-row entry to carry the FP32
+// unit roundoff and weights the gradient rows by 2 |grad J|_1, so it runs a
+// few times above the errors measured on the large synthetic molecule; this
+// cap sends about one walker in a hundred there to FP64 rows.
+constexpr double ESC_CAP = 1e-4;
+
 // Text of the last error of a context-free call (dmcx_last_error(NULL)).
 thread_local std::string g_free_err;
 
@@ -43,6 +51,14 @@ struct dmcx_ctx {
   int W = 0, Wpad = 0, ne = 0, n_up = 0, n_dn = 0, n_atom = 0, NP = 0, NOB = 0, K = 1, P = 1;
   int n_basis = 0;
   bool mixed = false;  // FP32 working precision (mixed path)
+  // mixed form with its energy in FP64: every step ends with FP64 value rows,
+  // an FP64 inverse and E_L from that inverse (single-determinant systems)
+  bool fp64e = false;
+  double *d_A64 = nullptr;  // [Wpad][ne][NP] FP64 orbital values (fp64e)
+  double *d_G64 = nullptr;  // [Wpad][2][NP][NP] FP64 inverses, GT layout (fp64e)
+  // walkers whose energy is re-evaluated with FP64 derivative rows (fp64e)
+  int *d_esc_count = nullptr, *d_esc_list = nullptr;
+  double *d_esc_gl = nullptr;  // [Wpad][ne][4]
   size_t es = 8;       // bytes per working-precision element
   int64_t step = 0;
   bool walkers_set = false;
@@ -385,29 +401,73 @@ dmcx_status launch_msd_rebuild(dmcx_ctx *c, int periodic = 0) {
   return hip_check(c, hipGetLastError(), "multideterminant table launch");
 }
 
+// FP64 inverse of the Slater matrices.  The mixed form with its FP64 energy
+// inverts the FP64 value rows of k_values64 (and keeps an FP64 copy of the
+// inverses for E_L); otherwise the cached working-precision value rows.  One
+// wave per matrix where the rows fit a wave (NP <= 64), else one workgroup.
 // periodic != 0: the kernel itself skips steps that are not multiples of P
 dmcx_status launch_inverse(dmcx_ctx *c, int periodic = 0) {
   const int n = std::max(c->n_up, c->n_dn);
   const size_t lds = (size_t)n * n * sizeof(double);
-  if (c->mixed)
-    hipLaunchKernelGGL(k_inverse<float>, dim3(c->Wpad, 2), dim3(NT_AUX), lds, c->stream, c->dc,
-                       periodic);
+  bool done;
+  if (c->fp64e)
+    done = inverse_w<float, double>(c->dc, c->d_A64, c->NP, c->d_G64, periodic, c->stream);
+  else if (c->mixed)
+    done = inverse_w<float, float>(c->dc, (const float *)c->dc.vglc, 5 * c->NP, nullptr, periodic,
+                                   c->stream);
   else
-    hipLaunchKernelGGL(k_inverse<double>, dim3(c->Wpad, 2), dim3(NT_AUX), lds, c->stream, c->dc,
-                       periodic);
+    done = inverse_w<double, double>(c->dc, (const double *)c->dc.vglc, 5 * c->NP, nullptr,
+                                     periodic, c->stream);
+  if (done) return hip_check(c, hipGetLastError(), "k_inverse_w launch");
+  if (c->fp64e)
+    hipLaunchKernelGGL((k_inverse<float, double>), dim3(c->Wpad, 2), dim3(NT_AUX), lds, c->stream,
+                       c->dc, (const double *)c->d_A64, c->NP, c->d_G64, periodic);
+  else if (c->mixed)
+    hipLaunchKernelGGL((k_inverse<float, float>), dim3(c->Wpad, 2), dim3(NT_AUX), lds, c->stream,
+                       c->dc, (const float *)c->dc.vglc, 5 * c->NP, (double *)nullptr, periodic);
+  else
+    hipLaunchKernelGGL((k_inverse<double, double>), dim3(c->Wpad, 2), dim3(NT_AUX), lds, c->stream,
+                       c->dc, (const double *)c->dc.vglc, 5 * c->NP, (double *)nullptr, periodic);
   return hip_check(c, hipGetLastError(), "k_inverse launch");
 }
 
+// FP64 value rows of every electron (the mixed form's FP64 energy).
+dmcx_status launch_values64(dmcx_ctx *c) {
+  if (!c->fp64e) return DMCX_OK;
+  NobLaunch<float>::values64(c->NOB, c->dc, c->d_A64, basis_lds(c), c->stream);
+  return hip_check(c, hipGetLastError(), "k_values64 launch");
+}
+
+__global__ void k_esc_reset(int *count) {
+  if (threadIdx.x == 0) *count = 0;
+}
+
 // measure_only != 0: E_L, V, log|Psi| only; else the end of a step (weights,
-// e_log row s_in_run of a table with row stride elog_ss)
+// e_log row s_in_run of a table with row stride elog_ss).  The mixed form
+// with its FP64 energy lists the walkers whose FP32 derivative rows could
+// move E_L by more than ESC_CAP per electron and recomputes their E_L (and
+// weight update) from FP64 rows.
 dmcx_status launch_local_energy(dmcx_ctx *c, int measure_only, double *e_log = nullptr,
                                 long long elog_ss = 0) {
-  if (c->mixed)
-    hipLaunchKernelGGL(k_local_energy<float>, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc,
-                       measure_only, e_log, elog_ss);
-  else
+  if (!c->mixed) {
     hipLaunchKernelGGL(k_local_energy<double>, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc,
-                       measure_only, e_log, elog_ss);
+                       measure_only, e_log, elog_ss, (const double *)nullptr, EscList{});
+    return hip_check(c, hipGetLastError(), "k_local_energy launch");
+  }
+  EscList esc{};
+  if (c->fp64e) {
+    esc = EscList{1, c->d_esc_count, c->d_esc_list, c->d_esc_gl, ESC_CAP};
+    hipLaunchKernelGGL(k_esc_reset, dim3(1), dim3(64), 0, c->stream, c->d_esc_count);
+  }
+  hipLaunchKernelGGL(k_local_energy<float>, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc,
+                     measure_only, e_log, elog_ss, (const double *)c->d_G64, esc);
+  HIP_TRY(c, hipGetLastError());
+  if (!c->fp64e) return DMCX_OK;
+  NobLaunch<float>::escalate_gl(c->NOB, c->dc, c->d_G64, esc, basis_lds(c), c->stream);
+  HIP_TRY(c, hipGetLastError());
+  esc.mode = 2;
+  hipLaunchKernelGGL(k_local_energy<float>, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc,
+                     measure_only, e_log, elog_ss, (const double *)c->d_G64, esc);
   return hip_check(c, hipGetLastError(), "k_local_energy launch");
 }
 
@@ -526,6 +586,7 @@ dmcx_status refresh_after_moves(dmcx_ctx *c) {
   dmcx_status st = flush_pending(c);
   if (st) return st;
   if (c->eloc_dirty) {
+    if (c->fp64e && ((st = launch_values64(c)) || (st = launch_inverse(c)))) return st;
     if ((st = launch_local_energy(c, 1))) return st;
     c->eloc_dirty = false;
   }
@@ -885,6 +946,14 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
     if ((st = dalloc(c, &pv, es * Wp * 2 * c->NP * c->NP))) return bail(st);
     c->d_zxt = pv;
   }
+  c->fp64e = c->mixed && s.n_det <= 1 && (opt->flags & DMCX_FLAG_FP32_ENERGY) == 0;
+  if (c->fp64e) {
+    if ((st = dalloc(c, &c->d_A64, Wp * c->ne * c->NP))) return bail(st);
+    if ((st = dalloc(c, &c->d_G64, Wp * 2 * c->NP * c->NP))) return bail(st);
+    if ((st = dalloc(c, &c->d_esc_count, 1))) return bail(st);
+    if ((st = dalloc(c, &c->d_esc_list, Wp))) return bail(st);
+    if ((st = dalloc(c, &c->d_esc_gl, Wp * c->ne * 4))) return bail(st);
+  }
   if ((st = dalloc(c, &d.nacc, Wp))) return bail(st);
   if ((st = dalloc(c, &d.nprop, Wp))) return bail(st);
   if ((st = dalloc(c, &c->d_est_part, (size_t)est_blocks(c->W) * EST_PART))) return bail(st);
@@ -946,7 +1015,7 @@ dmcx_status dmcx_create(const dmcx_system *sys, int32_t n_sys, const int32_t *wa
                         const dmcx_options *opt, void *hip_stream, dmcx_ctx **out) {
   if (!out || !sys || !walkers_per_sys || !opt || n_sys < 1) return DMCX_E_INVALID;
   *out = nullptr;
-  if (!(opt->tau > 0.0) || opt->recompute_period < 1 || (opt->flags & ~DMCX_FLAG_GRAPH) != 0 ||
+  if (!(opt->tau > 0.0) || opt->recompute_period < 1 || (opt->flags & ~(DMCX_FLAG_GRAPH | DMCX_FLAG_FP32_ENERGY)) != 0 ||
       (opt->precision != DMCX_FP64 && opt->precision != DMCX_MIXED) || opt->delay_rank < 0 ||
       opt->delay_rank > KMAX) {
     fprintf(stderr, "dmcx_create: invalid options\n");
@@ -1016,6 +1085,7 @@ dmcx_status rebuild_state(dmcx_ctx *c) {
   launch_orbitals_all(c);
   HIP_TRY(c, hipGetLastError());
   dmcx_status st;
+  if ((st = launch_values64(c))) return st;
   if ((st = launch_inverse(c))) return st;
   if ((st = launch_msd_rebuild(c))) return st;
   return launch_local_energy(c, 1);
@@ -1057,7 +1127,9 @@ void set_delay_rank(dmcx_ctx *c, int k) {
 dmcx_status enqueue_step(dmcx_ctx *c, bool graph, uint8_t *acc, long long acc_ss, int acc_ws,
                          double *elog, long long elog_ss, hipEvent_t e0, hipEvent_t e1) {
   dmcx_status st;
-  if (graph) {
+  if (c->fp64e) {
+    // the FP64 recompute runs at the end of every step (below)
+  } else if (graph) {
     if ((st = launch_inverse(c, 1))) return st;
     if ((st = launch_msd_rebuild(c, 1))) return st;
   } else if (c->step % c->P == 0) {
@@ -1068,6 +1140,10 @@ dmcx_status enqueue_step(dmcx_ctx *c, bool graph, uint8_t *acc, long long acc_ss
   launch_sweep(c, acc, acc_ss, acc_ws);
   HIP_TRY(c, hipGetLastError());
   if (e1) HIP_TRY(c, hipEventRecord(e1, c->stream));
+  if (c->fp64e) {
+    if ((st = launch_values64(c))) return st;
+    if ((st = launch_inverse(c, 0))) return st;
+  }
   if ((st = launch_local_energy(c, 0, elog, elog_ss))) return st;
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->d_run);
   return hip_check(c, hipGetLastError(), "k_advance launch");
@@ -1768,6 +1844,26 @@ dmcx_status dmcx_forces_zv(dmcx_ctx *c, int32_t warp, double *F, dmcx_mem mem) {
                      c->d_zlp, c->d_zj, dst);
   HIP_TRY(c, hipGetLastError());
   if (mem == DMCX_HOST) return copy_out(c, F, c->d_red, ncomp * sizeof(double), mem);
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_energy_escalations(dmcx_ctx *c, int32_t *n) {
+  if (!c || !n) return DMCX_E_INVALID;
+  *n = 0;
+  if (c->is_group()) {
+    for (dmcx_ctx *m : c->subs) {
+      int32_t k = 0;
+      const dmcx_status st = dmcx_energy_escalations(m, &k);
+      if (st) return c->err = m->err, st;
+      *n += k;
+    }
+    return DMCX_OK;
+  }
+  if (!c->fp64e) return DMCX_OK;
+  int k = 0;
+  HIP_TRY(c, hipMemcpyAsync(&k, c->d_esc_count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *n = k;
   return DMCX_OK;
 }
 

@@ -130,4 +130,29 @@ void NobLaunch<T>::flush(int nob, const DevCtx &c, int sp, int kb, hipStream_t s
 #undef DMCX_CALL
 }
 
+template <typename T>
+void NobLaunch<T>::values64(int nob, const DevCtx &c, double *A64, size_t lds, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    const int npts = c.Wpad * c.ne;
+#define DMCX_CALL(N)                                                                   \
+  if (allow_lds(k_values64<T, N>, lds) == hipSuccess) \
+  k_values64<T, N><<<dim3((npts + NVALID - 1) / NVALID), dim3(NT_TILE), lds, s>>>(c, A64)
+    DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+  }
+}
+
+template <typename T>
+void NobLaunch<T>::escalate_gl(int nob, const DevCtx &c, const double *G64, const EscList &esc,
+                               size_t lds, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    const int ntile = (c.ne + TW - 1) / TW;
+#define DMCX_CALL(N)                                                                   \
+  if (allow_lds(k_escalate_gl<N>, lds) == hipSuccess) \
+  k_escalate_gl<N><<<dim3(c.Wpad * ntile), dim3(NT_TILE), lds, s>>>(c, G64, esc)
+    DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+  }
+}
+
 }  // namespace dmcx

@@ -363,6 +363,69 @@ __device__ void basis_stage(const BasisLDS &B, int g_begin, int g_end, int fn_be
 #undef DMCX_BASIS_CASE
 }
 
+// Basis values only (no derivatives) of one stage at NVALID points into
+// Bs[f][point] (the orbital-value tile: one MFMA column per point).  A task is
+// one (point, shell): its radial part once, then every Cartesian component.
+template <typename T, int L, int NPR>
+__device__ void basis_stage_val_t(const BasisLDS &B, int g_begin, int g_end, int fn_begin,
+                                  const double (*pts)[3], T *Bs, int vt, int nvt,
+                                  int npr_rt = NPR) {
+  const int nsh = 4 * (g_end - g_begin);
+  const int ntask = NVALID * nsh;
+  for (int task = vt; task < ntask; task += nvt) {
+    const int pt = task % NVALID, sl = task / NVALID;
+    const int g = g_begin + (sl >> 2), s = sl & 3;
+    const int4 gi = B.ginfo[g];
+    const double *cxyz = B.xyz + (size_t)(g * 4 + s) * 3;
+    const T x = (T)(pts[pt][0] - cxyz[0]), y = (T)(pts[pt][1] - cxyz[1]), z = (T)(pts[pt][2] - cxyz[2]);
+    const T s2 = x * x + y * y + z * z;
+    T R0 = 0;
+    if constexpr (NPR > 0) {
+      T e[NPR];
+#pragma unroll
+      for (int p = 0; p < NPR; ++p) e[p] = (T)B.coef[gi.w + p * 4 + s] * texp(-(T)B.alpha[gi.w + p * 4 + s] * s2);
+#pragma unroll
+      for (int p = 0; p < NPR; ++p) R0 += e[p];
+    } else {
+      for (int p = 0; p < npr_rt; ++p)
+        R0 += (T)B.coef[gi.w + p * 4 + s] * texp(-(T)B.alpha[gi.w + p * 4 + s] * s2);
+    }
+    T *base = Bs + (size_t)(gi.z - fn_begin + s) * NCOL + pt;  // comp 0 of this shell
+    constexpr int NC = L == 0 ? 1 : (L == 1 ? 3 : 6);
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      T P, Px, Py, Pz, Lp;
+      switch (cc) {  // resolved at compile time after unrolling
+        case 0: cart_poly_t<L, 0, T>(x, y, z, P, Px, Py, Pz, Lp); break;
+        case 1: cart_poly_t<L, 1, T>(x, y, z, P, Px, Py, Pz, Lp); break;
+        case 2: cart_poly_t<L, 2, T>(x, y, z, P, Px, Py, Pz, Lp); break;
+        case 3: cart_poly_t<L, 3, T>(x, y, z, P, Px, Py, Pz, Lp); break;
+        case 4: cart_poly_t<L, 4, T>(x, y, z, P, Px, Py, Pz, Lp); break;
+        default: cart_poly_t<L, 5, T>(x, y, z, P, Px, Py, Pz, Lp); break;
+      }
+      base[(size_t)cc * 4 * NCOL] = P * R0;
+    }
+  }
+}
+
+template <typename T>
+__device__ void basis_stage_val(const BasisLDS &B, int g_begin, int g_end, int fn_begin,
+                                const double (*pts)[3], T *Bs, int vt, int nvt) {
+  const int4 gi = B.ginfo[g_begin];
+#define DMCX_BASIS_CASE(LL, NN) \
+  case LL * 16 + NN: basis_stage_val_t<T, LL, NN>(B, g_begin, g_end, fn_begin, pts, Bs, vt, nvt); break;
+  switch (gi.x * 16 + (gi.y <= 4 ? gi.y : 0)) {
+    DMCX_BASIS_CASE(0, 1) DMCX_BASIS_CASE(0, 2) DMCX_BASIS_CASE(0, 3) DMCX_BASIS_CASE(0, 4)
+    DMCX_BASIS_CASE(1, 1) DMCX_BASIS_CASE(1, 2) DMCX_BASIS_CASE(1, 3) DMCX_BASIS_CASE(1, 4)
+    DMCX_BASIS_CASE(2, 1) DMCX_BASIS_CASE(2, 2) DMCX_BASIS_CASE(2, 3) DMCX_BASIS_CASE(2, 4)
+    case 0: basis_stage_val_t<T, 0, 0>(B, g_begin, g_end, fn_begin, pts, Bs, vt, nvt, gi.y); break;
+    case 16: basis_stage_val_t<T, 1, 0>(B, g_begin, g_end, fn_begin, pts, Bs, vt, nvt, gi.y); break;
+    case 32: basis_stage_val_t<T, 2, 0>(B, g_begin, g_end, fn_begin, pts, Bs, vt, nvt, gi.y); break;
+    default: break;
+  }
+#undef DMCX_BASIS_CASE
+}
+
 // Workgroup barrier that orders LDS traffic only: waits for this wave's LDS
 // operations, then synchronises.  Outstanding global loads stay in flight
 // (a plain __syncthreads would drain them), which lets the LCAO operands of
@@ -439,7 +502,9 @@ __device__ __forceinline__ void mfma_stage(typename Acc4<T>::type (&acc)[(NOB + 
 // stage s, so they arrive during those MFMAs, the basis evaluation and the
 // barrier.  One barrier per stage; the two K-parity partial sums are added
 // once at the end.
-template <typename T, int NOB, int KS = stage_ksteps(NOB)>
+// VAL: the tile's NVALID columns are NVALID points with their values only
+// (basis_stage_val) instead of TW points with five VGL rows each.
+template <typename T, int NOB, int KS = stage_ksteps(NOB), bool VAL = false>
 __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)[3], T *Bs0,
                         T *Bs1, T *out) {
   constexpr int NQ = (NOB + 3) / 4;
@@ -475,7 +540,8 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
     Bs0[(i / NPADC) * NCOL + NVALID + i % NPADC] = (T)0;
     Bs1[(i / NPADC) * NCOL + NVALID + i % NPADC] = (T)0;
   }
-  basis_stage<T>(BL, g0, g1, fb, pts, Bs0, tid, NT_TILE);
+  if constexpr (VAL) basis_stage_val<T>(BL, g0, g1, fb, pts, Bs0, tid, NT_TILE);
+  else basis_stage<T>(BL, g0, g1, fb, pts, Bs0, tid, NT_TILE);
   lds_barrier();
   // The LCAO operands of stage s+1 are requested before the MFMAs of stage s
   // (their registers are free by then), so they have the MFMAs, the basis
@@ -490,7 +556,10 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
       SUB_T(tm0);
       mfma_stage<T, NOB, KH>(acc, a0, Bs0, nk_cur, ob0, kh, kq, col);
       SUB_T(tm1);
-      if (st + 1 < S) basis_stage<T>(BL, g0, g1, fb, pts, Bs1, tid, NT_TILE);
+      if (st + 1 < S) {
+        if constexpr (VAL) basis_stage_val<T>(BL, g0, g1, fb, pts, Bs1, tid, NT_TILE);
+        else basis_stage<T>(BL, g0, g1, fb, pts, Bs1, tid, NT_TILE);
+      }
       SUB_T(tm2);
       SUB_ADD(11, tm0, tm1);
       SUB_ADD(9, tm1, tm2);
@@ -506,7 +575,10 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
       SUB_T(tm0);
       mfma_stage<T, NOB, KH>(acc, a1, Bs1, nk_cur, ob0, kh, kq, col);
       SUB_T(tm1);
-      if (st + 2 < S) basis_stage<T>(BL, g0, g1, fb, pts, Bs0, tid, NT_TILE);
+      if (st + 2 < S) {
+        if constexpr (VAL) basis_stage_val<T>(BL, g0, g1, fb, pts, Bs0, tid, NT_TILE);
+        else basis_stage<T>(BL, g0, g1, fb, pts, Bs0, tid, NT_TILE);
+      }
       SUB_T(tm2);
       SUB_ADD(11, tm0, tm1);
       SUB_ADD(9, tm1, tm2);
@@ -664,14 +736,56 @@ __global__ __launch_bounds__(NT_TILE) void k_orbitals_at(DevCtx c, const double 
   }
 }
 
+// FP64 orbital values (no derivatives) of every electron of every walker,
+// NVALID (walker, electron) points per tile: A64[w][e][NP], the Slater
+// matrices from which the mixed form takes its FP64 inverse and energy each
+// step.  The working-precision value rows of vglc are refreshed from them, so
+// the next sweep's delayed updates start from rows that match the inverse.
+// The mixed form's stages are packed at half depth (its FP32 sweep's), so
+// this kernel sizes its stage buffers for that, keeps the output tile in the
+// same LDS (it is written after the last stage), and runs at four waves per
+// SIMD: two workgroups share a CU, and one's basis evaluation overlaps the
+// other's MFMAs.
+template <typename T, int NOB>
+__global__ __launch_bounds__(NT_TILE) __attribute__((amdgpu_waves_per_eu(4)))
+void k_values64(DevCtx c, double *A64) {
+  constexpr int NP = NOB * 16;
+  constexpr int KS = stage_ksteps_w4(NOB);
+  constexpr int FM = 4 * KS;
+  constexpr int NBS = 2 * FM * NCOL > NVALID * NP ? 2 * FM * NCOL : NVALID * NP;
+  extern __shared__ __align__(16) char smem_basis[];
+  const BasisLDS BL = stage_basis_lds(c.B, smem_basis);
+  __shared__ double Bsm[NBS];  // two stage buffers, then the output tile
+  double *Bs0 = Bsm, *Bs1 = Bsm + FM * NCOL, *out = Bsm;
+  __shared__ double pts[NVALID][3];
+  const int npts = c.Wpad * c.ne;
+  const int p0 = blockIdx.x * NVALID;
+  for (int i = threadIdx.x; i < NVALID * 3; i += NT_TILE) {
+    const int p = min(p0 + i / 3, npts - 1);
+    pts[i / 3][i % 3] = c.R[(size_t)p * 3 + i % 3];
+  }
+  __syncthreads();
+  mo_tile<double, NOB, KS, true>(c, BL, pts, Bs0, Bs1, out);
+  for (int i = threadIdx.x; i < NVALID * NP; i += NT_TILE) {
+    const int pl = i / NP, j = i - pl * NP, p = p0 + pl;
+    if (p < npts) {
+      A64[(size_t)p * NP + j] = out[i];
+      ((T *)c.vglc)[(size_t)p * 5 * NP + j] = (T)out[i];
+    }
+  }
+}
+
 // FP64 inverse of each walker's Slater matrix by in-place Gauss-Jordan
-// elimination with partial pivoting, built from the cached value rows.
-// grid (Wpad, 2); dynamic LDS n*n doubles.  Writes GT (transposed, zero
-// padded), log|det| and sign; flags singular matrices.
+// elimination with partial pivoting, one workgroup per matrix (the form for
+// matrices wider than a wave; inverse.h has the one-wave form).  Value rows
+// of precision S at rows + (w ne + e) rs.  grid (Wpad, 2); dynamic LDS n*n
+// doubles.  Writes GT (transposed, zero padded), log|det| and sign, and an
+// FP64 copy of the inverse to G64 if not null; flags singular matrices.
 // periodic != 0: runs only at steps s = 0 (mod P) of the device step counter
 // (the form captured into a step graph); periodic == 0: always.
-template <typename T>
-__global__ __launch_bounds__(NT_AUX) void k_inverse(DevCtx c, int periodic) {
+template <typename T, typename S>
+__global__ __launch_bounds__(NT_AUX) void k_inverse(DevCtx c, const S *rows, int rs, double *G64,
+                                                    int periodic) {
   extern __shared__ double A[];
   __shared__ int piv[128];
   __shared__ double fcol[128];
@@ -686,14 +800,17 @@ __global__ __launch_bounds__(NT_AUX) void k_inverse(DevCtx c, int periodic) {
   const int tid = threadIdx.x;
   T *GT = (T *)c.GT + gt_off(c, w, sp);
   if (n == 0) {
-    for (int i = tid; i < NP * NP; i += NT_AUX) GT[i] = (T)0;
+    for (int i = tid; i < NP * NP; i += NT_AUX) {
+      GT[i] = (T)0;
+      if (G64) G64[gt_off(c, w, sp) + i] = 0.0;
+    }
     if (tid == 0) { c.logdet[w * 2 + sp] = 0.0; c.sgn[w * 2 + sp] = 1.0; }
     return;
   }
   const int e0 = sp == 0 ? 0 : c.n_up;
   for (int i = tid; i < n * n; i += NT_AUX) {
     const int r = i / n, j = i % n;
-    A[i] = (double)((const T *)c.vglc)[vglc_off(c, w, e0 + r) + j];
+    A[i] = (double)rows[((size_t)w * c.ne + e0 + r) * rs + j];
   }
   if (tid == 0) { s_logdet = 0.0; s_sign = 1; s_sing = 0; }
   __syncthreads();
@@ -768,9 +885,12 @@ __global__ __launch_bounds__(NT_AUX) void k_inverse(DevCtx c, int periodic) {
     __syncthreads();
   }
   // GT[b][j] = Ainv[j][b]
+  double *G6 = G64 ? G64 + gt_off(c, w, sp) : nullptr;
   for (int i = tid; i < NP * NP; i += NT_AUX) {
     const int b = i / NP, j = i % NP;
-    GT[i] = (T)((b < n && j < n) ? A[j * n + b] : 0.0);
+    const double v = (b < n && j < n) ? A[j * n + b] : 0.0;
+    GT[i] = (T)v;
+    if (G6) G6[i] = v;
   }
   if (tid == 0) {
     c.logdet[w * 2 + sp] = s_logdet;
@@ -778,37 +898,77 @@ __global__ __launch_bounds__(NT_AUX) void k_inverse(DevCtx c, int periodic) {
   }
 }
 
+// Re-evaluation of the mixed form's energy for walkers whose FP32 derivative
+// rows could move E_L by more than a set bound.  The first-order change of
+// E_L from relative errors u in the derivative rows B is bounded by
+//   (u / 2) sum_i sum_j (|lap phi_j(r_i)| + 2 |grad_i J|_1 |grad phi_j(r_i)|_1) |G_ji|,
+// with G the FP64 inverse.  Walkers above cap N_e go on a list; their
+// derivative rows are then evaluated in FP64 and their E_L (and DMC weight)
+// recomputed.
+constexpr double ESC_U = 5.9604644775390625e-08;  // 2^-24, FP32 unit roundoff
+struct EscList {
+  int mode;       // 0 none; 1 collect onto the list; 2 re-evaluate the listed walkers
+  int *count;     // listed walkers
+  int *list;      // [Wpad] walker of each list slot
+  const double *gl;  // [Wpad][ne][4] FP64 (g_i, l_i) of each list slot (mode 2)
+  double cap;     // bound per electron above which a walker is listed (Ha)
+};
+
 // Local energy of each walker from the cached orbital rows and inverses:
 //   E_L = -1/2 sum_i [lap_i J + |grad_i J|^2 + 2 grad_i J . g_i + l_i] + V,
 //   g_i = sum_j grad phi_j(r_i) A^{-1}_{j i},  l_i = sum_j lap phi_j(r_i) A^{-1}_{j i}.
-// One workgroup per walker.  measure_only != 0: E_L only; otherwise the end
+// One workgroup per walker.  G64 (may be null): an FP64 copy of the inverses
+// to contract with instead of GT (the mixed form's FP64 energy).
+// measure_only != 0: E_L only; otherwise the end
 // of a step in the run state's mode: DMC updates the log-weight
 // (log w += -tau ((E_old + E_new)/2 - E_T)); e_log (may be null) receives
 // E_L in row s_in_run of a table with row stride elog_stride.
 template <typename T>
 __global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int measure_only, double *e_log,
-                                                           long long elog_stride) {
+                                                           long long elog_stride, const double *G64,
+                                                           EscList esc) {
   const int mode = measure_only ? -1 : c.run->mode;
   const double e_trial = c.run->e_trial;
   double *e_log_row = (e_log && !measure_only) ? e_log + c.run->s_in_run * elog_stride : nullptr;
-  __shared__ double part[NT_AUX / 64][3];
+  __shared__ double part[NT_AUX / 64][4];
   __shared__ double msx_le[NT_AUX / 64][4 * MSD_NV_MAX];  // MSD: w (3 rows) and y per wave
-  const int w = blockIdx.x;
+  int w = blockIdx.x;
+  if (esc.mode == 2) {
+    if ((int)blockIdx.x >= *esc.count) return;  // whole block
+    w = esc.list[blockIdx.x];
+  }
+  const double *glw = esc.mode == 2 ? esc.gl + (size_t)blockIdx.x * c.ne * 4 : nullptr;
   const int tid = threadIdx.x, wid = wave_id(), lane = tid & 63;
   const int NP = c.NP;
   const double *Rw = c.R + (size_t)w * c.ne * 3;
-  double kin = 0.0, pot = 0.0, jv = 0.0;
+  double kin = 0.0, pot = 0.0, jv = 0.0, bound = 0.0;
   for (int i = wid; i < c.ne; i += NT_AUX / 64) {
     const int sp = i < c.n_up ? 0 : 1, ii = i - sp * c.n_up;
     const T *row = (const T *)c.vglc + vglc_off(c, w, i);
     const T *gcol = (const T *)c.GT + gt_off(c, w, sp) + (size_t)ii * NP;
-    double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0;
-    for (int j = lane; j < NP; j += 64) {
-      const double gj = (double)gcol[j];
-      g0 += (double)row[NP + j] * gj;
-      g1 += (double)row[2 * NP + j] * gj;
-      g2 += (double)row[3 * NP + j] * gj;
-      l += (double)row[4 * NP + j] * gj;
+    const double *gcol64 = G64 ? G64 + gt_off(c, w, sp) + (size_t)ii * NP : nullptr;
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0, bl = 0.0, bg = 0.0;
+    if (glw) {
+      if (lane == 0) {
+        g0 = glw[4 * i];
+        g1 = glw[4 * i + 1];
+        g2 = glw[4 * i + 2];
+        l = glw[4 * i + 3];
+      }
+    } else {
+      for (int j = lane; j < NP; j += 64) {
+        const double gj = gcol64 ? gcol64[j] : (double)gcol[j];
+        const double r1 = (double)row[NP + j], r2 = (double)row[2 * NP + j],
+                     r3 = (double)row[3 * NP + j], r4 = (double)row[4 * NP + j];
+        g0 += r1 * gj;
+        g1 += r2 * gj;
+        g2 += r3 * gj;
+        l += r4 * gj;
+        if (esc.mode == 1) {
+          bl += fabs(r4 * gj);
+          bg += (fabs(r1) + fabs(r2) + fabs(r3)) * fabs(gj);
+        }
+      }
     }
     // Jastrow gradient / Laplacian, value (pairs counted once) and potential
     const double *ri = Rw + 3 * i;
@@ -911,13 +1071,30 @@ __global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int measure_o
     kin += jl + jg0 * jg0 + jg1 * jg1 + jg2 * jg2 + 2.0 * (jg0 * g0 + jg1 * g1 + jg2 * g2) + l + msd_k;
     pot += v;
     jv += ju;
+    if (esc.mode == 1) {
+      bl = sum64(bl);
+      bg = sum64(bg);
+      bound += bl + 2.0 * (fabs(jg0) + fabs(jg1) + fabs(jg2)) * bg;
+    }
   }
-  if (lane == 0) { part[wid][0] = kin; part[wid][1] = pot; part[wid][2] = jv; }
+  if (lane == 0) { part[wid][0] = kin; part[wid][1] = pot; part[wid][2] = jv; part[wid][3] = bound; }
   __syncthreads();
   if (tid == 0) {
-    double K = 0.0, V = 0.0, J = 0.0;
-    for (int q = 0; q < NT_AUX / 64; ++q) { K += part[q][0]; V += part[q][1]; J += part[q][2]; }
+    double K = 0.0, V = 0.0, J = 0.0, Bd = 0.0;
+    for (int q = 0; q < NT_AUX / 64; ++q) {
+      K += part[q][0]; V += part[q][1]; J += part[q][2]; Bd += part[q][3];
+    }
     const double e = -0.5 * K + V + c.v_nn;
+    if (esc.mode == 2) {
+      // the walker's E_L of this step was first taken from FP32 derivative
+      // rows (and entered its weight); replace it and correct the weight
+      const double efirst = c.eloc[w];
+      if (mode == 1) c.logw[w] += -c.tau * 0.5 * (e - efirst);
+      c.eloc[w] = e;
+      if (!isfinite(e)) c.flags[w] |= 1u;
+      if (e_log_row && w < c.W) e_log_row[w] = e;
+      return;
+    }
     const double eold = c.eloc[w];
     if (mode == 1) c.logw[w] += -c.tau * (0.5 * (eold + e) - e_trial);
     c.eloc[w] = e;
@@ -925,6 +1102,57 @@ __global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int measure_o
     c.logpsi[w] = J + c.logdet[w * 2] + c.logdet[w * 2 + 1] + (c.M.on ? log(fabs(c.M.S[w])) : 0.0);
     if (!isfinite(e) || !isfinite(c.logpsi[w])) c.flags[w] |= 1u;
     if (e_log_row && w < c.W) e_log_row[w] = e;
+    if (esc.mode == 1 && w < c.W && 0.5 * ESC_U * Bd > esc.cap * c.ne && isfinite(e))
+      esc.list[atomicAdd(esc.count, 1)] = w;
+  }
+}
+
+// FP64 orbital VGL of the listed walkers' electrons (TW per tile), contracted
+// with their FP64 inverses into g_i = sum_j grad phi_j(r_i) G_ji and
+// l_i = sum_j lap phi_j(r_i) G_ji: gl[slot][e][4].  grid: Wpad * ceil(ne / TW)
+// tiles; tiles past the listed walkers return at once.
+template <int NOB>
+__global__ __launch_bounds__(NT_TILE) void k_escalate_gl(DevCtx c, const double *G64, EscList esc) {
+  constexpr int NP = NOB * 16;
+  constexpr int FM = 4 * stage_ksteps(NOB);
+  const int ntile = (c.ne + TW - 1) / TW;
+  const int slot = blockIdx.x / ntile, tile = blockIdx.x % ntile;
+  if (slot >= *esc.count) return;  // whole block
+  extern __shared__ __align__(16) char smem_basis[];
+  const BasisLDS BL = stage_basis_lds(c.B, smem_basis);
+  __shared__ double Bs0[FM * NCOL], Bs1[FM * NCOL];
+  __shared__ double out[TW * 5 * NP];
+  __shared__ double pts[TW][3];
+  const int w = esc.list[slot];
+  const int e0 = tile * TW;
+  if (threadIdx.x < TW * 3) {
+    const int e = min(e0 + (int)threadIdx.x / 3, c.ne - 1);
+    pts[threadIdx.x / 3][threadIdx.x % 3] = c.R[((size_t)w * c.ne + e) * 3 + threadIdx.x % 3];
+  }
+  __syncthreads();
+  mo_tile<double, NOB>(c, BL, pts, Bs0, Bs1, out);
+  const int ws = wave_id(), t = threadIdx.x & 63;
+  const int e = e0 + ws;
+  if (e < c.ne) {
+    const int sp = e < c.n_up ? 0 : 1, ii = e - sp * c.n_up;
+    const double *gc = G64 + gt_off(c, w, sp) + (size_t)ii * NP;
+    const double *o = out + ws * 5 * NP;
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0;
+    for (int j = t; j < NP; j += 64) {
+      const double gj = gc[j];
+      g0 += o[NP + j] * gj;
+      g1 += o[2 * NP + j] * gj;
+      g2 += o[3 * NP + j] * gj;
+      l += o[4 * NP + j] * gj;
+    }
+    g0 = sum64(g0); g1 = sum64(g1); g2 = sum64(g2); l = sum64(l);
+    if (t == 0) {
+      double *dst = (double *)esc.gl + ((size_t)slot * c.ne + e) * 4;
+      dst[0] = g0;
+      dst[1] = g1;
+      dst[2] = g2;
+      dst[3] = l;
+    }
   }
 }
 

@@ -49,6 +49,23 @@ struct NobLaunch {
                      const uint8_t *acc8, const T *prop, const double *prop_rho,
                      const double *r_new, hipStream_t s);
   static void flush(int nob, const DevCtx &c, int sp, int kb, hipStream_t s);
+  // FP64 orbital values of every electron -> A64 [Wpad][ne][NP], and the
+  // working-precision value rows of vglc from them (mixed form only)
+  static void values64(int nob, const DevCtx &c, double *A64, size_t lds, hipStream_t s);
+  // FP64 (g_i, l_i) of the walkers on the re-evaluation list (mixed form only)
+  static void escalate_gl(int nob, const DevCtx &c, const double *G64, const EscList &esc,
+                          size_t lds, hipStream_t s);
 };
+
+// FP64 inverse with one wave per matrix (inverse.hip): value rows of
+// precision S at rows + (w ne + e) rs; writes GT (precision T), log|det|,
+// sign and, if G64 is not null, an FP64 copy of the inverses.  Returns false
+// (nothing launched) when NP > 64: the rows do not fit one wave.
+template <typename T, typename S>
+bool inverse_w(const DevCtx &c, const S *rows, int rs, double *G64, int periodic, hipStream_t s);
+// one padded width NR of it (instantiated in inv_*.hip)
+template <typename T, typename S, int NR>
+void launch_inverse_nr(const DevCtx &c, const S *rows, int rs, double *G64, int periodic,
+                       hipStream_t s);
 
 }  // namespace dmcx

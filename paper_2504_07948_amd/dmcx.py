@@ -23,6 +23,7 @@ DMCX_FP64, DMCX_MIXED = 0, 1
 DMCX_VMC, DMCX_DMC = 0, 1
 DMCX_HOST, DMCX_DEVICE = 0, 1
 DMCX_FLAG_GRAPH = 1
+DMCX_FLAG_FP32_ENERGY = 2
 DMCX_N_ESTIMATORS = 11
 DMCX_NOALLOC_MAX_WALKERS = 1048576
 
@@ -34,6 +35,7 @@ EXPORTED = [
     "dmcx_selftest", "dmcx_philox", "dmcx_strerror", "dmcx_last_error", "dmcx_autotune",
     "dmcx_autotune_report", "dmcx_get_delay_rank", "dmcx_reconfigure", "dmcx_estimators",
     "dmcx_zv_grads", "dmcx_forces_zv", "dmcx_estimators_noalloc",
+    "dmcx_energy_escalations",
 ]
 
 
@@ -112,6 +114,7 @@ def load():
         "dmcx_zv_grads": [P, I32, P, P, P, I32],
         "dmcx_forces_zv": [P, I32, P, I32],
         "dmcx_estimators_noalloc": [I32, P, P, P, P, P, P, P],
+        "dmcx_energy_escalations": [P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -315,7 +318,7 @@ class Context:
     """Owns one dmcx context for one or more systems."""
 
     def __init__(self, systems, walkers, precision=DMCX_FP64, delay_rank=32, recompute_period=64,
-                 tau=0.01, seed=1, stream=None, graph=False):
+                 tau=0.01, seed=1, stream=None, graph=False, fp32_energy=False):
         if not isinstance(systems, (list, tuple)):
             systems = [systems]
             walkers = [walkers]
@@ -331,7 +334,8 @@ class Context:
         self.offsets = np.concatenate([[0], np.cumsum(wps)[:-1]]).astype(int).tolist()
         opt = dmcx_options(precision=precision, delay_rank=delay_rank,
                            recompute_period=recompute_period, tau=tau, seed=seed,
-                           flags=DMCX_FLAG_GRAPH if graph else 0)
+                           flags=(DMCX_FLAG_GRAPH if graph else 0)
+                           | (DMCX_FLAG_FP32_ENERGY if fp32_energy else 0))
         h = C.c_void_p()
         st = load().dmcx_create(arr, len(systems), _ptr(wps), C.byref(opt), stream, C.byref(h))
         if st != DMCX_OK:
@@ -463,6 +467,12 @@ class Context:
         out = np.zeros((self.n_sys, DMCX_N_ESTIMATORS))
         self.check(dmcx_estimators(self.h, _ptr(out), DMCX_HOST))
         return out
+
+    def energy_escalations(self):
+        """Walkers whose E_L the last energy evaluation took from FP64 rows."""
+        n = C.c_int32(0)
+        self.check(load().dmcx_energy_escalations(self.h, C.byref(n)))
+        return int(n.value)
 
     def walker_flags(self):
         f = np.zeros(self.W, dtype=np.uint8)

@@ -122,16 +122,12 @@ def test_large_molecule_full_population():
     np.testing.assert_array_equal(sg_a, _apply(pairs, sg_b))
 
 
-@pytest.mark.parametrize("form", ["mixed", "msd"])
-def test_copies_carry_state_mixed_and_multideterminant(form):
+@pytest.mark.parametrize("form,prec", [("mixed", dmcx.DMCX_MIXED), ("msd", dmcx.DMCX_FP64),
+                                       ("msd", dmcx.DMCX_MIXED)])
+def test_copies_carry_state_mixed_and_multideterminant(form, prec):
     base = synth.small_random_system(77, n_atom=2, n_up=3, n_dn=3, shells=(0, 0, 1, 2), nprim=2,
                                      n_mo=10)
-    if form == "msd":
-        s = synth.make_msd(base, n_det=15, n_active=6, seed=78)
-        prec = dmcx.DMCX_MIXED
-    else:
-        s = base
-        prec = dmcx.DMCX_MIXED
+    s = synth.make_msd(base, n_det=15, n_active=6, seed=78) if form == "msd" else base
     W = 29
     ctx = dmcx.Context(s, W, precision=prec, delay_rank=2, recompute_period=4, seed=3)
     ctx.set_walkers(synth.make_walkers(s, W, 79))
