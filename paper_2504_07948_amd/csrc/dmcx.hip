@@ -773,6 +773,34 @@ dmcx_status setup_msd(dmcx_ctx *c, const dmcx_system &s, const std::vector<int> 
     M.rlst[sp] = dr;
     M.rcoef[sp] = drc;
     M.max_lst = std::max(M.max_lst, M.n_lst[sp]);
+    // gather lists of Gamma = d ln S / dT (force adjoint), one per table entry
+    const int n = sp == 0 ? s.n_up : s.n_dn;
+    std::vector<std::vector<int4>> per((size_t)std::max(n, 1) * std::max(M.nv, 1));
+    for (int q = 0; q < (int)lst[sp].size(); ++q) {
+      const int4 e = lst[sp][q];
+      const int h0 = e.z & 0xffff, h1 = (unsigned)e.z >> 16, v0 = e.w & 0xffff, v1 = (unsigned)e.w >> 16;
+      if (e.y == 1) {
+        per[(size_t)h0 * M.nv + v0].push_back(make_int4(q, -1, 0, 1));
+      } else {
+        per[(size_t)h0 * M.nv + v0].push_back(make_int4(q, h1, v1, 1));
+        per[(size_t)h1 * M.nv + v1].push_back(make_int4(q, h0, v0, 1));
+        per[(size_t)h0 * M.nv + v1].push_back(make_int4(q, h1, v0, -1));
+        per[(size_t)h1 * M.nv + v0].push_back(make_int4(q, h0, v1, -1));
+      }
+    }
+    std::vector<int> gptr(1, 0);
+    std::vector<int4> gcon;
+    for (const auto &v : per) {
+      gcon.insert(gcon.end(), v.begin(), v.end());
+      gptr.push_back((int)gcon.size());
+    }
+    if (gcon.empty()) gcon.push_back(make_int4(0, -1, 0, 0));
+    int *dgp;
+    int4 *dgc;
+    if ((st = upload(c, &dgp, gptr))) return st;
+    if ((st = upload(c, &dgc, gcon))) return st;
+    M.gptr[sp] = dgp;
+    M.gcon[sp] = dgc;
   }
   const size_t Wp = c->Wpad;
   char *pv;

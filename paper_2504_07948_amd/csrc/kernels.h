@@ -190,6 +190,12 @@ struct DevMsd {
   const int *rlst[2];
   const double *rcoef[2];
   int max_lst;
+  // Gamma = d ln S / dT of the force adjoint, gathered per entry: entry
+  // (h, v) of spin s sums its contributions gcon[s][gptr[s][h nv + v] ..) in
+  // determinant order, each {list index q, h', v', sign} meaning
+  // sign c_q R^other_q T[h'][v'] / S (h' < 0: no table factor)
+  const int *gptr[2];
+  const int4 *gcon[2];
   void *Tt;               // [Wpad][2][NP][ldt] the table (working precision)
   double *Rdet;           // [Wpad][2][n_det] D_d^s / D_0^s
   double *S;              // [Wpad] sum_d c_d R_d^up R_d^dn

@@ -87,22 +87,20 @@ __global__ __launch_bounds__(NT_AUX) void k_msd_force_weights(DevCtx c, T *WT) {
   const T *Tw = (const T *)M.Tt + ((size_t)w * 2 + sp) * NP * ldt;
   const double *Ro = M.Rdet + ((size_t)w * 2 + (1 - sp)) * M.n_det;
   T *Wo = WT + gt_off(c, w, sp);
-  for (int q = tid; q < n * nv; q += NT_AUX) Gam[q] = 0.0;
-  __syncthreads();
   const double iS = 1.0 / M.S[w];
-  for (int q = tid; q < M.n_lst[sp]; q += NT_AUX) {
-    const int4 e = M.lst[sp][q];
-    const int ne = e.y, h0 = e.z & 0xffff, h1 = (unsigned)e.z >> 16, v0 = e.w & 0xffff,
-              v1 = (unsigned)e.w >> 16;
-    const double cr = M.lcoef[sp][q] * Ro[e.x] * iS;
-    if (ne == 1) {
-      atomicAdd(&Gam[h0 * nv + v0], cr);
-    } else {
-      atomicAdd(&Gam[h0 * nv + v0], cr * (double)Tw[(size_t)h1 * ldt + v1]);
-      atomicAdd(&Gam[h1 * nv + v1], cr * (double)Tw[(size_t)h0 * ldt + v0]);
-      atomicAdd(&Gam[h0 * nv + v1], -cr * (double)Tw[(size_t)h1 * ldt + v0]);
-      atomicAdd(&Gam[h1 * nv + v0], -cr * (double)Tw[(size_t)h0 * ldt + v1]);
+  // each entry sums its own contributions in determinant order (no atomics,
+  // so the result does not depend on how the threads were scheduled)
+  const int *gptr = M.gptr[sp];
+  const int4 *gcon = M.gcon[sp];
+  for (int q = tid; q < n * nv; q += NT_AUX) {
+    double g = 0.0;
+    for (int k = gptr[q]; k < gptr[q + 1]; ++k) {
+      const int4 e = gcon[k];
+      const double cr = M.lcoef[sp][e.x] * Ro[M.lst[sp][e.x].x];
+      const double f = e.y < 0 ? 1.0 : (double)Tw[(size_t)e.y * ldt + e.z];
+      g += (double)e.w * cr * f;
     }
+    Gam[q] = g * iS;
   }
   __syncthreads();
   for (int q = tid; q < n * nv; q += NT_AUX) {
