@@ -119,6 +119,26 @@ struct dmcx_ctx {
   // share the caller's stream; runs fork them onto streams of their own
   std::vector<dmcx_ctx *> subs;
   std::vector<int> sub_off;  // first walker of each system, creation order
+  // A group's sweep classes: systems that share one sweep kernel (orbital-tile
+  // width and form) are swept by one launch over all their walker tiles, the
+  // costliest class and system first.  The launch reads each system's kernel
+  // arguments from d_cs, uploaded whenever a member's arguments change.
+  struct SweepClass {
+    std::vector<size_t> members;  // indices into the group's systems, costliest first
+    int nob = 0;
+    bool msd = false;
+    int ntiles = 0;
+    size_t lds = 0;
+    DevCtx *d_cs = nullptr;
+    int2 *d_tiles = nullptr;
+    SweepLog *d_logs = nullptr;
+    std::vector<DevCtx> h_cs;
+    std::vector<SweepLog> h_logs;
+    uint64_t key = 0;
+    uint8_t *acc = nullptr;
+    bool uploaded = false;
+  };
+  std::vector<SweepClass> classes;
   hipStream_t own = nullptr; // this system's run stream (groups, graphs)
   std::vector<hipEvent_t> fj;      // fork/join events of eager and graph runs
   std::vector<hipEvent_t> cap_ev;  // fork/join events inside a graph capture
@@ -1282,32 +1302,154 @@ std::vector<size_t> launch_order(const std::vector<dmcx_ctx *> &ms) {
 // Capture one step of every member (forked onto the members' own streams)
 // into a graph.  Log pointers and strides are baked in; the step index,
 // mode and E_T are read from each member's device run state.
+// Sweep classes of a group (built once): systems of one orbital-tile width
+// and form share a launch; tiles of the costliest system come first.
+dmcx_status build_classes(dmcx_ctx *top, const std::vector<dmcx_ctx *> &ms) {
+  if (!top->classes.empty()) return DMCX_OK;
+  for (size_t i : launch_order(ms)) {
+    dmcx_ctx *m = ms[i];
+    const bool msd = m->dc.M.on != 0;
+    size_t k = 0;
+    while (k < top->classes.size() && !(top->classes[k].nob == m->NOB && top->classes[k].msd == msd))
+      ++k;
+    if (k == top->classes.size()) {
+      top->classes.emplace_back();
+      top->classes.back().nob = m->NOB;
+      top->classes.back().msd = msd;
+    }
+    top->classes[k].members.push_back(i);
+  }
+  dmcx_status st;
+  for (auto &cl : top->classes) {
+    if (cl.members.size() < 2) continue;  // one system: its own launch
+    std::vector<int2> tiles;
+    for (size_t k = 0; k < cl.members.size(); ++k) {
+      const dmcx_ctx *m = ms[cl.members[k]];
+      for (int t = 0; t < m->Wpad / TW; ++t) tiles.push_back(make_int2((int)k, t));
+      cl.lds = std::max(cl.lds, basis_lds(m));
+    }
+    cl.ntiles = (int)tiles.size();
+    if ((st = upload(top, &cl.d_tiles, tiles))) return st;
+    if ((st = dalloc(top, &cl.d_cs, cl.members.size()))) return st;
+    if ((st = dalloc(top, &cl.d_logs, cl.members.size()))) return st;
+    cl.h_cs.resize(cl.members.size());
+    cl.h_logs.resize(cl.members.size());
+  }
+  return DMCX_OK;
+}
+
+// Upload each class's kernel arguments when a member's have changed (delay
+// rank, ions) or the run's accept log moved; on the group's stream, which the
+// class streams wait for.
+dmcx_status upload_classes(dmcx_ctx *top, const std::vector<dmcx_ctx *> &ms, uint8_t *acc) {
+  for (auto &cl : top->classes) {
+    if (cl.members.size() < 2) continue;
+    uint64_t key = 0;
+    for (size_t i : cl.members) key += ms[i]->dc_version;
+    if (cl.uploaded && key == cl.key && acc == cl.acc) continue;
+    for (size_t k = 0; k < cl.members.size(); ++k) {
+      const size_t i = cl.members[k];
+      cl.h_cs[k] = ms[i]->dc;
+      const size_t off = top->is_group() ? top->sub_off[i] : 0;
+      cl.h_logs[k] = SweepLog{acc ? acc + off * top->ne : nullptr, (long long)top->W * top->ne,
+                              top->ne};
+    }
+    HIP_TRY(top, hipMemcpyAsync(cl.d_cs, cl.h_cs.data(), cl.h_cs.size() * sizeof(DevCtx),
+                                hipMemcpyHostToDevice, top->stream));
+    HIP_TRY(top, hipMemcpyAsync(cl.d_logs, cl.h_logs.data(), cl.h_logs.size() * sizeof(SweepLog),
+                                hipMemcpyHostToDevice, top->stream));
+    HIP_TRY(top, hipStreamSynchronize(top->stream));
+    cl.key = key;
+    cl.acc = acc;
+    cl.uploaded = true;
+  }
+  return DMCX_OK;
+}
+
+// One step of the systems of class cl on stream s: their periodic FP64
+// recomputes, one sweep launch over all their tiles (the system's own launch
+// when the class has one system), then each system's local energies, weights
+// and step counter.  ev_step >= 0: the members' sweep timing events of that
+// step are recorded around the sweep.
+dmcx_status enqueue_class_step(dmcx_ctx *top, const std::vector<dmcx_ctx *> &ms,
+                               const dmcx_ctx::SweepClass &cl, bool graph, hipStream_t s,
+                               uint8_t *acc, double *elog, int ev_step) {
+  const long long acc_ss = (long long)top->W * top->ne, elog_ss = top->W;
+  std::vector<hipStream_t> keep;
+  for (size_t i : cl.members) {
+    keep.push_back(ms[i]->stream);
+    ms[i]->stream = s;
+  }
+  dmcx_status st = DMCX_OK;
+  auto off_of = [&](size_t i) { return top->is_group() ? (size_t)top->sub_off[i] : (size_t)0; };
+  for (size_t i : cl.members) {
+    dmcx_ctx *m = ms[i];
+    if (st || m->fp64e) continue;  // the mixed form's FP64 recompute ends its step
+    if (graph) {
+      if (!(st = launch_inverse(m, 1))) st = launch_msd_rebuild(m, 1);
+    } else if (m->step % m->P == 0) {
+      if (!(st = launch_inverse(m, 0))) st = launch_msd_rebuild(m, 0);
+    }
+    if (st) top->err = m->err;
+  }
+  if (!st && ev_step >= 0)
+    for (size_t i : cl.members)
+      if (hipEventRecord(ms[i]->ev[2 * ev_step], s) != hipSuccess) st = fail(top, DMCX_E_HIP, "event");
+  if (!st) {
+    if (cl.members.size() == 1) {
+      const size_t i = cl.members[0];
+      launch_sweep(ms[i], acc ? acc + off_of(i) * top->ne : nullptr, acc_ss, top->ne);
+    } else if (cl.msd) {
+      DMCX_BY_PRECISION(top, MsdLaunch<WT>::sweep_multi(cl.nob, cl.d_cs, cl.d_tiles, cl.ntiles,
+                                                        cl.d_logs, cl.lds, s));
+    } else {
+      DMCX_BY_PRECISION(top, NobLaunch<WT>::sweep_multi(cl.nob, cl.d_cs, cl.d_tiles, cl.ntiles,
+                                                        cl.d_logs, cl.lds, s));
+    }
+    st = hip_check(top, hipGetLastError(), "sweep launch");
+  }
+  if (!st && ev_step >= 0)
+    for (size_t i : cl.members)
+      if (hipEventRecord(ms[i]->ev[2 * ev_step + 1], s) != hipSuccess) st = fail(top, DMCX_E_HIP, "event");
+  for (size_t i : cl.members) {
+    dmcx_ctx *m = ms[i];
+    if (st) break;
+    if (m->fp64e && ((st = launch_values64(m)) || (st = launch_inverse(m, 0)))) {
+      top->err = m->err;
+      break;
+    }
+    if ((st = launch_local_energy(m, 0, elog ? elog + off_of(i) : nullptr, elog_ss))) {
+      top->err = m->err;
+      break;
+    }
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, m->d_run);
+    st = hip_check(top, hipGetLastError(), "k_advance launch");
+  }
+  size_t q = 0;
+  for (size_t i : cl.members) ms[i]->stream = keep[q++];
+  return st;
+}
+
 dmcx_status build_graph(dmcx_ctx *top, const std::vector<dmcx_ctx *> &ms, uint8_t *acc,
                         double *elog, uint64_t key) {
   if (top->gexec) { (void)hipGraphExecDestroy(top->gexec); top->gexec = nullptr; }
   if (top->graph) { (void)hipGraphDestroy(top->graph); top->graph = nullptr; }
   dmcx_status st;
-  if ((st = ensure_events(top, top->cap_ev, 1 + ms.size(), false))) return st;
-  const std::vector<size_t> order = launch_order(ms);
-  const hipStream_t s0 = ms[order[0]]->own;
+  if ((st = build_classes(top, ms)) || (st = upload_classes(top, ms, acc))) return st;
+  const size_t ncl = top->classes.size();
+  if ((st = ensure_events(top, top->cap_ev, 1 + ncl, false))) return st;
+  // each class runs on the stream of its costliest system
+  auto cls_stream = [&](size_t k) { return ms[top->classes[k].members[0]]->own; };
+  const hipStream_t s0 = cls_stream(0);
   HIP_TRY(top, hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed));
-  const long long acc_ss = (long long)top->W * top->ne, elog_ss = top->W;
   if (hipEventRecord(top->cap_ev[0], s0) != hipSuccess) st = fail(top, DMCX_E_HIP, "capture: fork event");
-  for (size_t ii = 1; ii < ms.size() && !st; ++ii)
-    if (hipStreamWaitEvent(ms[order[ii]]->own, top->cap_ev[0], 0) != hipSuccess)
+  for (size_t k = 1; k < ncl && !st; ++k)
+    if (hipStreamWaitEvent(cls_stream(k), top->cap_ev[0], 0) != hipSuccess)
       st = fail(top, DMCX_E_HIP, "capture: fork wait");
-  for (size_t ii = 0; ii < ms.size() && !st; ++ii) {
-    const size_t i = order[ii];
-    dmcx_ctx *m = ms[i];
-    const size_t off = top->is_group() ? top->sub_off[i] : 0;
-    const hipStream_t keep = m->stream;
-    m->stream = m->own;
-    st = enqueue_step(m, true, acc ? acc + off * top->ne : nullptr, acc_ss, top->ne,
-                      elog ? elog + off : nullptr, elog_ss, nullptr, nullptr);
-    m->stream = keep;
-    if (st) top->err = m->err;
-    if (!st && ii > 0 && (hipEventRecord(top->cap_ev[ii], m->own) != hipSuccess ||
-                          hipStreamWaitEvent(s0, top->cap_ev[ii], 0) != hipSuccess))
+  for (size_t k = 0; k < ncl && !st; ++k) {
+    st = enqueue_class_step(top, ms, top->classes[k], true, cls_stream(k), acc, elog, -1);
+    if (!st && k > 0 && (hipEventRecord(top->cap_ev[k], cls_stream(k)) != hipSuccess ||
+                         hipStreamWaitEvent(s0, top->cap_ev[k], 0) != hipSuccess))
       st = fail(top, DMCX_E_HIP, "capture: join");
   }
   hipGraph_t g = nullptr;
@@ -1359,14 +1501,15 @@ dmcx_status run_impl(dmcx_ctx *top, int mode, int n_steps, double e_trial, uint8
   }
   for (dmcx_ctx *m : ms)
     if ((st = ensure_own_stream(m))) { top->err = m->err; return st; }
-  if ((st = ensure_events(top, top->fj, 2 + ms.size(), false))) return st;
+  if ((st = build_classes(top, ms)) || (st = upload_classes(top, ms, acc))) return st;
+  if ((st = ensure_events(top, top->fj, 2 + top->classes.size(), false))) return st;
   HIP_TRY(top, hipEventRecord(top->fj[0], top->stream));
   if (graph) {
     uint64_t key = top->dc_version;
     for (dmcx_ctx *m : ms) key += m->dc_version;
     if (!top->gexec || top->g_acc != acc || top->g_elog != elog || top->g_version != key)
       if ((st = build_graph(top, ms, acc, elog, key))) return st;
-    const hipStream_t s0 = ms[launch_order(ms)[0]]->own;  // the capture stream
+    const hipStream_t s0 = ms[top->classes[0].members[0]]->own;  // the capture stream
     HIP_TRY(top, hipStreamWaitEvent(s0, top->fj[0], 0));
     for (int s = 0; s < n_steps; ++s) HIP_TRY(top, hipGraphLaunch(top->gexec, s0));
     HIP_TRY(top, hipEventRecord(top->fj[1], s0));
@@ -1377,34 +1520,28 @@ dmcx_status run_impl(dmcx_ctx *top, int mode, int n_steps, double e_trial, uint8
       m->version++;
     }
   } else {
-    // several systems, eager: each on its own stream, joined into the caller's.
-    // Streams share a few hardware queues, so the steps are enqueued step by
-    // step across systems (a system's whole run enqueued at once would hold
-    // up every system behind it on its queue).
-    const std::vector<size_t> order = launch_order(ms);
-    for (dmcx_ctx *m : ms) {
-      HIP_TRY(top, hipStreamWaitEvent(m->own, top->fj[0], 0));
+    // several systems, eager: one stream per sweep class, joined into the
+    // caller's.  Streams share a few hardware queues, so the steps are
+    // enqueued step by step across classes (a class's whole run enqueued at
+    // once would hold up every class behind it on its queue).
+    const size_t ncl = top->classes.size();
+    auto cls_stream = [&](size_t k) { return ms[top->classes[k].members[0]]->own; };
+    for (size_t k = 0; k < ncl; ++k) HIP_TRY(top, hipStreamWaitEvent(cls_stream(k), top->fj[0], 0));
+    for (dmcx_ctx *m : ms)
       if ((st = ensure_events(m, m->ev, 2 * (size_t)n_steps, true))) { top->err = m->err; return st; }
+    for (int s = 0; s < n_steps; ++s) {
+      for (size_t k = 0; k < ncl; ++k)
+        if ((st = enqueue_class_step(top, ms, top->classes[k], false, cls_stream(k), acc, elog, s)))
+          return st;
+      for (dmcx_ctx *m : ms) m->step++;
     }
-    for (int s = 0; s < n_steps; ++s)
-      for (size_t ii = 0; ii < ms.size(); ++ii) {
-        const size_t i = order[ii];
-        dmcx_ctx *m = ms[i];
-        const size_t off = top->sub_off[i];
-        const hipStream_t keep = m->stream;
-        m->stream = m->own;
-        st = enqueue_step(m, false, acc ? acc + off * top->ne : nullptr, acc_ss, top->ne,
-                          elog ? elog + off : nullptr, elog_ss, m->ev[2 * s], m->ev[2 * s + 1]);
-        m->stream = keep;
-        m->step++;
-        if (st) { top->err = m->err; return st; }
-      }
-    for (size_t i = 0; i < ms.size(); ++i) {
-      dmcx_ctx *m = ms[i];
+    for (dmcx_ctx *m : ms) {
       m->n_timed = n_steps;
       m->version++;
-      HIP_TRY(top, hipEventRecord(top->fj[1 + i], m->own));
-      HIP_TRY(top, hipStreamWaitEvent(top->stream, top->fj[1 + i], 0));
+    }
+    for (size_t k = 0; k < ncl; ++k) {
+      HIP_TRY(top, hipEventRecord(top->fj[1 + k], cls_stream(k)));
+      HIP_TRY(top, hipStreamWaitEvent(top->stream, top->fj[1 + k], 0));
     }
   }
   top->step = ms[0]->step;

@@ -60,6 +60,24 @@ void NobLaunch<T>::sweep(int nob, const DevCtx &c, uint8_t *acc, long long acc_s
 }
 
 template <typename T>
+void NobLaunch<T>::sweep_multi(int nob, const DevCtx *cs, const int2 *tiles, int ntiles,
+                               const SweepLog *logs, size_t lds, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+#define DMCX_CALL(N)                                                                   \
+  if (allow_lds(k_sweep_w4_multi<T, N>, lds) == hipSuccess) \
+  k_sweep_w4_multi<T, N><<<dim3(ntiles), dim3(NT_TILE), lds, s>>>(cs, tiles, logs)
+    DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+  } else {
+#define DMCX_CALL(N)                                                                   \
+  if (allow_lds(k_sweep_multi<T, N>, lds) == hipSuccess) \
+  k_sweep_multi<T, N><<<dim3(ntiles), dim3(NT_TILE), lds, s>>>(cs, tiles, logs)
+    DMCX_NOB_SWITCH(nob, DMCX_CALL)
+#undef DMCX_CALL
+  }
+}
+
+template <typename T>
 size_t NobLaunch<T>::sweep_lds(int nob) {
   hipFuncAttributes a{};
   if constexpr (sizeof(T) == 4) {

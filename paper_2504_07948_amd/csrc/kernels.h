@@ -1413,7 +1413,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // accepted move applies T += g_i q^T and keeps the new R_d^s and S.
 template <typename T, int NOB, bool MSD, int KS = stage_ksteps(NOB)>
 __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
-                                           long long acc_step_stride, int acc_w_stride) {
+                                           long long acc_step_stride, int acc_w_stride,
+                                           int tile) {
   constexpr int NP = NOB * 16;
   constexpr int FM = 4 * KS;
   extern __shared__ __align__(16) char smem_basis[];
@@ -1431,7 +1432,7 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
   __shared__ double s_S[TW], s_C0[TW];
   const int tid = threadIdx.x;
   const int ws = wave_id(), t = tid & 63;  // one wave per walker
-  const int w = blockIdx.x * TW + ws;
+  const int w = tile * TW + ws;
   double *Rw = c.R + (size_t)w * c.ne * 3;
   T *Gb = (T *)c.Gb + blk_off(c, w);
   const double tau = c.tau, sqt = sqrt(c.tau);
@@ -1659,7 +1660,7 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
     n_accepted += (unsigned)accepted;
     PHASE_MARK(4);
     // ---- P5: block end -> rank-k flush of the full inverse
-    if (m == kb - 1) flush_block<T, NOB>(c, blockIdx.x * TW, sp, kb);
+    if (m == kb - 1) flush_block<T, NOB>(c, tile * TW, sp, kb);
     PHASE_MARK(5);
     __syncthreads();
     PHASE_MARK(6);
@@ -1677,21 +1678,59 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
 template <typename T, int NOB>
 DMCX_TILE_KERNEL void k_sweep(DevCtx c, uint8_t *acc_log,
                                                     long long acc_step_stride, int acc_w_stride) {
-  sweep_body<T, NOB, false>(c, acc_log, acc_step_stride, acc_w_stride);
+  sweep_body<T, NOB, false>(c, acc_log, acc_step_stride, acc_w_stride, blockIdx.x);
 }
 
 // The FP32 single-determinant sweep (two workgroups per CU).
 template <typename T, int NOB>
 DMCX_TILE_KERNEL_W4 void k_sweep_w4(DevCtx c, uint8_t *acc_log, long long acc_step_stride,
                                     int acc_w_stride) {
-  sweep_body<T, NOB, false, stage_ksteps_w4(NOB)>(c, acc_log, acc_step_stride, acc_w_stride);
+  sweep_body<T, NOB, false, stage_ksteps_w4(NOB)>(c, acc_log, acc_step_stride, acc_w_stride,
+                                                   blockIdx.x);
 }
 
 // The same sweep for a multideterminant trial function (table method).
 template <typename T, int NOB>
 DMCX_TILE_KERNEL void k_sweep_msd(DevCtx c, uint8_t *acc_log,
                                                         long long acc_step_stride, int acc_w_stride) {
-  sweep_body<T, NOB, true>(c, acc_log, acc_step_stride, acc_w_stride);
+  sweep_body<T, NOB, true>(c, acc_log, acc_step_stride, acc_w_stride, blockIdx.x);
+}
+
+// Several systems of one orbital-tile width in one launch (a group): tile t
+// of the launch is walker tile tiles[t].y of system tiles[t].x, and runs
+// exactly as that system's own sweep runs it.  The host lists the tiles of
+// the costliest system first, so they are dispatched first.
+struct SweepLog {
+  uint8_t *acc;       // accept log of the system (may be null)
+  long long step_ss;  // its stride between steps
+  int walker_ss;      // and between walkers
+};
+template <typename T, int NOB, bool MSD, int KS>
+__device__ __forceinline__ void sweep_multi(const DevCtx *__restrict__ cs,
+                                            const int2 *__restrict__ tiles,
+                                            const SweepLog *__restrict__ logs) {
+  const int2 tl = tiles[blockIdx.x];
+  const int sys = __builtin_amdgcn_readfirstlane(tl.x);
+  const int tile = __builtin_amdgcn_readfirstlane(tl.y);
+  const SweepLog lg = logs[sys];
+  sweep_body<T, NOB, MSD, KS>(cs[sys], lg.acc, lg.step_ss, lg.walker_ss, tile);
+}
+template <typename T, int NOB>
+DMCX_TILE_KERNEL void k_sweep_multi(const DevCtx *__restrict__ cs, const int2 *__restrict__ tiles,
+                                    const SweepLog *__restrict__ logs) {
+  sweep_multi<T, NOB, false, stage_ksteps(NOB)>(cs, tiles, logs);
+}
+template <typename T, int NOB>
+DMCX_TILE_KERNEL_W4 void k_sweep_w4_multi(const DevCtx *__restrict__ cs,
+                                          const int2 *__restrict__ tiles,
+                                          const SweepLog *__restrict__ logs) {
+  sweep_multi<T, NOB, false, stage_ksteps_w4(NOB)>(cs, tiles, logs);
+}
+template <typename T, int NOB>
+DMCX_TILE_KERNEL void k_sweep_msd_multi(const DevCtx *__restrict__ cs,
+                                        const int2 *__restrict__ tiles,
+                                        const SweepLog *__restrict__ logs) {
+  sweep_multi<T, NOB, true, stage_ksteps(NOB)>(cs, tiles, logs);
 }
 
 

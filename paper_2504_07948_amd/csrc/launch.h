@@ -34,6 +34,9 @@ struct NobLaunch {
                     size_t lds, hipStream_t s);
   // static LDS bytes of that sweep kernel
   static size_t sweep_lds(int nob);
+  // one sweep over the tiles of several systems of this width (a group)
+  static void sweep_multi(int nob, const DevCtx *cs, const int2 *tiles, int ntiles,
+                          const SweepLog *logs, size_t lds, hipStream_t s);
   // per-tile determinant part of the ion derivatives
   static void ion_grad_det(int nob, const DevCtx &c, double *partial, int ntile, size_t lds,
                            hipStream_t s);

@@ -131,6 +131,8 @@ struct MsdLaunch {
   static void sweep(int nob, const DevCtx &c, uint8_t *acc, long long acc_ss, int acc_ws,
                     size_t lds, hipStream_t s);
   static size_t sweep_lds(int nob);
+  static void sweep_multi(int nob, const DevCtx *cs, const int2 *tiles, int ntiles,
+                          const SweepLog *logs, size_t lds, hipStream_t s);
 };
 
 }  // namespace dmcx
