@@ -470,14 +470,23 @@ __global__ void k_esc_reset(int *count) {
 dmcx_status launch_local_energy(dmcx_ctx *c, int measure_only, double *e_log = nullptr,
                                 long long elog_ss = 0) {
   if (!c->mixed) {
-    hipLaunchKernelGGL(k_local_energy<double>, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc,
-                       measure_only, e_log, elog_ss, (const double *)nullptr, EscList{});
+    if (c->dc.M.on)
+      hipLaunchKernelGGL((k_local_energy<double, 1024>), dim3(c->Wpad), dim3(1024), 0, c->stream,
+                         c->dc, measure_only, e_log, elog_ss, (const double *)nullptr, EscList{});
+    else
+      hipLaunchKernelGGL(k_local_energy<double>, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc,
+                         measure_only, e_log, elog_ss, (const double *)nullptr, EscList{});
     return hip_check(c, hipGetLastError(), "k_local_energy launch");
   }
   EscList esc{};
   if (c->fp64e) {
     esc = EscList{1, c->d_esc_count, c->d_esc_list, c->d_esc_gl, ESC_CAP};
     hipLaunchKernelGGL(k_esc_reset, dim3(1), dim3(64), 0, c->stream, c->d_esc_count);
+  }
+  if (c->dc.M.on) {
+    hipLaunchKernelGGL((k_local_energy<float, 1024>), dim3(c->Wpad), dim3(1024), 0, c->stream,
+                       c->dc, measure_only, e_log, elog_ss, (const double *)nullptr, esc);
+    return hip_check(c, hipGetLastError(), "k_local_energy launch");
   }
   hipLaunchKernelGGL(k_local_energy<float>, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc,
                      measure_only, e_log, elog_ss, (const double *)c->d_G64, esc);
@@ -1947,10 +1956,36 @@ dmcx_status dmcx_forces(dmcx_ctx *c, double *F, dmcx_mem mem) {
   if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
   dmcx_status st;
   if (c->is_group()) {
-    for (size_t i = 0; i < c->subs.size(); ++i) {
-      dmcx_ctx *m = c->subs[i];
-      if ((st = dmcx_forces(m, F + i * (size_t)c->n_atom * 3, mem))) return c->err = m->err, st;
+    // the systems' force computations are independent: each runs on its own
+    // stream (costliest first), joined back into the group's stream
+    const std::vector<dmcx_ctx *> &ms = c->subs;
+    for (dmcx_ctx *m : ms)
+      if ((st = ensure_own_stream(m))) return c->err = m->err, st;
+    if ((st = ensure_events(c, c->fj, 2 + ms.size(), false))) return st;
+    HIP_TRY(c, hipEventRecord(c->fj[0], c->stream));
+    for (size_t i : launch_order(ms)) {
+      dmcx_ctx *m = ms[i];
+      HIP_TRY(c, hipStreamWaitEvent(m->own, c->fj[0], 0));
+      const hipStream_t keep = m->stream;
+      m->stream = m->own;
+      st = compute_ion_grads(m);
+      if (!st) {
+        double *dst = mem == DMCX_DEVICE ? F + i * (size_t)c->n_atom * 3 : m->d_red;
+        hipLaunchKernelGGL(k_force_estimator, dim3(m->n_atom * 3), dim3(256), 0, m->own, m->dc,
+                           m->d_dl, m->d_dv, dst);
+        st = hip_check(m, hipGetLastError(), "k_force_estimator launch");
+      }
+      if (!st && (hipEventRecord(c->fj[1 + i], m->own) != hipSuccess ||
+                  hipStreamWaitEvent(c->stream, c->fj[1 + i], 0) != hipSuccess))
+        st = fail(m, DMCX_E_HIP, "force join");
+      m->stream = keep;
+      if (st) return c->err = m->err, st;
     }
+    if (mem == DMCX_HOST)
+      for (size_t i = 0; i < ms.size(); ++i)
+        if ((st = copy_out(c, F + i * (size_t)c->n_atom * 3, ms[i]->d_red,
+                           (size_t)ms[i]->n_atom * 3 * sizeof(double), mem)))
+          return st;
     return DMCX_OK;
   }
   if ((st = compute_ion_grads(c))) return st;

@@ -929,15 +929,18 @@ struct EscList {
 // of a step in the run state's mode: DMC updates the log-weight
 // (log w += -tau ((E_old + E_new)/2 - E_T)); e_log (may be null) receives
 // E_L in row s_in_run of a table with row stride elog_stride.
-template <typename T>
-__global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int measure_only, double *e_log,
-                                                           long long elog_stride, const double *G64,
-                                                           EscList esc) {
+// NTE threads per walker (one wave per electron at a time): 256, or 1024 for
+// multideterminant systems, whose per-electron work runs over the
+// determinant list.
+template <typename T, int NTE = NT_AUX>
+__global__ __launch_bounds__(NTE) void k_local_energy(DevCtx c, int measure_only, double *e_log,
+                                                      long long elog_stride, const double *G64,
+                                                      EscList esc) {
   const int mode = measure_only ? -1 : c.run->mode;
   const double e_trial = c.run->e_trial;
   double *e_log_row = (e_log && !measure_only) ? e_log + c.run->s_in_run * elog_stride : nullptr;
-  __shared__ double part[NT_AUX / 64][4];
-  __shared__ double msx_le[NT_AUX / 64][4 * MSD_NV_MAX];  // MSD: w (3 rows) and y per wave
+  __shared__ double part[NTE / 64][4];
+  __shared__ double msx_le[NTE / 64][4 * MSD_NV_MAX];  // MSD: w (3 rows) and y per wave
   int w = blockIdx.x;
   if (esc.mode == 2) {
     if ((int)blockIdx.x >= *esc.count) return;  // whole block
@@ -948,7 +951,7 @@ __global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int measure_o
   const int NP = c.NP;
   const double *Rw = c.R + (size_t)w * c.ne * 3;
   double kin = 0.0, pot = 0.0, jv = 0.0, bound = 0.0;
-  for (int i = wid; i < c.ne; i += NT_AUX / 64) {
+  for (int i = wid; i < c.ne; i += NTE / 64) {
     const int sp = i < c.n_up ? 0 : 1, ii = i - sp * c.n_up;
     const T *row = (const T *)c.vglc + vglc_off(c, w, i);
     const T *gcol = (const T *)c.GT + gt_off(c, w, sp) + (size_t)ii * NP;
@@ -1087,7 +1090,7 @@ __global__ __launch_bounds__(NT_AUX) void k_local_energy(DevCtx c, int measure_o
   __syncthreads();
   if (tid == 0) {
     double K = 0.0, V = 0.0, J = 0.0, Bd = 0.0;
-    for (int q = 0; q < NT_AUX / 64; ++q) {
+    for (int q = 0; q < NTE / 64; ++q) {
       K += part[q][0]; V += part[q][1]; J += part[q][2]; Bd += part[q][3];
     }
     const double e = -0.5 * K + V + c.v_nn;
