@@ -68,6 +68,9 @@ def _load():
         lib.orc_move_draws.restype = None
         lib.orc_run.argtypes = [P, C.c_int32, P, P, P, C.c_int64, C.c_int32, C.c_int32,
                                 C.c_double, C.c_uint64, C.c_double, C.c_int32, P, P, C.c_int32]
+        lib.orc_run_feedback.argtypes = [P, C.c_int32, P, P, P, C.c_int64, C.c_int32, C.c_double,
+                                         C.c_uint64, C.c_double, C.c_double, C.c_int32, P, P, P,
+                                         P, C.c_int32]
         lib.orc_ion_grads.argtypes = [P, P, P, P]
         lib.orc_ion_grads_batch.argtypes = [P, C.c_int32, P, P, P, C.c_int32]
         lib.orc_evaluate_batch.argtypes = [P, C.c_int32, P, P, P, P, C.c_int32]
@@ -217,6 +220,27 @@ def run(sys, R, log_w=None, step0=0, n_steps=1, mode=1, tau=0.01, seed=1, e_tria
     rc = _load().orc_run(o.ref, W, _ptr(R), _ptr(lw), _ptr(el), step0, n_steps, mode, tau, seed,
                          e_trial, walker_offset, _ptr(acc), _ptr(elog), n_threads)
     return dict(R=R, log_w=lw, e_local=el, accept_log=acc, e_log=elog, rc=rc)
+
+
+def run_feedback(sys, R, log_w=None, step0=0, n_steps=1, tau=0.01, seed=1, e_trial=0.0, gain=0.5,
+                 walker_offset=0, n_threads=0):
+    """DMC steps with E_T fed back from the population after every step (see
+    orc_run_feedback).  Returns dict(R, log_w, e_local, accept_log, e_log,
+    et_log[n_steps] (the E_T each step used), e_trial (the next one))."""
+    o = _osys(sys)
+    R = np.array(R, dtype=np.float64, copy=True, order="C")
+    W = R.shape[0]
+    lw = np.zeros(W) if log_w is None else np.array(log_w, dtype=np.float64, copy=True)
+    el = np.zeros(W)
+    acc = np.zeros((n_steps, W, o.n_elec), dtype=np.uint8)
+    elog = np.zeros((n_steps, W))
+    etlog = np.zeros(n_steps)
+    et = C.c_double()
+    rc = _load().orc_run_feedback(o.ref, W, _ptr(R), _ptr(lw), _ptr(el), step0, n_steps, tau,
+                                  seed, e_trial, gain, walker_offset, _ptr(acc), _ptr(elog),
+                                  _ptr(etlog), C.byref(et), n_threads)
+    return dict(R=R, log_w=lw, e_local=el, accept_log=acc, e_log=elog, et_log=etlog,
+                e_trial=float(et.value), rc=rc)
 
 
 def ion_grads(sys, R):

@@ -519,6 +519,49 @@ int orc_run(const orc_system *s, int32_t W, double *R, double *log_w, double *e_
   return rc;
 }
 
+/* ---------------------------------------------------- E_T feedback --- */
+/* DMC steps with the trial energy of the projection (Eq. 1) fed back from
+ * the population after every step (population control; the paper leaves E_T
+ * open):  E_T <- <E_L>_w - (gain / tau) ln(W_tot / W),
+ * <E_L>_w = sum_w omega_w E_w / sum_w omega_w, W_tot = sum_w exp(log w_w),
+ * omega_w = exp(log w_w - m), m the largest log w, over the walkers whose
+ * log w and E_L are finite (E_T unchanged if there is none).  Each step is
+ * one orc_run step of every walker; et_log[s] (may be NULL) receives the E_T
+ * that step s used, *e_trial_out the one the next step would use. */
+int orc_run_feedback(const orc_system *s, int32_t W, double *R, double *log_w, double *e_local,
+                     int64_t step0, int32_t n_steps, double tau, uint64_t seed, double e_trial,
+                     double gain, int32_t walker_offset, uint8_t *accept_log, double *e_log,
+                     double *et_log, double *e_trial_out, int32_t n_threads) {
+  const int ne = s->n_up + s->n_dn;
+  int rc = 0;
+  double et = e_trial;
+  for (int st = 0; st < n_steps; ++st) {
+    if (et_log) et_log[st] = et;
+    rc |= orc_run(s, W, R, log_w, e_local, step0 + st, 1, 1, tau, seed, et, walker_offset,
+                  accept_log ? accept_log + (size_t)st * W * ne : NULL,
+                  e_log ? e_log + (size_t)st * W : NULL, n_threads);
+    double m = -INFINITY;
+    int any = 0;
+    for (int w = 0; w < W; ++w)
+      if (isfinite(log_w[w]) && isfinite(e_local[w])) {
+        if (log_w[w] > m) m = log_w[w];
+        any = 1;
+      }
+    if (!any) continue;
+    double s0 = 0.0, s1 = 0.0;
+    for (int w = 0; w < W; ++w)
+      if (isfinite(log_w[w]) && isfinite(e_local[w])) {
+        const double om = exp(log_w[w] - m);
+        s0 += om;
+        s1 += om * e_local[w];
+      }
+    const double ln_wtot = m + log(s0);
+    et = s1 / s0 - gain / tau * (ln_wtot - log((double)W));
+  }
+  if (e_trial_out) *e_trial_out = et;
+  return rc;
+}
+
 /* ---------------------------------------------------------- ion grads --- */
 /* d ln|D_sigma| / dR_{a,x} = tr(G B), B_ij = dA_ij/dR_{a,x}
  *                          = -sum_{l on atom a} C_lj dPhi_l/dx (r_i)   (Eq. 3)

@@ -128,6 +128,13 @@ int orc_reconfigure(int32_t W, const double *log_w, double u, int32_t *copies, i
                     int32_t *n_pairs, double *log_wbar);
 
 
+/* DMC steps with E_T fed back from the population after every step:
+ * E_T <- <E_L>_w - (gain / tau) ln(sum_w exp(log w) / W) (see oracle.c). */
+int orc_run_feedback(const orc_system *s, int32_t W, double *R, double *log_w, double *e_local,
+                     int64_t step0, int32_t n_steps, double tau, uint64_t seed, double e_trial,
+                     double gain, int32_t walker_offset, uint8_t *accept_log, double *e_log,
+                     double *et_log, double *e_trial_out, int32_t n_threads);
+
 /* Derivative of the local energy (Single Determinant QMC Forces, Eq. 4) and
  * of ln|Psi| (Eq. 3) along a direction of the ions (dion [n_atom][3]) and
  * electrons (del [ne][3]); single determinant only (4 otherwise). */

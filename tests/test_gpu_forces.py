@@ -175,3 +175,41 @@ def test_large_system_ion_grads_vs_richardson_fd():
         np.testing.assert_allclose(dv[:, a, x], fd_v, rtol=1e-6, atol=1e-6)
     ctx.set_ions(base)
     print(f"[forces] 64-atom FD: worst rel deviation of d ln|Psi|/dR {worst:.2e}", flush=True)
+
+
+def test_mixed_force_estimator_against_oracle_runs():
+    """F_mixed = 2 F_DMC - F_VMC (the paper's mixed estimator in its force
+    comparison): F_DMC from a DMC-weighted population, F_VMC from a VMC
+    population of the same start (equal weights), each the Hellmann-Feynman +
+    Pulay estimate of dmcx_forces.  The oracle runs the same chains (accept
+    sequences bit-exact); its per-walker ion derivatives (forward mode, Eq. 3)
+    and energies at the final configurations, combined by the estimator's
+    definition with its log-weights, give the reference at 1e-10."""
+    s = synth.small_molecule()
+    W, steps = 32, 4
+    R = synth.make_walkers(s, W, 560)
+    _, _, e0, _ = oracle.evaluate_batch(s, R)
+    e_t = float(np.mean(e0))
+    F = {}
+    for mode in (dmcx.DMCX_DMC, dmcx.DMCX_VMC):
+        ctx = dmcx.Context(s, W, delay_rank=1, recompute_period=4, seed=23)
+        ctx.set_walkers(R)
+        acc, _ = ctx.run(steps, mode=mode, e_trial=e_t, logs=True)
+        ref = oracle.run(s, R, n_steps=steps, mode=mode, tau=0.01, seed=23, e_trial=e_t)
+        np.testing.assert_array_equal(acc, ref["accept_log"])
+        dl_o, dv_o, _ = oracle.ion_grads_batch(s, ref["R"])
+        _, _, e_o, _ = oracle.evaluate_batch(s, ref["R"])
+        lw = ref["log_w"] if mode == dmcx.DMCX_DMC else np.zeros(W)
+        om = np.exp(lw - lw.max())
+        om /= om.sum()
+        mean = lambda x: np.einsum("w,w...->...", om, x)
+        F_ref = -mean(dv_o) - 2 * (mean(e_o[:, None, None] * dl_o) - mean(e_o) * mean(dl_o))
+        # the estimator subtracts terms of size <|E_L| |dlnPsi|>: the bar scales with them
+        terms = np.abs(mean(np.abs(dv_o))) + 2 * mean(np.abs(e_o)[:, None, None] * np.abs(dl_o))
+        F[mode] = (ctx.forces(), F_ref, terms)
+        ctx.close()
+    mixed = 2 * F[dmcx.DMCX_DMC][0] - F[dmcx.DMCX_VMC][0]
+    mixed_ref = 2 * F[dmcx.DMCX_DMC][1] - F[dmcx.DMCX_VMC][1]
+    bar = 1e-10 * np.maximum(2 * F[dmcx.DMCX_DMC][2] + F[dmcx.DMCX_VMC][2], 1.0)
+    print(f"[forces] mixed estimator max |dF| {np.abs(mixed - mixed_ref).max():.3e}", flush=True)
+    assert np.all(np.abs(mixed - mixed_ref) <= bar)

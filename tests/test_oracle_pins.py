@@ -419,3 +419,39 @@ def test_msd_direct_reference_and_single_excitation():
     cols = [0, 5, 2]
     ratio = np.linalg.det(A[:, cols]) / np.linalg.det(A[:, :3])
     assert abs(oracle.msd_ratio_direct(s2, R) - (1.0 + 0.3 * ratio)) < 1e-11
+
+
+@pytest.mark.parametrize("gain", [0.3, 1.0])
+def test_et_feedback_zero_variance_closed_form(gain):
+    """E_T feedback on the exact hydrogen-like wavefunction, where E_L = -Z^2/2
+    at every point: every walker's log-weight changes by -tau (E - E_T) per
+    step, W_tot = W exp(log w), so the feedback E_T = E - (gain / tau) log w
+    gives, from log w = 0 and E_T = E + delta, log w after step s (s >= 1)
+    equal to tau delta (1 - gain)^(s - 1) for every walker."""
+    Z = 1.6
+    s = _one_electron_system(0, 0, 0.0, Z=Z, jen_a=-Z, jen_b=0.0)
+    W, n, tau, delta = 6, 7, 0.02, 0.4
+    R = np.random.default_rng(3).standard_normal((W, 1, 3))
+    E = -Z * Z / 2.0
+    lw = np.zeros(W)
+    for k in range(1, n + 1):
+        out = oracle.run_feedback(s, R, log_w=np.zeros(W), n_steps=k, tau=tau, seed=5,
+                                  e_trial=E + delta, gain=gain)
+        assert out["rc"] == 0
+        np.testing.assert_allclose(out["e_local"], E, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(out["log_w"], tau * delta * (1 - gain) ** (k - 1),
+                                   rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(out["et_log"][0], E + delta, rtol=0, atol=0)
+
+
+def test_et_feedback_first_step_is_plain_dmc():
+    """The first step uses the E_T it is given: one step with feedback equals
+    one plain DMC step at that E_T bit for bit."""
+    s = synth.small_molecule()
+    R = synth.make_walkers(s, 5, 81)
+    a = oracle.run(s, R, n_steps=1, mode=1, tau=0.01, seed=9, e_trial=-7.0)
+    b = oracle.run_feedback(s, R, n_steps=1, tau=0.01, seed=9, e_trial=-7.0, gain=0.7)
+    np.testing.assert_array_equal(a["accept_log"], b["accept_log"])
+    np.testing.assert_array_equal(a["log_w"], b["log_w"])
+    np.testing.assert_array_equal(a["R"], b["R"])
+    assert b["et_log"][0] == -7.0
