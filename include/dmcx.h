@@ -348,6 +348,20 @@ dmcx_status dmcx_estimators_noalloc(int32_t n_walkers, const double *log_w, cons
  * other forms.  Synchronises the context's stream. */
 dmcx_status dmcx_energy_escalations(dmcx_ctx *ctx, int32_t *n);
 
+/* Passage: QMC section, Eq. 1 (the trial energy E_T of the projection) and
+ * the population control its weights need (not fixed by the paper).
+ * E_T feedback for the DMC steps of later dmcx_run calls: after every step
+ * each system's E_T becomes <E_L>_w - (gain / tau) ln(W_tot / W), with
+ * <E_L>_w the weighted mean local energy, W_tot = sum_w exp(log w_w) over the
+ * walkers counted by dmcx_estimators and W the walker count (FP64,
+ * log-sum-exp; unchanged when no walker counts).  dmcx_run's e_trial is the
+ * E_T of the first step.  gain < 0 switches it off (E_T held fixed, the
+ * default).  Errors: DMCX_E_INVALID (non-finite gain). */
+dmcx_status dmcx_set_et_feedback(dmcx_ctx *ctx, double gain);
+/* E_T the next step would use, per system: e_trial[n_sys] (host).
+ * Synchronises the context's stream. */
+dmcx_status dmcx_get_trial_energy(dmcx_ctx *ctx, double *e_trial);
+
 /* Per-walker status bits [W]: 1 = non-finite value, 2 = singular matrix
  * (a zero pivot of A of Eq. 3 in the FP64 recompute).  Bits stay set until
  * the next dmcx_set_walkers. */

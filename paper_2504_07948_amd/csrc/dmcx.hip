@@ -51,6 +51,7 @@ struct dmcx_ctx {
   int W = 0, Wpad = 0, ne = 0, n_up = 0, n_dn = 0, n_atom = 0, NP = 0, NOB = 0, K = 1, P = 1;
   int n_basis = 0;
   bool mixed = false;  // FP32 working precision (mixed path)
+  double fb_gain = -1.0;  // E_T feedback gain after every DMC step (< 0: E_T held fixed)
   // mixed form with its energy in FP64: every step ends with FP64 value rows,
   // an FP64 inverse and E_L from that inverse (single-determinant systems)
   bool fp64e = false;
@@ -498,6 +499,18 @@ dmcx_status launch_local_energy(dmcx_ctx *c, int measure_only, double *e_log = n
   hipLaunchKernelGGL(k_local_energy<float>, dim3(c->Wpad), dim3(NT_AUX), 0, c->stream, c->dc,
                      measure_only, e_log, elog_ss, (const double *)c->d_G64, esc);
   return hip_check(c, hipGetLastError(), "k_local_energy launch");
+}
+
+// E_T feedback after a step's energies and weights (when switched on).
+dmcx_status launch_et_feedback(dmcx_ctx *c) {
+  if (c->fb_gain < 0.0) return DMCX_OK;
+  const int nblk = est_blocks(c->W);
+  const EstIn<unsigned> in{c->W, c->dc.logw, c->dc.eloc, c->dc.flags, nullptr, nullptr};
+  hipLaunchKernelGGL(k_est_partial<unsigned>, dim3(nblk), dim3(EST_NB), 0, c->stream, in,
+                     c->d_est_part);
+  hipLaunchKernelGGL(k_et_feedback, dim3(1), dim3(64), 0, c->stream, nblk, c->d_est_part,
+                     c->d_run, c->fb_gain, c->opt.tau, c->W);
+  return hip_check(c, hipGetLastError(), "E_T feedback launch");
 }
 
 __global__ void k_set_run(RunState *r, unsigned long long step, int mode, double e_trial) {
@@ -1202,6 +1215,7 @@ dmcx_status enqueue_step(dmcx_ctx *c, bool graph, uint8_t *acc, long long acc_ss
     if ((st = launch_inverse(c, 0))) return st;
   }
   if ((st = launch_local_energy(c, 0, elog, elog_ss))) return st;
+  if ((st = launch_et_feedback(c))) return st;
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->d_run);
   return hip_check(c, hipGetLastError(), "k_advance launch");
 }
@@ -1427,7 +1441,8 @@ dmcx_status enqueue_class_step(dmcx_ctx *top, const std::vector<dmcx_ctx *> &ms,
       top->err = m->err;
       break;
     }
-    if ((st = launch_local_energy(m, 0, elog ? elog + off_of(i) : nullptr, elog_ss))) {
+    if ((st = launch_local_energy(m, 0, elog ? elog + off_of(i) : nullptr, elog_ss)) ||
+        (st = launch_et_feedback(m))) {
       top->err = m->err;
       break;
     }
@@ -2044,6 +2059,34 @@ dmcx_status dmcx_forces_zv(dmcx_ctx *c, int32_t warp, double *F, dmcx_mem mem) {
                      c->d_zlp, c->d_zj, dst);
   HIP_TRY(c, hipGetLastError());
   if (mem == DMCX_HOST) return copy_out(c, F, c->d_red, ncomp * sizeof(double), mem);
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_set_et_feedback(dmcx_ctx *c, double gain) {
+  if (!c || !std::isfinite(gain)) return DMCX_E_INVALID;
+  const double g = gain < 0.0 ? -1.0 : gain;
+  if (c->is_group()) {
+    for (dmcx_ctx *m : c->subs) m->fb_gain = g, m->dc_version++;
+  } else {
+    c->fb_gain = g;
+  }
+  c->dc_version++;  // the captured step changes
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_get_trial_energy(dmcx_ctx *c, double *e_trial) {
+  if (!c || !e_trial) return DMCX_E_INVALID;
+  if (c->is_group()) {
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      const dmcx_status st = dmcx_get_trial_energy(c->subs[i], e_trial + i);
+      if (st) return c->err = c->subs[i]->err, st;
+    }
+    return DMCX_OK;
+  }
+  RunState r{};
+  HIP_TRY(c, hipMemcpyAsync(&r, c->d_run, sizeof(RunState), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *e_trial = r.e_trial;
   return DMCX_OK;
 }
 

@@ -107,8 +107,7 @@ __global__ __launch_bounds__(EST_NB) void k_est_partial(EstIn<F> in, double *par
 //   9 acceptance ratio (accepted / proposed moves since the previous call;
 //   NaN when no move was proposed), 10 moves proposed.
 // With no walker counted, 1..8 are NaN.
-__global__ void k_est_final(int nblk, const double *part, double *out) {
-  if (threadIdx.x != 0) return;
+__device__ inline void est_merge(int nblk, const double *part, double *out) {
   double m = -INFINITY, lmin = INFINITY, n = 0.0, acc = 0.0, prop = 0.0;
   for (int b = 0; b < nblk; ++b) {
     const double *r = part + (size_t)b * EST_PART;
@@ -150,6 +149,21 @@ __global__ void k_est_final(int nblk, const double *part, double *out) {
   out[8] = any ? lmin : nan;
   out[9] = prop > 0.0 ? acc / prop : nan;
   out[10] = prop;
+}
+__global__ void k_est_final(int nblk, const double *part, double *out) {
+  if (threadIdx.x == 0) est_merge(nblk, part, out);
+}
+
+// E_T feedback after a DMC step (population control of the projection of
+// Eq. 1):  E_T <- <E_L>_w - (gain / tau) ln(W_tot / W), with the weighted
+// mean energy and ln W_tot = m + ln S0 from the merged block records.  Left
+// unchanged in VMC steps and when no walker counts.
+__global__ void k_et_feedback(int nblk, const double *part, RunState *run, double gain,
+                              double tau, int W) {
+  if (threadIdx.x != 0 || run->mode != 1) return;
+  double r[EST_OUT];
+  est_merge(nblk, part, r);
+  if (r[0] > 0.0) run->e_trial = r[6] - gain / tau * (r[1] + log(r[2]) - log((double)W));
 }
 
 inline int est_blocks(int W) { return (W + EST_NB - 1) / EST_NB; }

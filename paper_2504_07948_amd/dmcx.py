@@ -35,7 +35,7 @@ EXPORTED = [
     "dmcx_selftest", "dmcx_philox", "dmcx_strerror", "dmcx_last_error", "dmcx_autotune",
     "dmcx_autotune_report", "dmcx_get_delay_rank", "dmcx_reconfigure", "dmcx_estimators",
     "dmcx_zv_grads", "dmcx_forces_zv", "dmcx_estimators_noalloc",
-    "dmcx_energy_escalations",
+    "dmcx_energy_escalations", "dmcx_set_et_feedback", "dmcx_get_trial_energy",
 ]
 
 
@@ -115,6 +115,8 @@ def load():
         "dmcx_forces_zv": [P, I32, P, I32],
         "dmcx_estimators_noalloc": [I32, P, P, P, P, P, P, P],
         "dmcx_energy_escalations": [P, P],
+        "dmcx_set_et_feedback": [P, D],
+        "dmcx_get_trial_energy": [P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -466,6 +468,16 @@ class Context:
         """[n_sys][DMCX_N_ESTIMATORS] weighted estimators (see include/dmcx.h)."""
         out = np.zeros((self.n_sys, DMCX_N_ESTIMATORS))
         self.check(dmcx_estimators(self.h, _ptr(out), DMCX_HOST))
+        return out
+
+    def set_et_feedback(self, gain):
+        """E_T <- <E_L>_w - (gain/tau) ln(W_tot/W) after every DMC step (gain < 0: off)."""
+        self.check(load().dmcx_set_et_feedback(self.h, float(gain)))
+
+    def trial_energy(self):
+        """E_T the next step would use, one per system."""
+        out = np.zeros(self.n_sys)
+        self.check(load().dmcx_get_trial_energy(self.h, _ptr(out)))
         return out
 
     def energy_escalations(self):
