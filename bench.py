@@ -164,6 +164,50 @@ def mixed_leg(s, torch, dmcx, stream, args, W=4096, steps=10, P=32, k=32):
     return out
 
 
+def flush_leg(s, torch, dmcx, stream, W=2048, k=32, reps=5):
+    """The delayed-update GEMMs alone: the rank-kb flush G <- G0 - (M Z)^T U
+    (Z = Delta G0, M = (I + L)^-1) of kb = k - 1 pending moves of every walker,
+    run through the move-by-move calls (dmcx_ratio_grad / dmcx_accept, then
+    dmcx_flush launches k_flush, the same code the sweep runs at each block
+    end) and timed with events on the context's stream.  Algorithmic FLOP per
+    walker: 2 kb n^2 (Z) + kb^2 n (M Z, M lower triangular) + 2 kb n^2
+    (the update), n = electrons per spin."""
+    from paper_2504_07948_amd import synth
+    ctx = dmcx.Context(s, W, precision=dmcx.DMCX_FP64, delay_rank=k, recompute_period=64,
+                       stream=stream)
+    R0 = synth.make_walkers(s, W, 2040)
+    ctx.set_walkers(torch.from_numpy(R0).cuda())
+    rng = np.random.default_rng(2041)
+    acc = torch.ones(W, dtype=torch.uint8, device="cuda")
+    ratio = torch.empty(W, dtype=torch.float64, device="cuda")
+    grad = torch.empty((W, 3), dtype=torch.float64, device="cuda")
+    kb = k - 1
+    times = []
+    for rep in range(reps + 1):
+        for i in range(kb):
+            rn = torch.from_numpy(R0[:, i, :] + 0.05 * rng.standard_normal((W, 3))).cuda()
+            ctx.check(dmcx.dmcx_ratio_grad(ctx.h, i, rn.data_ptr(), ratio.data_ptr(),
+                                           grad.data_ptr(), dmcx.DMCX_DEVICE))
+            ctx.check(dmcx.dmcx_accept(ctx.h, i, acc.data_ptr(), dmcx.DMCX_DEVICE))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.check(dmcx.dmcx_flush(ctx.h))
+        e1.record()
+        torch.cuda.synchronize()
+        if rep:  # the first flush is a warm-up
+            times.append(e0.elapsed_time(e1))
+    n = s.n_up
+    flop = W * (4 * kb * n * n + kb * kb * n)
+    ms = float(np.mean(times))
+    ach = flop / (ms * 1e-3) / 1e12
+    ctx.close()
+    return {"walkers": W, "pending_moves": kb, "electrons_per_spin": n, "kernel": "k_flush",
+            "ms_avg": ms, "flop_per_launch": flop,
+            "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS}}
+
+
 def batch5_leg(torch, dmcx, stream, steps=5, W=512, n_det=1000, n_active=100, P=32):
     """Eight alkane stand-ins (20..200 electrons), 512 walkers each, 1000-
     determinant expansions over 100 active orbitals (table method), mixed
@@ -311,9 +355,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the FP64 leg (same as --extras none)")
-    ap.add_argument("--extras", default="mixed,forces,batch,population",
+    ap.add_argument("--extras", default="mixed,forces,batch,population,flush",
                     help="comma list of the extra legs to run after the FP64 leg: mixed, forces, "
-                         "batch (eight multideterminant alkanes), or none")
+                         "batch (eight multideterminant alkanes), population, flush (the "
+                         "delayed-update GEMMs alone), or none")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed region, run one device copy of this many MiB "
                          "(a known-size kernel for scaling FETCH_SIZE/WRITE_SIZE counters)")
@@ -367,9 +412,9 @@ def main():
     torch.cuda.synchronize()
     dt_period = time.perf_counter() - tp0
 
-    mixed = forces = batch5 = population = None
+    mixed = forces = batch5 = population = flush = None
     extras = set() if args.skip_extras else set(args.extras.split(",")) - {"none", ""}
-    unknown = extras - {"mixed", "forces", "batch", "population"}
+    unknown = extras - {"mixed", "forces", "batch", "population", "flush"}
     if unknown:
         sys.exit(f"bench.py: unknown extra legs {sorted(unknown)}")
     if "mixed" in extras:
@@ -380,6 +425,8 @@ def main():
         batch5 = batch5_leg(torch, dmcx, stream)
     if "population" in extras:
         population = population_leg(s, torch, dmcx, stream)
+    if "flush" in extras:
+        flush = flush_leg(s, torch, dmcx, stream)
 
     ne, ns = s.n_elec, max(s.n_up, s.n_dn)
     moves = W * ne * args.steps
@@ -459,6 +506,7 @@ def main():
         "forces": forces,
         "batch_multideterminant": batch5,
         "population_control": population,
+        "delayed_update_flush": flush,
         "walker_flags_nonzero": int((flags != 0).sum()),
     }
     print(json.dumps(out))
