@@ -81,6 +81,9 @@ def _load():
         lib.orc_zv_grads_batch.argtypes = [P, C.c_int32, P, C.c_int32, P, P, P, C.c_int32]
         lib.orc_basis_d3.argtypes = [P, P, P]
         lib.orc_warp_weights.argtypes = [P, P, P, P]
+        lib.orc_jastrow_param_grads.argtypes = [P, P, P, P]
+        lib.orc_jastrow_param_grads_batch.argtypes = [P, C.c_int32, P, P, P, C.c_int32]
+        lib.orc_j3_values.argtypes = [P, P, P]
         _lib = lib
     return _lib
 
@@ -377,3 +380,74 @@ def zv_force_estimator(log_w, e_local, dEL, dlogpsi, dlogjac):
     em = mean(e)
     de = e - em
     return -mean(dEL) - mean(de[:, None, None] * (2.0 * np.asarray(dlogpsi) + np.asarray(dlogjac)))
+
+
+# the Jastrow parameters whose derivatives jastrow_param_grads returns
+JASTROW_PARAMS = ("b_ee", "b_en", "c3_110", "c3_101", "c3_111", "c3_210", "c3_201", "c3_102")
+
+
+def jastrow_param_grads(sys, R):
+    """O_p = d ln Psi / dp and dE_L / dp for the eight Jastrow parameters
+    (JASTROW_PARAMS: the two Pade b, then six three-body e-e-n coefficients at
+    zero) at one configuration R [n_elec][3].  Returns (O[8], dEL[8], rc)."""
+    o = _osys(sys)
+    O = np.zeros(8)
+    D = np.zeros(8)
+    rc = _load().orc_jastrow_param_grads(o.ref, _ptr(np.ascontiguousarray(R, dtype=np.float64)),
+                                         _ptr(O), _ptr(D))
+    return O, D, rc
+
+
+def jastrow_param_grads_batch(sys, R, n_threads=0):
+    """The same for a crowd R [W][n_elec][3]: O [W][8], dEL [W][8], rc."""
+    o = _osys(sys)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    W = R.shape[0]
+    O = np.zeros((W, 8))
+    D = np.zeros((W, 8))
+    rc = _load().orc_jastrow_param_grads_batch(o.ref, W, _ptr(R), _ptr(O), _ptr(D), n_threads)
+    return O, D, rc
+
+
+def j3_values(sys, R):
+    """The six three-body sums F_k(R) = sum_A sum_{i<j} (s_iA^l s_jA^m +
+    s_iA^m s_jA^l) s_ij^n, s(r) = r / (1 + r)."""
+    o = _osys(sys)
+    F = np.zeros(6)
+    _load().orc_j3_values(o.ref, _ptr(np.ascontiguousarray(R, dtype=np.float64)), _ptr(F))
+    return F
+
+
+def linear_method(log_w, e_local, O, dEL, flags=None):
+    """Linear-method matrices of the parameter derivatives (the first step of
+    the Jastrow optimisation), over the walkers with weights
+    omega = exp(log w - max), normalised; walkers with a non-finite log w or
+    E_L, or a non-zero flag, are left out.  With <.> the weighted mean,
+    dO_k = O_k - <O_k> and the basis {Psi, dO_k Psi}:
+      S[0][0] = 1, S[0][k] = S[k][0] = 0, S[k][l] = <dO_k dO_l>,
+      H[0][0] = <E_L>, H[k][0] = <dO_k E_L>,
+      H[0][l] = <E_L dO_l> + <dE_L/dp_l>,
+      H[k][l] = <dO_k (dO_l E_L + dE_L/dp_l)>.
+    Returns (S, H), each [1 + P][1 + P]."""
+    lw = np.asarray(log_w, dtype=np.float64)
+    e = np.asarray(e_local, dtype=np.float64)
+    O = np.asarray(O, dtype=np.float64)
+    D = np.asarray(dEL, dtype=np.float64)
+    ok = np.isfinite(lw) & np.isfinite(e)
+    if flags is not None:
+        ok &= np.asarray(flags) == 0
+    P = O.shape[1]
+    S = np.zeros((1 + P, 1 + P))
+    H = np.zeros((1 + P, 1 + P))
+    om = np.exp(lw[ok] - lw[ok].max())
+    om /= om.sum()
+    e, O, D = e[ok], O[ok], D[ok]
+    mean = lambda x: np.einsum("w,w...->...", om, x)
+    dO = O - mean(O)
+    S[0, 0] = 1.0
+    S[1:, 1:] = mean(dO[:, :, None] * dO[:, None, :])
+    H[0, 0] = mean(e)
+    H[1:, 0] = mean(dO * e[:, None])
+    H[0, 1:] = mean(e[:, None] * dO) + mean(D)
+    H[1:, 1:] = mean(dO[:, :, None] * (dO[:, None, :] * e[:, None, None] + D[:, None, :]))
+    return S, H

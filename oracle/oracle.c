@@ -562,6 +562,166 @@ int orc_run_feedback(const orc_system *s, int32_t W, double *R, double *log_w, d
   return rc;
 }
 
+/* ------------------------------------------- Jastrow parameter derivatives --- */
+/* Derivatives of ln Psi and of E_L with respect to the Jastrow parameters
+ * (QMC section: the Jastrow factor of Eq. 2; its parameters are what the
+ * VMC linear-method optimisation varies).  Parameters, in order:
+ *   0  b of the electron-electron Pade terms u = a r / (1 + b r),
+ *   1  b of the electron-nucleus Pade terms,
+ *   2..7  coefficients c_k of a three-body electron-electron-nucleus term
+ *      J3 = sum_k c_k sum_A sum_{i<j} (s_iA^l s_jA^m + s_iA^m s_jA^l) s_ij^n,
+ *      s(r) = r / (1 + r), (l, m, n) = (1,1,0), (1,0,1), (1,1,1), (2,1,0),
+ *      (2,0,1), (1,0,2), entering at c = 0 (the trial function is unchanged;
+ *      these are the derivatives of a first optimisation step).
+ * With O_p = d ln Psi / dp = dJ / dp and v_i = grad_i ln|Psi|,
+ *   dE_L / dp = -1/2 sum_i [lap_i O_p + 2 v_i . grad_i O_p].
+ * dlogpsi[8] = O_p, dEL[8].  Single determinant only (4 otherwise). */
+static const int J3_LMN[6][3] = {{1, 1, 0}, {1, 0, 1}, {1, 1, 1}, {2, 1, 0}, {2, 0, 1}, {1, 0, 2}};
+
+static double ipow(double x, int k) {
+  double r = 1.0;
+  for (int q = 0; q < k; ++q) r *= x;
+  return r;
+}
+
+/* d/db of a r / (1 + b r) and its first two r-derivatives */
+static void pade_db(double a, double b, double r, double *h, double *h1, double *h2) {
+  const double q = 1.0 / (1.0 + b * r);
+  *h = -a * r * r * q * q;
+  *h1 = -2.0 * a * r * q * q * q;
+  *h2 = -2.0 * a * (1.0 - 2.0 * b * r) * q * q * q * q;
+}
+
+int orc_jastrow_param_grads(const orc_system *s, const double *R, double *dlogpsi, double *dEL) {
+  if (s->n_det > 1) return 4;
+  const int ne = s->n_up + s->n_dn, na = s->n_atom, NP8 = 8;
+  double lp, el;
+  int32_t sg;
+  double *v = (double *)malloc(sizeof(double) * 3 * ne);
+  double *go = (double *)calloc((size_t)NP8 * ne * 3, sizeof(double));  /* grad_i O_p */
+  double *lo = (double *)calloc((size_t)NP8 * ne, sizeof(double));      /* lap_i O_p */
+  int rc = orc_evaluate(s, R, &lp, &sg, &el, v);
+  for (int p = 0; p < NP8; ++p) dlogpsi[p] = 0.0;
+  for (int i = 0; i < ne; ++i) {
+    const double *ri = R + 3 * i;
+    /* electron-electron Pade b */
+    for (int j = 0; j < ne; ++j) {
+      if (j == i) continue;
+      const double d[3] = {ri[0] - R[3 * j], ri[1] - R[3 * j + 1], ri[2] - R[3 * j + 2]};
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      double h, h1, h2;
+      pade_db(ee_a(s, i, j), s->jee_b, r, &h, &h1, &h2);
+      if (j > i) dlogpsi[0] += h;
+      for (int x = 0; x < 3; ++x) go[(0 * ne + i) * 3 + x] += h1 * d[x] / r;
+      lo[0 * ne + i] += h2 + 2.0 * h1 / r;
+    }
+    /* electron-nucleus Pade b */
+    for (int A = 0; A < na; ++A) {
+      const double *c = s->ion_xyz + 3 * A;
+      const double d[3] = {ri[0] - c[0], ri[1] - c[1], ri[2] - c[2]};
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      double h, h1, h2;
+      pade_db(s->jen_a[A], s->jen_b, r, &h, &h1, &h2);
+      dlogpsi[1] += h;
+      for (int x = 0; x < 3; ++x) go[(1 * ne + i) * 3 + x] += h1 * d[x] / r;
+      lo[1 * ne + i] += h2 + 2.0 * h1 / r;
+    }
+    /* three-body terms: f(x, y, z) with x = |r_i - R_A|, y = |r_j - R_A|,
+     * z = |r_i - r_j|; electron i sees df/dx along (r_i - R_A)/x and df/dz
+     * along (r_i - r_j)/z */
+    for (int j = 0; j < ne; ++j) {
+      if (j == i) continue;
+      const double dz[3] = {ri[0] - R[3 * j], ri[1] - R[3 * j + 1], ri[2] - R[3 * j + 2]};
+      const double z = sqrt(dz[0] * dz[0] + dz[1] * dz[1] + dz[2] * dz[2]);
+      for (int A = 0; A < na; ++A) {
+        const double *c = s->ion_xyz + 3 * A;
+        const double dx[3] = {ri[0] - c[0], ri[1] - c[1], ri[2] - c[2]};
+        const double x = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+        const double y = sqrt((R[3 * j] - c[0]) * (R[3 * j] - c[0]) +
+                              (R[3 * j + 1] - c[1]) * (R[3 * j + 1] - c[1]) +
+                              (R[3 * j + 2] - c[2]) * (R[3 * j + 2] - c[2]));
+        const double sx = x / (1.0 + x), sy = y / (1.0 + y), sz = z / (1.0 + z);
+        const double sx1 = 1.0 / ((1.0 + x) * (1.0 + x)), sz1 = 1.0 / ((1.0 + z) * (1.0 + z));
+        const double sx2 = -2.0 / ((1.0 + x) * (1.0 + x) * (1.0 + x));
+        const double sz2 = -2.0 / ((1.0 + z) * (1.0 + z) * (1.0 + z));
+        double cosxz = 0.0;
+        for (int q = 0; q < 3; ++q) cosxz += dx[q] * dz[q];
+        cosxz /= x * z;
+        for (int k = 0; k < 6; ++k) {
+          const int l = J3_LMN[k][0], m = J3_LMN[k][1], n = J3_LMN[k][2];
+          /* P(sx) = sx^l sy^m + sx^m sy^l and its sx-derivatives; Q(sz) = sz^n */
+          const double P = ipow(sx, l) * ipow(sy, m) + ipow(sx, m) * ipow(sy, l);
+          const double P1 = (l ? l * ipow(sx, l - 1) * ipow(sy, m) : 0.0) +
+                            (m ? m * ipow(sx, m - 1) * ipow(sy, l) : 0.0);
+          const double P2 = (l > 1 ? l * (l - 1) * ipow(sx, l - 2) * ipow(sy, m) : 0.0) +
+                            (m > 1 ? m * (m - 1) * ipow(sx, m - 2) * ipow(sy, l) : 0.0);
+          const double Q = ipow(sz, n);
+          const double Q1 = n ? n * ipow(sz, n - 1) : 0.0;
+          const double Q2 = n > 1 ? n * (n - 1) * ipow(sz, n - 2) : 0.0;
+          if (j > i) dlogpsi[2 + k] += P * Q;
+          const double fx = P1 * sx1 * Q, fz = P * Q1 * sz1;
+          const double fxx = (P2 * sx1 * sx1 + P1 * sx2) * Q;
+          const double fzz = P * (Q2 * sz1 * sz1 + Q1 * sz2);
+          const double fxz = P1 * sx1 * Q1 * sz1;
+          for (int q = 0; q < 3; ++q) go[((2 + k) * ne + i) * 3 + q] += fx * dx[q] / x + fz * dz[q] / z;
+          lo[(2 + k) * ne + i] += fxx + fzz + 2.0 * fxz * cosxz + 2.0 * fx / x + 2.0 * fz / z;
+        }
+      }
+    }
+  }
+  for (int p = 0; p < NP8; ++p) {
+    double acc = 0.0;
+    for (int i = 0; i < ne; ++i) {
+      double vg = 0.0;
+      for (int x = 0; x < 3; ++x) vg += v[3 * i + x] * go[(p * ne + i) * 3 + x];
+      acc += lo[p * ne + i] + 2.0 * vg;
+    }
+    dEL[p] = -0.5 * acc;
+  }
+  free(v);
+  free(go);
+  free(lo);
+  return rc;
+}
+
+int orc_j3_values(const orc_system *s, const double *R, double *F) {
+  const int ne = s->n_up + s->n_dn;
+  for (int k = 0; k < 6; ++k) F[k] = 0.0;
+  for (int A = 0; A < s->n_atom; ++A)
+    for (int i = 0; i < ne; ++i)
+      for (int j = i + 1; j < ne; ++j) {
+        double x2 = 0.0, y2 = 0.0, z2 = 0.0;
+        for (int q = 0; q < 3; ++q) {
+          const double a = R[3 * i + q] - s->ion_xyz[3 * A + q];
+          const double b = R[3 * j + q] - s->ion_xyz[3 * A + q];
+          const double c = R[3 * i + q] - R[3 * j + q];
+          x2 += a * a;
+          y2 += b * b;
+          z2 += c * c;
+        }
+        const double x = sqrt(x2), y = sqrt(y2), z = sqrt(z2);
+        const double sx = x / (1.0 + x), sy = y / (1.0 + y), sz = z / (1.0 + z);
+        for (int k = 0; k < 6; ++k) {
+          const int l = J3_LMN[k][0], m = J3_LMN[k][1], n = J3_LMN[k][2];
+          F[k] += (ipow(sx, l) * ipow(sy, m) + ipow(sx, m) * ipow(sy, l)) * ipow(sz, n);
+        }
+      }
+  return 0;
+}
+
+int orc_jastrow_param_grads_batch(const orc_system *s, int32_t W, const double *R,
+                                  double *dlogpsi, double *dEL, int32_t n_threads) {
+  const int ne = s->n_up + s->n_dn;
+  int rc = 0;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(dynamic) reduction(| : rc)
+  for (int w = 0; w < W; ++w)
+    rc |= orc_jastrow_param_grads(s, R + (size_t)w * ne * 3, dlogpsi + 8 * w, dEL + 8 * w);
+  return rc;
+}
+
 /* ---------------------------------------------------------- ion grads --- */
 /* d ln|D_sigma| / dR_{a,x} = tr(G B), B_ij = dA_ij/dR_{a,x}
  *                          = -sum_{l on atom a} C_lj dPhi_l/dx (r_i)   (Eq. 3)

@@ -135,6 +135,15 @@ int orc_run_feedback(const orc_system *s, int32_t W, double *R, double *log_w, d
                      double gain, int32_t walker_offset, uint8_t *accept_log, double *e_log,
                      double *et_log, double *e_trial_out, int32_t n_threads);
 
+/* Derivatives of ln Psi and E_L with respect to the 8 Jastrow parameters
+ * (e-e Pade b, e-n Pade b, six three-body coefficients at zero; see
+ * oracle.c): dlogpsi[8], dEL[8]; the batch form [W][8] each. */
+int orc_jastrow_param_grads(const orc_system *s, const double *R, double *dlogpsi, double *dEL);
+int orc_jastrow_param_grads_batch(const orc_system *s, int32_t W, const double *R,
+                                  double *dlogpsi, double *dEL, int32_t n_threads);
+/* The six three-body basis sums F_k(R) themselves (c = 0 derivatives of J). */
+int orc_j3_values(const orc_system *s, const double *R, double *F);
+
 /* Derivative of the local energy (Single Determinant QMC Forces, Eq. 4) and
  * of ln|Psi| (Eq. 3) along a direction of the ions (dion [n_atom][3]) and
  * electrons (del [ne][3]); single determinant only (4 otherwise). */
