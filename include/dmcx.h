@@ -362,6 +362,37 @@ dmcx_status dmcx_set_et_feedback(dmcx_ctx *ctx, double gain);
  * Synchronises the context's stream. */
 dmcx_status dmcx_get_trial_energy(dmcx_ctx *ctx, double *e_trial);
 
+/* Passage: QMC section, Eq. 2 (the Jastrow factor of the trial function,
+ * whose parameters the VMC optimisation varies before the DMC projection of
+ * Eq. 1; the paper does not fix the optimiser, the linear method is the
+ * published one).
+ * Derivatives with respect to DMCX_N_JASTROW_PARAMS = 8 Jastrow parameters,
+ * in order: 0 the b of the e-e Pade terms, 1 the b of the e-n Pade terms,
+ * 2..7 the coefficients c_k of six three-body e-e-n terms
+ * sum_A sum_{i<j} (s_iA^l s_jA^m + s_iA^m s_jA^l) s_ij^n, s(r) = r / (1 + r),
+ * (l, m, n) = (1,1,0), (1,0,1), (1,1,1), (2,1,0), (2,0,1), (1,0,2), taken at
+ * c = 0 (the trial function itself has no three-body term).
+ * Per walker at the current configuration: dlogpsi[W][8] = O_p = d ln Psi/dp
+ * and dEL[W][8] = dE_L/dp = -1/2 sum_i [lap_i O_p + 2 grad_i ln|Psi| . grad_i O_p]
+ * (either may be NULL).  FP64 arithmetic; grad_i ln|Psi| comes from the
+ * context's inverse and orbital rows (FP32 in the mixed form).  Single-
+ * determinant systems only (DMCX_E_UNSUPPORTED otherwise). */
+#define DMCX_N_JASTROW_PARAMS 8
+dmcx_status dmcx_jastrow_param_grads(dmcx_ctx *ctx, double *dlogpsi, double *dEL, dmcx_mem mem);
+
+/* Passage: as dmcx_jastrow_param_grads.
+ * Linear-method matrices of each system's walkers in the basis
+ * {Psi, (O_k - <O_k>) Psi}: S[n_sys][9][9], H[n_sys][9][9] with
+ *   S[0][0] = 1, S[0][k] = S[k][0] = 0, S[k][l] = <dO_k dO_l>,
+ *   H[0][0] = <E_L>, H[k][0] = <dO_k E_L>, H[0][l] = <E_L dO_l> + <dE_L/dp_l>,
+ *   H[k][l] = <dO_k (dO_l E_L + dE_L/dp_l)>,
+ * dO_k = O_k - <O_k>, <x> = sum_w omega_w x_w / sum_w omega_w in walker
+ * order, omega = exp(log w - max log w) over the walkers with finite log w
+ * and E_L and no status flag (every entry NaN if none counts).  Solving
+ * H c = E S c for the lowest E gives the parameter update c_k / c_0.
+ * Errors as dmcx_jastrow_param_grads. */
+dmcx_status dmcx_linear_method(dmcx_ctx *ctx, double *S, double *H, dmcx_mem mem);
+
 /* Per-walker status bits [W]: 1 = non-finite value, 2 = singular matrix
  * (a zero pivot of A of Eq. 3 in the FP64 recompute).  Bits stay set until
  * the next dmcx_set_walkers. */

@@ -14,6 +14,7 @@
 #include "dmcx.h"
 #include "estimators.h"
 #include "forces_aux.h"
+#include "jparams.h"
 #include "kernels.h"
 #include "launch.h"
 #include "msd.h"
@@ -93,6 +94,10 @@ struct dmcx_ctx {
   void *d_ztp = nullptr, *d_zxt = nullptr;
   uint64_t zv_version = 0;
   int zv_warp = -1;
+  // Jastrow parameter derivatives [W][NJP] each (cached per configuration
+  // version) and the linear-method matrices S, H [2][NJP + 1][NJP + 1]
+  double *d_jo = nullptr, *d_jd = nullptr, *d_lm = nullptr;
+  uint64_t jp_version = 0;
   // weighted estimators: block records [est_blocks(W)][EST_PART], host staging [EST_OUT]
   double *d_est_part = nullptr, *d_est_out = nullptr;
   // scratch
@@ -710,6 +715,33 @@ dmcx_status compute_zv(dmcx_ctx *c, int warp) {
   HIP_TRY(c, hipGetLastError());
   c->zv_version = c->version;
   c->zv_warp = warp;
+  return DMCX_OK;
+}
+
+// Per-walker Jastrow parameter derivatives of the current configuration
+// (cached per configuration version) in d_jo / d_jd.
+dmcx_status compute_jparams(dmcx_ctx *c) {
+  if (c->dc.M.on)
+    return fail(c, DMCX_E_UNSUPPORTED,
+                "Jastrow parameter derivatives: single-determinant systems only");
+  dmcx_status st = refresh_after_moves(c);
+  if (st) return st;
+  if (c->jp_version == c->version) return DMCX_OK;
+  if (!c->d_jo && ((st = dalloc(c, &c->d_jo, (size_t)c->W * NJP)) ||
+                   (st = dalloc(c, &c->d_jd, (size_t)c->W * NJP))))
+    return st;
+  const size_t lds = (size_t)c->ne * (3 + JE) * sizeof(double);
+  if (c->mixed) {
+    HIP_TRY(c, allow_lds(k_jparam<float>, lds));
+    hipLaunchKernelGGL(k_jparam<float>, dim3(c->W), dim3(NT_AUX), lds, c->stream, c->dc, c->d_jo,
+                       c->d_jd);
+  } else {
+    HIP_TRY(c, allow_lds(k_jparam<double>, lds));
+    hipLaunchKernelGGL(k_jparam<double>, dim3(c->W), dim3(NT_AUX), lds, c->stream, c->dc,
+                       c->d_jo, c->d_jd);
+  }
+  HIP_TRY(c, hipGetLastError());
+  c->jp_version = c->version;
   return DMCX_OK;
 }
 
@@ -2060,6 +2092,48 @@ dmcx_status dmcx_forces_zv(dmcx_ctx *c, int32_t warp, double *F, dmcx_mem mem) {
   HIP_TRY(c, hipGetLastError());
   if (mem == DMCX_HOST) return copy_out(c, F, c->d_red, ncomp * sizeof(double), mem);
   return DMCX_OK;
+}
+
+dmcx_status dmcx_jastrow_param_grads(dmcx_ctx *c, double *dlogpsi, double *dEL, dmcx_mem mem) {
+  if (!c) return DMCX_E_INVALID;
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  dmcx_status st;
+  if (c->is_group()) {
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      dmcx_ctx *m = c->subs[i];
+      const size_t off = c->sub_off[i] * (size_t)NJP, bytes = (size_t)m->W * NJP * sizeof(double);
+      if ((st = compute_jparams(m)) ||
+          (dlogpsi && (st = copy_out(m, dlogpsi + off, m->d_jo, bytes, mem))) ||
+          (dEL && (st = copy_out(m, dEL + off, m->d_jd, bytes, mem))))
+        return c->err = m->err, st;
+    }
+    return DMCX_OK;
+  }
+  if ((st = compute_jparams(c))) return st;
+  const size_t bytes = (size_t)c->W * NJP * sizeof(double);
+  if (dlogpsi && (st = copy_out(c, dlogpsi, c->d_jo, bytes, mem))) return st;
+  if (dEL && (st = copy_out(c, dEL, c->d_jd, bytes, mem))) return st;
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_linear_method(dmcx_ctx *c, double *S, double *H, dmcx_mem mem) {
+  if (!c || !S || !H) return DMCX_E_INVALID;
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  constexpr size_t NM = (size_t)(NJP + 1) * (NJP + 1);
+  dmcx_status st;
+  if (c->is_group()) {
+    for (size_t i = 0; i < c->subs.size(); ++i)
+      if ((st = dmcx_linear_method(c->subs[i], S + i * NM, H + i * NM, mem)))
+        return c->err = c->subs[i]->err, st;
+    return DMCX_OK;
+  }
+  if ((st = compute_jparams(c))) return st;
+  if (!c->d_lm && (st = dalloc(c, &c->d_lm, 2 * NM))) return st;
+  hipLaunchKernelGGL(k_linear_method, dim3(1), dim3(LM_NT), 0, c->stream, c->W, c->dc.logw,
+                     c->dc.eloc, c->dc.flags, c->d_jo, c->d_jd, c->d_lm);
+  HIP_TRY(c, hipGetLastError());
+  if ((st = copy_out(c, S, c->d_lm, NM * sizeof(double), mem))) return st;
+  return copy_out(c, H, c->d_lm + NM, NM * sizeof(double), mem);
 }
 
 dmcx_status dmcx_set_et_feedback(dmcx_ctx *c, double gain) {

@@ -63,6 +63,30 @@ __device__ __forceinline__ void hmul(const double H[6], const double v[3], doubl
   o[2] = H[2] * v[0] + H[4] * v[1] + H[5] * v[2];
 }
 
+// Jastrow gradient c_i and determinant drift g_i = sum_j grad phi_j(r_i)
+// (A^{-1})_{ji} of electron i of walker w, computed by the calling 64-lane
+// wave; every lane receives o = (c_i, g_i).
+template <typename T>
+__device__ __forceinline__ void electron_cg(const DevCtx &c, const double *Rw, int w, int i,
+                                            int lane, double o[6]) {
+  const int NP = c.NP;
+  const int sp = i < c.n_up ? 0 : 1, ii = i - sp * c.n_up;
+  const T *row = (const T *)c.vglc + vglc_off(c, w, i);
+  const T *gcol = (const T *)c.GT + gt_off(c, w, sp) + (size_t)ii * NP;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int j = lane; j < NP; j += 64) {
+    const double gj = (double)gcol[j];
+    g0 += (double)row[NP + j] * gj;
+    g1 += (double)row[2 * NP + j] * gj;
+    g2 += (double)row[3 * NP + j] * gj;
+  }
+  double u = 0.0, cj[3] = {0.0, 0.0, 0.0};
+  const double ri[3] = {Rw[3 * i], Rw[3 * i + 1], Rw[3 * i + 2]};
+  jastrow_one_partial(c, Rw, i, ri, lane, 64, u, cj);
+  o[3] = sum64(g0); o[4] = sum64(g1); o[5] = sum64(g2);
+  o[0] = sum64(cj[0]); o[1] = sum64(cj[1]); o[2] = sum64(cj[2]);
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT_AUX) void k_zv_prep(DevCtx c, double *cg, double *gjv,
                                                    double *djv) {
@@ -70,30 +94,17 @@ __global__ __launch_bounds__(NT_AUX) void k_zv_prep(DevCtx c, double *cg, double
   const int w = blockIdx.x;
   const int tid = threadIdx.x, wid = wave_id(), lane = tid & 63;
   constexpr int NWV = NT_AUX / 64;
-  const int NP = c.NP;
   const double *Rw = c.R + (size_t)w * c.ne * 3;
   // c_i and g_i, one wave per electron
   for (int i = wid; i < c.ne; i += NWV) {
-    const int sp = i < c.n_up ? 0 : 1, ii = i - sp * c.n_up;
-    const T *row = (const T *)c.vglc + vglc_off(c, w, i);
-    const T *gcol = (const T *)c.GT + gt_off(c, w, sp) + (size_t)ii * NP;
-    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-    for (int j = lane; j < NP; j += 64) {
-      const double gj = (double)gcol[j];
-      g0 += (double)row[NP + j] * gj;
-      g1 += (double)row[2 * NP + j] * gj;
-      g2 += (double)row[3 * NP + j] * gj;
-    }
-    double u = 0.0, cj[3] = {0.0, 0.0, 0.0};
-    const double ri[3] = {Rw[3 * i], Rw[3 * i + 1], Rw[3 * i + 2]};
-    jastrow_one_partial(c, Rw, i, ri, lane, 64, u, cj);
-    g0 = sum64(g0); g1 = sum64(g1); g2 = sum64(g2);
-    cj[0] = sum64(cj[0]); cj[1] = sum64(cj[1]); cj[2] = sum64(cj[2]);
+    double o[6];
+    electron_cg<T>(c, Rw, w, i, lane, o);
     if (lane == 0) {
-      double *o = s_cg + 6 * i;
-      o[0] = cj[0]; o[1] = cj[1]; o[2] = cj[2]; o[3] = g0; o[4] = g1; o[5] = g2;
       double *go = cg + ((size_t)w * c.ne + i) * 6;
-      for (int q = 0; q < 6; ++q) go[q] = o[q];
+      for (int q = 0; q < 6; ++q) {
+        s_cg[6 * i + q] = o[q];
+        go[q] = o[q];
+      }
     }
   }
   __syncthreads();

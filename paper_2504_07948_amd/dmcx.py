@@ -26,6 +26,7 @@ DMCX_FLAG_GRAPH = 1
 DMCX_FLAG_FP32_ENERGY = 2
 DMCX_N_ESTIMATORS = 11
 DMCX_NOALLOC_MAX_WALKERS = 1048576
+DMCX_N_JASTROW_PARAMS = 8
 
 EXPORTED = [
     "dmcx_create", "dmcx_destroy", "dmcx_set_walkers", "dmcx_get_walkers", "dmcx_set_step",
@@ -36,6 +37,7 @@ EXPORTED = [
     "dmcx_autotune_report", "dmcx_get_delay_rank", "dmcx_reconfigure", "dmcx_estimators",
     "dmcx_zv_grads", "dmcx_forces_zv", "dmcx_estimators_noalloc",
     "dmcx_energy_escalations", "dmcx_set_et_feedback", "dmcx_get_trial_energy",
+    "dmcx_jastrow_param_grads", "dmcx_linear_method",
 ]
 
 
@@ -117,6 +119,8 @@ def load():
         "dmcx_energy_escalations": [P, P],
         "dmcx_set_et_feedback": [P, D],
         "dmcx_get_trial_energy": [P, P],
+        "dmcx_jastrow_param_grads": [P, P, P, I32],
+        "dmcx_linear_method": [P, P, P, I32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -479,6 +483,22 @@ class Context:
         out = np.zeros(self.n_sys)
         self.check(load().dmcx_get_trial_energy(self.h, _ptr(out)))
         return out
+
+    def jastrow_param_grads(self):
+        """Per walker (d ln Psi/dp, dE_L/dp) [W][8] each for the Jastrow
+        parameters (e-e Pade b, e-n Pade b, six three-body coefficients)."""
+        O = np.zeros((self.W, DMCX_N_JASTROW_PARAMS))
+        D = np.zeros((self.W, DMCX_N_JASTROW_PARAMS))
+        self.check(load().dmcx_jastrow_param_grads(self.h, _ptr(O), _ptr(D), DMCX_HOST))
+        return O, D
+
+    def linear_method(self):
+        """Linear-method matrices (S, H), [n_sys][9][9] each."""
+        n = DMCX_N_JASTROW_PARAMS + 1
+        S = np.zeros((self.n_sys, n, n))
+        H = np.zeros((self.n_sys, n, n))
+        self.check(load().dmcx_linear_method(self.h, _ptr(S), _ptr(H), DMCX_HOST))
+        return S, H
 
     def energy_escalations(self):
         """Walkers whose E_L the last energy evaluation took from FP64 rows."""
