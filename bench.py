@@ -208,6 +208,62 @@ def flush_leg(s, torch, dmcx, stream, W=2048, k=32, reps=5):
                          "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS}}
 
 
+# FP64 additions and multiplications per electron pair and atom in the
+# three-body part of k_jparam as written (R_A . d, the two cosine terms, the
+# six terms and their sums; a fused multiply-add counts two)
+JPARAM_FLOP_PER_UNIT = 87
+
+
+def jparams_leg(s, torch, dmcx, stream, W=2048, reps=5, cpu_walkers=4):
+    """Jastrow parameter derivatives (two Pade b, six three-body e-e-n
+    coefficients) of the 2048 walkers, FP64: k_jparam timed with events on
+    the context's stream (a new configuration before each call, so nothing is
+    cached), then the linear-method matrices (four short launches).  Work unit:
+    one electron pair and one atom, W n(n-1)/2 n_atom per launch; the oracle
+    timed on a few walkers beside it."""
+    from paper_2504_07948_amd import synth
+    ctx = dmcx.Context(s, W, precision=dmcx.DMCX_FP64, delay_rank=32, recompute_period=64,
+                       stream=stream)
+    O = torch.empty((W, dmcx.DMCX_N_JASTROW_PARAMS), dtype=torch.float64, device="cuda")
+    D = torch.empty_like(O)
+    n9 = dmcx.DMCX_N_JASTROW_PARAMS + 1
+    S = torch.empty((n9, n9), dtype=torch.float64, device="cuda")
+    H = torch.empty_like(S)
+    t_jp, t_lm = [], []
+    for rep in range(reps + 1):
+        R = torch.from_numpy(synth.make_walkers(s, W, 2050 + rep)).cuda()
+        ctx.set_walkers(R)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        ctx.check(dmcx.dmcx_jastrow_param_grads(ctx.h, O.data_ptr(), D.data_ptr(),
+                                                dmcx.DMCX_DEVICE))
+        ev[1].record()
+        ctx.check(dmcx.dmcx_linear_method(ctx.h, S.data_ptr(), H.data_ptr(), dmcx.DMCX_DEVICE))
+        ev[2].record()
+        torch.cuda.synchronize()
+        if rep:  # the first call is a warm-up
+            t_jp.append(ev[0].elapsed_time(ev[1]))
+            t_lm.append(ev[1].elapsed_time(ev[2]))
+    ne = s.n_elec
+    units = W * ne * (ne - 1) // 2 * s.n_atom
+    ms = float(np.mean(t_jp))
+    ach = JPARAM_FLOP_PER_UNIT * units / (ms * 1e-3) / 1e12
+    import oracle
+    R = synth.make_walkers(s, cpu_walkers, 2050)
+    tc = time.perf_counter()
+    oracle.jastrow_param_grads_batch(s, R, n_threads=1)
+    tcpu = (time.perf_counter() - tc) / cpu_walkers
+    ctx.close()
+    return {"walkers": W, "params": dmcx.DMCX_N_JASTROW_PARAMS, "kernel": "k_jparam",
+            "ms_avg": ms, "pair_atom_units": units, "ns_per_unit_chip": 1e6 * ms / units,
+            "linear_method_ms_avg": float(np.mean(t_lm)),
+            "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
+                         "flop_per_unit": JPARAM_FLOP_PER_UNIT},
+            "oracle_ms_per_walker_one_thread": 1e3 * tcpu,
+            "gpu_ms_per_walker": ms / W}
+
+
 def batch5_leg(torch, dmcx, stream, steps=5, W=512, n_det=1000, n_active=100, P=32):
     """Eight alkane stand-ins (20..200 electrons), 512 walkers each, 1000-
     determinant expansions over 100 active orbitals (table method), mixed
@@ -355,10 +411,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the FP64 leg (same as --extras none)")
-    ap.add_argument("--extras", default="mixed,forces,batch,population,flush",
+    ap.add_argument("--extras", default="mixed,forces,batch,population,flush,jparams",
                     help="comma list of the extra legs to run after the FP64 leg: mixed, forces, "
                          "batch (eight multideterminant alkanes), population, flush (the "
-                         "delayed-update GEMMs alone), or none")
+                         "delayed-update GEMMs alone), jparams (Jastrow parameter derivatives "
+                         "and linear-method matrices), or none")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed region, run one device copy of this many MiB "
                          "(a known-size kernel for scaling FETCH_SIZE/WRITE_SIZE counters)")
@@ -412,9 +469,9 @@ def main():
     torch.cuda.synchronize()
     dt_period = time.perf_counter() - tp0
 
-    mixed = forces = batch5 = population = flush = None
+    mixed = forces = batch5 = population = flush = jparams = None
     extras = set() if args.skip_extras else set(args.extras.split(",")) - {"none", ""}
-    unknown = extras - {"mixed", "forces", "batch", "population", "flush"}
+    unknown = extras - {"mixed", "forces", "batch", "population", "flush", "jparams"}
     if unknown:
         sys.exit(f"bench.py: unknown extra legs {sorted(unknown)}")
     if "mixed" in extras:
@@ -427,6 +484,8 @@ def main():
         population = population_leg(s, torch, dmcx, stream)
     if "flush" in extras:
         flush = flush_leg(s, torch, dmcx, stream)
+    if "jparams" in extras:
+        jparams = jparams_leg(s, torch, dmcx, stream)
 
     ne, ns = s.n_elec, max(s.n_up, s.n_dn)
     moves = W * ne * args.steps
@@ -507,6 +566,7 @@ def main():
         "batch_multideterminant": batch5,
         "population_control": population,
         "delayed_update_flush": flush,
+        "jastrow_param_derivatives": jparams,
         "walker_flags_nonzero": int((flags != 0).sum()),
     }
     print(json.dumps(out))

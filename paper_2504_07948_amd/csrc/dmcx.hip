@@ -95,7 +95,8 @@ struct dmcx_ctx {
   uint64_t zv_version = 0;
   int zv_warp = -1;
   // Jastrow parameter derivatives [W][NJP] each (cached per configuration
-  // version) and the linear-method matrices S, H [2][NJP + 1][NJP + 1]
+  // version); the linear-method matrices S, H [2][NJP + 1][NJP + 1] followed
+  // by their merged means and block records
   double *d_jo = nullptr, *d_jd = nullptr, *d_lm = nullptr;
   uint64_t jp_version = 0;
   // weighted estimators: block records [est_blocks(W)][EST_PART], host staging [EST_OUT]
@@ -730,14 +731,15 @@ dmcx_status compute_jparams(dmcx_ctx *c) {
   if (!c->d_jo && ((st = dalloc(c, &c->d_jo, (size_t)c->W * NJP)) ||
                    (st = dalloc(c, &c->d_jd, (size_t)c->W * NJP))))
     return st;
-  const size_t lds = (size_t)c->ne * (3 + JE) * sizeof(double);
+  const size_t lds = jparam_lds(c->ne);
+  const int nch = jparam_chunk(c->ne);
   if (c->mixed) {
     HIP_TRY(c, allow_lds(k_jparam<float>, lds));
-    hipLaunchKernelGGL(k_jparam<float>, dim3(c->W), dim3(NT_AUX), lds, c->stream, c->dc, c->d_jo,
-                       c->d_jd);
+    hipLaunchKernelGGL(k_jparam<float>, dim3(c->W), dim3(NT_AUX), lds, c->stream, c->dc, nch,
+                       c->d_jo, c->d_jd);
   } else {
     HIP_TRY(c, allow_lds(k_jparam<double>, lds));
-    hipLaunchKernelGGL(k_jparam<double>, dim3(c->W), dim3(NT_AUX), lds, c->stream, c->dc,
+    hipLaunchKernelGGL(k_jparam<double>, dim3(c->W), dim3(NT_AUX), lds, c->stream, c->dc, nch,
                        c->d_jo, c->d_jd);
   }
   HIP_TRY(c, hipGetLastError());
@@ -2128,9 +2130,19 @@ dmcx_status dmcx_linear_method(dmcx_ctx *c, double *S, double *H, dmcx_mem mem) 
     return DMCX_OK;
   }
   if ((st = compute_jparams(c))) return st;
-  if (!c->d_lm && (st = dalloc(c, &c->d_lm, 2 * NM))) return st;
-  hipLaunchKernelGGL(k_linear_method, dim3(1), dim3(LM_NT), 0, c->stream, c->W, c->dc.logw,
-                     c->dc.eloc, c->dc.flags, c->d_jo, c->d_jd, c->d_lm);
+  const int nblk = lm_blocks(c->W);
+  // [2][9][9] result, the merged means (LM_Z + 1), the block records
+  if (!c->d_lm &&
+      (st = dalloc(c, &c->d_lm, 2 * NM + (LM_Z + 1) + (size_t)nblk * LM_REC)))
+    return st;
+  double *mm = c->d_lm + 2 * NM, *part = mm + LM_Z + 1;
+  const DevCtx &d = c->dc;
+  hipLaunchKernelGGL(k_lm_pass1, dim3(nblk), dim3(LM_NB), 0, c->stream, c->W, d.logw, d.eloc,
+                     d.flags, c->d_jo, c->d_jd, part);
+  hipLaunchKernelGGL(k_lm_merge, dim3(1), dim3(LM_NB), 0, c->stream, nblk, part, mm);
+  hipLaunchKernelGGL(k_lm_pass2, dim3(nblk), dim3(LM_NB), 0, c->stream, c->W, d.logw, d.eloc,
+                     d.flags, c->d_jo, c->d_jd, mm, part);
+  hipLaunchKernelGGL(k_lm_final, dim3(1), dim3(LM_NB), 0, c->stream, nblk, part, mm, c->d_lm);
   HIP_TRY(c, hipGetLastError());
   if ((st = copy_out(c, S, c->d_lm, NM * sizeof(double), mem))) return st;
   return copy_out(c, H, c->d_lm + NM, NM * sizeof(double), mem);

@@ -244,6 +244,26 @@ def dmcx_estimators_noalloc(n_walkers, log_w, e_local, flags, n_accepted, n_prop
                                           n_proposed, out, hip_stream)
 
 
+def dmcx_energy_escalations(ctx, n):
+    return load().dmcx_energy_escalations(ctx, n)
+
+
+def dmcx_set_et_feedback(ctx, gain):
+    return load().dmcx_set_et_feedback(ctx, gain)
+
+
+def dmcx_get_trial_energy(ctx, e_trial):
+    return load().dmcx_get_trial_energy(ctx, e_trial)
+
+
+def dmcx_jastrow_param_grads(ctx, dlogpsi, dEL, mem):
+    return load().dmcx_jastrow_param_grads(ctx, dlogpsi, dEL, mem)
+
+
+def dmcx_linear_method(ctx, S, H, mem):
+    return load().dmcx_linear_method(ctx, S, H, mem)
+
+
 def dmcx_potential(ctx, v, mem):
     return load().dmcx_potential(ctx, v, mem)
 

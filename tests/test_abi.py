@@ -21,6 +21,9 @@ def test_header_declares_expected_calls():
               "dmcx_flush", "dmcx_run", "dmcx_measure", "dmcx_ion_grads", "dmcx_logpsi_vjp"]:
         assert n in names
     assert set(names) == set(dmcx.EXPORTED)
+    # the binding carries a function of the same name for every entry point
+    missing = [n for n in names if not callable(getattr(dmcx, n, None))]
+    assert not missing, missing
 
 
 def test_library_exports_every_declared_symbol():
