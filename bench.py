@@ -128,30 +128,40 @@ def _energy_errors(s, torch, dmcx, stream, ctx, W):
             "logpsi_err_max": float(np.abs(dl).max())}
 
 
-def mixed_leg(s, torch, dmcx, stream, args, W=4096, steps=10, P=32, k=32):
+def mixed_leg(s, torch, dmcx, stream, args, W=4096, steps=10, P=32):
     """Mixed precision on the same system at 4096 walkers against FP64 at the
-    same 4096 walkers.  Two forms: the default (FP32 sweep, FP64 value rows,
-    inverse and E_L at the end of every step) and the FP32-energy variant
-    (E_L from the FP32 rows and inverse, FP64 recompute every 32 steps).
-    Reports moves/s and ms per step of each, the speedup over FP64 at equal
-    walker count, the FP32 sweep kernel's fraction of the FP32 peak, and the
-    energy error per electron at identical configurations."""
-    from paper_2504_07948_amd import synth  # noqa: F401
+    same 4096 walkers, each with the sweep's tile shape and delay rank chosen
+    by the autotuner in its warm-up step (ranks 8..56 of the 56 orbitals per
+    spin; the FP32 sweep offers two tile shapes, the FP64 sweep one).  Two
+    mixed forms: the default (FP32 sweep, FP64 value rows, inverse and E_L at
+    the end of every step) and the FP32-energy variant (E_L from the FP32
+    rows and inverse, FP64 recompute every 32 steps).  Reports moves/s and ms
+    per step of each, the speedup over FP64 at equal walker count, the FP32
+    sweep kernel's fraction of the FP32 peak, and the energy error per
+    electron at identical configurations."""
     ne, ns = s.n_elec, max(s.n_up, s.n_dn)
-    fpm = flops_per_move(s.n_basis, len(s.prim_alpha), ns, ne, s.n_atom, k)
     c64, ms64, sw64 = _timed_ctx(s, torch, dmcx, stream, W, steps, 19, precision=dmcx.DMCX_FP64,
-                                 delay_rank=k, recompute_period=64)
+                                 delay_rank=0, recompute_period=64)
+    k64 = c64.delay_rank()
     c64.close()
-    out = {"walkers": W, "steps": steps, "delay_rank": k, "unit": "electron-moves/s",
+    out = {"walkers": W, "steps": steps, "unit": "electron-moves/s",
            "fp64_same_walkers": {"ms_per_step": ms64, "value": W * ne / (ms64 * 1e-3),
-                                 "sweep_ms_avg": sw64, "recompute_period": 64}}
+                                 "sweep_ms_avg": sw64, "recompute_period": 64,
+                                 "delay_rank": k64, "tile_shape": "deep"}}
+    shape_name = {dmcx.DMCX_TILE_DEEP: "deep", dmcx.DMCX_TILE_SHALLOW: "shallow"}
     for name, fp32e in (("fp64_energy", False), ("fp32_energy", True)):
         ctx, ms, sw = _timed_ctx(s, torch, dmcx, stream, W, steps, 19, precision=dmcx.DMCX_MIXED,
-                                 delay_rank=k, recompute_period=P, fp32_energy=fp32e)
+                                 delay_rank=0, recompute_period=P, fp32_energy=fp32e)
+        k = ctx.delay_rank()
+        ranks, shapes, tms = ctx.autotune_report()
+        fpm = flops_per_move(s.n_basis, len(s.prim_alpha), ns, ne, s.n_atom, k)
         n_esc = ctx.energy_escalations()
         ach = fpm * W * ne / (sw * 1e-3) / 1e12
         rec = {"ms_per_step": ms, "value": W * ne / (ms * 1e-3), "speedup_vs_fp64_same_walkers":
-               ms64 / ms, "sweep_ms_avg": sw,
+               ms64 / ms, "sweep_ms_avg": sw, "delay_rank": k,
+               "tile_shape": shape_name[ctx.tile_shape()],
+               "autotune_ms_per_sweep": {f"{shape_name[int(a)]}/k={int(b)}": round(float(t), 3)
+                                         for a, b, t in zip(shapes, ranks, tms)},
                "sweep_roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
                                   "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS},
                "recompute_period": 1 if not fp32e else P,

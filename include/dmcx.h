@@ -199,27 +199,48 @@ dmcx_status dmcx_flush(dmcx_ctx *ctx);
  * into a hipGraph and replayed n_steps times; the capture is redone when
  * the log pointers, the delay rank or the ions change.  Results are the same
  * bits as without the flag.  With delay_rank == 0 the first run first
- * times 2 sweeps per candidate rank (dmcx_autotune) and restores the
- * walkers (inverses are then freshly recomputed). */
+ * times 2 sweeps per candidate (tile shape, rank) (dmcx_autotune) and
+ * restores the walkers (inverses are then freshly recomputed). */
 dmcx_status dmcx_run(dmcx_ctx *ctx, dmcx_mode mode, int32_t n_steps, double e_trial,
                      uint8_t *accept_log, double *e_log, dmcx_mem mem);
 
+/* Tile shapes of the single-determinant sweep (8 walkers per workgroup of 8
+ * waves in both): DMCX_TILE_DEEP stages 4 x stage depth basis functions per
+ * LDS stage of the orbital GEMM (one workgroup per CU at the FP64 register
+ * count); DMCX_TILE_SHALLOW stages half as many with four waves per SIMD (two
+ * workgroups per CU).  The FP32 (mixed) single-determinant sweep offers both
+ * (default shallow); the FP64 and multideterminant sweeps are deep only. */
+#define DMCX_TILE_DEEP 0
+#define DMCX_TILE_SHALLOW 1
+
 /* Passage: QMC Energy and Wavefunction Evaluation (batching chosen to keep
- * the GPU busy); the delay rank itself is not in the paper.
- * Delay-rank autotuner: for every system, time `steps` sweeps (after one
- * untimed sweep) at each candidate rank k in {8, 16, 24, 32, 48, 64} below
+ * the GPU busy); tile shapes and the delay rank are not in the paper.
+ * Autotuner of the sweep: for every system, time `steps` sweeps (after one
+ * untimed sweep) for each candidate pair (tile shape, rank): the shapes the
+ * system's sweep offers, and the ranks k in {8, 16, 24, 32, 48, 64} below
  * n_sigma plus n_sigma itself, limited to the rank the buffers were sized
- * for at create (min(64, n_sigma) with delay_rank == 0, else delay_rank),
- * keep the fastest, restore the walkers and recompute the inverses.
+ * for at create (min(64, n_sigma) with delay_rank == 0, else delay_rank);
+ * keep the fastest pair, restore the walkers and recompute the inverses.
  * chosen_k [n_sys] may be NULL.  The walker configurations and weights are
  * unchanged; the step counter is unchanged. */
 dmcx_status dmcx_autotune(dmcx_ctx *ctx, int32_t steps, int32_t *chosen_k);
 
 /* The autotuner's last measurements for system sys_index: up to max_n
- * candidate ranks and their average sweep times (ms); *n_cand = number of
- * candidates (0 if the tuner has not run).  ranks / ms may be NULL. */
+ * candidates, each a rank, a tile shape (DMCX_TILE_*) and its average sweep
+ * time (ms); *n_cand = number of candidates (0 if the tuner has not run).
+ * ranks / shapes / ms may be NULL. */
 dmcx_status dmcx_autotune_report(const dmcx_ctx *ctx, int32_t sys_index, int32_t max_n,
-                                 int32_t *ranks, float *ms_per_sweep, int32_t *n_cand);
+                                 int32_t *ranks, int32_t *shapes, float *ms_per_sweep,
+                                 int32_t *n_cand);
+
+/* Set the tile shape of system sys_index's sweep (DMCX_TILE_*), in place of
+ * the autotuner's choice.  DMCX_E_UNSUPPORTED for a shape the system's sweep
+ * does not offer (see DMCX_TILE_DEEP), DMCX_E_INVALID for a bad index or
+ * shape.  Results differ between shapes only by the order of the FP32 (or
+ * FP64) sums of the orbital GEMM. */
+dmcx_status dmcx_set_tile_shape(dmcx_ctx *ctx, int32_t sys_index, int32_t shape);
+/* Tile shape currently used by system sys_index's sweep. */
+dmcx_status dmcx_get_tile_shape(const dmcx_ctx *ctx, int32_t sys_index, int32_t *shape);
 
 /* Delay rank currently used by system sys_index. */
 dmcx_status dmcx_get_delay_rank(const dmcx_ctx *ctx, int32_t sys_index, int32_t *k);

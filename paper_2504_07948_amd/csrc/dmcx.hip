@@ -118,8 +118,14 @@ struct dmcx_ctx {
   // is chosen by timing candidate ranks at the first run
   int K_alloc = 1;
   bool tune_pending = false;
-  std::vector<int> tune_cand;
+  std::vector<int> tune_cand, tune_shape;
   std::vector<float> tune_ms;
+  // sweep tile shape (SweepShape) and the basis stage table of each shape;
+  // every other kernel uses dc.B's table
+  int shape = SHAPE_DEEP;
+  bool shape_ok[2] = {true, false};
+  int n_stage_s[2] = {0, 0};
+  int2 *d_stages_s[2] = {nullptr, nullptr};
   // kernel arguments baked into a captured graph change with this counter
   uint64_t dc_version = 1;
   // several systems: this context is a group of single-system contexts that
@@ -134,6 +140,7 @@ struct dmcx_ctx {
     std::vector<size_t> members;  // indices into the group's systems, costliest first
     int nob = 0;
     bool msd = false;
+    int shape = SHAPE_DEEP;
     int ntiles = 0;
     size_t lds = 0;
     DevCtx *d_cs = nullptr;
@@ -146,6 +153,7 @@ struct dmcx_ctx {
     bool uploaded = false;
   };
   std::vector<SweepClass> classes;
+  std::vector<int> class_shapes;  // the members' tile shapes the classes were built for
   hipStream_t own = nullptr; // this system's run stream (groups, graphs)
   std::vector<hipEvent_t> fj;      // fork/join events of eager and graph runs
   std::vector<hipEvent_t> cap_ev;  // fork/join events inside a graph capture
@@ -317,24 +325,32 @@ dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, const std::vector<int>
     pfn += 4 * NCART_[l];
   }
   const int n_group = (int)ginfo.size();
-  // stages: consecutive groups of one (l, nprim) type, at most fmax functions
-  std::vector<int2> stages;
-  int g = 0;
-  // stage depth of this context's sweep kernel (shallower for the FP32
-  // single-determinant sweep, two workgroups per CU)
-  const int ks = c->mixed && s.n_det <= 1 ? stage_ksteps_w4(c->NOB) : stage_ksteps(c->NOB);
-  const int fmax = 4 * ks;
-  while (g < n_group) {
-    int g1 = g, f = 0;
-    const int gmax = stage_max_groups(ginfo[g].x, ks);
-    while (g1 < n_group && ginfo[g1].x == ginfo[g].x && ginfo[g1].y == ginfo[g].y &&
-           f + 4 * NCART_[ginfo[g1].x] <= fmax && g1 - g < gmax) {
-      f += 4 * NCART_[ginfo[g1].x];
-      ++g1;
+  // stages: consecutive groups of one (l, nprim) type, at most 4 ks functions
+  auto make_stages = [&](int ks) {
+    std::vector<int2> st;
+    const int fmax = 4 * ks;
+    int g = 0;
+    while (g < n_group) {
+      int g1 = g, f = 0;
+      const int gmax = stage_max_groups(ginfo[g].x, ks);
+      while (g1 < n_group && ginfo[g1].x == ginfo[g].x && ginfo[g1].y == ginfo[g].y &&
+             f + 4 * NCART_[ginfo[g1].x] <= fmax && g1 - g < gmax) {
+        f += 4 * NCART_[ginfo[g1].x];
+        ++g1;
+      }
+      st.push_back(make_int2(g, g1));
+      g = g1;
     }
-    stages.push_back(make_int2(g, g1));
-    g = g1;
-  }
+    return st;
+  };
+  // The single-determinant FP32 sweep comes in both tile shapes (deep and
+  // shallow stages); every other sweep is deep.  dc.B carries the table of
+  // the default shape (shallow for the FP32 sweep), which the kernels other
+  // than the sweep use as well.
+  const bool two_shapes = c->mixed && s.n_det <= 1;
+  const std::vector<int2> stages = make_stages(two_shapes ? stage_ksteps_w4(c->NOB)
+                                                          : stage_ksteps(c->NOB));
+  const std::vector<int2> stages_deep = two_shapes ? make_stages(stage_ksteps(c->NOB)) : stages;
   const int NP = c->NP;
   // Zero rows past the last function: the orbital tile loads a whole stage
   // depth of LCAO rows (4 stage_ksteps) and four orbital blocks per wave
@@ -361,6 +377,15 @@ dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, const std::vector<int>
   if ((st = upload(c, &d_gcoef, gcoef))) return st;
   if ((st = upload(c, &d_gatom, gatom))) return st;
   if ((st = upload(c, &d_stages, stages))) return st;
+  c->shape = two_shapes ? SHAPE_SHALLOW : SHAPE_DEEP;
+  c->shape_ok[SHAPE_DEEP] = true;
+  c->shape_ok[SHAPE_SHALLOW] = two_shapes;
+  c->n_stage_s[c->shape] = (int)stages.size();
+  c->d_stages_s[c->shape] = d_stages;
+  if (two_shapes) {
+    if ((st = upload(c, &c->d_stages_s[SHAPE_DEEP], stages_deep))) return st;
+    c->n_stage_s[SHAPE_DEEP] = (int)stages_deep.size();
+  }
   if ((st = upload(c, &d_Cp, Cp))) return st;
   if ((st = upload(c, &d_Cp32, Cp32))) return st;
   c->gatom_host = gatom;
@@ -384,6 +409,22 @@ dmcx_status pack_basis(dmcx_ctx *c, const dmcx_system &s, const std::vector<int>
 size_t basis_lds(const dmcx_ctx *c) {
   return basis_lds_bytes(c->dc.B.n_group, c->dc.B.n_slot, c->dc.B.n_stage);
 }
+// The sweep's view of the context: the stage table of its tile shape.
+DevCtx sweep_dc(const dmcx_ctx *c, int shape) {
+  DevCtx d = c->dc;
+  d.B.n_stage = c->n_stage_s[shape];
+  d.B.stages = c->d_stages_s[shape];
+  return d;
+}
+size_t sweep_basis_lds(const dmcx_ctx *c, int shape) {
+  return basis_lds_bytes(c->dc.B.n_group, c->dc.B.n_slot, c->n_stage_s[shape]);
+}
+// static LDS of the sweep kernel of a shape (single determinant)
+size_t sweep_static_lds(const dmcx_ctx *c, int shape) {
+  if (!c->mixed) return SweepLaunch<double, SHAPE_DEEP>::sweep_lds(c->NOB);
+  return shape == SHAPE_SHALLOW ? SweepLaunch<float, SHAPE_SHALLOW>::sweep_lds(c->NOB)
+                                : SweepLaunch<float, SHAPE_DEEP>::sweep_lds(c->NOB);
+}
 
 // The working precision picks the launcher instantiation.
 #define DMCX_BY_PRECISION(c, CALL)  \
@@ -406,12 +447,19 @@ void launch_orbitals_at(dmcx_ctx *c, const double *pos, int npts, void *dst) {
                                                    basis_lds(c), c->stream));
 }
 void launch_sweep(dmcx_ctx *c, uint8_t *acc, long long acc_ss, int acc_ws) {
-  if (c->dc.M.on)
+  if (c->dc.M.on) {
     DMCX_BY_PRECISION(c, MsdLaunch<WT>::sweep(c->NOB, c->dc, acc, acc_ss, acc_ws, basis_lds(c),
                                               c->stream));
+    return;
+  }
+  const DevCtx d = sweep_dc(c, c->shape);
+  const size_t lds = sweep_basis_lds(c, c->shape);
+  if (!c->mixed)
+    SweepLaunch<double, SHAPE_DEEP>::sweep(c->NOB, d, acc, acc_ss, acc_ws, lds, c->stream);
+  else if (c->shape == SHAPE_SHALLOW)
+    SweepLaunch<float, SHAPE_SHALLOW>::sweep(c->NOB, d, acc, acc_ss, acc_ws, lds, c->stream);
   else
-    DMCX_BY_PRECISION(c, NobLaunch<WT>::sweep(c->NOB, c->dc, acc, acc_ss, acc_ws, basis_lds(c),
-                                              c->stream));
+    SweepLaunch<float, SHAPE_DEEP>::sweep(c->NOB, d, acc, acc_ss, acc_ws, lds, c->stream);
 }
 
 // Multideterminant: table T = A^{-1} M and every determinant ratio, from
@@ -1076,11 +1124,17 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
   {
     // the sweep's LDS (static arrays + staged basis tables) must fit a CU
     size_t stat = 0;
-    if (c->dc.M.on)
+    if (c->dc.M.on) {
       DMCX_BY_PRECISION(c, stat = MsdLaunch<WT>::sweep_lds(c->NOB));
-    else
-      DMCX_BY_PRECISION(c, stat = NobLaunch<WT>::sweep_lds(c->NOB));
-    if (stat + basis_lds(c) > 160 * 1024) {
+    } else {
+      // a second shape that does not fit is simply not offered
+      for (int sh = 0; sh < 2; ++sh)
+        if (c->shape_ok[sh] && sh != c->shape &&
+            sweep_static_lds(c, sh) + sweep_basis_lds(c, sh) > 160 * 1024)
+          c->shape_ok[sh] = false;
+      stat = sweep_static_lds(c, c->shape);
+    }
+    if (stat + (c->dc.M.on ? basis_lds(c) : sweep_basis_lds(c, c->shape)) > 160 * 1024) {
       c->err = "orbital tile and basis tables exceed the 160 KB of LDS (use the mixed precision "
                "form or a smaller basis)";
       return bail(DMCX_E_UNSUPPORTED);
@@ -1224,6 +1278,11 @@ void set_delay_rank(dmcx_ctx *c, int k) {
   c->dc.K16 = (k + 15) / 16 * 16;
   c->dc_version++;
 }
+void set_shape(dmcx_ctx *c, int shape) {
+  if (c->shape == shape) return;
+  c->shape = shape;
+  c->dc_version++;  // captured steps and sweep classes change
+}
 
 // Enqueue one step of a single-system context on c->stream: periodic FP64
 // recompute, the sweep, local energies + weights, step counter advance.
@@ -1268,22 +1327,32 @@ dmcx_status ensure_own_stream(dmcx_ctx *c) {
   return DMCX_OK;
 }
 
-// Delay-rank autotuner: time `steps` sweeps for each candidate rank (after
-// one untimed sweep) from the same walker state, keep the fastest, and
-// restore the walkers.  Candidates: 8, 16, 24, 32, 48, 64 below n_sigma, and
-// n_sigma itself, within the rank the buffers were sized for.
+// Autotuner of the sweep: time `steps` sweeps for each candidate (tile
+// shape, delay rank) (after one untimed sweep) from the same walker state,
+// keep the fastest, and restore the walkers.  Ranks: 8, 16, 24, 32, 48, 64
+// below n_sigma, and n_sigma itself, within the rank the buffers were sized
+// for; shapes: those the context's sweep offers (SweepShape).
 dmcx_status autotune_one(dmcx_ctx *c, int steps) {
   const int nsig = std::max(c->n_up, c->n_dn);
   const int kmax = std::min(nsig, c->K_alloc);
-  std::vector<int> cand;
+  std::vector<int> ranks;
   for (int k : {8, 16, 24, 32, 48, 64})
-    if (k < kmax) cand.push_back(k);
-  cand.push_back(kmax);
+    if (k < kmax) ranks.push_back(k);
+  ranks.push_back(kmax);
+  std::vector<int> cand, cshape;
+  for (int sh = 0; sh < 2; ++sh)
+    if (c->shape_ok[sh] && !(c->dc.M.on && sh != SHAPE_DEEP))
+      for (int k : ranks) {
+        cand.push_back(k);
+        cshape.push_back(sh);
+      }
   c->tune_cand = cand;
+  c->tune_shape = cshape;
   c->tune_ms.assign(cand.size(), 0.f);
   c->tune_pending = false;
   if (cand.size() == 1) {
     if (c->K != kmax) set_delay_rank(c, kmax);
+    set_shape(c, cshape[0]);
     return DMCX_OK;
   }
   dmcx_status st = DMCX_OK;
@@ -1309,6 +1378,7 @@ dmcx_status autotune_one(dmcx_ctx *c, int steps) {
   size_t best = 0;
   for (size_t q = 0; q < cand.size() && !st; ++q) {
     set_delay_rank(c, cand[q]);
+    set_shape(c, cshape[q]);
     if ((st = restore())) break;
     hipLaunchKernelGGL(k_set_run, dim3(1), dim3(64), 0, c->stream, c->d_run,
                        (unsigned long long)c->step, 0, 0.0);
@@ -1331,6 +1401,7 @@ dmcx_status autotune_one(dmcx_ctx *c, int steps) {
   }
   if (!st) {
     set_delay_rank(c, cand[best]);
+    set_shape(c, cshape[best]);
     st = restore();
   }
   if (!st) st = hip_check(c, hipStreamSynchronize(c->stream), "autotune: sync");
@@ -1362,17 +1433,26 @@ std::vector<size_t> launch_order(const std::vector<dmcx_ctx *> &ms) {
 // Sweep classes of a group (built once): systems of one orbital-tile width
 // and form share a launch; tiles of the costliest system come first.
 dmcx_status build_classes(dmcx_ctx *top, const std::vector<dmcx_ctx *> &ms) {
-  if (!top->classes.empty()) return DMCX_OK;
+  // rebuilt when a member's tile shape changed (autotuner); the device
+  // buffers of the old classes stay with the context until it is destroyed
+  std::vector<int> shapes;
+  for (const dmcx_ctx *m : ms) shapes.push_back(m->shape);
+  if (!top->classes.empty() && shapes == top->class_shapes) return DMCX_OK;
+  top->classes.clear();
+  top->class_shapes = shapes;
   for (size_t i : launch_order(ms)) {
     dmcx_ctx *m = ms[i];
     const bool msd = m->dc.M.on != 0;
     size_t k = 0;
-    while (k < top->classes.size() && !(top->classes[k].nob == m->NOB && top->classes[k].msd == msd))
+    while (k < top->classes.size() &&
+           !(top->classes[k].nob == m->NOB && top->classes[k].msd == msd &&
+             top->classes[k].shape == m->shape))
       ++k;
     if (k == top->classes.size()) {
       top->classes.emplace_back();
       top->classes.back().nob = m->NOB;
       top->classes.back().msd = msd;
+      top->classes.back().shape = m->shape;
     }
     top->classes[k].members.push_back(i);
   }
@@ -1383,7 +1463,7 @@ dmcx_status build_classes(dmcx_ctx *top, const std::vector<dmcx_ctx *> &ms) {
     for (size_t k = 0; k < cl.members.size(); ++k) {
       const dmcx_ctx *m = ms[cl.members[k]];
       for (int t = 0; t < m->Wpad / TW; ++t) tiles.push_back(make_int2((int)k, t));
-      cl.lds = std::max(cl.lds, basis_lds(m));
+      cl.lds = std::max(cl.lds, cl.msd ? basis_lds(m) : sweep_basis_lds(m, cl.shape));
     }
     cl.ntiles = (int)tiles.size();
     if ((st = upload(top, &cl.d_tiles, tiles))) return st;
@@ -1406,7 +1486,7 @@ dmcx_status upload_classes(dmcx_ctx *top, const std::vector<dmcx_ctx *> &ms, uin
     if (cl.uploaded && key == cl.key && acc == cl.acc) continue;
     for (size_t k = 0; k < cl.members.size(); ++k) {
       const size_t i = cl.members[k];
-      cl.h_cs[k] = ms[i]->dc;
+      cl.h_cs[k] = cl.msd ? ms[i]->dc : sweep_dc(ms[i], cl.shape);
       const size_t off = top->is_group() ? top->sub_off[i] : 0;
       cl.h_logs[k] = SweepLog{acc ? acc + off * top->ne : nullptr, (long long)top->W * top->ne,
                               top->ne};
@@ -1459,9 +1539,15 @@ dmcx_status enqueue_class_step(dmcx_ctx *top, const std::vector<dmcx_ctx *> &ms,
     } else if (cl.msd) {
       DMCX_BY_PRECISION(top, MsdLaunch<WT>::sweep_multi(cl.nob, cl.d_cs, cl.d_tiles, cl.ntiles,
                                                         cl.d_logs, cl.lds, s));
+    } else if (!top->mixed) {
+      SweepLaunch<double, SHAPE_DEEP>::sweep_multi(cl.nob, cl.d_cs, cl.d_tiles, cl.ntiles,
+                                                   cl.d_logs, cl.lds, s);
+    } else if (cl.shape == SHAPE_SHALLOW) {
+      SweepLaunch<float, SHAPE_SHALLOW>::sweep_multi(cl.nob, cl.d_cs, cl.d_tiles, cl.ntiles,
+                                                     cl.d_logs, cl.lds, s);
     } else {
-      DMCX_BY_PRECISION(top, NobLaunch<WT>::sweep_multi(cl.nob, cl.d_cs, cl.d_tiles, cl.ntiles,
-                                                        cl.d_logs, cl.lds, s));
+      SweepLaunch<float, SHAPE_DEEP>::sweep_multi(cl.nob, cl.d_cs, cl.d_tiles, cl.ntiles,
+                                                  cl.d_logs, cl.lds, s);
     }
     st = hip_check(top, hipGetLastError(), "sweep launch");
   }
@@ -1884,7 +1970,8 @@ dmcx_status dmcx_autotune(dmcx_ctx *c, int32_t steps, int32_t *chosen_k) {
 }
 
 dmcx_status dmcx_autotune_report(const dmcx_ctx *c, int32_t sys_index, int32_t max_n,
-                                 int32_t *ranks, float *ms_per_sweep, int32_t *n_cand) {
+                                 int32_t *ranks, int32_t *shapes, float *ms_per_sweep,
+                                 int32_t *n_cand) {
   if (!c || !n_cand || max_n < 0) return DMCX_E_INVALID;
   const dmcx_ctx *m = c;
   if (c->is_group()) {
@@ -1897,8 +1984,36 @@ dmcx_status dmcx_autotune_report(const dmcx_ctx *c, int32_t sys_index, int32_t m
   *n_cand = n;
   for (int q = 0; q < n && q < max_n; ++q) {
     if (ranks) ranks[q] = m->tune_cand[q];
+    if (shapes) shapes[q] = m->tune_shape[q];
     if (ms_per_sweep) ms_per_sweep[q] = m->tune_ms[q];
   }
+  return DMCX_OK;
+}
+
+// The system of a context by index (the context itself for one system).
+static dmcx_ctx *system_of(dmcx_ctx *c, int32_t sys_index) {
+  if (c->is_group()) return sys_index >= 0 && sys_index < (int)c->subs.size() ? c->subs[sys_index]
+                                                                              : nullptr;
+  return sys_index == 0 ? c : nullptr;
+}
+
+dmcx_status dmcx_set_tile_shape(dmcx_ctx *c, int32_t sys_index, int32_t shape) {
+  if (!c) return DMCX_E_INVALID;
+  dmcx_ctx *m = system_of(c, sys_index);
+  if (!m || (shape != DMCX_TILE_DEEP && shape != DMCX_TILE_SHALLOW)) return DMCX_E_INVALID;
+  if (m->dc.M.on ? shape != DMCX_TILE_DEEP : !m->shape_ok[shape])
+    return fail(c, DMCX_E_UNSUPPORTED, "tile shape not offered by this system's sweep");
+  set_shape(m, shape);
+  m->tune_pending = false;  // an explicit choice is kept
+  if (m != c) c->dc_version++;
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_get_tile_shape(const dmcx_ctx *c, int32_t sys_index, int32_t *shape) {
+  if (!c || !shape) return DMCX_E_INVALID;
+  const dmcx_ctx *m = system_of(const_cast<dmcx_ctx *>(c), sys_index);
+  if (!m) return DMCX_E_INVALID;
+  *shape = m->shape;
   return DMCX_OK;
 }
 

@@ -1,5 +1,5 @@
-// FP32 working precision (the mixed form): every NOB-templated kernel and
-// its launcher.
+// FP32 working precision (the mixed form): every NOB-templated kernel but the
+// sweep (sweep_f32_*.hip) and its launcher.
 #include "kern_impl.h"
 
 namespace dmcx {

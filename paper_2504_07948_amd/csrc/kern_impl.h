@@ -7,20 +7,6 @@
 
 namespace dmcx {
 
-#define DMCX_NOB_SWITCH(nob, CALL) \
-  switch (nob) {                   \
-    case 1: CALL(1); break;        \
-    case 2: CALL(2); break;        \
-    case 3: CALL(3); break;        \
-    case 4: CALL(4); break;        \
-    case 5: CALL(5); break;        \
-    case 6: CALL(6); break;        \
-    case 7: CALL(7); break;        \
-    case 8: CALL(8); break;        \
-    case 9: CALL(9); break;        \
-    default: CALL(10); break;      \
-  }
-
 template <typename T>
 void NobLaunch<T>::orbitals_all(int nob, const DevCtx &c, size_t lds, hipStream_t s) {
   const int npts = c.Wpad * c.ne;
@@ -39,57 +25,6 @@ void NobLaunch<T>::orbitals_at(int nob, const DevCtx &c, const double *pos, int 
   k_orbitals_at<T, N><<<dim3((npts + TW - 1) / TW), dim3(NT_TILE), lds, s>>>(c, pos, npts, dst)
   DMCX_NOB_SWITCH(nob, DMCX_CALL)
 #undef DMCX_CALL
-}
-
-template <typename T>
-void NobLaunch<T>::sweep(int nob, const DevCtx &c, uint8_t *acc, long long acc_ss, int acc_ws,
-                         size_t lds, hipStream_t s) {
-  if constexpr (sizeof(T) == 4) {
-#define DMCX_CALL(N)                                                                   \
-  if (allow_lds(k_sweep_w4<T, N>, lds) == hipSuccess) \
-  k_sweep_w4<T, N><<<dim3(c.Wpad / TW), dim3(NT_TILE), lds, s>>>(c, acc, acc_ss, acc_ws)
-    DMCX_NOB_SWITCH(nob, DMCX_CALL)
-#undef DMCX_CALL
-  } else {
-#define DMCX_CALL(N)                                                                   \
-  if (allow_lds(k_sweep<T, N>, lds) == hipSuccess) \
-  k_sweep<T, N><<<dim3(c.Wpad / TW), dim3(NT_TILE), lds, s>>>(c, acc, acc_ss, acc_ws)
-    DMCX_NOB_SWITCH(nob, DMCX_CALL)
-#undef DMCX_CALL
-  }
-}
-
-template <typename T>
-void NobLaunch<T>::sweep_multi(int nob, const DevCtx *cs, const int2 *tiles, int ntiles,
-                               const SweepLog *logs, size_t lds, hipStream_t s) {
-  if constexpr (sizeof(T) == 4) {
-#define DMCX_CALL(N)                                                                   \
-  if (allow_lds(k_sweep_w4_multi<T, N>, lds) == hipSuccess) \
-  k_sweep_w4_multi<T, N><<<dim3(ntiles), dim3(NT_TILE), lds, s>>>(cs, tiles, logs)
-    DMCX_NOB_SWITCH(nob, DMCX_CALL)
-#undef DMCX_CALL
-  } else {
-#define DMCX_CALL(N)                                                                   \
-  if (allow_lds(k_sweep_multi<T, N>, lds) == hipSuccess) \
-  k_sweep_multi<T, N><<<dim3(ntiles), dim3(NT_TILE), lds, s>>>(cs, tiles, logs)
-    DMCX_NOB_SWITCH(nob, DMCX_CALL)
-#undef DMCX_CALL
-  }
-}
-
-template <typename T>
-size_t NobLaunch<T>::sweep_lds(int nob) {
-  hipFuncAttributes a{};
-  if constexpr (sizeof(T) == 4) {
-#define DMCX_CALL(N) (void)hipFuncGetAttributes(&a, (const void *)k_sweep_w4<T, N>)
-    DMCX_NOB_SWITCH(nob, DMCX_CALL)
-#undef DMCX_CALL
-  } else {
-#define DMCX_CALL(N) (void)hipFuncGetAttributes(&a, (const void *)k_sweep<T, N>)
-    DMCX_NOB_SWITCH(nob, DMCX_CALL)
-#undef DMCX_CALL
-  }
-  return a.sharedSizeBytes;
 }
 
 template <typename T>

@@ -1,7 +1,7 @@
 // Host-side launchers of the kernels that are templated on the number of
-// 16-orbital blocks (NOB).  Each working precision is instantiated in a
-// translation unit of its own (kern_f64.hip, kern_f32.hip), so the builds of
-// the many NOB variants run in parallel; the runtime (dmcx.hip) calls these
+// 16-orbital blocks (NOB).  Each working precision (and each sweep shape) is
+// instantiated in a translation unit of its own (kern_f64.hip, kern_f32.hip,
+// sweep_*.hip), so the builds of the many NOB variants run in parallel; the runtime (dmcx.hip) calls these
 // with the context's NOB and never instantiates the kernels itself.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -22,13 +22,33 @@ inline hipError_t allow_lds(K kernel, size_t dyn) {
                              (int)dyn);
 }
 
-template <typename T>
-struct NobLaunch {
-  // orbital VGL rows of every electron of every walker -> vglc
-  static void orbitals_all(int nob, const DevCtx &c, size_t lds, hipStream_t s);
-  // orbitals at one point per walker -> dst [Wpad][5][NP]
-  static void orbitals_at(int nob, const DevCtx &c, const double *pos, int npts, T *dst,
-                          size_t lds, hipStream_t s);
+#define DMCX_NOB_SWITCH(nob, CALL) \
+  switch (nob) {                   \
+    case 1: CALL(1); break;        \
+    case 2: CALL(2); break;        \
+    case 3: CALL(3); break;        \
+    case 4: CALL(4); break;        \
+    case 5: CALL(5); break;        \
+    case 6: CALL(6); break;        \
+    case 7: CALL(7); break;        \
+    case 8: CALL(8); break;        \
+    case 9: CALL(9); break;        \
+    default: CALL(10); break;      \
+  }
+
+// Tile shapes of the single-determinant sweep.  Both put 8 walkers in a
+// workgroup of 8 waves; they differ in the depth of the staged basis tile
+// (the K extent of the orbital GEMM per LDS stage) and with it in how many
+// workgroups share a CU:
+//   SHAPE_DEEP     4 stage_ksteps(NOB) functions per stage, up to 2 waves per
+//                  SIMD (one workgroup per CU at the FP64 register count);
+//   SHAPE_SHALLOW  half as deep, 4 waves per SIMD (two workgroups per CU).
+enum SweepShape { SHAPE_DEEP = 0, SHAPE_SHALLOW = 1 };
+
+// The sweep launchers of one working precision and shape, instantiated in
+// translation units of their own (sweep_*.hip).
+template <typename T, int SHAPE>
+struct SweepLaunch {
   // one full sweep of the single-determinant trial function
   static void sweep(int nob, const DevCtx &c, uint8_t *acc, long long acc_ss, int acc_ws,
                     size_t lds, hipStream_t s);
@@ -37,6 +57,15 @@ struct NobLaunch {
   // one sweep over the tiles of several systems of this width (a group)
   static void sweep_multi(int nob, const DevCtx *cs, const int2 *tiles, int ntiles,
                           const SweepLog *logs, size_t lds, hipStream_t s);
+};
+
+template <typename T>
+struct NobLaunch {
+  // orbital VGL rows of every electron of every walker -> vglc
+  static void orbitals_all(int nob, const DevCtx &c, size_t lds, hipStream_t s);
+  // orbitals at one point per walker -> dst [Wpad][5][NP]
+  static void orbitals_at(int nob, const DevCtx &c, const double *pos, int npts, T *dst,
+                          size_t lds, hipStream_t s);
   // per-tile determinant part of the ion derivatives
   static void ion_grad_det(int nob, const DevCtx &c, double *partial, int ntile, size_t lds,
                            hipStream_t s);

@@ -27,6 +27,7 @@ DMCX_FLAG_FP32_ENERGY = 2
 DMCX_N_ESTIMATORS = 11
 DMCX_NOALLOC_MAX_WALKERS = 1048576
 DMCX_N_JASTROW_PARAMS = 8
+DMCX_TILE_DEEP, DMCX_TILE_SHALLOW = 0, 1
 
 EXPORTED = [
     "dmcx_create", "dmcx_destroy", "dmcx_set_walkers", "dmcx_get_walkers", "dmcx_set_step",
@@ -37,7 +38,8 @@ EXPORTED = [
     "dmcx_autotune_report", "dmcx_get_delay_rank", "dmcx_reconfigure", "dmcx_estimators",
     "dmcx_zv_grads", "dmcx_forces_zv", "dmcx_estimators_noalloc",
     "dmcx_energy_escalations", "dmcx_set_et_feedback", "dmcx_get_trial_energy",
-    "dmcx_jastrow_param_grads", "dmcx_linear_method",
+    "dmcx_jastrow_param_grads", "dmcx_linear_method", "dmcx_set_tile_shape",
+    "dmcx_get_tile_shape",
 ]
 
 
@@ -110,7 +112,9 @@ def load():
         "dmcx_strerror": [I32],
         "dmcx_last_error": [P],
         "dmcx_autotune": [P, I32, P],
-        "dmcx_autotune_report": [P, I32, I32, P, P, P],
+        "dmcx_autotune_report": [P, I32, I32, P, P, P, P],
+        "dmcx_set_tile_shape": [P, I32, I32],
+        "dmcx_get_tile_shape": [P, I32, P],
         "dmcx_get_delay_rank": [P, I32, P],
         "dmcx_estimators": [P, P, I32],
         "dmcx_zv_grads": [P, I32, P, P, P, I32],
@@ -296,8 +300,16 @@ def dmcx_autotune(ctx, steps, chosen_k):
     return load().dmcx_autotune(ctx, steps, chosen_k)
 
 
-def dmcx_autotune_report(ctx, sys_index, max_n, ranks, ms, n_cand):
-    return load().dmcx_autotune_report(ctx, sys_index, max_n, ranks, ms, n_cand)
+def dmcx_autotune_report(ctx, sys_index, max_n, ranks, shapes, ms, n_cand):
+    return load().dmcx_autotune_report(ctx, sys_index, max_n, ranks, shapes, ms, n_cand)
+
+
+def dmcx_set_tile_shape(ctx, sys_index, shape):
+    return load().dmcx_set_tile_shape(ctx, sys_index, shape)
+
+
+def dmcx_get_tile_shape(ctx, sys_index, shape):
+    return load().dmcx_get_tile_shape(ctx, sys_index, shape)
 
 
 def dmcx_get_delay_rank(ctx, sys_index, k):
@@ -555,11 +567,22 @@ class Context:
         return k
 
     def autotune_report(self, sys_index=0):
-        r = np.zeros(16, dtype=np.int32)
-        t = np.zeros(16, dtype=np.float32)
+        """The tuner's candidates: (ranks, shapes, ms per sweep)."""
+        r = np.zeros(32, dtype=np.int32)
+        sh = np.zeros(32, dtype=np.int32)
+        t = np.zeros(32, dtype=np.float32)
         n = C.c_int32()
-        self.check(dmcx_autotune_report(self.h, sys_index, 16, _ptr(r), _ptr(t), C.byref(n)))
-        return r[:n.value].copy(), t[:n.value].copy()
+        self.check(dmcx_autotune_report(self.h, sys_index, 32, _ptr(r), _ptr(sh), _ptr(t),
+                                        C.byref(n)))
+        return r[:n.value].copy(), sh[:n.value].copy(), t[:n.value].copy()
+
+    def set_tile_shape(self, shape, sys_index=0):
+        self.check(dmcx_set_tile_shape(self.h, sys_index, int(shape)))
+
+    def tile_shape(self, sys_index=0):
+        v = C.c_int32()
+        self.check(dmcx_get_tile_shape(self.h, sys_index, C.byref(v)))
+        return int(v.value)
 
     def delay_rank(self, sys_index=0):
         k = C.c_int32()

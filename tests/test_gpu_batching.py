@@ -160,10 +160,11 @@ def test_autotuner_picks_a_candidate_and_preserves_the_run():
     ctx = dmcx.Context(s, W, delay_rank=0, recompute_period=64, seed=13)
     ctx.set_walkers(R)
     acc, el = ctx.run(2, mode=dmcx.DMCX_DMC, e_trial=-50.0, logs=True)  # tunes first
-    ranks, ms = ctx.autotune_report()
+    ranks, shapes, ms = ctx.autotune_report()
     k = ctx.delay_rank()
     print(f"[batching] autotune ranks {ranks.tolist()} ms {np.round(ms, 3).tolist()} -> k={k}")
     assert ranks.tolist() == [8, 16, 24, 32, 48, 56]
+    assert np.all(shapes == dmcx.DMCX_TILE_DEEP) and ctx.tile_shape() == dmcx.DMCX_TILE_DEEP
     assert np.all(ms > 0) and k in ranks.tolist()
     assert ms[ranks.tolist().index(k)] == ms.min()
     ref = dmcx.Context(s, W, delay_rank=k, recompute_period=64, seed=13)
@@ -180,3 +181,74 @@ def test_autotuner_picks_a_candidate_and_preserves_the_run():
     np.testing.assert_array_equal(lwa, lwb)
     _close(ctx.measure()[0], eb, rel=1e-9)
     assert kk[0] == ctx.delay_rank()
+
+
+def test_autotuner_chooses_tile_shape_and_rank_mixed():
+    """The FP32 sweep offers two tile shapes: the tuner times every (shape,
+    rank) pair and keeps the fastest; a run after it is bit-identical to a
+    run of a fresh context given that shape and rank."""
+    s = synth.large_molecule()
+    W = 64
+    R = synth.make_walkers(s, W, 761)
+    ctx = dmcx.Context(s, W, precision=dmcx.DMCX_MIXED, delay_rank=0, recompute_period=32,
+                       seed=14)
+    ctx.set_walkers(R)
+    acc, el = ctx.run(2, mode=dmcx.DMCX_DMC, e_trial=-50.0, logs=True)
+    ranks, shapes, ms = ctx.autotune_report()
+    k, shape = ctx.delay_rank(), ctx.tile_shape()
+    print(f"[batching] mixed autotune {list(zip(shapes.tolist(), ranks.tolist()))} "
+          f"ms {np.round(ms, 3).tolist()} -> shape {shape}, k={k}", flush=True)
+    assert sorted(set(shapes.tolist())) == [dmcx.DMCX_TILE_DEEP, dmcx.DMCX_TILE_SHALLOW]
+    assert ranks.tolist() == [8, 16, 24, 32, 48, 56] * 2
+    best = int(np.argmin(ms))
+    assert (shapes[best], ranks[best]) == (shape, k)
+    ref = dmcx.Context(s, W, precision=dmcx.DMCX_MIXED, delay_rank=k, recompute_period=32,
+                       seed=14)
+    ref.set_tile_shape(shape)
+    ref.set_walkers(R)
+    acc_r, el_r = ref.run(2, mode=dmcx.DMCX_DMC, e_trial=-50.0, logs=True)
+    np.testing.assert_array_equal(acc, acc_r)
+    np.testing.assert_array_equal(el, el_r)
+
+
+@pytest.mark.parametrize("shape", [0, 1])
+def test_tile_shapes_mixed_against_oracle(shape):
+    """Both tile shapes of the FP32 sweep: VMC steps against the oracle run
+    on the same stream (every walker's accept sequence equal to the oracle's
+    but for at most two walkers, where a near-threshold FP32 ratio may fall
+    the other way; energies of the final configurations within the mixed
+    form's bar)."""
+    s = synth.small_molecule()
+    W = 48
+    R = synth.make_walkers(s, W, 762)
+    ctx = dmcx.Context(s, W, precision=dmcx.DMCX_MIXED, delay_rank=2, recompute_period=4,
+                       seed=15, tau=0.02)
+    ctx.set_tile_shape(shape)
+    assert ctx.tile_shape() == shape
+    ctx.set_walkers(R)
+    acc, _ = ctx.run(3, mode=dmcx.DMCX_VMC, logs=True)
+    ref = oracle.run(s, R, n_steps=3, mode=0, tau=0.02, seed=15)
+    same = np.all(acc == ref["accept_log"], axis=(0, 2))
+    print(f"[batching] shape {shape}: {same.sum()} of {W} walkers with the oracle's accept "
+          f"sequence", flush=True)
+    assert same.sum() >= W - 2
+    Rg, _ = ctx.get_walkers()
+    e = ctx.measure()[0]
+    _, _, eo, _ = oracle.evaluate_batch(s, Rg)
+    ne = s.n_up + s.n_dn
+    assert abs(np.mean(e - eo)) / ne <= 1e-6
+    assert np.all(np.abs(e - eo) <= 1e-5 * np.maximum(np.abs(eo), ne))
+
+
+def test_tile_shape_errors():
+    s = synth.small_molecule()
+    ctx = dmcx.Context(s, 8)  # FP64: deep only
+    with pytest.raises(dmcx.DmcxError) as e:
+        ctx.set_tile_shape(dmcx.DMCX_TILE_SHALLOW)
+    assert e.value.status == dmcx.DMCX_E_UNSUPPORTED
+    for bad in (2, -1):
+        with pytest.raises(dmcx.DmcxError):
+            ctx.set_tile_shape(bad)
+    with pytest.raises(dmcx.DmcxError):
+        ctx.set_tile_shape(0, sys_index=1)
+    ctx.set_tile_shape(dmcx.DMCX_TILE_DEEP)
