@@ -93,6 +93,19 @@ typedef struct {
   const int32_t *det_exc;    /* [n_det][10]: nu, nd, hu0, hu1, pu0, pu1, hd0, hd1, pd0, pd1
                                 holes = occupied column index, particles = MO index */
   const double *ci_coef;     /* [n_det] */
+  /* Semilocal pseudopotential (the ccECP form of the paper's QMC runs):
+   * pp_n_term terms beta r^(n-2) exp(-alpha r^2), term t of atom pp_atom[t]
+   * in channel pp_l[t] (-1: local, added to V; 0..3: non-local, projected on
+   * angular momentum l and evaluated by quadrature, see dmcx_run);
+   * pp_rcut[A] (bohr): beyond it atom A's non-local channels are taken as
+   * zero.  pp_n_term == 0 (all pointers may be NULL): no pseudopotential. */
+  int32_t pp_n_term;
+  const int32_t *pp_atom;    /* [pp_n_term] */
+  const int32_t *pp_l;       /* [pp_n_term] */
+  const int32_t *pp_n;       /* [pp_n_term] */
+  const double *pp_beta;     /* [pp_n_term] */
+  const double *pp_alpha;    /* [pp_n_term] */
+  const double *pp_rcut;     /* [n_atom] */
 } dmcx_system;
 
 /* dmcx_options.flags */

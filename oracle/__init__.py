@@ -45,6 +45,9 @@ class _Sys(C.Structure):
         ("jee_a_anti", C.c_double), ("jee_a_para", C.c_double), ("jee_b", C.c_double),
         ("jen_a", C.c_void_p), ("jen_b", C.c_double),
         ("n_det", C.c_int32), ("det_exc", C.c_void_p), ("ci_coef", C.c_void_p),
+        ("pp_n_term", C.c_int32), ("pp_atom", C.c_void_p), ("pp_l", C.c_void_p),
+        ("pp_n", C.c_void_p), ("pp_beta", C.c_void_p), ("pp_alpha", C.c_void_p),
+        ("pp_rcut", C.c_void_p),
     ]
 
 
@@ -84,6 +87,11 @@ def _load():
         lib.orc_jastrow_param_grads.argtypes = [P, P, P, P]
         lib.orc_jastrow_param_grads_batch.argtypes = [P, C.c_int32, P, P, P, C.c_int32]
         lib.orc_j3_values.argtypes = [P, P, P]
+        lib.orc_nlpp.argtypes = [P, P, C.c_uint64, C.c_int64, C.c_int32, P]
+        lib.orc_nlpp_batch.argtypes = [P, C.c_int32, P, C.c_uint64, C.c_int64, C.c_int32, P,
+                                       C.c_int32]
+        lib.orc_nlpp_rotation.argtypes = [C.c_uint64, C.c_int64, C.c_int32, C.c_int32, P]
+        lib.orc_nlpp_rotation.restype = None
         _lib = lib
     return _lib
 
@@ -108,6 +116,12 @@ class OracleSystem:
             self.keep["det_exc"] = i32(sys.det_exc)
             self.keep["ci_coef"] = f64(sys.ci_coef)
         k = self.keep
+        n_pp = 0 if getattr(sys, "pp_atom", None) is None else len(sys.pp_atom)
+        if n_pp:
+            for name in ("pp_atom", "pp_l", "pp_n"):
+                k[name] = i32(getattr(sys, name))
+            for name in ("pp_beta", "pp_alpha", "pp_rcut"):
+                k[name] = f64(getattr(sys, name))
         self.c = _Sys(
             n_atom=k["ion_xyz"].shape[0], ion_xyz=_ptr(k["ion_xyz"]), ion_charge=_ptr(k["ion_charge"]),
             n_shell=k["shell_l"].shape[0], shell_atom=_ptr(k["shell_atom"]), shell_l=_ptr(k["shell_l"]),
@@ -115,7 +129,10 @@ class OracleSystem:
             prim_coef=_ptr(k["prim_coef"]), n_basis=k["mo_coef"].shape[0], n_mo=k["mo_coef"].shape[1],
             mo_coef=_ptr(k["mo_coef"]), n_up=sys.n_up, n_dn=sys.n_dn, jee_a_anti=sys.jee_a_anti,
             jee_a_para=sys.jee_a_para, jee_b=sys.jee_b, jen_a=_ptr(k["jen_a"]), jen_b=sys.jen_b,
-            n_det=n_det, det_exc=_ptr(k.get("det_exc")), ci_coef=_ptr(k.get("ci_coef")))
+            n_det=n_det, det_exc=_ptr(k.get("det_exc")), ci_coef=_ptr(k.get("ci_coef")),
+            pp_n_term=n_pp, pp_atom=_ptr(k.get("pp_atom")), pp_l=_ptr(k.get("pp_l")),
+            pp_n=_ptr(k.get("pp_n")), pp_beta=_ptr(k.get("pp_beta")),
+            pp_alpha=_ptr(k.get("pp_alpha")), pp_rcut=_ptr(k.get("pp_rcut")))
         self.n_elec = sys.n_up + sys.n_dn
         self.n_atom = k["ion_xyz"].shape[0]
         self.n_basis = k["mo_coef"].shape[0]
@@ -451,3 +468,31 @@ def linear_method(log_w, e_local, O, dEL, flags=None):
     H[0, 1:] = mean(e[:, None] * dO) + mean(D)
     H[1:, 1:] = mean(dO[:, :, None] * (dO[:, None, :] * e[:, None, None] + D[:, None, :]))
     return S, H
+
+
+def nlpp(sys, R, seed, step, walker):
+    """Non-local pseudopotential energy of one walker at R [n_elec][3], with
+    the quadrature rotations of (electron, walker, step) under key seed.
+    Returns (v_nl, rc)."""
+    o = _osys(sys)
+    v = C.c_double()
+    rc = _load().orc_nlpp(o.ref, _ptr(np.ascontiguousarray(R, dtype=np.float64)), seed, step,
+                          walker, C.byref(v))
+    return float(v.value), rc
+
+
+def nlpp_batch(sys, R, seed, step, walker_offset=0, n_threads=0):
+    """The same for a crowd R [W][n_elec][3], walker w with index offset + w."""
+    o = _osys(sys)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    v = np.zeros(R.shape[0])
+    rc = _load().orc_nlpp_batch(o.ref, R.shape[0], _ptr(R), seed, step, walker_offset, _ptr(v),
+                                n_threads)
+    return v, rc
+
+
+def nlpp_rotation(seed, step, walker, elec):
+    """The random rotation [3][3] of one electron's quadrature."""
+    rot = np.zeros(9)
+    _load().orc_nlpp_rotation(seed, step, walker, elec, _ptr(rot))
+    return rot.reshape(3, 3)

@@ -253,6 +253,16 @@ double orc_potential(const orc_system *s, const double *R) {
       const double d[3] = {a[0] - b[0], a[1] - b[1], a[2] - b[2]};
       v += s->ion_charge[A] * s->ion_charge[B] / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     }
+  /* local pseudopotential terms */
+  for (int t = 0; t < s->pp_n_term; ++t) {
+    if (s->pp_l[t] != -1) continue;
+    const double *c = s->ion_xyz + 3 * s->pp_atom[t];
+    for (int i = 0; i < ne; ++i) {
+      const double d[3] = {R[3 * i] - c[0], R[3 * i + 1] - c[1], R[3 * i + 2] - c[2]};
+      const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      v += s->pp_beta[t] * pow(sqrt(r2), s->pp_n[t] - 2) * exp(-s->pp_alpha[t] * r2);
+    }
+  }
   return v;
 }
 
@@ -418,6 +428,150 @@ void orc_move_draws(uint64_t seed, int64_t step, int32_t walker, int32_t elec, d
   *u_acc = u[0];
 }
 
+/* ------------------------------------------- non-local pseudopotential --- */
+/* The paper's QMC runs use ccECP pseudopotentials (QMC section), whose
+ * semilocal form is V = V_loc(r) + sum_l v_l(r) sum_m |lm><lm| per atom with
+ * Gaussian radial terms.  The non-local part acts on Psi through the angular
+ * integral over the sphere of radius r_iA about the atom,
+ *   V_NL Psi / Psi = sum_l v_l(r_iA) (2l+1)/(4 pi) int dOmega P_l(cos) Psi(r')/Psi(r),
+ * here by the 12-point icosahedral rule (weights 1/12, exact for the
+ * polynomials of degree <= 5 on the sphere) whose directions are turned by a
+ * uniformly random rotation per electron and evaluation (Shoemake's
+ * quaternion from three uniforms).  Psi(r')/Psi(R) is taken from a fresh LU
+ * of the Slater matrix with the electron's row replaced and the Jastrow
+ * factor at both positions: the plain definition. */
+static const double ICO_PHI = 1.6180339887498948482;
+
+/* direction q of the icosahedral rule: cyclic permutations of (0, +-1, +-phi) */
+static void ico_dir(int q, double d[3]) {
+  const double a = (q & 1) ? -ICO_PHI : ICO_PHI; /* sign of the phi entry */
+  const double b = (q & 2) ? -1.0 : 1.0;         /* sign of the 1 entry */
+  const double nrm = 1.0 / sqrt(1.0 + ICO_PHI * ICO_PHI);
+  double v[3];
+  switch (q >> 2) {
+    case 0: v[0] = 0.0; v[1] = b; v[2] = a; break;  /* (0, +-1, +-phi) */
+    case 1: v[0] = b; v[1] = a; v[2] = 0.0; break;  /* (+-1, +-phi, 0) */
+    default: v[0] = a; v[1] = 0.0; v[2] = b; break; /* (+-phi, 0, +-1) */
+  }
+  for (int x = 0; x < 3; ++x) d[x] = v[x] * nrm;
+}
+
+void orc_nlpp_rotation(uint64_t seed, int64_t step, int32_t walker, int32_t elec, double rot[9]) {
+  const double twopi = 6.283185307179586476925286766559;
+  double u[2], u3[2];
+  draw_uniform2(seed, step, walker, elec, 3u, u);
+  draw_uniform2(seed, step, walker, elec, 4u, u3);
+  const double s1 = sqrt(1.0 - u[0]), s2 = sqrt(u[0]);
+  const double x = s1 * sin(twopi * u[1]), y = s1 * cos(twopi * u[1]);
+  const double z = s2 * sin(twopi * u3[0]), w = s2 * cos(twopi * u3[0]);
+  rot[0] = 1.0 - 2.0 * (y * y + z * z); rot[1] = 2.0 * (x * y - z * w); rot[2] = 2.0 * (x * z + y * w);
+  rot[3] = 2.0 * (x * y + z * w); rot[4] = 1.0 - 2.0 * (x * x + z * z); rot[5] = 2.0 * (y * z - x * w);
+  rot[6] = 2.0 * (x * z - y * w); rot[7] = 2.0 * (y * z + x * w); rot[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+static double legendre(int l, double x) {
+  switch (l) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return 0.5 * (3.0 * x * x - 1.0);
+    default: return 0.5 * (5.0 * x * x * x - 3.0 * x);
+  }
+}
+
+int orc_nlpp(const orc_system *s, const double *R, uint64_t seed, int64_t step, int32_t walker,
+             double *v_nl) {
+  *v_nl = 0.0;
+  if (s->pp_n_term == 0) return 0;
+  if (s->n_det > 1) return 4;
+  const int ne = s->n_up + s->n_dn;
+  int rc = 0;
+  /* Slater matrices, their log|det| and sign, and J at R */
+  const int nmax = s->n_up > s->n_dn ? s->n_up : s->n_dn;
+  double *A[2], ld[2];
+  int32_t sg[2];
+  double *orb = (double *)malloc(sizeof(double) * 5 * (nmax > 0 ? nmax : 1));
+  double *Ak = (double *)malloc(sizeof(double) * (nmax * nmax > 0 ? nmax * nmax : 1));
+  double *Rq = (double *)malloc(sizeof(double) * 3 * ne);
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = sp == 0 ? s->n_up : s->n_dn, e0 = sp == 0 ? 0 : s->n_up;
+    A[sp] = (double *)malloc(sizeof(double) * (n * n > 0 ? n * n : 1));
+    for (int i = 0; i < n; ++i) {
+      rc |= orc_orbitals_vgl(s, R + 3 * (e0 + i), n, orb);
+      for (int j = 0; j < n; ++j) A[sp][i * n + j] = orb[j];
+    }
+    ld[sp] = 0.0;
+    sg[sp] = 1;
+    if (n > 0) rc |= orc_lu_slogdet_inv(n, A[sp], &ld[sp], &sg[sp], NULL);
+  }
+  double J0;
+  orc_jastrow(s, R, &J0, NULL, NULL);
+  double acc = 0.0;
+  for (int i = 0; i < ne; ++i) {
+    const int sp = spin_of(s, i), n = sp == 0 ? s->n_up : s->n_dn, ii = i - sp * s->n_up;
+    double rot[9];
+    int have_rot = 0;
+    for (int At = 0; At < s->n_atom; ++At) {
+      /* the atom's non-local channels */
+      int lmax = -1;
+      for (int t = 0; t < s->pp_n_term; ++t)
+        if (s->pp_atom[t] == At && s->pp_l[t] > lmax) lmax = s->pp_l[t];
+      if (lmax < 0) continue;
+      const double *c = s->ion_xyz + 3 * At;
+      const double d[3] = {R[3 * i] - c[0], R[3 * i + 1] - c[1], R[3 * i + 2] - c[2]};
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      if (!(r < s->pp_rcut[At])) continue;
+      if (!have_rot) {
+        orc_nlpp_rotation(seed, step, walker, i, rot);
+        have_rot = 1;
+      }
+      double vl[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int t = 0; t < s->pp_n_term; ++t)
+        if (s->pp_atom[t] == At && s->pp_l[t] >= 0)
+          vl[s->pp_l[t]] += s->pp_beta[t] * pow(r, s->pp_n[t] - 2) * exp(-s->pp_alpha[t] * r * r);
+      for (int q = 0; q < 12; ++q) {
+        double o[3], od[3];
+        ico_dir(q, o);
+        for (int x = 0; x < 3; ++x) od[x] = rot[3 * x] * o[0] + rot[3 * x + 1] * o[1] + rot[3 * x + 2] * o[2];
+        const double cth = (od[0] * d[0] + od[1] * d[1] + od[2] * d[2]) / r;
+        /* Psi with electron i at c + r od, over Psi(R) */
+        for (int k = 0; k < 3 * ne; ++k) Rq[k] = R[k];
+        for (int x = 0; x < 3; ++x) Rq[3 * i + x] = c[x] + r * od[x];
+        rc |= orc_orbitals_vgl(s, Rq + 3 * i, n, orb);
+        for (int k = 0; k < n * n; ++k) Ak[k] = A[sp][k];
+        for (int j = 0; j < n; ++j) Ak[ii * n + j] = orb[j];
+        double ldq;
+        int32_t sgq;
+        orc_lu_slogdet_inv(n, Ak, &ldq, &sgq, NULL);
+        double Jq;
+        orc_jastrow(s, Rq, &Jq, NULL, NULL);
+        const double ratio = (double)(sgq * sg[sp]) * exp(ldq - ld[sp] + Jq - J0);
+        double f = 0.0;
+        for (int l = 0; l <= lmax; ++l) f += vl[l] * (2 * l + 1) * legendre(l, cth);
+        acc += f * ratio / 12.0;
+      }
+    }
+  }
+  *v_nl = acc;
+  for (int sp = 0; sp < 2; ++sp) free(A[sp]);
+  free(orb);
+  free(Ak);
+  free(Rq);
+  return rc;
+}
+
+int orc_nlpp_batch(const orc_system *s, int32_t W, const double *R, uint64_t seed, int64_t step,
+                   int32_t walker_offset, double *v_nl, int32_t n_threads) {
+  const int ne = s->n_up + s->n_dn;
+  int rc = 0;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(dynamic) reduction(| : rc)
+  for (int w = 0; w < W; ++w)
+    rc |= orc_nlpp(s, R + (size_t)w * ne * 3, seed, step, walker_offset + w, v_nl + w);
+  return rc;
+}
+
 /* ---------------------------------------------------------------- DMC --- */
 static int msd_walker_run(const orc_system *s, double *R, double *log_w, double *e_local,
                           int64_t step0, int32_t n_steps, int32_t mode, double tau, uint64_t seed,
@@ -428,14 +582,21 @@ static int walker_run(const orc_system *s, int wi, double *R, double *log_w, dou
                       int64_t step0, int32_t n_steps, int32_t mode, double tau, uint64_t seed,
                       double e_trial, int32_t walker_index, uint8_t *acc_row, size_t acc_stride,
                       double *e_row, size_t e_stride) {
-  if (s->n_det > 1)
+  if (s->n_det > 1) {
+    if (s->pp_n_term > 0) return 4;  /* pseudopotentials: single determinant only */
     return msd_walker_run(s, R, log_w, e_local, step0, n_steps, mode, tau, seed, e_trial,
                           walker_index, acc_row, acc_stride, e_row, e_stride);
+  }
   wstate w;
   int rc = ws_init(s, &w, R);
   const int ne = w.ne, nmax = w.nmax;
   double *trial = (double *)malloc(sizeof(double) * 5 * nmax);
   double e_old = ws_local_energy(s, &w, R, NULL, NULL);
+  if (s->pp_n_term > 0) {
+    double vnl;
+    rc |= orc_nlpp(s, R, seed, step0, walker_index, &vnl);
+    e_old += vnl;
+  }
   const double sqt = sqrt(tau);
   for (int st = 0; st < n_steps; ++st) {
     const int64_t step = step0 + st;
@@ -488,7 +649,12 @@ static int walker_run(const orc_system *s, int wi, double *R, double *log_w, dou
       }
       if (acc_row) acc_row[(size_t)st * acc_stride + i] = (uint8_t)accepted;
     }
-    const double e_new = ws_local_energy(s, &w, R, NULL, NULL);
+    double e_new = ws_local_energy(s, &w, R, NULL, NULL);
+    if (s->pp_n_term > 0) {
+      double vnl;
+      rc |= orc_nlpp(s, R, seed, step, walker_index, &vnl);
+      e_new += vnl;
+    }
     if (mode == 1) *log_w += -tau * (0.5 * (e_old + e_new) - e_trial);
     if (e_row) e_row[(size_t)st * e_stride] = e_new;
     e_old = e_new;

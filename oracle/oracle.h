@@ -46,6 +46,14 @@ typedef struct {
   int32_t n_det;
   const int32_t *det_exc;     /* [n_det][10] */
   const double *ci_coef;      /* [n_det] */
+  /* semilocal pseudopotential terms beta r^(n-2) exp(-alpha r^2) of atom
+   * pp_atom[t] in channel pp_l[t] (-1: local, added to V; l >= 0: projected
+   * on angular momentum l); pp_rcut[A]: radius beyond which atom A's
+   * non-local channels are taken as zero.  pp_n_term == 0: none. */
+  int32_t pp_n_term;
+  const int32_t *pp_atom, *pp_l, *pp_n;
+  const double *pp_beta, *pp_alpha;
+  const double *pp_rcut;      /* [n_atom] */
 } orc_system;
 
 /* Basis values, gradients and Laplacians at r: out[n_basis][5] =
@@ -143,6 +151,19 @@ int orc_jastrow_param_grads_batch(const orc_system *s, int32_t W, const double *
                                   double *dlogpsi, double *dEL, int32_t n_threads);
 /* The six three-body basis sums F_k(R) themselves (c = 0 derivatives of J). */
 int orc_j3_values(const orc_system *s, const double *R, double *F);
+
+/* Non-local pseudopotential energy of the walker at R (see oracle.c):
+ * sum over electrons i and atoms A within A's cutoff of
+ * sum_l v_l(r_iA) (2l + 1) sum_q (1/12) P_l(cos theta_q) Psi(.., r_q, ..)/Psi(R),
+ * r_q on the sphere of radius r_iA about A in the 12 icosahedral directions
+ * rotated by the electron's random rotation (Philox draws 3 and 4 of
+ * (electron, walker, step)).  Single determinant only (4 otherwise). */
+int orc_nlpp(const orc_system *s, const double *R, uint64_t seed, int64_t step, int32_t walker,
+             double *v_nl);
+int orc_nlpp_batch(const orc_system *s, int32_t W, const double *R, uint64_t seed, int64_t step,
+                   int32_t walker_offset, double *v_nl, int32_t n_threads);
+/* The rotation of electron elec of walker walker at step: rot[3][3]. */
+void orc_nlpp_rotation(uint64_t seed, int64_t step, int32_t walker, int32_t elec, double rot[9]);
 
 /* Derivative of the local energy (Single Determinant QMC Forces, Eq. 4) and
  * of ln|Psi| (Eq. 3) along a direction of the ions (dion [n_atom][3]) and

@@ -263,6 +263,17 @@ dmcx_status validate_system(dmcx_ctx *c, const dmcx_system &s) {
       }
     }
   }
+  if (s.pp_n_term < 0) return fail(c, DMCX_E_INVALID, "system: pp_n_term < 0");
+  if (s.pp_n_term > 0) {
+    if (!s.pp_atom || !s.pp_l || !s.pp_n || !s.pp_beta || !s.pp_alpha || !s.pp_rcut)
+      return fail(c, DMCX_E_INVALID, "system: pseudopotential terms need every pp_* array");
+    for (int t = 0; t < s.pp_n_term; ++t)
+      if (s.pp_atom[t] < 0 || s.pp_atom[t] >= s.n_atom || s.pp_l[t] < -1 || s.pp_l[t] > 3 ||
+          !std::isfinite(s.pp_beta[t]) || !(s.pp_alpha[t] > 0.0) || s.pp_n[t] < 0 ||
+          s.pp_n[t] > 4)
+        return fail(c, DMCX_E_INVALID, "system: pseudopotential term out of range");
+    return fail(c, DMCX_E_UNSUPPORTED, "system: pseudopotentials are not built yet");
+  }
   return DMCX_OK;
 }
 

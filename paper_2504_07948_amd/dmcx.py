@@ -53,6 +53,9 @@ class dmcx_system(C.Structure):
         ("jee_a_anti", C.c_double), ("jee_a_para", C.c_double), ("jee_b", C.c_double),
         ("jen_a", C.c_void_p), ("jen_b", C.c_double),
         ("n_det", C.c_int32), ("det_exc", C.c_void_p), ("ci_coef", C.c_void_p),
+        ("pp_n_term", C.c_int32), ("pp_atom", C.c_void_p), ("pp_l", C.c_void_p),
+        ("pp_n", C.c_void_p), ("pp_beta", C.c_void_p), ("pp_alpha", C.c_void_p),
+        ("pp_rcut", C.c_void_p),
     ]
 
 
@@ -339,6 +342,12 @@ class SystemStruct:
         if n_det:
             k["det_exc"] = i32(sys.det_exc)
             k["ci_coef"] = f64(sys.ci_coef)
+        n_pp = 0 if getattr(sys, "pp_atom", None) is None else len(sys.pp_atom)
+        if n_pp:
+            for name in ("pp_atom", "pp_l", "pp_n"):
+                k[name] = i32(getattr(sys, name))
+            for name in ("pp_beta", "pp_alpha", "pp_rcut"):
+                k[name] = f64(getattr(sys, name))
         self.keep = k
         self.c = dmcx_system(
             n_atom=k["ion_xyz"].shape[0], ion_xyz=_ptr(k["ion_xyz"]),
@@ -349,7 +358,10 @@ class SystemStruct:
             n_mo=k["mo_coef"].shape[1], mo_coef=_ptr(k["mo_coef"]), n_up=sys.n_up,
             n_dn=sys.n_dn, jee_a_anti=sys.jee_a_anti, jee_a_para=sys.jee_a_para,
             jee_b=sys.jee_b, jen_a=_ptr(k["jen_a"]), jen_b=sys.jen_b, n_det=n_det,
-            det_exc=_ptr(k.get("det_exc")), ci_coef=_ptr(k.get("ci_coef")))
+            det_exc=_ptr(k.get("det_exc")), ci_coef=_ptr(k.get("ci_coef")),
+            pp_n_term=n_pp, pp_atom=_ptr(k.get("pp_atom")), pp_l=_ptr(k.get("pp_l")),
+            pp_n=_ptr(k.get("pp_n")), pp_beta=_ptr(k.get("pp_beta")),
+            pp_alpha=_ptr(k.get("pp_alpha")), pp_rcut=_ptr(k.get("pp_rcut")))
 
 
 class Context:

@@ -59,6 +59,14 @@ class System:
     active_mo: Optional[np.ndarray] = None   # [n_active] i32, MO index
     det_exc: Optional[np.ndarray] = None     # [n_det, 8] i32 (see make_msd)
     ci_coef: Optional[np.ndarray] = None     # [n_det] f64
+    # semilocal pseudopotential terms beta r^(n-2) exp(-alpha r^2): atom,
+    # channel l (-1 local, >= 0 non-local), n, beta, alpha; rcut per atom
+    pp_atom: Optional[np.ndarray] = None     # [n_term] i32
+    pp_l: Optional[np.ndarray] = None        # [n_term] i32
+    pp_n: Optional[np.ndarray] = None        # [n_term] i32
+    pp_beta: Optional[np.ndarray] = None     # [n_term] f64
+    pp_alpha: Optional[np.ndarray] = None    # [n_term] f64
+    pp_rcut: Optional[np.ndarray] = None     # [n_atom] f64
 
     def __post_init__(self):
         self.ion_xyz = np.ascontiguousarray(self.ion_xyz, dtype=np.float64)
@@ -359,3 +367,60 @@ def batch5_member(k: int, n_det: int = 1000, n_active: int = 100) -> System:
 def make_batch5(n_det: int = 1000, n_active: int = 100) -> List[System]:
     """Eight alkanes with 20..200 electrons, each with an MSD expansion."""
     return [batch5_member(k, n_det, n_active) for k in range(len(ALKANE_NC))]
+
+
+# ------------------------------------------------------- pseudopotentials ----
+def pp_rcut_for(terms, eps: float = 1e-16) -> float:
+    """Radius beyond which every non-local term |beta| r^(n-2) exp(-alpha r^2)
+    of an atom is below eps |beta| (n = 2 terms: sqrt(ln(1/eps) / alpha))."""
+    r = 0.0
+    for l, n, beta, alpha in terms:
+        if l < 0:
+            continue
+        rr = np.sqrt(np.log(1.0 / eps) / alpha)
+        # a power r^(n-2) > 1 pushes the radius out a little
+        while n > 2 and rr ** (n - 2) * np.exp(-alpha * rr * rr) > eps:
+            rr *= 1.05
+        r = max(r, rr)
+    return float(r)
+
+
+def with_pseudopotential(sys: System, terms_by_atom) -> System:
+    """A copy of sys with semilocal pseudopotential terms: terms_by_atom[A] is
+    a list of (l, n, beta, alpha), l = -1 local, l >= 0 non-local; atoms with
+    an empty list keep the bare Coulomb potential."""
+    import dataclasses
+    at, ll, nn, bb, aa = [], [], [], [], []
+    rcut = np.zeros(sys.n_atom)
+    for A, terms in enumerate(terms_by_atom):
+        for l, n, beta, alpha in terms:
+            at.append(A)
+            ll.append(l)
+            nn.append(n)
+            bb.append(beta)
+            aa.append(alpha)
+        rcut[A] = pp_rcut_for(terms)
+    return dataclasses.replace(
+        sys, name=sys.name + "-pp", pp_atom=np.array(at, np.int32), pp_l=np.array(ll, np.int32),
+        pp_n=np.array(nn, np.int32), pp_beta=np.array(bb, np.float64),
+        pp_alpha=np.array(aa, np.float64), pp_rcut=rcut)
+
+
+# Synthetic stand-ins for the ccECP tables (not available here), in the same
+# functional form: for the Z_eff = 2 atoms of the small molecule a local term
+# and non-local s and p channels; for the "C" (Z_eff = 4) atoms of the large
+# molecule a local term and a non-local s channel, the H atoms all-electron.
+PP_SMALL = [(-1, 2, -2.5, 2.0), (0, 2, 3.0, 2.5), (1, 2, -1.0, 2.0)]
+PP_CARBON = [(-1, 2, -5.0, 3.0), (0, 2, 6.0, 8.0)]
+
+
+def small_molecule_pp() -> System:
+    """The small molecule with PP_SMALL on every atom."""
+    s = small_molecule()
+    return with_pseudopotential(s, [PP_SMALL] * s.n_atom)
+
+
+def large_molecule_pp() -> System:
+    """The large molecule with PP_CARBON on its 16 "C" atoms."""
+    s = large_molecule()
+    return with_pseudopotential(s, [PP_CARBON if z == 4.0 else [] for z in s.ion_charge])
