@@ -15,6 +15,7 @@
 #include "estimators.h"
 #include "forces_aux.h"
 #include "jparams.h"
+#include "pp.h"
 #include "kernels.h"
 #include "launch.h"
 #include "msd.h"
@@ -98,6 +99,9 @@ struct dmcx_ctx {
   // version); the linear-method matrices S, H [2][NJP + 1][NJP + 1] followed
   // by their merged means and block records
   double *d_jo = nullptr, *d_jd = nullptr, *d_lm = nullptr;
+  // pseudopotential: y_e = C (A^{-1})_{:,e} per walker and electron [W][ne][pp_ldy]
+  double *d_ppY = nullptr;
+  int pp_ldy = 0;
   uint64_t jp_version = 0;
   // weighted estimators: block records [est_blocks(W)][EST_PART], host staging [EST_OUT]
   double *d_est_part = nullptr, *d_est_out = nullptr;
@@ -272,7 +276,9 @@ dmcx_status validate_system(dmcx_ctx *c, const dmcx_system &s) {
           !std::isfinite(s.pp_beta[t]) || !(s.pp_alpha[t] > 0.0) || s.pp_n[t] < 0 ||
           s.pp_n[t] > 4)
         return fail(c, DMCX_E_INVALID, "system: pseudopotential term out of range");
-    return fail(c, DMCX_E_UNSUPPORTED, "system: pseudopotentials are not built yet");
+    if (s.n_det > 1)
+      return fail(c, DMCX_E_UNSUPPORTED,
+                  "system: pseudopotentials with a multideterminant expansion are not built");
   }
   return DMCX_OK;
 }
@@ -533,8 +539,32 @@ __global__ void k_esc_reset(int *count) {
 // with its FP64 energy lists the walkers whose FP32 derivative rows could
 // move E_L by more than ESC_CAP per electron and recomputes their E_L (and
 // weight update) from FP64 rows.
+// Pseudopotential energy of every walker (c.vps) at the current
+// configuration, from the current inverses.
+dmcx_status launch_pp(dmcx_ctx *c) {
+  if (c->dc.pp_n == 0) return DMCX_OK;
+  if (c->dc.pp_nl > 0) {
+    const dim3 gy(c->W, 2, (c->dc.B.Kp + 63) / 64);
+    if (!c->mixed)
+      hipLaunchKernelGGL(k_pp_y<double>, gy, dim3(256), 0, c->stream, c->dc,
+                         (const double *)c->dc.GT, c->d_ppY, c->pp_ldy);
+    else if (c->fp64e)
+      hipLaunchKernelGGL(k_pp_y<double>, gy, dim3(256), 0, c->stream, c->dc,
+                         (const double *)c->d_G64, c->d_ppY, c->pp_ldy);
+    else
+      hipLaunchKernelGGL(k_pp_y<float>, gy, dim3(256), 0, c->stream, c->dc,
+                         (const float *)c->dc.GT, c->d_ppY, c->pp_ldy);
+    HIP_TRY(c, hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_pp, dim3(c->W), dim3(NT_AUX), pp_lds_bytes(c->ne, c->dc.pp_nl), c->stream,
+                     c->dc, (const double *)c->d_ppY, c->pp_ldy);
+  return hip_check(c, hipGetLastError(), "pseudopotential launch");
+}
+
 dmcx_status launch_local_energy(dmcx_ctx *c, int measure_only, double *e_log = nullptr,
                                 long long elog_ss = 0) {
+  dmcx_status st0 = launch_pp(c);
+  if (st0) return st0;
   if (!c->mixed) {
     if (c->dc.M.on)
       hipLaunchKernelGGL((k_local_energy<double, 1024>), dim3(c->Wpad), dim3(1024), 0, c->stream,
@@ -702,6 +732,8 @@ dmcx_status refresh_after_moves(dmcx_ctx *c) {
 
 // Per-walker ion derivatives for the current configuration (cached).
 dmcx_status compute_ion_grads(dmcx_ctx *c) {
+  if (c->dc.pp_n > 0)
+    return fail(c, DMCX_E_UNSUPPORTED, "ion derivatives of pseudopotentials are not built");
   dmcx_status st0 = refresh_after_moves(c);
   if (st0) return st0;
   if (c->grads_version == c->version) return DMCX_OK;
@@ -781,6 +813,9 @@ dmcx_status compute_zv(dmcx_ctx *c, int warp) {
 // Per-walker Jastrow parameter derivatives of the current configuration
 // (cached per configuration version) in d_jo / d_jd.
 dmcx_status compute_jparams(dmcx_ctx *c) {
+  if (c->dc.pp_n > 0)
+    return fail(c, DMCX_E_UNSUPPORTED,
+                "Jastrow parameter derivatives: the non-local energy's are not built");
   if (c->dc.M.on)
     return fail(c, DMCX_E_UNSUPPORTED,
                 "Jastrow parameter derivatives: single-determinant systems only");
@@ -1079,6 +1114,48 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
   if ((st = dalloc(c, &d.logw, Wp))) return bail(st);
   if ((st = dalloc(c, &d.logpsi, Wp))) return bail(st);
   if ((st = dalloc(c, &d.vpot, Wp))) return bail(st);
+  if (s.pp_n_term > 0) {
+    std::vector<int4> pt(s.pp_n_term);
+    std::vector<double2> pb(s.pp_n_term);
+    std::vector<int> nl;
+    for (int t = 0; t < s.pp_n_term; ++t) {
+      pt[t] = make_int4(s.pp_atom[t], s.pp_l[t], s.pp_n[t], 0);
+      pb[t] = make_double2(s.pp_beta[t], s.pp_alpha[t]);
+    }
+    for (int a = 0; a < s.n_atom; ++a)
+      for (int t = 0; t < s.pp_n_term; ++t)
+        if (s.pp_atom[t] == a && s.pp_l[t] >= 0) {
+          nl.push_back(a);
+          break;
+        }
+    std::vector<double> rc(s.pp_rcut, s.pp_rcut + s.n_atom);
+    int4 *d_pt;
+    double2 *d_pb;
+    double *d_rc;
+    int *d_nl;
+    if ((st = upload(c, &d_pt, pt)) || (st = upload(c, &d_pb, pb)) || (st = upload(c, &d_rc, rc)) ||
+        (st = upload(c, &d_nl, nl)))
+      return bail(st);
+    d.pp_n = s.pp_n_term;
+    d.pp_t = d_pt;
+    d.pp_ba = d_pb;
+    d.pp_rcut = d_rc;
+    d.pp_nl = (int)nl.size();
+    d.pp_nl_atom = d_nl;
+    if ((st = dalloc(c, &d.vps, Wp))) return bail(st);
+    if (hipMemsetAsync(d.vps, 0, Wp * sizeof(double), c->stream) != hipSuccess) {
+      c->err = "initialisation copies failed";
+      return bail(DMCX_E_HIP);
+    }
+    if (d.pp_nl > 0) {
+      c->pp_ldy = (c->dc.B.Kp + 63) / 64 * 64;
+      if ((st = dalloc(c, &c->d_ppY, (size_t)c->W * c->ne * c->pp_ldy))) return bail(st);
+      if (pp_lds_bytes(c->ne, d.pp_nl) > 64 * 1024) {
+        c->err = "pseudopotential: pair list exceeds 64 KB of LDS";
+        return bail(DMCX_E_UNSUPPORTED);
+      }
+    }
+  }
   {
     const size_t ntile = (c->ne + FPTS - 1) / FPTS, na3 = (size_t)s.n_atom * 3;
     if ((st = dalloc(c, &c->d_partial, Wp * ntile * na3))) return bail(st);

@@ -236,6 +236,14 @@ struct DevCtx {
   unsigned *nacc;  // [Wpad] moves accepted since the last estimator call
   unsigned *nprop; // [Wpad] moves proposed since the last estimator call
   DevMsd M;        // multideterminant expansion (M.on == 0: none)
+  // semilocal pseudopotential (pp_n == 0: none)
+  int pp_n;                  // terms
+  const int4 *pp_t;          // [pp_n] (atom, l (-1 local), n, 0)
+  const double2 *pp_ba;      // [pp_n] (beta, alpha)
+  const double *pp_rcut;     // [n_atom]
+  int pp_nl;                 // atoms with non-local channels
+  const int *pp_nl_atom;     // [pp_nl] their indices, ascending
+  double *vps;               // [Wpad] pseudopotential energy of the current configuration
 };
 
 __device__ __forceinline__ size_t vglc_off(const DevCtx &c, int w, int e) {
@@ -1093,6 +1101,7 @@ __global__ __launch_bounds__(NTE) void k_local_energy(DevCtx c, int measure_only
     for (int q = 0; q < NTE / 64; ++q) {
       K += part[q][0]; V += part[q][1]; J += part[q][2]; Bd += part[q][3];
     }
+    if (c.vps) V += c.vps[w];  // pseudopotential (local + non-local), when the system has one
     const double e = -0.5 * K + V + c.v_nn;
     if (esc.mode == 2) {
       // the walker's E_L of this step was first taken from FP32 derivative

@@ -1,0 +1,258 @@
+// Semilocal pseudopotential energy (the ccECP form of the paper's QMC runs):
+// local terms beta r^(n-2) exp(-alpha r^2) added to V, and the non-local
+// channels v_l(r) projected on angular momentum l about their atom.  The
+// projection acts on Psi through the angular integral over the sphere of
+// radius r_iA about atom A,
+//   V_NL Psi / Psi = sum_l v_l(r_iA) (2l+1)/(4 pi) int dOmega P_l(cos) Psi(r')/Psi,
+// taken by the 12-point icosahedral rule (weights 1/12) turned by a random
+// rotation per electron and evaluation: Shoemake's quaternion from the
+// Philox draws 3 and 4 of (electron, walker, step) under the run's key.
+//
+// Psi(r')/Psi(R) for electron e moved to r' is the determinant ratio
+// sum_j phi_j(r') (A^{-1})_je times the Jastrow ratio.  With
+// y_e = C (A^{-1})_{:,e} (one vector over the basis per electron, k_pp_y: an
+// MFMA product of the inverse and the LCAO matrix) the determinant ratio at a
+// point is the dot product of the basis values there with y_e, so a point
+// costs one basis evaluation (values only) and no orbital GEMM.
+//
+// k_pp: one workgroup per walker.  Electron positions, rotations and the
+// electrons' own Jastrow sums go to LDS; the (electron, atom) pairs within
+// the atoms' cutoffs are listed electron by electron (a block scan, so the
+// order is fixed); then one lane per quadrature point.  Sums are added in a
+// fixed order per walker (bit-reproducible).
+#pragma once
+#include "kernels.h"
+
+namespace dmcx {
+
+constexpr int PP_MAXA = 8;  // listed (electron, atom) pairs: at most ne x min(nl atoms, 8)
+
+// Direction q (0..11) of the icosahedral rule: the cyclic arrangements of
+// (0, +-1, +-phi), normalised; bit 0 of q flips the phi entry, bit 1 the 1.
+__device__ __forceinline__ void ico_dir(int q, double d[3]) {
+  const double phi = 1.6180339887498948482;
+  const double a = (q & 1) ? -phi : phi, b = (q & 2) ? -1.0 : 1.0;
+  const double nrm = 1.0 / sqrt(1.0 + phi * phi);
+  const int k = q >> 2;
+  d[0] = (k == 0 ? 0.0 : (k == 1 ? b : a)) * nrm;
+  d[1] = (k == 0 ? b : (k == 1 ? a : 0.0)) * nrm;
+  d[2] = (k == 0 ? a : (k == 1 ? 0.0 : b)) * nrm;
+}
+
+// Rotation matrix of the unit quaternion (x, y, z, w) = (sqrt(1-u0) sin 2pi u1,
+// sqrt(1-u0) cos 2pi u1, sqrt(u0) sin 2pi u2, sqrt(u0) cos 2pi u2)
+// (Shoemake's uniform random rotation), row-major.
+__device__ inline void pp_rotation(uint64_t seed, uint32_t step, uint32_t walker, uint32_t elec,
+                                   double rot[9]) {
+  const double two_pi = 6.283185307179586476925286766559;
+  double u0, u1, u2, unused;
+  uniform_pair(seed, step, walker, elec, 3u, u0, u1);
+  uniform_pair(seed, step, walker, elec, 4u, u2, unused);
+  const double s1 = sqrt(1.0 - u0), s2 = sqrt(u0);
+  const double x = s1 * sin(two_pi * u1), y = s1 * cos(two_pi * u1);
+  const double z = s2 * sin(two_pi * u2), w = s2 * cos(two_pi * u2);
+  rot[0] = 1.0 - 2.0 * (y * y + z * z); rot[1] = 2.0 * (x * y - z * w); rot[2] = 2.0 * (x * z + y * w);
+  rot[3] = 2.0 * (x * y + z * w); rot[4] = 1.0 - 2.0 * (x * x + z * z); rot[5] = 2.0 * (y * z - x * w);
+  rot[6] = 2.0 * (x * z - y * w); rot[7] = 2.0 * (y * z + x * w); rot[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+__device__ __forceinline__ double legendre_pl(int l, double x) {
+  return l == 0 ? 1.0 : (l == 1 ? x : (l == 2 ? 0.5 * (3.0 * x * x - 1.0) : 0.5 * (5.0 * x * x * x - 3.0 * x)));
+}
+
+// beta r^(n-2) exp(-alpha r^2), n in 0..4
+__device__ __forceinline__ double pp_term(int n, double beta, double alpha, double r) {
+  const double ir = 1.0 / r;
+  const double pw = n == 0 ? ir * ir : (n == 1 ? ir : (n == 2 ? 1.0 : (n == 3 ? r : r * r)));
+  return beta * pw * exp(-alpha * r * r);
+}
+
+// y_e = C (A^{-1})_{:,e} for every electron of walker w and spin sp, into
+// Y [W][ne][ldy] (FP64, permuted basis order).  G is the inverse in the GT
+// layout (row e = column e of A^{-1}, zero padded), of element type TG.
+// grid (W, 2, ceil(Kp / 64)), block 256: wave v computes the 16 functions
+// fn0 + 16 v .. + 15 for all electrons of the spin, one 16 x 16 MFMA tile per
+// 16 electrons over the NP orbitals.
+template <typename TG>
+__global__ __launch_bounds__(256) void k_pp_y(DevCtx c, const TG *G, double *Y, int ldy) {
+  const int w = blockIdx.x, sp = blockIdx.y;
+  const int n = sp == 0 ? c.n_up : c.n_dn;
+  if (n == 0) return;
+  const int e0 = sp == 0 ? 0 : c.n_up;
+  const int NP = c.NP, Kp = c.B.Kp;
+  const int lane = threadIdx.x & 63;
+  const int fn0 = blockIdx.z * 64 + wave_id() * 16;
+  const int fnl = fn0 + (lane & 15);
+  const bool fok = fnl < Kp;
+  const double *Crow = c.B.Cp + (size_t)(fok ? fnl : 0) * NP;
+  const TG *Gw = G + gt_off(c, w, sp);
+  for (int m0 = 0; m0 < n; m0 += 16) {
+    // A operand: lane l holds G[m0 + l % 16][k0 + l / 16]; B: Cp[fn0 + l % 16][k0 + l / 16]
+    const TG *Grow = Gw + (size_t)(m0 + (lane & 15)) * NP;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < NP; k0 += 4) {
+      const int k = k0 + (lane >> 4);
+      acc = mfma16x16x4((double)Grow[k], fok ? Crow[k] : 0.0, acc);
+    }
+    // lane l, element r: electron m0 + l / 16 + 4 r, function fn0 + l % 16
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + (lane >> 4) + 4 * r;
+      if (m < n && fok) Y[((size_t)w * c.ne + e0 + m) * ldy + fnl] = acc[r];
+    }
+  }
+}
+
+// Basis values at p dotted with y (permuted order): sum_fn Phi_fn(p) y[fn].
+__device__ inline double basis_dot(const DevBasis &B, const double p[3], const double *y) {
+  double acc = 0.0;
+  for (int g = 0; g < B.n_group; ++g) {
+    const int4 gi = B.ginfo[g];  // (l, nprim, first permuted function, first primitive slot)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double *ctr = B.gxyz + (size_t)(g * 4 + q) * 3;
+      const double dx = p[0] - ctr[0], dy = p[1] - ctr[1], dz = p[2] - ctr[2];
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      double rad = 0.0;
+      for (int k = 0; k < gi.y; ++k) {
+        const int sl = gi.w + k * 4 + q;
+        rad += B.gcoef[sl] * exp(-B.galpha[sl] * r2);
+      }
+      const double *yq = y + gi.z + q;  // component c of shell q at gi.z + 4 c + q
+      if (gi.x == 0) {
+        acc += rad * yq[0];
+      } else if (gi.x == 1) {
+        acc += rad * (dx * yq[0] + dy * yq[4] + dz * yq[8]);
+      } else {
+        acc += rad * (dx * dx * yq[0] + dx * dy * yq[4] + dx * dz * yq[8] + dy * dy * yq[12] +
+                      dy * dz * yq[16] + dz * dz * yq[20]);
+      }
+    }
+  }
+  return acc;
+}
+
+// J terms of electron e placed at p, summed over the other electrons (LDS
+// positions s_r) and the atoms.
+__device__ inline double jastrow_at(const DevCtx &c, const double *s_r, int e, const double p[3]) {
+  const int se = e < c.n_up ? 0 : 1;
+  double u = 0.0;
+  for (int j = 0; j < c.ne; ++j) {
+    if (j == e) continue;
+    const double dx = p[0] - s_r[3 * j], dy = p[1] - s_r[3 * j + 1], dz = p[2] - s_r[3 * j + 2];
+    const double a = ((j < c.n_up ? 0 : 1) == se) ? c.jee_para : c.jee_anti;
+    u += pade(a, c.jee_b, sqrt(dx * dx + dy * dy + dz * dz)).u;
+  }
+  for (int A = 0; A < c.n_atom; ++A) {
+    const double dx = p[0] - c.ion[3 * A], dy = p[1] - c.ion[3 * A + 1], dz = p[2] - c.ion[3 * A + 2];
+    u += pade(c.jen_a[A], c.jen_b, sqrt(dx * dx + dy * dy + dz * dz)).u;
+  }
+  return u;
+}
+
+inline size_t pp_lds_bytes(int ne, int n_nl) {
+  const int cap = ne * (n_nl < PP_MAXA ? n_nl : PP_MAXA);
+  return (size_t)ne * 13 * sizeof(double) + (size_t)(cap > 0 ? cap : 1) * sizeof(int);
+}
+
+// Pseudopotential energy (local terms + non-local quadrature) of every walker
+// into c.vps [W].  grid W, block NT_AUX (NT_AUX >= ne), dynamic LDS
+// pp_lds_bytes(ne, c.pp_nl).  A walker whose listed pairs exceed the LDS list
+// gets NaN (flagged by the energy kernel), never a partial sum.
+__global__ __launch_bounds__(NT_AUX) void k_pp(DevCtx c, const double *Y, int ldy) {
+  extern __shared__ double sm[];
+  __shared__ int s_cnt[NT_AUX];
+  __shared__ double red[NT_AUX / 64];
+  const int ne = c.ne, w = blockIdx.x, tid = threadIdx.x;
+  double *s_r = sm;             // [ne][3]
+  double *s_rot = sm + 3 * ne;  // [ne][9]
+  double *s_J = sm + 12 * ne;   // [ne]
+  int *s_pair = (int *)(sm + 13 * ne);
+  const int cap = ne * (c.pp_nl < PP_MAXA ? c.pp_nl : PP_MAXA);
+  const double *Rw = c.R + (size_t)w * ne * 3;
+  const uint32_t step = (uint32_t)c.run->step;
+  double acc = 0.0;
+  int cnt = 0;
+  if (tid < ne) {
+    const double r[3] = {Rw[3 * tid], Rw[3 * tid + 1], Rw[3 * tid + 2]};
+    for (int x = 0; x < 3; ++x) s_r[3 * tid + x] = r[x];
+    // local terms, and the atoms whose non-local channels reach this electron
+    for (int t = 0; t < c.pp_n; ++t) {
+      const int4 tt = c.pp_t[t];
+      if (tt.y != -1) continue;
+      const double *RA = c.ion + 3 * tt.x;
+      const double dx = r[0] - RA[0], dy = r[1] - RA[1], dz = r[2] - RA[2];
+      const double2 ba = c.pp_ba[t];
+      acc += pp_term(tt.z, ba.x, ba.y, sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    for (int k = 0; k < c.pp_nl; ++k) {
+      const double *RA = c.ion + 3 * c.pp_nl_atom[k];
+      const double dx = r[0] - RA[0], dy = r[1] - RA[1], dz = r[2] - RA[2];
+      if (sqrt(dx * dx + dy * dy + dz * dz) < c.pp_rcut[c.pp_nl_atom[k]]) ++cnt;
+    }
+    if (cnt) pp_rotation(c.seed, step, (uint32_t)w, (uint32_t)tid, s_rot + 9 * tid);
+  }
+  s_cnt[tid] = cnt;
+  __syncthreads();
+  // inclusive scan of the per-electron pair counts (electron order)
+  for (int o = 1; o < NT_AUX; o <<= 1) {
+    const int v = tid >= o ? s_cnt[tid - o] : 0;
+    __syncthreads();
+    s_cnt[tid] += v;
+    __syncthreads();
+  }
+  const int npair = s_cnt[NT_AUX - 1];
+  const bool over = npair > cap;
+  if (tid < ne) {
+    s_J[tid] = cnt ? jastrow_at(c, s_r, tid, s_r + 3 * tid) : 0.0;
+    if (!over && cnt) {
+      int slot = s_cnt[tid] - cnt;
+      const double r[3] = {s_r[3 * tid], s_r[3 * tid + 1], s_r[3 * tid + 2]};
+      for (int k = 0; k < c.pp_nl; ++k) {
+        const int A = c.pp_nl_atom[k];
+        const double *RA = c.ion + 3 * A;
+        const double dx = r[0] - RA[0], dy = r[1] - RA[1], dz = r[2] - RA[2];
+        if (sqrt(dx * dx + dy * dy + dz * dz) < c.pp_rcut[A]) s_pair[slot++] = tid | (A << 16);
+      }
+    }
+  }
+  __syncthreads();
+  if (!over) {
+    for (int p = tid; p < npair * 12; p += NT_AUX) {
+      const int pr = s_pair[p / 12], q = p - (p / 12) * 12;
+      const int e = pr & 0xffff, A = pr >> 16;
+      const double *RA = c.ion + 3 * A;
+      const double d[3] = {s_r[3 * e] - RA[0], s_r[3 * e + 1] - RA[1], s_r[3 * e + 2] - RA[2]};
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      double o[3], od[3];
+      ico_dir(q, o);
+      const double *rot = s_rot + 9 * e;
+#pragma unroll
+      for (int x = 0; x < 3; ++x) od[x] = rot[3 * x] * o[0] + rot[3 * x + 1] * o[1] + rot[3 * x + 2] * o[2];
+      const double cth = (od[0] * d[0] + od[1] * d[1] + od[2] * d[2]) / r;
+      const double pq[3] = {RA[0] + r * od[0], RA[1] + r * od[1], RA[2] + r * od[2]};
+      const double rdet = basis_dot(c.B, pq, Y + ((size_t)w * ne + e) * ldy);
+      const double ratio = rdet * exp(jastrow_at(c, s_r, e, pq) - s_J[e]);
+      double vl[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int t = 0; t < c.pp_n; ++t) {
+        const int4 tt = c.pp_t[t];
+        if (tt.x == A && tt.y >= 0) vl[tt.y] += pp_term(tt.z, c.pp_ba[t].x, c.pp_ba[t].y, r);
+      }
+      double f = 0.0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) f += vl[l] * (2 * l + 1) * legendre_pl(l, cth);
+      acc += f * ratio * (1.0 / 12.0);
+    }
+  }
+  // fixed-order block sum
+  double v = sum64(acc);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int k = 0; k < NT_AUX / 64; ++k) t += red[k];
+    c.vps[w] = over ? __builtin_nan("") : t;
+  }
+}
+
+}  // namespace dmcx

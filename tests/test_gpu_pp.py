@@ -1,0 +1,182 @@
+"""Semilocal pseudopotential on the GPU (local terms in V, the non-local
+energy by the rotated 12-point rule, ratios through y_e = C (A^-1)_{:,e})
+against the oracle, with synthetic stand-ins for the ccECP tables.
+
+Bars: E_L (which now carries the pseudopotential energy with the rotations of
+(electron, walker, step)) within 1e-10 x max(|E_L|, 1) of the oracle's
+E_L + V_NL at the same configurations; DMC runs with the accept sequence
+bit-exact and E_L, positions and log-weights within 1e-10; in the mixed form
+the pseudopotential part (from the FP64 inverse) within 1e-10 and E_L at the
+mixed form's bars; graph replays bit-identical to eager steps;
+a group equal to its systems' own contexts; forces on such systems rejected.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_07948_amd import dmcx, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _close(a, b, rel=1e-10, floor=1.0, label=""):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    err = np.abs(a - b) / np.maximum(np.maximum(np.abs(a), np.abs(b)), floor)
+    print(f"[pp] {label}: max rel err {err.max():.2e}", flush=True)
+    assert np.all(err <= rel), f"{(err > rel).sum()} of {err.size} outside"
+
+
+def _oracle_energy(s, R, seed, step, offset=0):
+    _, _, e, rc = oracle.evaluate_batch(s, R)
+    assert rc == 0
+    v, rc = oracle.nlpp_batch(s, R, seed, step, offset)
+    assert rc == 0
+    return e + v
+
+
+def test_measure_small_against_oracle():
+    s = synth.small_molecule_pp()
+    W, seed = 40, 21
+    R = synth.make_walkers(s, W, 3300)
+    ctx = dmcx.Context(s, W, seed=seed)
+    ctx.set_walkers(R)
+    e, _, _ = ctx.measure()
+    ref = _oracle_energy(s, R, seed, 0)
+    _close(e, ref, label="small E_L with pseudopotential")
+    # the pseudopotential moves E_L by O(1) Ha: the comparison would fail without it
+    bare = dmcx.Context(synth.small_molecule(), W, seed=seed)
+    bare.set_walkers(R)
+    assert np.abs(bare.measure()[0] - e).max() > 0.1
+
+
+@pytest.mark.parametrize("k", [1, 4])
+def test_dmc_run_small_against_oracle(k):
+    s = synth.small_molecule_pp()
+    W, seed, tau, et = 24, 22, 0.02, -10.0
+    R = synth.make_walkers(s, W, 3301)
+    ctx = dmcx.Context(s, W, seed=seed, tau=tau, delay_rank=k, recompute_period=3)
+    ctx.set_walkers(R)
+    acc, el = ctx.run(4, mode=dmcx.DMCX_DMC, e_trial=et, logs=True)
+    ref = oracle.run(s, R, n_steps=4, mode=1, tau=tau, seed=seed, e_trial=et)
+    assert ref["rc"] == 0
+    np.testing.assert_array_equal(acc, ref["accept_log"])
+    _close(el, ref["e_log"], label="E_L log")
+    Rg, lw = ctx.get_walkers()
+    _close(Rg, ref["R"], label="positions")
+    _close(lw, ref["log_w"], label="log w")
+
+
+def test_large_molecule_sampled_and_run():
+    s = synth.large_molecule_pp()
+    W, seed = 64, 23
+    R = synth.make_walkers(s, W, 3302)
+    ctx = dmcx.Context(s, W, seed=seed, delay_rank=32, recompute_period=64)
+    ctx.set_walkers(R)
+    e, _, _ = ctx.measure()
+    assert np.all(np.isfinite(e))
+    idx = np.array([0, 17, W - 1])
+    ref = np.array([_oracle_energy(s, R[i:i + 1], seed, 0, offset=int(i))[0] for i in idx])
+    _close(e[idx], ref, label="large E_L with pseudopotential")
+    # one DMC step of the first 3 walkers, against the oracle
+    ctx3 = dmcx.Context(s, 3, seed=seed, delay_rank=32, recompute_period=64, tau=0.01)
+    ctx3.set_walkers(R[:3])
+    acc, el = ctx3.run(1, mode=dmcx.DMCX_DMC, e_trial=-150.0, logs=True)
+    out = oracle.run(s, R[:3], n_steps=1, mode=1, tau=0.01, seed=seed, e_trial=-150.0)
+    np.testing.assert_array_equal(acc, out["accept_log"])
+    _close(el, out["e_log"], label="large E_L after a step")
+    _close(ctx3.get_walkers()[1], out["log_w"], label="large log w")
+
+
+def test_mixed_form_against_oracle():
+    """The mixed form takes the kinetic energy from FP32 derivative rows
+    (per-walker errors near 1e-6 relative), so E_L is held to the mixed
+    form's bars; the pseudopotential part itself, computed from the FP64
+    inverse, is isolated as the difference to the same context without it
+    (the moves do not depend on the pseudopotential, so both contexts move
+    the walkers identically) and held to 1e-10 x max(|E_L|, 1)."""
+    s = synth.small_molecule_pp()
+    bare_s = synth.small_molecule()
+    W, seed = 32, 24
+    R = synth.make_walkers(s, W, 3303)
+    ctx = dmcx.Context(s, W, seed=seed, precision=dmcx.DMCX_MIXED)
+    bare = dmcx.Context(bare_s, W, seed=seed, precision=dmcx.DMCX_MIXED)
+    ne = s.n_elec
+    for st, nsteps in ((0, 0), (1, 2)):
+        if nsteps == 0:
+            ctx.set_walkers(R)
+            bare.set_walkers(R)
+        else:
+            ctx.run(nsteps, mode=dmcx.DMCX_VMC)
+            bare.run(nsteps, mode=dmcx.DMCX_VMC)
+        Rg, _ = ctx.get_walkers()
+        np.testing.assert_array_equal(Rg, bare.get_walkers()[0])
+        e, _, _ = ctx.measure()
+        eb, _, _ = bare.measure()
+        ref = _oracle_energy(s, Rg, seed, st)
+        dv = np.array([oracle.potential(s, Rg[w]) - oracle.potential(bare_s, Rg[w])
+                       for w in range(W)])
+        vnl, _ = oracle.nlpp_batch(s, Rg, seed, st)
+        scale = np.maximum(np.abs(e), 1.0)
+        err = np.abs((e - eb) - (dv + vnl)) / scale
+        print(f"[pp] mixed step {st}: pseudopotential part max rel err {err.max():.2e}", flush=True)
+        assert np.all(err <= 1e-10)
+        assert abs(np.mean(e - ref)) / ne <= 1e-6
+        assert np.all(np.abs(e - ref) <= 1e-5 * np.maximum(np.abs(ref), ne))
+
+
+def test_graph_replay_matches_eager():
+    s = synth.small_molecule_pp()
+    W, seed = 16, 25
+    R = synth.make_walkers(s, W, 3304)
+    out = []
+    for graph in (False, True):
+        ctx = dmcx.Context(s, W, seed=seed, graph=graph, delay_rank=2, recompute_period=2)
+        ctx.set_walkers(R)
+        acc, el = ctx.run(3, mode=dmcx.DMCX_DMC, e_trial=-10.0, logs=True)
+        out.append((acc, el, ctx.get_walkers()))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    np.testing.assert_array_equal(out[0][2][0], out[1][2][0])
+    np.testing.assert_array_equal(out[0][2][1], out[1][2][1])
+
+
+def test_group_with_and_without_pseudopotential():
+    a = synth.small_molecule_pp()
+    b = synth.small_random_system(91, n_atom=2, n_up=2, n_dn=1, shells=(0, 1), nprim=1,
+                                  charge=1.5)
+    Ws = [12, 9]
+    Ra = synth.make_walkers(a, Ws[0], 3305)
+    Rb = synth.make_walkers(b, Ws[1], 3306)
+    ne = max(a.n_elec, b.n_elec)
+    R = np.zeros((sum(Ws), ne, 3))
+    R[: Ws[0], : a.n_elec] = Ra
+    R[Ws[0]:, : b.n_elec] = Rb
+    grp = dmcx.Context([a, b], Ws, seed=26)
+    grp.set_walkers(R)
+    acc, el = grp.run(2, mode=dmcx.DMCX_DMC, e_trial=-8.0, logs=True)
+    for i, (sysi, Ri, sl) in enumerate(((a, Ra, slice(0, Ws[0])), (b, Rb, slice(Ws[0], None)))):
+        one = dmcx.Context(sysi, Ws[i], seed=26)
+        one.set_walkers(Ri)
+        acc1, el1 = one.run(2, mode=dmcx.DMCX_DMC, e_trial=-8.0, logs=True)
+        np.testing.assert_array_equal(acc[:, sl, : sysi.n_elec], acc1)
+        np.testing.assert_array_equal(el[:, sl], el1)
+
+
+def test_forces_and_multideterminant_rejected():
+    s = synth.small_molecule_pp()
+    ctx = dmcx.Context(s, 8)
+    ctx.set_walkers(synth.make_walkers(s, 8, 1))
+    with pytest.raises(dmcx.DmcxError) as e:
+        ctx.forces()
+    assert e.value.status == dmcx.DMCX_E_UNSUPPORTED
+    with pytest.raises(dmcx.DmcxError) as e:
+        ctx.jastrow_param_grads()
+    assert e.value.status == dmcx.DMCX_E_UNSUPPORTED
+    base = synth.small_random_system(77, n_atom=2, n_up=3, n_dn=3, shells=(0, 0, 1, 2), nprim=2,
+                                     n_mo=10)
+    msd = synth.with_pseudopotential(synth.make_msd(base, n_det=5, n_active=6, seed=78),
+                                     [synth.PP_SMALL] * 2)
+    with pytest.raises(dmcx.DmcxError) as e:
+        dmcx.Context(msd, 8)
+    assert e.value.status == dmcx.DMCX_E_UNSUPPORTED
