@@ -274,6 +274,40 @@ def jparams_leg(s, torch, dmcx, stream, W=2048, reps=5, cpu_walkers=4):
             "gpu_ms_per_walker": ms / W}
 
 
+def pp_leg(torch, dmcx, stream, W=2048, steps=5, cpu_walkers=2):
+    """DMC steps of the large molecule with a semilocal pseudopotential on its
+    16 "C" atoms (synthetic stand-in tables in the ccECP form: a local term
+    and a non-local s channel, cutoff 2.15 bohr), FP64, k = 32, P = 64,
+    against the same steps without it.  Every step's E_L then carries the
+    non-local energy: 12 quadrature points per (electron, atom) pair within
+    the cutoff, each a basis evaluation dotted with y_e = C (A^-1)_{:,e} and
+    a Jastrow ratio.  Points are counted on the host from the final walkers;
+    the oracle's non-local energy is timed on a few walkers beside it."""
+    from paper_2504_07948_amd import synth
+    out = {"walkers": W, "steps": steps}
+    for name, s in (("without", synth.large_molecule()), ("with", synth.large_molecule_pp())):
+        ctx, ms, sw = _timed_ctx(s, torch, dmcx, stream, W, steps, 31, precision=dmcx.DMCX_FP64,
+                                 delay_rank=32, recompute_period=64)
+        out[f"ms_per_step_{name}_pp"] = ms
+        if name == "with":
+            R, _ = ctx.get_walkers()
+            nl = [a for a in range(s.n_atom) if np.any((s.pp_atom == a) & (s.pp_l >= 0))]
+            d = np.linalg.norm(R[:, :, None, :] - s.ion_xyz[None, None, nl, :], axis=-1)
+            pairs = int((d < s.pp_rcut[nl][None, None, :]).sum())
+            out["quadrature_points_per_step"] = 12 * pairs
+            out["points_per_walker"] = 12 * pairs / W
+            import oracle
+            tc = time.perf_counter()
+            oracle.nlpp_batch(s, R[:cpu_walkers], 31, 0, 0, n_threads=1)
+            out["oracle_nlpp_ms_per_walker_one_thread"] = 1e3 * (time.perf_counter() - tc) / cpu_walkers
+        ctx.close()
+    out["pp_cost_ratio"] = out["ms_per_step_with_pp"] / out["ms_per_step_without_pp"]
+    extra = out["ms_per_step_with_pp"] - out["ms_per_step_without_pp"]
+    out["pp_ms_per_step"] = extra
+    out["points_per_s"] = out["quadrature_points_per_step"] / (extra * 1e-3) if extra > 0 else None
+    return out
+
+
 def batch5_leg(torch, dmcx, stream, steps=5, W=512, n_det=1000, n_active=100, P=32):
     """Eight alkane stand-ins (20..200 electrons), 512 walkers each, 1000-
     determinant expansions over 100 active orbitals (table method), mixed
@@ -421,11 +455,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the FP64 leg (same as --extras none)")
-    ap.add_argument("--extras", default="mixed,forces,batch,population,flush,jparams",
+    ap.add_argument("--extras", default="mixed,forces,batch,population,flush,jparams,pp",
                     help="comma list of the extra legs to run after the FP64 leg: mixed, forces, "
                          "batch (eight multideterminant alkanes), population, flush (the "
                          "delayed-update GEMMs alone), jparams (Jastrow parameter derivatives "
-                         "and linear-method matrices), or none")
+                         "and linear-method matrices), pp (pseudopotential), or none")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed region, run one device copy of this many MiB "
                          "(a known-size kernel for scaling FETCH_SIZE/WRITE_SIZE counters)")
@@ -479,9 +513,9 @@ def main():
     torch.cuda.synchronize()
     dt_period = time.perf_counter() - tp0
 
-    mixed = forces = batch5 = population = flush = jparams = None
+    mixed = forces = batch5 = population = flush = jparams = pp = None
     extras = set() if args.skip_extras else set(args.extras.split(",")) - {"none", ""}
-    unknown = extras - {"mixed", "forces", "batch", "population", "flush", "jparams"}
+    unknown = extras - {"mixed", "forces", "batch", "population", "flush", "jparams", "pp"}
     if unknown:
         sys.exit(f"bench.py: unknown extra legs {sorted(unknown)}")
     if "mixed" in extras:
@@ -496,6 +530,8 @@ def main():
         flush = flush_leg(s, torch, dmcx, stream)
     if "jparams" in extras:
         jparams = jparams_leg(s, torch, dmcx, stream)
+    if "pp" in extras:
+        pp = pp_leg(torch, dmcx, stream)
 
     ne, ns = s.n_elec, max(s.n_up, s.n_dn)
     moves = W * ne * args.steps
@@ -577,6 +613,7 @@ def main():
         "population_control": population,
         "delayed_update_flush": flush,
         "jastrow_param_derivatives": jparams,
+        "pseudopotential": pp,
         "walker_flags_nonzero": int((flags != 0).sum()),
     }
     print(json.dumps(out))

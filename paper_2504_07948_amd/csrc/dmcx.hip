@@ -544,16 +544,12 @@ __global__ void k_esc_reset(int *count) {
 dmcx_status launch_pp(dmcx_ctx *c) {
   if (c->dc.pp_n == 0) return DMCX_OK;
   if (c->dc.pp_nl > 0) {
-    const dim3 gy(c->W, 2, (c->dc.B.Kp + 63) / 64);
     if (!c->mixed)
-      hipLaunchKernelGGL(k_pp_y<double>, gy, dim3(256), 0, c->stream, c->dc,
-                         (const double *)c->dc.GT, c->d_ppY, c->pp_ldy);
+      launch_pp_y(c->NOB, c->dc, (const double *)c->dc.GT, c->d_ppY, c->pp_ldy, c->stream);
     else if (c->fp64e)
-      hipLaunchKernelGGL(k_pp_y<double>, gy, dim3(256), 0, c->stream, c->dc,
-                         (const double *)c->d_G64, c->d_ppY, c->pp_ldy);
+      launch_pp_y(c->NOB, c->dc, (const double *)c->d_G64, c->d_ppY, c->pp_ldy, c->stream);
     else
-      hipLaunchKernelGGL(k_pp_y<float>, gy, dim3(256), 0, c->stream, c->dc,
-                         (const float *)c->dc.GT, c->d_ppY, c->pp_ldy);
+      launch_pp_y(c->NOB, c->dc, (const float *)c->dc.GT, c->d_ppY, c->pp_ldy, c->stream);
     HIP_TRY(c, hipGetLastError());
   }
   hipLaunchKernelGGL(k_pp, dim3(c->W), dim3(NT_AUX), pp_lds_bytes(c->ne, c->dc.pp_nl), c->stream,
@@ -1148,6 +1144,10 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
       return bail(DMCX_E_HIP);
     }
     if (d.pp_nl > 0) {
+      if (c->NOB > 8) {
+        c->err = "pseudopotential: at most 128 orbital columns";
+        return bail(DMCX_E_UNSUPPORTED);
+      }
       c->pp_ldy = (c->dc.B.Kp + 63) / 64 * 64;
       if ((st = dalloc(c, &c->d_ppY, (size_t)c->W * c->ne * c->pp_ldy))) return bail(st);
       if (pp_lds_bytes(c->ne, d.pp_nl) > 64 * 1024) {

@@ -69,41 +69,72 @@ __device__ __forceinline__ double pp_term(int n, double beta, double alpha, doub
 
 // y_e = C (A^{-1})_{:,e} for every electron of walker w and spin sp, into
 // Y [W][ne][ldy] (FP64, permuted basis order).  G is the inverse in the GT
-// layout (row e = column e of A^{-1}, zero padded), of element type TG.
-// grid (W, 2, ceil(Kp / 64)), block 256: wave v computes the 16 functions
-// fn0 + 16 v .. + 15 for all electrons of the spin, one 16 x 16 MFMA tile per
-// 16 electrons over the NP orbitals.
-template <typename TG>
+// layout (row e = column e of A^{-1}, zero padded to NP = 16 NOB), of element
+// type TG.  grid (W, 2), block 256, dynamic LDS NP (NP + 1) doubles: the
+// block stages the spin's inverse in LDS (row stride NP + 1, so the 16 rows
+// an MFMA operand reads fall in distinct banks); wave v takes the function
+// tiles v, v + 4, ..., holds that tile's LCAO operand (NP / 4 registers) and
+// runs the 16 x 16 MFMA tiles of every 16 electrons against it.
+template <typename TG, int NOB>
 __global__ __launch_bounds__(256) void k_pp_y(DevCtx c, const TG *G, double *Y, int ldy) {
+  constexpr int NP = 16 * NOB, KS = NP / 4, LD = NP + 1;
+  extern __shared__ double s_g[];
   const int w = blockIdx.x, sp = blockIdx.y;
   const int n = sp == 0 ? c.n_up : c.n_dn;
   if (n == 0) return;
   const int e0 = sp == 0 ? 0 : c.n_up;
-  const int NP = c.NP, Kp = c.B.Kp;
-  const int lane = threadIdx.x & 63;
-  const int fn0 = blockIdx.z * 64 + wave_id() * 16;
-  const int fnl = fn0 + (lane & 15);
-  const bool fok = fnl < Kp;
-  const double *Crow = c.B.Cp + (size_t)(fok ? fnl : 0) * NP;
+  const int Kp = c.B.Kp, lane = threadIdx.x & 63;
   const TG *Gw = G + gt_off(c, w, sp);
-  for (int m0 = 0; m0 < n; m0 += 16) {
-    // A operand: lane l holds G[m0 + l % 16][k0 + l / 16]; B: Cp[fn0 + l % 16][k0 + l / 16]
-    const TG *Grow = Gw + (size_t)(m0 + (lane & 15)) * NP;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < NP; k0 += 4) {
-      const int k = k0 + (lane >> 4);
-      acc = mfma16x16x4((double)Grow[k], fok ? Crow[k] : 0.0, acc);
-    }
-    // lane l, element r: electron m0 + l / 16 + 4 r, function fn0 + l % 16
+  for (int i = threadIdx.x; i < NP * NP; i += 256) s_g[(i / NP) * LD + i % NP] = (double)Gw[i];
+  __syncthreads();
+  const int ntile = (Kp + 15) / 16, nm = (n + 15) / 16;
+  for (int t = wave_id(); t < ntile; t += 4) {
+    const int fnl = t * 16 + (lane & 15);
+    const bool fok = fnl < Kp;
+    // B operand of k-step s: Cp[fn][4 s + lane / 16]
+    const double *Crow = c.B.Cp + (size_t)(fok ? fnl : 0) * NP + (lane >> 4);
+    double b[KS];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = m0 + (lane >> 4) + 4 * r;
-      if (m < n && fok) Y[((size_t)w * c.ne + e0 + m) * ldy + fnl] = acc[r];
+    for (int st = 0; st < KS; ++st) b[st] = fok ? Crow[4 * st] : 0.0;
+    for (int mt = 0; mt < nm; ++mt) {
+      // A operand of k-step s: G[16 mt + lane % 16][4 s + lane / 16]
+      const double *arow = s_g + (size_t)(16 * mt + (lane & 15)) * LD + (lane >> 4);
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < KS; ++st) acc = mfma16x16x4(arow[4 * st], b[st], acc);
+      // lane l, element r: electron 16 mt + l / 16 + 4 r, function fnl
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = 16 * mt + (lane >> 4) + 4 * r;
+        if (m < n && fok) Y[((size_t)w * c.ne + e0 + m) * ldy + fnl] = acc[r];
+      }
     }
   }
 }
 
+template <typename TG>
+inline void launch_pp_y(int nob, const DevCtx &c, const TG *G, double *Y, int ldy, hipStream_t s) {
+  const size_t lds = (size_t)16 * nob * (16 * nob + 1) * sizeof(double);
+  const dim3 grid(c.W, 2);
+#define DMCX_CALL(N)                                                                  \
+  if (hipFuncSetAttribute((const void *)k_pp_y<TG, N>,                                \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess) \
+  k_pp_y<TG, N><<<grid, dim3(256), lds, s>>>(c, G, Y, ldy)
+  switch (nob) {
+    case 1: DMCX_CALL(1); break;
+    case 2: DMCX_CALL(2); break;
+    case 3: DMCX_CALL(3); break;
+    case 4: DMCX_CALL(4); break;
+    case 5: DMCX_CALL(5); break;
+    case 6: DMCX_CALL(6); break;
+    case 7: DMCX_CALL(7); break;
+    default: DMCX_CALL(8); break;
+  }
+#undef DMCX_CALL
+}
+
 // Basis values at p dotted with y (permuted order): sum_fn Phi_fn(p) y[fn].
+// Called by every active lane of a wave, one point per lane.
 __device__ inline double basis_dot(const DevBasis &B, const double p[3], const double *y) {
   double acc = 0.0;
   for (int g = 0; g < B.n_group; ++g) {
@@ -116,7 +147,10 @@ __device__ inline double basis_dot(const DevBasis &B, const double p[3], const d
       double rad = 0.0;
       for (int k = 0; k < gi.y; ++k) {
         const int sl = gi.w + k * 4 + q;
-        rad += B.gcoef[sl] * exp(-B.galpha[sl] * r2);
+        // a primitive below exp(-46) (1e-20) at every point of the wave is
+        // skipped by the whole wave
+        const double ar = B.galpha[sl] * r2;
+        if (__any(ar < 46.0)) rad += B.gcoef[sl] * exp(-ar);
       }
       const double *yq = y + gi.z + q;  // component c of shell q at gi.z + 4 c + q
       if (gi.x == 0) {
