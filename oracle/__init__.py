@@ -91,6 +91,7 @@ def _load():
         lib.orc_nlpp_batch.argtypes = [P, C.c_int32, P, C.c_uint64, C.c_int64, C.c_int32, P,
                                        C.c_int32]
         lib.orc_nlpp_rotation.argtypes = [C.c_uint64, C.c_int64, C.c_int32, C.c_int32, P]
+        lib.orc_pp_ion_grads.argtypes = [P, P, C.c_uint64, C.c_int64, C.c_int32, P]
         lib.orc_nlpp_rotation.restype = None
         _lib = lib
     return _lib
@@ -496,3 +497,13 @@ def nlpp_rotation(seed, step, walker, elec):
     rot = np.zeros(9)
     _load().orc_nlpp_rotation(seed, step, walker, elec, _ptr(rot))
     return rot.reshape(3, 3)
+
+
+def pp_ion_grads(sys, R, seed, step, walker):
+    """d(V_loc + V_NL)/dR_A [n_atom][3] at fixed electrons, rotations and
+    Psi: the pseudopotential's Hellmann-Feynman force term.  Returns (g, rc)."""
+    o = _osys(sys)
+    g = np.zeros((o.n_atom, 3))
+    rc = _load().orc_pp_ion_grads(o.ref, _ptr(np.ascontiguousarray(R, dtype=np.float64)), seed,
+                                  step, walker, _ptr(g))
+    return g, rc

@@ -559,6 +559,98 @@ int orc_nlpp(const orc_system *s, const double *R, uint64_t seed, int64_t step, 
   return rc;
 }
 
+/* Derivative of the pseudopotential operator with respect to its centres
+ * (the Hellmann-Feynman part of the Eq. 3 force; Psi, with its basis and
+ * Jastrow centres, held fixed): dvpp[A][3] = d(V_loc + V_NL)/dR_A at fixed
+ * electrons and rotations.  With d = r_i - R_A, r = |d|, n = d / r,
+ * o_q = Q Omega_q, c_q = o_q . n, r_q = R_A + r o_q, rho_q = Psi(r_q)/Psi(R):
+ *   dr/dR_A = -n,  dc_q/dR_A = -(o_q - c_q n) / r,
+ *   drho_q/dR_A = (I - o_q n^T)^T grad rho_q = g - n (o_q . g),
+ *   g = rho_q grad_{r_q} ln Psi (the drift of electron i at the moved
+ *   configuration, from a plain evaluation there). */
+int orc_pp_ion_grads(const orc_system *s, const double *R, uint64_t seed, int64_t step,
+                     int32_t walker, double *dvpp) {
+  const int ne = s->n_up + s->n_dn;
+  for (int k = 0; k < 3 * s->n_atom; ++k) dvpp[k] = 0.0;
+  if (s->pp_n_term == 0) return 0;
+  if (s->n_det > 1) return 4;
+  int rc = 0;
+  /* local terms: d/dR_A beta r^(n-2) exp(-alpha r^2) = -f'(r) n */
+  for (int t = 0; t < s->pp_n_term; ++t) {
+    if (s->pp_l[t] != -1) continue;
+    const int A = s->pp_atom[t];
+    const double *c = s->ion_xyz + 3 * A;
+    for (int i = 0; i < ne; ++i) {
+      const double d[3] = {R[3 * i] - c[0], R[3 * i + 1] - c[1], R[3 * i + 2] - c[2]};
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const int n = s->pp_n[t];
+      const double f = s->pp_beta[t] * pow(r, n - 2) * exp(-s->pp_alpha[t] * r * r);
+      const double fp = f * ((n - 2) / r - 2.0 * s->pp_alpha[t] * r);
+      for (int x = 0; x < 3; ++x) dvpp[3 * A + x] -= fp * d[x] / r;
+    }
+  }
+  double lp0, e0;
+  int32_t sg0;
+  rc |= orc_evaluate(s, R, &lp0, &sg0, &e0, NULL);
+  double *Rq = (double *)malloc(sizeof(double) * 3 * ne);
+  double *drq = (double *)malloc(sizeof(double) * 3 * ne);
+  for (int i = 0; i < ne; ++i) {
+    double rot[9];
+    int have_rot = 0;
+    for (int At = 0; At < s->n_atom; ++At) {
+      int lmax = -1;
+      for (int t = 0; t < s->pp_n_term; ++t)
+        if (s->pp_atom[t] == At && s->pp_l[t] > lmax) lmax = s->pp_l[t];
+      if (lmax < 0) continue;
+      const double *c = s->ion_xyz + 3 * At;
+      const double d[3] = {R[3 * i] - c[0], R[3 * i + 1] - c[1], R[3 * i + 2] - c[2]};
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      if (!(r < s->pp_rcut[At])) continue;
+      if (!have_rot) {
+        orc_nlpp_rotation(seed, step, walker, i, rot);
+        have_rot = 1;
+      }
+      const double nv[3] = {d[0] / r, d[1] / r, d[2] / r};
+      double vl[4] = {0, 0, 0, 0}, vlp[4] = {0, 0, 0, 0};
+      for (int t = 0; t < s->pp_n_term; ++t)
+        if (s->pp_atom[t] == At && s->pp_l[t] >= 0) {
+          const int n = s->pp_n[t];
+          const double f = s->pp_beta[t] * pow(r, n - 2) * exp(-s->pp_alpha[t] * r * r);
+          vl[s->pp_l[t]] += f;
+          vlp[s->pp_l[t]] += f * ((n - 2) / r - 2.0 * s->pp_alpha[t] * r);
+        }
+      for (int q = 0; q < 12; ++q) {
+        double o[3], od[3];
+        ico_dir(q, o);
+        for (int x = 0; x < 3; ++x) od[x] = rot[3 * x] * o[0] + rot[3 * x + 1] * o[1] + rot[3 * x + 2] * o[2];
+        const double cq = od[0] * nv[0] + od[1] * nv[1] + od[2] * nv[2];
+        for (int k = 0; k < 3 * ne; ++k) Rq[k] = R[k];
+        for (int x = 0; x < 3; ++x) Rq[3 * i + x] = c[x] + r * od[x];
+        double lpq, eq;
+        int32_t sgq;
+        rc |= orc_evaluate(s, Rq, &lpq, &sgq, &eq, drq);
+        const double rho = (double)(sgq * sg0) * exp(lpq - lp0);
+        const double g[3] = {rho * drq[3 * i], rho * drq[3 * i + 1], rho * drq[3 * i + 2]};
+        const double og = od[0] * g[0] + od[1] * g[1] + od[2] * g[2];
+        double f = 0.0, fp = 0.0, fc = 0.0; /* sum_l (2l+1)/12 x (v_l P_l, v_l' P_l, v_l P_l') */
+        for (int l = 0; l <= lmax; ++l) {
+          const double P = legendre(l, cq);
+          const double dP = l == 0 ? 0.0 : (l == 1 ? 1.0 : (l == 2 ? 3.0 * cq : 0.5 * (15.0 * cq * cq - 3.0)));
+          f += (2 * l + 1) / 12.0 * vl[l] * P;
+          fp += (2 * l + 1) / 12.0 * vlp[l] * P;
+          fc += (2 * l + 1) / 12.0 * vl[l] * dP;
+        }
+        for (int x = 0; x < 3; ++x)
+          dvpp[3 * At + x] += -fp * nv[x] * rho - fc * (od[x] - cq * nv[x]) / r * rho +
+                              f * (g[x] - nv[x] * og);
+      }
+    }
+  }
+  free(Rq);
+  free(drq);
+  return rc;
+}
+
 int orc_nlpp_batch(const orc_system *s, int32_t W, const double *R, uint64_t seed, int64_t step,
                    int32_t walker_offset, double *v_nl, int32_t n_threads) {
   const int ne = s->n_up + s->n_dn;

@@ -162,6 +162,10 @@ int orc_nlpp(const orc_system *s, const double *R, uint64_t seed, int64_t step, 
              double *v_nl);
 int orc_nlpp_batch(const orc_system *s, int32_t W, const double *R, uint64_t seed, int64_t step,
                    int32_t walker_offset, double *v_nl, int32_t n_threads);
+/* d(V_loc + V_NL)/dR_A at fixed electrons, rotations and Psi (the
+ * pseudopotential's Hellmann-Feynman force term): dvpp[n_atom][3]. */
+int orc_pp_ion_grads(const orc_system *s, const double *R, uint64_t seed, int64_t step,
+                     int32_t walker, double *dvpp);
 /* The rotation of electron elec of walker walker at step: rot[3][3]. */
 void orc_nlpp_rotation(uint64_t seed, int64_t step, int32_t walker, int32_t elec, double rot[9]);
 

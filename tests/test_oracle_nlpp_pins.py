@@ -15,7 +15,10 @@ facts that do not come from that code:
   re-evaluations of ln|Psi| at the moved configurations);
 * electrons outside the cutoff contribute nothing;
 * DMC runs: log w rebuilt from independent step-end energies that include
-  each step's non-local energy with that step's rotations.
+  each step's non-local energy with that step's rotations;
+* the Hellmann-Feynman force term d(V_loc + V_NL)/dR_A (Psi fixed) against
+  Richardson differences in the position of a ghost centre that carries the
+  pseudopotential alone (no charge, no basis functions, no Jastrow term).
 """
 import dataclasses
 import math
@@ -166,3 +169,44 @@ def test_dmc_weights_rebuilt_with_nonlocal_energies():
         lw += -tau * (0.5 * (es[k] + es[k + 1]) - et)
     np.testing.assert_allclose(full["e_log"][-1], es[-1], rtol=1e-13)
     np.testing.assert_allclose(full["log_w"], lw, rtol=1e-12, atol=1e-13)
+
+
+def _ghost_pp_system(pos):
+    """The small molecule with a pseudopotential on a ghost centre (no
+    charge, no basis functions, no Jastrow term): moving the ghost moves the
+    pseudopotential operator alone, Psi stays fixed."""
+    s = synth.small_molecule()
+    ion = np.vstack([s.ion_xyz, np.asarray(pos, dtype=np.float64)[None, :]])
+    g = dataclasses.replace(s, ion_xyz=ion, ion_charge=np.append(s.ion_charge, 0.0),
+                            jen_a=np.append(s.jen_a, 0.0))
+    return synth.with_pseudopotential(g, [[]] * s.n_atom + [PP_GHOST])
+
+
+PP_GHOST = [(-1, 2, -1.2, 0.9), (-1, 3, 0.6, 1.3), (0, 2, 2.5, 0.8), (1, 2, -1.1, 0.7),
+            (2, 3, 0.9, 1.2)]
+
+
+def test_pp_ion_grads_against_ghost_centre_differences():
+    """d(V_loc + V_NL)/dR_A with Psi fixed: Richardson differences of the
+    local potential plus the non-local energy (same rotations) in the
+    position of a ghost centre that carries only the pseudopotential."""
+    pos0 = np.array([0.9, 1.7, 2.2])
+    s = _ghost_pp_system(pos0)
+    R = synth.make_walkers(synth.small_molecule(), 2, 47)
+    seed, step = 13, 2
+    for w in range(2):
+        g, rc = oracle.pp_ion_grads(s, R[w], seed, step, w)
+        assert rc == 0
+        assert np.all(g[:-1] == 0.0)
+        for x in range(3):
+            def energy(t):
+                p = pos0.copy()
+                p[x] += t
+                sg = _ghost_pp_system(p)
+                return oracle.potential(sg, R[w]) + oracle.nlpp(sg, R[w], seed, step, w)[0]
+            h = 1e-3
+            d1 = (energy(h) - energy(-h)) / (2 * h)
+            d2 = (energy(2 * h) - energy(-2 * h)) / (4 * h)
+            fd = (4 * d1 - d2) / 3
+            print(f"[nlpp] walker {w} x{x}: analytic {g[-1, x]:.10f} fd {fd:.10f}")
+            assert abs(g[-1, x] - fd) < 1e-7 * max(1.0, abs(fd))
