@@ -261,14 +261,19 @@ dmcx_status dmcx_get_delay_rank(const dmcx_ctx *ctx, int32_t sys_index, int32_t 
 /* Passage: QMC section, Eq. 2 (log|Psi_T| and sign) and Single Determinant
  * QMC Forces (E_L through tr(A^{-1} B) with B the Laplacian rows, Eq. 3).
  * Current local energy, log|Psi| and sign of every walker ([W] each;
- * any pointer may be NULL). */
+ * any pointer may be NULL).  With a pseudopotential, E_L carries its local
+ * terms and its non-local energy: per electron and atom within the cutoff
+ * the 12-point icosahedral rule, turned by a random rotation (Philox draws 3
+ * and 4 of (electron, walker, step) under the seed, step = the step counter
+ * when the energy was formed: the step's own index inside a run). */
 dmcx_status dmcx_measure(dmcx_ctx *ctx, double *e_local, double *log_psi, int8_t *sign,
                          dmcx_mem mem);
 
 /* Passage: QMC section (the many-body Hamiltonian's potential; its ion
  * derivative is the Hellmann-Feynman term of Single Determinant QMC Forces).
  * Coulomb potential V(R) of each walker's current configuration, [W]
- * (electron-electron + electron-ion + ion-ion). */
+ * (electron-electron + electron-ion + ion-ion), plus the pseudopotential's
+ * local and non-local energies when the system has one. */
 dmcx_status dmcx_potential(dmcx_ctx *ctx, double *v, dmcx_mem mem);
 
 /* Passage: Single Determinant QMC Forces, Eq. 3 with lambda = an ion
@@ -276,7 +281,11 @@ dmcx_status dmcx_potential(dmcx_ctx *ctx, double *v, dmcx_mem mem);
  * Multideterminant QMC Forces for n_det > 1.
  * Per-walker ion derivatives: dlogpsi_dR and dV_dR, [W][n_atom_max][3]
  * (either may be NULL).  Reverse-mode adjoint of basis, MO contraction,
- * log-determinant and Jastrow (Eq. 3 with lambda = an ion coordinate). */
+ * log-determinant and Jastrow (Eq. 3 with lambda = an ion coordinate).
+ * With a pseudopotential dV_dR includes its Hellmann-Feynman term, the
+ * derivative of the local terms and of the non-local quadrature with respect
+ * to the pseudopotential's centre at fixed electrons and Psi (rotations of
+ * the current step counter). */
 dmcx_status dmcx_ion_grads(dmcx_ctx *ctx, double *dlogpsi_dR, double *dV_dR, dmcx_mem mem);
 
 /* Passage: Single Determinant QMC Forces, Eq. 3 (the same derivatives as
@@ -306,8 +315,8 @@ dmcx_status dmcx_forces(dmcx_ctx *ctx, double *F, dmcx_mem mem);
  * the warp.  warp = 0: the ion coordinate alone (dlogjac = 0); warp = 1:
  * ion plus warped electrons.  Reverse-mode adjoint through the inverse, the
  * MO contraction (two MFMA products per electron) and third derivatives of
- * the basis.  Single-determinant systems only (DMCX_E_UNSUPPORTED
- * otherwise); DMCX_E_INVALID for warp outside {0, 1}. */
+ * the basis.  Single-determinant systems without a pseudopotential only
+ * (DMCX_E_UNSUPPORTED otherwise); DMCX_E_INVALID for warp outside {0, 1}. */
 dmcx_status dmcx_zv_grads(dmcx_ctx *ctx, int32_t warp, double *dEL, double *dlogpsi,
                           double *dlogjac, dmcx_mem mem);
 
@@ -410,7 +419,8 @@ dmcx_status dmcx_get_trial_energy(dmcx_ctx *ctx, double *e_trial);
  * and dEL[W][8] = dE_L/dp = -1/2 sum_i [lap_i O_p + 2 grad_i ln|Psi| . grad_i O_p]
  * (either may be NULL).  FP64 arithmetic; grad_i ln|Psi| comes from the
  * context's inverse and orbital rows (FP32 in the mixed form).  Single-
- * determinant systems only (DMCX_E_UNSUPPORTED otherwise). */
+ * determinant systems without a pseudopotential only (DMCX_E_UNSUPPORTED
+ * otherwise). */
 #define DMCX_N_JASTROW_PARAMS 8
 dmcx_status dmcx_jastrow_param_grads(dmcx_ctx *ctx, double *dlogpsi, double *dEL, dmcx_mem mem);
 

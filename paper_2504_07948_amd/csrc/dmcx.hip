@@ -728,8 +728,6 @@ dmcx_status refresh_after_moves(dmcx_ctx *c) {
 
 // Per-walker ion derivatives for the current configuration (cached).
 dmcx_status compute_ion_grads(dmcx_ctx *c) {
-  if (c->dc.pp_n > 0)
-    return fail(c, DMCX_E_UNSUPPORTED, "ion derivatives of pseudopotentials are not built");
   dmcx_status st0 = refresh_after_moves(c);
   if (st0) return st0;
   if (c->grads_version == c->version) return DMCX_OK;
@@ -764,6 +762,13 @@ dmcx_status compute_ion_grads(dmcx_ctx *c) {
   hipLaunchKernelGGL(k_ion_grad_finalize, dim3(c->Wpad), dim3(64), 0, c->stream, c->dc,
                      c->d_partial, c->d_dl, c->d_dv);
   HIP_TRY(c, hipGetLastError());
+  if (c->dc.pp_n > 0) {
+    // the pseudopotential's Hellmann-Feynman term, with the inverse-column
+    // products y_e of the last energy evaluation (the current configuration)
+    hipLaunchKernelGGL(k_pp_grad, dim3(c->W), dim3(NT_AUX), pp_grad_lds_bytes(c->ne, c->dc.pp_nl),
+                       c->stream, c->dc, (const double *)c->d_ppY, c->pp_ldy, c->d_dv);
+    HIP_TRY(c, hipGetLastError());
+  }
   c->grads_version = c->version;
   return DMCX_OK;
 }
@@ -771,6 +776,9 @@ dmcx_status compute_ion_grads(dmcx_ctx *c) {
 // Per-walker zero-variance derivatives (Eq. 4, optionally space-warped) for
 // the current configuration (cached per configuration version and warp flag).
 dmcx_status compute_zv(dmcx_ctx *c, int warp) {
+  if (c->dc.pp_n > 0)
+    return fail(c, DMCX_E_UNSUPPORTED,
+                "zero-variance forces: the non-local pseudopotential's term is not built");
   if (c->dc.M.on)
     return fail(c, DMCX_E_UNSUPPORTED, "zero-variance forces: single-determinant systems only");
   dmcx_status st = compute_ion_grads(c);  // also brings E_L and the inverses up to date
@@ -1150,7 +1158,7 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
       }
       c->pp_ldy = (c->dc.B.Kp + 63) / 64 * 64;
       if ((st = dalloc(c, &c->d_ppY, (size_t)c->W * c->ne * c->pp_ldy))) return bail(st);
-      if (pp_lds_bytes(c->ne, d.pp_nl) > 64 * 1024) {
+      if (pp_grad_lds_bytes(c->ne, d.pp_nl) + 8 * 1024 > 64 * 1024) {
         c->err = "pseudopotential: pair list exceeds 64 KB of LDS";
         return bail(DMCX_E_UNSUPPORTED);
       }

@@ -189,23 +189,21 @@ inline size_t pp_lds_bytes(int ne, int n_nl) {
   return (size_t)ne * 13 * sizeof(double) + (size_t)(cap > 0 ? cap : 1) * sizeof(int);
 }
 
-// Pseudopotential energy (local terms + non-local quadrature) of every walker
-// into c.vps [W].  grid W, block NT_AUX (NT_AUX >= ne), dynamic LDS
-// pp_lds_bytes(ne, c.pp_nl).  A walker whose listed pairs exceed the LDS list
-// gets NaN (flagged by the energy kernel), never a partial sum.
-__global__ __launch_bounds__(NT_AUX) void k_pp(DevCtx c, const double *Y, int ldy) {
-  extern __shared__ double sm[];
-  __shared__ int s_cnt[NT_AUX];
-  __shared__ double red[NT_AUX / 64];
-  const int ne = c.ne, w = blockIdx.x, tid = threadIdx.x;
-  double *s_r = sm;             // [ne][3]
-  double *s_rot = sm + 3 * ne;  // [ne][9]
-  double *s_J = sm + 12 * ne;   // [ne]
+// Per-walker set-up shared by the energy and force kernels: positions to
+// s_r, the rotations of electrons with pairs to s_rot, their own Jastrow
+// sums to s_J, and the (electron, atom) pairs within the cutoffs to s_pair,
+// electron by electron (a block scan, so the order is fixed).  Returns the
+// pair count (block-uniform); *over is set when it exceeds the list.  e_loc
+// receives this thread's share of the local-term energy.
+__device__ inline int pp_setup(const DevCtx &c, int w, double *sm, int *s_cnt, bool &over,
+                               double &e_loc) {
+  const int ne = c.ne, tid = threadIdx.x;
+  double *s_r = sm, *s_rot = sm + 3 * ne, *s_J = sm + 12 * ne;
   int *s_pair = (int *)(sm + 13 * ne);
   const int cap = ne * (c.pp_nl < PP_MAXA ? c.pp_nl : PP_MAXA);
   const double *Rw = c.R + (size_t)w * ne * 3;
   const uint32_t step = (uint32_t)c.run->step;
-  double acc = 0.0;
+  e_loc = 0.0;
   int cnt = 0;
   if (tid < ne) {
     const double r[3] = {Rw[3 * tid], Rw[3 * tid + 1], Rw[3 * tid + 2]};
@@ -217,7 +215,7 @@ __global__ __launch_bounds__(NT_AUX) void k_pp(DevCtx c, const double *Y, int ld
       const double *RA = c.ion + 3 * tt.x;
       const double dx = r[0] - RA[0], dy = r[1] - RA[1], dz = r[2] - RA[2];
       const double2 ba = c.pp_ba[t];
-      acc += pp_term(tt.z, ba.x, ba.y, sqrt(dx * dx + dy * dy + dz * dz));
+      e_loc += pp_term(tt.z, ba.x, ba.y, sqrt(dx * dx + dy * dy + dz * dz));
     }
     for (int k = 0; k < c.pp_nl; ++k) {
       const double *RA = c.ion + 3 * c.pp_nl_atom[k];
@@ -236,7 +234,7 @@ __global__ __launch_bounds__(NT_AUX) void k_pp(DevCtx c, const double *Y, int ld
     __syncthreads();
   }
   const int npair = s_cnt[NT_AUX - 1];
-  const bool over = npair > cap;
+  over = npair > cap;
   if (tid < ne) {
     s_J[tid] = cnt ? jastrow_at(c, s_r, tid, s_r + 3 * tid) : 0.0;
     if (!over && cnt) {
@@ -251,30 +249,61 @@ __global__ __launch_bounds__(NT_AUX) void k_pp(DevCtx c, const double *Y, int ld
     }
   }
   __syncthreads();
+  return npair;
+}
+
+// Geometry of quadrature point q of pair pr: the electron e, atom A, the
+// electron's offset d from the atom, its distance r, the rotated direction od,
+// cos theta and the point itself.
+struct PPPoint {
+  int e, A;
+  double d[3], r, od[3], cth, p[3];
+};
+__device__ __forceinline__ PPPoint pp_point(const DevCtx &c, const double *s_r,
+                                            const double *s_rot, int pr, int q) {
+  PPPoint P;
+  P.e = pr & 0xffff;
+  P.A = pr >> 16;
+  const double *RA = c.ion + 3 * P.A;
+  for (int x = 0; x < 3; ++x) P.d[x] = s_r[3 * P.e + x] - RA[x];
+  P.r = sqrt(P.d[0] * P.d[0] + P.d[1] * P.d[1] + P.d[2] * P.d[2]);
+  double o[3];
+  ico_dir(q, o);
+  const double *rot = s_rot + 9 * P.e;
+#pragma unroll
+  for (int x = 0; x < 3; ++x) P.od[x] = rot[3 * x] * o[0] + rot[3 * x + 1] * o[1] + rot[3 * x + 2] * o[2];
+  P.cth = (P.od[0] * P.d[0] + P.od[1] * P.d[1] + P.od[2] * P.d[2]) / P.r;
+  for (int x = 0; x < 3; ++x) P.p[x] = RA[x] + P.r * P.od[x];
+  return P;
+}
+
+// Pseudopotential energy (local terms + non-local quadrature) of every walker
+// into c.vps [W].  grid W, block NT_AUX (NT_AUX >= ne), dynamic LDS
+// pp_lds_bytes(ne, c.pp_nl).  A walker whose listed pairs exceed the LDS list
+// gets NaN (flagged by the energy kernel), never a partial sum.
+__global__ __launch_bounds__(NT_AUX) void k_pp(DevCtx c, const double *Y, int ldy) {
+  extern __shared__ double sm[];
+  __shared__ int s_cnt[NT_AUX];
+  __shared__ double red[NT_AUX / 64];
+  const int ne = c.ne, w = blockIdx.x, tid = threadIdx.x;
+  const double *s_r = sm, *s_rot = sm + 3 * ne, *s_J = sm + 12 * ne;
+  const int *s_pair = (const int *)(sm + 13 * ne);
+  bool over;
+  double acc;
+  const int npair = pp_setup(c, w, sm, s_cnt, over, acc);
   if (!over) {
     for (int p = tid; p < npair * 12; p += NT_AUX) {
-      const int pr = s_pair[p / 12], q = p - (p / 12) * 12;
-      const int e = pr & 0xffff, A = pr >> 16;
-      const double *RA = c.ion + 3 * A;
-      const double d[3] = {s_r[3 * e] - RA[0], s_r[3 * e + 1] - RA[1], s_r[3 * e + 2] - RA[2]};
-      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      double o[3], od[3];
-      ico_dir(q, o);
-      const double *rot = s_rot + 9 * e;
-#pragma unroll
-      for (int x = 0; x < 3; ++x) od[x] = rot[3 * x] * o[0] + rot[3 * x + 1] * o[1] + rot[3 * x + 2] * o[2];
-      const double cth = (od[0] * d[0] + od[1] * d[1] + od[2] * d[2]) / r;
-      const double pq[3] = {RA[0] + r * od[0], RA[1] + r * od[1], RA[2] + r * od[2]};
-      const double rdet = basis_dot(c.B, pq, Y + ((size_t)w * ne + e) * ldy);
-      const double ratio = rdet * exp(jastrow_at(c, s_r, e, pq) - s_J[e]);
+      const PPPoint P = pp_point(c, s_r, s_rot, s_pair[p / 12], p % 12);
+      const double rdet = basis_dot(c.B, P.p, Y + ((size_t)w * ne + P.e) * ldy);
+      const double ratio = rdet * exp(jastrow_at(c, s_r, P.e, P.p) - s_J[P.e]);
       double vl[4] = {0.0, 0.0, 0.0, 0.0};
       for (int t = 0; t < c.pp_n; ++t) {
         const int4 tt = c.pp_t[t];
-        if (tt.x == A && tt.y >= 0) vl[tt.y] += pp_term(tt.z, c.pp_ba[t].x, c.pp_ba[t].y, r);
+        if (tt.x == P.A && tt.y >= 0) vl[tt.y] += pp_term(tt.z, c.pp_ba[t].x, c.pp_ba[t].y, P.r);
       }
       double f = 0.0;
 #pragma unroll
-      for (int l = 0; l < 4; ++l) f += vl[l] * (2 * l + 1) * legendre_pl(l, cth);
+      for (int l = 0; l < 4; ++l) f += vl[l] * (2 * l + 1) * legendre_pl(l, P.cth);
       acc += f * ratio * (1.0 / 12.0);
     }
   }
@@ -287,6 +316,178 @@ __global__ __launch_bounds__(NT_AUX) void k_pp(DevCtx c, const double *Y, int ld
     for (int k = 0; k < NT_AUX / 64; ++k) t += red[k];
     c.vps[w] = over ? __builtin_nan("") : t;
   }
+}
+
+// Basis values and gradients at p dotted with y: val = sum Phi y,
+// grad = sum grad Phi y.  Called by every active lane of a wave.
+__device__ inline void basis_dot_grad(const DevBasis &B, const double p[3], const double *y,
+                                      double &val, double grad[3]) {
+  val = 0.0;
+  grad[0] = grad[1] = grad[2] = 0.0;
+  for (int g = 0; g < B.n_group; ++g) {
+    const int4 gi = B.ginfo[g];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double *ctr = B.gxyz + (size_t)(g * 4 + q) * 3;
+      const double dx = p[0] - ctr[0], dy = p[1] - ctr[1], dz = p[2] - ctr[2];
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      double rad = 0.0, rp = 0.0;  // sum c e^{-a r^2}, sum -2 a c e^{-a r^2}
+      for (int k = 0; k < gi.y; ++k) {
+        const int sl = gi.w + k * 4 + q;
+        const double ar = B.galpha[sl] * r2;
+        if (__any(ar < 46.0)) {
+          const double e = B.gcoef[sl] * exp(-ar);
+          rad += e;
+          rp -= 2.0 * B.galpha[sl] * e;
+        }
+      }
+      const double *yq = y + gi.z + q;
+      // Phi = P rad, grad Phi = grad P rad + P rp (dx, dy, dz)
+      double P = 0.0, Px = 0.0, Py = 0.0, Pz = 0.0;
+      if (gi.x == 0) {
+        P = yq[0];
+      } else if (gi.x == 1) {
+        P = dx * yq[0] + dy * yq[4] + dz * yq[8];
+        Px = yq[0];
+        Py = yq[4];
+        Pz = yq[8];
+      } else {
+        const double xx = yq[0], xy = yq[4], xz = yq[8], yy = yq[12], yz = yq[16], zz = yq[20];
+        P = dx * dx * xx + dx * dy * xy + dx * dz * xz + dy * dy * yy + dy * dz * yz + dz * dz * zz;
+        Px = 2.0 * dx * xx + dy * xy + dz * xz;
+        Py = dx * xy + 2.0 * dy * yy + dz * yz;
+        Pz = dx * xz + dy * yz + 2.0 * dz * zz;
+      }
+      val += P * rad;
+      grad[0] += Px * rad + P * rp * dx;
+      grad[1] += Py * rad + P * rp * dy;
+      grad[2] += Pz * rad + P * rp * dz;
+    }
+  }
+}
+
+// J terms of electron e at p and their gradient with respect to p.
+__device__ inline double jastrow_at_grad(const DevCtx &c, const double *s_r, int e,
+                                         const double p[3], double g[3]) {
+  const int se = e < c.n_up ? 0 : 1;
+  double u = 0.0;
+  g[0] = g[1] = g[2] = 0.0;
+  for (int j = 0; j < c.ne + c.n_atom; ++j) {
+    if (j == e) continue;
+    const bool el = j < c.ne;
+    const double *x = el ? s_r + 3 * j : c.ion + 3 * (j - c.ne);
+    const double dx = p[0] - x[0], dy = p[1] - x[1], dz = p[2] - x[2];
+    const double rr = sqrt(dx * dx + dy * dy + dz * dz);
+    const double a = el ? (((j < c.n_up ? 0 : 1) == se) ? c.jee_para : c.jee_anti) : c.jen_a[j - c.ne];
+    const Pade pd = pade(a, el ? c.jee_b : c.jen_b, rr);
+    u += pd.u;
+    const double f = pd.d1 / rr;
+    g[0] += f * dx;
+    g[1] += f * dy;
+    g[2] += f * dz;
+  }
+  return u;
+}
+
+constexpr int PP_CHUNK = 20;  // pairs per round of the force kernel (240 points)
+
+// Hellmann-Feynman term of the pseudopotential in the ion derivative of V:
+// d(V_loc + V_NL)/dR_A at fixed electrons, rotations and Psi, added to
+// dv [W][n_atom][3].  Per quadrature point, with n = d / r, c = od . n,
+// rho = Psi(p)/Psi(R) and g = grad_p rho:
+//   -(f' n + f_c (od - c n) / r) rho + f (g - n (od . g)),
+//   f = sum_l (2l+1)/12 v_l P_l(c), f' its r-derivative, f_c its c-derivative.
+// The 12 points of a pair are taken by 12 lanes of one round (20 pairs per
+// round) and summed through LDS in point order, the pairs of an atom in pair
+// order: no atomics, bit-reproducible.  grid W, block NT_AUX, dynamic LDS
+// pp_grad_lds_bytes(ne, c.pp_nl).
+__global__ __launch_bounds__(NT_AUX) void k_pp_grad(DevCtx c, const double *Y, int ldy,
+                                                    double *dv) {
+  extern __shared__ double sm[];
+  __shared__ int s_cnt[NT_AUX];
+  __shared__ double s_pt[PP_CHUNK * 12][3];
+  const int ne = c.ne, w = blockIdx.x, tid = threadIdx.x;
+  const double *s_r = sm, *s_rot = sm + 3 * ne, *s_J = sm + 12 * ne;
+  const int *s_pair = (const int *)(sm + 13 * ne);
+  const int cap = ne * (c.pp_nl < PP_MAXA ? c.pp_nl : PP_MAXA);
+  double *s_pv = sm + 13 * ne + (cap + 1) / 2;  // [cap][3] per-pair sums
+  bool over;
+  double e_unused;
+  const int npair = pp_setup(c, w, sm, s_cnt, over, e_unused);
+  for (int p0 = 0; p0 < npair && !over; p0 += PP_CHUNK) {
+    const int pl = p0 + tid / 12;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (tid < PP_CHUNK * 12 && pl < npair) {
+      const PPPoint P = pp_point(c, s_r, s_rot, s_pair[pl], tid % 12);
+      double rdet, gdet[3], gj[3];
+      basis_dot_grad(c.B, P.p, Y + ((size_t)w * ne + P.e) * ldy, rdet, gdet);
+      const double ej = exp(jastrow_at_grad(c, s_r, P.e, P.p, gj) - s_J[P.e]);
+      const double rho = rdet * ej;
+      double g[3];
+      for (int x = 0; x < 3; ++x) g[x] = ej * (gdet[x] + rdet * gj[x]);
+      double vl[4] = {0, 0, 0, 0}, vlp[4] = {0, 0, 0, 0};
+      for (int t = 0; t < c.pp_n; ++t) {
+        const int4 tt = c.pp_t[t];
+        if (tt.x == P.A && tt.y >= 0) {
+          const double f = pp_term(tt.z, c.pp_ba[t].x, c.pp_ba[t].y, P.r);
+          vl[tt.y] += f;
+          vlp[tt.y] += f * ((tt.z - 2) / P.r - 2.0 * c.pp_ba[t].y * P.r);
+        }
+      }
+      const double cq = P.cth;
+      double f = 0.0, fp = 0.0, fc = 0.0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const double Pl = legendre_pl(l, cq);
+        const double dP = l == 0 ? 0.0 : (l == 1 ? 1.0 : (l == 2 ? 3.0 * cq : 0.5 * (15.0 * cq * cq - 3.0)));
+        f += (2 * l + 1) / 12.0 * vl[l] * Pl;
+        fp += (2 * l + 1) / 12.0 * vlp[l] * Pl;
+        fc += (2 * l + 1) / 12.0 * vl[l] * dP;
+      }
+      const double n[3] = {P.d[0] / P.r, P.d[1] / P.r, P.d[2] / P.r};
+      const double og = P.od[0] * g[0] + P.od[1] * g[1] + P.od[2] * g[2];
+      for (int x = 0; x < 3; ++x)
+        v[x] = -fp * n[x] * rho - fc * (P.od[x] - cq * n[x]) / P.r * rho + f * (g[x] - n[x] * og);
+    }
+    if (tid < PP_CHUNK * 12)
+      for (int x = 0; x < 3; ++x) s_pt[tid][x] = v[x];
+    __syncthreads();
+    if (tid < PP_CHUNK && p0 + tid < npair)
+      for (int x = 0; x < 3; ++x) {
+        double t = 0.0;
+        for (int q = 0; q < 12; ++q) t += s_pt[tid * 12 + q][x];
+        s_pv[(p0 + tid) * 3 + x] = t;
+      }
+    __syncthreads();
+  }
+  // per atom: the local terms over electrons, then the pairs in pair order
+  for (int A = tid; A < c.n_atom; A += NT_AUX) {
+    double g[3] = {0.0, 0.0, 0.0};
+    const double *RA = c.ion + 3 * A;
+    for (int t = 0; t < c.pp_n; ++t) {
+      const int4 tt = c.pp_t[t];
+      if (tt.x != A || tt.y != -1) continue;
+      for (int e = 0; e < ne; ++e) {
+        const double d[3] = {s_r[3 * e] - RA[0], s_r[3 * e + 1] - RA[1], s_r[3 * e + 2] - RA[2]};
+        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double f = pp_term(tt.z, c.pp_ba[t].x, c.pp_ba[t].y, r);
+        const double fp = f * ((tt.z - 2) / r - 2.0 * c.pp_ba[t].y * r);
+        for (int x = 0; x < 3; ++x) g[x] -= fp * d[x] / r;
+      }
+    }
+    if (!over)
+      for (int p = 0; p < npair; ++p)
+        if ((s_pair[p] >> 16) == A)
+          for (int x = 0; x < 3; ++x) g[x] += s_pv[p * 3 + x];
+    double *o = dv + ((size_t)w * c.n_atom + A) * 3;
+    for (int x = 0; x < 3; ++x) o[x] = over ? __builtin_nan("") : o[x] + g[x];
+  }
+}
+
+inline size_t pp_grad_lds_bytes(int ne, int n_nl) {
+  const int cap = ne * (n_nl < PP_MAXA ? n_nl : PP_MAXA);
+  return (size_t)ne * 13 * sizeof(double) + (size_t)((cap + 1) / 2) * sizeof(double) +
+         (size_t)(cap > 0 ? cap : 1) * 3 * sizeof(double);
 }
 
 }  // namespace dmcx

@@ -8,7 +8,10 @@ E_L + V_NL at the same configurations; DMC runs with the accept sequence
 bit-exact and E_L, positions and log-weights within 1e-10; in the mixed form
 the pseudopotential part (from the FP64 inverse) within 1e-10 and E_L at the
 mixed form's bars; graph replays bit-identical to eager steps;
-a group equal to its systems' own contexts; forces on such systems rejected.
+a group equal to its systems' own contexts; Eq. 3 ion derivatives with the
+pseudopotential's Hellmann-Feynman term and the force estimate at 1e-10;
+zero-variance forces, Jastrow derivatives and multideterminant expansions
+with a pseudopotential rejected.
 """
 import numpy as np
 import pytest
@@ -163,12 +166,72 @@ def test_group_with_and_without_pseudopotential():
         np.testing.assert_array_equal(el[:, sl], el1)
 
 
-def test_forces_and_multideterminant_rejected():
+def _oracle_dv(s, R, seed, step):
+    _, dv, rc = oracle.ion_grads_batch(s, R)
+    assert rc == 0
+    for w in range(R.shape[0]):
+        g, rc = oracle.pp_ion_grads(s, R[w], seed, step, w)
+        assert rc == 0
+        dv[w] += g
+    return dv
+
+
+def test_ion_grads_and_forces_with_pseudopotential():
+    """Eq. 3 ion derivatives with the pseudopotential's Hellmann-Feynman term
+    (its centre moved at fixed electrons and Psi, rotations of the current
+    step counter) against the oracle, at set-up and after DMC steps; the
+    force estimate F = -<dV> - 2(<E_L dlnPsi> - <E_L><dlnPsi>) against the
+    oracle's per-walker values (E_L with the rotations of its own step)."""
+    s = synth.small_molecule_pp()
+    W, seed = 16, 27
+    R = synth.make_walkers(s, W, 3307)
+    lw = np.random.default_rng(2).normal(0.0, 0.3, W)
+    ctx = dmcx.Context(s, W, seed=seed, delay_rank=2, recompute_period=3)
+    ctx.set_walkers(R, lw)
+    dl, dv = ctx.ion_grads()
+    dl_o, _, _ = oracle.ion_grads_batch(s, R)
+    _close(dl, dl_o, label="dln|Psi|/dR (set-up)")
+    _close(dv, _oracle_dv(s, R, seed, 0), label="dV/dR with pseudopotential (set-up)")
+    e, _, _ = ctx.measure()
+    om = np.exp(lw - lw.max())
+    om /= om.sum()
+    mean = lambda x: np.einsum("w,w...->...", om, x)
+    e_o = _oracle_energy(s, R, seed, 0)
+    dv_o = _oracle_dv(s, R, seed, 0)
+    F_ref = -mean(dv_o) - 2 * (mean(e_o[:, None, None] * dl_o) - mean(e_o) * mean(dl_o))
+    _close(ctx.forces(), F_ref, rel=1e-10, label="force estimate")
+    ctx.run(2, mode=dmcx.DMCX_DMC, e_trial=-10.0)
+    Rg, _ = ctx.get_walkers()
+    dl, dv = ctx.ion_grads()
+    _close(dv, _oracle_dv(s, Rg, seed, 2), label="dV/dR with pseudopotential (after steps)")
+
+
+def test_ion_grads_large_molecule_sampled():
+    s = synth.large_molecule_pp()
+    W, seed = 32, 28
+    R = synth.make_walkers(s, W, 3308)
+    ctx = dmcx.Context(s, W, seed=seed, delay_rank=32, recompute_period=64)
+    ctx.set_walkers(R)
+    _, dv = ctx.ion_grads()
+    idx = [0, W - 1]
+    ref = np.array([_oracle_dv(s, R[i:i + 1], seed, 0)[0] if i == 0 else
+                    _oracle_dv_one(s, R[i], seed, 0, i) for i in idx])
+    _close(dv[idx], ref, label="large dV/dR with pseudopotential")
+
+
+def _oracle_dv_one(s, Rw, seed, step, w):
+    _, dv, _ = oracle.ion_grads_batch(s, Rw[None])
+    g, rc = oracle.pp_ion_grads(s, Rw, seed, step, w)
+    assert rc == 0
+    return dv[0] + g
+
+
+def test_unsupported_with_pseudopotential():
     s = synth.small_molecule_pp()
     ctx = dmcx.Context(s, 8)
     ctx.set_walkers(synth.make_walkers(s, 8, 1))
     with pytest.raises(dmcx.DmcxError) as e:
-        ctx.forces()
+        ctx.zv_grads(warp=True)
     assert e.value.status == dmcx.DMCX_E_UNSUPPORTED
     with pytest.raises(dmcx.DmcxError) as e:
         ctx.jastrow_param_grads()
