@@ -278,7 +278,9 @@ def pp_leg(torch, dmcx, stream, W=2048, steps=5, cpu_walkers=2):
     """DMC steps of the large molecule with a semilocal pseudopotential on its
     16 "C" atoms (synthetic stand-in tables in the ccECP form: a local term
     and a non-local s channel, cutoff 2.15 bohr), FP64, k = 32, P = 64,
-    against the same steps without it.  Every step's E_L then carries the
+    against the same steps without it, each also with the Eq. 3 force
+    estimate after every step (with the pseudopotential its Hellmann-Feynman
+    term comes in).  Every step's E_L then carries the
     non-local energy: 12 quadrature points per (electron, atom) pair within
     the cutoff, each a basis evaluation dotted with y_e = C (A^-1)_{:,e} and
     a Jastrow ratio.  Points are counted on the host from the final walkers;
@@ -289,6 +291,17 @@ def pp_leg(torch, dmcx, stream, W=2048, steps=5, cpu_walkers=2):
         ctx, ms, sw = _timed_ctx(s, torch, dmcx, stream, W, steps, 31, precision=dmcx.DMCX_FP64,
                                  delay_rank=32, recompute_period=64)
         out[f"ms_per_step_{name}_pp"] = ms
+        # the same steps with the Eq. 3 force estimate after each
+        F = torch.empty((s.n_atom, 3), dtype=torch.float64, device="cuda")
+        e_t = float(np.mean(ctx.measure()[0]))
+        ctx.check(dmcx.dmcx_forces(ctx.h, F.data_ptr(), dmcx.DMCX_DEVICE))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.run_device(1, mode=dmcx.DMCX_DMC, e_trial=e_t)
+            ctx.check(dmcx.dmcx_forces(ctx.h, F.data_ptr(), dmcx.DMCX_DEVICE))
+        torch.cuda.synchronize()
+        out[f"ms_per_step_with_forces_{name}_pp"] = 1e3 * (time.perf_counter() - t0) / steps
         if name == "with":
             R, _ = ctx.get_walkers()
             nl = [a for a in range(s.n_atom) if np.any((s.pp_atom == a) & (s.pp_l >= 0))]
@@ -302,6 +315,8 @@ def pp_leg(torch, dmcx, stream, W=2048, steps=5, cpu_walkers=2):
             out["oracle_nlpp_ms_per_walker_one_thread"] = 1e3 * (time.perf_counter() - tc) / cpu_walkers
         ctx.close()
     out["pp_cost_ratio"] = out["ms_per_step_with_pp"] / out["ms_per_step_without_pp"]
+    out["force_energy_cost_ratio_with_pp"] = (out["ms_per_step_with_forces_with_pp"] /
+                                              out["ms_per_step_with_pp"])
     extra = out["ms_per_step_with_pp"] - out["ms_per_step_without_pp"]
     out["pp_ms_per_step"] = extra
     out["points_per_s"] = out["quadrature_points_per_step"] / (extra * 1e-3) if extra > 0 else None
