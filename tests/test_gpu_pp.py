@@ -243,3 +243,36 @@ def test_unsupported_with_pseudopotential():
     with pytest.raises(dmcx.DmcxError) as e:
         dmcx.Context(msd, 8)
     assert e.value.status == dmcx.DMCX_E_UNSUPPORTED
+
+
+def test_mixed_fp32_energy_form():
+    """The mixed form with its FP32 energy (E_L from the FP32 rows and the
+    FP32 inverse, which also feeds y_e): E_L and the pseudopotential part at
+    that form's bar, |dE| <= 1e-6 cond(A) max(|E|, N_e) per walker at set-up
+    (no FP32 update has accumulated yet)."""
+    s = synth.small_molecule_pp()
+    bare_s = synth.small_molecule()
+    W, seed = 24, 29
+    R = synth.make_walkers(s, W, 3309)
+    ctx = dmcx.Context(s, W, seed=seed, precision=dmcx.DMCX_MIXED, fp32_energy=True)
+    bare = dmcx.Context(bare_s, W, seed=seed, precision=dmcx.DMCX_MIXED, fp32_energy=True)
+    ctx.set_walkers(R)
+    bare.set_walkers(R)
+    e, _, _ = ctx.measure()
+    eb, _, _ = bare.measure()
+    ref = _oracle_energy(s, R, seed, 0)
+    dv = np.array([oracle.potential(s, R[w]) - oracle.potential(bare_s, R[w]) for w in range(W)])
+    vnl, _ = oracle.nlpp_batch(s, R, seed, 0)
+    cond = []
+    for w in range(W):
+        for sp, (a, b) in enumerate(((0, s.n_up), (s.n_up, s.n_elec))):
+            A = np.array([oracle.orbitals_vgl(s, R[w, i], b - a)[0] for i in range(a, b)])
+            cond.append(np.linalg.cond(A))
+    cmax = max(cond)
+    ne = s.n_elec
+    err_pp = np.abs((e - eb) - (dv + vnl)) / np.maximum(np.abs(e), 1.0)
+    err = np.abs(e - ref) / np.maximum(np.abs(ref), ne)
+    print(f"[pp] fp32-energy: max cond {cmax:.1e}, pseudopotential part {err_pp.max():.2e}, "
+          f"E_L {err.max():.2e}", flush=True)
+    assert np.all(err_pp <= 1e-6 * cmax)
+    assert np.all(err <= 1e-6 * cmax)
