@@ -144,3 +144,26 @@ def test_multideterminant_unsupported():
         ctx.jastrow_param_grads()
     with pytest.raises(dmcx.DmcxError):
         ctx.linear_method()
+
+
+def test_optimisation_on_the_gpu_reaches_the_exact_jastrow():
+    """The linear method end to end on the GPU path: VMC runs, the
+    walkers' derivatives and the matrices S, H from the library, the step
+    from optimize.linear_method_update; the hydrogen-like 1s with the Pade
+    e-n term goes from b = 0.4 to the exact b = 0 (E_L = -Z^2/2)."""
+    from paper_2504_07948_amd import optimize
+    b, W = 0.4, 512
+    R = np.random.default_rng(5).normal(0.0, 1.0, (W, 1, 3))
+    for it in range(6):
+        s = synth.System("h1s", np.zeros((1, 3)), np.array([1.0]), [0], [0], [1], [0.0], [1.0],
+                         np.ones((1, 1)), 1, 0, jen_a=np.array([-1.0]), jen_b=b)
+        ctx = dmcx.Context(s, W, tau=0.1, seed=11 + it, delay_rank=1)
+        ctx.set_walkers(R)
+        ctx.run(30, mode=dmcx.DMCX_VMC)
+        R, _ = ctx.get_walkers()
+        S, H = ctx.linear_method()
+        dp, _ = optimize.linear_method_update(S[0], H[0], params=[1], shift=1e-4)
+        print(f"[jparams] optimisation step {it}: b {b:.5f} -> {b + dp[0]:.5f}, "
+              f"<E> {H[0][0, 0]:.6f}", flush=True)
+        b += dp[0]
+    assert abs(b) < 0.02
