@@ -79,6 +79,7 @@ def _load():
         lib.orc_evaluate_batch.argtypes = [P, C.c_int32, P, P, P, P, C.c_int32]
         lib.orc_msd_ratio_direct.argtypes = [P, P, P]
         lib.orc_reconfigure.argtypes = [C.c_int32, P, C.c_double, P, P, P, P]
+        lib.orc_branch.argtypes = [C.c_int32, P, P, C.c_uint64, C.c_int64, C.c_int32, P, P, P, P]
         lib.orc_local_energy_dir.argtypes = [P, P, P, P, P, P]
         lib.orc_zv_grads.argtypes = [P, P, C.c_int32, P, P, P]
         lib.orc_zv_grads_batch.argtypes = [P, C.c_int32, P, C.c_int32, P, P, P, C.c_int32]
@@ -507,3 +508,18 @@ def pp_ion_grads(sys, R, seed, step, walker):
     rc = _load().orc_pp_ion_grads(o.ref, _ptr(np.ascontiguousarray(R, dtype=np.float64)), seed,
                                   step, walker, _ptr(g))
     return g, rc
+
+
+def branch(log_w, seed, step, cap, flags=None):
+    """Birth/death branching: (copies [W], pairs [n][2] (destination,
+    source), W', rc)."""
+    lw = np.ascontiguousarray(log_w, dtype=np.float64)
+    W = lw.shape[0]
+    fl = None if flags is None else np.ascontiguousarray(flags, dtype=np.uint8)
+    copies = np.zeros(W, dtype=np.int32)
+    pairs = np.zeros((W + cap + 1, 2), dtype=np.int32)
+    n = C.c_int32()
+    wn = C.c_int32()
+    rc = _load().orc_branch(W, _ptr(lw), _ptr(fl), seed, step, cap, _ptr(copies), _ptr(pairs),
+                            C.byref(n), C.byref(wn))
+    return copies, pairs[: n.value].copy(), int(wn.value), rc

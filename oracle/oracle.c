@@ -777,6 +777,68 @@ int orc_run(const orc_system *s, int32_t W, double *R, double *log_w, double *e_
   return rc;
 }
 
+/* ------------------------------------------------------- branching --- */
+/* Birth/death branching of the DMC population (the weights of Eq. 1 turned
+ * into walker counts; the paper leaves the control scheme open).  Walker j
+ * has weight w_j = exp(log_w_j) (a non-finite log w or a non-zero flag: 0)
+ * and M_j = floor(w_j + u_j) copies, u_j the first uniform of the Philox
+ * draw 5 of (electron 0, walker j, step) under the key.  The new population
+ * has W' = sum M_j walkers; its layout (the slot rule):
+ *   - a walker with M_j >= 1 keeps its slot;
+ *   - its M_j - 1 extra copies, walkers in order, fill the slots of the
+ *     walkers without a copy, lowest first, and then the slots W, W + 1, ...;
+ *   - when the extras do not fill every empty slot below W', the walkers in
+ *     slots >= W' move, in slot order, into the empty slots below W', lowest
+ *     first.
+ * Every destination is an empty or new slot and every source a surviving
+ * walker's own slot, so all copies read the population before the branch.
+ * pairs[2p] = destination, pairs[2p + 1] = source, p < *n_pairs (W' + W at
+ * most); copies[W] = M_j.  Returns 5 (nothing selected) when W' < 1 or
+ * W' > cap. */
+int orc_branch(int32_t W, const double *log_w, const uint8_t *flags, uint64_t seed, int64_t step,
+               int32_t cap, int32_t *copies, int32_t *pairs, int32_t *n_pairs, int32_t *w_new) {
+  double tot = 0.0;
+  for (int j = 0; j < W; ++j) {
+    double u[2];
+    draw_uniform2(seed, step, j, 0, 5u, u);
+    const int ok = isfinite(log_w[j]) && (!flags || flags[j] == 0);
+    const double m = ok ? floor(exp(log_w[j]) + u[0]) : 0.0;
+    tot += m;
+    copies[j] = m > (double)cap ? cap + 1 : (int32_t)m;
+  }
+  *n_pairs = 0;
+  *w_new = tot > (double)cap ? cap + 1 : (int32_t)tot;
+  if (tot < 1.0 || tot > (double)cap) return 5;
+  const int Wn = (int)tot;
+  int np = 0;
+  /* empty slots below W, in order; extras in walker order */
+  int *empty = (int *)malloc(sizeof(int) * (W > 0 ? W : 1));
+  int ne = 0;
+  for (int j = 0; j < W; ++j)
+    if (copies[j] == 0) empty[ne++] = j;
+  int fill = 0, next_new = W;
+  for (int j = 0; j < W; ++j)
+    for (int k = 1; k < copies[j]; ++k) {
+      const int dst = fill < ne ? empty[fill++] : next_new++;
+      pairs[2 * np] = dst;
+      pairs[2 * np + 1] = j;
+      ++np;
+    }
+  /* remaining empty slots below W': filled by the walkers in slots >= W' */
+  int mv = Wn; /* next slot >= W' to inspect */
+  for (int e = fill; e < ne && empty[e] < Wn; ++e) {
+    while (mv < W && copies[mv] == 0) ++mv;
+    pairs[2 * np] = empty[e];
+    pairs[2 * np + 1] = mv;
+    ++np;
+    ++mv;
+  }
+  free(empty);
+  *n_pairs = np;
+  *w_new = Wn;
+  return 0;
+}
+
 /* ---------------------------------------------------- E_T feedback --- */
 /* DMC steps with the trial energy of the projection (Eq. 1) fed back from
  * the population after every step (population control; the paper leaves E_T

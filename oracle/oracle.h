@@ -136,6 +136,12 @@ int orc_reconfigure(int32_t W, const double *log_w, double u, int32_t *copies, i
                     int32_t *n_pairs, double *log_wbar);
 
 
+/* Birth/death branching: copies[W] = floor(w_j + u_j), the new population's
+ * (destination, source) pairs and size W' (see oracle.c); 5 when W' < 1 or
+ * W' > cap (nothing selected). */
+int orc_branch(int32_t W, const double *log_w, const uint8_t *flags, uint64_t seed, int64_t step,
+               int32_t cap, int32_t *copies, int32_t *pairs, int32_t *n_pairs, int32_t *w_new);
+
 /* DMC steps with E_T fed back from the population after every step:
  * E_T <- <E_L>_w - (gain / tau) ln(sum_w exp(log w) / W) (see oracle.c). */
 int orc_run_feedback(const orc_system *s, int32_t W, double *R, double *log_w, double *e_local,
