@@ -72,8 +72,8 @@ def _load():
         lib.orc_run.argtypes = [P, C.c_int32, P, P, P, C.c_int64, C.c_int32, C.c_int32,
                                 C.c_double, C.c_uint64, C.c_double, C.c_int32, P, P, C.c_int32]
         lib.orc_run_feedback.argtypes = [P, C.c_int32, P, P, P, C.c_int64, C.c_int32, C.c_double,
-                                         C.c_uint64, C.c_double, C.c_double, C.c_int32, P, P, P,
-                                         P, C.c_int32]
+                                         C.c_uint64, C.c_double, C.c_double, C.c_int32,
+                                         C.c_int32, P, P, P, P, C.c_int32]
         lib.orc_ion_grads.argtypes = [P, P, P, P]
         lib.orc_ion_grads_batch.argtypes = [P, C.c_int32, P, P, P, C.c_int32]
         lib.orc_evaluate_batch.argtypes = [P, C.c_int32, P, P, P, P, C.c_int32]
@@ -245,9 +245,10 @@ def run(sys, R, log_w=None, step0=0, n_steps=1, mode=1, tau=0.01, seed=1, e_tria
 
 
 def run_feedback(sys, R, log_w=None, step0=0, n_steps=1, tau=0.01, seed=1, e_trial=0.0, gain=0.5,
-                 walker_offset=0, n_threads=0):
+                 walker_offset=0, n_threads=0, target=0):
     """DMC steps with E_T fed back from the population after every step (see
-    orc_run_feedback).  Returns dict(R, log_w, e_local, accept_log, e_log,
+    orc_run_feedback; target: the target population, 0 for the walker
+    count).  Returns dict(R, log_w, e_local, accept_log, e_log,
     et_log[n_steps] (the E_T each step used), e_trial (the next one))."""
     o = _osys(sys)
     R = np.array(R, dtype=np.float64, copy=True, order="C")
@@ -259,7 +260,8 @@ def run_feedback(sys, R, log_w=None, step0=0, n_steps=1, tau=0.01, seed=1, e_tri
     etlog = np.zeros(n_steps)
     et = C.c_double()
     rc = _load().orc_run_feedback(o.ref, W, _ptr(R), _ptr(lw), _ptr(el), step0, n_steps, tau,
-                                  seed, e_trial, gain, walker_offset, _ptr(acc), _ptr(elog),
+                                  seed, e_trial, gain, target, walker_offset, _ptr(acc),
+                                  _ptr(elog),
                                   _ptr(etlog), C.byref(et), n_threads)
     return dict(R=R, log_w=lw, e_local=el, accept_log=acc, e_log=elog, et_log=etlog,
                 e_trial=float(et.value), rc=rc)

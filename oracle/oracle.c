@@ -842,15 +842,17 @@ int orc_branch(int32_t W, const double *log_w, const uint8_t *flags, uint64_t se
 /* ---------------------------------------------------- E_T feedback --- */
 /* DMC steps with the trial energy of the projection (Eq. 1) fed back from
  * the population after every step (population control; the paper leaves E_T
- * open):  E_T <- <E_L>_w - (gain / tau) ln(W_tot / W),
+ * open):  E_T <- <E_L>_w - (gain / tau) ln(W_tot / W_T),
  * <E_L>_w = sum_w omega_w E_w / sum_w omega_w, W_tot = sum_w exp(log w_w),
  * omega_w = exp(log w_w - m), m the largest log w, over the walkers whose
  * log w and E_L are finite (E_T unchanged if there is none).  Each step is
  * one orc_run step of every walker; et_log[s] (may be NULL) receives the E_T
- * that step s used, *e_trial_out the one the next step would use. */
+ * that step s used, *e_trial_out the one the next step would use.  W_T is
+ * the target population: w_target, or W when w_target is 0 (a population
+ * that branching has moved away from its target feeds back through it). */
 int orc_run_feedback(const orc_system *s, int32_t W, double *R, double *log_w, double *e_local,
                      int64_t step0, int32_t n_steps, double tau, uint64_t seed, double e_trial,
-                     double gain, int32_t walker_offset, uint8_t *accept_log, double *e_log,
+                     double gain, int32_t w_target, int32_t walker_offset, uint8_t *accept_log, double *e_log,
                      double *et_log, double *e_trial_out, int32_t n_threads) {
   const int ne = s->n_up + s->n_dn;
   int rc = 0;
@@ -876,7 +878,7 @@ int orc_run_feedback(const orc_system *s, int32_t W, double *R, double *log_w, d
         s1 += om * e_local[w];
       }
     const double ln_wtot = m + log(s0);
-    et = s1 / s0 - gain / tau * (ln_wtot - log((double)W));
+    et = s1 / s0 - gain / tau * (ln_wtot - log((double)(w_target > 0 ? w_target : W)));
   }
   if (e_trial_out) *e_trial_out = et;
   return rc;

@@ -143,10 +143,11 @@ int orc_branch(int32_t W, const double *log_w, const uint8_t *flags, uint64_t se
                int32_t cap, int32_t *copies, int32_t *pairs, int32_t *n_pairs, int32_t *w_new);
 
 /* DMC steps with E_T fed back from the population after every step:
- * E_T <- <E_L>_w - (gain / tau) ln(sum_w exp(log w) / W) (see oracle.c). */
+ * E_T <- <E_L>_w - (gain / tau) ln(sum_w exp(log w) / W_T), W_T = w_target
+ * or, when it is 0, W (see oracle.c). */
 int orc_run_feedback(const orc_system *s, int32_t W, double *R, double *log_w, double *e_local,
                      int64_t step0, int32_t n_steps, double tau, uint64_t seed, double e_trial,
-                     double gain, int32_t walker_offset, uint8_t *accept_log, double *e_log,
+                     double gain, int32_t w_target, int32_t walker_offset, uint8_t *accept_log, double *e_log,
                      double *et_log, double *e_trial_out, int32_t n_threads);
 
 /* Derivatives of ln Psi and E_L with respect to the 8 Jastrow parameters

@@ -421,13 +421,15 @@ def test_msd_direct_reference_and_single_excitation():
     assert abs(oracle.msd_ratio_direct(s2, R) - (1.0 + 0.3 * ratio)) < 1e-11
 
 
-@pytest.mark.parametrize("gain", [0.3, 1.0])
-def test_et_feedback_zero_variance_closed_form(gain):
+@pytest.mark.parametrize("gain,target", [(0.3, 0), (1.0, 0), (0.3, 12), (0.6, 4)])
+def test_et_feedback_zero_variance_closed_form(gain, target):
     """E_T feedback on the exact hydrogen-like wavefunction, where E_L = -Z^2/2
     at every point: every walker's log-weight changes by -tau (E - E_T) per
-    step, W_tot = W exp(log w), so the feedback E_T = E - (gain / tau) log w
-    gives, from log w = 0 and E_T = E + delta, log w after step s (s >= 1)
-    equal to tau delta (1 - gain)^(s - 1) for every walker."""
+    step, W_tot = W exp(log w), so the feedback E_T = E - (gain / tau)
+    (log w + c), c = ln(W / W_T) for the target population W_T (c = 0 for the
+    default W_T = W), gives, from log w = 0 and E_T = E + delta, log w after
+    step s (s >= 1) equal to -c + (tau delta + c) (1 - gain)^(s - 1) for
+    every walker."""
     Z = 1.6
     s = _one_electron_system(0, 0, 0.0, Z=Z, jen_a=-Z, jen_b=0.0)
     W, n, tau, delta = 6, 7, 0.02, 0.4
@@ -436,11 +438,12 @@ def test_et_feedback_zero_variance_closed_form(gain):
     lw = np.zeros(W)
     for k in range(1, n + 1):
         out = oracle.run_feedback(s, R, log_w=np.zeros(W), n_steps=k, tau=tau, seed=5,
-                                  e_trial=E + delta, gain=gain)
+                                  e_trial=E + delta, gain=gain, target=target)
         assert out["rc"] == 0
         np.testing.assert_allclose(out["e_local"], E, rtol=0, atol=1e-12)
-        np.testing.assert_allclose(out["log_w"], tau * delta * (1 - gain) ** (k - 1),
-                                   rtol=1e-12, atol=1e-15)
+        c = math.log(W / target) if target else 0.0
+        np.testing.assert_allclose(out["log_w"], -c + (tau * delta + c) * (1 - gain) ** (k - 1),
+                                   rtol=1e-11, atol=1e-14)
     np.testing.assert_allclose(out["et_log"][0], E + delta, rtol=0, atol=0)
 
 
