@@ -449,12 +449,34 @@ def population_leg(s, torch, dmcx, stream, W=2048, steps=10, sigma=0.5):
     ne = s.n_elec
     state = ne * 3 * 8 + ne * 5 * NP * 8 + 2 * NP * NP * 8 + 8 * 8
     gbs = 2.0 * state * replaced / (ms * 1e-3) / 1e9
+    ctx.close()
+    # birth/death branching of the same walkers in a context of twice the
+    # capacity: the call includes the host read of the new count (the
+    # launches after it are sized by it), so it is timed on the host clock
+    bctx = dmcx.Context(s, 2 * W, delay_rank=32, recompute_period=64, tau=0.01, seed=29,
+                        stream=stream)
+    bms, wnew = [], []
+    for i in range(steps + 1):
+        bctx.set_walker_count(W)
+        bctx.set_walkers(R1, torch.from_numpy(rng.normal(0.0, sigma, W)).cuda())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, wn = bctx.branch(100 + i)
+        bctx.sync()
+        t1 = time.perf_counter()
+        if i > 0:
+            bms.append((t1 - t0) * 1e3)
+            wnew.append(wn)
+    bctx.close()
     return {"walkers": W, "calls": steps, "log_w_sigma": sigma,
             "reconfigure_ms_avg": float(ms.mean()),
             "walkers_replaced_avg": float(replaced.mean()),
             "state_bytes_per_walker": state,
             "copy_GB_per_s_avg": float(gbs.mean()),
-            "hbm_fraction": float(gbs.mean() / 8000.0)}
+            "hbm_fraction": float(gbs.mean() / 8000.0),
+            "branch_capacity": 2 * W,
+            "branch_ms_avg": float(np.mean(bms)),
+            "branch_walkers_after_avg": float(np.mean(wnew))}
 
 
 def main():

@@ -396,7 +396,8 @@ dmcx_status dmcx_energy_escalations(dmcx_ctx *ctx, int32_t *n);
  * E_T feedback for the DMC steps of later dmcx_run calls: after every step
  * each system's E_T becomes <E_L>_w - (gain / tau) ln(W_tot / W), with
  * <E_L>_w the weighted mean local energy, W_tot = sum_w exp(log w_w) over the
- * walkers counted by dmcx_estimators and W the walker count (FP64,
+ * walkers counted by dmcx_estimators and W the system's walker count when
+ * this call was made (the target population once dmcx_branch varies it; FP64,
  * log-sum-exp; unchanged when no walker counts).  dmcx_run's e_trial is the
  * E_T of the first step.  gain < 0 switches it off (E_T held fixed, the
  * default).  Errors: DMCX_E_INVALID (non-finite gain). */
@@ -466,6 +467,46 @@ dmcx_status dmcx_walker_flags(dmcx_ctx *ctx, uint8_t *flags, dmcx_mem mem);
  * move-by-move calls pending). */
 dmcx_status dmcx_reconfigure(dmcx_ctx *ctx, const double *u, int32_t *copies, double *log_wbar,
                              dmcx_mem mem);
+
+/* Passage: QMC section, Eq. 1 (walker weights of the projection).
+ * Birth/death branching of a one-system context: the weights become walker
+ * counts, so the population size varies (the paper does not fix the control
+ * scheme; this is the published integer branching with a uniform offset).
+ * Walker j of W gets M_j = floor(w_j + u_j) copies, w_j = exp(log_w_j) (0
+ * for a non-finite log_w or a flagged walker), u_j the first uniform of the
+ * Philox block of counter (electron 0, walker j, step, draw 5) under the
+ * context's seed; so E[M_j] = w_j.  The new population has W' = sum M_j
+ * walkers, each with log_w = 0, laid out as follows:
+ *   - a walker with a copy keeps its slot;
+ *   - its extra copies, walkers in order, fill the slots of the walkers
+ *     without a copy, lowest first, and then the slots W, W + 1, ...;
+ *   - walkers left in slots >= W' move into the empty slots below W', both
+ *     in slot order.
+ * A copy takes every state the walker carries between steps (as in
+ * dmcx_reconfigure).  step: the Philox step counter of the draws (the
+ * caller's choice, e.g. the step after the last one run).
+ * copies: [W] int32 (the count before the call), or NULL; mem applies to it.
+ * n_walkers: W' (host), or NULL; read also on DMCX_E_INVALID, where it holds
+ * 0 (nothing survives) or the capacity + 1 (too many).  Walker counts of
+ * later calls (dmcx_run, dmcx_get_walkers, the estimators, ...) are W'.
+ * Synchronises the context's stream (the new count sizes later launches).
+ * Errors: DMCX_E_INVALID (W' < 1 or W' > capacity: nothing changed),
+ * DMCX_E_STATE (walkers not set, electron block pending),
+ * DMCX_E_UNSUPPORTED (a context of several systems). */
+dmcx_status dmcx_branch(dmcx_ctx *ctx, int64_t step, int32_t *copies, int32_t *n_walkers,
+                        dmcx_mem mem);
+
+/* Passage: QMC section, Eq. 1 (the walker population).
+ * Sets the walker count of a one-system context to n_walkers, 1 ..
+ * capacity (the n_walkers it was created with, which sizes its buffers);
+ * dmcx_set_walkers must follow (the walkers are unset).  Errors:
+ * DMCX_E_INVALID (count out of range), DMCX_E_STATE (electron block
+ * pending), DMCX_E_UNSUPPORTED (a context of several systems). */
+dmcx_status dmcx_set_walker_count(dmcx_ctx *ctx, int32_t n_walkers);
+
+/* Current walker count and capacity (host, either may be NULL); for a
+ * context of several systems both are the total over its systems. */
+dmcx_status dmcx_walker_count(const dmcx_ctx *ctx, int32_t *n_walkers, int32_t *capacity);
 
 /* Wait for all work queued on the context's stream. */
 dmcx_status dmcx_sync(dmcx_ctx *ctx);

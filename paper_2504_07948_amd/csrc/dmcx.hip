@@ -50,10 +50,14 @@ struct DeviceBuffers {
 struct dmcx_ctx {
   hipStream_t stream = nullptr;
   dmcx_options opt{};
+  // W: the walkers of the population (branching changes it, up to Wcap, the
+  // count the context was created for, which sizes every per-walker buffer)
+  int Wcap = 0;
   int W = 0, Wpad = 0, ne = 0, n_up = 0, n_dn = 0, n_atom = 0, NP = 0, NOB = 0, K = 1, P = 1;
   int n_basis = 0;
   bool mixed = false;  // FP32 working precision (mixed path)
   double fb_gain = -1.0;  // E_T feedback gain after every DMC step (< 0: E_T held fixed)
+  int fb_W = 0;           // the feedback's target population (W when it was switched on)
   // mixed form with its energy in FP64: every step ends with FP64 value rows,
   // an FP64 inverse and E_L from that inverse (single-determinant systems)
   bool fp64e = false;
@@ -600,7 +604,7 @@ dmcx_status launch_et_feedback(dmcx_ctx *c) {
   hipLaunchKernelGGL(k_est_partial<unsigned>, dim3(nblk), dim3(EST_NB), 0, c->stream, in,
                      c->d_est_part);
   hipLaunchKernelGGL(k_et_feedback, dim3(1), dim3(64), 0, c->stream, nblk, c->d_est_part,
-                     c->d_run, c->fb_gain, c->opt.tau, c->W);
+                     c->d_run, c->fb_gain, c->opt.tau, c->fb_W);
   return hip_check(c, hipGetLastError(), "E_T feedback launch");
 }
 
@@ -763,8 +767,16 @@ dmcx_status compute_ion_grads(dmcx_ctx *c) {
                      c->d_partial, c->d_dl, c->d_dv);
   HIP_TRY(c, hipGetLastError());
   if (c->dc.pp_n > 0) {
-    // the pseudopotential's Hellmann-Feynman term, with the inverse-column
-    // products y_e of the last energy evaluation (the current configuration)
+    // the pseudopotential's Hellmann-Feynman term; y_e from the current
+    // inverses (a reconfiguration copies walkers after the last energy
+    // evaluation; the working-precision inverse is part of what it copies)
+    if (c->dc.pp_nl > 0) {
+      if (!c->mixed)
+        launch_pp_y(c->NOB, c->dc, (const double *)c->dc.GT, c->d_ppY, c->pp_ldy, c->stream);
+      else
+        launch_pp_y(c->NOB, c->dc, (const float *)c->dc.GT, c->d_ppY, c->pp_ldy, c->stream);
+      HIP_TRY(c, hipGetLastError());
+    }
     hipLaunchKernelGGL(k_pp_grad, dim3(c->W), dim3(NT_AUX), pp_grad_lds_bytes(c->ne, c->dc.pp_nl),
                        c->stream, c->dc, (const double *)c->d_ppY, c->pp_ldy, c->d_dv);
     HIP_TRY(c, hipGetLastError());
@@ -826,8 +838,8 @@ dmcx_status compute_jparams(dmcx_ctx *c) {
   dmcx_status st = refresh_after_moves(c);
   if (st) return st;
   if (c->jp_version == c->version) return DMCX_OK;
-  if (!c->d_jo && ((st = dalloc(c, &c->d_jo, (size_t)c->W * NJP)) ||
-                   (st = dalloc(c, &c->d_jd, (size_t)c->W * NJP))))
+  if (!c->d_jo && ((st = dalloc(c, &c->d_jo, (size_t)c->Wcap * NJP)) ||
+                   (st = dalloc(c, &c->d_jd, (size_t)c->Wcap * NJP))))
     return st;
   const size_t lds = jparam_lds(c->ne);
   const int nch = jparam_chunk(c->ne);
@@ -1006,7 +1018,7 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
     c->err = "need at least one walker";
     return bail(DMCX_E_INVALID);
   }
-  c->W = n_walkers;
+  c->W = c->Wcap = n_walkers;
   c->Wpad = (c->W + TW - 1) / TW * TW;
   c->n_up = s.n_up;
   c->n_dn = s.n_dn;
@@ -1157,7 +1169,7 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
         return bail(DMCX_E_UNSUPPORTED);
       }
       c->pp_ldy = (c->dc.B.Kp + 63) / 64 * 64;
-      if ((st = dalloc(c, &c->d_ppY, (size_t)c->W * c->ne * c->pp_ldy))) return bail(st);
+      if ((st = dalloc(c, &c->d_ppY, (size_t)c->Wcap * c->ne * c->pp_ldy))) return bail(st);
       if (pp_grad_lds_bytes(c->ne, d.pp_nl) + 8 * 1024 > 64 * 1024) {
         c->err = "pseudopotential: pair list exceeds 64 KB of LDS";
         return bail(DMCX_E_UNSUPPORTED);
@@ -1204,15 +1216,17 @@ dmcx_status create_one(const dmcx_system &s, int32_t n_walkers, const dmcx_optio
   }
   if ((st = dalloc(c, &d.nacc, Wp))) return bail(st);
   if ((st = dalloc(c, &d.nprop, Wp))) return bail(st);
-  if ((st = dalloc(c, &c->d_est_part, (size_t)est_blocks(c->W) * EST_PART))) return bail(st);
+  if ((st = dalloc(c, &c->d_est_part, (size_t)est_blocks(c->Wcap) * EST_PART))) return bail(st);
   if ((st = dalloc(c, &c->d_est_out, EST_OUT))) return bail(st);
   if ((st = dalloc(c, &c->pop.w, Wp))) return bail(st);
   if ((st = dalloc(c, &c->pop.copies, Wp))) return bail(st);
   if ((st = dalloc(c, &c->pop.dead, Wp))) return bail(st);
   if ((st = dalloc(c, &c->pop.ex, Wp))) return bail(st);
   if ((st = dalloc(c, &c->pop.pairs, Wp))) return bail(st);
-  if ((st = dalloc(c, &c->pop.n_pairs, 1))) return bail(st);
+  if ((st = dalloc(c, &c->pop.n_pairs, 2))) return bail(st);
   if ((st = dalloc(c, &c->pop.lwbar, 1))) return bail(st);
+  if ((st = dalloc(c, &c->pop.alive, Wp))) return bail(st);
+  if ((st = dalloc(c, &c->pop.info, 4))) return bail(st);
   if ((st = dalloc(c, &c->d_pos, Wp * 3))) return bail(st);
   if ((st = dalloc(c, &c->d_orb, Wp * 5 * c->NP))) return bail(st);
   if ((st = dalloc(c, &c->d_orb_out, Wp * 5 * c->NP))) return bail(st);
@@ -2342,9 +2356,10 @@ dmcx_status dmcx_linear_method(dmcx_ctx *c, double *S, double *H, dmcx_mem mem) 
   }
   if ((st = compute_jparams(c))) return st;
   const int nblk = lm_blocks(c->W);
-  // [2][9][9] result, the merged means (LM_Z + 1), the block records
+  // [2][9][9] result, the merged means (LM_Z + 1), the block records (as
+  // many as the largest population needs)
   if (!c->d_lm &&
-      (st = dalloc(c, &c->d_lm, 2 * NM + (LM_Z + 1) + (size_t)nblk * LM_REC)))
+      (st = dalloc(c, &c->d_lm, 2 * NM + (LM_Z + 1) + (size_t)lm_blocks(c->Wcap) * LM_REC)))
     return st;
   double *mm = c->d_lm + 2 * NM, *part = mm + LM_Z + 1;
   const DevCtx &d = c->dc;
@@ -2363,9 +2378,10 @@ dmcx_status dmcx_set_et_feedback(dmcx_ctx *c, double gain) {
   if (!c || !std::isfinite(gain)) return DMCX_E_INVALID;
   const double g = gain < 0.0 ? -1.0 : gain;
   if (c->is_group()) {
-    for (dmcx_ctx *m : c->subs) m->fb_gain = g, m->dc_version++;
+    for (dmcx_ctx *m : c->subs) m->fb_gain = g, m->fb_W = m->W, m->dc_version++;
   } else {
     c->fb_gain = g;
+    c->fb_W = c->W;
   }
   c->dc_version++;  // the captured step changes
   return DMCX_OK;
@@ -2547,6 +2563,61 @@ dmcx_status dmcx_reconfigure(dmcx_ctx *c, const double *u, int32_t *copies, doub
   c->version++;
   if (mem == DMCX_HOST && (copies || log_wbar))
     for (dmcx_ctx *m : ms) HIP_TRY(c, hipStreamSynchronize(m->stream));
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_branch(dmcx_ctx *c, int64_t step, int32_t *copies, int32_t *n_walkers,
+                        dmcx_mem mem) {
+  if (!c) return DMCX_E_INVALID;
+  if (c->is_group())
+    return fail(c, DMCX_E_UNSUPPORTED, "branching: one system per context (the batch of "
+                                       "systems keeps fixed populations)");
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  if (c->blk_active) return fail(c, DMCX_E_STATE, "an electron block is pending (dmcx_flush)");
+  const int W = c->W;
+  HIP_TRY(c, launch_branch_select(c->dc, (uint64_t)step, c->Wcap, TW, c->pop, c->stream));
+  if (copies)
+    HIP_TRY(c, hipMemcpyAsync(copies, c->pop.copies, (size_t)W * sizeof(int32_t),
+                              mem == DMCX_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                              c->stream));
+  int info[4];
+  HIP_TRY(c, hipMemcpyAsync(info, c->pop.info, sizeof(info), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (n_walkers) *n_walkers = info[1];
+  if (info[0] != 0)
+    return fail(c, DMCX_E_INVALID, info[1] < 1 ? "branching: no walker would survive"
+                                               : "branching: the population would exceed the capacity");
+  c->W = info[1];
+  c->Wpad = (c->W + TW - 1) / TW * TW;
+  c->dc.W = c->W;
+  c->dc.Wpad = c->Wpad;
+  c->dc_version++;  // launch sizes and captured steps change
+  HIP_TRY(c, launch_branch_copy(c->dc, c->es, info[2], info[3], c->pop, c->stream));
+  c->version++;
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_set_walker_count(dmcx_ctx *c, int32_t n_walkers) {
+  if (!c) return DMCX_E_INVALID;
+  if (c->is_group())
+    return fail(c, DMCX_E_UNSUPPORTED, "walker count: one system per context");
+  if (c->blk_active) return fail(c, DMCX_E_STATE, "an electron block is pending (dmcx_flush)");
+  if (n_walkers < 1 || n_walkers > c->Wcap)
+    return fail(c, DMCX_E_INVALID, "walker count outside 1..capacity");
+  c->W = n_walkers;
+  c->Wpad = (c->W + TW - 1) / TW * TW;
+  c->dc.W = c->W;
+  c->dc.Wpad = c->Wpad;
+  c->dc_version++;
+  c->walkers_set = false;
+  c->version++;
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_walker_count(const dmcx_ctx *c, int32_t *n_walkers, int32_t *capacity) {
+  if (!c) return DMCX_E_INVALID;
+  if (n_walkers) *n_walkers = c->W;
+  if (capacity) *capacity = c->is_group() ? c->W : c->Wcap;
   return DMCX_OK;
 }
 

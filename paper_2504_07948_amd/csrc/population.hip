@@ -9,6 +9,11 @@
 // copy receive the extra copies, lowest slot first, sources in walker order
 // (integer scans, exact in any order), and every walker then carries the
 // mean weight S / W (times e^m).
+//
+// Birth/death branching (the second half of this file) turns the weights
+// into integer multiplicities M_j = floor(w_j + u_j), so the walker count
+// changes; the host reads the new count between the selection and the
+// copies (the launches after it size their grids by it).
 #include "population.h"
 
 namespace dmcx {
@@ -225,7 +230,127 @@ __global__ void k_pop_finish(DevCtx c, PopScratch p) {
   if (j < c.W && isfinite(lw)) c.logw[j] = lw;
 }
 
+// Branching selection (one workgroup; see launch_branch_select).
+__global__ __launch_bounds__(NT_SEL) void k_branch_select(DevCtx c, uint64_t step, int cap, int tw,
+                                                          PopScratch p) {
+  __shared__ int sh[NT_SEL / 64];
+  __shared__ double red[NT_SEL / 64];
+  __shared__ int s_carry[3];
+  const int W = c.W, t = threadIdx.x;
+  // multiplicities (clamped at cap + 1: any larger total is refused anyway);
+  // their total as a double is exact while below 2^53 and above cap beyond
+  double tot = 0.0;
+  for (int j = t; j < W; j += NT_SEL) {
+    double u0, u1;
+    uniform_pair(c.seed, (uint32_t)step, (uint32_t)j, 0u, 5u, u0, u1);
+    const double x = c.logw[j];
+    const double m = (isfinite(x) && c.flags[j] == 0u) ? floor(exp(x) + u0) : 0.0;
+    const int mj = m > (double)cap ? cap + 1 : (int)m;
+    p.copies[j] = mj;
+    tot += (double)mj;
+  }
+  for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
+  if ((t & 63) == 0) red[t >> 6] = tot;
+  if (t < 3) s_carry[t] = 0;
+  __syncthreads();
+  tot = 0.0;
+  for (int i = 0; i < NT_SEL / 64; ++i) tot += red[i];
+  if (tot < 1.0 || tot > (double)cap) {
+    if (t == 0) {
+      p.info[0] = 5;
+      p.info[1] = tot > (double)cap ? cap + 1 : (int)tot;
+      p.info[2] = 0;
+      p.info[3] = 0;
+    }
+    return;
+  }
+  const int Wn = (int)tot;
+  // dead slots in order, the inclusive prefixes of the extra copies and of
+  // the walkers with a copy (all counts <= cap now)
+  for (int j0 = 0; j0 < W; j0 += NT_SEL) {
+    const int j = j0 + t;
+    const int cj = j < W ? p.copies[j] : 1;
+    const int d = cj == 0 ? 1 : 0;
+    const int e = cj > 1 ? cj - 1 : 0;
+    const int a = (j < W && cj > 0) ? 1 : 0;
+    const int di = block_scan_incl(d, sh);
+    const int ei = block_scan_incl(e, sh);
+    const int ai = block_scan_incl(a, sh);
+    if (d && j < W) p.dead[s_carry[0] + di - 1] = j;
+    if (j < W) {
+      p.ex[j] = s_carry[1] + ei;
+      p.alive[j] = s_carry[2] + ai;
+    }
+    __syncthreads();
+    if (t == NT_SEL - 1) {
+      s_carry[0] += di;
+      s_carry[1] += ei;
+      s_carry[2] += ai;
+    }
+    __syncthreads();
+  }
+  const int nd = s_carry[0], E = s_carry[1];
+  // extra copy r (walkers in order): the r-th dead slot, then the new slots
+  for (int r = t; r < E; r += NT_SEL) {
+    int lo = 0, hi = W - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (p.ex[mid] > r) hi = mid; else lo = mid + 1;
+    }
+    p.pairs[r] = make_int2(r < nd ? p.dead[r] : W + (r - nd), lo);
+  }
+  // walkers in slots >= W' (in order) -> the dead slots after the extras'
+  // (these lie below W': as many empty slots below W' remain as there are
+  // walkers with a copy at or above W')
+  const int base = Wn < W ? p.alive[Wn - 1] : 0;
+  for (int j = Wn + t; j < W; j += NT_SEL)
+    if (p.copies[j] > 0) {
+      const int k = p.alive[j] - base - 1;
+      p.pairs[E + k] = make_int2(p.dead[E + k], j);
+    }
+  const int nmove = Wn < W ? p.alive[W - 1] - base : 0;
+  const int np = E + nmove;
+  const int Wnp = (Wn + tw - 1) / tw * tw;
+  for (int i = t; i < Wnp - Wn; i += NT_SEL) p.pairs[np + i] = make_int2(Wn + i, 0);
+  if (t == 0) {
+    p.n_pairs[0] = np;
+    p.n_pairs[1] = Wnp - Wn;
+    p.info[0] = 0;
+    p.info[1] = Wn;
+    p.info[2] = np;
+    p.info[3] = Wnp - Wn;
+  }
+}
+
+__global__ void k_branch_finish(DevCtx c) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < c.Wpad) c.logw[j] = 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_branch_select(const DevCtx &c, uint64_t step, int cap, int tw,
+                                const PopScratch &p, hipStream_t s) {
+  hipLaunchKernelGGL(k_branch_select, dim3(1), dim3(NT_SEL), 0, s, c, step, cap, tw, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_branch_copy(const DevCtx &c, size_t es, int n_main, int n_pad,
+                              const PopScratch &p, hipStream_t s) {
+  // every destination is an empty slot and every source a surviving walker's
+  // own slot, so the main copies are independent; the padding copies read
+  // slot 0 after them
+  if (n_main > 0)
+    hipLaunchKernelGGL(k_pop_copy, dim3(n_main, COPY_SPLIT), dim3(NT_COPY), 0, s, c, es, p);
+  if (n_pad > 0) {
+    PopScratch q = p;
+    q.pairs = p.pairs + n_main;
+    q.n_pairs = p.n_pairs + 1;
+    hipLaunchKernelGGL(k_pop_copy, dim3(n_pad, COPY_SPLIT), dim3(NT_COPY), 0, s, c, es, q);
+  }
+  hipLaunchKernelGGL(k_branch_finish, dim3((c.Wpad + 255) / 256), dim3(256), 0, s, c);
+  return hipGetLastError();
+}
 
 hipError_t launch_reconfigure(const DevCtx &c, size_t es, double u, const PopScratch &p,
                               hipStream_t s) {

@@ -39,7 +39,7 @@ EXPORTED = [
     "dmcx_zv_grads", "dmcx_forces_zv", "dmcx_estimators_noalloc",
     "dmcx_energy_escalations", "dmcx_set_et_feedback", "dmcx_get_trial_energy",
     "dmcx_jastrow_param_grads", "dmcx_linear_method", "dmcx_set_tile_shape",
-    "dmcx_get_tile_shape",
+    "dmcx_get_tile_shape", "dmcx_branch", "dmcx_set_walker_count", "dmcx_walker_count",
 ]
 
 
@@ -108,6 +108,9 @@ def load():
         "dmcx_potential": [P, P, I32],
         "dmcx_walker_flags": [P, P, I32],
         "dmcx_reconfigure": [P, P, P, P, I32],
+        "dmcx_branch": [P, I64, P, P, I32],
+        "dmcx_set_walker_count": [P, I32],
+        "dmcx_walker_count": [P, P, P],
         "dmcx_sync": [P],
         "dmcx_last_run_timing": [P, P, P, P],
         "dmcx_selftest": [P],
@@ -281,6 +284,18 @@ def dmcx_walker_flags(ctx, flags, mem):
 
 def dmcx_reconfigure(ctx, u, copies, log_wbar, mem):
     return load().dmcx_reconfigure(ctx, u, copies, log_wbar, mem)
+
+
+def dmcx_branch(ctx, step, copies, n_walkers, mem):
+    return load().dmcx_branch(ctx, step, copies, n_walkers, mem)
+
+
+def dmcx_set_walker_count(ctx, n):
+    return load().dmcx_set_walker_count(ctx, n)
+
+
+def dmcx_walker_count(ctx, n, cap):
+    return load().dmcx_walker_count(ctx, n, cap)
 
 
 def dmcx_sync(ctx):
@@ -569,6 +584,33 @@ class Context:
         lwbar = np.zeros(self.n_sys)
         self.check(dmcx_reconfigure(self.h, _ptr(uu), _ptr(copies), _ptr(lwbar), DMCX_HOST))
         return copies, lwbar
+
+    def branch(self, step):
+        """Birth/death branching (one system): M_j = floor(w_j + u_j) copies
+        of walker j.  Returns (copies[W before], W after).  Raises DmcxError
+        when nothing would survive or the capacity would be exceeded (the
+        population is then unchanged)."""
+        copies = np.zeros(self.W, dtype=np.int32)
+        n = C.c_int32(0)
+        st = dmcx_branch(self.h, int(step), _ptr(copies), C.byref(n), DMCX_HOST)
+        self.check(st)
+        self._set_w(int(n.value))
+        return copies, self.W
+
+    def set_walker_count(self, n):
+        """Set the walker count (1 .. capacity) of a one-system context;
+        set_walkers must follow."""
+        self.check(dmcx_set_walker_count(self.h, int(n)))
+        self._set_w(int(n))
+
+    def walker_count(self):
+        n, cap = C.c_int32(0), C.c_int32(0)
+        self.check(dmcx_walker_count(self.h, C.byref(n), C.byref(cap)))
+        return int(n.value), int(cap.value)
+
+    def _set_w(self, n):
+        self.W = n
+        self.walkers = [n]
 
     def sync(self):
         self.check(dmcx_sync(self.h))

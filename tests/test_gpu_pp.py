@@ -206,6 +206,34 @@ def test_ion_grads_and_forces_with_pseudopotential():
     _close(dv, _oracle_dv(s, Rg, seed, 2), label="dV/dR with pseudopotential (after steps)")
 
 
+def test_ion_grads_after_population_control():
+    """The pseudopotential's force term after walkers were copied: comb
+    reconfiguration and branching replace slots' inverses after the last
+    energy evaluation, and dV/dR of every slot must follow its new walker
+    (rotations of the slot's own index and the current step)."""
+    s = synth.small_molecule_pp()
+    cap, W, seed = 40, 16, 29
+    ctx = dmcx.Context(s, cap, seed=seed, delay_rank=2, recompute_period=3)
+    ctx.set_walker_count(W)
+    ctx.set_walkers(synth.make_walkers(s, W, 3309))
+    ctx.run(2, mode=dmcx.DMCX_DMC, e_trial=-10.0)
+    R1, lw1 = ctx.get_walkers()
+    ctx.set_walkers(R1, np.random.default_rng(4).normal(0.0, 1.0, W))
+    ctx.set_step(2)
+    copies, _ = ctx.reconfigure(0.37)
+    assert (copies != 1).any()
+    Rg, _ = ctx.get_walkers()
+    _, dv = ctx.ion_grads()
+    _close(dv, _oracle_dv(s, Rg, seed, 2), label="dV/dR after reconfiguration")
+    ctx.set_walkers(Rg, 0.4 + np.random.default_rng(5).normal(0.0, 0.5, W))
+    ctx.set_step(2)
+    _, wn = ctx.branch(2)
+    assert wn > W
+    Rb, _ = ctx.get_walkers()
+    _, dv = ctx.ion_grads()
+    _close(dv, _oracle_dv(s, Rb, seed, 2), label="dV/dR after branching")
+
+
 def test_ion_grads_large_molecule_sampled():
     s = synth.large_molecule_pp()
     W, seed = 32, 28
