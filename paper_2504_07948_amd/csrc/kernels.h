@@ -1200,14 +1200,18 @@ __device__ __forceinline__ typename Acc4<T>::type mfma_tile(int K, FA fa, FB fb)
 // column over its ratio) and Delta_l = Dl[l] (its orbital-row change, zero
 // when rejected).  Expanding G_{l-1} gives z_l = Z_l - sum_{p<l} C[l][p] z_p
 // with Z = Delta G0 and C[l][p] = Delta_l . u_p, so z = M Z with
-// M = (I + L)^{-1} (L the strictly lower part of C), which the sweep builds
-// row by row.  Here: Z = Delta G0, Z' = M Z and G = G0 - Z'^T U, three
-// MFMA GEMMs per walker.  Each GEMM runs over the tiles of all the tile's
-// walkers at once (one barrier per GEMM); operands outside the block are
-// read from a clamped row and zeroed by a select, so the K loop's loads
-// carry no branches and can be issued ahead of their MFMAs.
+// M = (I + L)^{-1} (L the strictly lower part of C).  Here: C = Dl Gb^T and
+// Z = Delta G0 (MFMA GEMMs), M by forward substitution (one wave per
+// walker), then Z' = M Z and G = G0 - Z'^T U (MFMA GEMMs).  A rejected move
+// p leaves Gb[p] unscaled, but its C[l][p] meets only zeros: row p of M is
+// e_p (Delta_p = 0) and column p of M multiplies Z[p] = 0.  Each GEMM runs
+// over the tiles of all the tile's walkers at once (one barrier per phase);
+// operands outside the block are read from a clamped row and zeroed by a
+// select, so the K loop's loads carry no branches and can be issued ahead
+// of their MFMAs.  mscr: TW K x K scratch for C and M (the sweep passes its
+// free basis-tile LDS when it is large enough), or null for the global Ms.
 template <typename T, int NOB>
-__device__ void flush_block(const DevCtx &c, int w0, int sp, int kb) {
+__device__ void flush_block(const DevCtx &c, int w0, int sp, int kb, T *mscr) {
   constexpr int NP = NOB * 16;
   const int tid = threadIdx.x, wid = wave_id();
   const int lane = tid & 63, kq = lane >> 4, cl = lane & 15;
@@ -1215,31 +1219,87 @@ __device__ void flush_block(const DevCtx &c, int w0, int sp, int kb) {
   const int KBP = (kb + 15) & ~15;
   const int nlt = KBP / 16;
   const int kl = kb - 1;  // last row of the block
-  const int nz = nlt * NOB;
-  __syncthreads();  // Dl, Gb, Ms of every walker complete
-  // Z[l][b] = sum_j Dl[l][j] GT[b][j]
-  for (int tt = wid; tt < TW * nz; tt += NW_TILE) {
-    const int w = w0 + tt / nz, r = tt % nz;
-    const int l0 = (r / NOB) * 16, b0 = (r % NOB) * 16;
+  const int nz = nlt * NOB, nzc = nz + nlt * nlt;
+  T *Mbase = mscr ? mscr : (T *)c.Ms + (size_t)w0 * K * K;
+  __syncthreads();  // Dl and Gb of every walker complete
+  // Z[l][b] = sum_j Dl[l][j] GT[b][j]; C[l][p] = sum_j Dl[l][j] Gb[p][j]
+  // (tiles on or below the diagonal)
+  for (int tt = wid; tt < TW * nzc; tt += NW_TILE) {
+    const int w = w0 + tt / nzc, r = tt % nzc;
     const T *Dl = (const T *)c.Dl + blk_off(c, w);
-    const T *GT = (const T *)c.GT + gt_off(c, w, sp);
-    T *Zs = (T *)c.Zs + (size_t)w * c.K16 * NP;
-    const auto z = mfma_tile<T>(
-        NP,
-        [&](int i, int k) {
-          const T v = Dl[min(l0 + i, kl) * NP + k];
-          return (l0 + i < kb) ? v : (T)0;
-        },
-        [&](int k, int j) { return GT[(size_t)(b0 + j) * NP + k]; });
+    if (r < nz) {
+      const int l0 = (r / NOB) * 16, b0 = (r % NOB) * 16;
+      const T *GT = (const T *)c.GT + gt_off(c, w, sp);
+      T *Zs = (T *)c.Zs + (size_t)w * c.K16 * NP;
+      const auto z = mfma_tile<T>(
+          NP,
+          [&](int i, int k) {
+            const T v = Dl[min(l0 + i, kl) * NP + k];
+            return (l0 + i < kb) ? v : (T)0;
+          },
+          [&](int k, int j) { return GT[(size_t)(b0 + j) * NP + k]; });
 #pragma unroll
-    for (int q = 0; q < 4; ++q) Zs[(l0 + Acc4<T>::row(kq, q)) * NP + b0 + cl] = z[q];
+      for (int q = 0; q < 4; ++q) Zs[(l0 + Acc4<T>::row(kq, q)) * NP + b0 + cl] = z[q];
+    } else {
+      const int l0 = ((r - nz) / nlt) * 16, p0 = ((r - nz) % nlt) * 16;
+      if (p0 > l0) continue;  // wave-uniform: no barrier inside the loop
+      const T *Gb = (const T *)c.Gb + blk_off(c, w);
+      T *Mw = Mbase + (size_t)(w - w0) * K * K;
+      const auto z = mfma_tile<T>(
+          NP,
+          [&](int i, int k) {
+            const T v = Dl[min(l0 + i, kl) * NP + k];
+            return (l0 + i < kb) ? v : (T)0;
+          },
+          [&](int k, int j) {
+            const T v = Gb[min(p0 + j, kl) * NP + k];
+            return (p0 + j < kb) ? v : (T)0;
+          });
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int l = l0 + Acc4<T>::row(kq, q), p = p0 + cl;
+        if (l < kb && p < kb) Mw[l * K + p] = z[q];
+      }
+    }
+  }
+  __syncthreads();
+  // M = (I + L)^{-1} in place: wave ws takes walker w0 + ws, lane q column
+  // q.  Row m needs C[m][q..m-1] and the finished rows q..m-1 of column q;
+  // each lane reads only its own column of M and rows of C not yet
+  // replaced, and writes row m after its reads.  Eight terms per round
+  // (their loads issued together; past m the row index is clamped and the
+  // weight is zero).
+  {
+    T *Mw = Mbase + (size_t)wid * K * K;
+    const int q = lane;
+    if (q < kb) Mw[q * K + q] = (T)1;
+    for (int m = 1; m < kb; ++m) {
+      if (q < m) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int p0 = q; p0 < m; p0 += 8) {
+          T mv[8], cv[8];
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const int pr = p0 + r < m ? p0 + r : q;
+            mv[r] = Mw[pr * K + q];
+            cv[r] = p0 + r < m ? Mw[m * K + pr] : (T)0;
+          }
+#pragma unroll
+          for (int r = 0; r < 8; r += 2) {
+            s0 += (double)cv[r] * (double)mv[r];
+            s1 += (double)cv[r + 1] * (double)mv[r + 1];
+          }
+        }
+        Mw[m * K + q] = (T)(-(s0 + s1));
+      }
+    }
   }
   __syncthreads();
   // Z'[l][b] = sum_{p <= l} M[l][p] Z[p][b]
   for (int tt = wid; tt < TW * nz; tt += NW_TILE) {
     const int w = w0 + tt / nz, r = tt % nz;
     const int l0 = (r / NOB) * 16, b0 = (r % NOB) * 16;
-    const T *Ms = (const T *)c.Ms + (size_t)w * K * K;
+    const T *Ms = Mbase + (size_t)(w - w0) * K * K;
     const T *Zs = (const T *)c.Zs + (size_t)w * c.K16 * NP;
     T *Z2 = (T *)c.Vs + (size_t)w * c.K16 * NP;
     const auto z = mfma_tile<T>(
@@ -1274,26 +1334,22 @@ __device__ void flush_block(const DevCtx &c, int w0, int sp, int kb) {
 
 // Block update after a move of electron i (block position m of kb) of walker
 // w, served by the 64 lanes t of one wave.  Accepted: Delta = a' - a_old
-// enters Dl[m]; each block row b is formed z_b = Delta . Gb[b] by a pair of
-// lanes (one half of the row each); later rows take the
-// Sherman-Morrison correction Gb[b] -= z_b / rho * Gb[m], earlier rows' z_b
-// are the coefficients C[m][b] = Delta_m . u_b, from which row m of
-// M = (I + L)^{-1} is formed; Gb[m] becomes u_m = col / rho; the orbital row,
-// position and log|D| follow.  Rejected: Dl[m] = 0 and M row m = e_m.
+// enters Dl[m]; each later block row b > m is formed z_b = Delta . Gb[b] by a
+// pair of lanes (one half of the row each) and takes the Sherman-Morrison
+// correction Gb[b] -= z_b / rho * Gb[m]; Gb[m] becomes u_m = col / rho; the
+// orbital row, position and log|D| follow.  (The coefficients
+// C[m][p] = Delta_m . u_p of the earlier rows are formed at the flush, all at
+// once.)  Rejected: Dl[m] = 0.
 // vw: proposal VGL [5][NP]; colm: current inverse column of i (Gb[m]);
-// aold: old value row of i (overwritten with Delta); crow: scratch [KMAX].
+// aold: old value row of i (overwritten with Delta).
 template <typename T, int NOB>
 __device__ void block_accept(const DevCtx &c, int w, int t, int i, int sp, int m, int kb,
                              int accepted, double rho, const T *vw, T *colm_w, T *aold_w,
-                             T *crow_w, const double rn[3]) {
+                             const double rn[3]) {
   constexpr int NP = NOB * 16;
   T *Gb = (T *)c.Gb + blk_off(c, w);
   T *Dl = (T *)c.Dl + blk_off(c, w);
   double *Rw = c.R + (size_t)w * c.ne * 3;
-    // Later rows take the Sherman-Morrison correction
-    // Gb[b] -= z_b / rho * Gb[m]; earlier rows' z_b are the coefficients
-    // C[m][b] = Delta_m . u_b the flush needs.
-    T *Ms = (T *)c.Ms + (size_t)w * c.K * c.K;
     if (accepted) {
       const double irho = 1.0 / rho;
       for (int j = t; j < NP; j += 64) {
@@ -1312,9 +1368,9 @@ __device__ void block_accept(const DevCtx &c, int w, int t, int i, int sp, int m
       const int h = t >> 5;
       const T *dl = aold_w + h * HALF;
       const T *cm = colm_w + h * HALF;
-      for (int b0 = 0; b0 < kb; b0 += 32) {
+      for (int b0 = (m + 1) & ~31; b0 < kb; b0 += 32) {
         const int b = b0 + (t & 31);
-        const bool live = b < kb && b != m;  // row m (u_m) is rewritten below
+        const bool live = b < kb && b > m;
         vecT *row = (vecT *)(Gb + (size_t)(live ? b : 0) * NP + h * HALF);
         vecT keep[KEEP ? HALF / VW : 1];
         double zp = 0.0;
@@ -1334,45 +1390,17 @@ __device__ void block_accept(const DevCtx &c, int w, int t, int i, int sp, int m
         }
         const double z = zp + __shfl_xor(zp, 32, 64);
         if (live) {
-          if (b > m) {
-            const T f = (T)(z * irho);
+          const T f = (T)(z * irho);
 #pragma unroll
-            for (int q = 0; q < HALF / VW; ++q) {
-              vecT x;
-              if constexpr (KEEP) x = keep[q]; else x = row[q];
+          for (int q = 0; q < HALF / VW; ++q) {
+            vecT x;
+            if constexpr (KEEP) x = keep[q]; else x = row[q];
 #pragma unroll
-              for (int e = 0; e < VW; ++e) x[e] -= f * cm[q * VW + e];
-              row[q] = x;
-            }
-          } else if (h == 0) {
-            crow_w[b] = (T)z;  // C[m][b] = Delta_m . u_b
+            for (int e = 0; e < VW; ++e) x[e] -= f * cm[q * VW + e];
+            row[q] = x;
           }
         }
       }
-      // Row m of M = (I + L)^{-1} (L strictly lower, L[m][p] = C[m][p]):
-      // M[m][q] = -sum_{p=q}^{m-1} C[m][p] M[p][q]; lane q owns column q.
-      // Eight terms per round (their loads issued together; past m the row
-      // index is clamped and the weight is zero), so a column costs at most
-      // ceil(m / 8) memory round trips instead of m.
-      for (int q = t; q < m; q += 64) {
-        double s0 = 0.0, s1 = 0.0;
-        for (int p0 = q; p0 < m; p0 += 8) {
-          T mv[8], cv[8];
-#pragma unroll
-          for (int r = 0; r < 8; ++r) {
-            const int pr = p0 + r < m ? p0 + r : q;
-            mv[r] = Ms[pr * c.K + q];
-            cv[r] = p0 + r < m ? crow_w[pr] : (T)0;
-          }
-#pragma unroll
-          for (int r = 0; r < 8; r += 2) {
-            s0 += (double)cv[r] * (double)mv[r];
-            s1 += (double)cv[r + 1] * (double)mv[r + 1];
-          }
-        }
-        Ms[m * c.K + q] = (T)(-(s0 + s1));
-      }
-      if (t == 0) Ms[m * c.K + m] = (T)1;
       for (int j = t; j < NP; j += 64) Gb[m * NP + j] = (T)((double)colm_w[j] * irho);
       T *dst = (T *)c.vglc + vglc_off(c, w, i);
       for (int j = t; j < 5 * NP; j += 64) dst[j] = vw[j];
@@ -1383,8 +1411,6 @@ __device__ void block_accept(const DevCtx &c, int w, int t, int i, int sp, int m
       }
     } else {
       for (int j = t; j < NP; j += 64) Dl[m * NP + j] = (T)0;
-      for (int q = t; q < m; q += 64) Ms[m * c.K + q] = (T)0;
-      if (t == 0) Ms[m * c.K + m] = (T)1;
     }
 }
 
@@ -1440,7 +1466,6 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
   __shared__ double s_v[TW][3];
   __shared__ double s_uacc[TW], s_uold[TW], s_rho[TW];
   __shared__ int s_acc[TW];
-  __shared__ T crow[TW][KMAX];
   __shared__ double s_S[TW], s_C0[TW];
   const int tid = threadIdx.x;
   const int ws = wave_id(), t = tid & 63;  // one wave per walker
@@ -1650,7 +1675,7 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
     if (!isfinite(rho_all)) c.flags[w] |= 1u;
     PHASE_MARK(3);
     // ---- P4: delayed update of the block (lanes of this walker only)
-    block_accept<T, NOB>(c, w, t, i, sp, m, kb, accepted, rho, vw, colm[ws], aold[ws], crow[ws], rn);
+    block_accept<T, NOB>(c, w, t, i, sp, m, kb, accepted, rho, vw, colm[ws], aold[ws], rn);
     if constexpr (MSD) {
       if (accepted) {
         // T += g_i q^T (g_i: the column before the move), keep R_d' and S'
@@ -1672,7 +1697,10 @@ __device__ __forceinline__ void sweep_body(const DevCtx &c, uint8_t *acc_log,
     n_accepted += (unsigned)accepted;
     PHASE_MARK(4);
     // ---- P5: block end -> rank-k flush of the full inverse
-    if (m == kb - 1) flush_block<T, NOB>(c, tile * TW, sp, kb);
+    // (C and M go to the basis tiles' LDS, free between moves, when they fit)
+    if (m == kb - 1)
+      flush_block<T, NOB>(c, tile * TW, sp, kb,
+                          (size_t)TW * c.K * c.K <= (size_t)2 * FM * NCOL ? Bs : nullptr);
     PHASE_MARK(5);
     __syncthreads();
     PHASE_MARK(6);
@@ -1821,7 +1849,7 @@ __global__ __launch_bounds__(64) void k_accept(DevCtx c, int i, int sp, int m, i
                                                const uint8_t *acc, const T *prop,
                                                const double *prop_rho, const double *r_new) {
   constexpr int NP = NOB * 16;
-  __shared__ T colm[NP], aold[NP], crow[KMAX];
+  __shared__ T colm[NP], aold[NP];
   const int w = blockIdx.x, t = threadIdx.x;
   const T *Gb = (const T *)c.Gb + blk_off(c, w);
   const T *row = (const T *)c.vglc + vglc_off(c, w, i);
@@ -1839,13 +1867,13 @@ __global__ __launch_bounds__(64) void k_accept(DevCtx c, int i, int sp, int m, i
     c.nprop[w] += 1u;
   }
   block_accept<T, NOB>(c, w, t, i, sp, m, kb, accepted && rho != 0.0, rho,
-                       prop + (size_t)w * 5 * NP, colm, aold, crow, rn);
+                       prop + (size_t)w * 5 * NP, colm, aold, rn);
 }
 
 // Rank-k flush of the pending moves of the current block (kb of them).
 template <typename T, int NOB>
 __global__ __launch_bounds__(NT_TILE) void k_flush(DevCtx c, int sp, int kb) {
-  flush_block<T, NOB>(c, blockIdx.x * TW, sp, kb);
+  flush_block<T, NOB>(c, blockIdx.x * TW, sp, kb, nullptr);
 }
 
 }  // namespace dmcx
