@@ -99,8 +99,8 @@ def test_c3h8_full_expansion_runs_match_oracle(prec):
 @pytest.mark.parametrize("prec", [dmcx.DMCX_FP64, dmcx.DMCX_MIXED])
 def test_large_alkanes_measure_and_ion_grads(k, prec):
     """C24H50, C29H60, C33H68 (128, 144 and 160 orbital columns): E_L, log|Psi|
-    and the ion gradients of 2 walkers against the oracle.  The FP64 form of
-    C33H68 does not fit the LDS of a CU and is reported as unsupported."""
+    and the ion gradients of 2 walkers against the oracle.  Should a form
+    not fit the LDS of a CU, creation reports it as unsupported."""
     s = _mol(k)
     W = 2
     R = synth.make_walkers(s, W, 9302 + k)
@@ -110,7 +110,7 @@ def test_large_alkanes_measure_and_ion_grads(k, prec):
         ctx = dmcx.Context(s, W, precision=prec)
     except dmcx.DmcxError as ex:
         assert prec == dmcx.DMCX_FP64 and k == 7 and ex.status == dmcx.DMCX_E_UNSUPPORTED
-        pytest.skip("FP64 form of the 160-column tile does not fit the LDS (documented)")
+        pytest.skip("FP64 form of the 160-column tile does not fit the LDS")
     ctx.set_walkers(R)
     e, lp, sg = ctx.measure()
     lp_o, sg_o, e_o, rc = oracle.evaluate_batch(s, R)
@@ -127,6 +127,30 @@ def test_large_alkanes_measure_and_ion_grads(k, prec):
     print(f"[config5] {s.name} ion grads: max rel err {err.max():.2e}, amp {amp.max():.3g}",
           flush=True)
     assert np.all(err <= rel * amp)
+
+
+def test_largest_alkane_fp64_step_state():
+    """C33H68 (200 e, 1740 functions, 160 orbital columns) in FP64: after one
+    DMC step through the multideterminant sweep (delayed updates and flushes
+    at the widest tile), the step-end E_L of the run and a fresh measure of
+    the final configurations agree with the oracle's evaluation of those
+    configurations (an oracle run takes minutes per walker at this size, so
+    the step's own moves are not replayed)."""
+    s = _mol(7)
+    W = 2
+    R = synth.make_walkers(s, W, 9320)
+    ctx = dmcx.Context(s, W, precision=dmcx.DMCX_FP64, delay_rank=32, recompute_period=64)
+    ctx.set_walkers(R)
+    acc, el = ctx.run(1, mode=dmcx.DMCX_DMC, e_trial=-300.0, logs=True)
+    assert acc.mean() > 0.5
+    Rg, _ = ctx.get_walkers()
+    lp_o, sg_o, e_o, rc = oracle.evaluate_batch(s, Rg)
+    assert rc == 0
+    _check(el[-1], e_o, s, Rg, "E_L at the step end", 1e-10)
+    e, lp, sg = ctx.measure()
+    np.testing.assert_array_equal(sg, sg_o)
+    _check(e, e_o, s, Rg, "E_L measured", 1e-10)
+    _check(lp, lp_o, s, Rg, "log|Psi|", 1e-10)
 
 
 def test_whole_group_graph_matches_single_contexts():
