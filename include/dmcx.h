@@ -468,6 +468,20 @@ dmcx_status dmcx_walker_flags(dmcx_ctx *ctx, uint8_t *flags, dmcx_mem mem);
 dmcx_status dmcx_reconfigure(dmcx_ctx *ctx, const double *u, int32_t *copies, double *log_wbar,
                              dmcx_mem mem);
 
+/* Passage: Eq. 3 (the determinant ratios through the inverse A^{-1} that the
+ * delayed updates keep and the periodic LU recompute rebuilds).
+ * Residual of the stored inverses, a diagnostic: res[W][2], for walker w and
+ * spin s, max_ij |sum_k A_ik (A^{-1})_kj - delta_ij| over the spin's Slater
+ * matrix A_ik = phi_k(r_i) of the current positions (the cached orbital
+ * value rows) and the stored inverse, in the working precision of the
+ * context (FP32 for the mixed forms), products and sums in FP64.  NaN when
+ * any entry is NaN, 0 for an empty spin.  Right after an FP64 recompute it
+ * is at round-off; between recomputes it shows the drift of the delayed
+ * updates.  A pending electron block of the move-by-move calls is flushed
+ * first.  mem applies to res; host output is complete on return.  Errors:
+ * DMCX_E_STATE (walkers not set). */
+dmcx_status dmcx_inverse_residual(dmcx_ctx *ctx, double *res, dmcx_mem mem);
+
 /* Passage: QMC section, Eq. 1 (walker weights of the projection).
  * Birth/death branching of a one-system context: the weights become walker
  * counts, so the population size varies (the paper does not fix the control

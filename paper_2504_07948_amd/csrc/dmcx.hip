@@ -13,6 +13,7 @@
 
 #include "dmcx.h"
 #include "estimators.h"
+#include "residual.h"
 #include "forces_aux.h"
 #include "jparams.h"
 #include "pp.h"
@@ -2618,6 +2619,28 @@ dmcx_status dmcx_walker_count(const dmcx_ctx *c, int32_t *n_walkers, int32_t *ca
   if (!c) return DMCX_E_INVALID;
   if (n_walkers) *n_walkers = c->W;
   if (capacity) *capacity = c->is_group() ? c->W : c->Wcap;
+  return DMCX_OK;
+}
+
+dmcx_status dmcx_inverse_residual(dmcx_ctx *c, double *res, dmcx_mem mem) {
+  if (!c || !res) return DMCX_E_INVALID;
+  if (c->is_group()) {
+    for (size_t i = 0; i < c->subs.size(); ++i) {
+      const dmcx_status st = dmcx_inverse_residual(c->subs[i], res + 2 * (size_t)c->sub_off[i], mem);
+      if (st) return c->err = c->subs[i]->err, st;
+    }
+    return DMCX_OK;
+  }
+  if (!c->walkers_set) return fail(c, DMCX_E_STATE, "walkers not set");
+  dmcx_status st = refresh_after_moves(c);  // a pending electron block is flushed first
+  if (st) return st;
+  double *dst = mem == DMCX_DEVICE ? res : c->d_orb;  // staging: [W][2] doubles fit
+  if (!c->mixed)
+    hipLaunchKernelGGL(k_inv_residual<double>, dim3(c->W, 2), dim3(NT_AUX), 0, c->stream, c->dc, dst);
+  else
+    hipLaunchKernelGGL(k_inv_residual<float>, dim3(c->W, 2), dim3(NT_AUX), 0, c->stream, c->dc, dst);
+  HIP_TRY(c, hipGetLastError());
+  if (mem == DMCX_HOST) return copy_out(c, res, dst, (size_t)c->W * 2 * sizeof(double), mem);
   return DMCX_OK;
 }
 

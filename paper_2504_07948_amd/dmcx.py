@@ -40,6 +40,7 @@ EXPORTED = [
     "dmcx_energy_escalations", "dmcx_set_et_feedback", "dmcx_get_trial_energy",
     "dmcx_jastrow_param_grads", "dmcx_linear_method", "dmcx_set_tile_shape",
     "dmcx_get_tile_shape", "dmcx_branch", "dmcx_set_walker_count", "dmcx_walker_count",
+    "dmcx_inverse_residual",
 ]
 
 
@@ -111,6 +112,7 @@ def load():
         "dmcx_branch": [P, I64, P, P, I32],
         "dmcx_set_walker_count": [P, I32],
         "dmcx_walker_count": [P, P, P],
+        "dmcx_inverse_residual": [P, P, I32],
         "dmcx_sync": [P],
         "dmcx_last_run_timing": [P, P, P, P],
         "dmcx_selftest": [P],
@@ -296,6 +298,10 @@ def dmcx_set_walker_count(ctx, n):
 
 def dmcx_walker_count(ctx, n, cap):
     return load().dmcx_walker_count(ctx, n, cap)
+
+
+def dmcx_inverse_residual(ctx, res, mem):
+    return load().dmcx_inverse_residual(ctx, res, mem)
 
 
 def dmcx_sync(ctx):
@@ -607,6 +613,13 @@ class Context:
         n, cap = C.c_int32(0), C.c_int32(0)
         self.check(dmcx_walker_count(self.h, C.byref(n), C.byref(cap)))
         return int(n.value), int(cap.value)
+
+    def inverse_residual(self):
+        """[W][2] max_ij |A A^{-1} - I| of each walker's spin matrices (the
+        stored inverse of the working precision)."""
+        out = np.zeros((self.W, 2))
+        self.check(dmcx_inverse_residual(self.h, _ptr(out), DMCX_HOST))
+        return out
 
     def _set_w(self, n):
         self.W = n
