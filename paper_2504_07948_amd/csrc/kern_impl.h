@@ -78,7 +78,12 @@ void NobLaunch<T>::accept(int nob, const DevCtx &c, int iel, int sp, int m, int 
 
 template <typename T>
 void NobLaunch<T>::flush(int nob, const DevCtx &c, int sp, int kb, hipStream_t s) {
-#define DMCX_CALL(N) k_flush<T, N><<<dim3(c.Wpad / TW), dim3(NT_TILE), 0, s>>>(c, sp, kb)
+  // the coefficient and M scratch in LDS when the tile's K x K blocks fit in
+  // the default 64 KB of dynamic LDS, else in the global Ms
+  const size_t lds = (size_t)TW * c.K * c.K * sizeof(T);
+  const int use_lds = lds <= 65536 ? 1 : 0;
+#define DMCX_CALL(N) \
+  k_flush<T, N><<<dim3(c.Wpad / TW), dim3(NT_TILE), use_lds ? lds : 0, s>>>(c, sp, kb, use_lds)
   DMCX_NOB_SWITCH(nob, DMCX_CALL)
 #undef DMCX_CALL
 }

@@ -1872,8 +1872,9 @@ __global__ __launch_bounds__(64) void k_accept(DevCtx c, int i, int sp, int m, i
 
 // Rank-k flush of the pending moves of the current block (kb of them).
 template <typename T, int NOB>
-__global__ __launch_bounds__(NT_TILE) void k_flush(DevCtx c, int sp, int kb) {
-  flush_block<T, NOB>(c, blockIdx.x * TW, sp, kb, nullptr);
+__global__ __launch_bounds__(NT_TILE) void k_flush(DevCtx c, int sp, int kb, int use_lds) {
+  extern __shared__ __align__(16) char smem_basis[];  // TW K x K scratch (use_lds)
+  flush_block<T, NOB>(c, blockIdx.x * TW, sp, kb, use_lds ? (T *)smem_basis : nullptr);
 }
 
 }  // namespace dmcx
