@@ -94,7 +94,7 @@ void NobLaunch<T>::values64(int nob, const DevCtx &c, double *A64, size_t lds, h
     const int npts = c.Wpad * c.ne;
 #define DMCX_CALL(N)                                                                   \
   if (allow_lds(k_values64<T, N>, lds) == hipSuccess) \
-  k_values64<T, N><<<dim3((npts + NVALID - 1) / NVALID), dim3(NT_TILE), lds, s>>>(c, A64)
+  k_values64<T, N><<<dim3((npts + NPV - 1) / NPV), dim3(NT_TILE), lds, s>>>(c, A64)
     DMCX_NOB_SWITCH(nob, DMCX_CALL)
 #undef DMCX_CALL
   }

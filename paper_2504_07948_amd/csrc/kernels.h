@@ -64,6 +64,7 @@ static_assert(TW == 4 || TW == 8, "tile width");
 constexpr int NVALID = 5 * TW;              // MFMA columns in use: 5 VGL rows per walker
 constexpr int NCB = (NVALID + 15) / 16;     // 16-column MFMA blocks (3 or 2)
 constexpr int NCOL = 16 * NCB;              // padded column count (48 or 32)
+constexpr int NPV = NCOL;                   // values-only tile: one point per column
 constexpr int NT_TILE = 64 * TW;            // tile kernels: one wave per walker
 constexpr int NW_TILE = TW;
 constexpr int NKH = NW_TILE / 4;            // K-parity groups of the orbital tile (2 or 1)
@@ -377,7 +378,7 @@ __device__ void basis_stage(const BasisLDS &B, int g_begin, int g_end, int fn_be
 #undef DMCX_BASIS_CASE
 }
 
-// Basis values only (no derivatives) of one stage at NVALID points into
+// Basis values only (no derivatives) of one stage at NPV points into
 // Bs[f][point] (the orbital-value tile: one MFMA column per point).  A task is
 // one (point, shell): its radial part once, then every Cartesian component.
 template <typename T, int L, int NPR>
@@ -385,9 +386,9 @@ __device__ void basis_stage_val_t(const BasisLDS &B, int g_begin, int g_end, int
                                   const double (*pts)[3], T *Bs, int vt, int nvt,
                                   int npr_rt = NPR) {
   const int nsh = 4 * (g_end - g_begin);
-  const int ntask = NVALID * nsh;
+  const int ntask = NPV * nsh;
   for (int task = vt; task < ntask; task += nvt) {
-    const int pt = task % NVALID, sl = task / NVALID;
+    const int pt = task % NPV, sl = task / NPV;
     const int g = g_begin + (sl >> 2), s = sl & 3;
     const int4 gi = B.ginfo[g];
     const double *cxyz = B.xyz + (size_t)(g * 4 + s) * 3;
@@ -516,7 +517,7 @@ __device__ __forceinline__ void mfma_stage(typename Acc4<T>::type (&acc)[(NOB + 
 // stage s, so they arrive during those MFMAs, the basis evaluation and the
 // barrier.  One barrier per stage; the two K-parity partial sums are added
 // once at the end.
-// VAL: the tile's NVALID columns are NVALID points with their values only
+// VAL: the tile's NPV columns are NPV points with their values only
 // (basis_stage_val) instead of TW points with five VGL rows each.
 template <typename T, int NOB, int KS = stage_ksteps(NOB), bool VAL = false>
 __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)[3], T *Bs0,
@@ -549,10 +550,13 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
   };
   stage_range(0);
   load_stage_a<T, NOB, KH>(Cp, fb, ob0, kh, kq, col, a0);
-  constexpr int NPADC = NCOL - NVALID;  // padding columns, zero for every stage
-  for (int i = tid; i < FM * NPADC; i += NT_TILE) {
-    Bs0[(i / NPADC) * NCOL + NVALID + i % NPADC] = (T)0;
-    Bs1[(i / NPADC) * NCOL + NVALID + i % NPADC] = (T)0;
+  constexpr int NUSE = VAL ? NPV : NVALID;  // columns in use
+  constexpr int NPADC = NCOL - NUSE;       // padding columns, zero for every stage
+  if constexpr (NPADC > 0) {
+    for (int i = tid; i < FM * NPADC; i += NT_TILE) {
+      Bs0[(i / NPADC) * NCOL + NUSE + i % NPADC] = (T)0;
+      Bs1[(i / NPADC) * NCOL + NUSE + i % NPADC] = (T)0;
+    }
   }
   if constexpr (VAL) basis_stage_val<T>(BL, g0, g1, fb, pts, Bs0, tid, NT_TILE);
   else basis_stage<T>(BL, g0, g1, fb, pts, Bs0, tid, NT_TILE);
@@ -610,7 +614,7 @@ __device__ void mo_tile(const DevCtx &c, const BasisLDS &BL, const double (*pts)
 #pragma unroll
           for (int cb = 0; cb < NCB; ++cb) {
             const int n = cb * 16 + col;
-            if (n < NVALID) {
+            if (n < NUSE) {
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 T *o = out + n * NP + ob * 16 + Acc4<T>::row(kq, r);
@@ -751,7 +755,7 @@ __global__ __launch_bounds__(NT_TILE) void k_orbitals_at(DevCtx c, const double 
 }
 
 // FP64 orbital values (no derivatives) of every electron of every walker,
-// NVALID (walker, electron) points per tile: A64[w][e][NP], the Slater
+// NPV (walker, electron) points per tile (one per MFMA column): A64[w][e][NP], the Slater
 // matrices from which the mixed form takes its FP64 inverse and energy each
 // step.  The working-precision value rows of vglc are refreshed from them, so
 // the next sweep's delayed updates start from rows that match the inverse.
@@ -766,21 +770,21 @@ void k_values64(DevCtx c, double *A64) {
   constexpr int NP = NOB * 16;
   constexpr int KS = stage_ksteps_w4(NOB);
   constexpr int FM = 4 * KS;
-  constexpr int NBS = 2 * FM * NCOL > NVALID * NP ? 2 * FM * NCOL : NVALID * NP;
+  constexpr int NBS = 2 * FM * NCOL > NPV * NP ? 2 * FM * NCOL : NPV * NP;
   extern __shared__ __align__(16) char smem_basis[];
   const BasisLDS BL = stage_basis_lds(c.B, smem_basis);
   __shared__ double Bsm[NBS];  // two stage buffers, then the output tile
   double *Bs0 = Bsm, *Bs1 = Bsm + FM * NCOL, *out = Bsm;
-  __shared__ double pts[NVALID][3];
+  __shared__ double pts[NPV][3];
   const int npts = c.Wpad * c.ne;
-  const int p0 = blockIdx.x * NVALID;
-  for (int i = threadIdx.x; i < NVALID * 3; i += NT_TILE) {
+  const int p0 = blockIdx.x * NPV;
+  for (int i = threadIdx.x; i < NPV * 3; i += NT_TILE) {
     const int p = min(p0 + i / 3, npts - 1);
     pts[i / 3][i % 3] = c.R[(size_t)p * 3 + i % 3];
   }
   __syncthreads();
   mo_tile<double, NOB, KS, true>(c, BL, pts, Bs0, Bs1, out);
-  for (int i = threadIdx.x; i < NVALID * NP; i += NT_TILE) {
+  for (int i = threadIdx.x; i < NPV * NP; i += NT_TILE) {
     const int pl = i / NP, j = i - pl * NP, p = p0 + pl;
     if (p < npts) {
       A64[(size_t)p * NP + j] = out[i];
