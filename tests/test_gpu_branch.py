@@ -180,3 +180,36 @@ def test_group_context_refuses_branching():
     g = dmcx.Context([a, b], [8, 8], seed=1)
     with pytest.raises(dmcx.DmcxError):
         g.set_walker_count(4)
+
+
+def test_calls_after_growth_match_a_fresh_context():
+    """After a branch that grows the population, the per-walker calls whose
+    buffers are sized by the capacity (estimators, ion derivatives, Jastrow
+    parameter derivatives, linear-method matrices) agree with a context made
+    for the new count on the same positions."""
+    s = synth.small_molecule()
+    cap, W0, seed = 64, 20, 9
+    ctx = dmcx.Context(s, cap, delay_rank=2, seed=seed)
+    ctx.set_walker_count(W0)
+    R = synth.make_walkers(s, W0, 531)
+    ctx.set_walkers(R, 0.5 + np.random.default_rng(10).normal(0.0, 0.4, W0))
+    _, wn = ctx.branch(0)
+    assert wn > W0
+    Rb, lw = ctx.get_walkers()
+    fresh = dmcx.Context(s, wn, delay_rank=2, seed=seed)
+    fresh.set_walkers(Rb, lw)
+    est, est_f = ctx.estimators(), fresh.estimators()
+    assert est[0][0] == wn
+    np.testing.assert_allclose(est[0][:9], est_f[0][:9], rtol=1e-13, atol=0)
+    dl, dv = ctx.ion_grads()
+    dl_f, dv_f = fresh.ion_grads()
+    _close(dl, dl_f, rel=1e-12)
+    _close(dv, dv_f, rel=1e-12)
+    O, D = ctx.jastrow_param_grads()
+    O_f, D_f = fresh.jastrow_param_grads()
+    _close(O, O_f, rel=1e-12)
+    _close(D, D_f, rel=1e-12)
+    S, H = ctx.linear_method()
+    S_f, H_f = fresh.linear_method()
+    _close(S, S_f, rel=1e-11)
+    _close(H, H_f, rel=1e-11)
