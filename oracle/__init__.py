@@ -89,6 +89,7 @@ def _load():
         lib.orc_jastrow_param_grads_batch.argtypes = [P, C.c_int32, P, P, P, C.c_int32]
         lib.orc_j3_values.argtypes = [P, P, P]
         lib.orc_nlpp.argtypes = [P, P, C.c_uint64, C.c_int64, C.c_int32, P]
+        lib.orc_nlpp_param_grads.argtypes = [P, P, C.c_uint64, C.c_int64, C.c_int32, P]
         lib.orc_nlpp_batch.argtypes = [P, C.c_int32, P, C.c_uint64, C.c_int64, C.c_int32, P,
                                        C.c_int32]
         lib.orc_nlpp_rotation.argtypes = [C.c_uint64, C.c_int64, C.c_int32, C.c_int32, P]
@@ -483,6 +484,16 @@ def nlpp(sys, R, seed, step, walker):
     rc = _load().orc_nlpp(o.ref, _ptr(np.ascontiguousarray(R, dtype=np.float64)), seed, step,
                           walker, C.byref(v))
     return float(v.value), rc
+
+
+def nlpp_param_grads(sys, R, seed, step, walker):
+    """d V_NL / dp [8] for the Jastrow parameter directions (the non-local
+    part of dE_L/dp) at fixed rotations.  Returns (dv, rc)."""
+    o = _osys(sys)
+    dv = np.zeros(8)
+    rc = _load().orc_nlpp_param_grads(o.ref, _ptr(np.ascontiguousarray(R, dtype=np.float64)),
+                                      seed, step, walker, _ptr(dv))
+    return dv, rc
 
 
 def nlpp_batch(sys, R, seed, step, walker_offset=0, n_threads=0):

@@ -1031,6 +1031,89 @@ int orc_j3_values(const orc_system *s, const double *R, double *F) {
   return 0;
 }
 
+/* The eight Jastrow-parameter directions of a configuration, from their
+ * definitions: O_0 = sum_{i<j} dU_ee/db, O_1 = sum_{i,A} dU_en/db,
+ * O_{2+k} = F_k(R) (the three-body sums). */
+static void jastrow_param_values(const orc_system *s, const double *R, double O[8]) {
+  const int ne = s->n_up + s->n_dn;
+  double h, h1, h2;
+  O[0] = O[1] = 0.0;
+  for (int i = 0; i < ne; ++i) {
+    for (int j = i + 1; j < ne; ++j) {
+      double r2 = 0.0;
+      for (int x = 0; x < 3; ++x) r2 += (R[3 * i + x] - R[3 * j + x]) * (R[3 * i + x] - R[3 * j + x]);
+      pade_db(ee_a(s, i, j), s->jee_b, sqrt(r2), &h, &h1, &h2);
+      O[0] += h;
+    }
+    for (int A = 0; A < s->n_atom; ++A) {
+      double r2 = 0.0;
+      for (int x = 0; x < 3; ++x)
+        r2 += (R[3 * i + x] - s->ion_xyz[3 * A + x]) * (R[3 * i + x] - s->ion_xyz[3 * A + x]);
+      pade_db(s->jen_a[A], s->jen_b, sqrt(r2), &h, &h1, &h2);
+      O[1] += h;
+    }
+  }
+  orc_j3_values(s, R, O + 2);
+}
+
+/* Derivatives of the non-local pseudopotential energy with respect to the
+ * eight Jastrow parameters (the same directions as orc_jastrow_param_grads,
+ * whose dEL covers the kinetic part): each quadrature ratio Psi(R_q)/Psi(R)
+ * carries exp(J(R_q) - J(R)), so at fixed rotations
+ *   dV_NL/dp = sum_{i,A,q} (1/12) f_q rho_q (O_p(R_q) - O_p(R)),
+ * f_q = sum_l v_l(r) (2l+1) P_l(cos theta_q), O_p as above.  Straight from
+ * that sum: every moved configuration is evaluated in full.  dv[8]. */
+int orc_nlpp_param_grads(const orc_system *s, const double *R, uint64_t seed, int64_t step,
+                         int32_t walker, double *dv) {
+  for (int p = 0; p < 8; ++p) dv[p] = 0.0;
+  if (s->pp_n_term == 0) return 0;
+  if (s->n_det > 1) return 4;
+  const int ne = s->n_up + s->n_dn;
+  double *Rq = (double *)malloc(sizeof(double) * 3 * ne);
+  double lp0, lpq, O0[8], Oq[8];
+  int32_t sg0, sgq;
+  int rc = orc_evaluate(s, R, &lp0, &sg0, NULL, NULL);
+  jastrow_param_values(s, R, O0);
+  for (int i = 0; i < ne; ++i) {
+    double rot[9];
+    int have_rot = 0;
+    for (int At = 0; At < s->n_atom; ++At) {
+      int lmax = -1;
+      for (int t = 0; t < s->pp_n_term; ++t)
+        if (s->pp_atom[t] == At && s->pp_l[t] > lmax) lmax = s->pp_l[t];
+      if (lmax < 0) continue;
+      const double *c = s->ion_xyz + 3 * At;
+      const double d[3] = {R[3 * i] - c[0], R[3 * i + 1] - c[1], R[3 * i + 2] - c[2]};
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      if (!(r < s->pp_rcut[At])) continue;
+      if (!have_rot) {
+        orc_nlpp_rotation(seed, step, walker, i, rot);
+        have_rot = 1;
+      }
+      double vl[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int t = 0; t < s->pp_n_term; ++t)
+        if (s->pp_atom[t] == At && s->pp_l[t] >= 0)
+          vl[s->pp_l[t]] += s->pp_beta[t] * pow(r, s->pp_n[t] - 2) * exp(-s->pp_alpha[t] * r * r);
+      for (int q = 0; q < 12; ++q) {
+        double o[3], od[3];
+        ico_dir(q, o);
+        for (int x = 0; x < 3; ++x) od[x] = rot[3 * x] * o[0] + rot[3 * x + 1] * o[1] + rot[3 * x + 2] * o[2];
+        const double cth = (od[0] * d[0] + od[1] * d[1] + od[2] * d[2]) / r;
+        for (int k = 0; k < 3 * ne; ++k) Rq[k] = R[k];
+        for (int x = 0; x < 3; ++x) Rq[3 * i + x] = c[x] + r * od[x];
+        rc |= orc_evaluate(s, Rq, &lpq, &sgq, NULL, NULL);
+        jastrow_param_values(s, Rq, Oq);
+        const double ratio = (double)(sgq * sg0) * exp(lpq - lp0);
+        double f = 0.0;
+        for (int l = 0; l <= lmax; ++l) f += vl[l] * (2 * l + 1) * legendre(l, cth);
+        for (int p = 0; p < 8; ++p) dv[p] += f * ratio * (Oq[p] - O0[p]) / 12.0;
+      }
+    }
+  }
+  free(Rq);
+  return rc;
+}
+
 int orc_jastrow_param_grads_batch(const orc_system *s, int32_t W, const double *R,
                                   double *dlogpsi, double *dEL, int32_t n_threads) {
   const int ne = s->n_up + s->n_dn;

@@ -156,6 +156,11 @@ int orc_run_feedback(const orc_system *s, int32_t W, double *R, double *log_w, d
 int orc_jastrow_param_grads(const orc_system *s, const double *R, double *dlogpsi, double *dEL);
 int orc_jastrow_param_grads_batch(const orc_system *s, int32_t W, const double *R,
                                   double *dlogpsi, double *dEL, int32_t n_threads);
+/* d V_NL / dp for the same eight directions at fixed quadrature rotations
+ * (the non-local part of dE_L/dp; see oracle.c); 4 with a multideterminant
+ * expansion. */
+int orc_nlpp_param_grads(const orc_system *s, const double *R, uint64_t seed, int64_t step,
+                         int32_t walker, double *dv);
 /* The six three-body basis sums F_k(R) themselves (c = 0 derivatives of J). */
 int orc_j3_values(const orc_system *s, const double *R, double *F);
 

@@ -210,3 +210,60 @@ def test_pp_ion_grads_against_ghost_centre_differences():
             fd = (4 * d1 - d2) / 3
             print(f"[nlpp] walker {w} x{x}: analytic {g[-1, x]:.10f} fd {fd:.10f}")
             assert abs(g[-1, x] - fd) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_nlpp_param_grads_pade_against_differences():
+    """d V_NL / d b for the two Pade b (rotations fixed): Richardson
+    differences of the oracle's non-local energy in jee_b and jen_b."""
+    s = synth.small_molecule_pp()
+    R = synth.make_walkers(s, 2, 51)
+    for w in range(2):
+        dv, rc = oracle.nlpp_param_grads(s, R[w], 3, 1, w)
+        assert rc == 0
+        for name, p in (("jee_b", 0), ("jen_b", 1)):
+            b0 = getattr(s, name)
+
+            def V(t):
+                return oracle.nlpp(dataclasses.replace(s, **{name: b0 + t}), R[w], 3, 1, w)[0]
+            h = 1e-4
+            d1 = (V(h) - V(-h)) / (2 * h)
+            d2 = (V(2 * h) - V(-2 * h)) / (4 * h)
+            fd = (4 * d1 - d2) / 3
+            print(f"[nlpp] walker {w} {name}: {dv[p]:.12f} fd {fd:.12f}")
+            assert abs(dv[p] - fd) < 1e-8 * max(1.0, abs(fd))
+
+
+def test_nlpp_param_grads_three_body_point_by_point():
+    """The three-body directions: sum over the quadrature points, rebuilt
+    here from the icosahedron, the Legendre polynomials, ratios from full
+    evaluations of ln|Psi| and the three-body sums F_k of each moved
+    configuration (the exponent of a trial function J + c F_k moves each
+    ratio by c (F_k(R_q) - F_k(R)))."""
+    s = synth.small_molecule_pp()
+    R = synth.make_walkers(s, 1, 52)[0]
+    seed, step, w = 7, 2, 0
+    ico = _ico()
+    lp0, sg0, _, _, _ = oracle.evaluate(s, R)
+    F0 = oracle.j3_values(s, R)
+    ref = np.zeros(6)
+    for i in range(s.n_elec):
+        rot = oracle.nlpp_rotation(seed, step, w, i)
+        for A in range(s.n_atom):
+            d = R[i] - s.ion_xyz[A]
+            r = np.linalg.norm(d)
+            if not r < s.pp_rcut[A]:
+                continue
+            terms = [(l, n, b, a) for (at, l, n, b, a) in zip(s.pp_atom, s.pp_l, s.pp_n,
+                                                              s.pp_beta, s.pp_alpha) if at == A]
+            for q in range(12):
+                od = rot @ ico[q]
+                Rq = R.copy()
+                Rq[i] = s.ion_xyz[A] + r * od
+                lp, sg, _, _, _ = oracle.evaluate(s, Rq)
+                ratio = sg * sg0 * math.exp(lp - lp0)
+                f = sum(_v(terms, l, r) * (2 * l + 1) * _legendre(l, od @ d / r) for l in range(3))
+                ref += f * ratio * (oracle.j3_values(s, Rq) - F0) / 12
+    dv, rc = oracle.nlpp_param_grads(s, R, seed, step, w)
+    assert rc == 0
+    print(f"[nlpp] three-body directions {dv[2:]} point by point {ref}")
+    np.testing.assert_allclose(dv[2:], ref, rtol=1e-11, atol=1e-13)
