@@ -302,6 +302,21 @@ def pp_leg(torch, dmcx, stream, W=2048, steps=5, cpu_walkers=2):
             ctx.check(dmcx.dmcx_forces(ctx.h, F.data_ptr(), dmcx.DMCX_DEVICE))
         torch.cuda.synchronize()
         out[f"ms_per_step_with_forces_{name}_pp"] = 1e3 * (time.perf_counter() - t0) / steps
+        # the Jastrow parameter derivatives (with the pseudopotential, its
+        # non-local part too); dmcx_set_step forces a fresh evaluation
+        O = torch.empty((W, 8), dtype=torch.float64, device="cuda")
+        Dd = torch.empty((W, 8), dtype=torch.float64, device="cuda")
+        jt = []
+        for i in range(3):
+            ctx.set_step(ctx.get_step())
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ctx.check(dmcx.dmcx_jastrow_param_grads(ctx.h, O.data_ptr(), Dd.data_ptr(),
+                                                    dmcx.DMCX_DEVICE))
+            torch.cuda.synchronize()
+            if i > 0:
+                jt.append(1e3 * (time.perf_counter() - t1))
+        out[f"jastrow_param_grads_ms_{name}_pp"] = float(np.mean(jt))
         if name == "with":
             R, _ = ctx.get_walkers()
             nl = [a for a in range(s.n_atom) if np.any((s.pp_atom == a) & (s.pp_l >= 0))]

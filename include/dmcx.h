@@ -152,8 +152,10 @@ dmcx_status dmcx_get_walkers(dmcx_ctx *ctx, double *R, double *log_w, dmcx_mem m
 
 /* Step counter used as the Philox counter's step field (checkpoint/resume: a
  * run resumed with dmcx_set_walkers + dmcx_set_step at the saved step draws
- * the same random numbers as an uninterrupted one).  The paper does not fix
- * the random stream; these calls carry no physics. */
+ * the same random numbers as an uninterrupted one).  dmcx_set_step also sets
+ * the counter later evaluations outside a run take their pseudopotential
+ * quadrature rotations from (measure, ion and parameter derivatives).  The
+ * paper does not fix the random stream; these calls carry no physics. */
 dmcx_status dmcx_set_step(dmcx_ctx *ctx, int64_t step);
 dmcx_status dmcx_get_step(const dmcx_ctx *ctx, int64_t *step);
 
@@ -418,10 +420,13 @@ dmcx_status dmcx_get_trial_energy(dmcx_ctx *ctx, double *e_trial);
  * c = 0 (the trial function itself has no three-body term).
  * Per walker at the current configuration: dlogpsi[W][8] = O_p = d ln Psi/dp
  * and dEL[W][8] = dE_L/dp = -1/2 sum_i [lap_i O_p + 2 grad_i ln|Psi| . grad_i O_p]
- * (either may be NULL).  FP64 arithmetic; grad_i ln|Psi| comes from the
- * context's inverse and orbital rows (FP32 in the mixed form).  Single-
- * determinant systems without a pseudopotential only (DMCX_E_UNSUPPORTED
- * otherwise). */
+ * (either may be NULL); with a pseudopotential dEL also holds the non-local
+ * energy's part, sum over the quadrature points of (1/12) f rho
+ * (O_p(R_q) - O_p(R)) with the rotations of the current step counter (each
+ * quadrature ratio carries the Jastrow factor's change).  FP64 arithmetic;
+ * grad_i ln|Psi| and the quadrature ratios come from the context's inverse
+ * and orbital rows (FP32 in the mixed form).  Single-determinant systems only
+ * (DMCX_E_UNSUPPORTED otherwise). */
 #define DMCX_N_JASTROW_PARAMS 8
 dmcx_status dmcx_jastrow_param_grads(dmcx_ctx *ctx, double *dlogpsi, double *dEL, dmcx_mem mem);
 

@@ -17,6 +17,7 @@
 #include "forces_aux.h"
 #include "jparams.h"
 #include "pp.h"
+#include "pp_jparam.h"
 #include "kernels.h"
 #include "launch.h"
 #include "msd.h"
@@ -618,6 +619,10 @@ __global__ void k_set_run(RunState *r, unsigned long long step, int mode, double
   }
 }
 
+__global__ void k_set_step(RunState *r, unsigned long long step) {
+  if (threadIdx.x == 0) r->step = step;
+}
+
 __global__ void k_advance(RunState *r) {
   if (threadIdx.x == 0) {
     r->step += 1ull;
@@ -830,9 +835,6 @@ dmcx_status compute_zv(dmcx_ctx *c, int warp) {
 // Per-walker Jastrow parameter derivatives of the current configuration
 // (cached per configuration version) in d_jo / d_jd.
 dmcx_status compute_jparams(dmcx_ctx *c) {
-  if (c->dc.pp_n > 0)
-    return fail(c, DMCX_E_UNSUPPORTED,
-                "Jastrow parameter derivatives: the non-local energy's are not built");
   if (c->dc.M.on)
     return fail(c, DMCX_E_UNSUPPORTED,
                 "Jastrow parameter derivatives: single-determinant systems only");
@@ -854,6 +856,27 @@ dmcx_status compute_jparams(dmcx_ctx *c) {
                        c->d_jo, c->d_jd);
   }
   HIP_TRY(c, hipGetLastError());
+  if (c->dc.pp_nl > 0) {
+    // the non-local energy's part of dE_L/dp, with y_e from the current
+    // inverses (walkers may have been copied since the last energy)
+    if (!c->mixed)
+      launch_pp_y(c->NOB, c->dc, (const double *)c->dc.GT, c->d_ppY, c->pp_ldy, c->stream);
+    else
+      launch_pp_y(c->NOB, c->dc, (const float *)c->dc.GT, c->d_ppY, c->pp_ldy, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    // the table of scaled electron-atom distances in LDS when it fits
+    const size_t static_lds = NT_AUX * sizeof(int) + NT_AUX / 64 * 8 * sizeof(double);
+    int tab = 1;
+    size_t jl = pp_jp_lds_bytes(c->ne, c->dc.pp_nl, c->n_atom, true);
+    if (jl + static_lds > 160 * 1024) {
+      tab = 0;
+      jl = pp_jp_lds_bytes(c->ne, c->dc.pp_nl, c->n_atom, false);
+    }
+    HIP_TRY(c, allow_lds(k_pp_jparam, jl));
+    hipLaunchKernelGGL(k_pp_jparam, dim3(c->W), dim3(NT_AUX), jl, c->stream, c->dc,
+                       (const double *)c->d_ppY, c->pp_ldy, tab, c->d_jd);
+    HIP_TRY(c, hipGetLastError());
+  }
   c->jp_version = c->version;
   return DMCX_OK;
 }
@@ -1872,8 +1895,17 @@ dmcx_status dmcx_get_walkers(dmcx_ctx *c, double *R, double *log_w, dmcx_mem mem
 
 dmcx_status dmcx_set_step(dmcx_ctx *c, int64_t step) {
   if (!c || step < 0) return DMCX_E_INVALID;
-  for (dmcx_ctx *m : members(c)) m->step = step;
+  // the device counter too: the quadrature rotations of later evaluations
+  // (measure, ion derivatives, parameter derivatives) are those of this step
+  for (dmcx_ctx *m : members(c)) {
+    m->step = step;
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, m->stream, m->d_run,
+                       (unsigned long long)step);
+    HIP_TRY(c, hipGetLastError());
+    m->version++;
+  }
   c->step = step;
+  c->version++;
   return DMCX_OK;
 }
 

@@ -254,15 +254,68 @@ def _oracle_dv_one(s, Rw, seed, step, w):
     return dv[0] + g
 
 
+def _oracle_jparams(s, R, seed, step):
+    O, D, rc = oracle.jastrow_param_grads_batch(s, R)
+    assert rc == 0
+    for w in range(R.shape[0]):
+        dv, rc = oracle.nlpp_param_grads(s, R[w], seed, step, w)
+        assert rc == 0
+        D[w] += dv
+    return O, D
+
+
+def _medium_pp():
+    base = synth.small_random_system(431, n_atom=10, n_up=14, n_dn=13, shells=(0, 0, 1, 2),
+                                     nprim=2, box=7.0, charge=2.7)
+    return synth.with_pseudopotential(base, [synth.PP_SMALL if a % 2 == 0 else []
+                                             for a in range(10)])
+
+
+@pytest.mark.parametrize("mol", ["small", "medium"])
+def test_jastrow_param_grads_with_pseudopotential(mol):
+    """dE_L/dp with the non-local energy's part (each quadrature ratio
+    carries the Jastrow factor's change) against the oracle's kinetic part
+    plus its pseudopotential part, at set-up (rotations of the step set by
+    dmcx_set_step) and after DMC steps; the linear-method matrices built on
+    them are finite."""
+    s = synth.small_molecule_pp() if mol == "small" else _medium_pp()
+    W, seed = 6, 61
+    R = synth.make_walkers(s, W, 3410)
+    ctx = dmcx.Context(s, W, seed=seed, delay_rank=2, recompute_period=3)
+    ctx.set_walkers(R)
+    ctx.set_step(3)
+    O, D = ctx.jastrow_param_grads()
+    O_o, D_o = _oracle_jparams(s, R, seed, 3)
+    _close(O, O_o, rel=1e-12, label="O_p with pseudopotential")
+    _close(D, D_o, rel=1e-10, label="dE_L/dp with pseudopotential")
+    ctx.run(2, mode=dmcx.DMCX_DMC, e_trial=-10.0)
+    Rg, _ = ctx.get_walkers()
+    step = ctx.get_step()
+    O, D = ctx.jastrow_param_grads()
+    O_o, D_o = _oracle_jparams(s, Rg, seed, step)
+    _close(D, D_o, rel=1e-10, label="dE_L/dp with pseudopotential after steps")
+    S, H = ctx.linear_method()
+    assert np.all(np.isfinite(S)) and np.all(np.isfinite(H))
+
+
+def test_jastrow_param_grads_with_pseudopotential_mixed():
+    s = synth.small_molecule_pp()
+    W, seed = 6, 62
+    R = synth.make_walkers(s, W, 3411)
+    ctx = dmcx.Context(s, W, precision=dmcx.DMCX_MIXED, seed=seed)
+    ctx.set_walkers(R)
+    ctx.set_step(4)
+    _, D = ctx.jastrow_param_grads()
+    _, D_o = _oracle_jparams(s, R, seed, 4)
+    _close(D, D_o, rel=1e-4, label="dE_L/dp with pseudopotential, mixed")
+
+
 def test_unsupported_with_pseudopotential():
     s = synth.small_molecule_pp()
     ctx = dmcx.Context(s, 8)
     ctx.set_walkers(synth.make_walkers(s, 8, 1))
     with pytest.raises(dmcx.DmcxError) as e:
         ctx.zv_grads(warp=True)
-    assert e.value.status == dmcx.DMCX_E_UNSUPPORTED
-    with pytest.raises(dmcx.DmcxError) as e:
-        ctx.jastrow_param_grads()
     assert e.value.status == dmcx.DMCX_E_UNSUPPORTED
     base = synth.small_random_system(77, n_atom=2, n_up=3, n_dn=3, shells=(0, 0, 1, 2), nprim=2,
                                      n_mo=10)
