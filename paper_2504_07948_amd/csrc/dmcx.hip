@@ -864,11 +864,12 @@ dmcx_status compute_jparams(dmcx_ctx *c) {
     else
       launch_pp_y(c->NOB, c->dc, (const float *)c->dc.GT, c->d_ppY, c->pp_ldy, c->stream);
     HIP_TRY(c, hipGetLastError());
-    // the table of scaled electron-atom distances in LDS when it fits
+    // the table of scaled electron-atom distances in LDS when two workgroups
+    // still fit on a CU (occupancy matters more than the square roots it saves)
     const size_t static_lds = NT_AUX * sizeof(int) + NT_AUX / 64 * 8 * sizeof(double);
     int tab = 1;
     size_t jl = pp_jp_lds_bytes(c->ne, c->dc.pp_nl, c->n_atom, true);
-    if (jl + static_lds > 160 * 1024) {
+    if (jl + static_lds > 80 * 1024) {
       tab = 0;
       jl = pp_jp_lds_bytes(c->ne, c->dc.pp_nl, c->n_atom, false);
     }

@@ -16,116 +16,188 @@
 
 namespace dmcx {
 
-// The terms of the eight directions that involve electron e placed at pos
-// (the other electrons at s_r).  s_y: [ne][na] table of s(|r_j - R_A|), or
-// null to compute it in place.
-__device__ inline void pp_dir_terms(const DevCtx &c, const double *s_r, const double *s_y, int e,
-                                    const double pos[3], double o[8]) {
-  const int ne = c.ne, na = c.n_atom;
+// The Pade directions' terms of electron e placed at pos (the other
+// electrons at s_r): sum_{j != e} dU_ee/db and sum_A dU_en/db.
+__device__ inline void pp_dir_pade(const DevCtx &c, const double *s_r, int e, const double pos[3],
+                                   double &o0, double &o1) {
   const bool up = e < c.n_up;
-  for (int k = 0; k < 8; ++k) o[k] = 0.0;
   double h, h1, h2;
-  for (int j = 0; j < ne; ++j) {
+  o0 = o1 = 0.0;
+  for (int j = 0; j < c.ne; ++j) {
     if (j == e) continue;
     const double dx = pos[0] - s_r[3 * j], dy = pos[1] - s_r[3 * j + 1], dz = pos[2] - s_r[3 * j + 2];
     pade_db(((j < c.n_up) == up) ? c.jee_para : c.jee_anti, c.jee_b,
             sqrt(dx * dx + dy * dy + dz * dz), h, h1, h2);
-    o[0] += h;
+    o0 += h;
   }
-  for (int A = 0; A < na; ++A) {
+  for (int A = 0; A < c.n_atom; ++A) {
     const double *RA = c.ion + 3 * A;
     const double dx = pos[0] - RA[0], dy = pos[1] - RA[1], dz = pos[2] - RA[2];
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    pade_db(c.jen_a[A], c.jen_b, r, h, h1, h2);
-    o[1] += h;
-    const double x = r / (1.0 + r), x2 = x * x;
-    for (int j = 0; j < ne; ++j) {
-      if (j == e) continue;
-      double y;
-      if (s_y) {
-        y = s_y[j * na + A];
-      } else {
-        const double ax = s_r[3 * j] - RA[0], ay = s_r[3 * j + 1] - RA[1], az = s_r[3 * j + 2] - RA[2];
-        const double ry = sqrt(ax * ax + ay * ay + az * az);
-        y = ry / (1.0 + ry);
-      }
-      const double bx = pos[0] - s_r[3 * j], by = pos[1] - s_r[3 * j + 1], bz = pos[2] - s_r[3 * j + 2];
-      const double rz = sqrt(bx * bx + by * by + bz * bz);
-      const double z = rz / (1.0 + rz);
-      // (l, m, n) = (1,1,0), (1,0,1), (1,1,1), (2,1,0), (2,0,1), (1,0,2)
-      const double xy = x * y, xpy = x + y;
-      o[2] += 2.0 * xy;
-      o[3] += xpy * z;
-      o[4] += 2.0 * xy * z;
-      o[5] += xy * xpy;
-      o[6] += (x2 + y * y) * z;
-      o[7] += xpy * z * z;
-    }
+    pade_db(c.jen_a[A], c.jen_b, sqrt(dx * dx + dy * dy + dz * dz), h, h1, h2);
+    o1 += h;
   }
 }
 
+// s(|r_j - R_A|) from the LDS table (atom-major, so the lanes of a wave, one
+// per electron j, read consecutive entries), or computed in place without one.
+__device__ __forceinline__ double pp_sy(const DevCtx &c, const double *s_r, const double *s_y,
+                                        int j, int A) {
+  if (s_y) return s_y[A * c.ne + j];
+  const double *RA = c.ion + 3 * A;
+  const double ax = s_r[3 * j] - RA[0], ay = s_r[3 * j + 1] - RA[1], az = s_r[3 * j + 2] - RA[2];
+  const double r = sqrt(ax * ax + ay * ay + az * az);
+  return r / (1.0 + r);
+}
+
+// The six three-body terms (l, m, n) = (1,1,0), (1,0,1), (1,1,1), (2,1,0),
+// (2,0,1), (1,0,2) of one (x, y, z), added with weight wt.
+__device__ __forceinline__ void pp_j3_add(double x, double y, double z, double wt, double a[6]) {
+  const double xy = x * y, xpy = x + y, wz = wt * z;
+  a[0] += wt * 2.0 * xy;
+  a[1] += wz * xpy;
+  a[2] += wz * 2.0 * xy;
+  a[3] += wt * xy * xpy;
+  a[4] += wz * (x * x + y * y);
+  a[5] += wz * z * xpy;
+}
+
+constexpr int PPJ_CHUNK = 16;  // pairs per round (their 192 points, one per lane)
+
+// Dynamic LDS: the set-up block (positions, rotations, J sums, pair list),
+// each electron's own terms [ne][8], the round's points and weights
+// [PPJ_CHUNK * 12][4], each wave's s(|p_q - R_A|) [4][12][na], and the
+// table s(|r_j - R_A|) [na][ne] when tab.
 inline size_t pp_jp_lds_bytes(int ne, int n_nl, int na, bool tab) {
   const int cap = ne * (n_nl < PP_MAXA ? n_nl : PP_MAXA);
-  return (size_t)ne * 13 * sizeof(double) + (size_t)((cap + 1) / 2) * sizeof(double) +
-         (size_t)ne * 8 * sizeof(double) + (tab ? (size_t)ne * na * sizeof(double) : 0);
+  return ((size_t)ne * 13 + (size_t)(cap + 1) / 2 + (size_t)ne * 8 + PPJ_CHUNK * 12 * 4 +
+          (size_t)(NT_AUX / 64) * 12 * na + (tab ? (size_t)ne * na : 0)) * sizeof(double);
 }
 
 // grid W, block NT_AUX (>= ne), dynamic LDS pp_jp_lds_bytes(ne, n_nl, na, tab).
 // Adds dV_NL/dp into D[w][8]; a walker whose pairs exceed the list gets NaN.
-// Sums in a fixed order (per lane over its points, then the waves in order).
+// Rounds of PPJ_CHUNK pairs: one lane per point forms its weight
+// f rho / 12 (the quadrature ratio as k_pp) and the Pade directions' change;
+// then each wave takes whole pairs, one lane per other electron j, and sums
+// the three-body terms of the pair's 12 points over the atoms (the points'
+// atom distances staged per wave in LDS).  Each electron's own three-body
+// terms are formed once, the same way.  Sums in a fixed order (each lane
+// over its terms, then the lanes of a wave, then the waves in order).
 __global__ __launch_bounds__(NT_AUX) void k_pp_jparam(DevCtx c, const double *Y, int ldy, int tab,
                                                      double *D) {
   extern __shared__ double sm[];
   __shared__ int s_cnt[NT_AUX];
   __shared__ double red[NT_AUX / 64][8];
   const int ne = c.ne, na = c.n_atom, w = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
   const double *s_r = sm, *s_rot = sm + 3 * ne, *s_J = sm + 12 * ne;
   const int *s_pair = (const int *)(sm + 13 * ne);
   const int cap = ne * (c.pp_nl < PP_MAXA ? c.pp_nl : PP_MAXA);
-  double *s_old = sm + 13 * ne + (cap + 1) / 2;  // [ne][8] each electron's terms where it is
-  double *s_y = tab ? s_old + 8 * ne : nullptr;  // [ne][na]
+  double *s_old = sm + 13 * ne + (cap + 1) / 2;  // [ne][8]: Pade (0, 1), three-body (2..7)
+  double *s_pw = s_old + 8 * ne;                 // [PPJ_CHUNK * 12][4]: point, weight
+  double *s_xa = s_pw + PPJ_CHUNK * 12 * 4;      // [waves][12][na]
+  double *s_y = tab ? s_xa + (NT_AUX / 64) * 12 * na : nullptr;  // [na][ne]
   bool over;
   double e_unused;
   const int npair = pp_setup(c, w, sm, s_cnt, over, e_unused);
   if (s_y)
     for (int i = tid; i < ne * na; i += NT_AUX) {
-      const int j = i / na, A = i - j * na;
+      const int A = i / ne, j = i - A * ne;
       const double *RA = c.ion + 3 * A;
       const double ax = s_r[3 * j] - RA[0], ay = s_r[3 * j + 1] - RA[1], az = s_r[3 * j + 2] - RA[2];
       const double r = sqrt(ax * ax + ay * ay + az * az);
       s_y[i] = r / (1.0 + r);
     }
   __syncthreads();
-  if (tid < ne && !over) {
-    // electrons with listed pairs only (the others are not moved)
-    const bool has = (tid == 0 ? s_cnt[0] : s_cnt[tid] - s_cnt[tid - 1]) > 0;
-    if (has) pp_dir_terms(c, s_r, s_y, tid, s_r + 3 * tid, s_old + 8 * tid);
-  }
-  __syncthreads();
   double acc[8];
   for (int k = 0; k < 8; ++k) acc[k] = 0.0;
   if (!over) {
-    for (int p = tid; p < npair * 12; p += NT_AUX) {
-      const PPPoint P = pp_point(c, s_r, s_rot, s_pair[p / 12], p % 12);
-      const double rdet = basis_dot(c.B, P.p, Y + ((size_t)w * ne + P.e) * ldy);
-      const double ratio = rdet * exp(jastrow_at(c, s_r, P.e, P.p) - s_J[P.e]);
-      double vl[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int t = 0; t < c.pp_n; ++t) {
-        const int4 tt = c.pp_t[t];
-        if (tt.x == P.A && tt.y >= 0) vl[tt.y] += pp_term(tt.z, c.pp_ba[t].x, c.pp_ba[t].y, P.r);
+    // each electron's own terms where it is (electrons with listed pairs)
+    if (tid < ne && (tid == 0 ? s_cnt[0] : s_cnt[tid] - s_cnt[tid - 1]) > 0)
+      pp_dir_pade(c, s_r, tid, s_r + 3 * tid, s_old[8 * tid], s_old[8 * tid + 1]);
+    for (int e = wv; e < ne; e += NT_AUX / 64) {
+      if ((e == 0 ? s_cnt[0] : s_cnt[e] - s_cnt[e - 1]) == 0) continue;  // wave-uniform
+      double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int j = lane; j < ne; j += 64) {
+        if (j == e) continue;
+        const double bx = s_r[3 * e] - s_r[3 * j], by = s_r[3 * e + 1] - s_r[3 * j + 1],
+                     bz = s_r[3 * e + 2] - s_r[3 * j + 2];
+        const double rz = sqrt(bx * bx + by * by + bz * bz), z = rz / (1.0 + rz);
+        for (int A = 0; A < na; ++A)
+          pp_j3_add(pp_sy(c, s_r, s_y, e, A), pp_sy(c, s_r, s_y, j, A), z, 1.0, a);
       }
-      double f = 0.0;
+      for (int k = 0; k < 6; ++k) {
+        const double t = sum64(a[k]);
+        if (lane == 0) s_old[8 * e + 2 + k] = t;
+      }
+    }
+  }
+  __syncthreads();
+  if (!over) {
+    for (int p0 = 0; p0 < npair; p0 += PPJ_CHUNK) {
+      const int np = min(PPJ_CHUNK, npair - p0);
+      // one lane per point: its weight, the Pade change, minus the
+      // electron's own three-body terms times the weight
+      if (tid < np * 12) {
+        const PPPoint P = pp_point(c, s_r, s_rot, s_pair[p0 + tid / 12], tid % 12);
+        const double rdet = basis_dot(c.B, P.p, Y + ((size_t)w * ne + P.e) * ldy);
+        const double ratio = rdet * exp(jastrow_at(c, s_r, P.e, P.p) - s_J[P.e]);
+        double vl[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < c.pp_n; ++t) {
+          const int4 tt = c.pp_t[t];
+          if (tt.x == P.A && tt.y >= 0) vl[tt.y] += pp_term(tt.z, c.pp_ba[t].x, c.pp_ba[t].y, P.r);
+        }
+        double f = 0.0;
 #pragma unroll
-      for (int l = 0; l < 4; ++l) f += vl[l] * (2 * l + 1) * legendre_pl(l, P.cth);
-      const double wt = f * ratio * (1.0 / 12.0);
-      double o[8];
-      pp_dir_terms(c, s_r, s_y, P.e, P.p, o);
-      for (int k = 0; k < 8; ++k) acc[k] += wt * (o[k] - s_old[8 * P.e + k]);
+        for (int l = 0; l < 4; ++l) f += vl[l] * (2 * l + 1) * legendre_pl(l, P.cth);
+        const double wt = f * ratio * (1.0 / 12.0);
+        double o0, o1;
+        pp_dir_pade(c, s_r, P.e, P.p, o0, o1);
+        acc[0] += wt * (o0 - s_old[8 * P.e]);
+        acc[1] += wt * (o1 - s_old[8 * P.e + 1]);
+        for (int k = 0; k < 6; ++k) acc[2 + k] -= wt * s_old[8 * P.e + 2 + k];
+        for (int x = 0; x < 3; ++x) s_pw[4 * tid + x] = P.p[x];
+        s_pw[4 * tid + 3] = wt;
+      }
+      __syncthreads();
+      // one wave per pair, one lane per other electron
+      double *xa = s_xa + (size_t)wv * 12 * na;
+      for (int pl = wv; pl < np; pl += NT_AUX / 64) {
+        const int e = s_pair[p0 + pl] & 0xffff;
+        const double *pw = s_pw + 4 * 12 * pl;
+        for (int i = lane; i < 12 * na; i += 64) {
+          const int q = i / na, A = i - q * na;
+          const double *RA = c.ion + 3 * A;
+          const double dx = pw[4 * q] - RA[0], dy = pw[4 * q + 1] - RA[1], dz = pw[4 * q + 2] - RA[2];
+          const double r = sqrt(dx * dx + dy * dy + dz * dz);
+          xa[i] = r / (1.0 + r);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // this wave's LDS writes are visible to its lanes
+        for (int j = lane; j < ne; j += 64) {
+          if (j == e) continue;
+          double zq[12], wq[12];
+#pragma unroll
+          for (int q = 0; q < 12; ++q) {
+            const double bx = pw[4 * q] - s_r[3 * j], by = pw[4 * q + 1] - s_r[3 * j + 1],
+                         bz = pw[4 * q + 2] - s_r[3 * j + 2];
+            const double rz = sqrt(bx * bx + by * by + bz * bz);
+            zq[q] = rz / (1.0 + rz);
+            wq[q] = pw[4 * q + 3];
+          }
+          for (int A = 0; A < na; ++A) {
+            const double y = pp_sy(c, s_r, s_y, j, A);
+#pragma unroll
+            for (int q = 0; q < 12; ++q) pp_j3_add(xa[q * na + A], y, zq[q], wq[q], acc + 2);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      __syncthreads();
     }
   }
   for (int k = 0; k < 8; ++k) {
     const double v = sum64(acc[k]);
-    if ((tid & 63) == 0) red[tid >> 6][k] = v;
+    if (lane == 0) red[wv][k] = v;
   }
   __syncthreads();
   if (tid < 8) {
