@@ -442,6 +442,8 @@ class Context:
         return R, lw
 
     def set_step(self, step):
+        """Set the step counter (the Philox step field of later draws, and
+        the pseudopotential rotations of evaluations outside a run)."""
         self.check(dmcx_set_step(self.h, step))
 
     def run(self, n_steps, mode=DMCX_DMC, e_trial=0.0, logs=False):
@@ -551,7 +553,9 @@ class Context:
 
     def jastrow_param_grads(self):
         """Per walker (d ln Psi/dp, dE_L/dp) [W][8] each for the Jastrow
-        parameters (e-e Pade b, e-n Pade b, six three-body coefficients)."""
+        parameters (e-e Pade b, e-n Pade b, six three-body coefficients);
+        with a pseudopotential dE_L/dp includes the non-local energy's part
+        (rotations of the current step counter)."""
         O = np.zeros((self.W, DMCX_N_JASTROW_PARAMS))
         D = np.zeros((self.W, DMCX_N_JASTROW_PARAMS))
         self.check(load().dmcx_jastrow_param_grads(self.h, _ptr(O), _ptr(D), DMCX_HOST))
