@@ -213,3 +213,28 @@ def test_calls_after_growth_match_a_fresh_context():
     S_f, H_f = fresh.linear_method()
     _close(S, S_f, rel=1e-11)
     _close(H, H_f, rel=1e-11)
+
+
+@pytest.mark.parametrize("case", ["one", "full"])
+def test_branch_to_one_walker_and_to_capacity(case):
+    """The extremes: one walker left (every other weight zero), and the
+    population filling the capacity exactly (every walker doubled, W' a
+    multiple of the 8-walker tile so no padding copy runs); the next DMC step
+    against the oracle run from the laid-out positions."""
+    s = synth.small_molecule()
+    cap, W0, tau, seed, et = 24, 12, 0.02, 17, -8.0
+    ctx = dmcx.Context(s, cap, delay_rank=2, recompute_period=4, tau=tau, seed=seed)
+    ctx.set_walker_count(W0)
+    R = synth.make_walkers(s, W0, 541)
+    if case == "one":
+        lw = np.full(W0, -np.inf)
+        lw[7] = 0.0
+    else:
+        lw = np.full(W0, np.log(2.0))
+    R2 = _branch_and_check(ctx, s, R, lw, 5, seed, cap)
+    assert R2.shape[0] == (1 if case == "one" else cap)
+    acc, el = ctx.run(1, mode=dmcx.DMCX_DMC, e_trial=et, logs=True)
+    ref = oracle.run(s, R2, log_w=np.zeros(R2.shape[0]), step0=5, n_steps=1, mode=1, tau=tau,
+                     seed=seed, e_trial=et)
+    np.testing.assert_array_equal(acc, ref["accept_log"])
+    _close(el, ref["e_log"])
