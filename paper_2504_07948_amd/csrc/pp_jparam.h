@@ -65,12 +65,13 @@ constexpr int PPJ_CHUNK = 16;  // pairs per round (their 192 points, one per lan
 
 // Dynamic LDS: the set-up block (positions, rotations, J sums, pair list),
 // each electron's own terms [ne][8], the round's points and weights
-// [PPJ_CHUNK * 12][4], each wave's s(|p_q - R_A|) [4][12][na], and the
+// [PPJ_CHUNK * 12][4], each wave's s(|p_q - R_A|) [12][na] and point sums
+// [12][2], and the
 // table s(|r_j - R_A|) [na][ne] when tab.
 inline size_t pp_jp_lds_bytes(int ne, int n_nl, int na, bool tab) {
   const int cap = ne * (n_nl < PP_MAXA ? n_nl : PP_MAXA);
   return ((size_t)ne * 13 + (size_t)(cap + 1) / 2 + (size_t)ne * 8 + PPJ_CHUNK * 12 * 4 +
-          (size_t)(NT_AUX / 64) * 12 * na + (tab ? (size_t)ne * na : 0)) * sizeof(double);
+          (size_t)(NT_AUX / 64) * (12 * na + 24) + (tab ? (size_t)ne * na : 0)) * sizeof(double);
 }
 
 // grid W, block NT_AUX (>= ne), dynamic LDS pp_jp_lds_bytes(ne, n_nl, na, tab).
@@ -78,8 +79,9 @@ inline size_t pp_jp_lds_bytes(int ne, int n_nl, int na, bool tab) {
 // Rounds of PPJ_CHUNK pairs: one lane per point forms its weight
 // f rho / 12 (the quadrature ratio as k_pp) and the Pade directions' change;
 // then each wave takes whole pairs, one lane per other electron j, and sums
-// the three-body terms of the pair's 12 points over the atoms (the points'
-// atom distances staged per wave in LDS).  Each electron's own three-body
+// the three-body terms of the pair's 12 points over the atoms, factored into
+// sums of one point, of one electron and three cross sums (the points' atom
+// distances staged per wave in LDS).  Each electron's own three-body
 // terms are formed once, the same way.  Sums in a fixed order (each lane
 // over its terms, then the lanes of a wave, then the waves in order).
 __global__ __launch_bounds__(NT_AUX) void k_pp_jparam(DevCtx c, const double *Y, int ldy, int tab,
@@ -94,8 +96,8 @@ __global__ __launch_bounds__(NT_AUX) void k_pp_jparam(DevCtx c, const double *Y,
   const int cap = ne * (c.pp_nl < PP_MAXA ? c.pp_nl : PP_MAXA);
   double *s_old = sm + 13 * ne + (cap + 1) / 2;  // [ne][8]: Pade (0, 1), three-body (2..7)
   double *s_pw = s_old + 8 * ne;                 // [PPJ_CHUNK * 12][4]: point, weight
-  double *s_xa = s_pw + PPJ_CHUNK * 12 * 4;      // [waves][12][na]
-  double *s_y = tab ? s_xa + (NT_AUX / 64) * 12 * na : nullptr;  // [na][ne]
+  double *s_xa = s_pw + PPJ_CHUNK * 12 * 4;      // [waves][12 na + 24]
+  double *s_y = tab ? s_xa + (NT_AUX / 64) * (12 * na + 24) : nullptr;  // [na][ne]
   bool over;
   double e_unused;
   const int npair = pp_setup(c, w, sm, s_cnt, over, e_unused);
@@ -159,8 +161,15 @@ __global__ __launch_bounds__(NT_AUX) void k_pp_jparam(DevCtx c, const double *Y,
         s_pw[4 * tid + 3] = wt;
       }
       __syncthreads();
-      // one wave per pair, one lane per other electron
-      double *xa = s_xa + (size_t)wv * 12 * na;
+      // one wave per pair, one lane per other electron.  Over the atoms the
+      // six terms factor into sums of one point (S1_q = sum_A x, S2_q =
+      // sum_A x^2), of one electron (Y1 = sum_A y, Y2 = sum_A y^2) and the
+      // cross sums C^{ab}_q = sum_A x^a y^b, (a, b) = (1,1), (2,1), (1,2):
+      //   2xy -> 2 C11, (x+y)z -> z (S1 + Y1), 2xyz -> 2 z C11,
+      //   x^2 y + x y^2 -> C21 + C12, (x^2+y^2)z -> z (S2 + Y2),
+      //   (x+y)z^2 -> z^2 (S1 + Y1).
+      double *xa = s_xa + (size_t)wv * (12 * na + 24);
+      double *s12 = xa + 12 * na;  // [12][2]: S1_q, S2_q
       for (int pl = wv; pl < np; pl += NT_AUX / 64) {
         const int e = s_pair[p0 + pl] & 0xffff;
         const double *pw = s_pw + 4 * 12 * pl;
@@ -173,21 +182,49 @@ __global__ __launch_bounds__(NT_AUX) void k_pp_jparam(DevCtx c, const double *Y,
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_s_waitcnt(0xC07F);  // this wave's LDS writes are visible to its lanes
+        if (lane < 12) {
+          double a1 = 0.0, a2 = 0.0;
+          for (int A = 0; A < na; ++A) {
+            const double x = xa[lane * na + A];
+            a1 += x;
+            a2 += x * x;
+          }
+          s12[2 * lane] = a1;
+          s12[2 * lane + 1] = a2;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_s_waitcnt(0xC07F);
         for (int j = lane; j < ne; j += 64) {
           if (j == e) continue;
-          double zq[12], wq[12];
+          double c11[12], c21[12], c12[12];
+#pragma unroll
+          for (int q = 0; q < 12; ++q) c11[q] = c21[q] = c12[q] = 0.0;
+          double y1 = 0.0, y2 = 0.0;
+          for (int A = 0; A < na; ++A) {
+            const double y = pp_sy(c, s_r, s_y, j, A), yy = y * y;
+            y1 += y;
+            y2 += yy;
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+              const double x = xa[q * na + A], xy = x * y;
+              c11[q] += xy;
+              c21[q] += x * xy;
+              c12[q] += x * yy;
+            }
+          }
 #pragma unroll
           for (int q = 0; q < 12; ++q) {
             const double bx = pw[4 * q] - s_r[3 * j], by = pw[4 * q + 1] - s_r[3 * j + 1],
                          bz = pw[4 * q + 2] - s_r[3 * j + 2];
-            const double rz = sqrt(bx * bx + by * by + bz * bz);
-            zq[q] = rz / (1.0 + rz);
-            wq[q] = pw[4 * q + 3];
-          }
-          for (int A = 0; A < na; ++A) {
-            const double y = pp_sy(c, s_r, s_y, j, A);
-#pragma unroll
-            for (int q = 0; q < 12; ++q) pp_j3_add(xa[q * na + A], y, zq[q], wq[q], acc + 2);
+            const double rz = sqrt(bx * bx + by * by + bz * bz), z = rz / (1.0 + rz);
+            const double wt = pw[4 * q + 3], wz = wt * z;
+            const double sy1 = s12[2 * q] + y1, sy2 = s12[2 * q + 1] + y2;
+            acc[2] += wt * 2.0 * c11[q];
+            acc[3] += wz * sy1;
+            acc[4] += wz * 2.0 * c11[q];
+            acc[5] += wt * (c21[q] + c12[q]);
+            acc[6] += wz * sy2;
+            acc[7] += wz * z * sy1;
           }
         }
         __builtin_amdgcn_wave_barrier();
