@@ -66,8 +66,7 @@ constexpr int PPJ_CHUNK = 16;  // pairs per round (their 192 points, one per lan
 // Dynamic LDS: the set-up block (positions, rotations, J sums, pair list),
 // each electron's own terms [ne][8], the round's points and weights
 // [PPJ_CHUNK * 12][4], each wave's s(|p_q - R_A|) [12][na] and point sums
-// [12][2], and the
-// table s(|r_j - R_A|) [na][ne] when tab.
+// [12][2], and the table s(|r_j - R_A|) [na][ne] when tab.
 inline size_t pp_jp_lds_bytes(int ne, int n_nl, int na, bool tab) {
   const int cap = ne * (n_nl < PP_MAXA ? n_nl : PP_MAXA);
   return ((size_t)ne * 13 + (size_t)(cap + 1) / 2 + (size_t)ne * 8 + PPJ_CHUNK * 12 * 4 +
@@ -82,7 +81,8 @@ inline size_t pp_jp_lds_bytes(int ne, int n_nl, int na, bool tab) {
 // the three-body terms of the pair's 12 points over the atoms, factored into
 // sums of one point, of one electron and three cross sums (the points' atom
 // distances staged per wave in LDS).  Each electron's own three-body
-// terms are formed once, the same way.  Sums in a fixed order (each lane
+// terms are formed once, a wave per electron and a lane per other electron.
+// Sums in a fixed order (each lane
 // over its terms, then the lanes of a wave, then the waves in order).
 __global__ __launch_bounds__(NT_AUX) void k_pp_jparam(DevCtx c, const double *Y, int ldy, int tab,
                                                      double *D) {
