@@ -392,6 +392,12 @@ dmcx_status dmcx_estimators_noalloc(int32_t n_walkers, const double *log_w, cons
  * 1e-4 Ha per electron (Eq. 2 trial function, E_L of Eq. 3 form).  0 for the
  * other forms.  Synchronises the context's stream. */
 dmcx_status dmcx_energy_escalations(dmcx_ctx *ctx, int32_t *n);
+/* The bound of those re-evaluations, in Ha per electron (default 1e-4; 0
+ * re-evaluates every walker with a finite E_L, which makes every E_L the
+ * FP64 rows' and inverse's).  Applies to later energy evaluations of the
+ * mixed form with its FP64 energy; no effect on the other forms.  Errors:
+ * DMCX_E_INVALID (negative or non-finite cap). */
+dmcx_status dmcx_set_energy_escalation_cap(dmcx_ctx *ctx, double cap);
 
 /* Passage: QMC section, Eq. 1 (the trial energy E_T of the projection) and
  * the population control its weights need (not fixed by the paper).

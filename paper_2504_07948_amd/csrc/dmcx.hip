@@ -63,6 +63,7 @@ struct dmcx_ctx {
   // mixed form with its energy in FP64: every step ends with FP64 value rows,
   // an FP64 inverse and E_L from that inverse (single-determinant systems)
   bool fp64e = false;
+  double esc_cap = ESC_CAP;  // fp64e: bound per electron above which E_L is recomputed
   double *d_A64 = nullptr;  // [Wpad][ne][NP] FP64 orbital values (fp64e)
   double *d_G64 = nullptr;  // [Wpad][2][NP][NP] FP64 inverses, GT layout (fp64e)
   // walkers whose energy is re-evaluated with FP64 derivative rows (fp64e)
@@ -578,7 +579,7 @@ dmcx_status launch_local_energy(dmcx_ctx *c, int measure_only, double *e_log = n
   }
   EscList esc{};
   if (c->fp64e) {
-    esc = EscList{1, c->d_esc_count, c->d_esc_list, c->d_esc_gl, ESC_CAP};
+    esc = EscList{1, c->d_esc_count, c->d_esc_list, c->d_esc_gl, c->esc_cap};
     hipLaunchKernelGGL(k_esc_reset, dim3(1), dim3(64), 0, c->stream, c->d_esc_count);
   }
   if (c->dc.M.on) {
@@ -2406,6 +2407,19 @@ dmcx_status dmcx_linear_method(dmcx_ctx *c, double *S, double *H, dmcx_mem mem) 
   HIP_TRY(c, hipGetLastError());
   if ((st = copy_out(c, S, c->d_lm, NM * sizeof(double), mem))) return st;
   return copy_out(c, H, c->d_lm + NM, NM * sizeof(double), mem);
+}
+
+dmcx_status dmcx_set_energy_escalation_cap(dmcx_ctx *c, double cap) {
+  if (!c || !(cap >= 0.0) || !std::isfinite(cap)) return DMCX_E_INVALID;
+  for (dmcx_ctx *m : members(c)) {
+    m->esc_cap = cap;
+    m->dc_version++;  // captured steps carry the bound
+    m->version++;
+  }
+  c->esc_cap = cap;
+  c->dc_version++;
+  c->version++;
+  return DMCX_OK;
 }
 
 dmcx_status dmcx_set_et_feedback(dmcx_ctx *c, double gain) {

@@ -1131,50 +1131,56 @@ __global__ __launch_bounds__(NTE) void k_local_energy(DevCtx c, int measure_only
 
 // FP64 orbital VGL of the listed walkers' electrons (TW per tile), contracted
 // with their FP64 inverses into g_i = sum_j grad phi_j(r_i) G_ji and
-// l_i = sum_j lap phi_j(r_i) G_ji: gl[slot][e][4].  grid: Wpad * ceil(ne / TW)
-// tiles; tiles past the listed walkers return at once.
+// l_i = sum_j lap phi_j(r_i) G_ji: gl[slot][e][4].  grid: G * ceil(ne / TW)
+// blocks; block b takes tile b % ntile of the slots b / ntile, + G, + 2G, ...
+// up to the listed count (a few hundred blocks, not one per walker: the list
+// is short and most blocks would only read the count).
 template <int NOB>
 __global__ __launch_bounds__(NT_TILE) void k_escalate_gl(DevCtx c, const double *G64, EscList esc) {
   constexpr int NP = NOB * 16;
   constexpr int FM = 4 * stage_ksteps(NOB);
   const int ntile = (c.ne + TW - 1) / TW;
-  const int slot = blockIdx.x / ntile, tile = blockIdx.x % ntile;
-  if (slot >= *esc.count) return;  // whole block
+  const int ngrp = gridDim.x / ntile, tile = blockIdx.x % ntile;
+  const int count = *esc.count;
+  if ((int)blockIdx.x / ntile >= count) return;  // whole block
   extern __shared__ __align__(16) char smem_basis[];
   const BasisLDS BL = stage_basis_lds(c.B, smem_basis);
   __shared__ double Bs0[FM * NCOL], Bs1[FM * NCOL];
   __shared__ double out[TW * 5 * NP];
   __shared__ double pts[TW][3];
-  const int w = esc.list[slot];
   const int e0 = tile * TW;
-  if (threadIdx.x < TW * 3) {
-    const int e = min(e0 + (int)threadIdx.x / 3, c.ne - 1);
-    pts[threadIdx.x / 3][threadIdx.x % 3] = c.R[((size_t)w * c.ne + e) * 3 + threadIdx.x % 3];
-  }
-  __syncthreads();
-  mo_tile<double, NOB>(c, BL, pts, Bs0, Bs1, out);
-  const int ws = wave_id(), t = threadIdx.x & 63;
-  const int e = e0 + ws;
-  if (e < c.ne) {
-    const int sp = e < c.n_up ? 0 : 1, ii = e - sp * c.n_up;
-    const double *gc = G64 + gt_off(c, w, sp) + (size_t)ii * NP;
-    const double *o = out + ws * 5 * NP;
-    double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0;
-    for (int j = t; j < NP; j += 64) {
-      const double gj = gc[j];
-      g0 += o[NP + j] * gj;
-      g1 += o[2 * NP + j] * gj;
-      g2 += o[3 * NP + j] * gj;
-      l += o[4 * NP + j] * gj;
+  for (int slot = blockIdx.x / ntile; slot < count; slot += ngrp) {
+    const int w = esc.list[slot];
+    if (threadIdx.x < TW * 3) {
+      const int e = min(e0 + (int)threadIdx.x / 3, c.ne - 1);
+      pts[threadIdx.x / 3][threadIdx.x % 3] = c.R[((size_t)w * c.ne + e) * 3 + threadIdx.x % 3];
     }
-    g0 = sum64(g0); g1 = sum64(g1); g2 = sum64(g2); l = sum64(l);
-    if (t == 0) {
-      double *dst = (double *)esc.gl + ((size_t)slot * c.ne + e) * 4;
-      dst[0] = g0;
-      dst[1] = g1;
-      dst[2] = g2;
-      dst[3] = l;
+    __syncthreads();
+    mo_tile<double, NOB>(c, BL, pts, Bs0, Bs1, out);
+    const int ws = wave_id(), t = threadIdx.x & 63;
+    const int e = e0 + ws;
+    if (e < c.ne) {
+      const int sp = e < c.n_up ? 0 : 1, ii = e - sp * c.n_up;
+      const double *gc = G64 + gt_off(c, w, sp) + (size_t)ii * NP;
+      const double *o = out + ws * 5 * NP;
+      double g0 = 0.0, g1 = 0.0, g2 = 0.0, l = 0.0;
+      for (int j = t; j < NP; j += 64) {
+        const double gj = gc[j];
+        g0 += o[NP + j] * gj;
+        g1 += o[2 * NP + j] * gj;
+        g2 += o[3 * NP + j] * gj;
+        l += o[4 * NP + j] * gj;
+      }
+      g0 = sum64(g0); g1 = sum64(g1); g2 = sum64(g2); l = sum64(l);
+      if (t == 0) {
+        double *dst = (double *)esc.gl + ((size_t)slot * c.ne + e) * 4;
+        dst[0] = g0;
+        dst[1] = g1;
+        dst[2] = g2;
+        dst[3] = l;
+      }
     }
+    __syncthreads();  // pts and the tiles are rewritten by the next slot
   }
 }
 

@@ -40,7 +40,7 @@ EXPORTED = [
     "dmcx_energy_escalations", "dmcx_set_et_feedback", "dmcx_get_trial_energy",
     "dmcx_jastrow_param_grads", "dmcx_linear_method", "dmcx_set_tile_shape",
     "dmcx_get_tile_shape", "dmcx_branch", "dmcx_set_walker_count", "dmcx_walker_count",
-    "dmcx_inverse_residual",
+    "dmcx_inverse_residual", "dmcx_set_energy_escalation_cap",
 ]
 
 
@@ -113,6 +113,7 @@ def load():
         "dmcx_set_walker_count": [P, I32],
         "dmcx_walker_count": [P, P, P],
         "dmcx_inverse_residual": [P, P, I32],
+        "dmcx_set_energy_escalation_cap": [P, D],
         "dmcx_sync": [P],
         "dmcx_last_run_timing": [P, P, P, P],
         "dmcx_selftest": [P],
@@ -302,6 +303,10 @@ def dmcx_walker_count(ctx, n, cap):
 
 def dmcx_inverse_residual(ctx, res, mem):
     return load().dmcx_inverse_residual(ctx, res, mem)
+
+
+def dmcx_set_energy_escalation_cap(ctx, cap):
+    return load().dmcx_set_energy_escalation_cap(ctx, cap)
 
 
 def dmcx_sync(ctx):
@@ -617,6 +622,11 @@ class Context:
         n, cap = C.c_int32(0), C.c_int32(0)
         self.check(dmcx_walker_count(self.h, C.byref(n), C.byref(cap)))
         return int(n.value), int(cap.value)
+
+    def set_energy_escalation_cap(self, cap):
+        """Bound (Ha per electron) above which the mixed form's FP64 energy
+        recomputes a walker's E_L from FP64 rows (0: every walker)."""
+        self.check(dmcx_set_energy_escalation_cap(self.h, float(cap)))
 
     def inverse_residual(self):
         """[W][2] max_ij |A A^{-1} - I| of each walker's spin matrices (the

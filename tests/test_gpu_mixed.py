@@ -148,3 +148,38 @@ def test_mixed_ion_grads():
     _report("ion grads dlnPsi/dR (rel. to max)", err)
     assert np.abs(err).max() <= 1e-4
     np.testing.assert_allclose(dv, dv_o, rtol=1e-12, atol=1e-12)
+
+
+def test_escalation_of_every_walker_matches_fp64():
+    """With the escalation bound at zero every walker's E_L is recomputed from
+    FP64 value and derivative rows and the FP64 inverse, so the mixed form's
+    energies equal the FP64 path's (to FP64 round-off, 1e-11 relative) and
+    the oracle's; 300 walkers exceed the re-evaluation kernel's 256 slot
+    groups, so some groups take two walkers.  The bound back at its default
+    re-evaluates few walkers; a negative bound is refused."""
+    s = synth.small_molecule()
+    W = 300
+    R = synth.make_walkers(s, W, 851)
+    m = dmcx.Context(s, W, precision=dmcx.DMCX_MIXED, seed=4)
+    m.set_energy_escalation_cap(0.0)
+    m.set_walkers(R)
+    e_m, lp_m, sg_m = m.measure()
+    n = m.energy_escalations()
+    print(f"[mixed] escalations with bound 0: {n} of {W}", flush=True)
+    assert n == W
+    f = dmcx.Context(s, W, seed=4)
+    f.set_walkers(R)
+    e_f, lp_f, sg_f = f.measure()
+    err = np.abs(e_m - e_f) / np.maximum(np.abs(e_f), 1.0)
+    print(f"[mixed] E_L against FP64, every walker escalated: max rel err {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-11
+    _, _, e_o, rc = oracle.evaluate_batch(s, R)
+    assert rc == 0
+    assert np.max(np.abs(e_m - e_o) / np.maximum(np.abs(e_o), 1.0)) <= 1e-10
+    np.testing.assert_array_equal(sg_m, sg_f)
+    # the default bound again, after a step (a step-end evaluation)
+    m.set_energy_escalation_cap(1e-4)
+    m.run(1, mode=dmcx.DMCX_DMC, e_trial=-8.0)
+    assert m.energy_escalations() < W
+    with pytest.raises(dmcx.DmcxError):
+        m.set_energy_escalation_cap(-1.0)
