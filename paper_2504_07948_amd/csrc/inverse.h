@@ -142,6 +142,7 @@ __global__ __launch_bounds__(64 * INV_WAVES) void k_inverse_w(DevCtx c, const S 
                                                               double *G64, int periodic) {
   __shared__ __align__(16) double prow_all[INV_WAVES][NR];
   __shared__ int piv_all[INV_WAVES][NR];
+  __shared__ __align__(16) double stage_all[INV_WAVES][64 * 8];  // 8 columns of 64 rows
   if (periodic && (c.run->step % (unsigned long long)c.P) != 0ull) return;
   const int wv = wave_id(), lane = threadIdx.x & 63;
   const int q = blockIdx.x * INV_WAVES + wv;
@@ -166,13 +167,26 @@ __global__ __launch_bounds__(64 * INV_WAVES) void k_inverse_w(DevCtx c, const S 
     return;
   }
   // lane r < n: row r; lanes past n hold zeros and are never pivots
+  // Rows are read eight columns at a time: each load instruction covers
+  // eight rows' 8-column segments (64 consecutive bytes per row, so eight
+  // cache lines instead of one line per lane), staged in LDS, from which
+  // every lane takes its own row's eight entries.
   double a[NR];
   {
-    const S *src = rows + ((size_t)w * c.ne + e0 + min(lane, n - 1)) * rs;
+    double *stg = stage_all[wv];
+    const S *base = rows + ((size_t)w * c.ne + e0) * rs;
 #pragma unroll
-    for (int j = 0; j < NR; ++j) {
-      const double v = (double)src[j];
-      a[j] = (lane < n && j < n) ? v : 0.0;
+    for (int j0 = 0; j0 < NR; j0 += 8) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int r = 8 * k + (lane >> 3), j = j0 + (lane & 7);
+        const double v = (double)base[(size_t)min(r, n - 1) * rs + j];
+        stg[r * 8 + (lane & 7)] = (r < n && j < n) ? v : 0.0;
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) a[j0 + jj] = stg[lane * 8 + jj];
+      wave_lds_sync();  // the next columns are staged in the same place
     }
   }
   GJState st{lane >= n, 0, 1.0, 0, false, false};
