@@ -105,7 +105,10 @@ void NobLaunch<T>::escalate_gl(int nob, const DevCtx &c, const double *G64, cons
                                size_t lds, hipStream_t s) {
   if constexpr (sizeof(T) == 4) {
     const int ntile = (c.ne + TW - 1) / TW;
-    const int ngrp = c.Wpad < 256 ? c.Wpad : 256;  // slot groups; each loops over its slots
+    // slot groups, each looping over its slots: few, because every block,
+    // even one that finds no slot, holds a CU's worth of LDS while it is
+    // dispatched (the list is usually a handful of walkers)
+    const int ngrp = c.Wpad < 32 ? c.Wpad : 32;
 #define DMCX_CALL(N)                                                                   \
   if (allow_lds(k_escalate_gl<N>, lds) == hipSuccess) \
   k_escalate_gl<N><<<dim3(ngrp * ntile), dim3(NT_TILE), lds, s>>>(c, G64, esc)
