@@ -99,3 +99,32 @@ def test_metrics_log_matches_walker_sums(tmp_path):
     assert 0.0 < last["acceptance"] <= 1.0
     assert last["residual_max"] is not None and last["residual_max"] < 1e-9
     assert recs[-1]["systems"][0] == last
+
+
+def test_metrics_log_for_a_group(tmp_path):
+    """A context of two systems: one record per system, each over its own
+    walkers (counts, estimators equal to the systems' own contexts)."""
+    a = synth.small_molecule()
+    b = synth.small_random_system(91, n_atom=2, n_up=2, n_dn=1, shells=(0, 1), nprim=1,
+                                  charge=1.5)
+    Ws = [16, 9]
+    ne = max(a.n_elec, b.n_elec)
+    Ra = synth.make_walkers(a, Ws[0], 805)
+    Rb = synth.make_walkers(b, Ws[1], 806)
+    R = np.zeros((sum(Ws), ne, 3))
+    R[:Ws[0], :a.n_elec] = Ra
+    R[Ws[0]:, :b.n_elec] = Rb
+    g = dmcx.Context([a, b], Ws, delay_rank=2, seed=8)
+    g.set_walkers(R)
+    with metrics.MetricsLog(str(tmp_path / "g.jsonl")) as log:
+        recs = metrics.run_logged(g, 2, log, mode=dmcx.DMCX_DMC, e_trial=-5.0, every=2)
+    sysrec = recs[-1]["systems"]
+    assert [r["walkers"] for r in sysrec] == Ws and [r["system"] for r in sysrec] == [0, 1]
+    for i, (s, Rs) in enumerate(((a, Ra), (b, Rb))):
+        solo = dmcx.Context(s, Ws[i], delay_rank=2, seed=8)
+        solo.set_walkers(Rs)
+        solo.run(2, mode=dmcx.DMCX_DMC, e_trial=-5.0)
+        est = solo.estimators()[0]
+        assert sysrec[i]["counted"] == Ws[i] and sysrec[i]["flagged"] == 0
+        assert sysrec[i]["e_mean"] == est[6]
+        assert sysrec[i]["moves"] == int(est[10])
