@@ -962,7 +962,10 @@ __global__ __launch_bounds__(NTE) void k_local_energy(DevCtx c, int measure_only
   const int tid = threadIdx.x, wid = wave_id(), lane = tid & 63;
   const int NP = c.NP;
   const double *Rw = c.R + (size_t)w * c.ne * 3;
-  double kin = 0.0, pot = 0.0, jv = 0.0, bound = 0.0;
+  // the terms linear in the pair sums (lap J, l_i, U, V) stay lane partials
+  // until the end; only g_i and grad_i J, whose products enter E_L, are
+  // reduced per electron
+  double kin = 0.0, bound = 0.0, kin_l = 0.0, pot_l = 0.0, jv_l = 0.0;
   for (int i = wid; i < c.ne; i += NTE / 64) {
     const int sp = i < c.n_up ? 0 : 1, ii = i - sp * c.n_up;
     const T *row = (const T *)c.vglc + vglc_off(c, w, i);
@@ -1022,9 +1025,8 @@ __global__ __launch_bounds__(NTE) void k_local_energy(DevCtx c, int measure_only
       ju += q * pd.u;
       v += ee ? 0.5 / rr : -c.Z[j - c.ne] / rr;
     }
-    g0 = sum64(g0); g1 = sum64(g1); g2 = sum64(g2); l = sum64(l);
-    jg0 = sum64(jg0); jg1 = sum64(jg1); jg2 = sum64(jg2); jl = sum64(jl);
-    ju = sum64(ju); v = sum64(v);
+    g0 = sum64(g0); g1 = sum64(g1); g2 = sum64(g2);
+    jg0 = sum64(jg0); jg1 = sum64(jg1); jg2 = sum64(jg2);
     double msd_k = 0.0;
     if (c.M.on) {
       // grad_i T_hv = g_hi w_v and lap_i T_hv = g_hi y_v with
@@ -1089,15 +1091,18 @@ __global__ __launch_bounds__(NTE) void k_local_energy(DevCtx c, int measure_only
       __builtin_amdgcn_s_waitcnt(0xC07F);
       __builtin_amdgcn_wave_barrier();
     }
-    kin += jl + jg0 * jg0 + jg1 * jg1 + jg2 * jg2 + 2.0 * (jg0 * g0 + jg1 * g1 + jg2 * g2) + l + msd_k;
-    pot += v;
-    jv += ju;
+    kin += jg0 * jg0 + jg1 * jg1 + jg2 * jg2 + 2.0 * (jg0 * g0 + jg1 * g1 + jg2 * g2) + msd_k;
+    kin_l += jl + l;
+    pot_l += v;
+    jv_l += ju;
     if (esc.mode == 1) {
       bl = sum64(bl);
       bg = sum64(bg);
       bound += bl + 2.0 * (fabs(jg0) + fabs(jg1) + fabs(jg2)) * bg;
     }
   }
+  kin += sum64(kin_l);
+  const double pot = sum64(pot_l), jv = sum64(jv_l);
   if (lane == 0) { part[wid][0] = kin; part[wid][1] = pot; part[wid][2] = jv; part[wid][3] = bound; }
   __syncthreads();
   if (tid == 0) {
