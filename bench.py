@@ -30,27 +30,32 @@ PEAK_FP32_TFLOPS = 157.3
 # HBM traffic of one sweep launch, from two counter passes (FETCH_SIZE, then
 # WRITE_SIZE, KiB per dispatch) over the default FP64 workload, each scaled by
 # what the same counter reads for a 512 MiB device copy (fetch x 2.0, write x
-# 1.0).  Reported only while the kernel sources hash to the value they had
-# when the counters were taken, and only for that workload.
+# 1.0).  Reported only while the kernel sources and their compiler flags hash
+# to the value they had when the counters were taken, and only for that workload.
 SWEEP_TRAFFIC = {
-    "sources_sha256": "ffbc8d988014f8e3b08458f79f0707029151367155f33869874fd83d51b7e1bf",
+    "sources_sha256": "e8781b47bf8fff232927474165f480c6fb0c790d34fc6c36b824805c1fa9d737",
     "workload": {"walkers": 2048, "delay": 32, "precision": "fp64"},
-    "fetch_bytes": 3.3149e+09,
-    "write_bytes": 2.7139e+09,
+    "fetch_bytes": 3.2809e+09,
+    "write_bytes": 2.7211e+09,
 }
 
 
-# the sources the FP64 sweep kernel is compiled from (the host runtime is not)
+# the sources the FP64 sweep kernel is compiled from (the host runtime is not);
+# its flags are hashed with them
 SWEEP_SOURCES = ("device_common.h", "kernels.h", "launch.h", "sweep_impl.h", "sweep_f64.hip")
 
 
 def kernel_sources_sha256():
+    """Hash of the FP64 sweep's sources and of the compiler flags they are
+    built with (a scheduler flag changes the code as much as an edit)."""
     import hashlib
+    from paper_2504_07948_amd import build_ext
     h = hashlib.sha256()
     for name in SWEEP_SOURCES:
         h.update(name.encode())
         with open(os.path.join(ROOT, "paper_2504_07948_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(build_ext.HIPCC_FLAGS + build_ext.SOURCE_FLAGS.get("sweep_f64.hip", [])).encode())
     return h.hexdigest()
 
 
