@@ -45,3 +45,24 @@ def test_invalid_arguments_rejected_without_device():
     assert lib.dmcx_run(None, 1, 1, 0.0, None, None, 0) == dmcx.DMCX_E_INVALID
     assert lib.dmcx_measure(None, None, None, None, 0) == dmcx.DMCX_E_INVALID
     assert lib.dmcx_create(None, 1, None, None, None, None) == dmcx.DMCX_E_INVALID
+
+
+def test_sweep_traffic_hash_covers_the_compiler_flags():
+    """The sweep's stored traffic figures are keyed by a hash of its sources
+    and of the flags it is compiled with: a change of either invalidates
+    them."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2504_07948_amd import build_ext
+    h0 = bench.kernel_sources_sha256()
+    saved = dict(build_ext.SOURCE_FLAGS)
+    try:
+        build_ext.SOURCE_FLAGS["sweep_f64.hip"] = saved.get("sweep_f64.hip", []) + ["-DX"]
+        assert bench.kernel_sources_sha256() != h0
+        build_ext.SOURCE_FLAGS.pop("sweep_f64.hip")
+        assert bench.kernel_sources_sha256() != h0 or not saved.get("sweep_f64.hip")
+    finally:
+        build_ext.SOURCE_FLAGS.clear()
+        build_ext.SOURCE_FLAGS.update(saved)
+    assert bench.kernel_sources_sha256() == h0
