@@ -952,7 +952,11 @@ __global__ __launch_bounds__(NTE) void k_local_energy(DevCtx c, int measure_only
   const double e_trial = c.run->e_trial;
   double *e_log_row = (e_log && !measure_only) ? e_log + c.run->s_in_run * elog_stride : nullptr;
   __shared__ double part[NTE / 64][4];
-  __shared__ double msx_le[NTE / 64][4 * MSD_NV_MAX];  // MSD: w (3 rows) and y per wave
+  // MSD: w (3 rows) and y per wave; only the 1024-thread instantiation serves
+  // multideterminant systems, so the others carry neither this array nor the
+  // determinant-list code (fewer registers, more waves per SIMD)
+  constexpr bool MSD_LE = NTE == 1024;
+  __shared__ double msx_le[MSD_LE ? NTE / 64 : 1][MSD_LE ? 4 * MSD_NV_MAX : 1];
   int w = blockIdx.x;
   if (esc.mode == 2) {
     if ((int)blockIdx.x >= *esc.count) return;  // whole block
@@ -1028,7 +1032,7 @@ __global__ __launch_bounds__(NTE) void k_local_energy(DevCtx c, int measure_only
     g0 = sum64(g0); g1 = sum64(g1); g2 = sum64(g2);
     jg0 = sum64(jg0); jg1 = sum64(jg1); jg2 = sum64(jg2);
     double msd_k = 0.0;
-    if (c.M.on) {
+    if constexpr (MSD_LE) if (c.M.on) {
       // grad_i T_hv = g_hi w_v and lap_i T_hv = g_hi y_v with
       //   w = grad m_i - T^T grad a_i,  y = lap m_i - T^T lap a_i - 2 w . grad ln D_0,
       // give grad_i S and lap_i S; per electron the kinetic sum gains
